@@ -1,0 +1,215 @@
+"""CPU oracle for coarse-path ray launching (test infrastructure).
+
+Only ``tests/``, ``__graft_entry__.smoke()`` and ``bench.py``'s
+``cpu_baseline`` leg may import this package.  It is a plain, slow FP64
+definition of what the HIP path computes and shares no code with it.
+
+* ``fibonacci(n)``       uniformly spaced launch directions (Fibonacci lattice)
+* ``ray_spacing(n)``     ideal angular spacing alpha of n directions
+* ``launch(...)``        brute force: every ray against every point
+                         (``oracle.c``), with parity bands on request
+* ``dedup(...)``         coarse paths = records grouped by (tx, rx, b, labels)
+                         with the kappa shortest kept (Section 2.2.3)
+* ``image_method``       closed-form image-source paths in a box room
+                         (the refinement reference of Section 2.3)
+
+Parity unpinned: sigma (reception sphere scale), r_s (surfel radius) and
+t_eps (self-intersection distance) are conventions the paper does not fix;
+they are pinned only by the shared definition.
+"""
+from __future__ import annotations
+
+import ctypes as C
+import os
+import subprocess
+from collections import defaultdict
+
+import numpy as np
+
+from . import image_method  # noqa: F401  (closed forms)
+
+_HERE = os.path.dirname(os.path.abspath(__file__))
+_SO = os.path.join(_HERE, "liboracle.so")
+_SRC = os.path.join(_HERE, "oracle.c")
+MAXACC = 16
+
+
+def build(force: bool = True) -> str:
+    """Compile oracle.c with gcc (plain FP64, no FMA contraction)."""
+    if force or not os.path.exists(_SO) or os.path.getmtime(_SO) < os.path.getmtime(_SRC):
+        tmp = _SO + ".tmp"
+        subprocess.check_call(["gcc", "-O2", "-std=c11", "-D_GNU_SOURCE", "-ffp-contract=off",
+                               "-fno-fast-math", "-fPIC", "-shared", "-pthread", _SRC, "-o", tmp, "-lm"])
+        os.replace(tmp, _SO)
+    return _SO
+
+
+class OracleArgs(C.Structure):
+    _fields_ = [
+        ("xyz", C.c_void_p), ("nrm", C.c_void_p), ("label", C.c_void_p), ("n_pts", C.c_int64),
+        ("tx", C.c_void_p), ("n_tx", C.c_int32), ("rx", C.c_void_p), ("n_rx", C.c_int32),
+        ("dirs", C.c_void_p), ("n_rays", C.c_int64), ("sel", C.c_void_p), ("n_sel", C.c_int64),
+        ("K", C.c_int32), ("r_s", C.c_double), ("t_eps", C.c_double), ("sigma", C.c_double),
+        ("alpha", C.c_double),
+        ("parity", C.c_int32), ("tie_rel", C.c_double), ("err_abs", C.c_double), ("err_dir", C.c_double),
+        ("edge_rel", C.c_double), ("den_amb", C.c_double), ("n_threads", C.c_int32),
+        ("hit_id", C.c_void_p), ("hit_t", C.c_void_p), ("acc_n", C.c_void_p), ("acc_id", C.c_void_p),
+        ("seg_o", C.c_void_p), ("seg_d", C.c_void_p),
+        ("seq", C.c_void_p), ("pts", C.c_void_p),
+        ("rec_cap", C.c_int64), ("n_rec", C.c_int64),
+        ("rec_sel", C.c_void_p), ("rec_g", C.c_void_p), ("rec_tx", C.c_void_p), ("rec_rx", C.c_void_p),
+        ("rec_b", C.c_void_p), ("rec_lpoly", C.c_void_p), ("rec_lunf", C.c_void_p), ("rec_flags", C.c_void_p),
+    ]
+
+
+_lib = None
+
+
+def _load():
+    global _lib
+    if _lib is None:
+        if not os.path.exists(_SO) or os.path.getmtime(_SO) < os.path.getmtime(_SRC):
+            build(force=True)
+        lib = C.CDLL(_SO)
+        lib.oracle_fibonacci.argtypes = [C.c_int64, C.c_void_p]
+        lib.oracle_fibonacci.restype = C.c_int
+        lib.oracle_ray_spacing.argtypes = [C.c_int64]
+        lib.oracle_ray_spacing.restype = C.c_double
+        lib.oracle_launch.argtypes = [C.POINTER(OracleArgs)]
+        lib.oracle_launch.restype = C.c_int
+        _lib = lib
+    return _lib
+
+
+def _p(a):
+    return None if a is None else a.ctypes.data
+
+
+def fibonacci(n: int) -> np.ndarray:
+    """[n, 3] float32 unit directions on the Fibonacci lattice (FP64, then rounded)."""
+    out = np.empty((n, 3), np.float32)
+    if _load().oracle_fibonacci(int(n), _p(out)) != 0:
+        raise ValueError("n must be positive")
+    return out
+
+
+def ray_spacing(n: int) -> float:
+    return float(_load().oracle_ray_spacing(int(n)))
+
+
+def default_threads() -> int:
+    try:
+        return len(os.sched_getaffinity(0))
+    except AttributeError:  # pragma: no cover
+        return os.cpu_count() or 1
+
+
+def launch(xyz, normal, label, tx, rx, dirs, K, r_s, t_eps, sigma=1.25, alpha=0.0, sel=None,
+           parity=False, tie_rel=1e-4, err_abs=0.0, err_dir=0.0, edge_rel=1e-4, den_amb=1e-6,
+           n_threads=None, want_segments=False, rec_cap=None):
+    """Brute-force launch of ``len(dirs)`` rays from every TX (FP64).
+
+    Returns a dict of numpy arrays.  Per traced ray r and segment b (index
+    ``[r, b]``): ``hit_id`` (-1 none), ``hit_t``; in parity mode ``acc_n`` and
+    ``acc_id`` (the acceptable answers, -1 = no hit).  Per reflection:
+    ``seq`` labels and ``pts`` points.  Records: ``rec_*`` arrays in traced-ray
+    order (``rec_flags`` bit0 received, bit1 ambiguous).
+    """
+    lib = _load()
+    xyz = np.ascontiguousarray(xyz, np.float32)
+    normal = np.ascontiguousarray(normal, np.float32)
+    label = np.ascontiguousarray(label, np.uint32)
+    tx = np.ascontiguousarray(np.asarray(tx, np.float32).reshape(-1, 3))
+    rx = np.ascontiguousarray(np.asarray(rx, np.float32).reshape(-1, 3))
+    dirs = np.ascontiguousarray(np.asarray(dirs, np.float32).reshape(-1, 3))
+    n_rays = dirs.shape[0]
+    if sel is not None:
+        sel = np.ascontiguousarray(sel, np.int64)
+        n_trace = sel.shape[0]
+    else:
+        n_trace = tx.shape[0] * n_rays
+    S = K + 1
+    out = {
+        "hit_id": np.empty((n_trace, S), np.int64),
+        "hit_t": np.empty((n_trace, S), np.float64),
+        "seq": np.empty((n_trace, max(K, 1)), np.int64),
+        "pts": np.empty((n_trace, max(K, 1), 3), np.float64),
+    }
+    if parity:
+        out["acc_n"] = np.zeros((n_trace, S), np.int32)
+        out["acc_id"] = np.full((n_trace, S, MAXACC), -3, np.int64)
+    if want_segments:
+        out["seg_o"] = np.full((n_trace, S, 3), np.nan)
+        out["seg_d"] = np.full((n_trace, S, 3), np.nan)
+    cap = rec_cap if rec_cap is not None else max(1024, 4 * n_trace)
+    for _ in range(2):
+        recs = {
+            "rec_sel": np.empty(cap, np.int64), "rec_g": np.empty(cap, np.int64),
+            "rec_tx": np.empty(cap, np.int32), "rec_rx": np.empty(cap, np.int32),
+            "rec_b": np.empty(cap, np.int32), "rec_lpoly": np.empty(cap, np.float64),
+            "rec_lunf": np.empty(cap, np.float64), "rec_flags": np.empty(cap, np.int32),
+        }
+        a = OracleArgs()
+        a.xyz, a.nrm, a.label, a.n_pts = _p(xyz), _p(normal), _p(label), xyz.shape[0]
+        a.tx, a.n_tx, a.rx, a.n_rx = _p(tx), tx.shape[0], _p(rx), rx.shape[0]
+        a.dirs, a.n_rays = _p(dirs), n_rays
+        a.sel, a.n_sel = (_p(sel), sel.shape[0]) if sel is not None else (None, 0)
+        a.K, a.r_s, a.t_eps, a.sigma, a.alpha = K, r_s, t_eps, sigma, alpha
+        a.parity, a.tie_rel, a.err_abs, a.err_dir = int(bool(parity)), tie_rel, err_abs, err_dir
+        a.edge_rel, a.den_amb = edge_rel, den_amb
+        a.n_threads = int(n_threads or default_threads())
+        a.hit_id, a.hit_t = _p(out["hit_id"]), _p(out["hit_t"])
+        a.acc_n = _p(out.get("acc_n"))
+        a.acc_id = _p(out.get("acc_id"))
+        a.seg_o, a.seg_d = _p(out.get("seg_o")), _p(out.get("seg_d"))
+        a.seq = _p(out["seq"]) if K > 0 else None
+        a.pts = _p(out["pts"]) if K > 0 else None
+        a.rec_cap = cap
+        for k, v in recs.items():
+            setattr(a, k, _p(v))
+        rc = lib.oracle_launch(C.byref(a))
+        if rc == -3:
+            cap = int(a.n_rec)
+            continue
+        if rc != 0:
+            raise RuntimeError(f"oracle_launch failed with status {rc}")
+        n = int(a.n_rec)
+        for k, v in recs.items():
+            out[k] = v[:n]
+        out["n_rec"] = n
+        out["alpha"] = alpha if alpha > 0 else ray_spacing(n_rays)
+        out["sel"] = sel if sel is not None else np.arange(n_trace, dtype=np.int64)
+        return out
+    raise RuntimeError("record capacity retry failed")
+
+
+def dedup(res, K, kappa=1, include_ambiguous=False):
+    """Coarse paths: group reception records by (tx, rx, b, labels[0:b]).
+
+    Section 2.2.3 limits the number of paths with the same labels in the same
+    order to kappa; here the kappa records with the smallest (L_poly, ray id)
+    are kept per key, together with the total count.  Returns a dict
+    key -> {"count", "rows": [(L_poly, L_unf, g, sel_index), ...]} and the
+    list of keys in sorted order.  Only received records count unless
+    ``include_ambiguous``; ambiguous-only receptions are returned separately
+    in "ambiguous_keys".
+    """
+    groups = defaultdict(list)
+    amb_keys = set()
+    flags = res["rec_flags"]
+    for q in range(res["n_rec"]):
+        r = int(res["rec_sel"][q])
+        b = int(res["rec_b"][q])
+        labels = tuple(int(x) for x in res["seq"][r, :b]) if b > 0 else ()
+        key = (int(res["rec_tx"][q]), int(res["rec_rx"][q]), b, labels)
+        if flags[q] & 2:
+            amb_keys.add(key)
+        if not (flags[q] & 1) and not include_ambiguous:
+            continue
+        groups[key].append((float(res["rec_lpoly"][q]), float(res["rec_lunf"][q]), int(res["rec_g"][q]), r,
+                            int(flags[q])))
+    paths = {}
+    for key, rows in groups.items():
+        rows.sort(key=lambda x: (x[0], x[2]))
+        paths[key] = {"count": len(rows), "rows": rows[:kappa], "all": rows}
+    return paths, sorted(paths.keys()), amb_keys

@@ -1,0 +1,433 @@
+/*
+ * oracle.c -- plain FP64 brute-force reference for coarse-path ray launching.
+ *
+ * TEST INFRASTRUCTURE.  Only tests/, __graft_entry__.smoke() and bench.py's
+ * cpu_baseline leg may call this library.  It shares no code with the HIP
+ * path and is never used by it.
+ *
+ * What it computes (paper, Section 2.2 "Coarse Path Tracing", read with the
+ * uniform ray launching of the Introduction): from each TX, rays leave in the
+ * directions given by the caller (renormalised in FP64); every ray is tested against EVERY point of
+ * the cloud (no acceleration structure), reflects specularly at the nearest
+ * hit up to K times (Section 2.2.3, propagation phase: rays are traced until
+ * they hit nothing or reach the interaction limit), and is tested against
+ * every RX sphere on every segment.  Receptions are emitted as records; the
+ * label sequence of each record is the coarse path of Section 2.2.3 (labels
+ * in interaction order), deduplicated in oracle/__init__.py.
+ *
+ * Readings where the paper is silent (Section 2.2.1 uses an SDF over nearby
+ * points; the launching here uses point-wise surfels instead):
+ *   - each point is a two-sided disk: centre p, unit normal n (the input
+ *     normal normalised in FP64), radius r_s;
+ *   - a ray o + t d hits point m iff |d.n| > 1e-12, t = ((p-o).n)/(d.n) > t_eps,
+ *     m is not the point the ray just left, and |o + t d - p| <= r_s;
+ *   - the nearest hit wins; equal t is broken by the smaller point index;
+ *   - reflection uses the hit point's own normal: d' = d - 2 (d.n) n,
+ *     renormalised;
+ *   - a segment [0, t_end] (t_end = hit distance or +inf) is received by RX r
+ *     iff s = (rx - o).d lies in (0, t_end] and the closest approach
+ *     |o + s d - rx| <= rho(L + s), rho(u) = sigma * u * alpha / sqrt(3),
+ *     alpha = sqrt(8 pi / (sqrt(3) N)) the ideal angular spacing of N rays;
+ *     L is the polyline length already travelled.  RX spheres are
+ *     transparent.
+ *
+ * Besides the exact answer, the parity mode lists for every segment the set
+ * of answers that an FP32 implementation may legitimately give (near ties and
+ * surfels whose thresholds lie inside an error band), and flags receptions
+ * whose thresholds lie inside a band.  The bands are inputs.
+ */
+#include <math.h>
+#include <pthread.h>
+#include <stdint.h>
+#include <stdlib.h>
+#include <string.h>
+
+#define ORACLE_MAXACC 16
+#define ORACLE_DEN_SKIP 1e-12
+
+typedef struct {
+    /* scene */
+    const float* xyz;          /* [n_pts*3] */
+    const float* nrm;          /* [n_pts*3] */
+    const uint32_t* label;     /* [n_pts]   */
+    int64_t n_pts;
+    /* antennas and rays */
+    const float* tx;           /* [n_tx*3] */
+    int32_t n_tx;
+    const float* rx;           /* [n_rx*3] */
+    int32_t n_rx;
+    const float* dirs;         /* [n_rays*3], shared by every TX */
+    int64_t n_rays;            /* rays per TX */
+    const int64_t* sel;        /* global ray ids g = tx*n_rays + j to trace; NULL: all */
+    int64_t n_sel;
+    /* method parameters */
+    int32_t K;                 /* maximum number of reflections */
+    double r_s;                /* surfel radius */
+    double t_eps;              /* self-intersection distance */
+    double sigma;              /* reception sphere scale */
+    double alpha;              /* angular ray spacing; <= 0: ideal spacing of n_rays */
+    /* parity bands (parity != 0) */
+    int32_t parity;
+    double tie_rel;            /* relative window on hit distance (1e-4) */
+    double err_abs;            /* absolute position error per segment of the compared implementation */
+    double err_dir;            /* direction error per segment of the compared implementation */
+    double edge_rel;           /* relative band on r_s, t_eps and rho */
+    double den_amb;            /* |d.n| at or below this is ambiguous */
+    int32_t n_threads;
+    /* per traced ray and segment b = 0..K: index r*(K+1) + b */
+    int64_t* hit_id;           /* -1: no hit */
+    double* hit_t;             /* +inf: no hit */
+    int32_t* acc_n;            /* size of the acceptable set (parity) */
+    int64_t* acc_id;           /* [.. * ORACLE_MAXACC], -1 stands for "no hit" */
+    double* seg_o;             /* optional [.. * 3] segment origin */
+    double* seg_d;             /* optional [.. * 3] segment direction */
+    /* per traced ray and reflection k = 0..K-1: index r*K + k */
+    int64_t* seq;              /* label of the k-th interaction, -1 */
+    double* pts;               /* [.. * 3] k-th interaction point */
+    /* reception records, in traced-ray order */
+    int64_t rec_cap;
+    int64_t n_rec;             /* out: number of records (may exceed rec_cap) */
+    int64_t* rec_sel;          /* index into the traced rays */
+    int64_t* rec_g;            /* global ray id */
+    int32_t* rec_tx;
+    int32_t* rec_rx;
+    int32_t* rec_b;            /* number of reflections before reception */
+    double* rec_lpoly;         /* L + |rx - o| */
+    double* rec_lunf;          /* L + s */
+    int32_t* rec_flags;        /* bit0 received, bit1 ambiguous */
+} OracleArgs;
+
+/* ------------------------------------------------------------------------ */
+/* ray directions                                                            */
+/* ------------------------------------------------------------------------ */
+
+/* Uniformly spaced directions on the unit sphere (Fibonacci lattice):
+ * z_j = 1 - (2j+1)/N, phi_j = 2 pi frac(j (3 - sqrt 5)/2), computed in FP64
+ * and rounded to FP32.  The fractional part is taken before the multiply by
+ * 2 pi so that large j keeps its angular resolution. */
+int oracle_fibonacci(int64_t n, float* out)
+{
+    if (n <= 0 || !out) return -1;
+    const double g = (3.0 - sqrt(5.0)) / 2.0;
+    const double two_pi = 6.283185307179586476925286766559;
+    for (int64_t j = 0; j < n; ++j) {
+        double z = 1.0 - (double)(2 * j + 1) / (double)n;
+        double r = sqrt(fmax(0.0, 1.0 - z * z));
+        double jg = (double)j * g;
+        double f = jg - floor(jg);
+        double phi = two_pi * f;
+        out[3 * j + 0] = (float)(r * cos(phi));
+        out[3 * j + 1] = (float)(r * sin(phi));
+        out[3 * j + 2] = (float)z;
+    }
+    return 0;
+}
+
+/* Ideal angular spacing of N directions on the sphere: hexagonal cells of
+ * area (sqrt 3 / 2) a^2 tile the 4 pi steradians. */
+double oracle_ray_spacing(int64_t n)
+{
+    return sqrt(8.0 * M_PI / (sqrt(3.0) * (double)n));
+}
+
+/* ------------------------------------------------------------------------ */
+/* brute force                                                               */
+/* ------------------------------------------------------------------------ */
+
+typedef struct {
+    double *px, *py, *pz, *nx, *ny, *nz;
+} Pts64;
+
+typedef struct {
+    int64_t n, cap;
+    int64_t *sel, *g;
+    int32_t *tx, *rx, *b, *flags;
+    double *lp, *lu;
+} RecBuf;
+
+static int rec_push(RecBuf* r, int64_t sel, int64_t g, int32_t tx, int32_t rx, int32_t b,
+                    double lp, double lu, int32_t flags)
+{
+    if (r->n == r->cap) {
+        int64_t c = r->cap ? 2 * r->cap : 256;
+#define GROW(f, T) do { void* q = realloc(r->f, (size_t)c * sizeof(T)); if (!q) return -1; r->f = (T*)q; } while (0)
+        GROW(sel, int64_t); GROW(g, int64_t); GROW(tx, int32_t); GROW(rx, int32_t);
+        GROW(b, int32_t); GROW(flags, int32_t); GROW(lp, double); GROW(lu, double);
+#undef GROW
+        r->cap = c;
+    }
+    int64_t i = r->n++;
+    r->sel[i] = sel; r->g[i] = g; r->tx[i] = tx; r->rx[i] = rx; r->b[i] = b;
+    r->lp[i] = lp; r->lu[i] = lu; r->flags[i] = flags;
+    return 0;
+}
+
+static void rec_free(RecBuf* r)
+{
+    free(r->sel); free(r->g); free(r->tx); free(r->rx); free(r->b); free(r->flags);
+    free(r->lp); free(r->lu);
+}
+
+typedef struct {
+    const OracleArgs* a;
+    const Pts64* P;
+    double alpha;
+    int64_t lo, hi;            /* traced-ray range */
+    RecBuf rec;
+    int status;
+} Work;
+
+static inline double dot3(const double* u, const double* v) { return u[0] * v[0] + u[1] * v[1] + u[2] * v[2]; }
+
+/* One segment: the exact nearest hit (definition), and in parity mode the
+ * set of answers compatible with the error bands. */
+static void nearest_hit(const OracleArgs* a, const Pts64* P, const double* o, const double* d,
+                        int64_t last, int32_t b, int64_t* best_out, double* tb_out,
+                        int32_t* acc_n, int64_t* acc_id)
+{
+    const double rs2 = a->r_s * a->r_s;
+    int64_t best = -1;
+    double tb = INFINITY;
+    for (int64_t m = 0; m < a->n_pts; ++m) {
+        if (m == last) continue;
+        double den = d[0] * P->nx[m] + d[1] * P->ny[m] + d[2] * P->nz[m];
+        if (fabs(den) <= ORACLE_DEN_SKIP) continue;
+        double wx = P->px[m] - o[0], wy = P->py[m] - o[1], wz = P->pz[m] - o[2];
+        double t = (wx * P->nx[m] + wy * P->ny[m] + wz * P->nz[m]) / den;
+        if (!(t > a->t_eps)) continue;
+        double qx = o[0] + t * d[0] - P->px[m];
+        double qy = o[1] + t * d[1] - P->py[m];
+        double qz = o[2] + t * d[2] - P->pz[m];
+        double dist2 = qx * qx + qy * qy + qz * qz;
+        if (dist2 <= rs2 && (t < tb || (t == tb && m < best))) {
+            tb = t;
+            best = m;
+        }
+    }
+    *best_out = best;
+    *tb_out = tb;
+    if (!a->parity) return;
+
+    /* Parity mode.  A surfel is ambiguous when one of its thresholds lies
+     * within the error band of the compared implementation; a clear
+     * candidate is a hit that no band can undo.  Acceptable answers: every
+     * clear or ambiguous surfel whose t does not exceed the nearest clear
+     * hit by more than the tie window, plus "no hit" if no clear hit. */
+    const double bb = (double)(b + 1);
+    double tc = INFINITY;
+    for (int pass = 0; pass < 2; ++pass) {
+        int32_t na = 0;
+        for (int64_t m = 0; m < a->n_pts; ++m) {
+            if (m == last) continue;
+            double den = d[0] * P->nx[m] + d[1] * P->ny[m] + d[2] * P->nz[m];
+            if (fabs(den) <= ORACLE_DEN_SKIP) continue;
+            double wx = P->px[m] - o[0], wy = P->py[m] - o[1], wz = P->pz[m] - o[2];
+            double t = (wx * P->nx[m] + wy * P->ny[m] + wz * P->nz[m]) / den;
+            double qx = o[0] + t * d[0] - P->px[m];
+            double qy = o[1] + t * d[1] - P->py[m];
+            double qz = o[2] + t * d[2] - P->pz[m];
+            double dist = sqrt(qx * qx + qy * qy + qz * qz);
+            /* position error of the compared ray at this distance, projected
+             * into the disk plane (grows as 1/|den| at grazing incidence) */
+            double band = bb * (a->err_abs + fabs(t) * a->err_dir) * (1.0 + 1.0 / fabs(den));
+            double band_r = band + a->edge_rel * a->r_s;
+            double band_t = band + a->edge_rel * a->t_eps;
+            if (dist > a->r_s + band_r) continue;         /* clearly outside the disk */
+            if (t <= a->t_eps - band_t) continue;         /* clearly behind / too close */
+            int cand = (t > a->t_eps) && (dist <= a->r_s);
+            int amb = (fabs(den) <= a->den_amb) || (fabs(dist - a->r_s) <= band_r) ||
+                      (fabs(t - a->t_eps) <= band_t);
+            if (pass == 0) {
+                if (cand && !amb && t < tc) tc = t;
+            } else {
+                double win = tc * (1.0 + a->tie_rel) + band;
+                if (t <= win && (cand || amb)) {
+                    if (na < ORACLE_MAXACC) acc_id[na] = m;
+                    ++na;
+                }
+            }
+        }
+        if (pass == 1) {
+            if (tc == INFINITY) {
+                if (na < ORACLE_MAXACC) acc_id[na] = -1;
+                ++na;
+            }
+            *acc_n = na;
+        }
+    }
+}
+
+static void trace_range(Work* w)
+{
+    const OracleArgs* a = w->a;
+    const Pts64* P = w->P;
+    const int32_t K = a->K;
+    const double inv_sqrt3 = 1.0 / sqrt(3.0);
+    for (int64_t r = w->lo; r < w->hi; ++r) {
+        int64_t g = a->sel ? a->sel[r] : r;
+        int32_t i = (int32_t)(g / a->n_rays);
+        int64_t j = g % a->n_rays;
+        double o[3] = {a->tx[3 * i], a->tx[3 * i + 1], a->tx[3 * i + 2]};
+        double d[3] = {a->dirs[3 * j], a->dirs[3 * j + 1], a->dirs[3 * j + 2]};
+        {   /* launch directions are FP32 approximations of unit vectors:
+             * renormalise so that ray parameters are lengths */
+            double inv = 1.0 / sqrt(dot3(d, d));
+            d[0] *= inv; d[1] *= inv; d[2] *= inv;
+        }
+        double L = 0.0;
+        int64_t last = -1;
+        for (int32_t k = 0; k < K; ++k) {
+            if (a->seq) a->seq[r * K + k] = -1;
+            if (a->pts) a->pts[(r * K + k) * 3] = a->pts[(r * K + k) * 3 + 1] = a->pts[(r * K + k) * 3 + 2] = NAN;
+        }
+        for (int32_t b = 0; b <= K; ++b) {
+            int64_t s_idx = r * (K + 1) + b;
+            if (a->hit_id) a->hit_id[s_idx] = -2;     /* -2: segment not traced */
+            if (a->hit_t) a->hit_t[s_idx] = NAN;
+            if (a->acc_n) a->acc_n[s_idx] = 0;
+        }
+        for (int32_t b = 0; b <= K; ++b) {
+            int64_t s_idx = r * (K + 1) + b;
+            int64_t best;
+            double tb;
+            int32_t na = 1;
+            int64_t acc[ORACLE_MAXACC];
+            nearest_hit(a, P, o, d, last, b, &best, &tb, &na, acc);
+            if (a->hit_id) a->hit_id[s_idx] = best;
+            if (a->hit_t) a->hit_t[s_idx] = tb;
+            if (a->seg_o) { a->seg_o[3 * s_idx] = o[0]; a->seg_o[3 * s_idx + 1] = o[1]; a->seg_o[3 * s_idx + 2] = o[2]; }
+            if (a->seg_d) { a->seg_d[3 * s_idx] = d[0]; a->seg_d[3 * s_idx + 1] = d[1]; a->seg_d[3 * s_idx + 2] = d[2]; }
+            double t_lo = tb, t_hi = tb;
+            if (a->parity) {
+                if (a->acc_n) a->acc_n[s_idx] = na;
+                for (int32_t q = 0; q < na && q < ORACLE_MAXACC; ++q) {
+                    if (a->acc_id) a->acc_id[s_idx * ORACLE_MAXACC + q] = acc[q];
+                    if (acc[q] < 0) { t_hi = INFINITY; continue; }
+                    int64_t m = acc[q];
+                    double den = d[0] * P->nx[m] + d[1] * P->ny[m] + d[2] * P->nz[m];
+                    double t = ((P->px[m] - o[0]) * P->nx[m] + (P->py[m] - o[1]) * P->ny[m] +
+                                (P->pz[m] - o[2]) * P->nz[m]) / den;
+                    if (t < t_lo) t_lo = t;
+                    if (t > t_hi) t_hi = t;
+                }
+            }
+            /* reception on [0, tb] */
+            const double bb = (double)(b + 1);
+            for (int32_t q = 0; q < a->n_rx; ++q) {
+                const double rxp[3] = {a->rx[3 * q], a->rx[3 * q + 1], a->rx[3 * q + 2]};
+                double v[3] = {rxp[0] - o[0], rxp[1] - o[1], rxp[2] - o[2]};
+                double s = dot3(v, d);
+                double c[3] = {o[0] + s * d[0] - rxp[0], o[1] + s * d[1] - rxp[1], o[2] + s * d[2] - rxp[2]};
+                double dist = sqrt(dot3(c, c));
+                double rho = a->sigma * (L + s) * w->alpha * inv_sqrt3;
+                int received = (s > 0.0) && (s <= tb) && (dist <= rho);
+                int amb = 0;
+                if (a->parity) {
+                    double band = bb * (a->err_abs + fabs(s) * a->err_dir);
+                    if (fabs(s) <= band) amb = 1;
+                    if (isfinite(tb) && fabs(s - tb) <= a->tie_rel * tb + band) amb = 1;
+                    if (fabs(dist - rho) <= a->edge_rel * fabs(rho) + band) amb = 1;
+                    if (na > 1 && s >= t_lo * (1.0 - a->tie_rel) - band &&
+                        (s <= t_hi * (1.0 + a->tie_rel) + band || !isfinite(t_hi))) amb = 1;
+                    if (s <= -band || dist > rho + a->edge_rel * fabs(rho) + band) amb = 0;   /* clearly out */
+                    if (s > t_hi * (1.0 + a->tie_rel) + band) amb = 0;                         /* clearly past */
+                }
+                if (received || amb) {
+                    double lp = L + sqrt(dot3(v, v));
+                    if (rec_push(&w->rec, r, g, i, q, b, lp, L + s, (received ? 1 : 0) | (amb ? 2 : 0))) {
+                        w->status = -2;
+                        return;
+                    }
+                }
+            }
+            if (best < 0 || b == K) break;
+            /* specular reflection at the hit point */
+            double n[3] = {P->nx[best], P->ny[best], P->nz[best]};
+            double qp[3] = {o[0] + tb * d[0], o[1] + tb * d[1], o[2] + tb * d[2]};
+            if (a->seq) a->seq[r * K + b] = (int64_t)a->label[best];
+            if (a->pts) { a->pts[(r * K + b) * 3] = qp[0]; a->pts[(r * K + b) * 3 + 1] = qp[1]; a->pts[(r * K + b) * 3 + 2] = qp[2]; }
+            L += tb;
+            double dn = dot3(d, n);
+            double e[3] = {d[0] - 2.0 * dn * n[0], d[1] - 2.0 * dn * n[1], d[2] - 2.0 * dn * n[2]};
+            double inv = 1.0 / sqrt(dot3(e, e));
+            d[0] = e[0] * inv; d[1] = e[1] * inv; d[2] = e[2] * inv;
+            o[0] = qp[0]; o[1] = qp[1]; o[2] = qp[2];
+            last = best;
+        }
+    }
+}
+
+static void* worker(void* p)
+{
+    trace_range((Work*)p);
+    return NULL;
+}
+
+/* Returns 0 on success, -1 on bad arguments, -2 out of host memory,
+ * -3 if the records did not fit (n_rec holds the number needed). */
+int oracle_launch(OracleArgs* a)
+{
+    if (!a || a->n_pts < 0 || (a->n_pts > 0 && (!a->xyz || !a->nrm || !a->label)) || a->n_tx < 1 ||
+        !a->tx || a->n_rx < 0 || (a->n_rx > 0 && !a->rx) || a->n_rays < 1 || !a->dirs || a->K < 0 ||
+        !(a->r_s > 0.0))
+        return -1;
+    int64_t n_trace = a->sel ? a->n_sel : (int64_t)a->n_tx * a->n_rays;
+    Pts64 P;
+    size_t nb = (size_t)(a->n_pts > 0 ? a->n_pts : 1) * sizeof(double);
+    P.px = malloc(nb); P.py = malloc(nb); P.pz = malloc(nb);
+    P.nx = malloc(nb); P.ny = malloc(nb); P.nz = malloc(nb);
+    if (!P.px || !P.py || !P.pz || !P.nx || !P.ny || !P.nz) return -2;
+    for (int64_t m = 0; m < a->n_pts; ++m) {
+        P.px[m] = a->xyz[3 * m]; P.py[m] = a->xyz[3 * m + 1]; P.pz[m] = a->xyz[3 * m + 2];
+        double nx = a->nrm[3 * m], ny = a->nrm[3 * m + 1], nz = a->nrm[3 * m + 2];
+        double len = sqrt(nx * nx + ny * ny + nz * nz);
+        if (!(len > 0.0) || !isfinite(len)) {
+            free(P.px); free(P.py); free(P.pz); free(P.nx); free(P.ny); free(P.nz);
+            return -1;
+        }
+        P.nx[m] = nx / len; P.ny[m] = ny / len; P.nz[m] = nz / len;
+    }
+    double alpha = a->alpha > 0.0 ? a->alpha : oracle_ray_spacing(a->n_rays);
+    int nt = a->n_threads > 0 ? a->n_threads : 1;
+    if (nt > n_trace) nt = (int)(n_trace > 0 ? n_trace : 1);
+    Work* W = calloc((size_t)nt, sizeof(Work));
+    pthread_t* T = calloc((size_t)nt, sizeof(pthread_t));
+    int status = 0;
+    if (!W || !T) status = -2;
+    for (int k = 0; k < nt && !status; ++k) {
+        W[k].a = a; W[k].P = &P; W[k].alpha = alpha;
+        W[k].lo = n_trace * k / nt; W[k].hi = n_trace * (k + 1) / nt;
+    }
+    if (!status) {
+        for (int k = 1; k < nt; ++k) pthread_create(&T[k], NULL, worker, &W[k]);
+        worker(&W[0]);
+        for (int k = 1; k < nt; ++k) pthread_join(T[k], NULL);
+        int64_t total = 0;
+        for (int k = 0; k < nt; ++k) {
+            if (W[k].status) status = W[k].status;
+            total += W[k].rec.n;
+        }
+        a->n_rec = total;
+        if (!status && total > a->rec_cap) status = -3;
+        if (!status) {
+            int64_t at = 0;
+            for (int k = 0; k < nt; ++k) {
+                RecBuf* r = &W[k].rec;
+                for (int64_t q = 0; q < r->n; ++q, ++at) {
+                    if (a->rec_sel) a->rec_sel[at] = r->sel[q];
+                    if (a->rec_g) a->rec_g[at] = r->g[q];
+                    if (a->rec_tx) a->rec_tx[at] = r->tx[q];
+                    if (a->rec_rx) a->rec_rx[at] = r->rx[q];
+                    if (a->rec_b) a->rec_b[at] = r->b[q];
+                    if (a->rec_lpoly) a->rec_lpoly[at] = r->lp[q];
+                    if (a->rec_lunf) a->rec_lunf[at] = r->lu[q];
+                    if (a->rec_flags) a->rec_flags[at] = r->flags[q];
+                }
+            }
+        }
+    }
+    for (int k = 0; W && k < nt; ++k) rec_free(&W[k].rec);
+    free(W); free(T);
+    free(P.px); free(P.py); free(P.pz); free(P.nx); free(P.ny); free(P.nz);
+    return status;
+}
