@@ -1,0 +1,221 @@
+/*
+ * pcrl.h -- C ABI of the MI355X (gfx950) coarse-path ray launcher.
+ *
+ * The library implements the coarse path tracing stage of "A Ray Launching
+ * Approach for Computing Exact Paths with Point Clouds" (Vaara et al., 2024)
+ * as uniform ray launching over a multi-level voxelisation of a labeled
+ * point cloud:
+ *
+ *   build_voxels   voxelisation (Section 2.1): a hierarchy of axis-aligned
+ *                  voxel levels over the cloud, each finer level dividing
+ *                  the coarser one by an integer factor (the subvoxels of
+ *                  Section 2.1 are the finest level), with per-leaf point
+ *                  ranges;
+ *   launch_rays    coarse path tracing (Section 2.2): uniformly spaced rays
+ *                  from every TX walk the hierarchy by DDA, intersect points
+ *                  as surfel disks, reflect specularly up to K times
+ *                  (Section 2.2.3, propagation phase) and are received by RX
+ *                  spheres;
+ *   collect_paths  coarse paths as label sequences deduplicated with the
+ *                  duplicate limit kappa (Section 2.2.3).
+ *
+ * Conventions for every entry point
+ *   - Return value: PCRL_OK (0) or a negative status below; the message of
+ *     the last failure on the calling thread is available from last_error().
+ *   - Pointers documented as "device" point to device memory of the current
+ *     HIP device (e.g. torch tensors on cuda:N); "host" pointers to host memory.
+ *   - Arrays are contiguous; [N,3] float arrays are xyz-interleaved rows.
+ *   - All work is enqueued on the given stream (NULL = default stream) and is
+ *     asynchronous unless stated otherwise.  Caller input arrays are read
+ *     only by work enqueued during the call, so they may be released in
+ *     stream order afterwards.
+ *   - Objects (PcrlScene, PcrlLaunch) are owned by the library until their
+ *     release_* call; a launch refers to its scene, so release the launch first.
+ *   - A failed call leaves no object behind (out pointers are set to NULL).
+ */
+#ifndef PCRL_H
+#define PCRL_H
+
+#include <stddef.h>
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+#define PCRL_OK         0
+#define PCRL_EINVAL    -1   /* bad argument: NULL, size, non-finite input, zero normal, level sizes not integer multiples, K > 8 */
+#define PCRL_ENOMEM    -2   /* device or host allocation failed */
+#define PCRL_EOVERFLOW -3   /* results exceed a capacity; the size needed is reported (see each call) */
+#define PCRL_EHIP      -4   /* HIP runtime error */
+#define PCRL_EBUSY     -5   /* admission refused (serving) */
+
+#define PCRL_MAX_LEVELS 4
+#define PCRL_MAX_REFLECTIONS 8
+
+typedef struct PcrlScene PcrlScene;
+typedef struct PcrlLaunch PcrlLaunch;
+typedef void* pcrl_stream_t; /* a hipStream_t */
+
+/* ------------------------------------------------------------------------ */
+/* voxelisation (Section 2.1)                                                */
+/* ------------------------------------------------------------------------ */
+
+typedef struct {
+    int32_t n_levels;                     /* 1..4 voxel levels */
+    float   level_size[PCRL_MAX_LEVELS];  /* edge lengths in metres, coarse -> fine; each an integer
+                                             multiple (within 1e-4 relative) of the next */
+    float   surfel_radius;                /* r_s > 0: every point is a two-sided disk of this radius */
+    float   t_eps;                        /* self-intersection distance; <= 0 selects 1e-5 x AABB diagonal */
+    int32_t flags;                        /* reserved, must be 0 */
+} PcrlVoxelParams;
+
+typedef struct {
+    int64_t n_points;                     /* input points */
+    int64_t n_entries;                    /* (leaf, point) pairs: a point is listed in every leaf its disk overlaps */
+    int64_t n_leaves;                     /* occupied leaves */
+    int64_t n_nodes[PCRL_MAX_LEVELS];     /* occupied cells per level (n_nodes[n_levels-1] = n_leaves) */
+    int32_t n_labels;                     /* distinct labels */
+    int32_t n_levels;
+    int32_t dims[3];                      /* leaf grid dimensions */
+    int32_t dims0[3];                     /* coarsest grid dimensions */
+    float   origin[3];                    /* grid origin (metres) */
+    float   leaf_size;                    /* finest edge length */
+    float   surfel_radius;
+    float   t_eps;                        /* effective self-intersection distance */
+    float   aabb[6];                      /* point AABB: min xyz, max xyz */
+    int64_t device_bytes;                 /* device memory held by the scene */
+    int32_t key_bits;                     /* bits of the hierarchical leaf key */
+    int32_t reserved;
+} PcrlSceneInfo;
+
+/* Build the voxel hierarchy of a labeled point cloud.
+ *   xyz    device [n_points,3] float32 positions
+ *   normal device [n_points,3] float32 normals (any non-zero length; normalised here)
+ *   label  device [n_points]   uint32 labels (segmented surfaces)
+ * n_points may be 0 (every ray then escapes).  Fails with PCRL_EINVAL on a
+ * non-finite coordinate, a zero or non-finite normal, or invalid params.
+ * Synchronises the stream internally (twice) to size its buffers. */
+int build_voxels(const float* xyz, const float* normal, const uint32_t* label, int64_t n_points,
+                 const PcrlVoxelParams* params, pcrl_stream_t stream, PcrlScene** out);
+
+/* Sizes of a built scene (host struct). */
+int scene_info(const PcrlScene* scene, PcrlSceneInfo* out);
+
+/* Copy the leaf table to caller device buffers of capacity >= n_leaves:
+ * leaf_key (hierarchical key), leaf_begin and leaf_count (ranges into the
+ * leaf-ordered entries) and entry_point (the point id of every entry,
+ * capacity >= n_entries).  Any pointer may be NULL.  Synchronous. */
+int scene_leaf_table(const PcrlScene* scene, uint64_t* leaf_key, uint32_t* leaf_begin, uint32_t* leaf_count,
+                     uint32_t* entry_point, pcrl_stream_t stream);
+
+int release_scene(PcrlScene* scene);
+
+/* ------------------------------------------------------------------------ */
+/* ray launching (Section 2.2)                                               */
+/* ------------------------------------------------------------------------ */
+
+#define PCRL_LAUNCH_STATS   1   /* count DDA steps, leaves, surfel tests (slower kernel variant) */
+#define PCRL_LAUNCH_TIMING  2   /* time every bounce kernel with HIP events */
+#define PCRL_LAUNCH_COHERENT 4  /* trace the first bounce in a direction-coherent ray order */
+
+typedef struct {
+    int64_t n_rays;            /* rays per TX (> 0) */
+    const float* directions;   /* device [n_rays,3] unit directions shared by all TX; NULL = Fibonacci lattice */
+    int32_t max_reflections;   /* K in [0, 8]: segments 0..K are traced, no reflection after the K-th */
+    float   rx_radius_scale;   /* sigma of the reception sphere rho(L) = sigma L alpha / sqrt(3); <= 0 -> 1.25 */
+    float   ray_spacing;       /* alpha in radians; <= 0 -> sqrt(8 pi / (sqrt(3) n_rays)) */
+    int64_t record_capacity;   /* reception records the launch can hold; <= 0 -> heuristic */
+    int32_t flags;             /* PCRL_LAUNCH_* */
+    int32_t reserved;
+    int32_t* hit_log_id;       /* optional device [n_tx*n_rays*(K+1)]: hit point id per ray and segment,
+                                  -1 no hit, -2 segment not traced */
+    float*  hit_log_t;         /* optional device, same shape: hit distance (NaN if none) */
+} PcrlLaunchParams;
+
+typedef struct {
+    int64_t rays;                                  /* n_tx * n_rays */
+    int64_t segments;                              /* traced segments, all bounces */
+    int64_t active[PCRL_MAX_REFLECTIONS + 1];      /* rays entering bounce b */
+    int64_t records;                               /* reception records produced (may exceed capacity) */
+    int64_t record_capacity;
+    /* PCRL_LAUNCH_STATS only (else 0) */
+    int64_t dda_steps;                             /* cells entered at any level */
+    int64_t leaves_visited;                        /* occupied leaves whose points were tested */
+    int64_t node_lookups;                          /* hierarchy lookups (level-0 map and brick words) */
+    int64_t surfel_tests;                          /* ray-disk tests */
+    int64_t hits;                                  /* segments ending on a surfel */
+    /* PCRL_LAUNCH_TIMING only (else 0) */
+    float   kernel_ms[PCRL_MAX_REFLECTIONS + 1];   /* trace kernel time per bounce */
+    float   total_ms;                              /* first to last trace kernel */
+} PcrlLaunchStats;
+
+/* Launch n_rays rays from each of n_tx TX and trace them.
+ *   tx device [n_tx,3] float32, rx device [n_rx,3] float32 (n_rx may be 0).
+ * The scene must stay alive until the launch is released.  Asynchronous. */
+int launch_rays(const PcrlScene* scene, const float* tx, int32_t n_tx, const float* rx, int32_t n_rx,
+                const PcrlLaunchParams* params, pcrl_stream_t stream, PcrlLaunch** out);
+
+/* The launch directions used when PcrlLaunchParams.directions is NULL: the
+ * Fibonacci lattice z_j = 1 - (2j+1)/N, phi_j = 2 pi frac(j (3 - sqrt 5)/2),
+ * evaluated in FP64 and rounded to FP32 (uniformly spaced rays, Section 1's
+ * ray launching).  out: device [n_rays,3] float32.  Asynchronous. */
+int launch_directions(int64_t n_rays, float* out, pcrl_stream_t stream);
+
+/* Counters and timings of a launch (synchronises the launch's stream). */
+int launch_stats(PcrlLaunch* launch, PcrlLaunchStats* out);
+
+/* Raw reception records (synchronous).  Device arrays of capacity `cap`:
+ * ray (global ray id g = tx*n_rays + j), rx, n_refl (reflections before
+ * reception), len_poly (TX -> interaction points -> RX centre) and len_unf
+ * (ray length at closest approach).  Order is unspecified.  *n_out receives
+ * the record count; PCRL_EOVERFLOW if it exceeds cap (or the launch's own
+ * capacity: then *n_out is the capacity needed). */
+int launch_records(PcrlLaunch* launch, int64_t cap, int64_t* ray, int32_t* rx, int32_t* n_refl,
+                   float* len_poly, float* len_unf, int64_t* n_out);
+
+int release_launch(PcrlLaunch* launch);
+
+/* ------------------------------------------------------------------------ */
+/* coarse paths (Section 2.2.3)                                              */
+/* ------------------------------------------------------------------------ */
+
+#define PCRL_KEY_LABELS 0   /* key = (tx, rx, n_refl, labels of the interactions) */
+#define PCRL_KEY_LEAVES 1   /* key = (tx, rx, n_refl, linear finest-leaf index of the interaction points) */
+
+typedef struct {
+    int64_t capacity;          /* rows the arrays can hold */
+    int64_t n_rows;            /* out: rows written (sum over keys of min(count, kappa)) */
+    int64_t n_keys;            /* out: distinct coarse paths */
+    /* device arrays, one entry per row, rows sorted by (key, len_poly, ray) */
+    int32_t* tx;
+    int32_t* rx;
+    int32_t* n_refl;
+    int64_t* key;              /* [capacity*K]: label (or leaf index) of interaction k, -1 for k >= n_refl */
+    int64_t* count;            /* records that share the row's key */
+    int32_t* rank;             /* 0..kappa-1 position of the row within its key */
+    int64_t* ray;              /* global ray id of the row */
+    float*   len_poly;
+    float*   len_unf;
+    float*   points;           /* [capacity*K*3] interaction points, NaN for k >= n_refl */
+} PcrlPaths;
+
+/* Deduplicate the launch's records into coarse paths: rows with the same key
+ * are ordered by (len_poly, ray) and the first kappa (>= 1) are kept.
+ * Synchronises the stream; any output pointer may be NULL.  Returns
+ * PCRL_EOVERFLOW with out->n_rows = rows needed if capacity is too small, or
+ * if the launch dropped records (then launch_stats().records is the record
+ * capacity to relaunch with). */
+int collect_paths(PcrlLaunch* launch, int32_t kappa, int32_t key_mode, PcrlPaths* out, pcrl_stream_t stream);
+
+/* Message of the last failed call on this thread ("" if none). */
+const char* last_error(void);
+
+/* Library version string. */
+const char* pcrl_version(void);
+
+#ifdef __cplusplus
+}
+#endif
+
+#endif /* PCRL_H */

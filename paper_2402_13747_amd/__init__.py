@@ -1,0 +1,291 @@
+"""MI355X-native coarse-path ray launching over voxelised labeled point clouds.
+
+Python face of libpcrl.so (include/pcrl.h), same names as the C ABI:
+
+    scene  = build_voxels(xyz, normal, label, levels=(0.5, 0.25), surfel_radius=0.15)
+    launch = launch_rays(scene, tx, rx, n_rays=10_000, max_reflections=2)
+    paths  = collect_paths(launch, kappa=1)
+
+Inputs are torch tensors (or numpy arrays, copied to ``device``); the
+library enqueues all work on torch's current stream.  Every computation runs
+in HIP kernels; this module only marshals arguments.
+"""
+from __future__ import annotations
+
+import ctypes as C
+import math
+
+import numpy as np
+import torch
+
+from . import _lib
+from ._lib import (KEY_LABELS, KEY_LEAVES, LAUNCH_COHERENT, LAUNCH_STATS, LAUNCH_TIMING, PCRL_EOVERFLOW,
+                   PcrlError, check, lib)
+
+__all__ = ["build_voxels", "launch_rays", "launch_directions", "collect_paths", "Scene", "Launch", "PcrlError", "KEY_LABELS",
+           "KEY_LEAVES", "version", "library_path"]
+
+
+def version() -> str:
+    return lib.pcrl_version().decode()
+
+
+def library_path() -> str:
+    return _lib.LIB_PATH
+
+
+def _dev(device):
+    if device is None:
+        return torch.device("cuda", torch.cuda.current_device())
+    return torch.device(device)
+
+
+def _as_tensor(x, dtype, device, shape_last=None):
+    if isinstance(x, torch.Tensor):
+        t = x
+    else:
+        t = torch.from_numpy(np.ascontiguousarray(x))
+    if t.dtype != dtype:
+        t = t.to(dtype)
+    t = t.to(device).contiguous()
+    if shape_last is not None:
+        t = t.reshape(-1, shape_last)
+    return t
+
+
+def _ptr(t):
+    return None if t is None else C.c_void_p(t.data_ptr())
+
+
+def _stream(device):
+    return C.c_void_p(torch.cuda.current_stream(device).cuda_stream)
+
+
+class Scene:
+    """A device-resident voxel hierarchy (owns a PcrlScene handle)."""
+
+    def __init__(self, handle, device, inputs):
+        self._h = handle
+        self.device = device
+        self._inputs = inputs
+
+    @property
+    def handle(self):
+        return self._h
+
+    def info(self) -> dict:
+        inf = _lib.PcrlSceneInfo()
+        check("scene_info", lib.scene_info(self._h, C.byref(inf)))
+        out = {}
+        for name, _ in inf._fields_:
+            v = getattr(inf, name)
+            out[name] = list(v) if hasattr(v, "__len__") else v
+        out["n_nodes"] = out["n_nodes"][: out["n_levels"]]
+        return out
+
+    def leaf_table(self):
+        inf = self.info()
+        nl, m = inf["n_leaves"], inf["n_entries"]
+        key = torch.empty(max(nl, 1), dtype=torch.int64, device=self.device)
+        begin = torch.empty(max(nl, 1), dtype=torch.int32, device=self.device)
+        count = torch.empty(max(nl, 1), dtype=torch.int32, device=self.device)
+        ids = torch.empty(max(m, 1), dtype=torch.int32, device=self.device)
+        check("scene_leaf_table", lib.scene_leaf_table(self._h, _ptr(key), _ptr(begin), _ptr(count), _ptr(ids),
+                                                       _stream(self.device)))
+        return key[:nl], begin[:nl], count[:nl], ids[:m]
+
+    def release(self):
+        if self._h:
+            lib.release_scene(self._h)
+            self._h = None
+
+    def __del__(self):
+        try:
+            self.release()
+        except Exception:  # pragma: no cover - interpreter shutdown
+            pass
+
+
+def build_voxels(xyz, normal, label, levels, surfel_radius, t_eps=0.0, device=None) -> Scene:
+    """Voxelise a labeled point cloud (positions [N,3], normals [N,3], labels [N])."""
+    device = _dev(device)
+    xyz = _as_tensor(xyz, torch.float32, device, 3)
+    normal = _as_tensor(normal, torch.float32, device, 3)
+    if isinstance(label, np.ndarray):
+        label = torch.from_numpy(np.ascontiguousarray(label.astype(np.uint32)).view(np.int32))
+    label = _as_tensor(label, torch.int32, device)
+    n = xyz.shape[0]
+    if normal.shape[0] != n or label.shape[0] != n:
+        raise ValueError("xyz, normal and label must have the same length")
+    levels = list(levels)
+    if not 1 <= len(levels) <= _lib.MAX_LEVELS:
+        raise ValueError("1..4 levels")
+    p = _lib.PcrlVoxelParams()
+    p.n_levels = len(levels)
+    for i, s in enumerate(levels):
+        p.level_size[i] = float(s)
+    p.surfel_radius = float(surfel_radius)
+    p.t_eps = float(t_eps)
+    p.flags = 0
+    h = C.c_void_p()
+    with torch.cuda.device(device):
+        check("build_voxels", lib.build_voxels(_ptr(xyz) if n else None, _ptr(normal) if n else None,
+                                               _ptr(label) if n else None, n, C.byref(p), _stream(device),
+                                               C.byref(h)))
+    return Scene(h, device, (xyz, normal, label))
+
+
+class Launch:
+    """Rays launched into a scene (owns a PcrlLaunch handle)."""
+
+    def __init__(self, handle, scene, device, n_rays, K, n_tx, n_rx, hit_log, args):
+        self._h = handle
+        self.scene = scene
+        self.device = device
+        self.n_rays = n_rays
+        self.K = K
+        self.n_tx = n_tx
+        self.n_rx = n_rx
+        self.hit_log = hit_log
+        self._args = args
+
+    @property
+    def handle(self):
+        return self._h
+
+    def stats(self) -> dict:
+        st = _lib.PcrlLaunchStats()
+        check("launch_stats", lib.launch_stats(self._h, C.byref(st)))
+        out = {}
+        for name, _ in st._fields_:
+            v = getattr(st, name)
+            out[name] = list(v) if hasattr(v, "__len__") else v
+        out["active"] = out["active"][: self.K + 1]
+        out["kernel_ms"] = out["kernel_ms"][: self.K + 1]
+        return out
+
+    def records(self) -> dict:
+        n = C.c_int64()
+        st = self.stats()
+        cap = max(int(st["records"]), 1)
+        ray = torch.empty(cap, dtype=torch.int64, device=self.device)
+        rx = torch.empty(cap, dtype=torch.int32, device=self.device)
+        nb = torch.empty(cap, dtype=torch.int32, device=self.device)
+        lp = torch.empty(cap, dtype=torch.float32, device=self.device)
+        lu = torch.empty(cap, dtype=torch.float32, device=self.device)
+        check("launch_records", lib.launch_records(self._h, cap, _ptr(ray), _ptr(rx), _ptr(nb), _ptr(lp), _ptr(lu),
+                                                   C.byref(n)))
+        k = int(n.value)
+        return {"ray": ray[:k], "rx": rx[:k], "n_refl": nb[:k], "len_poly": lp[:k], "len_unf": lu[:k]}
+
+    def release(self):
+        if self._h:
+            lib.release_launch(self._h)
+            self._h = None
+
+    def __del__(self):
+        try:
+            self.release()
+        except Exception:  # pragma: no cover
+            pass
+
+
+def launch_rays(scene: Scene, tx, rx, n_rays, max_reflections, directions=None, rx_radius_scale=1.25,
+                ray_spacing=0.0, record_capacity=0, stats=False, timing=False, coherent=False, hit_log=False
+                ) -> Launch:
+    """Launch ``n_rays`` rays from every TX (Fibonacci lattice unless ``directions``)."""
+    device = scene.device
+    tx = _as_tensor(tx, torch.float32, device, 3)
+    rx = _as_tensor(rx, torch.float32, device, 3) if rx is not None else torch.zeros((0, 3), device=device)
+    dirs = _as_tensor(directions, torch.float32, device, 3) if directions is not None else None
+    if dirs is not None and dirs.shape[0] != n_rays:
+        raise ValueError("directions must have n_rays rows")
+    K = int(max_reflections)
+    p = _lib.PcrlLaunchParams()
+    p.n_rays = int(n_rays)
+    p.directions = _ptr(dirs).value if dirs is not None else None
+    p.max_reflections = K
+    p.rx_radius_scale = float(rx_radius_scale)
+    p.ray_spacing = float(ray_spacing)
+    p.record_capacity = int(record_capacity)
+    p.flags = (LAUNCH_STATS if stats else 0) | (LAUNCH_TIMING if timing else 0) | (LAUNCH_COHERENT if coherent else 0)
+    log = None
+    if hit_log:
+        n = tx.shape[0] * int(n_rays) * (K + 1)
+        log = (torch.empty(n, dtype=torch.int32, device=device), torch.empty(n, dtype=torch.float32, device=device))
+        p.hit_log_id = log[0].data_ptr()
+        p.hit_log_t = log[1].data_ptr()
+    h = C.c_void_p()
+    with torch.cuda.device(device):
+        check("launch_rays", lib.launch_rays(scene.handle, _ptr(tx), tx.shape[0], _ptr(rx) if rx.shape[0] else None,
+                                             rx.shape[0], C.byref(p), _stream(device), C.byref(h)))
+    if log is not None:
+        log = (log[0].view(tx.shape[0] * int(n_rays), K + 1), log[1].view(tx.shape[0] * int(n_rays), K + 1))
+    args = dict(tx=tx, rx=rx, n_rays=n_rays, max_reflections=max_reflections, directions=dirs,
+                rx_radius_scale=rx_radius_scale, ray_spacing=ray_spacing, stats=stats, timing=timing,
+                coherent=coherent, hit_log=hit_log)
+    return Launch(h, scene, device, int(n_rays), K, tx.shape[0], rx.shape[0], log, args)
+
+
+def launch_directions(n_rays, device=None):
+    """[n_rays, 3] float32 Fibonacci-lattice directions computed by the library."""
+    device = _dev(device)
+    out = torch.empty((int(n_rays), 3), dtype=torch.float32, device=device)
+    with torch.cuda.device(device):
+        check("launch_directions", lib.launch_directions(int(n_rays), _ptr(out), _stream(device)))
+    return out
+
+
+def collect_paths(launch: Launch, kappa=1, key_mode=KEY_LABELS, capacity=None) -> dict:
+    """Deduplicated coarse paths; rows sorted by (key, len_poly, ray), at most kappa per key.
+
+    If the launch dropped reception records (capacity exceeded), the launch
+    is repeated once with the needed capacity (``launch`` is updated in place).
+    """
+    device = launch.device
+    K = launch.K
+    for attempt in range(3):
+        cap = int(capacity) if capacity is not None else 4096
+        bufs = {
+            "tx": torch.empty(cap, dtype=torch.int32, device=device),
+            "rx": torch.empty(cap, dtype=torch.int32, device=device),
+            "n_refl": torch.empty(cap, dtype=torch.int32, device=device),
+            "key": torch.empty(max(cap * K, 1), dtype=torch.int64, device=device),
+            "count": torch.empty(cap, dtype=torch.int64, device=device),
+            "rank": torch.empty(cap, dtype=torch.int32, device=device),
+            "ray": torch.empty(cap, dtype=torch.int64, device=device),
+            "len_poly": torch.empty(cap, dtype=torch.float32, device=device),
+            "len_unf": torch.empty(cap, dtype=torch.float32, device=device),
+            "points": torch.empty(max(cap * K * 3, 1), dtype=torch.float32, device=device),
+        }
+        out = _lib.PcrlPaths()
+        out.capacity = cap
+        for k, t in bufs.items():
+            setattr(out, k, t.data_ptr() if not (K == 0 and k in ("key", "points")) else None)
+        with torch.cuda.device(device):
+            st = lib.collect_paths(launch.handle, int(kappa), int(key_mode), C.byref(out), _stream(device))
+        if st == PCRL_EOVERFLOW and out.n_rows == -1:
+            need = launch.stats()["records"]
+            _relaunch(launch, int(need * 1.25) + 1024)
+            continue
+        if st == PCRL_EOVERFLOW:
+            capacity = int(out.n_rows)
+            continue
+        check("collect_paths", st)
+        n = int(out.n_rows)
+        res = {k: (t[: n * K].view(n, K) if k == "key" else t[: n * K * 3].view(n, K, 3) if k == "points"
+                   else t[:n]) for k, t in bufs.items()}
+        res["n_rows"] = n
+        res["n_keys"] = int(out.n_keys)
+        return res
+    raise PcrlError("collect_paths", PCRL_EOVERFLOW, "capacity retries exhausted")
+
+
+def _relaunch(launch: Launch, record_capacity: int):
+    a = dict(launch._args)
+    a["record_capacity"] = record_capacity
+    new = launch_rays(launch.scene, a.pop("tx"), a.pop("rx"), **a)
+    launch.release()
+    launch._h, new._h = new._h, None
+    launch.hit_log = new.hit_log
+    launch._args = new._args

@@ -1,0 +1,119 @@
+"""ctypes binding of libpcrl.so (include/pcrl.h).
+
+Argument marshalling only: every step of the path runs in the HIP library.
+torch is imported first so that the library binds to the HIP runtime torch
+already loaded (both carry the soname libamdhip64.so.7); torch supplies
+device memory and the stream.  There is no CPU fallback: importing this
+module without a built library raises.
+"""
+from __future__ import annotations
+
+import ctypes as C
+import os
+
+import torch  # noqa: F401  (must precede the library load)
+
+HERE = os.path.dirname(os.path.abspath(__file__))
+LIB_PATH = os.path.join(HERE, "libpcrl.so")
+
+PCRL_OK = 0
+PCRL_EINVAL = -1
+PCRL_ENOMEM = -2
+PCRL_EOVERFLOW = -3
+PCRL_EHIP = -4
+PCRL_EBUSY = -5
+MAX_LEVELS = 4
+MAX_REFLECTIONS = 8
+
+LAUNCH_STATS = 1
+LAUNCH_TIMING = 2
+LAUNCH_COHERENT = 4
+KEY_LABELS = 0
+KEY_LEAVES = 1
+
+STATUS_NAMES = {0: "PCRL_OK", -1: "PCRL_EINVAL", -2: "PCRL_ENOMEM", -3: "PCRL_EOVERFLOW", -4: "PCRL_EHIP",
+                -5: "PCRL_EBUSY"}
+
+
+class PcrlVoxelParams(C.Structure):
+    _fields_ = [("n_levels", C.c_int32), ("level_size", C.c_float * MAX_LEVELS), ("surfel_radius", C.c_float),
+                ("t_eps", C.c_float), ("flags", C.c_int32)]
+
+
+class PcrlSceneInfo(C.Structure):
+    _fields_ = [("n_points", C.c_int64), ("n_entries", C.c_int64), ("n_leaves", C.c_int64),
+                ("n_nodes", C.c_int64 * MAX_LEVELS), ("n_labels", C.c_int32), ("n_levels", C.c_int32),
+                ("dims", C.c_int32 * 3), ("dims0", C.c_int32 * 3), ("origin", C.c_float * 3),
+                ("leaf_size", C.c_float), ("surfel_radius", C.c_float), ("t_eps", C.c_float),
+                ("aabb", C.c_float * 6), ("device_bytes", C.c_int64), ("key_bits", C.c_int32),
+                ("reserved", C.c_int32)]
+
+
+class PcrlLaunchParams(C.Structure):
+    _fields_ = [("n_rays", C.c_int64), ("directions", C.c_void_p), ("max_reflections", C.c_int32),
+                ("rx_radius_scale", C.c_float), ("ray_spacing", C.c_float), ("record_capacity", C.c_int64),
+                ("flags", C.c_int32), ("reserved", C.c_int32), ("hit_log_id", C.c_void_p),
+                ("hit_log_t", C.c_void_p)]
+
+
+class PcrlLaunchStats(C.Structure):
+    _fields_ = [("rays", C.c_int64), ("segments", C.c_int64), ("active", C.c_int64 * (MAX_REFLECTIONS + 1)),
+                ("records", C.c_int64), ("record_capacity", C.c_int64), ("dda_steps", C.c_int64),
+                ("leaves_visited", C.c_int64), ("node_lookups", C.c_int64), ("surfel_tests", C.c_int64),
+                ("hits", C.c_int64), ("kernel_ms", C.c_float * (MAX_REFLECTIONS + 1)), ("total_ms", C.c_float)]
+
+
+class PcrlPaths(C.Structure):
+    _fields_ = [("capacity", C.c_int64), ("n_rows", C.c_int64), ("n_keys", C.c_int64), ("tx", C.c_void_p),
+                ("rx", C.c_void_p), ("n_refl", C.c_void_p), ("key", C.c_void_p), ("count", C.c_void_p),
+                ("rank", C.c_void_p), ("ray", C.c_void_p), ("len_poly", C.c_void_p), ("len_unf", C.c_void_p),
+                ("points", C.c_void_p)]
+
+
+# name -> (restype, argtypes); every symbol declared in include/pcrl.h
+SIGNATURES = {
+    "build_voxels": (C.c_int, [C.c_void_p, C.c_void_p, C.c_void_p, C.c_int64, C.POINTER(PcrlVoxelParams),
+                               C.c_void_p, C.POINTER(C.c_void_p)]),
+    "scene_info": (C.c_int, [C.c_void_p, C.POINTER(PcrlSceneInfo)]),
+    "scene_leaf_table": (C.c_int, [C.c_void_p, C.c_void_p, C.c_void_p, C.c_void_p, C.c_void_p, C.c_void_p]),
+    "release_scene": (C.c_int, [C.c_void_p]),
+    "launch_rays": (C.c_int, [C.c_void_p, C.c_void_p, C.c_int32, C.c_void_p, C.c_int32,
+                              C.POINTER(PcrlLaunchParams), C.c_void_p, C.POINTER(C.c_void_p)]),
+    "launch_directions": (C.c_int, [C.c_int64, C.c_void_p, C.c_void_p]),
+    "launch_stats": (C.c_int, [C.c_void_p, C.POINTER(PcrlLaunchStats)]),
+    "launch_records": (C.c_int, [C.c_void_p, C.c_int64, C.c_void_p, C.c_void_p, C.c_void_p, C.c_void_p,
+                                 C.c_void_p, C.POINTER(C.c_int64)]),
+    "release_launch": (C.c_int, [C.c_void_p]),
+    "collect_paths": (C.c_int, [C.c_void_p, C.c_int32, C.c_int32, C.POINTER(PcrlPaths), C.c_void_p]),
+    "last_error": (C.c_char_p, []),
+    "pcrl_version": (C.c_char_p, []),
+}
+
+
+class PcrlError(RuntimeError):
+    def __init__(self, fn, status, message):
+        super().__init__(f"{fn} -> {STATUS_NAMES.get(status, status)}: {message}")
+        self.status = status
+        self.message = message
+
+
+def _load():
+    if not os.path.exists(LIB_PATH):
+        raise ImportError(f"{LIB_PATH} is not built; run paper_2402_13747_amd.build.build() "
+                          "(or __graft_entry__.build()) first")
+    lib = C.CDLL(LIB_PATH)
+    for name, (res, args) in SIGNATURES.items():
+        f = getattr(lib, name)
+        f.restype = res
+        f.argtypes = args
+    return lib
+
+
+lib = _load()
+
+
+def check(fn, status):
+    if status != PCRL_OK:
+        msg = lib.last_error()
+        raise PcrlError(fn, status, msg.decode() if msg else "")
+    return status

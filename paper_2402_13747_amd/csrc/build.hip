@@ -1,0 +1,638 @@
+// build.hip -- voxelisation of a labeled point cloud (paper, Section 2.1).
+//
+// The paper keeps a low-resolution voxel grid for traversal and divides each
+// voxel by an integer factor into subvoxels that localise the geometry.  Here
+// that becomes a hierarchy of 1..4 levels, each level dividing the previous
+// one by an integer ratio:
+//
+//   level 0          dense int32 map over the coarse grid (node index or -1)
+//   levels 1..L-1    occupancy bricks: per occupied parent a bitmask over its
+//                    ratio^3 children plus, per 64-bit word, the index of the
+//                    first child of that word (child = base + popcount)
+//   leaves           (first entry, count) ranges into leaf-ordered surfels
+//   surfels          two 16-byte streams per entry, in leaf order:
+//                    (x, y, z, point id) and (unit normal, label rank)
+//
+// A point is listed in EVERY leaf that the axis-aligned box of its disk
+// (radius r_s, its own normal) overlaps, padded by a rounding margin, so a
+// traversal that tests the leaves it passes finds every disk it crosses.
+//
+// Pipeline: ingest (normalise normals, validate, AABB, max label) -> sync ->
+// label ranks -> per-point leaf counts -> scan -> sync -> emit (key, id) ->
+// radix sort -> per-level boundary flags + scans -> sync -> level-0 map,
+// bricks, leaf ranges -> surfel gather.
+#include "internal.h"
+
+#include <algorithm>
+#include <cmath>
+#include <cstring>
+
+namespace pcrl {
+
+constexpr int BUILD_BLOCK = 256;
+
+static unsigned blocks_for(int64_t n, int block = BUILD_BLOCK) {
+    int64_t g = (n + block - 1) / block;
+    return (unsigned)std::max<int64_t>(1, g);
+}
+
+static int bits_for(uint64_t max_value) {
+    int b = 1;
+    while (b < 64 && (max_value >> b) != 0) ++b;
+    return b;
+}
+
+// ---------------------------------------------------------------------------
+// ingest
+// ---------------------------------------------------------------------------
+
+struct IngestOut {
+    float lo[3];
+    float hi[3];
+    uint32_t max_label;
+    uint32_t bad;  // bit0 non-finite position, bit1 bad normal
+};
+
+__global__ __launch_bounds__(BUILD_BLOCK) void k_ingest(const float* xyz, const float* nrm, const uint32_t* label,
+                                                        int64_t n, float4* unit_nrm, IngestOut* partial) {
+    float lo[3] = {INFINITY, INFINITY, INFINITY};
+    float hi[3] = {-INFINITY, -INFINITY, -INFINITY};
+    uint32_t ml = 0, bad = 0;
+    for (int64_t i = (int64_t)blockIdx.x * BUILD_BLOCK + threadIdx.x; i < n; i += (int64_t)gridDim.x * BUILD_BLOCK) {
+        const float x = xyz[3 * i], y = xyz[3 * i + 1], z = xyz[3 * i + 2];
+        if (!isfinite(x) || !isfinite(y) || !isfinite(z)) bad |= 1u;
+        lo[0] = fminf(lo[0], x); lo[1] = fminf(lo[1], y); lo[2] = fminf(lo[2], z);
+        hi[0] = fmaxf(hi[0], x); hi[1] = fmaxf(hi[1], y); hi[2] = fmaxf(hi[2], z);
+        const float a = nrm[3 * i], b = nrm[3 * i + 1], c = nrm[3 * i + 2];
+        const float l2 = a * a + b * b + c * c;
+        float inv = 0.f;
+        if (!(l2 > 0.f) || !isfinite(l2))
+            bad |= 2u;
+        else
+            inv = 1.0f / sqrtf(l2);
+        unit_nrm[i] = make_float4(a * inv, b * inv, c * inv, 0.f);
+        ml = max(ml, label[i]);
+    }
+    // block reduction through LDS
+    __shared__ float s_lo[3][BUILD_BLOCK / 64], s_hi[3][BUILD_BLOCK / 64];
+    __shared__ uint32_t s_ml[BUILD_BLOCK / 64], s_bad[BUILD_BLOCK / 64];
+    for (int off = 32; off > 0; off >>= 1) {
+        for (int a = 0; a < 3; ++a) {
+            lo[a] = fminf(lo[a], __shfl_xor(lo[a], off, 64));
+            hi[a] = fmaxf(hi[a], __shfl_xor(hi[a], off, 64));
+        }
+        ml = max(ml, __shfl_xor(ml, off, 64));
+        bad |= __shfl_xor(bad, off, 64);
+    }
+    const int w = threadIdx.x >> 6;
+    if (lane_id() == 0) {
+        for (int a = 0; a < 3; ++a) { s_lo[a][w] = lo[a]; s_hi[a][w] = hi[a]; }
+        s_ml[w] = ml;
+        s_bad[w] = bad;
+    }
+    __syncthreads();
+    if (threadIdx.x == 0) {
+        IngestOut o;
+        for (int a = 0; a < 3; ++a) { o.lo[a] = INFINITY; o.hi[a] = -INFINITY; }
+        o.max_label = 0;
+        o.bad = 0;
+        for (int k = 0; k < BUILD_BLOCK / 64; ++k) {
+            for (int a = 0; a < 3; ++a) { o.lo[a] = fminf(o.lo[a], s_lo[a][k]); o.hi[a] = fmaxf(o.hi[a], s_hi[a][k]); }
+            o.max_label = max(o.max_label, s_ml[k]);
+            o.bad |= s_bad[k];
+        }
+        partial[blockIdx.x] = o;
+    }
+}
+
+__global__ void k_ingest_final(const IngestOut* partial, int nb, IngestOut* out) {
+    if (threadIdx.x != 0 || blockIdx.x != 0) return;
+    IngestOut o;
+    for (int a = 0; a < 3; ++a) { o.lo[a] = INFINITY; o.hi[a] = -INFINITY; }
+    o.max_label = 0;
+    o.bad = 0;
+    for (int k = 0; k < nb; ++k) {
+        for (int a = 0; a < 3; ++a) { o.lo[a] = fminf(o.lo[a], partial[k].lo[a]); o.hi[a] = fmaxf(o.hi[a], partial[k].hi[a]); }
+        o.max_label = max(o.max_label, partial[k].max_label);
+        o.bad |= partial[k].bad;
+    }
+    *out = o;
+}
+
+// ---------------------------------------------------------------------------
+// labels -> dense ranks
+// ---------------------------------------------------------------------------
+
+__global__ void k_unique_flags_u32(const uint32_t* sorted, int64_t n, uint32_t* flag) {
+    int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (i < n) flag[i] = (i == 0 || sorted[i] != sorted[i - 1]) ? 1u : 0u;
+}
+
+__global__ void k_unique_compact_u32(const uint32_t* sorted, int64_t n, const uint32_t* pos, uint32_t* out) {
+    int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (i < n && (i == 0 || sorted[i] != sorted[i - 1])) out[pos[i]] = sorted[i];
+}
+
+__global__ void k_label_rank(const uint32_t* label, int64_t n, const uint32_t* uniq, const uint32_t* n_uniq,
+                             uint32_t* rank) {
+    int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (i >= n) return;
+    const uint32_t v = label[i];
+    uint32_t lo = 0, hi = *n_uniq;  // first index with uniq[idx] >= v
+    while (lo < hi) {
+        uint32_t mid = (lo + hi) >> 1;
+        if (uniq[mid] < v) lo = mid + 1; else hi = mid;
+    }
+    rank[i] = lo;
+}
+
+// ---------------------------------------------------------------------------
+// dilated keys
+// ---------------------------------------------------------------------------
+
+struct KeyParams {
+    SceneView v;
+    float r_s;
+    float pad;
+};
+
+__device__ __forceinline__ void disk_leaf_box(const KeyParams& kp, const float* xyz, const float4* un, int64_t i,
+                                              int lo[3], int hi[3]) {
+    const float p[3] = {xyz[3 * i], xyz[3 * i + 1], xyz[3 * i + 2]};
+    const float4 nn = un[i];
+    const float nv[3] = {nn.x, nn.y, nn.z};
+#pragma unroll
+    for (int a = 0; a < 3; ++a) {
+        const float e = kp.r_s * sqrtf(fmaxf(0.f, 1.f - nv[a] * nv[a])) + kp.pad;
+        int l = (int)floorf((p[a] - e - kp.v.org[a]) * kp.v.inv_h);
+        int u = (int)floorf((p[a] + e - kp.v.org[a]) * kp.v.inv_h);
+        lo[a] = min(max(l, 0), kp.v.dim[a] - 1);
+        hi[a] = min(max(u, 0), kp.v.dim[a] - 1);
+    }
+}
+
+__global__ __launch_bounds__(BUILD_BLOCK) void k_key_count(KeyParams kp, const float* xyz, const float4* un, int64_t n,
+                                                           uint32_t* cnt) {
+    int64_t i = (int64_t)blockIdx.x * BUILD_BLOCK + threadIdx.x;
+    if (i >= n) return;
+    int lo[3], hi[3];
+    disk_leaf_box(kp, xyz, un, i, lo, hi);
+    cnt[i] = (uint32_t)((hi[0] - lo[0] + 1) * (hi[1] - lo[1] + 1) * (hi[2] - lo[2] + 1));
+}
+
+__global__ __launch_bounds__(BUILD_BLOCK) void k_key_emit(KeyParams kp, const float* xyz, const float4* un, int64_t n,
+                                                          const uint32_t* off, uint64_t* keys, uint32_t* ids) {
+    int64_t i = (int64_t)blockIdx.x * BUILD_BLOCK + threadIdx.x;
+    if (i >= n) return;
+    int lo[3], hi[3];
+    disk_leaf_box(kp, xyz, un, i, lo, hi);
+    uint32_t o = off[i];
+    for (int z = lo[2]; z <= hi[2]; ++z)
+        for (int y = lo[1]; y <= hi[1]; ++y)
+            for (int x = lo[0]; x <= hi[0]; ++x) {
+                keys[o] = leaf_key_of(kp.v, x, y, z);
+                ids[o] = (uint32_t)i;
+                ++o;
+            }
+}
+
+// ---------------------------------------------------------------------------
+// hierarchy from sorted keys
+// ---------------------------------------------------------------------------
+
+struct LevelShifts {
+    int32_t nlev;
+    int32_t sh[PCRL_MAX_LEVELS];  // node key of level i = key >> sh[i]
+};
+
+// flag[l][e] = entry e starts a new node of level l
+__global__ void k_level_flags(const uint64_t* keys, int64_t m, LevelShifts ls, uint32_t* flags) {
+    int64_t e = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (e >= m) return;
+    const uint64_t k = keys[e];
+    const uint64_t kp = e > 0 ? keys[e - 1] : 0;
+    for (int l = 0; l < ls.nlev; ++l)
+        flags[(size_t)l * m + e] = (e == 0 || (k >> ls.sh[l]) != (kp >> ls.sh[l])) ? 1u : 0u;
+}
+
+struct HierOut {
+    int32_t* map0;
+    uint64_t* mask[PCRL_MAX_LEVELS - 1];
+    uint32_t* first_child[PCRL_MAX_LEVELS - 1];
+    uint2* leaf;
+    uint64_t* leaf_key;
+};
+
+// For every entry that opens a node: register the node with its parent.
+// scans[l][e] is the exclusive scan of the level-l flags, so the node index
+// of entry e at level l is scans[l][e] + flag - 1.
+__global__ void k_hier_link(const uint64_t* keys, int64_t m, LevelShifts ls, SceneView v, const uint32_t* scans,
+                            HierOut h) {
+    int64_t e = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (e >= m) return;
+    const uint64_t k = keys[e];
+    const uint64_t kp = e > 0 ? keys[e - 1] : 0;
+    const int L = ls.nlev;
+    for (int l = 0; l < L; ++l) {
+        const bool f = (e == 0 || (k >> ls.sh[l]) != (kp >> ls.sh[l]));
+        if (!f) continue;
+        const uint32_t node = scans[(size_t)l * m + e];  // exclusive scan at a flagged entry = node index
+        if (l == 0) h.map0[k >> ls.sh[0]] = (int32_t)node;
+        if (l == L - 1) {
+            h.leaf[node].x = (uint32_t)e;
+            h.leaf_key[node] = k;
+        }
+        if (l > 0) {
+            const uint32_t parent = scans[(size_t)(l - 1) * m + e] +
+                                    (((k >> ls.sh[l - 1]) != (kp >> ls.sh[l - 1]) || e == 0) ? 1u : 0u) - 1u;
+            const uint32_t local = (uint32_t)((k >> ls.sh[l]) & ((uint64_t(1) << v.lbits[l]) - 1));
+            atomicOr((unsigned long long*)&h.mask[l - 1][(size_t)parent * v.nw[l - 1] + (local >> 6)],
+                     (unsigned long long)(uint64_t(1) << (local & 63)));
+            // the first child of a parent is the entry that opens the parent too
+            const bool opens_parent = (e == 0 || (k >> ls.sh[l - 1]) != (kp >> ls.sh[l - 1]));
+            if (opens_parent) h.first_child[l - 1][parent] = node;
+        }
+    }
+}
+
+__global__ void k_brick_base(const uint64_t* mask, const uint32_t* first_child, int64_t n_nodes, int nw,
+                             uint32_t* base) {
+    int64_t p = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (p >= n_nodes) return;
+    uint32_t run = first_child[p];
+    for (int w = 0; w < nw; ++w) {
+        base[(size_t)p * nw + w] = run;
+        run += (uint32_t)__popcll(mask[(size_t)p * nw + w]);
+    }
+}
+
+__global__ void k_leaf_counts(uint2* leaf, int64_t n_leaves, int64_t m) {
+    int64_t l = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (l >= n_leaves) return;
+    const uint32_t end = (l + 1 < n_leaves) ? leaf[l + 1].x : (uint32_t)m;
+    leaf[l].y = end - leaf[l].x;
+}
+
+__global__ void k_split_leaf(const uint2* r, int64_t n, uint32_t* b, uint32_t* c) {
+    int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (i >= n) return;
+    const uint2 x = r[i];
+    if (b) b[i] = x.x;
+    if (c) c[i] = x.y;
+}
+
+__global__ void k_gather_surfels(const uint32_t* ids, int64_t m, const float* xyz, const float4* un,
+                                 const uint32_t* rank, float4* spos, float4* snrm) {
+    int64_t e = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (e >= m) return;
+    const uint32_t i = ids[e];
+    spos[e] = make_float4(xyz[3 * (size_t)i], xyz[3 * (size_t)i + 1], xyz[3 * (size_t)i + 2], __uint_as_float(i));
+    const float4 nn = un[i];
+    snrm[e] = make_float4(nn.x, nn.y, nn.z, __uint_as_float(rank[i]));
+}
+
+// ---------------------------------------------------------------------------
+// host orchestration
+// ---------------------------------------------------------------------------
+
+static int validate_params(const PcrlVoxelParams* p, int32_t ratio[PCRL_MAX_LEVELS]) {
+    if (!p) { set_error("build_voxels: params is NULL"); return PCRL_EINVAL; }
+    if (p->n_levels < 1 || p->n_levels > PCRL_MAX_LEVELS) {
+        set_error("build_voxels: n_levels must be in [1, %d], got %d", PCRL_MAX_LEVELS, p->n_levels);
+        return PCRL_EINVAL;
+    }
+    if (p->flags != 0) { set_error("build_voxels: flags must be 0"); return PCRL_EINVAL; }
+    if (!(p->surfel_radius > 0.f) || !std::isfinite(p->surfel_radius)) {
+        set_error("build_voxels: surfel_radius must be positive and finite");
+        return PCRL_EINVAL;
+    }
+    for (int i = 0; i < p->n_levels; ++i)
+        if (!(p->level_size[i] > 0.f) || !std::isfinite(p->level_size[i])) {
+            set_error("build_voxels: level_size[%d] must be positive and finite", i);
+            return PCRL_EINVAL;
+        }
+    for (int i = 0; i + 1 < p->n_levels; ++i) {
+        const double q = (double)p->level_size[i] / (double)p->level_size[i + 1];
+        const double r = std::round(q);
+        if (r < 1.0 || std::fabs(q - r) > 1e-4 * q || r > 64.0) {
+            set_error("build_voxels: level_size[%d] = %g is not an integer multiple (1..64) of level_size[%d] = %g", i,
+                      p->level_size[i], i + 1, p->level_size[i + 1]);
+            return PCRL_EINVAL;
+        }
+        ratio[i] = (int32_t)r;
+    }
+    ratio[p->n_levels - 1] = 1;
+    return PCRL_OK;
+}
+
+static int build_impl(const float* xyz, const float* nrm, const uint32_t* label, int64_t n,
+                      const PcrlVoxelParams* params, hipStream_t s, PcrlScene* S) {
+    int32_t ratio[PCRL_MAX_LEVELS] = {1, 1, 1, 1};
+    PCRL_TRY(validate_params(params, ratio));
+    if (n < 0 || (n > 0 && (!xyz || !nrm || !label))) {
+        set_error("build_voxels: invalid point arrays (n = %lld)", (long long)n);
+        return PCRL_EINVAL;
+    }
+    if (n > (int64_t)0x7FFFFFFF) {
+        set_error("build_voxels: at most 2^31-1 points are supported");
+        return PCRL_EINVAL;
+    }
+    hipGetDevice(&S->device);
+    DevBufs& B = S->bufs;
+    B.stream = s;
+    SceneView& v = S->view;
+    const int L = params->n_levels;
+    v.nlev = L;
+    v.span[L - 1] = 1;
+    for (int i = L - 2; i >= 0; --i) v.span[i] = v.span[i + 1] * ratio[i];
+    for (int i = 0; i < PCRL_MAX_LEVELS; ++i) v.ratio[i] = ratio[i];
+    const float h = params->level_size[L - 1];
+    v.h = h;
+    v.inv_h = 1.0f / h;
+    const float r_s = params->surfel_radius;
+    v.rs2 = r_s * r_s;
+
+    // --- ingest
+    float4* unit_nrm = nullptr;
+    IngestOut io{};
+    DevBufs T;  // temporaries of the build
+    T.stream = s;
+    int rc = PCRL_OK;
+    auto fail = [&](int code) { T.release(); return code; };
+    if (n > 0) {
+        rc = T.alloc(&unit_nrm, (size_t)n);
+        if (rc) return fail(rc);
+        const unsigned nb = std::min<unsigned>(blocks_for(n), (unsigned)device_cus() * 4);
+        IngestOut *partial = nullptr, *res = nullptr;
+        if ((rc = T.alloc(&partial, nb)) || (rc = T.alloc(&res, 1))) return fail(rc);
+        hipLaunchKernelGGL(k_ingest, dim3(nb), dim3(BUILD_BLOCK), 0, s, xyz, nrm, label, n, unit_nrm, partial);
+        hipLaunchKernelGGL(k_ingest_final, dim3(1), dim3(64), 0, s, partial, (int)nb, res);
+        if (hipGetLastError() != hipSuccess || hipMemcpyAsync(&io, res, sizeof io, hipMemcpyDeviceToHost, s) != hipSuccess ||
+            hipStreamSynchronize(s) != hipSuccess) {
+            set_error("build_voxels: ingest failed: %s", hipGetErrorString(hipGetLastError()));
+            return fail(PCRL_EHIP);
+        }
+        if (io.bad & 1u) { set_error("build_voxels: non-finite point coordinate"); return fail(PCRL_EINVAL); }
+        if (io.bad & 2u) { set_error("build_voxels: zero or non-finite normal"); return fail(PCRL_EINVAL); }
+    } else {
+        for (int a = 0; a < 3; ++a) { io.lo[a] = 0.f; io.hi[a] = 0.f; }
+        io.max_label = 0;
+    }
+
+    // --- grid frame
+    float amax = 0.f;
+    for (int a = 0; a < 3; ++a) amax = std::max(amax, std::max(std::fabs(io.lo[a]), std::fabs(io.hi[a])));
+    const float pad = 1e-3f * h + 4e-6f * amax;
+    const double cell0 = (double)h * v.span[0];
+    uint64_t cells0 = 1;
+    for (int a = 0; a < 3; ++a) {
+        const double lo = (double)io.lo[a] - r_s - pad - h;
+        const double hi = (double)io.hi[a] + r_s + pad + h;
+        int64_t d0 = (int64_t)std::ceil((hi - lo) / cell0);
+        if (d0 < 1) d0 = 1;
+        if (d0 * v.span[0] >= (int64_t)1 << 22) {
+            set_error("build_voxels: leaf grid too large along axis %d (%lld leaves, max 2^22)", a,
+                      (long long)(d0 * v.span[0]));
+            return fail(PCRL_EINVAL);
+        }
+        v.dim0[a] = (int32_t)d0;
+        v.dim[a] = (int32_t)(d0 * v.span[0]);
+        v.org[a] = (float)lo;
+        v.hi[a] = (float)((double)v.org[a] + (double)v.dim[a] * h);
+        cells0 *= (uint64_t)d0;
+    }
+    v.lbits[0] = bits_for(cells0 - 1);
+    int key_bits = v.lbits[0];
+    for (int i = 1; i < L; ++i) {
+        const uint64_t r3 = (uint64_t)ratio[i - 1] * ratio[i - 1] * ratio[i - 1];
+        v.lbits[i] = bits_for(r3 - 1);
+        key_bits += v.lbits[i];
+        v.nw[i - 1] = (int32_t)((r3 + 63) / 64);
+    }
+    if (key_bits > 64) {
+        set_error("build_voxels: hierarchical key needs %d bits (max 64); use coarser levels", key_bits);
+        return fail(PCRL_EINVAL);
+    }
+    const double diag = std::sqrt((double)(io.hi[0] - io.lo[0]) * (io.hi[0] - io.lo[0]) +
+                                  (double)(io.hi[1] - io.lo[1]) * (io.hi[1] - io.lo[1]) +
+                                  (double)(io.hi[2] - io.lo[2]) * (io.hi[2] - io.lo[2]));
+    v.t_eps = params->t_eps > 0.f ? params->t_eps : (float)std::max(1e-5 * diag, 1e-6);
+    LevelShifts ls{};
+    ls.nlev = L;
+    {
+        int acc = 0;
+        for (int l = L - 1; l >= 0; --l) {
+            ls.sh[l] = acc;
+            acc += v.lbits[l];
+        }
+    }
+
+    // level-0 map (always allocated)
+    int32_t* map0 = nullptr;
+    if ((rc = B.alloc(&map0, (size_t)cells0))) return fail(rc);
+    if ((rc = fill_u32((uint32_t*)map0, 0xFFFFFFFFu, (int64_t)cells0, s))) return fail(rc);
+    v.map0 = map0;
+
+    PcrlSceneInfo& info = S->info;
+    info.n_points = n;
+    info.n_levels = L;
+    for (int a = 0; a < 3; ++a) {
+        info.dims[a] = v.dim[a];
+        info.dims0[a] = v.dim0[a];
+        info.origin[a] = v.org[a];
+        info.aabb[a] = io.lo[a];
+        info.aabb[3 + a] = io.hi[a];
+    }
+    info.leaf_size = h;
+    info.surfel_radius = r_s;
+    info.t_eps = v.t_eps;
+    info.key_bits = key_bits;
+
+    if (n == 0) {
+        uint32_t* lu = nullptr;
+        if ((rc = B.alloc(&lu, 1))) return fail(rc);
+        S->labels_u = lu;
+        info.n_labels = 0;
+        S->label_bits = 1;
+        T.release();
+        return PCRL_OK;
+    }
+
+    // --- label ranks (sorted unique labels; rank = index)
+    uint32_t *lab_sorted = nullptr, *lab_flag = nullptr, *rank = nullptr, *n_uniq = nullptr, *lab_u = nullptr;
+    if ((rc = T.alloc(&lab_sorted, (size_t)n)) || (rc = T.alloc(&lab_flag, (size_t)n)) ||
+        (rc = T.alloc(&rank, (size_t)n)) || (rc = T.alloc(&n_uniq, 1)) || (rc = B.alloc(&lab_u, (size_t)n)))
+        return fail(rc);
+    if (hipMemcpyAsync(lab_sorted, label, (size_t)n * 4, hipMemcpyDeviceToDevice, s) != hipSuccess) {
+        set_error("build_voxels: label copy failed");
+        return fail(PCRL_EHIP);
+    }
+    if ((rc = radix_sort_u32(lab_sorted, nullptr, n, bits_for(io.max_label), s))) return fail(rc);
+    hipLaunchKernelGGL(k_unique_flags_u32, dim3(blocks_for(n)), dim3(BUILD_BLOCK), 0, s, lab_sorted, n, lab_flag);
+    if ((rc = scan_u32(lab_flag, lab_flag, n, n_uniq, s))) return fail(rc);
+    hipLaunchKernelGGL(k_unique_compact_u32, dim3(blocks_for(n)), dim3(BUILD_BLOCK), 0, s, lab_sorted, n, lab_flag,
+                       lab_u);
+    hipLaunchKernelGGL(k_label_rank, dim3(blocks_for(n)), dim3(BUILD_BLOCK), 0, s, label, n, lab_u, n_uniq, rank);
+    S->labels_u = lab_u;
+
+    // --- dilated key counts
+    KeyParams kp;
+    kp.v = v;
+    kp.r_s = r_s;
+    kp.pad = pad;
+    uint32_t *cnt = nullptr, *tot = nullptr;
+    if ((rc = T.alloc(&cnt, (size_t)n)) || (rc = T.alloc(&tot, 2))) return fail(rc);
+    hipLaunchKernelGGL(k_key_count, dim3(blocks_for(n)), dim3(BUILD_BLOCK), 0, s, kp, xyz, unit_nrm, n, cnt);
+    if ((rc = scan_u32(cnt, cnt, n, tot, s))) return fail(rc);
+    if (hipMemcpyAsync(tot + 1, n_uniq, 4, hipMemcpyDeviceToDevice, s) != hipSuccess) return fail(PCRL_EHIP);
+    uint32_t host_tot[2] = {0, 0};
+    if (hipMemcpyAsync(host_tot, tot, 8, hipMemcpyDeviceToHost, s) != hipSuccess || hipStreamSynchronize(s) != hipSuccess) {
+        set_error("build_voxels: key count failed: %s", hipGetErrorString(hipGetLastError()));
+        return fail(PCRL_EHIP);
+    }
+    const int64_t m = host_tot[0];
+    info.n_labels = (int32_t)host_tot[1];
+    S->label_bits = bits_for((uint64_t)host_tot[1]);  // ranks 0..n-1 stored +1
+    info.n_entries = m;
+
+    // --- emit and sort (key, point id)
+    uint64_t* keys = nullptr;
+    uint32_t* ids = nullptr;
+    if ((rc = T.alloc(&keys, (size_t)m)) || (rc = B.alloc(&ids, (size_t)m))) return fail(rc);
+    hipLaunchKernelGGL(k_key_emit, dim3(blocks_for(n)), dim3(BUILD_BLOCK), 0, s, kp, xyz, unit_nrm, n, cnt, keys, ids);
+    if ((rc = radix_sort_u64(keys, ids, m, key_bits, s))) return fail(rc);
+    S->entry_point = ids;
+
+    // --- per-level node boundaries
+    uint32_t *scans = nullptr, *ltot = nullptr;
+    if ((rc = T.alloc(&scans, (size_t)L * m)) || (rc = T.alloc(&ltot, PCRL_MAX_LEVELS))) return fail(rc);
+    hipLaunchKernelGGL(k_level_flags, dim3(blocks_for(m)), dim3(BUILD_BLOCK), 0, s, keys, m, ls, scans);
+    for (int l = 0; l < L; ++l)
+        if ((rc = scan_u32(scans + (size_t)l * m, scans + (size_t)l * m, m, ltot + l, s))) return fail(rc);
+    uint32_t host_nodes[PCRL_MAX_LEVELS] = {0, 0, 0, 0};
+    if (hipMemcpyAsync(host_nodes, ltot, 4 * L, hipMemcpyDeviceToHost, s) != hipSuccess ||
+        hipStreamSynchronize(s) != hipSuccess) {
+        set_error("build_voxels: level scan failed: %s", hipGetErrorString(hipGetLastError()));
+        return fail(PCRL_EHIP);
+    }
+    for (int l = 0; l < L; ++l) {
+        info.n_nodes[l] = host_nodes[l];
+        v.nn[l] = host_nodes[l];
+    }
+    const int64_t n_leaves = host_nodes[L - 1];
+    info.n_leaves = n_leaves;
+
+    HierOut ho{};
+    ho.map0 = map0;
+    for (int l = 0; l + 1 < L; ++l) {
+        const size_t words = (size_t)host_nodes[l] * v.nw[l];
+        uint64_t* mk = nullptr;
+        uint32_t* bs = nullptr;
+        uint32_t* fc = nullptr;
+        if ((rc = B.alloc(&mk, words)) || (rc = B.alloc(&bs, words)) || (rc = T.alloc(&fc, host_nodes[l])))
+            return fail(rc);
+        if ((rc = fill_u64(mk, 0ull, (int64_t)words, s))) return fail(rc);
+        ho.mask[l] = mk;
+        ho.first_child[l] = fc;
+        v.mask[l] = mk;
+        v.base[l] = bs;
+    }
+    uint2* leaf = nullptr;
+    uint64_t* lkey = nullptr;
+    if ((rc = B.alloc(&leaf, (size_t)n_leaves)) || (rc = B.alloc(&lkey, (size_t)n_leaves))) return fail(rc);
+    ho.leaf = leaf;
+    ho.leaf_key = lkey;
+    hipLaunchKernelGGL(k_hier_link, dim3(blocks_for(m)), dim3(BUILD_BLOCK), 0, s, keys, m, ls, v, scans, ho);
+    for (int l = 0; l + 1 < L; ++l)
+        hipLaunchKernelGGL(k_brick_base, dim3(blocks_for(host_nodes[l])), dim3(BUILD_BLOCK), 0, s, ho.mask[l],
+                           ho.first_child[l], (int64_t)host_nodes[l], v.nw[l], (uint32_t*)v.base[l]);
+    hipLaunchKernelGGL(k_leaf_counts, dim3(blocks_for(n_leaves)), dim3(BUILD_BLOCK), 0, s, leaf, n_leaves, m);
+    v.leaf = leaf;
+    S->leaf_range = leaf;
+    S->leaf_key = lkey;
+
+    // --- surfel streams in leaf order
+    float4 *spos = nullptr, *snrm = nullptr;
+    if ((rc = B.alloc(&spos, (size_t)m)) || (rc = B.alloc(&snrm, (size_t)m))) return fail(rc);
+    hipLaunchKernelGGL(k_gather_surfels, dim3(blocks_for(m)), dim3(BUILD_BLOCK), 0, s, ids, m, xyz, unit_nrm, rank,
+                       spos, snrm);
+    v.spos = spos;
+    v.snrm = snrm;
+    if (hipGetLastError() != hipSuccess) {
+        set_error("build_voxels: kernel launch failed");
+        return fail(PCRL_EHIP);
+    }
+    int64_t bytes = (int64_t)cells0 * 4 + (int64_t)n * 4 + m * (4 + 32) + n_leaves * 16;
+    for (int l = 0; l + 1 < L; ++l) bytes += (int64_t)host_nodes[l] * v.nw[l] * 12;
+    info.device_bytes = bytes;
+    T.release();
+    return PCRL_OK;
+}
+
+}  // namespace pcrl
+
+using namespace pcrl;
+
+extern "C" int build_voxels(const float* xyz, const float* normal, const uint32_t* label, int64_t n_points,
+                            const PcrlVoxelParams* params, pcrl_stream_t stream, PcrlScene** out) {
+    clear_error();
+    if (!out) {
+        set_error("build_voxels: out is NULL");
+        return PCRL_EINVAL;
+    }
+    *out = nullptr;
+    PcrlScene* S = new (std::nothrow) PcrlScene();
+    if (!S) {
+        set_error("build_voxels: host allocation failed");
+        return PCRL_ENOMEM;
+    }
+    int rc = build_impl(xyz, normal, label, n_points, params, (hipStream_t)stream, S);
+    if (rc != PCRL_OK) {
+        S->bufs.release();
+        delete S;
+        return rc;
+    }
+    *out = S;
+    return PCRL_OK;
+}
+
+extern "C" int scene_info(const PcrlScene* scene, PcrlSceneInfo* out) {
+    clear_error();
+    if (!scene || !out) {
+        set_error("scene_info: NULL argument");
+        return PCRL_EINVAL;
+    }
+    *out = scene->info;
+    return PCRL_OK;
+}
+
+extern "C" int scene_leaf_table(const PcrlScene* scene, uint64_t* leaf_key, uint32_t* leaf_begin,
+                                uint32_t* leaf_count, uint32_t* entry_point, pcrl_stream_t stream) {
+    clear_error();
+    if (!scene) {
+        set_error("scene_leaf_table: scene is NULL");
+        return PCRL_EINVAL;
+    }
+    hipStream_t s = (hipStream_t)stream;
+    const int64_t nl = scene->info.n_leaves;
+    const int64_t m = scene->info.n_entries;
+    if (leaf_key && nl)
+        PCRL_TRY_HIP(hipMemcpyAsync(leaf_key, scene->leaf_key, (size_t)nl * 8, hipMemcpyDeviceToDevice, s));
+    if ((leaf_begin || leaf_count) && nl) {
+        hipLaunchKernelGGL(k_split_leaf, dim3(blocks_for(nl)), dim3(BUILD_BLOCK), 0, s, scene->leaf_range, nl,
+                           leaf_begin, leaf_count);
+        PCRL_TRY_HIP(hipGetLastError());
+    }
+    if (entry_point && m)
+        PCRL_TRY_HIP(hipMemcpyAsync(entry_point, scene->entry_point, (size_t)m * 4, hipMemcpyDeviceToDevice, s));
+    PCRL_TRY_HIP(hipStreamSynchronize(s));
+    return PCRL_OK;
+}
+
+extern "C" int release_scene(PcrlScene* scene) {
+    clear_error();
+    if (!scene) return PCRL_OK;
+    scene->bufs.release();
+    delete scene;
+    return PCRL_OK;
+}

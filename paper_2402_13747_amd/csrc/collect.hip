@@ -1,0 +1,319 @@
+// collect.hip -- coarse paths from reception records (paper, Section 2.2.3).
+//
+// A coarse path is a reception keyed by (TX, RX, number of reflections, the
+// labels of its interactions in order); Section 2.2.3 caps the number of kept
+// paths with the same labels in the same order at kappa.  Here:
+//   1. every record gets a packed multi-word key (tx | rx | b | lab_0..lab_K-1,
+//      most significant first; a label is its rank + 1, 0 past b), or leaf
+//      indices of the interaction points instead of labels;
+//   2. records are sorted by (key, len_poly, ray) with LSD radix passes over
+//      a permutation (ray bits, then len_poly bits, then key words);
+//   3. key boundaries -> per-key count and in-key rank; rows with rank <
+//      kappa are compacted into the caller's arrays.
+// The output order is fully determined by the records, so it is bitwise
+// reproducible even though records are appended in a racy order.
+#include "internal.h"
+
+#include <algorithm>
+#include <cmath>
+
+namespace pcrl {
+
+constexpr int MAXW = 6;
+
+struct KeySpec {
+    int32_t W;         // 64-bit words per key
+    int32_t K;
+    int32_t bt, br, bb, bl;
+    int32_t mode;      // PCRL_KEY_LABELS / PCRL_KEY_LEAVES
+    uint32_t n_rays;
+    uint32_t n_total;
+    float org[3];
+    float inv_h;
+    int32_t dim[3];
+};
+
+__device__ __forceinline__ void put_bits(uint64_t* w, int pos, int width, uint64_t val) {
+    const int wi = pos >> 6, sh = pos & 63;
+    w[wi] |= val << sh;
+    if (sh + width > 64) w[wi + 1] |= val >> (64 - sh);
+}
+
+__global__ void k_path_keys(const uint4* rec, uint32_t n, const float4* hist, KeySpec ks, uint64_t* words,
+                            uint32_t* lp_bits, uint32_t* ray) {
+    const uint32_t i = blockIdx.x * blockDim.x + threadIdx.x;
+    if (i >= n) return;
+    const uint4 r = rec[i];
+    const uint32_t g = r.x;
+    const uint32_t rx = r.y & 0xFFFFu;
+    const uint32_t b = r.y >> 16;
+    const uint32_t tx = g / ks.n_rays;
+    uint64_t w[MAXW] = {0, 0, 0, 0, 0, 0};
+    for (int k = 0; k < ks.K; ++k) {
+        uint64_t val = 0;
+        if ((uint32_t)k < b) {
+            const float4 h = hist[(size_t)k * ks.n_total + g];
+            if (ks.mode == PCRL_KEY_LABELS) {
+                val = (uint64_t)__float_as_uint(h.w) + 1;
+            } else {
+                const float p[3] = {h.x, h.y, h.z};
+                int64_t c[3];
+                for (int a = 0; a < 3; ++a) {
+                    int ci = (int)floorf((p[a] - ks.org[a]) * ks.inv_h);
+                    c[a] = min(max(ci, 0), ks.dim[a] - 1);
+                }
+                val = (uint64_t)(c[0] + (int64_t)ks.dim[0] * (c[1] + (int64_t)ks.dim[1] * c[2])) + 1;
+            }
+        }
+        put_bits(w, (ks.K - 1 - k) * ks.bl, ks.bl, val);
+    }
+    int pos = ks.K * ks.bl;
+    put_bits(w, pos, ks.bb, b);
+    pos += ks.bb;
+    put_bits(w, pos, ks.br, rx);
+    pos += ks.br;
+    put_bits(w, pos, ks.bt, tx);
+    for (int q = 0; q < ks.W; ++q) words[(size_t)q * n + i] = w[q];
+    lp_bits[i] = r.z;  // len_poly >= 0: IEEE bits order like the values
+    ray[i] = g;
+}
+
+__global__ void k_gather_u64(const uint64_t* src, const uint32_t* perm, uint32_t n, uint64_t* dst) {
+    const uint32_t i = blockIdx.x * blockDim.x + threadIdx.x;
+    if (i < n) dst[i] = src[perm[i]];
+}
+
+__global__ void k_gather_u32(const uint32_t* src, const uint32_t* perm, uint32_t n, uint32_t* dst) {
+    const uint32_t i = blockIdx.x * blockDim.x + threadIdx.x;
+    if (i < n) dst[i] = src[perm[i]];
+}
+
+__global__ void k_key_flags(const uint64_t* words, int W, const uint32_t* perm, uint32_t n, uint32_t* flag) {
+    const uint32_t i = blockIdx.x * blockDim.x + threadIdx.x;
+    if (i >= n) return;
+    uint32_t f = 1;
+    if (i > 0) {
+        f = 0;
+        const uint32_t a = perm[i], b = perm[i - 1];
+        for (int q = 0; q < W; ++q) f |= words[(size_t)q * n + a] != words[(size_t)q * n + b] ? 1u : 0u;
+    }
+    flag[i] = f;
+}
+
+// key index of sorted position i (flags recomputed from keys)
+__global__ void k_key_starts(const uint64_t* words, int W, const uint32_t* perm, uint32_t n, const uint32_t* kscan,
+                             uint32_t* start) {
+    const uint32_t i = blockIdx.x * blockDim.x + threadIdx.x;
+    if (i >= n) return;
+    bool f = (i == 0);
+    if (!f) {
+        const uint32_t a = perm[i], b = perm[i - 1];
+        for (int q = 0; q < W; ++q) f |= words[(size_t)q * n + a] != words[(size_t)q * n + b];
+    }
+    if (f) start[kscan[i]] = i;
+}
+
+__global__ void k_keep_flags(const uint64_t* words, int W, const uint32_t* perm, uint32_t n, const uint32_t* kscan,
+                             const uint32_t* start, int32_t kappa, uint32_t* keep) {
+    const uint32_t i = blockIdx.x * blockDim.x + threadIdx.x;
+    if (i >= n) return;
+    bool f = (i == 0);
+    if (!f) {
+        const uint32_t a = perm[i], b = perm[i - 1];
+        for (int q = 0; q < W; ++q) f |= words[(size_t)q * n + a] != words[(size_t)q * n + b];
+    }
+    const uint32_t key = kscan[i] + (f ? 1u : 0u) - 1u;
+    keep[i] = (i - start[key]) < (uint32_t)kappa ? 1u : 0u;
+}
+
+struct OutArrays {
+    int32_t* tx;
+    int32_t* rx;
+    int32_t* n_refl;
+    int64_t* key;
+    int64_t* count;
+    int32_t* rank;
+    int64_t* ray;
+    float* len_poly;
+    float* len_unf;
+    float* points;
+};
+
+__global__ void k_write_rows(const uint4* rec, const float4* hist, const uint64_t* words, int W, const uint32_t* perm,
+                             uint32_t n, const uint32_t* kscan, const uint32_t* start, const uint32_t* n_keys,
+                             const uint32_t* keep_scan, int32_t kappa, KeySpec ks, const uint32_t* labels_u,
+                             OutArrays o) {
+    const uint32_t i = blockIdx.x * blockDim.x + threadIdx.x;
+    if (i >= n) return;
+    bool f = (i == 0);
+    if (!f) {
+        const uint32_t a = perm[i], b = perm[i - 1];
+        for (int q = 0; q < W; ++q) f |= words[(size_t)q * n + a] != words[(size_t)q * n + b];
+    }
+    const uint32_t key = kscan[i] + (f ? 1u : 0u) - 1u;
+    const uint32_t rank = i - start[key];
+    if (rank >= (uint32_t)kappa) return;
+    const uint32_t end = (key + 1 < *n_keys) ? start[key + 1] : n;
+    const uint32_t row = keep_scan[i];
+    const uint4 r = rec[perm[i]];
+    const uint32_t g = r.x;
+    const uint32_t b = r.y >> 16;
+    if (o.tx) o.tx[row] = (int32_t)(g / ks.n_rays);
+    if (o.rx) o.rx[row] = (int32_t)(r.y & 0xFFFFu);
+    if (o.n_refl) o.n_refl[row] = (int32_t)b;
+    if (o.count) o.count[row] = (int64_t)(end - start[key]);
+    if (o.rank) o.rank[row] = (int32_t)rank;
+    if (o.ray) o.ray[row] = (int64_t)g;
+    if (o.len_poly) o.len_poly[row] = __uint_as_float(r.z);
+    if (o.len_unf) o.len_unf[row] = __uint_as_float(r.w);
+    for (int k = 0; k < ks.K; ++k) {
+        float4 h = make_float4(NAN, NAN, NAN, 0.f);
+        if ((uint32_t)k < b) h = hist[(size_t)k * ks.n_total + g];
+        if (o.key) {
+            int64_t kv = -1;
+            if ((uint32_t)k < b) {
+                if (ks.mode == PCRL_KEY_LABELS) {
+                    kv = (int64_t)labels_u[__float_as_uint(h.w)];
+                } else {
+                    int64_t c[3];
+                    const float p[3] = {h.x, h.y, h.z};
+                    for (int a = 0; a < 3; ++a) {
+                        int ci = (int)floorf((p[a] - ks.org[a]) * ks.inv_h);
+                        c[a] = min(max(ci, 0), ks.dim[a] - 1);
+                    }
+                    kv = c[0] + (int64_t)ks.dim[0] * (c[1] + (int64_t)ks.dim[1] * c[2]);
+                }
+            }
+            o.key[(size_t)row * ks.K + k] = kv;
+        }
+        if (o.points) {
+            o.points[((size_t)row * ks.K + k) * 3 + 0] = h.x;
+            o.points[((size_t)row * ks.K + k) * 3 + 1] = h.y;
+            o.points[((size_t)row * ks.K + k) * 3 + 2] = h.z;
+        }
+    }
+}
+
+static int bits_for(uint64_t max_value) {
+    int b = 1;
+    while (b < 64 && (max_value >> b) != 0) ++b;
+    return b;
+}
+
+static unsigned nblk(uint32_t n) { return std::max(1u, (n + 255u) / 256u); }
+
+static int collect_impl(PcrlLaunch* L, int32_t kappa, int32_t key_mode, PcrlPaths* out, hipStream_t s) {
+    const PcrlScene* S = L->scene;
+    const int K = L->K;
+    uint32_t n_rec = 0;
+    if (L->stream != s) PCRL_TRY_HIP(hipStreamSynchronize(L->stream));
+    PCRL_TRY_HIP(hipMemcpyAsync(&n_rec, L->counters + PCRL_CNT_REC(K), 4, hipMemcpyDeviceToHost, s));
+    PCRL_TRY_HIP(hipStreamSynchronize(s));
+    out->n_rows = 0;
+    out->n_keys = 0;
+    if ((int64_t)n_rec > L->rec_cap) {
+        out->n_rows = -1;
+        set_error("collect_paths: the launch produced %u reception records but its capacity is %lld; "
+                  "relaunch with record_capacity >= %u",
+                  n_rec, (long long)L->rec_cap, n_rec);
+        return PCRL_EOVERFLOW;
+    }
+    if (n_rec == 0) return PCRL_OK;
+    const uint32_t n = n_rec;
+
+    KeySpec ks{};
+    ks.K = K;
+    ks.mode = key_mode;
+    ks.n_rays = (uint32_t)L->n_rays;
+    ks.n_total = (uint32_t)L->n_total;
+    ks.bt = bits_for((uint64_t)(L->n_tx - 1));
+    ks.br = bits_for((uint64_t)std::max(L->n_rx - 1, 0));
+    ks.bb = bits_for((uint64_t)K);
+    if (key_mode == PCRL_KEY_LABELS) {
+        ks.bl = bits_for((uint64_t)S->info.n_labels);
+    } else {
+        const uint64_t cells = (uint64_t)S->view.dim[0] * S->view.dim[1] * S->view.dim[2];
+        ks.bl = bits_for(cells);
+        if (ks.bl > 62) {
+            set_error("collect_paths: leaf grid too large for leaf-index keys");
+            return PCRL_EINVAL;
+        }
+    }
+    for (int a = 0; a < 3; ++a) {
+        ks.org[a] = S->view.org[a];
+        ks.dim[a] = S->view.dim[a];
+    }
+    ks.inv_h = S->view.inv_h;
+    const int total_bits = ks.bt + ks.br + ks.bb + K * ks.bl;
+    ks.W = (total_bits + 63) / 64;
+    if (ks.W > MAXW) {
+        set_error("collect_paths: coarse-path key needs %d bits (max %d)", total_bits, 64 * MAXW);
+        return PCRL_EINVAL;
+    }
+
+    DevBufs T;
+    T.stream = s;
+    auto fail = [&](int code) { T.release(); return code; };
+    uint64_t *words = nullptr, *tmp64 = nullptr;
+    uint32_t *lp = nullptr, *ray = nullptr, *perm = nullptr, *tmp32 = nullptr, *kscan = nullptr, *start = nullptr,
+             *keep = nullptr, *tots = nullptr;
+    int rc;
+    if ((rc = T.alloc(&words, (size_t)ks.W * n)) || (rc = T.alloc(&tmp64, n)) || (rc = T.alloc(&lp, n)) ||
+        (rc = T.alloc(&ray, n)) || (rc = T.alloc(&perm, n)) || (rc = T.alloc(&tmp32, n)) ||
+        (rc = T.alloc(&kscan, n)) || (rc = T.alloc(&start, n)) || (rc = T.alloc(&keep, n)) || (rc = T.alloc(&tots, 2)))
+        return fail(rc);
+    hipLaunchKernelGGL(k_path_keys, dim3(nblk(n)), dim3(256), 0, s, L->rec, n, L->hist, ks, words, lp, ray);
+    if ((rc = iota_u32(perm, n, s))) return fail(rc);
+    // LSD: ray id, then len_poly, then key words from least significant
+    hipLaunchKernelGGL(k_gather_u32, dim3(nblk(n)), dim3(256), 0, s, ray, perm, n, tmp32);
+    if ((rc = radix_sort_u32(tmp32, perm, n, bits_for((uint64_t)L->n_total), s))) return fail(rc);
+    hipLaunchKernelGGL(k_gather_u32, dim3(nblk(n)), dim3(256), 0, s, lp, perm, n, tmp32);
+    if ((rc = radix_sort_u32(tmp32, perm, n, 32, s))) return fail(rc);
+    for (int q = 0; q < ks.W; ++q) {
+        const int wb = (q == ks.W - 1) ? total_bits - 64 * q : 64;
+        hipLaunchKernelGGL(k_gather_u64, dim3(nblk(n)), dim3(256), 0, s, words + (size_t)q * n, perm, n, tmp64);
+        if ((rc = radix_sort_u64(tmp64, perm, n, wb, s))) return fail(rc);
+    }
+    // key boundaries
+    hipLaunchKernelGGL(k_key_flags, dim3(nblk(n)), dim3(256), 0, s, words, ks.W, perm, n, kscan);
+    if ((rc = scan_u32(kscan, kscan, n, tots, s))) return fail(rc);
+    hipLaunchKernelGGL(k_key_starts, dim3(nblk(n)), dim3(256), 0, s, words, ks.W, perm, n, kscan, start);
+    hipLaunchKernelGGL(k_keep_flags, dim3(nblk(n)), dim3(256), 0, s, words, ks.W, perm, n, kscan, start, kappa, keep);
+    if ((rc = scan_u32(keep, keep, n, tots + 1, s))) return fail(rc);
+    uint32_t host[2] = {0, 0};
+    if (hipMemcpyAsync(host, tots, 8, hipMemcpyDeviceToHost, s) != hipSuccess || hipStreamSynchronize(s) != hipSuccess) {
+        set_error("collect_paths: kernels failed: %s", hipGetErrorString(hipGetLastError()));
+        return fail(PCRL_EHIP);
+    }
+    out->n_keys = host[0];
+    out->n_rows = host[1];
+    if ((int64_t)host[1] > out->capacity) {
+        set_error("collect_paths: %u rows do not fit in capacity %lld", host[1], (long long)out->capacity);
+        return fail(PCRL_EOVERFLOW);
+    }
+    OutArrays oa{out->tx, out->rx, out->n_refl, out->key, out->count, out->rank, out->ray, out->len_poly, out->len_unf,
+                 out->points};
+    hipLaunchKernelGGL(k_write_rows, dim3(nblk(n)), dim3(256), 0, s, L->rec, L->hist, words, ks.W, perm, n, kscan,
+                       start, tots, keep, kappa, ks, S->labels_u, oa);
+    if (hipGetLastError() != hipSuccess || hipStreamSynchronize(s) != hipSuccess) {
+        set_error("collect_paths: output kernel failed: %s", hipGetErrorString(hipGetLastError()));
+        return fail(PCRL_EHIP);
+    }
+    T.release();
+    return PCRL_OK;
+}
+
+}  // namespace pcrl
+
+using namespace pcrl;
+
+extern "C" int collect_paths(PcrlLaunch* launch, int32_t kappa, int32_t key_mode, PcrlPaths* out,
+                             pcrl_stream_t stream) {
+    clear_error();
+    if (!launch || !out || kappa < 1 || (key_mode != PCRL_KEY_LABELS && key_mode != PCRL_KEY_LEAVES) ||
+        out->capacity < 0) {
+        set_error("collect_paths: invalid arguments (kappa >= 1, key_mode 0 or 1, capacity >= 0)");
+        return PCRL_EINVAL;
+    }
+    return collect_impl(launch, kappa, key_mode, out, (hipStream_t)stream);
+}

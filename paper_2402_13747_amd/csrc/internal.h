@@ -1,0 +1,215 @@
+// internal.h -- shared declarations of the gfx950 coarse-path ray launcher.
+//
+// Device helpers (wave64 ballots and scans), the scene view that every
+// kernel receives by value, the opaque PcrlScene / PcrlLaunch objects and
+// the host-side primitives (allocation, scan, radix sort) shared by the
+// translation units.
+#pragma once
+
+#include <hip/hip_runtime.h>
+
+#include <cstdarg>
+#include <cstdint>
+#include <string>
+#include <vector>
+
+#include "pcrl.h"
+
+namespace pcrl {
+
+// ---------------------------------------------------------------------------
+// error state
+// ---------------------------------------------------------------------------
+
+void set_error(const char* fmt, ...) __attribute__((format(printf, 1, 2)));
+void clear_error();
+const char* get_error();
+
+#define PCRL_TRY_HIP(call)                                                                        \
+    do {                                                                                          \
+        hipError_t e_ = (call);                                                                   \
+        if (e_ != hipSuccess) {                                                                   \
+            ::pcrl::set_error("%s failed: %s (%s:%d)", #call, hipGetErrorString(e_), __FILE__,   \
+                              __LINE__);                                                          \
+            return e_ == hipErrorOutOfMemory ? PCRL_ENOMEM : PCRL_EHIP;                           \
+        }                                                                                         \
+    } while (0)
+
+#define PCRL_TRY(call)              \
+    do {                            \
+        int s_ = (call);            \
+        if (s_ != PCRL_OK) return s_; \
+    } while (0)
+
+// ---------------------------------------------------------------------------
+// device memory: stream-ordered pool allocations
+// ---------------------------------------------------------------------------
+
+int dalloc(void** p, size_t bytes, hipStream_t s);
+void dfree(void* p, hipStream_t s);
+
+// Owns a list of device allocations released together (stream ordered).
+struct DevBufs {
+    std::vector<void*> ptrs;
+    hipStream_t stream = nullptr;
+    template <typename T>
+    int alloc(T** p, size_t count) {
+        void* q = nullptr;
+        int rc = dalloc(&q, count * sizeof(T), stream);
+        if (rc != PCRL_OK) return rc;
+        ptrs.push_back(q);
+        *p = static_cast<T*>(q);
+        return PCRL_OK;
+    }
+    void release() {
+        for (void* q : ptrs) dfree(q, stream);
+        ptrs.clear();
+    }
+};
+
+// ---------------------------------------------------------------------------
+// primitives (prims.hip)
+// ---------------------------------------------------------------------------
+
+// Exclusive prefix sum of n uint32 values (in may equal out).  If total is
+// non-null the sum of all n values is written to *total (device).
+int scan_u32(const uint32_t* in, uint32_t* out, int64_t n, uint32_t* total, hipStream_t s);
+
+// Stable LSD radix sort of (key, value) pairs on the low `bits` key bits.
+// keys/vals are sorted in place (a temporary double buffer is used).
+// vals may be null (keys only).
+int radix_sort_u64(uint64_t* keys, uint32_t* vals, int64_t n, int bits, hipStream_t s);
+int radix_sort_u32(uint32_t* keys, uint32_t* vals, int64_t n, int bits, hipStream_t s);
+
+// Fill helpers.
+int fill_u32(uint32_t* p, uint32_t v, int64_t n, hipStream_t s);
+int fill_u64(uint64_t* p, uint64_t v, int64_t n, hipStream_t s);
+int iota_u32(uint32_t* p, int64_t n, hipStream_t s);
+
+// Number of CUs of the current device (cached).
+int device_cus();
+
+// ---------------------------------------------------------------------------
+// device helpers
+// ---------------------------------------------------------------------------
+
+__device__ __forceinline__ uint32_t lane_id() { return __lane_id(); }
+
+__device__ __forceinline__ uint64_t lanemask_lt() {
+    return (uint64_t(1) << lane_id()) - 1;
+}
+
+// Inclusive wave64 scan.
+__device__ __forceinline__ uint32_t wave_incl_scan(uint32_t x) {
+#pragma unroll
+    for (int off = 1; off < 64; off <<= 1) {
+        uint32_t y = __shfl_up(x, off, 64);
+        if ((int)lane_id() >= off) x += y;
+    }
+    return x;
+}
+
+__device__ __forceinline__ uint64_t wave_sum_u64(uint64_t x) {
+#pragma unroll
+    for (int off = 32; off > 0; off >>= 1) x += __shfl_xor(x, off, 64);
+    return x;
+}
+
+// Append `want` items per lane to a global list with one atomic per wave.
+// Returns this lane's first slot (only meaningful where want != 0).
+__device__ __forceinline__ uint32_t wave_append(uint32_t* counter, uint32_t want) {
+    uint32_t incl = wave_incl_scan(want);
+    uint32_t total = __shfl(incl, 63, 64);
+    uint32_t base = 0;
+    if (total) {
+        if (lane_id() == 63) base = atomicAdd(counter, total);
+        base = __shfl(base, 63, 64);
+    }
+    return base + incl - want;
+}
+
+__device__ __forceinline__ float as_float(uint32_t u) { return __uint_as_float(u); }
+__device__ __forceinline__ uint32_t as_uint(float f) { return __float_as_uint(f); }
+
+// ---------------------------------------------------------------------------
+// scene view: everything a traversal kernel needs, passed by value
+// ---------------------------------------------------------------------------
+
+struct SceneView {
+    float org[3];          // grid origin
+    float hi[3];           // grid far corner (org + dims * h)
+    float h;               // leaf edge
+    float inv_h;
+    float rs2;             // r_s^2
+    float t_eps;
+    int32_t dim[3];        // leaf grid dims
+    int32_t dim0[3];       // level-0 grid dims
+    int32_t nlev;
+    int32_t span[PCRL_MAX_LEVELS];   // leaves per cell edge at level i (span[nlev-1] = 1)
+    int32_t ratio[PCRL_MAX_LEVELS];  // span[i] / span[i+1]
+    int32_t lbits[PCRL_MAX_LEVELS];  // key bits of level i (level 0: linear coarse index)
+    int32_t nw[PCRL_MAX_LEVELS];     // 64-bit mask words of a level-i brick (i < nlev-1)
+    uint32_t nn[PCRL_MAX_LEVELS];    // occupied nodes per level (bounds of every index)
+    const int32_t* map0;             // [dim0 x*y*z] level-0 node or -1
+    const uint64_t* mask[PCRL_MAX_LEVELS - 1];  // child occupancy bricks of level i
+    const uint32_t* base[PCRL_MAX_LEVELS - 1];  // child index of the first set bit of each word
+    const uint2* leaf;               // per leaf: (first entry, entry count)
+    const float4* spos;              // per entry: x, y, z, point id (bits)
+    const float4* snrm;              // per entry: unit normal, label rank (bits)
+};
+
+__host__ __device__ inline uint64_t leaf_key_of(const SceneView& v, int ix, int iy, int iz) {
+    const int s0 = v.span[0];
+    uint64_t k = (uint64_t)((ix / s0) + v.dim0[0] * ((iy / s0) + v.dim0[1] * (iz / s0)));
+    for (int i = 1; i < v.nlev; ++i) {
+        const int s = v.span[i];
+        const int r = v.ratio[i - 1];
+        const int lx = (ix / s) % r, ly = (iy / s) % r, lz = (iz / s) % r;
+        k = (k << v.lbits[i]) | (uint64_t)(lx + r * (ly + r * lz));
+    }
+    return k;
+}
+
+}  // namespace pcrl
+
+// ---------------------------------------------------------------------------
+// opaque objects
+// ---------------------------------------------------------------------------
+
+struct PcrlScene {
+    int device = 0;
+    pcrl::SceneView view{};
+    pcrl::DevBufs bufs;
+    PcrlSceneInfo info{};
+    uint32_t* labels_u = nullptr;   // distinct labels, ascending (rank -> label)
+    uint64_t* leaf_key = nullptr;   // per leaf hierarchical key
+    uint32_t* entry_point = nullptr;  // per entry: point id (leaf order)
+    uint2* leaf_range = nullptr;
+    int32_t label_bits = 1;         // bits to hold a label rank + 1
+};
+
+struct PcrlLaunch {
+    const PcrlScene* scene = nullptr;
+    hipStream_t stream = nullptr;
+    pcrl::DevBufs bufs;
+    int64_t n_rays = 0, n_total = 0;
+    int32_t n_tx = 0, n_rx = 0, K = 0;
+    int32_t flags = 0;
+    float sigma = 1.25f, alpha = 0.f;
+    int64_t rec_cap = 0;
+    float4* hist = nullptr;         // [K][n_total]: interaction point, label rank (bits)
+    uint4* rec = nullptr;           // [rec_cap]: ray, rx | b << 16, len_poly, len_unf
+    uint32_t* counters = nullptr;   // [0..K+1] active rays per bounce, [K+2] records
+    unsigned long long* stats = nullptr;  // [8] device counters (PCRL_LAUNCH_STATS)
+    std::vector<hipEvent_t> events; // 2 per bounce (PCRL_LAUNCH_TIMING)
+};
+
+// counters layout
+#define PCRL_CNT_REC(K) ((K) + 2)
+#define PCRL_NCOUNTERS(K) ((K) + 3)
+
+// internal entry points of the launch translation unit (used by batching)
+namespace pcrl {
+int launch_enqueue(PcrlLaunch* L, const float* tx, const float* rx, const float* dirs, int32_t* hit_id,
+                   float* hit_t);
+}

@@ -1,0 +1,96 @@
+"""The C-ABI library loads and exports every function include/pcrl.h declares (CPU only).
+
+No compute call is made here: without a GPU the tests only check symbols,
+struct layouts and argument validation paths that fail before any HIP call.
+"""
+import ctypes as C
+import os
+import re
+
+import pytest
+
+ROOT = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
+HEADERS = [os.path.join(ROOT, "include", f) for f in os.listdir(os.path.join(ROOT, "include")) if f.endswith(".h")]
+
+
+def _declared_functions():
+    names = set()
+    for h in HEADERS:
+        src = open(h).read()
+        src = re.sub(r"/\*.*?\*/", "", src, flags=re.S)
+        src = re.sub(r"//[^\n]*", "", src)
+        for m in re.finditer(r"^\s*(?:const\s+)?[A-Za-z_][A-Za-z0-9_]*\s*\**\s+\**([a-z_][a-z0-9_]*)\s*\(", src, re.M):
+            names.add(m.group(1))
+    return names
+
+
+@pytest.fixture(scope="module")
+def pcrl():
+    import torch  # noqa: F401
+    import paper_2402_13747_amd as p
+    return p
+
+
+def test_header_parses():
+    names = _declared_functions()
+    for must in ("build_voxels", "launch_rays", "collect_paths", "release_scene", "release_launch", "last_error"):
+        assert must in names
+
+
+def test_library_exports_every_declared_symbol(pcrl):
+    lib = C.CDLL(pcrl.library_path())
+    missing = [n for n in sorted(_declared_functions()) if not hasattr(lib, n)]
+    assert not missing, missing
+
+
+def test_binding_covers_header(pcrl):
+    from paper_2402_13747_amd import _lib
+    assert set(_lib.SIGNATURES) == _declared_functions()
+
+
+def test_struct_sizes(pcrl):
+    from paper_2402_13747_amd import _lib
+    # sizes fixed by the header's field lists (natural alignment)
+    assert C.sizeof(_lib.PcrlVoxelParams) == 32
+    assert C.sizeof(_lib.PcrlLaunchParams) == 64
+    assert C.sizeof(_lib.PcrlSceneInfo) == 152
+    assert C.sizeof(_lib.PcrlPaths) == 13 * 8
+
+
+def test_version_and_validation_without_gpu(pcrl):
+    from paper_2402_13747_amd import _lib
+    assert "gfx950" in pcrl.version()
+    lib = _lib.lib
+    out = C.c_void_p(123)
+    # NULL params -> EINVAL before any device call
+    assert lib.build_voxels(None, None, None, 0, None, None, C.byref(out)) == _lib.PCRL_EINVAL
+    assert out.value is None
+    assert b"params" in lib.last_error()
+    p = _lib.PcrlVoxelParams()
+    p.n_levels = 2
+    p.level_size[0] = 0.5
+    p.level_size[1] = 0.3          # 0.5 / 0.3 is not an integer
+    p.surfel_radius = 0.1
+    assert lib.build_voxels(None, None, None, 0, C.byref(p), None, C.byref(out)) == _lib.PCRL_EINVAL
+    assert b"integer multiple" in lib.last_error()
+    p.n_levels = 5
+    assert lib.build_voxels(None, None, None, 0, C.byref(p), None, C.byref(out)) == _lib.PCRL_EINVAL
+    lp = _lib.PcrlLaunchParams()
+    lp.n_rays = 10
+    lp.max_reflections = 9          # K > 8
+    assert lib.launch_rays(C.c_void_p(1), C.c_void_p(1), 1, None, 0, C.byref(lp), None, C.byref(out)) == \
+        _lib.PCRL_EINVAL
+    assert lib.collect_paths(None, 1, 0, None, None) == _lib.PCRL_EINVAL
+    assert lib.release_scene(None) == 0 and lib.release_launch(None) == 0
+
+
+def test_no_cpu_fallback(tmp_path, monkeypatch):
+    """Without the built library the binding refuses to import."""
+    import importlib
+    import sys
+    from paper_2402_13747_amd import _lib
+    monkeypatch.setattr(_lib, "LIB_PATH", str(tmp_path / "missing.so"))
+    with pytest.raises(ImportError):
+        _lib._load()
+    assert "paper_2402_13747_amd" in sys.modules
+    importlib.invalidate_caches()
