@@ -145,6 +145,10 @@ typedef struct {
     int64_t node_lookups;                          /* hierarchy lookups (level-0 map and brick words) */
     int64_t surfel_tests;                          /* ray-disk tests */
     int64_t hits;                                  /* segments ending on a surfel */
+    int64_t algo_bytes;                            /* algorithmic bytes of the trace kernels: hierarchy
+                                                      reads (4 B level-0, 8-12 B per brick word, 8 B per
+                                                      leaf), 32 B per surfel tested, 36 B ray state read per
+                                                      later segment, 52 B per reflection, 16 B per record */
     /* PCRL_LAUNCH_TIMING only (else 0) */
     float   kernel_ms[PCRL_MAX_REFLECTIONS + 1];   /* trace kernel time per bounce */
     float   total_ms;                              /* first to last trace kernel */

@@ -191,9 +191,12 @@ class Launch:
 
 
 def launch_rays(scene: Scene, tx, rx, n_rays, max_reflections, directions=None, rx_radius_scale=1.25,
-                ray_spacing=0.0, record_capacity=0, stats=False, timing=False, coherent=False, hit_log=False
+                ray_spacing=0.0, record_capacity=0, stats=False, timing=False, coherent=True, hit_log=False
                 ) -> Launch:
-    """Launch ``n_rays`` rays from every TX (Fibonacci lattice unless ``directions``)."""
+    """Launch ``n_rays`` rays from every TX (Fibonacci lattice unless ``directions``).
+
+    ``coherent`` traces the first bounce in a direction-sorted ray order (same
+    results, better locality)."""
     device = scene.device
     tx = _as_tensor(tx, torch.float32, device, 3)
     rx = _as_tensor(rx, torch.float32, device, 3) if rx is not None else torch.zeros((0, 3), device=device)

@@ -105,18 +105,42 @@ __global__ __launch_bounds__(BUILD_BLOCK) void k_ingest(const float* xyz, const 
     }
 }
 
-__global__ void k_ingest_final(const IngestOut* partial, int nb, IngestOut* out) {
-    if (threadIdx.x != 0 || blockIdx.x != 0) return;
-    IngestOut o;
-    for (int a = 0; a < 3; ++a) { o.lo[a] = INFINITY; o.hi[a] = -INFINITY; }
-    o.max_label = 0;
-    o.bad = 0;
-    for (int k = 0; k < nb; ++k) {
-        for (int a = 0; a < 3; ++a) { o.lo[a] = fminf(o.lo[a], partial[k].lo[a]); o.hi[a] = fmaxf(o.hi[a], partial[k].hi[a]); }
-        o.max_label = max(o.max_label, partial[k].max_label);
-        o.bad |= partial[k].bad;
+// One block of BUILD_BLOCK threads folds the per-block partials.
+__global__ __launch_bounds__(BUILD_BLOCK) void k_ingest_final(const IngestOut* partial, int nb, IngestOut* out) {
+    float lo[3] = {INFINITY, INFINITY, INFINITY};
+    float hi[3] = {-INFINITY, -INFINITY, -INFINITY};
+    uint32_t ml = 0, bad = 0;
+    for (int k = threadIdx.x; k < nb; k += BUILD_BLOCK) {
+        const IngestOut p = partial[k];
+        for (int a = 0; a < 3; ++a) { lo[a] = fminf(lo[a], p.lo[a]); hi[a] = fmaxf(hi[a], p.hi[a]); }
+        ml = max(ml, p.max_label);
+        bad |= p.bad;
     }
-    *out = o;
+    for (int off = 32; off > 0; off >>= 1) {
+        for (int a = 0; a < 3; ++a) {
+            lo[a] = fminf(lo[a], __shfl_xor(lo[a], off, 64));
+            hi[a] = fmaxf(hi[a], __shfl_xor(hi[a], off, 64));
+        }
+        ml = max(ml, __shfl_xor(ml, off, 64));
+        bad |= __shfl_xor(bad, off, 64);
+    }
+    __shared__ IngestOut s[BUILD_BLOCK / 64];
+    const int w = threadIdx.x >> 6;
+    if (lane_id() == 0) {
+        for (int a = 0; a < 3; ++a) { s[w].lo[a] = lo[a]; s[w].hi[a] = hi[a]; }
+        s[w].max_label = ml;
+        s[w].bad = bad;
+    }
+    __syncthreads();
+    if (threadIdx.x == 0) {
+        IngestOut o = s[0];
+        for (int k = 1; k < BUILD_BLOCK / 64; ++k) {
+            for (int a = 0; a < 3; ++a) { o.lo[a] = fminf(o.lo[a], s[k].lo[a]); o.hi[a] = fmaxf(o.hi[a], s[k].hi[a]); }
+            o.max_label = max(o.max_label, s[k].max_label);
+            o.bad |= s[k].bad;
+        }
+        *out = o;
+    }
 }
 
 // ---------------------------------------------------------------------------
@@ -345,6 +369,11 @@ static int build_impl(const float* xyz, const float* nrm, const uint32_t* label,
     v.nlev = L;
     v.span[L - 1] = 1;
     for (int i = L - 2; i >= 0; --i) v.span[i] = v.span[i + 1] * ratio[i];
+    if (v.span[0] > (1 << 18)) {
+        set_error("build_voxels: at most 2^18 leaves per coarse cell edge (got %d)", v.span[0]);
+        return PCRL_EINVAL;
+    }
+    for (int i = 0; i < L; ++i) v.mspan[i] = (((uint64_t)1 << 40) + (uint64_t)v.span[i] - 1) / (uint64_t)v.span[i];
     for (int i = 0; i < PCRL_MAX_LEVELS; ++i) v.ratio[i] = ratio[i];
     const float h = params->level_size[L - 1];
     v.h = h;
@@ -366,7 +395,7 @@ static int build_impl(const float* xyz, const float* nrm, const uint32_t* label,
         IngestOut *partial = nullptr, *res = nullptr;
         if ((rc = T.alloc(&partial, nb)) || (rc = T.alloc(&res, 1))) return fail(rc);
         hipLaunchKernelGGL(k_ingest, dim3(nb), dim3(BUILD_BLOCK), 0, s, xyz, nrm, label, n, unit_nrm, partial);
-        hipLaunchKernelGGL(k_ingest_final, dim3(1), dim3(64), 0, s, partial, (int)nb, res);
+        hipLaunchKernelGGL(k_ingest_final, dim3(1), dim3(BUILD_BLOCK), 0, s, partial, (int)nb, res);
         if (hipGetLastError() != hipSuccess || hipMemcpyAsync(&io, res, sizeof io, hipMemcpyDeviceToHost, s) != hipSuccess ||
             hipStreamSynchronize(s) != hipSuccess) {
             set_error("build_voxels: ingest failed: %s", hipGetErrorString(hipGetLastError()));

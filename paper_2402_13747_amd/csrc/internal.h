@@ -150,6 +150,7 @@ struct SceneView {
     int32_t lbits[PCRL_MAX_LEVELS];  // key bits of level i (level 0: linear coarse index)
     int32_t nw[PCRL_MAX_LEVELS];     // 64-bit mask words of a level-i brick (i < nlev-1)
     uint32_t nn[PCRL_MAX_LEVELS];    // occupied nodes per level (bounds of every index)
+    uint64_t mspan[PCRL_MAX_LEVELS]; // ceil(2^40 / span[i]): x / span[i] == (x * mspan[i]) >> 40 for x < 2^22
     const int32_t* map0;             // [dim0 x*y*z] level-0 node or -1
     const uint64_t* mask[PCRL_MAX_LEVELS - 1];  // child occupancy bricks of level i
     const uint32_t* base[PCRL_MAX_LEVELS - 1];  // child index of the first set bit of each word
@@ -157,6 +158,13 @@ struct SceneView {
     const float4* spos;              // per entry: x, y, z, point id (bits)
     const float4* snrm;              // per entry: unit normal, label rank (bits)
 };
+
+// x / span for 0 <= x < 2^22 and span <= 2^18 with a precomputed ceil(2^40 / span):
+// x * m / 2^40 = x / span + x * e / 2^40 with 0 <= e < 1, and x * e / 2^40 < 1 / span,
+// so the floor is exact.
+__host__ __device__ __forceinline__ int span_div(int x, uint64_t m) {
+    return (int)(((uint64_t)(uint32_t)x * m) >> 40);
+}
 
 __host__ __device__ inline uint64_t leaf_key_of(const SceneView& v, int ix, int iy, int iz) {
     const int s0 = v.span[0];

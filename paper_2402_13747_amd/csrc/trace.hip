@@ -25,13 +25,20 @@ namespace pcrl {
 constexpr int TRACE_BLOCK = 256;
 constexpr uint32_t NO_HIT = 0xFFFFFFFFu;
 
-enum StatSlot { ST_SEGMENTS = 0, ST_DDA, ST_LEAVES, ST_NODES, ST_TESTS, ST_HITS, ST_COUNT };
+// Statistics of the PCRL_LAUNCH_STATS kernel variant.  ST_BYTES is the exact
+// algorithmic traffic of the trace kernels: 4 B per level-0 map read, 8 B per
+// brick mask word (+4 B base when the bit is set), 8 B per leaf range, 32 B
+// per surfel tested, 36 B of ray state read per segment after the first,
+// 36 B of ray state + 16 B of history per reflection, 16 B per record.
+enum StatSlot { ST_SEGMENTS = 0, ST_DDA, ST_LEAVES, ST_NODES, ST_TESTS, ST_HITS, ST_BYTES, ST_COUNT };
+typedef unsigned long long stat_t;
 
 struct TraceArgs {
     SceneView v;
     const float* tx;
     const float* rx;
     const float* dirs;      // null: Fibonacci lattice
+    const uint32_t* perm;   // null, or bounce-0 order of the directions
     int32_t n_rx;
     int32_t K;
     int32_t b;
@@ -77,34 +84,44 @@ __device__ __forceinline__ void fib_dir(uint32_t j, uint32_t n, float& x, float&
     z = (float)zz;
 }
 
-// Top-down lookup of leaf cell (cx, cy, cz).  Returns the level at which the
-// cell is empty, or nlev if the leaf is occupied (node = leaf index).
+// Descend from level 0 to level `to` (< nlev) for leaf cell c.  Returns the
+// level at which the path is empty, or to + 1 when the level-`to` node exists
+// (its index in `node`).  Quotients c / span[i] use the precomputed magics.
 template <bool STATS>
-__device__ __forceinline__ int lookup(const SceneView& v, int cx, int cy, int cz, uint32_t& node, uint32_t& n_nodes) {
-    const int s0 = v.span[0];
-    const int32_t n0 = v.map0[(cx / s0) + v.dim0[0] * ((cy / s0) + v.dim0[1] * (cz / s0))];
-    if (STATS) ++n_nodes;
+__device__ __forceinline__ int descend(const SceneView& v, const int c[3], int to, uint32_t& node, stat_t* cnt) {
+    int p[3] = {span_div(c[0], v.mspan[0]), span_div(c[1], v.mspan[0]), span_div(c[2], v.mspan[0])};
+    const int32_t n0 = v.map0[p[0] + v.dim0[0] * (p[1] + v.dim0[1] * p[2])];
+    if (STATS) {
+        ++cnt[ST_NODES];
+        cnt[ST_BYTES] += 4;
+    }
     if (n0 < 0 || (uint32_t)n0 >= v.nn[0]) return 0;
     uint32_t n = (uint32_t)n0;
-    for (int i = 1; i < v.nlev; ++i) {
-        const int s = v.span[i];
+    for (int i = 1; i <= to; ++i) {
+        const int q[3] = {span_div(c[0], v.mspan[i]), span_div(c[1], v.mspan[i]), span_div(c[2], v.mspan[i])};
         const int r = v.ratio[i - 1];
-        const int loc = ((cx / s) % r) + r * (((cy / s) % r) + r * ((cz / s) % r));
+        const int loc = (q[0] - r * p[0]) + r * ((q[1] - r * p[1]) + r * (q[2] - r * p[2]));
         const size_t wi = (size_t)n * v.nw[i - 1] + (loc >> 6);
         const uint64_t w = v.mask[i - 1][wi];
-        if (STATS) ++n_nodes;
         const uint64_t bit = uint64_t(1) << (loc & 63);
+        if (STATS) {
+            ++cnt[ST_NODES];
+            cnt[ST_BYTES] += (w & bit) ? 12 : 8;
+        }
         if (!(w & bit)) return i;
         n = v.base[i - 1][wi] + (uint32_t)__popcll(w & (bit - 1));
         if (n >= v.nn[i]) return i;
+        p[0] = q[0];
+        p[1] = q[1];
+        p[2] = q[2];
     }
     node = n;
-    return v.nlev;
+    return to + 1;
 }
 
 template <bool STATS>
 __device__ void trace_segment(const SceneView& v, const float o[3], const float d[3], uint32_t last, Hit& hit,
-                              uint32_t cnt[ST_COUNT]) {
+                              stat_t cnt[ST_COUNT]) {
     hit.id = NO_HIT;
     hit.t = INFINITY;
     hit.lab = 0;
@@ -138,25 +155,68 @@ __device__ void trace_segment(const SceneView& v, const float o[3], const float 
         c[a] = min(max(ci, 0), v.dim[a] - 1);
     }
     const int max_iter = v.dim[0] + v.dim[1] + v.dim[2] + 8;
+    const int L = v.nlev;
+    const int P = L - 2;  // level of the leaves' parents (-1: single-level grid)
+    // Cache of the parent lookup: consecutive leaves mostly share a parent, so
+    // the descent from level 0 runs only when the parent cell changes.
+    int cq[3] = {-1, -1, -1};
+    int cres = 0;
+    uint32_t cnode = 0;
     for (int it = 0; it < max_iter; ++it) {
         uint32_t node = 0;
-        const int lvl = lookup<STATS>(v, c[0], c[1], c[2], node, cnt[ST_NODES]);
+        int lvl;  // level of the empty cell containing c, or L for an occupied leaf
+        if (P < 0) {
+            const int32_t n0 = v.map0[c[0] + v.dim0[0] * (c[1] + v.dim0[1] * c[2])];
+            if (STATS) {
+                ++cnt[ST_NODES];
+                cnt[ST_BYTES] += 4;
+            }
+            lvl = (n0 < 0 || (uint32_t)n0 >= v.nn[0]) ? 0 : L;
+            node = (uint32_t)n0;
+        } else {
+            const int q[3] = {span_div(c[0], v.mspan[P]), span_div(c[1], v.mspan[P]), span_div(c[2], v.mspan[P])};
+            if (q[0] != cq[0] || q[1] != cq[1] || q[2] != cq[2]) {
+                cq[0] = q[0];
+                cq[1] = q[1];
+                cq[2] = q[2];
+                cres = descend<STATS>(v, c, P, cnode, cnt);
+            }
+            if (cres <= P) {
+                lvl = cres;
+            } else {
+                const int r = v.ratio[P];
+                const int loc = (c[0] - r * q[0]) + r * ((c[1] - r * q[1]) + r * (c[2] - r * q[2]));
+                const size_t wi = (size_t)cnode * v.nw[P] + (loc >> 6);
+                const uint64_t w = v.mask[P][wi];
+                const uint64_t bit = uint64_t(1) << (loc & 63);
+                if (STATS) {
+                    ++cnt[ST_NODES];
+                    cnt[ST_BYTES] += (w & bit) ? 12 : 8;
+                }
+                lvl = L - 1;
+                if (w & bit) {
+                    node = v.base[P][wi] + (uint32_t)__popcll(w & (bit - 1));
+                    if (node < v.nn[L - 1]) lvl = L;
+                }
+            }
+        }
         if (STATS) ++cnt[ST_DDA];
         int S = 1;
-        if (lvl == v.nlev) {
+        if (lvl == L) {
             const uint2 r = v.leaf[node];
             if (STATS) {
                 ++cnt[ST_LEAVES];
                 cnt[ST_TESTS] += r.y;
+                cnt[ST_BYTES] += 8 + 32ull * r.y;
             }
             for (uint32_t k = r.x; k < r.x + r.y; ++k) {
-                const float4 P = v.spos[k];
+                const float4 P4 = v.spos[k];
                 const float4 N = v.snrm[k];
-                const uint32_t id = __float_as_uint(P.w);
-                const float wx = P.x - o[0], wy = P.y - o[1], wz = P.z - o[2];
+                const uint32_t id = __float_as_uint(P4.w);
+                const float wx = P4.x - o[0], wy = P4.y - o[1], wz = P4.z - o[2];
                 const float den = d[0] * N.x + d[1] * N.y + d[2] * N.z;
                 const float num = wx * N.x + wy * N.y + wz * N.z;
-                const float t = num / den;
+                const float t = num * __builtin_amdgcn_rcpf(den);
                 const float qx = t * d[0] - wx, qy = t * d[1] - wy, qz = t * d[2] - wz;
                 const float dist2 = qx * qx + qy * qy + qz * qz;
                 const bool ok = fabsf(den) > 1e-7f && t > v.t_eps && id != last && dist2 <= v.rs2 &&
@@ -179,7 +239,7 @@ __device__ void trace_segment(const SceneView& v, const float o[3], const float 
         int axis = 0;
 #pragma unroll
         for (int a = 0; a < 3; ++a) {
-            lo[a] = (c[a] / S) * S;
+            lo[a] = (S == 1) ? c[a] : span_div(c[a], v.mspan[lvl]) * S;
             hi[a] = lo[a] + S;
             float ta = INFINITY;
             if (step[a] > 0)
@@ -210,11 +270,17 @@ __device__ void trace_segment(const SceneView& v, const float o[3], const float 
 template <bool FIRST, bool STATS>
 __global__ __launch_bounds__(TRACE_BLOCK) void k_trace(TraceArgs a) {
     const uint32_t n_act = FIRST ? a.n_total : a.counters[a.b];
-    const uint32_t wave = (blockIdx.x * TRACE_BLOCK + threadIdx.x) >> 6;
+    // Workgroups are dispatched round-robin over the 8 XCDs (block b -> XCD
+    // b % 8).  Renumber them so that each XCD works on one contiguous range of
+    // rays: neighbouring (coherent) rays then share that XCD's L2.
+    const uint32_t nb = gridDim.x, bx = blockIdx.x;
+    const uint32_t xcd = bx & 7u, per = nb >> 3, extra = nb & 7u;
+    const uint32_t lblock = xcd * per + min(xcd, extra) + (bx >> 3);
+    const uint32_t wave = lblock * (TRACE_BLOCK / 64) + (threadIdx.x >> 6);
     const uint32_t n_waves = gridDim.x * (TRACE_BLOCK / 64);
     const uint32_t lane = lane_id();
     const uint64_t lt = lanemask_lt();
-    uint32_t cnt[ST_COUNT] = {0, 0, 0, 0, 0, 0};
+    stat_t cnt[ST_COUNT] = {0, 0, 0, 0, 0, 0, 0};
     uint32_t* rec_counter = &a.counters[PCRL_CNT_REC(a.K)];
     for (uint32_t base = wave * 64; base < n_act; base += n_waves * 64) {
         const uint32_t i = base + lane;
@@ -224,9 +290,10 @@ __global__ __launch_bounds__(TRACE_BLOCK) void k_trace(TraceArgs a) {
         uint32_t last = NO_HIT, g = 0;
         if (act) {
             if (FIRST) {
-                g = i;
-                const uint32_t ti = g / a.n_rays;
-                const uint32_t j = g - ti * a.n_rays;
+                const uint32_t ti = i / a.n_rays;
+                const uint32_t jl = i - ti * a.n_rays;
+                const uint32_t j = a.perm ? a.perm[jl] : jl;  // direction-coherent order
+                g = ti * a.n_rays + j;
                 o[0] = a.tx[3 * ti];
                 o[1] = a.tx[3 * ti + 1];
                 o[2] = a.tx[3 * ti + 2];
@@ -257,6 +324,7 @@ __global__ __launch_bounds__(TRACE_BLOCK) void k_trace(TraceArgs a) {
             if (STATS) {
                 ++cnt[ST_SEGMENTS];
                 if (hit.id != NO_HIT) ++cnt[ST_HITS];
+                if (!FIRST) cnt[ST_BYTES] += 36;
             }
             if (a.hit_id) {
                 const size_t idx = (size_t)g * (a.K + 1) + a.b;
@@ -281,6 +349,7 @@ __global__ __launch_bounds__(TRACE_BLOCK) void k_trace(TraceArgs a) {
                 uint32_t slot = 0;
                 if ((int)lane == leader) slot = atomicAdd(rec_counter, (uint32_t)__popcll(m));
                 slot = __shfl(slot, leader, 64) + (uint32_t)__popcll(m & lt);
+                if (STATS && got) cnt[ST_BYTES] += 16;
                 if (got && slot < a.rec_cap) {
                     const float lp = L + sqrtf(vx * vx + vy * vy + vz * vz);
                     a.rec[slot] = make_uint4(g, (uint32_t)r | ((uint32_t)a.b << 16), __float_as_uint(lp),
@@ -307,6 +376,7 @@ __global__ __launch_bounds__(TRACE_BLOCK) void k_trace(TraceArgs a) {
             uint32_t slot = 0;
             if ((int)lane == leader) slot = atomicAdd(&a.counters[a.b + 1], (uint32_t)__popcll(m));
             slot = __shfl(slot, leader, 64) + (uint32_t)__popcll(m & lt);
+            if (STATS && surv) cnt[ST_BYTES] += 52;
             if (surv) {
                 a.out_o[slot] = make_float4(o[0], o[1], o[2], L);
                 a.out_d[slot] = make_float4(d[0], d[1], d[2], __uint_as_float(last));
@@ -331,6 +401,42 @@ __global__ void k_fib(uint32_t n, float* out) {
     out[3 * (size_t)j] = x;
     out[3 * (size_t)j + 1] = y;
     out[3 * (size_t)j + 2] = z;
+}
+
+__device__ __forceinline__ uint32_t spread_bits16(uint32_t x) {
+    x &= 0xFFFFu;
+    x = (x | (x << 8)) & 0x00FF00FFu;
+    x = (x | (x << 4)) & 0x0F0F0F0Fu;
+    x = (x | (x << 2)) & 0x33333333u;
+    x = (x | (x << 1)) & 0x55555555u;
+    return x;
+}
+
+// Sort key of a launch direction: Morton code of its octahedral map, so rays
+// that are close on the sphere are close in the bounce-0 order.
+__global__ void k_dir_keys(const float* dirs, uint32_t n, uint32_t* keys, uint32_t* idx) {
+    const uint32_t j = blockIdx.x * blockDim.x + threadIdx.x;
+    if (j >= n) return;
+    float x, y, z;
+    if (dirs) {
+        x = dirs[3 * (size_t)j];
+        y = dirs[3 * (size_t)j + 1];
+        z = dirs[3 * (size_t)j + 2];
+    } else {
+        fib_dir(j, n, x, y, z);
+    }
+    const float s = fabsf(x) + fabsf(y) + fabsf(z);
+    float u = s > 0.f ? x / s : 0.f, w = s > 0.f ? y / s : 0.f;
+    if (z < 0.f) {
+        const float uu = (1.f - fabsf(w)) * (u >= 0.f ? 1.f : -1.f);
+        const float ww = (1.f - fabsf(u)) * (w >= 0.f ? 1.f : -1.f);
+        u = uu;
+        w = ww;
+    }
+    const uint32_t qu = (uint32_t)fminf(fmaxf((u * 0.5f + 0.5f) * 65535.f, 0.f), 65535.f);
+    const uint32_t qw = (uint32_t)fminf(fmaxf((w * 0.5f + 0.5f) * 65535.f, 0.f), 65535.f);
+    keys[j] = spread_bits16(qu) | (spread_bits16(qw) << 1);
+    idx[j] = j;
 }
 
 __global__ void k_fill_logs(int32_t* id, float* t, size_t n) {
@@ -386,11 +492,22 @@ int launch_enqueue(PcrlLaunch* L, const float* tx, const float* rx, const float*
         const size_t n = (size_t)n_total * (K + 1);
         hipLaunchKernelGGL(k_fill_logs, dim3((unsigned)((n + 255) / 256)), dim3(256), 0, s, hit_id, hit_t, n);
     }
+    uint32_t* perm = nullptr;
+    if (L->flags & PCRL_LAUNCH_COHERENT) {
+        const uint32_t nr = (uint32_t)L->n_rays;
+        uint32_t* keys = nullptr;
+        PCRL_TRY(B.alloc(&keys, nr));
+        PCRL_TRY(B.alloc(&perm, nr));
+        hipLaunchKernelGGL(k_dir_keys, dim3((nr + 255) / 256), dim3(256), 0, s, dirs, nr, keys, perm);
+        PCRL_TRY_HIP(hipGetLastError());
+        PCRL_TRY(radix_sort_u32(keys, perm, nr, 32, s));
+    }
     TraceArgs a{};
     a.v = S->view;
     a.tx = tx;
     a.rx = rx;
     a.dirs = dirs;
+    a.perm = perm;
     a.n_rx = L->n_rx;
     a.K = K;
     a.n_rays = (uint32_t)L->n_rays;
@@ -536,7 +653,7 @@ extern "C" int launch_stats(PcrlLaunch* L, PcrlLaunchStats* out) {
     std::memset(out, 0, sizeof *out);
     const int K = L->K;
     uint32_t cnt[PCRL_NCOUNTERS(PCRL_MAX_REFLECTIONS)];
-    unsigned long long st[8] = {0};
+    unsigned long long st[8] = {0, 0, 0, 0, 0, 0, 0, 0};
     PCRL_TRY_HIP(hipMemcpyAsync(cnt, L->counters, sizeof(uint32_t) * PCRL_NCOUNTERS(K), hipMemcpyDeviceToHost, L->stream));
     if (L->stats) PCRL_TRY_HIP(hipMemcpyAsync(st, L->stats, sizeof st, hipMemcpyDeviceToHost, L->stream));
     PCRL_TRY_HIP(hipStreamSynchronize(L->stream));
@@ -555,6 +672,7 @@ extern "C" int launch_stats(PcrlLaunch* L, PcrlLaunchStats* out) {
     out->node_lookups = (int64_t)st[ST_NODES];
     out->surfel_tests = (int64_t)st[ST_TESTS];
     out->hits = (int64_t)st[ST_HITS];
+    out->algo_bytes = (int64_t)st[ST_BYTES];
     if (!L->events.empty()) {
         float total = 0.f;
         for (int b = 0; b <= K; ++b) {

@@ -31,7 +31,8 @@ def _f32(x):
     return float(np.float32(x))
 
 
-def _run(env, s, n_rays, K, sel=None, levels=None, hit_log=True, directions=None, kappa=1 << 30, n_threads=None):
+def _run(env, s, n_rays, K, sel=None, levels=None, hit_log=True, directions=None, kappa=1 << 30, n_threads=None,
+         coherent=True):
     torch, pcrl, oracle = env
     t_eps = _f32(parity.t_eps_of(s))
     r_s = _f32(s.surfel_radius)
@@ -39,7 +40,7 @@ def _run(env, s, n_rays, K, sel=None, levels=None, hit_log=True, directions=None
           flush=True)
     scene = pcrl.build_voxels(s.xyz, s.normal, s.label, levels or s.levels, r_s, t_eps=t_eps)
     launch = pcrl.launch_rays(scene, s.tx, s.rx, n_rays=n_rays, max_reflections=K, hit_log=hit_log,
-                              directions=directions)
+                              directions=directions, coherent=coherent)
     paths = parity.to_numpy(pcrl.collect_paths(launch, kappa=kappa))
     rec = parity.to_numpy(launch.records())
     ids = launch.hit_log[0].cpu().numpy() if hit_log else None
@@ -47,6 +48,31 @@ def _run(env, s, n_rays, K, sel=None, levels=None, hit_log=True, directions=None
     orc = oracle.launch(s.xyz, s.normal, s.label, s.tx, s.rx, dirs, K=K, r_s=r_s, t_eps=t_eps, sel=sel, parity=True,
                         n_threads=n_threads, **parity.fp32_bands(s.xyz, s.tx, s.rx))
     return scene, launch, paths, rec, ids, orc
+
+
+def _reception_rich_sample(oracle, s, n_rays, n_rx, radius, n_random, planes=None):
+    """Ray ids aimed (within radius * alpha) at the first n_rx RX and at their mirror
+    images in the room's six walls, plus n_random random rays.  Pure geometry:
+    independent of both the oracle's and the device's tracing."""
+    d = oracle.fibonacci(n_rays).astype(np.float64)
+    alpha = oracle.ray_spacing(n_rays)
+    tx = s.tx[0].astype(np.float64)
+    size = s.extra.get("size", (12.0, 10.0, 3.0))
+    targets = []
+    for r in s.rx[:n_rx].astype(np.float64):
+        targets.append(r)
+        for axis in range(3):
+            for c in (0.0, size[axis]):
+                m = r.copy()
+                m[axis] = 2 * c - m[axis]
+                targets.append(m)
+    pick = set()
+    for t in targets:
+        u = (t - tx) / np.linalg.norm(t - tx)
+        pick.update(np.nonzero(d @ u > math.cos(radius * alpha))[0].tolist())
+    rng = np.random.default_rng(3)
+    pick.update(rng.choice(n_rays, size=n_random, replace=False).tolist())
+    return np.array(sorted(pick), np.int64)
 
 
 def test_directions_match_oracle(env):
@@ -125,13 +151,15 @@ def test_box_room_full_parity(env):
     assert all(abs(r["len_poly"] - math.sqrt(34.0)) <= 1e-6 * math.sqrt(34.0) for r in los)
 
 
-@pytest.mark.parametrize("seed,levels,n_rays,K", [
-    (1, None, 3000, 3), (2, (0.25,), 2500, 2), (3, (1.0, 0.25), 4099, 3), (4, None, 1531, 4), (5, (0.5, 0.25), 777, 1),
+@pytest.mark.parametrize("seed,levels,n_rays,K,coherent", [
+    (1, None, 3000, 3, True), (2, (0.25,), 2500, 2, False), (3, (1.0, 0.25), 4099, 3, True),
+    (4, None, 1531, 4, False), (5, (0.5, 0.25), 777, 1, True), (6, (1.25, 0.25), 2048, 3, True),
+    (8, (2.0, 1.0, 0.5, 0.25), 3001, 2, True),
 ])
-def test_random_scene_parity(env, seed, levels, n_rays, K):
+def test_random_scene_parity(env, seed, levels, n_rays, K, coherent):
     torch, pcrl, oracle = env
     s = scenes.random_scene(seed, tilt_sigma=0.05 * (seed % 3), pos_sigma=0.003 * (seed % 2), n_tx=2, n_rx=4)
-    scene, launch, paths, rec, ids, orc = _run(env, s, n_rays, K, levels=levels)
+    scene, launch, paths, rec, ids, orc = _run(env, s, n_rays, K, levels=levels, coherent=coherent)
     rep = parity.compare(orc, ids, rec, s.xyz, s.normal, s.label, K)
     print(rep.summary())
     assert rep.ok(), (rep.mismatch[:5], rep.record_missing[:5], rep.record_extra[:5], rep.length_bad[:5])
@@ -225,15 +253,16 @@ def test_edge_cases(env):
 
 
 def test_furnished_room_full_size_sampled(env):
-    """Furnished room at full size (1M points, 1M rays, K = 3, 16 RX); 192 sampled rays against the oracle."""
+    """Furnished room at full size (1M points, 1M rays, K = 3, 16 RX); ~650 sampled rays against the oracle."""
     torch, pcrl, oracle = env
     s = scenes.furnished_room()
     n_rays, K = s.n_rays, s.max_reflections
-    sel = np.sort(np.random.default_rng(3).choice(n_rays, size=192, replace=False)).astype(np.int64)
+    sel = _reception_rich_sample(oracle, s, n_rays, n_rx=16, radius=1.2, n_random=64)
     scene, launch, paths, rec, ids, orc = _run(env, s, n_rays, K, sel=sel)
     rep = parity.compare(orc, ids, rec, s.xyz, s.normal, s.label, K)
     print(rep.summary())
     assert rep.ok(), (rep.mismatch[:5], rep.record_missing[:5], rep.record_extra[:5], rep.length_bad[:5])
     assert rep.exact + rep.equivalent >= 0.95 * rep.segments
+    assert rep.records_checked >= 15
     st = launch.stats()
     assert st["records"] <= st["record_capacity"]
