@@ -75,7 +75,7 @@ typedef struct {
     int64_t n_entries;                    /* (leaf, point) pairs: a point is listed in every leaf its disk overlaps */
     int64_t n_leaves;                     /* occupied leaves */
     int64_t n_nodes[PCRL_MAX_LEVELS];     /* occupied cells per level (n_nodes[n_levels-1] = n_leaves) */
-    int32_t n_labels;                     /* distinct labels */
+    int32_t max_label;                    /* largest label of the static points (bit pattern of the uint32) */
     int32_t n_levels;
     int32_t dims[3];                      /* leaf grid dimensions */
     int32_t dims0[3];                     /* coarsest grid dimensions */
@@ -87,6 +87,8 @@ typedef struct {
     int64_t device_bytes;                 /* device memory held by the scene */
     int32_t key_bits;                     /* bits of the hierarchical leaf key */
     int32_t reserved;
+    int64_t n_dynamic;                    /* points of the current dynamic overlay (update_points) */
+    int64_t epoch;                        /* number of update_points calls so far */
 } PcrlSceneInfo;
 
 /* Build the voxel hierarchy of a labeled point cloud.
@@ -98,6 +100,21 @@ typedef struct {
  * Synchronises the stream internally (twice) to size its buffers. */
 int build_voxels(const float* xyz, const float* normal, const uint32_t* label, int64_t n_points,
                  const PcrlVoxelParams* params, pcrl_stream_t stream, PcrlScene** out);
+
+/* Incremental re-voxelisation: replace the scene's dynamic points.
+ *   ids    device [n] uint32 global point ids of the dynamic points; they must
+ *          differ from the static ids 0..n_points-1 of build_voxels
+ *   xyz, normal, label as in build_voxels (device, [n,3] / [n,3] / [n])
+ * The points are voxelised into an overlay on the base grid (same origin,
+ * levels, surfel radius and t_eps); traversal takes the nearest hit over base
+ * and overlay, which is exactly the nearest hit of a scene built from all
+ * points with these ids.  Each call starts a new epoch: launches enqueued
+ * earlier keep tracing the overlay they started with (it is freed when the
+ * last of them is released).  n = 0 removes the overlay.  The static base is
+ * never rebuilt.  PCRL_EINVAL if a dynamic point leaves the base grid.
+ * Synchronises the stream twice. */
+int update_points(PcrlScene* scene, const uint32_t* ids, const float* xyz, const float* normal, const uint32_t* label,
+                  int64_t n, pcrl_stream_t stream);
 
 /* Sizes of a built scene (host struct). */
 int scene_info(const PcrlScene* scene, PcrlSceneInfo* out);
@@ -181,6 +198,51 @@ int launch_records(PcrlLaunch* launch, int64_t cap, int64_t* ray, int32_t* rx, i
 int release_launch(PcrlLaunch* launch);
 
 /* ------------------------------------------------------------------------ */
+/* batched launching: many TX/RX queries on many scenes (Section 2.2 per TX)  */
+/* ------------------------------------------------------------------------ */
+
+/* One query: launch params.n_rays rays from each of n_tx TX into `scene` and
+ * receive them at n_rx RX (arrays as in launch_rays). */
+typedef struct {
+    const PcrlScene* scene;
+    const float* tx;           /* device [n_tx,3] */
+    int32_t n_tx;
+    int32_t n_rx;
+    const float* rx;           /* device [n_rx,3] */
+    PcrlLaunchParams params;   /* per-query parameters; PCRL_LAUNCH_TIMING times the whole batch */
+} PcrlQuery;
+
+typedef struct {
+    int32_t tile_rays;          /* ray slots per work item (multiple of 64); <= 0 -> 1024 */
+    float   compact_threshold;  /* theta: a bounce keeps survivors in place when the predicted density of live
+                                   rays is >= theta, else compacts them; > 1 always compacts; < 0 -> 0.6 */
+    int32_t waves_per_cu;       /* persistent waves per compute unit; <= 0 -> 16 */
+    int32_t use_graph;          /* replay the bounce loop as a cached hipGraph (ignored with TIMING) */
+    int32_t autotune;           /* take tile / theta / waves from the autotuner's table for this batch's
+                                   scene class, tuning on up to 32 of its queries on first use */
+    int32_t flags;              /* reserved, 0 */
+} PcrlBatchParams;
+
+/* Trace all queries together: one persistent work-queue kernel per bounce
+ * serves every query's rays (tiles of tile_rays slots), so queries of very
+ * different sizes share the GPU.  Each query gets its own launch object in
+ * out[i] (use collect_paths / launch_stats / launch_records / release_launch
+ * on it as for launch_rays); its results are bitwise those of launch_rays
+ * with the same arguments.  Scenes must outlive the launches.  Asynchronous
+ * (the autotuner, when it runs, synchronises).  On failure every out[i] is
+ * NULL. */
+int launch_batch(const PcrlQuery* queries, int32_t n_queries, const PcrlBatchParams* params, pcrl_stream_t stream,
+                 PcrlLaunch** out);
+
+/* Tune tile_rays, compact_threshold and waves_per_cu on the given queries
+ * (coordinate descent over measured batch times; the queries are traced
+ * several times and the results discarded).  The winner is stored in the
+ * process-wide table used by launch_batch(autotune = 1) for this scene class
+ * (GPU architecture, number of levels, log2 mean entries, log2 mean rays)
+ * and returned in *out.  Synchronous. */
+int batch_autotune(const PcrlQuery* queries, int32_t n_queries, pcrl_stream_t stream, PcrlBatchParams* out);
+
+/* ------------------------------------------------------------------------ */
 /* coarse paths (Section 2.2.3)                                              */
 /* ------------------------------------------------------------------------ */
 
@@ -211,6 +273,87 @@ typedef struct {
  * if the launch dropped records (then launch_stats().records is the record
  * capacity to relaunch with). */
 int collect_paths(PcrlLaunch* launch, int32_t kappa, int32_t key_mode, PcrlPaths* out, pcrl_stream_t stream);
+
+/* ------------------------------------------------------------------------ */
+/* serving: a request loop over one device-resident, incrementally           */
+/* re-voxelised scene                                                         */
+/* ------------------------------------------------------------------------ */
+
+typedef struct PcrlServer PcrlServer;
+
+typedef struct {
+    int32_t max_inflight;       /* queries in flight at once; <= 0 -> 256 */
+    int32_t n_streams;          /* admission rounds running concurrently; <= 0 -> 4 */
+    int64_t hbm_budget_bytes;   /* device memory the queries in flight may use; <= 0 -> 64 GiB */
+    int32_t max_batch;          /* queries per admission round; <= 0 -> 64 */
+    int32_t kappa;              /* duplicate limit of every result; <= 0 -> 1 */
+    int32_t key_mode;           /* PCRL_KEY_LABELS or PCRL_KEY_LEAVES */
+    int32_t reserved;
+    PcrlBatchParams batch;      /* launch shape of every round (see launch_batch) */
+} PcrlServeParams;
+
+typedef struct {
+    int32_t status;             /* 0 pending, 1 running, 2 done, < 0 failed with that PCRL status */
+    int32_t reserved;
+    int64_t epoch;              /* scene epoch (update count) the query traced */
+    int64_t n_rows;             /* result rows (done) */
+    int64_t n_keys;             /* distinct coarse paths (done) */
+    double  queue_ms;           /* submission -> admission */
+    double  latency_ms;         /* submission -> result on the host */
+} PcrlServeResult;
+
+typedef struct {
+    int64_t completed;
+    int64_t pending;
+    int32_t inflight;
+    int32_t reserved;
+    int64_t rounds;             /* admission rounds started */
+    double  mean_batch;         /* queries per round */
+    int64_t rays;               /* rays of completed queries */
+    double  p50_ms, p99_ms, max_ms, mean_ms;   /* latency of completed queries */
+    double  rays_per_s;         /* rays of completed queries / (last completion - first admission) */
+    int64_t used_bytes;         /* memory estimate of the queries in flight */
+} PcrlServeStats;
+
+/* Start a server on `scene` (which must outlive it) with its own worker
+ * thread and streams.  Queries are admitted while the stream budget, the
+ * in-flight limit and the memory budget allow; each admission round packs
+ * every admissible pending query into one launch_batch on a free stream, so
+ * rounds overlap on the device (continuous batching).  The memory estimate
+ * of a query with R = n_tx * n_rays rays is R*72 (ray state, if K > 0) +
+ * R*16*K (history) + 16*C (records; C = record_capacity, or its default
+ * R*(K+1)*min(n_rx,8)/16 + 65536) + 8*n_rays (ray order) + 4096. */
+int serve_create(PcrlScene* scene, const PcrlServeParams* params, PcrlServer** out);
+
+/* Queue one query (host arrays tx [n_tx,3], rx [n_rx,3]; params as in
+ * launch_rays, Fibonacci directions, no hit log).  Returns at once with a
+ * ticket.  PCRL_EBUSY if the query alone needs more than the memory budget
+ * or the server is shutting down.  Thread-safe. */
+int serve_submit(PcrlServer* server, const float* tx, int32_t n_tx, const float* rx, int32_t n_rx,
+                 const PcrlLaunchParams* params, int64_t* ticket);
+
+/* Frame update: replace the dynamic points (update_points on the server's
+ * update stream).  Rounds admitted afterwards trace the new epoch; rounds in
+ * flight finish on theirs.  Synchronous.  Thread-safe. */
+int serve_update(PcrlServer* server, const uint32_t* ids, const float* xyz, const float* normal, const uint32_t* label,
+                 int64_t n);
+
+/* State of a ticket; waits up to timeout_s seconds (0: no wait) for it to
+ * finish.  Returns the query's failure status if it failed. */
+int serve_poll(PcrlServer* server, int64_t ticket, double timeout_s, PcrlServeResult* out);
+
+/* Copy a finished query's coarse paths (rows as in collect_paths) into HOST
+ * arrays of out->capacity rows.  PCRL_EOVERFLOW if they do not fit. */
+int serve_result(PcrlServer* server, int64_t ticket, PcrlPaths* out);
+
+/* Forget a finished ticket (frees its host result). */
+int serve_release(PcrlServer* server, int64_t ticket);
+
+/* Throughput and latency (p50 / p99 over completed queries). */
+int serve_stats(PcrlServer* server, PcrlServeStats* out);
+
+/* Finish every pending and running query, then stop the worker. */
+int serve_destroy(PcrlServer* server);
 
 /* Message of the last failed call on this thread ("" if none). */
 const char* last_error(void);

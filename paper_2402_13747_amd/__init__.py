@@ -22,7 +22,7 @@ from . import _lib
 from ._lib import (KEY_LABELS, KEY_LEAVES, LAUNCH_COHERENT, LAUNCH_STATS, LAUNCH_TIMING, PCRL_EOVERFLOW,
                    PcrlError, check, lib)
 
-__all__ = ["build_voxels", "launch_rays", "launch_directions", "collect_paths", "Scene", "Launch", "PcrlError", "KEY_LABELS",
+__all__ = ["build_voxels", "launch_rays", "launch_batch", "batch_autotune", "launch_directions", "collect_paths", "Scene", "Launch", "Server", "PcrlError", "KEY_LABELS",
            "KEY_LEAVES", "version", "library_path"]
 
 
@@ -93,6 +93,24 @@ class Scene:
         check("scene_leaf_table", lib.scene_leaf_table(self._h, _ptr(key), _ptr(begin), _ptr(count), _ptr(ids),
                                                        _stream(self.device)))
         return key[:nl], begin[:nl], count[:nl], ids[:m]
+
+    def update_points(self, ids, xyz, normal, label):
+        """Replace the dynamic points (global ids distinct from the static ones) -- a new epoch."""
+        ids = _as_tensor(np.asarray(ids, np.int64).astype(np.uint32).view(np.int32)
+                         if isinstance(ids, np.ndarray) else ids, torch.int32, self.device)
+        xyz = _as_tensor(xyz, torch.float32, self.device, 3)
+        normal = _as_tensor(normal, torch.float32, self.device, 3)
+        if isinstance(label, np.ndarray):
+            label = torch.from_numpy(np.ascontiguousarray(label.astype(np.uint32)).view(np.int32))
+        label = _as_tensor(label, torch.int32, self.device)
+        n = xyz.shape[0]
+        if ids.shape[0] != n or normal.shape[0] != n or label.shape[0] != n:
+            raise ValueError("ids, xyz, normal and label must have the same length")
+        with torch.cuda.device(self.device):
+            check("update_points", lib.update_points(self._h, _ptr(ids) if n else None, _ptr(xyz) if n else None,
+                                                     _ptr(normal) if n else None, _ptr(label) if n else None, n,
+                                                     _stream(self.device)))
+        self._dyn = (ids, xyz, normal, label)
 
     def release(self):
         if self._h:
@@ -197,6 +215,20 @@ def launch_rays(scene: Scene, tx, rx, n_rays, max_reflections, directions=None, 
 
     ``coherent`` traces the first bounce in a direction-sorted ray order (same
     results, better locality)."""
+    q = _query(scene, tx, rx, n_rays, max_reflections, directions, rx_radius_scale, ray_spacing, record_capacity,
+               stats, timing, coherent, hit_log)
+    h = C.c_void_p()
+    device = scene.device
+    with torch.cuda.device(device):
+        check("launch_rays", lib.launch_rays(scene.handle, _ptr(q["tx"]), q["tx"].shape[0],
+                                             _ptr(q["rx"]) if q["rx"].shape[0] else None, q["rx"].shape[0],
+                                             C.byref(q["params"]), _stream(device), C.byref(h)))
+    return _make_launch(h, q)
+
+
+def _query(scene, tx, rx, n_rays, max_reflections, directions=None, rx_radius_scale=1.25, ray_spacing=0.0,
+           record_capacity=0, stats=False, timing=False, coherent=True, hit_log=False):
+    """Marshal one query: device tensors, PcrlLaunchParams and the optional hit log."""
     device = scene.device
     tx = _as_tensor(tx, torch.float32, device, 3)
     rx = _as_tensor(rx, torch.float32, device, 3) if rx is not None else torch.zeros((0, 3), device=device)
@@ -218,16 +250,74 @@ def launch_rays(scene: Scene, tx, rx, n_rays, max_reflections, directions=None, 
         log = (torch.empty(n, dtype=torch.int32, device=device), torch.empty(n, dtype=torch.float32, device=device))
         p.hit_log_id = log[0].data_ptr()
         p.hit_log_t = log[1].data_ptr()
-    h = C.c_void_p()
-    with torch.cuda.device(device):
-        check("launch_rays", lib.launch_rays(scene.handle, _ptr(tx), tx.shape[0], _ptr(rx) if rx.shape[0] else None,
-                                             rx.shape[0], C.byref(p), _stream(device), C.byref(h)))
-    if log is not None:
-        log = (log[0].view(tx.shape[0] * int(n_rays), K + 1), log[1].view(tx.shape[0] * int(n_rays), K + 1))
     args = dict(tx=tx, rx=rx, n_rays=n_rays, max_reflections=max_reflections, directions=dirs,
                 rx_radius_scale=rx_radius_scale, ray_spacing=ray_spacing, stats=stats, timing=timing,
                 coherent=coherent, hit_log=hit_log)
-    return Launch(h, scene, device, int(n_rays), K, tx.shape[0], rx.shape[0], log, args)
+    return {"scene": scene, "tx": tx, "rx": rx, "dirs": dirs, "params": p, "log": log, "args": args, "K": K,
+            "n_rays": int(n_rays)}
+
+
+def _make_launch(h, q):
+    log = q["log"]
+    n_tx = q["tx"].shape[0]
+    if log is not None:
+        log = (log[0].view(n_tx * q["n_rays"], q["K"] + 1), log[1].view(n_tx * q["n_rays"], q["K"] + 1))
+    return Launch(h, q["scene"], q["scene"].device, q["n_rays"], q["K"], n_tx, q["rx"].shape[0], log, q["args"])
+
+
+def launch_batch(queries, tile_rays=0, compact_threshold=-1.0, waves_per_cu=0, use_graph=False, autotune=False):
+    """Trace many queries together (one persistent kernel per bounce for all of them).
+
+    ``queries``: list of dicts with the keyword arguments of ``launch_rays``
+    (``scene``, ``tx``, ``rx``, ``n_rays``, ``max_reflections``, ...).  Returns
+    one Launch per query; each is bitwise the same as its solo launch_rays.
+    """
+    qs = [_query(**q) for q in queries]
+    if not qs:
+        return []
+    device = qs[0]["scene"].device
+    arr = (_lib.PcrlQuery * len(qs))()
+    for i, q in enumerate(qs):
+        arr[i].scene = q["scene"].handle
+        arr[i].tx = q["tx"].data_ptr()
+        arr[i].n_tx = q["tx"].shape[0]
+        arr[i].rx = q["rx"].data_ptr() if q["rx"].shape[0] else None
+        arr[i].n_rx = q["rx"].shape[0]
+        arr[i].params = q["params"]
+    bp = _batch_params(tile_rays, compact_threshold, waves_per_cu, use_graph, autotune)
+    out = (C.c_void_p * len(qs))()
+    with torch.cuda.device(device):
+        check("launch_batch", lib.launch_batch(arr, len(qs), C.byref(bp), _stream(device), out))
+    return [_make_launch(C.c_void_p(out[i]), q) for i, q in enumerate(qs)]
+
+
+def _batch_params(tile_rays=0, compact_threshold=-1.0, waves_per_cu=0, use_graph=False, autotune=False):
+    bp = _lib.PcrlBatchParams()
+    bp.tile_rays = int(tile_rays)
+    bp.compact_threshold = float(compact_threshold)
+    bp.waves_per_cu = int(waves_per_cu)
+    bp.use_graph = int(bool(use_graph))
+    bp.autotune = int(bool(autotune))
+    bp.flags = 0
+    return bp
+
+
+def batch_autotune(queries, use_graph=False) -> dict:
+    """Tune (tile_rays, compact_threshold, waves_per_cu) on these queries; returns the winner."""
+    qs = [_query(**q) for q in queries]
+    device = qs[0]["scene"].device
+    arr = (_lib.PcrlQuery * len(qs))()
+    for i, q in enumerate(qs):
+        arr[i].scene = q["scene"].handle
+        arr[i].tx = q["tx"].data_ptr()
+        arr[i].n_tx = q["tx"].shape[0]
+        arr[i].rx = q["rx"].data_ptr() if q["rx"].shape[0] else None
+        arr[i].n_rx = q["rx"].shape[0]
+        arr[i].params = q["params"]
+    bp = _batch_params(use_graph=use_graph)
+    with torch.cuda.device(device):
+        check("batch_autotune", lib.batch_autotune(arr, len(qs), _stream(device), C.byref(bp)))
+    return {"tile_rays": bp.tile_rays, "compact_threshold": bp.compact_threshold, "waves_per_cu": bp.waves_per_cu}
 
 
 def launch_directions(n_rays, device=None):
@@ -292,3 +382,107 @@ def _relaunch(launch: Launch, record_capacity: int):
     launch._h, new._h = new._h, None
     launch.hit_log = new.hit_log
     launch._args = new._args
+
+
+class Server:
+    """Request loop over one device-resident, incrementally re-voxelised scene (serve_* of the C ABI).
+
+    ``submit`` queues a TX/RX query (host arrays) and returns a ticket at once;
+    a native worker thread admits queries by memory budget and free slots,
+    packs them into batched launches on several streams (continuous batching)
+    and copies each result to host memory.  ``update`` replaces the dynamic
+    points (a new scene epoch).
+    """
+
+    def __init__(self, scene: Scene, max_inflight=256, n_streams=4, hbm_budget_bytes=0, max_batch=64, kappa=1,
+                 key_mode=KEY_LABELS, tile_rays=0, compact_threshold=-1.0, waves_per_cu=0, use_graph=False,
+                 autotune=False):
+        self.scene = scene
+        self.device = scene.device
+        p = _lib.PcrlServeParams()
+        p.max_inflight = int(max_inflight)
+        p.n_streams = int(n_streams)
+        p.hbm_budget_bytes = int(hbm_budget_bytes)
+        p.max_batch = int(max_batch)
+        p.kappa = int(kappa)
+        p.key_mode = int(key_mode)
+        p.batch = _batch_params(tile_rays, compact_threshold, waves_per_cu, use_graph, autotune)
+        self._h = C.c_void_p()
+        self._K = {}
+        with torch.cuda.device(self.device):
+            check("serve_create", lib.serve_create(scene.handle, C.byref(p), C.byref(self._h)))
+
+    def submit(self, tx, rx, n_rays, max_reflections, record_capacity=0, coherent=True) -> int:
+        tx = np.ascontiguousarray(np.asarray(tx, np.float32).reshape(-1, 3))
+        rx = np.ascontiguousarray(np.asarray(rx, np.float32).reshape(-1, 3)) if rx is not None else \
+            np.zeros((0, 3), np.float32)
+        p = _lib.PcrlLaunchParams()
+        p.n_rays = int(n_rays)
+        p.max_reflections = int(max_reflections)
+        p.record_capacity = int(record_capacity)
+        p.flags = LAUNCH_COHERENT if coherent else 0
+        t = C.c_int64()
+        check("serve_submit", lib.serve_submit(self._h, tx.ctypes.data, tx.shape[0],
+                                               rx.ctypes.data if rx.shape[0] else None, rx.shape[0], C.byref(p),
+                                               C.byref(t)))
+        self._K[t.value] = int(max_reflections)
+        return t.value
+
+    def update(self, ids, xyz, normal, label):
+        """Frame update: replace the dynamic points (device tensors or numpy arrays)."""
+        ids = _as_tensor(np.asarray(ids, np.int64).astype(np.uint32).view(np.int32)
+                         if isinstance(ids, np.ndarray) else ids, torch.int32, self.device)
+        xyz = _as_tensor(xyz, torch.float32, self.device, 3)
+        normal = _as_tensor(normal, torch.float32, self.device, 3)
+        if isinstance(label, np.ndarray):
+            label = torch.from_numpy(np.ascontiguousarray(label.astype(np.uint32)).view(np.int32))
+        label = _as_tensor(label, torch.int32, self.device)
+        torch.cuda.current_stream(self.device).synchronize()
+        n = xyz.shape[0]
+        with torch.cuda.device(self.device):
+            check("serve_update", lib.serve_update(self._h, _ptr(ids) if n else None, _ptr(xyz) if n else None,
+                                                   _ptr(normal) if n else None, _ptr(label) if n else None, n))
+
+    def poll(self, ticket, timeout=0.0) -> dict:
+        r = _lib.PcrlServeResult()
+        check("serve_poll", lib.serve_poll(self._h, int(ticket), float(timeout), C.byref(r)))
+        return {name: getattr(r, name) for name, _ in r._fields_ if name != "reserved"}
+
+    def result(self, ticket) -> dict:
+        info = self.poll(ticket)
+        if info["status"] != 2:
+            raise PcrlError("serve_result", -1, f"ticket {ticket} is not finished (status {info['status']})")
+        n, K = info["n_rows"], self._K[int(ticket)]
+        out = {"tx": np.empty(n, np.int32), "rx": np.empty(n, np.int32), "n_refl": np.empty(n, np.int32),
+               "key": np.empty((n, K), np.int64), "count": np.empty(n, np.int64), "rank": np.empty(n, np.int32),
+               "ray": np.empty(n, np.int64), "len_poly": np.empty(n, np.float32), "len_unf": np.empty(n, np.float32),
+               "points": np.empty((n, K, 3), np.float32)}
+        P = _lib.PcrlPaths()
+        P.capacity = n
+        for k, a in out.items():
+            setattr(P, k, a.ctypes.data if a.size else None)
+        check("serve_result", lib.serve_result(self._h, int(ticket), C.byref(P)))
+        out["n_rows"] = n
+        out["n_keys"] = info["n_keys"]
+        out["epoch"] = info["epoch"]
+        return out
+
+    def release(self, ticket):
+        check("serve_release", lib.serve_release(self._h, int(ticket)))
+        self._K.pop(int(ticket), None)
+
+    def stats(self) -> dict:
+        s = _lib.PcrlServeStats()
+        check("serve_stats", lib.serve_stats(self._h, C.byref(s)))
+        return {name: getattr(s, name) for name, _ in s._fields_ if name != "reserved"}
+
+    def close(self):
+        if self._h:
+            lib.serve_destroy(self._h)
+            self._h = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:  # pragma: no cover
+            pass

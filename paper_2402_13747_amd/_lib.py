@@ -42,11 +42,11 @@ class PcrlVoxelParams(C.Structure):
 
 class PcrlSceneInfo(C.Structure):
     _fields_ = [("n_points", C.c_int64), ("n_entries", C.c_int64), ("n_leaves", C.c_int64),
-                ("n_nodes", C.c_int64 * MAX_LEVELS), ("n_labels", C.c_int32), ("n_levels", C.c_int32),
+                ("n_nodes", C.c_int64 * MAX_LEVELS), ("max_label", C.c_int32), ("n_levels", C.c_int32),
                 ("dims", C.c_int32 * 3), ("dims0", C.c_int32 * 3), ("origin", C.c_float * 3),
                 ("leaf_size", C.c_float), ("surfel_radius", C.c_float), ("t_eps", C.c_float),
                 ("aabb", C.c_float * 6), ("device_bytes", C.c_int64), ("key_bits", C.c_int32),
-                ("reserved", C.c_int32)]
+                ("reserved", C.c_int32), ("n_dynamic", C.c_int64), ("epoch", C.c_int64)]
 
 
 class PcrlLaunchParams(C.Structure):
@@ -71,11 +71,40 @@ class PcrlPaths(C.Structure):
                 ("points", C.c_void_p)]
 
 
+class PcrlQuery(C.Structure):
+    _fields_ = [("scene", C.c_void_p), ("tx", C.c_void_p), ("n_tx", C.c_int32), ("n_rx", C.c_int32),
+                ("rx", C.c_void_p), ("params", PcrlLaunchParams)]
+
+
+class PcrlBatchParams(C.Structure):
+    _fields_ = [("tile_rays", C.c_int32), ("compact_threshold", C.c_float), ("waves_per_cu", C.c_int32),
+                ("use_graph", C.c_int32), ("autotune", C.c_int32), ("flags", C.c_int32)]
+
+
+class PcrlServeParams(C.Structure):
+    _fields_ = [("max_inflight", C.c_int32), ("n_streams", C.c_int32), ("hbm_budget_bytes", C.c_int64),
+                ("max_batch", C.c_int32), ("kappa", C.c_int32), ("key_mode", C.c_int32), ("reserved", C.c_int32),
+                ("batch", PcrlBatchParams)]
+
+
+class PcrlServeResult(C.Structure):
+    _fields_ = [("status", C.c_int32), ("reserved", C.c_int32), ("epoch", C.c_int64), ("n_rows", C.c_int64),
+                ("n_keys", C.c_int64), ("queue_ms", C.c_double), ("latency_ms", C.c_double)]
+
+
+class PcrlServeStats(C.Structure):
+    _fields_ = [("completed", C.c_int64), ("pending", C.c_int64), ("inflight", C.c_int32), ("reserved", C.c_int32),
+                ("rounds", C.c_int64), ("mean_batch", C.c_double), ("rays", C.c_int64), ("p50_ms", C.c_double),
+                ("p99_ms", C.c_double), ("max_ms", C.c_double), ("mean_ms", C.c_double), ("rays_per_s", C.c_double),
+                ("used_bytes", C.c_int64)]
+
+
 # name -> (restype, argtypes); every symbol declared in include/pcrl.h
 SIGNATURES = {
     "build_voxels": (C.c_int, [C.c_void_p, C.c_void_p, C.c_void_p, C.c_int64, C.POINTER(PcrlVoxelParams),
                                C.c_void_p, C.POINTER(C.c_void_p)]),
     "scene_info": (C.c_int, [C.c_void_p, C.POINTER(PcrlSceneInfo)]),
+    "update_points": (C.c_int, [C.c_void_p, C.c_void_p, C.c_void_p, C.c_void_p, C.c_void_p, C.c_int64, C.c_void_p]),
     "scene_leaf_table": (C.c_int, [C.c_void_p, C.c_void_p, C.c_void_p, C.c_void_p, C.c_void_p, C.c_void_p]),
     "release_scene": (C.c_int, [C.c_void_p]),
     "launch_rays": (C.c_int, [C.c_void_p, C.c_void_p, C.c_int32, C.c_void_p, C.c_int32,
@@ -86,6 +115,18 @@ SIGNATURES = {
                                  C.c_void_p, C.POINTER(C.c_int64)]),
     "release_launch": (C.c_int, [C.c_void_p]),
     "collect_paths": (C.c_int, [C.c_void_p, C.c_int32, C.c_int32, C.POINTER(PcrlPaths), C.c_void_p]),
+    "launch_batch": (C.c_int, [C.POINTER(PcrlQuery), C.c_int32, C.POINTER(PcrlBatchParams), C.c_void_p,
+                               C.POINTER(C.c_void_p)]),
+    "batch_autotune": (C.c_int, [C.POINTER(PcrlQuery), C.c_int32, C.c_void_p, C.POINTER(PcrlBatchParams)]),
+    "serve_create": (C.c_int, [C.c_void_p, C.POINTER(PcrlServeParams), C.POINTER(C.c_void_p)]),
+    "serve_submit": (C.c_int, [C.c_void_p, C.c_void_p, C.c_int32, C.c_void_p, C.c_int32, C.POINTER(PcrlLaunchParams),
+                               C.POINTER(C.c_int64)]),
+    "serve_update": (C.c_int, [C.c_void_p, C.c_void_p, C.c_void_p, C.c_void_p, C.c_void_p, C.c_int64]),
+    "serve_poll": (C.c_int, [C.c_void_p, C.c_int64, C.c_double, C.POINTER(PcrlServeResult)]),
+    "serve_result": (C.c_int, [C.c_void_p, C.c_int64, C.POINTER(PcrlPaths)]),
+    "serve_release": (C.c_int, [C.c_void_p, C.c_int64]),
+    "serve_stats": (C.c_int, [C.c_void_p, C.POINTER(PcrlServeStats)]),
+    "serve_destroy": (C.c_int, [C.c_void_p]),
     "last_error": (C.c_char_p, []),
     "pcrl_version": (C.c_char_p, []),
 }

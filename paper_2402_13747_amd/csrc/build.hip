@@ -144,33 +144,6 @@ __global__ __launch_bounds__(BUILD_BLOCK) void k_ingest_final(const IngestOut* p
 }
 
 // ---------------------------------------------------------------------------
-// labels -> dense ranks
-// ---------------------------------------------------------------------------
-
-__global__ void k_unique_flags_u32(const uint32_t* sorted, int64_t n, uint32_t* flag) {
-    int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
-    if (i < n) flag[i] = (i == 0 || sorted[i] != sorted[i - 1]) ? 1u : 0u;
-}
-
-__global__ void k_unique_compact_u32(const uint32_t* sorted, int64_t n, const uint32_t* pos, uint32_t* out) {
-    int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
-    if (i < n && (i == 0 || sorted[i] != sorted[i - 1])) out[pos[i]] = sorted[i];
-}
-
-__global__ void k_label_rank(const uint32_t* label, int64_t n, const uint32_t* uniq, const uint32_t* n_uniq,
-                             uint32_t* rank) {
-    int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
-    if (i >= n) return;
-    const uint32_t v = label[i];
-    uint32_t lo = 0, hi = *n_uniq;  // first index with uniq[idx] >= v
-    while (lo < hi) {
-        uint32_t mid = (lo + hi) >> 1;
-        if (uniq[mid] < v) lo = mid + 1; else hi = mid;
-    }
-    rank[i] = lo;
-}
-
-// ---------------------------------------------------------------------------
 // dilated keys
 // ---------------------------------------------------------------------------
 
@@ -306,13 +279,14 @@ __global__ void k_split_leaf(const uint2* r, int64_t n, uint32_t* b, uint32_t* c
 }
 
 __global__ void k_gather_surfels(const uint32_t* ids, int64_t m, const float* xyz, const float4* un,
-                                 const uint32_t* rank, float4* spos, float4* snrm) {
+                                 const uint32_t* label, const uint32_t* gid, float4* spos, float4* snrm) {
     int64_t e = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
     if (e >= m) return;
     const uint32_t i = ids[e];
-    spos[e] = make_float4(xyz[3 * (size_t)i], xyz[3 * (size_t)i + 1], xyz[3 * (size_t)i + 2], __uint_as_float(i));
+    const uint32_t g = gid ? gid[i] : i;
+    spos[e] = make_float4(xyz[3 * (size_t)i], xyz[3 * (size_t)i + 1], xyz[3 * (size_t)i + 2], __uint_as_float(g));
     const float4 nn = un[i];
-    snrm[e] = make_float4(nn.x, nn.y, nn.z, __uint_as_float(rank[i]));
+    snrm[e] = make_float4(nn.x, nn.y, nn.z, __uint_as_float(label[i]));
 }
 
 // ---------------------------------------------------------------------------
@@ -349,22 +323,9 @@ static int validate_params(const PcrlVoxelParams* p, int32_t ratio[PCRL_MAX_LEVE
     return PCRL_OK;
 }
 
-static int build_impl(const float* xyz, const float* nrm, const uint32_t* label, int64_t n,
-                      const PcrlVoxelParams* params, hipStream_t s, PcrlScene* S) {
-    int32_t ratio[PCRL_MAX_LEVELS] = {1, 1, 1, 1};
-    PCRL_TRY(validate_params(params, ratio));
-    if (n < 0 || (n > 0 && (!xyz || !nrm || !label))) {
-        set_error("build_voxels: invalid point arrays (n = %lld)", (long long)n);
-        return PCRL_EINVAL;
-    }
-    if (n > (int64_t)0x7FFFFFFF) {
-        set_error("build_voxels: at most 2^31-1 points are supported");
-        return PCRL_EINVAL;
-    }
-    hipGetDevice(&S->device);
-    DevBufs& B = S->bufs;
-    B.stream = s;
-    SceneView& v = S->view;
+// Grid frame of a new scene from its parameters and point AABB.
+static int make_frame(const PcrlVoxelParams* params, const int32_t ratio[PCRL_MAX_LEVELS], const IngestOut& io,
+                      SceneView& v) {
     const int L = params->n_levels;
     v.nlev = L;
     v.span[L - 1] = 1;
@@ -379,57 +340,28 @@ static int build_impl(const float* xyz, const float* nrm, const uint32_t* label,
     v.h = h;
     v.inv_h = 1.0f / h;
     const float r_s = params->surfel_radius;
+    v.r_s = r_s;
     v.rs2 = r_s * r_s;
-
-    // --- ingest
-    float4* unit_nrm = nullptr;
-    IngestOut io{};
-    DevBufs T;  // temporaries of the build
-    T.stream = s;
-    int rc = PCRL_OK;
-    auto fail = [&](int code) { T.release(); return code; };
-    if (n > 0) {
-        rc = T.alloc(&unit_nrm, (size_t)n);
-        if (rc) return fail(rc);
-        const unsigned nb = std::min<unsigned>(blocks_for(n), (unsigned)device_cus() * 4);
-        IngestOut *partial = nullptr, *res = nullptr;
-        if ((rc = T.alloc(&partial, nb)) || (rc = T.alloc(&res, 1))) return fail(rc);
-        hipLaunchKernelGGL(k_ingest, dim3(nb), dim3(BUILD_BLOCK), 0, s, xyz, nrm, label, n, unit_nrm, partial);
-        hipLaunchKernelGGL(k_ingest_final, dim3(1), dim3(BUILD_BLOCK), 0, s, partial, (int)nb, res);
-        if (hipGetLastError() != hipSuccess || hipMemcpyAsync(&io, res, sizeof io, hipMemcpyDeviceToHost, s) != hipSuccess ||
-            hipStreamSynchronize(s) != hipSuccess) {
-            set_error("build_voxels: ingest failed: %s", hipGetErrorString(hipGetLastError()));
-            return fail(PCRL_EHIP);
-        }
-        if (io.bad & 1u) { set_error("build_voxels: non-finite point coordinate"); return fail(PCRL_EINVAL); }
-        if (io.bad & 2u) { set_error("build_voxels: zero or non-finite normal"); return fail(PCRL_EINVAL); }
-    } else {
-        for (int a = 0; a < 3; ++a) { io.lo[a] = 0.f; io.hi[a] = 0.f; }
-        io.max_label = 0;
-    }
-
-    // --- grid frame
     float amax = 0.f;
     for (int a = 0; a < 3; ++a) amax = std::max(amax, std::max(std::fabs(io.lo[a]), std::fabs(io.hi[a])));
-    const float pad = 1e-3f * h + 4e-6f * amax;
+    v.pad = 1e-3f * h + 4e-6f * amax;
     const double cell0 = (double)h * v.span[0];
-    uint64_t cells0 = 1;
     for (int a = 0; a < 3; ++a) {
-        const double lo = (double)io.lo[a] - r_s - pad - h;
-        const double hi = (double)io.hi[a] + r_s + pad + h;
+        const double lo = (double)io.lo[a] - r_s - v.pad - h;
+        const double hi = (double)io.hi[a] + r_s + v.pad + h;
         int64_t d0 = (int64_t)std::ceil((hi - lo) / cell0);
         if (d0 < 1) d0 = 1;
         if (d0 * v.span[0] >= (int64_t)1 << 22) {
             set_error("build_voxels: leaf grid too large along axis %d (%lld leaves, max 2^22)", a,
                       (long long)(d0 * v.span[0]));
-            return fail(PCRL_EINVAL);
+            return PCRL_EINVAL;
         }
         v.dim0[a] = (int32_t)d0;
         v.dim[a] = (int32_t)(d0 * v.span[0]);
         v.org[a] = (float)lo;
         v.hi[a] = (float)((double)v.org[a] + (double)v.dim[a] * h);
-        cells0 *= (uint64_t)d0;
     }
+    const uint64_t cells0 = (uint64_t)v.dim0[0] * v.dim0[1] * v.dim0[2];
     v.lbits[0] = bits_for(cells0 - 1);
     int key_bits = v.lbits[0];
     for (int i = 1; i < L; ++i) {
@@ -440,12 +372,33 @@ static int build_impl(const float* xyz, const float* nrm, const uint32_t* label,
     }
     if (key_bits > 64) {
         set_error("build_voxels: hierarchical key needs %d bits (max 64); use coarser levels", key_bits);
-        return fail(PCRL_EINVAL);
+        return PCRL_EINVAL;
     }
+    v.key_bits = key_bits;
     const double diag = std::sqrt((double)(io.hi[0] - io.lo[0]) * (io.hi[0] - io.lo[0]) +
                                   (double)(io.hi[1] - io.lo[1]) * (io.hi[1] - io.lo[1]) +
                                   (double)(io.hi[2] - io.lo[2]) * (io.hi[2] - io.lo[2]));
     v.t_eps = params->t_eps > 0.f ? params->t_eps : (float)std::max(1e-5 * diag, 1e-6);
+    return PCRL_OK;
+}
+
+// What a hierarchy build produces besides its view.
+struct HierBuild {
+    int64_t n_entries = 0;
+    int64_t n_leaves = 0;
+    int64_t n_nodes[PCRL_MAX_LEVELS] = {0, 0, 0, 0};
+    int64_t bytes = 0;
+    uint64_t* leaf_key = nullptr;
+    uint32_t* entry_point = nullptr;
+    uint2* leaf_range = nullptr;
+};
+
+// Voxelise n ingested points into the frame already set in v (level-0 map,
+// bricks, leaves, surfel streams).  gid: global point ids (null: 0..n-1).
+static int build_hierarchy(const float* xyz, const float4* unit_nrm, const uint32_t* label, const uint32_t* gid,
+                           int64_t n, hipStream_t s, SceneView& v, DevBufs& B, DevBufs& T, HierBuild& hb) {
+    const int L = v.nlev;
+    int rc = PCRL_OK;
     LevelShifts ls{};
     ls.nlev = L;
     {
@@ -455,101 +408,58 @@ static int build_impl(const float* xyz, const float* nrm, const uint32_t* label,
             acc += v.lbits[l];
         }
     }
-
-    // level-0 map (always allocated)
+    const uint64_t cells0 = (uint64_t)v.dim0[0] * v.dim0[1] * v.dim0[2];
     int32_t* map0 = nullptr;
-    if ((rc = B.alloc(&map0, (size_t)cells0))) return fail(rc);
-    if ((rc = fill_u32((uint32_t*)map0, 0xFFFFFFFFu, (int64_t)cells0, s))) return fail(rc);
+    if ((rc = B.alloc(&map0, (size_t)cells0))) return rc;
+    if ((rc = fill_u32((uint32_t*)map0, 0xFFFFFFFFu, (int64_t)cells0, s))) return rc;
     v.map0 = map0;
+    for (int l = 0; l < PCRL_MAX_LEVELS; ++l) v.nn[l] = 0;
+    hb.bytes = (int64_t)cells0 * 4;
+    if (n == 0) return PCRL_OK;
 
-    PcrlSceneInfo& info = S->info;
-    info.n_points = n;
-    info.n_levels = L;
-    for (int a = 0; a < 3; ++a) {
-        info.dims[a] = v.dim[a];
-        info.dims0[a] = v.dim0[a];
-        info.origin[a] = v.org[a];
-        info.aabb[a] = io.lo[a];
-        info.aabb[3 + a] = io.hi[a];
-    }
-    info.leaf_size = h;
-    info.surfel_radius = r_s;
-    info.t_eps = v.t_eps;
-    info.key_bits = key_bits;
-
-    if (n == 0) {
-        uint32_t* lu = nullptr;
-        if ((rc = B.alloc(&lu, 1))) return fail(rc);
-        S->labels_u = lu;
-        info.n_labels = 0;
-        S->label_bits = 1;
-        T.release();
-        return PCRL_OK;
-    }
-
-    // --- label ranks (sorted unique labels; rank = index)
-    uint32_t *lab_sorted = nullptr, *lab_flag = nullptr, *rank = nullptr, *n_uniq = nullptr, *lab_u = nullptr;
-    if ((rc = T.alloc(&lab_sorted, (size_t)n)) || (rc = T.alloc(&lab_flag, (size_t)n)) ||
-        (rc = T.alloc(&rank, (size_t)n)) || (rc = T.alloc(&n_uniq, 1)) || (rc = B.alloc(&lab_u, (size_t)n)))
-        return fail(rc);
-    if (hipMemcpyAsync(lab_sorted, label, (size_t)n * 4, hipMemcpyDeviceToDevice, s) != hipSuccess) {
-        set_error("build_voxels: label copy failed");
-        return fail(PCRL_EHIP);
-    }
-    if ((rc = radix_sort_u32(lab_sorted, nullptr, n, bits_for(io.max_label), s))) return fail(rc);
-    hipLaunchKernelGGL(k_unique_flags_u32, dim3(blocks_for(n)), dim3(BUILD_BLOCK), 0, s, lab_sorted, n, lab_flag);
-    if ((rc = scan_u32(lab_flag, lab_flag, n, n_uniq, s))) return fail(rc);
-    hipLaunchKernelGGL(k_unique_compact_u32, dim3(blocks_for(n)), dim3(BUILD_BLOCK), 0, s, lab_sorted, n, lab_flag,
-                       lab_u);
-    hipLaunchKernelGGL(k_label_rank, dim3(blocks_for(n)), dim3(BUILD_BLOCK), 0, s, label, n, lab_u, n_uniq, rank);
-    S->labels_u = lab_u;
-
-    // --- dilated key counts
+    // dilated key counts and their total
     KeyParams kp;
     kp.v = v;
-    kp.r_s = r_s;
-    kp.pad = pad;
+    kp.r_s = v.r_s;
+    kp.pad = v.pad;
     uint32_t *cnt = nullptr, *tot = nullptr;
-    if ((rc = T.alloc(&cnt, (size_t)n)) || (rc = T.alloc(&tot, 2))) return fail(rc);
+    if ((rc = T.alloc(&cnt, (size_t)n)) || (rc = T.alloc(&tot, 1))) return rc;
     hipLaunchKernelGGL(k_key_count, dim3(blocks_for(n)), dim3(BUILD_BLOCK), 0, s, kp, xyz, unit_nrm, n, cnt);
-    if ((rc = scan_u32(cnt, cnt, n, tot, s))) return fail(rc);
-    if (hipMemcpyAsync(tot + 1, n_uniq, 4, hipMemcpyDeviceToDevice, s) != hipSuccess) return fail(PCRL_EHIP);
-    uint32_t host_tot[2] = {0, 0};
-    if (hipMemcpyAsync(host_tot, tot, 8, hipMemcpyDeviceToHost, s) != hipSuccess || hipStreamSynchronize(s) != hipSuccess) {
+    if ((rc = scan_u32(cnt, cnt, n, tot, s))) return rc;
+    uint32_t host_tot = 0;
+    if (hipMemcpyAsync(&host_tot, tot, 4, hipMemcpyDeviceToHost, s) != hipSuccess || hipStreamSynchronize(s) != hipSuccess) {
         set_error("build_voxels: key count failed: %s", hipGetErrorString(hipGetLastError()));
-        return fail(PCRL_EHIP);
+        return PCRL_EHIP;
     }
-    const int64_t m = host_tot[0];
-    info.n_labels = (int32_t)host_tot[1];
-    S->label_bits = bits_for((uint64_t)host_tot[1]);  // ranks 0..n-1 stored +1
-    info.n_entries = m;
+    const int64_t m = host_tot;
+    hb.n_entries = m;
 
-    // --- emit and sort (key, point id)
+    // emit and sort (key, local point index)
     uint64_t* keys = nullptr;
     uint32_t* ids = nullptr;
-    if ((rc = T.alloc(&keys, (size_t)m)) || (rc = B.alloc(&ids, (size_t)m))) return fail(rc);
+    if ((rc = T.alloc(&keys, (size_t)m)) || (rc = B.alloc(&ids, (size_t)m))) return rc;
     hipLaunchKernelGGL(k_key_emit, dim3(blocks_for(n)), dim3(BUILD_BLOCK), 0, s, kp, xyz, unit_nrm, n, cnt, keys, ids);
-    if ((rc = radix_sort_u64(keys, ids, m, key_bits, s))) return fail(rc);
-    S->entry_point = ids;
+    if ((rc = radix_sort_u64(keys, ids, m, v.key_bits, s))) return rc;
+    hb.entry_point = ids;
 
-    // --- per-level node boundaries
+    // per-level node boundaries
     uint32_t *scans = nullptr, *ltot = nullptr;
-    if ((rc = T.alloc(&scans, (size_t)L * m)) || (rc = T.alloc(&ltot, PCRL_MAX_LEVELS))) return fail(rc);
+    if ((rc = T.alloc(&scans, (size_t)L * m)) || (rc = T.alloc(&ltot, PCRL_MAX_LEVELS))) return rc;
     hipLaunchKernelGGL(k_level_flags, dim3(blocks_for(m)), dim3(BUILD_BLOCK), 0, s, keys, m, ls, scans);
     for (int l = 0; l < L; ++l)
-        if ((rc = scan_u32(scans + (size_t)l * m, scans + (size_t)l * m, m, ltot + l, s))) return fail(rc);
+        if ((rc = scan_u32(scans + (size_t)l * m, scans + (size_t)l * m, m, ltot + l, s))) return rc;
     uint32_t host_nodes[PCRL_MAX_LEVELS] = {0, 0, 0, 0};
     if (hipMemcpyAsync(host_nodes, ltot, 4 * L, hipMemcpyDeviceToHost, s) != hipSuccess ||
         hipStreamSynchronize(s) != hipSuccess) {
         set_error("build_voxels: level scan failed: %s", hipGetErrorString(hipGetLastError()));
-        return fail(PCRL_EHIP);
+        return PCRL_EHIP;
     }
     for (int l = 0; l < L; ++l) {
-        info.n_nodes[l] = host_nodes[l];
+        hb.n_nodes[l] = host_nodes[l];
         v.nn[l] = host_nodes[l];
     }
     const int64_t n_leaves = host_nodes[L - 1];
-    info.n_leaves = n_leaves;
+    hb.n_leaves = n_leaves;
 
     HierOut ho{};
     ho.map0 = map0;
@@ -558,9 +468,8 @@ static int build_impl(const float* xyz, const float* nrm, const uint32_t* label,
         uint64_t* mk = nullptr;
         uint32_t* bs = nullptr;
         uint32_t* fc = nullptr;
-        if ((rc = B.alloc(&mk, words)) || (rc = B.alloc(&bs, words)) || (rc = T.alloc(&fc, host_nodes[l])))
-            return fail(rc);
-        if ((rc = fill_u64(mk, 0ull, (int64_t)words, s))) return fail(rc);
+        if ((rc = B.alloc(&mk, words)) || (rc = B.alloc(&bs, words)) || (rc = T.alloc(&fc, host_nodes[l]))) return rc;
+        if ((rc = fill_u64(mk, 0ull, (int64_t)words, s))) return rc;
         ho.mask[l] = mk;
         ho.first_child[l] = fc;
         v.mask[l] = mk;
@@ -568,7 +477,7 @@ static int build_impl(const float* xyz, const float* nrm, const uint32_t* label,
     }
     uint2* leaf = nullptr;
     uint64_t* lkey = nullptr;
-    if ((rc = B.alloc(&leaf, (size_t)n_leaves)) || (rc = B.alloc(&lkey, (size_t)n_leaves))) return fail(rc);
+    if ((rc = B.alloc(&leaf, (size_t)n_leaves)) || (rc = B.alloc(&lkey, (size_t)n_leaves))) return rc;
     ho.leaf = leaf;
     ho.leaf_key = lkey;
     hipLaunchKernelGGL(k_hier_link, dim3(blocks_for(m)), dim3(BUILD_BLOCK), 0, s, keys, m, ls, v, scans, ho);
@@ -577,24 +486,145 @@ static int build_impl(const float* xyz, const float* nrm, const uint32_t* label,
                            ho.first_child[l], (int64_t)host_nodes[l], v.nw[l], (uint32_t*)v.base[l]);
     hipLaunchKernelGGL(k_leaf_counts, dim3(blocks_for(n_leaves)), dim3(BUILD_BLOCK), 0, s, leaf, n_leaves, m);
     v.leaf = leaf;
-    S->leaf_range = leaf;
-    S->leaf_key = lkey;
+    hb.leaf_range = leaf;
+    hb.leaf_key = lkey;
 
-    // --- surfel streams in leaf order
+    // surfel streams in leaf order
     float4 *spos = nullptr, *snrm = nullptr;
-    if ((rc = B.alloc(&spos, (size_t)m)) || (rc = B.alloc(&snrm, (size_t)m))) return fail(rc);
-    hipLaunchKernelGGL(k_gather_surfels, dim3(blocks_for(m)), dim3(BUILD_BLOCK), 0, s, ids, m, xyz, unit_nrm, rank,
-                       spos, snrm);
+    if ((rc = B.alloc(&spos, (size_t)m)) || (rc = B.alloc(&snrm, (size_t)m))) return rc;
+    hipLaunchKernelGGL(k_gather_surfels, dim3(blocks_for(m)), dim3(BUILD_BLOCK), 0, s, ids, m, xyz, unit_nrm, label,
+                       gid, spos, snrm);
     v.spos = spos;
     v.snrm = snrm;
     if (hipGetLastError() != hipSuccess) {
         set_error("build_voxels: kernel launch failed");
-        return fail(PCRL_EHIP);
+        return PCRL_EHIP;
     }
-    int64_t bytes = (int64_t)cells0 * 4 + (int64_t)n * 4 + m * (4 + 32) + n_leaves * 16;
-    for (int l = 0; l + 1 < L; ++l) bytes += (int64_t)host_nodes[l] * v.nw[l] * 12;
-    info.device_bytes = bytes;
+    hb.bytes += m * (4 + 32) + n_leaves * 16;
+    for (int l = 0; l + 1 < L; ++l) hb.bytes += (int64_t)host_nodes[l] * v.nw[l] * 12;
+    return PCRL_OK;
+}
+
+// Validate and normalise n points (one synchronisation).  unit_nrm is
+// allocated in T.
+static int ingest(const float* xyz, const float* nrm, const uint32_t* label, int64_t n, hipStream_t s, DevBufs& T,
+                  float4** unit_nrm, IngestOut& io, const char* fn) {
+    for (int a = 0; a < 3; ++a) { io.lo[a] = 0.f; io.hi[a] = 0.f; }
+    io.max_label = 0;
+    io.bad = 0;
+    *unit_nrm = nullptr;
+    if (n == 0) return PCRL_OK;
+    int rc;
+    if ((rc = T.alloc(unit_nrm, (size_t)n))) return rc;
+    const unsigned nb = std::min<unsigned>(blocks_for(n), (unsigned)device_cus() * 4);
+    IngestOut *partial = nullptr, *res = nullptr;
+    if ((rc = T.alloc(&partial, nb)) || (rc = T.alloc(&res, 1))) return rc;
+    hipLaunchKernelGGL(k_ingest, dim3(nb), dim3(BUILD_BLOCK), 0, s, xyz, nrm, label, n, *unit_nrm, partial);
+    hipLaunchKernelGGL(k_ingest_final, dim3(1), dim3(BUILD_BLOCK), 0, s, partial, (int)nb, res);
+    if (hipGetLastError() != hipSuccess || hipMemcpyAsync(&io, res, sizeof io, hipMemcpyDeviceToHost, s) != hipSuccess ||
+        hipStreamSynchronize(s) != hipSuccess) {
+        set_error("%s: ingest failed: %s", fn, hipGetErrorString(hipGetLastError()));
+        return PCRL_EHIP;
+    }
+    if (io.bad & 1u) { set_error("%s: non-finite point coordinate", fn); return PCRL_EINVAL; }
+    if (io.bad & 2u) { set_error("%s: zero or non-finite normal", fn); return PCRL_EINVAL; }
+    return PCRL_OK;
+}
+
+static int build_impl(const float* xyz, const float* nrm, const uint32_t* label, int64_t n,
+                      const PcrlVoxelParams* params, hipStream_t s, PcrlScene* S) {
+    int32_t ratio[PCRL_MAX_LEVELS] = {1, 1, 1, 1};
+    PCRL_TRY(validate_params(params, ratio));
+    if (n < 0 || (n > 0 && (!xyz || !nrm || !label))) {
+        set_error("build_voxels: invalid point arrays (n = %lld)", (long long)n);
+        return PCRL_EINVAL;
+    }
+    if (n > (int64_t)0x7FFFFFFF) {
+        set_error("build_voxels: at most 2^31-1 points are supported");
+        return PCRL_EINVAL;
+    }
+    (void)hipGetDevice(&S->device);
+    S->bufs.stream = s;
+    DevBufs T;
+    T.stream = s;
+    auto fail = [&](int code) { T.release(); return code; };
+    float4* unit_nrm = nullptr;
+    IngestOut io{};
+    int rc;
+    if ((rc = ingest(xyz, nrm, label, n, s, T, &unit_nrm, io, "build_voxels"))) return fail(rc);
+    SceneView& v = S->view;
+    if ((rc = make_frame(params, ratio, io, v))) return fail(rc);
+    HierBuild hb;
+    if ((rc = build_hierarchy(xyz, unit_nrm, label, nullptr, n, s, v, S->bufs, T, hb))) return fail(rc);
+    S->max_label = io.max_label;
+    S->leaf_key = hb.leaf_key;
+    S->entry_point = hb.entry_point;
+    S->leaf_range = hb.leaf_range;
+    PcrlSceneInfo& info = S->info;
+    info.n_points = n;
+    info.n_entries = hb.n_entries;
+    info.n_leaves = hb.n_leaves;
+    for (int l = 0; l < PCRL_MAX_LEVELS; ++l) info.n_nodes[l] = hb.n_nodes[l];
+    info.max_label = (int32_t)io.max_label;
+    info.n_levels = params->n_levels;
+    for (int a = 0; a < 3; ++a) {
+        info.dims[a] = v.dim[a];
+        info.dims0[a] = v.dim0[a];
+        info.origin[a] = v.org[a];
+        info.aabb[a] = io.lo[a];
+        info.aabb[3 + a] = io.hi[a];
+    }
+    info.leaf_size = v.h;
+    info.surfel_radius = v.r_s;
+    info.t_eps = v.t_eps;
+    info.key_bits = v.key_bits;
+    info.device_bytes = hb.bytes;
+    info.n_dynamic = 0;
+    info.epoch = 0;
     T.release();
+    return PCRL_OK;
+}
+
+// Overlay of dynamic points on the frame of `base`.
+static int overlay_impl(PcrlScene* S, const uint32_t* gid, const float* xyz, const float* nrm, const uint32_t* label,
+                        int64_t n, hipStream_t s) {
+    auto ov = std::make_shared<Overlay>();
+    ov->bufs.stream = s;
+    DevBufs T;
+    T.stream = s;
+    auto fail = [&](int code) { T.release(); return code; };
+    float4* unit_nrm = nullptr;
+    IngestOut io{};
+    int rc;
+    if ((rc = ingest(xyz, nrm, label, n, s, T, &unit_nrm, io, "update_points"))) return fail(rc);
+    const SceneView& bv = S->view;
+    for (int a = 0; a < 3; ++a) {
+        if (n > 0 && (io.lo[a] < bv.org[a] + bv.r_s + bv.h || io.hi[a] > bv.hi[a] - bv.r_s - bv.h)) {
+            set_error("update_points: dynamic points leave the scene grid along axis %d ([%g, %g] vs grid [%g, %g])", a,
+                      io.lo[a], io.hi[a], bv.org[a], bv.hi[a]);
+            return fail(PCRL_EINVAL);
+        }
+    }
+    SceneView v = bv;  // same frame: origin, levels, padding, t_eps
+    v.map0 = nullptr;
+    for (int l = 0; l + 1 < PCRL_MAX_LEVELS; ++l) {
+        v.mask[l] = nullptr;
+        v.base[l] = nullptr;
+    }
+    v.leaf = nullptr;
+    v.spos = v.snrm = nullptr;
+    HierBuild hb;
+    if ((rc = build_hierarchy(xyz, unit_nrm, label, gid, n, s, v, ov->bufs, T, hb))) return fail(rc);
+    ov->view = v;
+    ov->n_points = n;
+    ov->n_entries = hb.n_entries;
+    ov->max_label = io.max_label;
+    ov->bytes = hb.bytes;
+    T.release();
+    ov->epoch = S->info.epoch + 1;
+    S->info.epoch = ov->epoch;
+    S->info.n_dynamic = n;
+    S->overlay = n > 0 ? ov : nullptr;
     return PCRL_OK;
 }
 
@@ -625,6 +655,16 @@ extern "C" int build_voxels(const float* xyz, const float* normal, const uint32_
     return PCRL_OK;
 }
 
+extern "C" int update_points(PcrlScene* scene, const uint32_t* ids, const float* xyz, const float* normal,
+                             const uint32_t* label, int64_t n, pcrl_stream_t stream) {
+    clear_error();
+    if (!scene || n < 0 || (n > 0 && (!ids || !xyz || !normal || !label)) || n > (int64_t)0x7FFFFFFF) {
+        set_error("update_points: invalid arguments");
+        return PCRL_EINVAL;
+    }
+    return overlay_impl(scene, ids, xyz, normal, label, n, (hipStream_t)stream);
+}
+
 extern "C" int scene_info(const PcrlScene* scene, PcrlSceneInfo* out) {
     clear_error();
     if (!scene || !out) {
@@ -632,6 +672,7 @@ extern "C" int scene_info(const PcrlScene* scene, PcrlSceneInfo* out) {
         return PCRL_EINVAL;
     }
     *out = scene->info;
+    if (scene->overlay) out->device_bytes += scene->overlay->bytes;
     return PCRL_OK;
 }
 
@@ -661,6 +702,7 @@ extern "C" int scene_leaf_table(const PcrlScene* scene, uint64_t* leaf_key, uint
 extern "C" int release_scene(PcrlScene* scene) {
     clear_error();
     if (!scene) return PCRL_OK;
+    scene->overlay.reset();
     scene->bufs.release();
     delete scene;
     return PCRL_OK;

@@ -141,7 +141,7 @@ struct OutArrays {
 
 __global__ void k_write_rows(const uint4* rec, const float4* hist, const uint64_t* words, int W, const uint32_t* perm,
                              uint32_t n, const uint32_t* kscan, const uint32_t* start, const uint32_t* n_keys,
-                             const uint32_t* keep_scan, int32_t kappa, KeySpec ks, const uint32_t* labels_u,
+                             const uint32_t* keep_scan, int32_t kappa, KeySpec ks,
                              OutArrays o) {
     const uint32_t i = blockIdx.x * blockDim.x + threadIdx.x;
     if (i >= n) return;
@@ -173,7 +173,7 @@ __global__ void k_write_rows(const uint4* rec, const float4* hist, const uint64_
             int64_t kv = -1;
             if ((uint32_t)k < b) {
                 if (ks.mode == PCRL_KEY_LABELS) {
-                    kv = (int64_t)labels_u[__float_as_uint(h.w)];
+                    kv = (int64_t)__float_as_uint(h.w);
                 } else {
                     int64_t c[3];
                     const float p[3] = {h.x, h.y, h.z};
@@ -230,7 +230,7 @@ static int collect_impl(PcrlLaunch* L, int32_t kappa, int32_t key_mode, PcrlPath
     ks.br = bits_for((uint64_t)std::max(L->n_rx - 1, 0));
     ks.bb = bits_for((uint64_t)K);
     if (key_mode == PCRL_KEY_LABELS) {
-        ks.bl = bits_for((uint64_t)S->info.n_labels);
+        ks.bl = bits_for((uint64_t)L->max_label + 1);  // label + 1, 0 past the path's end
     } else {
         const uint64_t cells = (uint64_t)S->view.dim[0] * S->view.dim[1] * S->view.dim[2];
         ks.bl = bits_for(cells);
@@ -294,7 +294,7 @@ static int collect_impl(PcrlLaunch* L, int32_t kappa, int32_t key_mode, PcrlPath
     OutArrays oa{out->tx, out->rx, out->n_refl, out->key, out->count, out->rank, out->ray, out->len_poly, out->len_unf,
                  out->points};
     hipLaunchKernelGGL(k_write_rows, dim3(nblk(n)), dim3(256), 0, s, L->rec, L->hist, words, ks.W, perm, n, kscan,
-                       start, tots, keep, kappa, ks, S->labels_u, oa);
+                       start, tots, keep, kappa, ks, oa);
     if (hipGetLastError() != hipSuccess || hipStreamSynchronize(s) != hipSuccess) {
         set_error("collect_paths: output kernel failed: %s", hipGetErrorString(hipGetLastError()));
         return fail(PCRL_EHIP);

@@ -10,6 +10,7 @@
 
 #include <cstdarg>
 #include <cstdint>
+#include <memory>
 #include <string>
 #include <vector>
 
@@ -142,6 +143,9 @@ struct SceneView {
     float inv_h;
     float rs2;             // r_s^2
     float t_eps;
+    float r_s;
+    float pad;             // rounding margin added to every disk's leaf box
+    int32_t key_bits;      // bits of the hierarchical leaf key
     int32_t dim[3];        // leaf grid dims
     int32_t dim0[3];       // level-0 grid dims
     int32_t nlev;
@@ -156,7 +160,7 @@ struct SceneView {
     const uint32_t* base[PCRL_MAX_LEVELS - 1];  // child index of the first set bit of each word
     const uint2* leaf;               // per leaf: (first entry, entry count)
     const float4* spos;              // per entry: x, y, z, point id (bits)
-    const float4* snrm;              // per entry: unit normal, label rank (bits)
+    const float4* snrm;              // per entry: unit normal, label (bits)
 };
 
 // x / span for 0 <= x < 2^22 and span <= 2^18 with a precomputed ceil(2^40 / span):
@@ -184,16 +188,31 @@ __host__ __device__ inline uint64_t leaf_key_of(const SceneView& v, int ix, int 
 // opaque objects
 // ---------------------------------------------------------------------------
 
+namespace pcrl {
+// Dynamic points of one epoch, voxelised on the base scene's frame.  Held by
+// the scene until the next update and by every launch that traced it.
+struct Overlay {
+    SceneView view{};
+    DevBufs bufs;
+    int64_t n_points = 0;
+    int64_t n_entries = 0;
+    int64_t bytes = 0;
+    uint32_t max_label = 0;
+    int64_t epoch = 0;
+    ~Overlay() { bufs.release(); }
+};
+}  // namespace pcrl
+
 struct PcrlScene {
     int device = 0;
-    pcrl::SceneView view{};
+    pcrl::SceneView view{};           // static base hierarchy
     pcrl::DevBufs bufs;
     PcrlSceneInfo info{};
-    uint32_t* labels_u = nullptr;   // distinct labels, ascending (rank -> label)
-    uint64_t* leaf_key = nullptr;   // per leaf hierarchical key
+    uint64_t* leaf_key = nullptr;     // per leaf hierarchical key
     uint32_t* entry_point = nullptr;  // per entry: point id (leaf order)
     uint2* leaf_range = nullptr;
-    int32_t label_bits = 1;         // bits to hold a label rank + 1
+    uint32_t max_label = 0;
+    std::shared_ptr<pcrl::Overlay> overlay;  // current epoch of dynamic points (may be null)
 };
 
 struct PcrlLaunch {
@@ -205,11 +224,15 @@ struct PcrlLaunch {
     int32_t flags = 0;
     float sigma = 1.25f, alpha = 0.f;
     int64_t rec_cap = 0;
-    float4* hist = nullptr;         // [K][n_total]: interaction point, label rank (bits)
+    std::shared_ptr<pcrl::Overlay> overlay;  // epoch of dynamic points this launch traced
+    uint32_t max_label = 0;         // largest label of base and overlay
+    float4* hist = nullptr;         // [K][n_total]: interaction point, label (bits)
     uint4* rec = nullptr;           // [rec_cap]: ray, rx | b << 16, len_poly, len_unf
     uint32_t* counters = nullptr;   // [0..K+1] active rays per bounce, [K+2] records
     unsigned long long* stats = nullptr;  // [8] device counters (PCRL_LAUNCH_STATS)
     std::vector<hipEvent_t> events; // 2 per bounce (PCRL_LAUNCH_TIMING)
+    bool owns_events = false;       // false: events belong to a batch (shared)
+    std::shared_ptr<void> shared;   // batch-level state kept alive by every query of a batch
 };
 
 // counters layout
@@ -218,6 +241,8 @@ struct PcrlLaunch {
 
 // internal entry points of the launch translation unit (used by batching)
 namespace pcrl {
-int launch_enqueue(PcrlLaunch* L, const float* tx, const float* rx, const float* dirs, int32_t* hit_id,
-                   float* hit_t);
+struct TraceArgs;
+int launch_prepare(const PcrlScene* scene, const float* tx, int32_t n_tx, const float* rx, int32_t n_rx,
+                   const PcrlLaunchParams* p, hipStream_t s, bool timing_events, PcrlLaunch** out, TraceArgs* args);
+void destroy_launch(PcrlLaunch* L);
 }

@@ -12,6 +12,7 @@
 #include "internal.h"
 
 #include <cstdio>
+#include <mutex>
 
 namespace pcrl {
 
@@ -39,11 +40,12 @@ const char* get_error() { return g_err.c_str(); }
 // ---------------------------------------------------------------------------
 
 static int g_pool_ready = -1;  // -1 unknown, 0 no async pool, 1 pool configured
+static std::once_flag g_pool_once;
 
 int dalloc(void** p, size_t bytes, hipStream_t s) {
     *p = nullptr;
     if (bytes == 0) bytes = 256;
-    if (g_pool_ready < 0) {
+    std::call_once(g_pool_once, [] {
         int dev = 0;
         int supported = 0;
         if (hipGetDevice(&dev) == hipSuccess &&
@@ -60,7 +62,7 @@ int dalloc(void** p, size_t bytes, hipStream_t s) {
         } else {
             g_pool_ready = 0;
         }
-    }
+    });
     hipError_t e = g_pool_ready ? hipMallocAsync(p, bytes, s) : hipMalloc(p, bytes);
     if (e != hipSuccess) {
         (void)hipGetLastError();

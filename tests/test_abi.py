@@ -53,7 +53,7 @@ def test_struct_sizes(pcrl):
     # sizes fixed by the header's field lists (natural alignment)
     assert C.sizeof(_lib.PcrlVoxelParams) == 32
     assert C.sizeof(_lib.PcrlLaunchParams) == 64
-    assert C.sizeof(_lib.PcrlSceneInfo) == 152
+    assert C.sizeof(_lib.PcrlSceneInfo) == 168
     assert C.sizeof(_lib.PcrlPaths) == 13 * 8
 
 
