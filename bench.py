@@ -72,12 +72,250 @@ def cpu_baseline(s, t_eps, seconds):
                       f"FP64 brute force over all {s.n_points} points, {dt2:.1f} s"}
 
 
+def _gen_batch_scene(args):
+    import scenes
+    seed, point_scale, ray_scale = args
+    return scenes.batch_scenes(seeds=[seed], point_scale=point_scale, ray_scale=ray_scale)[0]
+
+
+def bench_batch(args, pcrl, torch):
+    """256 scenes of uneven size, one query each: 256 plain launches vs one batched launch."""
+    import multiprocessing as mp
+    dev = torch.device("cuda", 0)
+    n = args.batch_scenes
+    log(f"[batch] generating {n} scenes (point scale {args.batch_point_scale}, ray scale {args.batch_ray_scale})")
+    with mp.get_context("fork").Pool(min(16, os.cpu_count() or 1)) as pool:
+        specs = pool.map(_gen_batch_scene, [(s, args.batch_point_scale, args.batch_ray_scale) for s in range(n)])
+    from tests.parity import t_eps_of
+    queries = []
+    total_rays = 0
+    total_points = 0
+    for k, s in enumerate(specs):
+        sc = pcrl.build_voxels(s.xyz, s.normal, s.label, s.levels, float(np.float32(s.surfel_radius)),
+                               t_eps=float(np.float32(t_eps_of(s))), device=dev)
+        sc._inputs = None
+        queries.append(dict(scene=sc, tx=s.tx, rx=s.rx, n_rays=s.n_rays, max_reflections=s.max_reflections))
+        total_rays += s.n_rays * len(s.tx)
+        total_points += s.n_points
+        if k % 32 == 31:
+            log(f"[batch] built {k + 1} scenes")
+    torch.cuda.synchronize()
+    # inputs already on the device
+    for q in queries:
+        q["tx"] = torch.from_numpy(q["tx"]).to(dev)
+        q["rx"] = torch.from_numpy(q["rx"]).to(dev)
+
+    def plain():
+        out = []
+        for q in queries:
+            L = pcrl.launch_rays(**q)
+            out.append(pcrl.collect_paths(L, kappa=1))
+            L.release()
+        return out
+
+    def batched(**kw):
+        Ls = pcrl.launch_batch(queries, **kw)
+        out = [pcrl.collect_paths(L, kappa=1) for L in Ls]
+        for L in Ls:
+            L.release()
+        return out
+
+    def timed(fn, reps, **kw):
+        fn(**kw)  # warm-up
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        for _ in range(reps):
+            res = fn(**kw)
+        torch.cuda.synchronize()
+        return (time.perf_counter() - t0) / reps, res
+
+    log("[batch] autotuning on 32 queries")
+    tuned = pcrl.batch_autotune(queries[:32])
+    log(f"[batch] tuned {tuned}")
+    t_plain, r_plain = timed(plain, args.steps)
+    log(f"[batch] plain {t_plain * 1e3:.1f} ms")
+    t_batch, r_batch = timed(batched, args.steps, **tuned)
+    log(f"[batch] batched {t_batch * 1e3:.1f} ms")
+    t_graph, r_graph = timed(batched, args.steps, use_graph=True, **tuned)
+    log(f"[batch] batched+graph {t_graph * 1e3:.1f} ms")
+    t_default, _ = timed(batched, args.steps)
+
+    def same(a, b):
+        return all(a["n_rows"] == b["n_rows"] and all(torch.equal(a[k], b[k]) for k in ("ray", "key", "count"))
+                   for a, b in zip(a, b))
+
+    identical = same(r_plain, r_batch) and same(r_plain, r_graph)
+    best = min(t_batch, t_graph)
+    out = {
+        "metric": "rays/s, batched vs 256 plain launches",
+        "workload": "batch",
+        "value": round(total_rays / best, 1),
+        "unit": "rays/s",
+        "n_gpus": 1,
+        "steps": args.steps,
+        "higher_is_better": True,
+        "dtype": "f32",
+        "data": "synthetic",
+        "config": {"workload": "batch", "scenes": n, "points": total_points, "rays": total_rays,
+                   "max_reflections": 3, "point_scale": args.batch_point_scale, "ray_scale": args.batch_ray_scale},
+        "plain_rays_per_s": round(total_rays / t_plain, 1),
+        "batched_rays_per_s": round(total_rays / t_batch, 1),
+        "batched_graph_rays_per_s": round(total_rays / t_graph, 1),
+        "batched_default_params_rays_per_s": round(total_rays / t_default, 1),
+        "speedup_vs_plain": round(t_plain / best, 3),
+        "ms": {"plain": round(t_plain * 1e3, 2), "batched": round(t_batch * 1e3, 2),
+               "batched_graph": round(t_graph * 1e3, 2), "batched_default": round(t_default * 1e3, 2)},
+        "autotuned": tuned,
+        "identical_results": bool(identical),
+    }
+    print(json.dumps(out), flush=True)
+
+
+def bench_serve(args, pcrl, torch):
+    """Poisson stream of TX/RX queries on a 5M-point canyon with moving vehicles (100 ms frames)."""
+    import scenes
+    dev = torch.device("cuda", 0)
+    log("[serve] generating the moving canyon")
+    sc, mover = scenes.moving_canyon(n_points=args.serve_points)
+    ids = sc.extra["moving_idx"]
+    n_static = int(ids[0])
+    r_s = float(np.float32(sc.surfel_radius))
+    t_eps = float(np.float32(sc.t_eps))
+    base = pcrl.build_voxels(sc.xyz[:n_static], sc.normal[:n_static], sc.label[:n_static], sc.levels, r_s,
+                             t_eps=t_eps, device=dev)
+    base._inputs = None
+    labels_dyn = sc.label[ids]
+    frames = {}
+
+    def frame_data(f):
+        if f not in frames:
+            idx, xyz, nrm = mover(f)
+            frames[f] = (torch.from_numpy(idx.astype(np.uint32).view(np.int32)).to(dev), torch.from_numpy(xyz).to(dev),
+                         torch.from_numpy(nrm).to(dev), torch.from_numpy(labels_dyn.view(np.int32)).to(dev))
+        return frames[f]
+
+    stream = scenes.poisson_queries(seed=1, rate=args.serve_rate, duration=args.serve_seconds + args.serve_warmup,
+                                    scene=sc, K=3)
+    total_rays = sum(q["n_rays"] for q in stream)
+    log(f"[serve] {len(stream)} queries, {total_rays} rays over {args.serve_seconds + args.serve_warmup:.0f} s")
+    for f in range(int((args.serve_seconds + args.serve_warmup) / 0.1) + 2):
+        frame_data(f)
+    torch.cuda.synchronize()
+
+    def run_served():
+        srv = pcrl.Server(base, n_streams=4, max_batch=64, hbm_budget_bytes=64 << 30, kappa=1)
+        srv.update(*frame_data(0))
+        frame = 0
+        tickets = []
+        t0 = time.perf_counter()
+        for q in stream:
+            while True:
+                now = time.perf_counter() - t0
+                if now >= (frame + 1) * 0.1:
+                    frame += 1
+                    srv.update(*frame_data(frame))
+                    continue
+                if now >= q["t"]:
+                    break
+                time.sleep(min(q["t"] - now, (frame + 1) * 0.1 - now))
+            tickets.append((q, srv.submit(q["tx"], q["rx"], q["n_rays"], q["K"])))
+        lat = []
+        for q, t in tickets:
+            info = srv.poll(t, timeout=600.0)
+            if q["t"] >= args.serve_warmup:
+                lat.append(info["latency_ms"])
+        t_end = time.perf_counter() - t0
+        st = srv.stats()
+        srv.close()
+        return lat, st, t_end, frame
+
+    def run_plain():
+        frame = 0
+        base.update_points(*frame_data(0))
+        lat = []
+        t0 = time.perf_counter()
+        for q in stream:
+            now = time.perf_counter() - t0
+            if now < q["t"]:
+                time.sleep(q["t"] - now)
+            now = time.perf_counter() - t0
+            if now >= (frame + 1) * 0.1:
+                frame = int(now / 0.1)
+                base.update_points(*frame_data(frame))
+            L = pcrl.launch_rays(base, q["tx"], q["rx"], n_rays=q["n_rays"], max_reflections=q["K"])
+            pcrl.collect_paths(L, kappa=1)
+            L.release()
+            done = time.perf_counter() - t0
+            if q["t"] >= args.serve_warmup:
+                lat.append(1e3 * (done - q["t"]))
+        return lat, time.perf_counter() - t0
+
+    log("[serve] served run")
+    lat_s, st, t_s, frames_s = run_served()
+    log(f"[serve] served: {st}")
+    log("[serve] plain FIFO run")
+    lat_p, t_p = run_plain()
+    measured_rays = sum(q["n_rays"] for q in stream if q["t"] >= args.serve_warmup)
+
+    def pct(x, p):
+        return float(np.percentile(np.asarray(x), p)) if x else None
+
+    out = {
+        "metric": "p50/p99 query latency and rays/s, served vs plain per-query launches",
+        "workload": "serve",
+        "value": round(st["rays_per_s"], 1),
+        "unit": "rays/s",
+        "n_gpus": 1,
+        "higher_is_better": True,
+        "dtype": "f32",
+        "data": "synthetic",
+        "config": {"workload": "serve", "points": sc.n_points, "moving_points": int(len(ids)),
+                   "rate_qps": args.serve_rate, "seconds": args.serve_seconds, "warmup_s": args.serve_warmup,
+                   "queries": len(stream), "rays": total_rays, "max_reflections": 3, "frame_ms": 100},
+        "served": {"p50_ms": round(pct(lat_s, 50), 2), "p99_ms": round(pct(lat_s, 99), 2),
+                   "rays_per_s": round(st["rays_per_s"], 1), "wall_s": round(t_s, 2),
+                   "mean_batch": round(st["mean_batch"], 2), "rounds": st["rounds"], "frames": frames_s},
+        "plain": {"p50_ms": round(pct(lat_p, 50), 2), "p99_ms": round(pct(lat_p, 99), 2),
+                  "rays_per_s": round(total_rays / t_p, 1), "wall_s": round(t_p, 2)},
+        "measured_rays": measured_rays,
+    }
+    print(json.dumps(out), flush=True)
+
+
+def bench_copy(args, torch):
+    """Calibration for the HBM traffic counters: a plain device copy of known size."""
+    dev = torch.device("cuda", 0)
+    n = args.copy_mib * (1 << 20) // 4
+    x = torch.ones(n, dtype=torch.float32, device=dev)
+    y = torch.empty_like(x)
+    y.copy_(x)
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    for _ in range(args.steps):
+        y.copy_(x)
+    torch.cuda.synchronize()
+    dt = (time.perf_counter() - t0) / args.steps
+    nbytes = 4 * n
+    print(json.dumps({"workload": "copy", "bytes_read_per_copy": nbytes, "bytes_written_per_copy": nbytes,
+                      "copies": args.steps + 1, "ms_per_copy": round(dt * 1e3, 4),
+                      "achieved_GBps": round(2 * nbytes / dt / 1e9, 1)}), flush=True)
+
+
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
     ap.add_argument("--steps", type=int, default=10)
     ap.add_argument("--warmup", type=int, default=3)
-    ap.add_argument("--workload", default="furnished_room", choices=["furnished_room", "box_room", "street_canyon"])
+    ap.add_argument("--workload", default="furnished_room",
+                    choices=["furnished_room", "box_room", "street_canyon", "batch", "serve", "copy"])
+    ap.add_argument("--copy-mib", type=int, default=1024)
+    ap.add_argument("--batch-scenes", type=int, default=256)
+    ap.add_argument("--batch-point-scale", type=float, default=1.0)
+    ap.add_argument("--batch-ray-scale", type=float, default=1.0)
+    ap.add_argument("--serve-points", type=int, default=5_000_000)
+    ap.add_argument("--serve-rate", type=float, default=200.0)
+    ap.add_argument("--serve-seconds", type=float, default=30.0)
+    ap.add_argument("--serve-warmup", type=float, default=2.0)
     ap.add_argument("--kappa", type=int, default=100)
     ap.add_argument("--cpu-seconds", type=float, default=12.0)
     ap.add_argument("--no-cpu-baseline", action="store_true")
@@ -95,6 +333,12 @@ def main():
 
     dev = torch.device("cuda", 0)
     torch.cuda.set_device(dev)
+    if args.workload == "copy":
+        return bench_copy(args, torch)
+    if args.workload == "batch":
+        return bench_batch(args, pcrl, torch)
+    if args.workload == "serve":
+        return bench_serve(args, pcrl, torch)
     log(f"[bench] generating {args.workload}")
     s = make_workload(args.workload)
     K = s.max_reflections
@@ -205,7 +449,8 @@ def main():
     }
     if algo is not None:
         out["trace_stats"] = {k: algo[k] for k in ("segments", "dda_steps", "leaves_visited", "node_lookups",
-                                                   "surfel_tests", "hits", "records", "active")}
+                                                   "surfel_tests", "hits", "records", "active", "empty_leaf_steps",
+                                                   "uniform_leaf_visits")}
     print(json.dumps(out), flush=True)
 
 

@@ -166,6 +166,8 @@ typedef struct {
                                                       reads (4 B level-0, 8-12 B per brick word, 8 B per
                                                       leaf), 32 B per surfel tested, 36 B ray state read per
                                                       later segment, 52 B per reflection, 16 B per record */
+    int64_t empty_leaf_steps;                      /* DDA steps into empty leaves of occupied parents */
+    int64_t uniform_leaf_visits;                   /* leaf visits shared by every walking lane of the wave */
     /* PCRL_LAUNCH_TIMING only (else 0) */
     float   kernel_ms[PCRL_MAX_REFLECTIONS + 1];   /* trace kernel time per bounce */
     float   total_ms;                              /* first to last trace kernel */

@@ -60,7 +60,8 @@ class PcrlLaunchStats(C.Structure):
     _fields_ = [("rays", C.c_int64), ("segments", C.c_int64), ("active", C.c_int64 * (MAX_REFLECTIONS + 1)),
                 ("records", C.c_int64), ("record_capacity", C.c_int64), ("dda_steps", C.c_int64),
                 ("leaves_visited", C.c_int64), ("node_lookups", C.c_int64), ("surfel_tests", C.c_int64),
-                ("hits", C.c_int64), ("algo_bytes", C.c_int64), ("kernel_ms", C.c_float * (MAX_REFLECTIONS + 1)),
+                ("hits", C.c_int64), ("algo_bytes", C.c_int64), ("empty_leaf_steps", C.c_int64),
+                ("uniform_leaf_visits", C.c_int64), ("kernel_ms", C.c_float * (MAX_REFLECTIONS + 1)),
                 ("total_ms", C.c_float)]
 
 

@@ -104,7 +104,7 @@ __global__ __launch_bounds__(TILE_BLOCK) void k_batch_tiles(BatchCtl* c, int b) 
 
 template <bool FIRST, bool STATS>
 __global__ __launch_bounds__(TRACE_BLOCK) void k_trace_batch(BatchCtl* c, int b) {
-    stat_t cnt[ST_COUNT] = {0, 0, 0, 0, 0, 0, 0};
+    stat_t cnt[ST_COUNT] = {};
     const uint32_t n_tiles = c->n_tiles;
     const uint32_t n_q = c->n_q;
     const uint32_t tile = c->tile;

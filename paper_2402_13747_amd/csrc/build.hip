@@ -263,6 +263,46 @@ __global__ void k_brick_base(const uint64_t* mask, const uint32_t* first_child, 
     }
 }
 
+// Empty-space skip radius of every leaf cell of an occupied parent brick
+// (r^3 cells, r <= 16): R = 0 for an occupied leaf; otherwise the largest k
+// such that the cube of cells within Chebyshev distance k - 1 is empty and
+// inside the brick.  This is the per-voxel march distance of Section 2.2.4
+// (the longest per-axis distance to the closest voxel with content), limited
+// to the brick.  The L-infinity distance transform is separable: 1D distances
+// along x, then min over y' of max(|y - y'|, .), then the same along z.
+__global__ __launch_bounds__(BUILD_BLOCK) void k_brick_dist(const uint64_t* mask, int nw, int r, uint8_t* dist) {
+    extern __shared__ uint8_t sm[];
+    const int n3 = r * r * r;
+    uint8_t* A = sm;
+    uint8_t* B = sm + n3;
+    const size_t P = blockIdx.x;
+    for (int c = threadIdx.x; c < n3; c += BUILD_BLOCK)
+        A[c] = ((mask[P * nw + (c >> 6)] >> (c & 63)) & 1ull) ? 0 : 255;
+    __syncthreads();
+    for (int c = threadIdx.x; c < n3; c += BUILD_BLOCK) {
+        const int x = c % r, row = c - x;
+        int m = 255;
+        for (int xp = 0; xp < r; ++xp)
+            if (A[row + xp] == 0) m = min(m, abs(x - xp));
+        B[c] = (uint8_t)m;
+    }
+    __syncthreads();
+    for (int c = threadIdx.x; c < n3; c += BUILD_BLOCK) {
+        const int x = c % r, y = (c / r) % r, z = c / (r * r);
+        int m = 255;
+        for (int yp = 0; yp < r; ++yp) m = min(m, max(abs(y - yp), (int)B[x + r * (yp + r * z)]));
+        A[c] = (uint8_t)m;
+    }
+    __syncthreads();
+    for (int c = threadIdx.x; c < n3; c += BUILD_BLOCK) {
+        const int x = c % r, y = (c / r) % r, z = c / (r * r);
+        int m = 255;
+        for (int zp = 0; zp < r; ++zp) m = min(m, max(abs(z - zp), (int)A[x + r * (y + r * zp)]));
+        const int db = min(min(min(x, r - 1 - x), min(y, r - 1 - y)), min(z, r - 1 - z));
+        dist[P * n3 + c] = (uint8_t)min(m, db + 1);
+    }
+}
+
 __global__ void k_leaf_counts(uint2* leaf, int64_t n_leaves, int64_t m) {
     int64_t l = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
     if (l >= n_leaves) return;
@@ -488,6 +528,18 @@ static int build_hierarchy(const float* xyz, const float4* unit_nrm, const uint3
     v.leaf = leaf;
     hb.leaf_range = leaf;
     hb.leaf_key = lkey;
+    // empty-space skip radii inside the leaves' parent bricks
+    v.ldist = nullptr;
+    if (L >= 2 && v.ratio[L - 2] >= 3 && v.ratio[L - 2] <= 16 && host_nodes[L - 2] > 0) {
+        const int r = v.ratio[L - 2];
+        const size_t n3 = (size_t)r * r * r;
+        uint8_t* ld = nullptr;
+        if ((rc = B.alloc(&ld, (size_t)host_nodes[L - 2] * n3))) return rc;
+        hipLaunchKernelGGL(k_brick_dist, dim3(host_nodes[L - 2]), dim3(BUILD_BLOCK), 2 * n3, s, ho.mask[L - 2],
+                           v.nw[L - 2], r, ld);
+        v.ldist = ld;
+        hb.bytes += (int64_t)host_nodes[L - 2] * (int64_t)n3;
+    }
 
     // surfel streams in leaf order
     float4 *spos = nullptr, *snrm = nullptr;
@@ -612,6 +664,7 @@ static int overlay_impl(PcrlScene* S, const uint32_t* gid, const float* xyz, con
         v.base[l] = nullptr;
     }
     v.leaf = nullptr;
+    v.ldist = nullptr;
     v.spos = v.snrm = nullptr;
     HierBuild hb;
     if ((rc = build_hierarchy(xyz, unit_nrm, label, gid, n, s, v, ov->bufs, T, hb))) return fail(rc);

@@ -159,6 +159,7 @@ struct SceneView {
     const uint64_t* mask[PCRL_MAX_LEVELS - 1];  // child occupancy bricks of level i
     const uint32_t* base[PCRL_MAX_LEVELS - 1];  // child index of the first set bit of each word
     const uint2* leaf;               // per leaf: (first entry, entry count)
+    const uint8_t* ldist;            // null, or per leaf cell of each parent brick its empty-space skip radius
     const float4* spos;              // per entry: x, y, z, point id (bits)
     const float4* snrm;              // per entry: unit normal, label (bits)
 };
@@ -238,6 +239,7 @@ struct PcrlLaunch {
 // counters layout
 #define PCRL_CNT_REC(K) ((K) + 2)
 #define PCRL_NCOUNTERS(K) ((K) + 3)
+#define PCRL_NSTATS 16  // device statistics slots of a launch (PCRL_LAUNCH_STATS)
 
 // internal entry points of the launch translation unit (used by batching)
 namespace pcrl {

@@ -27,7 +27,7 @@ __global__ __launch_bounds__(TRACE_BLOCK) void k_trace(TraceArgs a, int b) {
     const uint32_t n_act = FIRST ? a.n_total : a.counters[b];
     const uint32_t wave = xcd_block() * (TRACE_BLOCK / 64) + (threadIdx.x >> 6);
     const uint32_t n_waves = gridDim.x * (TRACE_BLOCK / 64);
-    stat_t cnt[ST_COUNT] = {0, 0, 0, 0, 0, 0, 0};
+    stat_t cnt[ST_COUNT] = {};
     for (uint32_t base = wave * 64; base < n_act; base += n_waves * 64)
         trace_chunk<FIRST, STATS>(a, b, base, n_act, false, cnt);
     flush_stats<STATS>(cnt, a.stats);
@@ -176,7 +176,7 @@ int launch_prepare(const PcrlScene* scene, const float* tx, int32_t n_tx, const 
     if (K > 0) rc = B.alloc(&L->hist, (size_t)K * n_total);
     if (!rc) rc = B.alloc(&L->rec, (size_t)L->rec_cap);
     if (!rc) rc = B.alloc(&L->counters, PCRL_NCOUNTERS(K));
-    if (!rc && (p->flags & PCRL_LAUNCH_STATS)) rc = B.alloc(&L->stats, 8);
+    if (!rc && (p->flags & PCRL_LAUNCH_STATS)) rc = B.alloc(&L->stats, PCRL_NSTATS);
     if (!rc && K > 0) {
         if (!(rc = B.alloc(&oa, (size_t)n_total)) && !(rc = B.alloc(&da, (size_t)n_total)))
             rc = B.alloc(&ga, (size_t)n_total);
@@ -184,7 +184,7 @@ int launch_prepare(const PcrlScene* scene, const float* tx, int32_t n_tx, const 
             rc = B.alloc(&gb, (size_t)n_total);
     }
     if (!rc) rc = fill_u32(L->counters, 0u, PCRL_NCOUNTERS(K), s);
-    if (!rc && L->stats) rc = fill_u64((uint64_t*)L->stats, 0ull, 8, s);
+    if (!rc && L->stats) rc = fill_u64((uint64_t*)L->stats, 0ull, PCRL_NSTATS, s);
     if (!rc && p->hit_log_id) {
         const size_t n = (size_t)n_total * (K + 1);
         hipLaunchKernelGGL(k_fill_logs, dim3((unsigned)((n + 255) / 256)), dim3(256), 0, s, p->hit_log_id,
@@ -320,7 +320,7 @@ extern "C" int launch_stats(PcrlLaunch* L, PcrlLaunchStats* out) {
     std::memset(out, 0, sizeof *out);
     const int K = L->K;
     uint32_t cnt[PCRL_NCOUNTERS(PCRL_MAX_REFLECTIONS)];
-    unsigned long long st[8] = {0, 0, 0, 0, 0, 0, 0, 0};
+    unsigned long long st[PCRL_NSTATS] = {};
     PCRL_TRY_HIP(hipMemcpyAsync(cnt, L->counters, sizeof(uint32_t) * PCRL_NCOUNTERS(K), hipMemcpyDeviceToHost, L->stream));
     if (L->stats) PCRL_TRY_HIP(hipMemcpyAsync(st, L->stats, sizeof st, hipMemcpyDeviceToHost, L->stream));
     PCRL_TRY_HIP(hipStreamSynchronize(L->stream));
@@ -340,6 +340,8 @@ extern "C" int launch_stats(PcrlLaunch* L, PcrlLaunchStats* out) {
     out->surfel_tests = (int64_t)st[ST_TESTS];
     out->hits = (int64_t)st[ST_HITS];
     out->algo_bytes = (int64_t)st[ST_BYTES];
+    out->empty_leaf_steps = (int64_t)st[ST_EMPTY_LEAF];
+    out->uniform_leaf_visits = (int64_t)st[ST_UNIFORM];
     if (!L->events.empty()) {
         float total = 0.f;
         for (int b = 0; b <= K; ++b) {

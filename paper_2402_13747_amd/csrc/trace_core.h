@@ -17,8 +17,11 @@ constexpr uint32_t NO_HIT = 0xFFFFFFFFu;
 // brick mask word (+4 B base when the bit is set), 8 B per leaf range, 32 B
 // per surfel tested, 36 B of ray state read per segment after the first,
 // 36 B of ray state + 16 B of history per reflection, 16 B per record.
-enum StatSlot { ST_SEGMENTS = 0, ST_DDA, ST_LEAVES, ST_NODES, ST_TESTS, ST_HITS, ST_BYTES, ST_COUNT };
+enum StatSlot {
+    ST_SEGMENTS = 0, ST_DDA, ST_LEAVES, ST_NODES, ST_TESTS, ST_HITS, ST_BYTES, ST_EMPTY_LEAF, ST_UNIFORM, ST_COUNT
+};
 typedef unsigned long long stat_t;
+static_assert(ST_COUNT <= PCRL_NSTATS, "device statistics buffer too small");
 
 struct TraceArgs {
     SceneView v;
@@ -151,7 +154,8 @@ __device__ void trace_segment(const SceneView& v, const float o[3], const float 
     uint32_t cnode = 0;
     for (int it = 0; it < max_iter; ++it) {
         uint32_t node = 0;
-        int lvl;  // level of the empty cell containing c, or L for an occupied leaf
+        int skip = 1;  // > 1: an empty cube of 2 skip - 1 leaves centred on c
+        int lvl;       // level of the empty cell containing c, or L for an occupied leaf
         if (P < 0) {
             const int32_t n0 = v.map0[c[0] + v.dim0[0] * (c[1] + v.dim0[1] * c[2])];
             if (STATS) {
@@ -184,10 +188,23 @@ __device__ void trace_segment(const SceneView& v, const float o[3], const float 
                 if (w & bit) {
                     node = v.base[P][wi] + (uint32_t)__popcll(w & (bit - 1));
                     if (node < v.nn[L - 1]) lvl = L;
+                } else if (v.ldist) {
+                    // empty leaf: the whole cube of radius skip - 1 around it is empty
+                    skip = max(1, (int)v.ldist[(size_t)cnode * (size_t)(r * r * r) + loc]);
+                    if (STATS) cnt[ST_BYTES] += 1;
                 }
             }
         }
-        if (STATS) ++cnt[ST_DDA];
+        if (STATS) {
+            ++cnt[ST_DDA];
+            if (lvl == L - 1 && L > 1) ++cnt[ST_EMPTY_LEAF];
+            // leaf visits where every lane of the wave still walking is in the same leaf
+            const uint64_t m_leaf = __ballot(lvl == L);
+            const int first = m_leaf ? __ffsll((long long)m_leaf) - 1 : 0;
+            const uint32_t lead = __shfl(node, first, 64);
+            const uint64_t m_walk = __ballot(true);
+            if (lvl == L && __ballot(lvl == L && node == lead) == m_walk) ++cnt[ST_UNIFORM];
+        }
         int S = 1;
         if (lvl == L) {
             const uint2 r = v.leaf[node];
@@ -226,8 +243,13 @@ __device__ void trace_segment(const SceneView& v, const float o[3], const float 
         int axis = 0;
 #pragma unroll
         for (int a = 0; a < 3; ++a) {
-            lo[a] = (S == 1) ? c[a] : span_div(c[a], v.mspan[lvl]) * S;
-            hi[a] = lo[a] + S;
+            if (skip > 1) {
+                lo[a] = c[a] - (skip - 1);
+                hi[a] = c[a] + skip;
+            } else {
+                lo[a] = (S == 1) ? c[a] : span_div(c[a], v.mspan[lvl]) * S;
+                hi[a] = lo[a] + S;
+            }
             float ta = INFINITY;
             if (step[a] > 0)
                 ta = ((float)hi[a] * v.h + v.org[a] - o[a]) * inv[a];

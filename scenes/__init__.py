@@ -283,11 +283,28 @@ def _canyon_faces(extent, blds, n_labels):
     return faces
 
 
-def _ground(extent, blds, h):
+def _ground(extent, blds, h, lots=None):
+    """Ground grid minus building footprints.
+
+    With ``lots`` (one building per lot, inside its lot, in lot-major order)
+    each point is tested against its own lot's footprint only; the result is
+    the same as testing every footprint.
+    """
     p, n, l = face_grid((0, 0, 0), (extent[0], 0, 0), (0, extent[1], 0), (0, 0, 1), h, 0)
-    keep = np.ones(p.shape[0], bool)
-    for lo, hi in blds:
-        keep &= ~((p[:, 0] > lo[0]) & (p[:, 0] < hi[0]) & (p[:, 1] > lo[1]) & (p[:, 1] < hi[1]))
+    if lots is None:
+        keep = np.ones(p.shape[0], bool)
+        for lo, hi in blds:
+            keep &= ~((p[:, 0] > lo[0]) & (p[:, 0] < hi[0]) & (p[:, 1] > lo[1]) & (p[:, 1] < hi[1]))
+        return p[keep], n[keep], l[keep]
+    lx = extent[0] / lots[0]
+    ly = extent[1] / lots[1]
+    i = np.minimum((p[:, 0] / lx).astype(np.int64), lots[0] - 1)
+    j = np.minimum((p[:, 1] / ly).astype(np.int64), lots[1] - 1)
+    lo = np.array([b[0] for b in blds])
+    hi = np.array([b[1] for b in blds])
+    k = i * lots[1] + j
+    inside = (p[:, 0] > lo[k, 0]) & (p[:, 0] < hi[k, 0]) & (p[:, 1] > lo[k, 1]) & (p[:, 1] < hi[k, 1])
+    keep = ~inside
     return p[keep], n[keep], l[keep]
 
 
@@ -319,7 +336,7 @@ def street_canyon(n_points=20_000_000, seed=0, antenna_seed=1, n_tx=4, n_rx=64, 
         faces = _canyon_faces(extent, blds, n_labels)
         area = ground_area + sum(np.linalg.norm(np.cross(u, v)) for _, u, v, _, _ in faces)
         h = math.sqrt(area / max(n_points, 1))
-    g = _ground(extent, blds, h)
+    g = _ground(extent, blds, h, lots)
     b = _sample_faces(_canyon_faces(extent, blds, n_labels), h)
     xyz = np.concatenate([g[0], b[0]])
     nrm = np.concatenate([g[1], b[1]])
@@ -426,7 +443,7 @@ def moving_canyon(n_points=5_000_000, seed=0, moving_fraction=0.05, vehicle=(4.5
     area = ground_area + sum(np.linalg.norm(np.cross(u, v)) for _, u, v, _, _ in faces)
     static_n = int(n_points * (1.0 - moving_fraction))
     h = math.sqrt(area / static_n)
-    g = _ground(extent, blds, h)
+    g = _ground(extent, blds, h, lots)
     b = _sample_faces(faces, h)
     vx, vy, vz = vehicle
     vfaces = _box_faces((0, 0, 0), (vx, vy, vz), label=(49,) * 6, inward=False, bottom=False)

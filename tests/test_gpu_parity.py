@@ -75,6 +75,32 @@ def _reception_rich_sample(oracle, s, n_rays, n_rx, radius, n_random, planes=Non
     return np.array(sorted(pick), np.int64)
 
 
+def test_street_canyon_full_size_sampled(env):
+    """Street canyon at full size (20M points, 4 x 4M rays, K = 4, 64 RX, three levels); ~80 sampled rays of
+    the first TX (aimed at 8 RX and at their ground images, plus random ones) against the oracle."""
+    torch, pcrl, oracle = env
+    s = scenes.street_canyon()
+    n_rays, K = s.n_rays, s.max_reflections
+    d = oracle.fibonacci(n_rays).astype(np.float64)
+    alpha = oracle.ray_spacing(n_rays)
+    tx = s.tx[0].astype(np.float64)
+    pick = set()
+    for r in s.rx[:8].astype(np.float64):
+        for tgt in (r, r * np.array([1.0, 1.0, -1.0])):
+            u = (tgt - tx) / np.linalg.norm(tgt - tx)
+            pick.update(np.nonzero(d @ u > math.cos(1.0 * alpha))[0].tolist())
+    pick.update(np.random.default_rng(5).choice(n_rays, size=16, replace=False).tolist())
+    sel = np.array(sorted(pick), np.int64)
+    scene, launch, paths, rec, ids, orc = _run(env, s, n_rays, K, sel=sel)
+    rep = parity.compare(orc, ids, rec, s.xyz, s.normal, s.label, K)
+    print(rep.summary())
+    assert rep.ok(), (rep.mismatch[:5], rep.record_missing[:5], rep.record_extra[:5], rep.length_bad[:5])
+    assert rep.exact + rep.equivalent >= 0.95 * rep.segments
+    assert rep.records_checked >= 3        # most RX are hidden from this TX by buildings
+    st = launch.stats()
+    assert st["records"] <= st["record_capacity"] and st["rays"] == 4 * n_rays
+
+
 def test_directions_match_oracle(env):
     torch, pcrl, oracle = env
     for n in (1, 7, 10_000, 1_000_003):
