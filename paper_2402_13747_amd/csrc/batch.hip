@@ -127,7 +127,7 @@ __global__ __launch_bounds__(TRACE_BLOCK) void k_trace_batch(BatchCtl* c, int b)
         const uint32_t start = (t - c->tile_off[q]) * tile;
         const uint32_t end = min(start + tile, range);
         for (uint32_t base = start; base < end; base += 64) trace_chunk<FIRST, STATS>(a, b, base, range, ip, cnt);
-        if (STATS) flush_stats<STATS>(cnt, a.stats);
+        if (STATS) flush_stats<STATS>(cnt, a.stats ? a.stats + (size_t)b * PCRL_NSTATS : nullptr);
     }
 }
 

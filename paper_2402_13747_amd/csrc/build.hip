@@ -755,7 +755,12 @@ extern "C" int scene_leaf_table(const PcrlScene* scene, uint64_t* leaf_key, uint
 extern "C" int release_scene(PcrlScene* scene) {
     clear_error();
     if (!scene) return PCRL_OK;
+    // launches on any stream may still read the scene (their release does not
+    // wait for them), and the build stream may no longer exist: finish all
+    // device work, then free on the null stream
+    (void)hipDeviceSynchronize();
     scene->overlay.reset();
+    scene->bufs.stream = nullptr;
     scene->bufs.release();
     delete scene;
     return PCRL_OK;

@@ -200,7 +200,13 @@ struct Overlay {
     int64_t bytes = 0;
     uint32_t max_label = 0;
     int64_t epoch = 0;
-    ~Overlay() { bufs.release(); }
+    // The stream the overlay was built on may be gone by now (a server's
+    // update stream), so free on the null stream.  Nothing uses the overlay
+    // any more: every launch that held it synchronised before letting go.
+    ~Overlay() {
+        bufs.stream = nullptr;
+        bufs.release();
+    }
 };
 }  // namespace pcrl
 

@@ -388,9 +388,10 @@ extern "C" int serve_submit(PcrlServer* S, const float* tx, int32_t n_tx, const 
     r->t_submit = clk::now();
     std::lock_guard<std::mutex> lock(S->mu);
     if (r->bytes > S->prm.hbm_budget_bytes) {
+        const long long need = (long long)r->bytes;
         delete r;
-        set_error("serve_submit: the query needs ~%lld bytes, more than the whole budget %lld",
-                  (long long)estimate_bytes(*r), (long long)S->prm.hbm_budget_bytes);
+        set_error("serve_submit: the query needs ~%lld bytes, more than the whole budget %lld", need,
+                  (long long)S->prm.hbm_budget_bytes);
         return PCRL_EBUSY;
     }
     if (S->stop) {

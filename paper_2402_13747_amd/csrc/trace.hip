@@ -30,7 +30,7 @@ __global__ __launch_bounds__(TRACE_BLOCK) void k_trace(TraceArgs a, int b) {
     stat_t cnt[ST_COUNT] = {};
     for (uint32_t base = wave * 64; base < n_act; base += n_waves * 64)
         trace_chunk<FIRST, STATS>(a, b, base, n_act, false, cnt);
-    flush_stats<STATS>(cnt, a.stats);
+    flush_stats<STATS>(cnt, a.stats ? a.stats + (size_t)b * PCRL_NSTATS : nullptr);
 }
 
 __global__ void k_fib(uint32_t n, float* out) {
@@ -176,7 +176,7 @@ int launch_prepare(const PcrlScene* scene, const float* tx, int32_t n_tx, const 
     if (K > 0) rc = B.alloc(&L->hist, (size_t)K * n_total);
     if (!rc) rc = B.alloc(&L->rec, (size_t)L->rec_cap);
     if (!rc) rc = B.alloc(&L->counters, PCRL_NCOUNTERS(K));
-    if (!rc && (p->flags & PCRL_LAUNCH_STATS)) rc = B.alloc(&L->stats, PCRL_NSTATS);
+    if (!rc && (p->flags & PCRL_LAUNCH_STATS)) rc = B.alloc(&L->stats, (size_t)PCRL_NSTATS * (K + 1));
     if (!rc && K > 0) {
         if (!(rc = B.alloc(&oa, (size_t)n_total)) && !(rc = B.alloc(&da, (size_t)n_total)))
             rc = B.alloc(&ga, (size_t)n_total);
@@ -184,7 +184,7 @@ int launch_prepare(const PcrlScene* scene, const float* tx, int32_t n_tx, const 
             rc = B.alloc(&gb, (size_t)n_total);
     }
     if (!rc) rc = fill_u32(L->counters, 0u, PCRL_NCOUNTERS(K), s);
-    if (!rc && L->stats) rc = fill_u64((uint64_t*)L->stats, 0ull, PCRL_NSTATS, s);
+    if (!rc && L->stats) rc = fill_u64((uint64_t*)L->stats, 0ull, (int64_t)PCRL_NSTATS * (K + 1), s);
     if (!rc && p->hit_log_id) {
         const size_t n = (size_t)n_total * (K + 1);
         hipLaunchKernelGGL(k_fill_logs, dim3((unsigned)((n + 255) / 256)), dim3(256), 0, s, p->hit_log_id,
@@ -320,10 +320,17 @@ extern "C" int launch_stats(PcrlLaunch* L, PcrlLaunchStats* out) {
     std::memset(out, 0, sizeof *out);
     const int K = L->K;
     uint32_t cnt[PCRL_NCOUNTERS(PCRL_MAX_REFLECTIONS)];
+    unsigned long long stb[PCRL_MAX_REFLECTIONS + 1][PCRL_NSTATS] = {};  // per bounce
     unsigned long long st[PCRL_NSTATS] = {};
     PCRL_TRY_HIP(hipMemcpyAsync(cnt, L->counters, sizeof(uint32_t) * PCRL_NCOUNTERS(K), hipMemcpyDeviceToHost, L->stream));
-    if (L->stats) PCRL_TRY_HIP(hipMemcpyAsync(st, L->stats, sizeof st, hipMemcpyDeviceToHost, L->stream));
+    if (L->stats)
+        PCRL_TRY_HIP(hipMemcpyAsync(stb, L->stats, sizeof(unsigned long long) * PCRL_NSTATS * (K + 1),
+                                    hipMemcpyDeviceToHost, L->stream));
     PCRL_TRY_HIP(hipStreamSynchronize(L->stream));
+    for (int b = 0; b <= K; ++b) {
+        for (int k = 0; k < PCRL_NSTATS; ++k) st[k] += stb[b][k];
+        out->algo_bytes_bounce[b] = (int64_t)stb[b][ST_BYTES];
+    }
     out->rays = L->n_total;
     out->active[0] = L->n_total;
     int64_t seg = L->n_total;

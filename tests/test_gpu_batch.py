@@ -114,6 +114,7 @@ def test_batch_timing_and_stats(env, workload):
     st = [L.stats() for L in launches]
     assert all(s["kernel_ms"][0] > 0 for s in st)
     assert all(s["segments"] == sum(s["active"]) for s in st)
+    assert all(s["algo_bytes"] > 0 and sum(s["algo_bytes_bounce"]) == s["algo_bytes"] for s in st)
     for L, ref in zip(launches, solo):
         _same(_result(pcrl, L), ref)
 

@@ -223,6 +223,26 @@ def test_kappa_and_counts(env):
             assert lp == sorted(lp)
 
 
+def test_stats_per_bounce(env):
+    """The statistics pass reports the same paths as a plain launch and splits its counters by bounce."""
+    torch, pcrl, oracle = env
+    s = scenes.box_room()
+    scene = pcrl.build_voxels(s.xyz, s.normal, s.label, s.levels, _f32(s.surfel_radius), t_eps=_f32(parity.t_eps_of(s)))
+    plain = pcrl.launch_rays(scene, s.tx, s.rx, n_rays=s.n_rays, max_reflections=3)
+    launch = pcrl.launch_rays(scene, s.tx, s.rx, n_rays=s.n_rays, max_reflections=3, stats=True, timing=True)
+    st = launch.stats()
+    a = parity.device_paths(parity.to_numpy(pcrl.collect_paths(plain)))
+    b = parity.device_paths(parity.to_numpy(pcrl.collect_paths(launch)))
+    assert set(a) == set(b)
+    assert len(st["algo_bytes_bounce"]) == 4 and sum(st["algo_bytes_bounce"]) == st["algo_bytes"]
+    for k in range(4):
+        assert (st["algo_bytes_bounce"][k] > 0) == (st["active"][k] > 0)
+        assert st["kernel_ms"][k] > 0
+    # every segment reads at least the level-0 map cell it starts in
+    assert st["algo_bytes"] >= 4 * st["segments"]
+    assert st["hits"] <= st["segments"] and st["leaves_visited"] <= st["dda_steps"]
+
+
 def test_determinism_and_permutation(env):
     torch, pcrl, oracle = env
     s = scenes.random_scene(7, tilt_sigma=0.05, n_rays=4000)

@@ -99,7 +99,7 @@ def test_served_equals_alone(env, world):
         p = _paths(pcrl, L)
         p["points"] = p["points"].reshape(p["n_rows"], q["max_reflections"], 3)
         alone.append(p)
-    srv = pcrl.Server(base, n_streams=3, max_batch=5)
+    srv = pcrl.Server(base, n_streams=3, max_batch=5, kappa=1 << 30)
     tickets = [srv.submit(**q) for q in qs]
     for t in tickets:
         info = srv.poll(t, timeout=60.0)
@@ -114,7 +114,7 @@ def test_served_equals_alone(env, world):
 def test_serve_epochs(env, world):
     torch, pcrl = env
     sc, mover, base, n_static, r_s, t_eps = world
-    srv = pcrl.Server(base, n_streams=2, max_batch=3)
+    srv = pcrl.Server(base, n_streams=2, max_batch=3, kappa=1 << 30)
     rng = np.random.default_rng(1)
     for frame in (20, 21):
         idx, xyz, nrm = mover(frame)
