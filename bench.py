@@ -463,6 +463,7 @@ def main():
                 "traffic_unit": "HBM bytes per launch (rocprofv3 FETCH_SIZE + WRITE_SIZE, copy-calibrated)",
                 "kernel": "k_trace<false,false> (bounce kernel, one launch per bounce 1..K)",
                 "launches_per_step": len(bl), "algo_bytes_per_launch": int(launch_bytes),
+                "bounce_ms": [round(float(np.mean([m[k] for m in kern_b])), 4) for k in range(K + 1)],
                 "launch_ms": round(launch_ms, 4), "source_hash": trace_source_hash(),
                 "all_bounces": {"algo_bytes_per_step": int(bytes_per_step), "trace_ms_per_step": round(avg_ms, 4),
                                 "achieved_gbs": round(bytes_per_step / (avg_ms * 1e-3) / 1e9, 2),
@@ -500,7 +501,9 @@ def main():
     if algo is not None:
         out["trace_stats"] = {k: algo[k] for k in ("segments", "dda_steps", "leaves_visited", "node_lookups",
                                                    "surfel_tests", "hits", "records", "active", "empty_leaf_steps",
-                                                   "uniform_leaf_visits")}
+                                                   "uniform_leaf_visits", "wave_dda_iters", "wave_test_iters")}
+        out["trace_stats"]["dda_lane_efficiency"] = round(algo["dda_steps"] / max(64 * algo["wave_dda_iters"], 1), 4)
+        out["trace_stats"]["test_lane_efficiency"] = round(algo["surfel_tests"] / max(64 * algo["wave_test_iters"], 1), 4)
     print(json.dumps(out), flush=True)
 
 

@@ -168,6 +168,8 @@ typedef struct {
                                                       later segment, 52 B per reflection, 16 B per record */
     int64_t empty_leaf_steps;                      /* DDA steps into empty leaves of occupied parents */
     int64_t uniform_leaf_visits;                   /* leaf visits shared by every walking lane of the wave */
+    int64_t wave_dda_iters;                        /* DDA loop iterations per wave, summed over waves */
+    int64_t wave_test_iters;                       /* surfel-test loop iterations per wave, summed over waves */
     int64_t algo_bytes_bounce[PCRL_MAX_REFLECTIONS + 1];  /* algo_bytes of each bounce kernel */
     /* PCRL_LAUNCH_TIMING only (else 0) */
     float   kernel_ms[PCRL_MAX_REFLECTIONS + 1];   /* trace kernel time per bounce */

@@ -61,7 +61,8 @@ class PcrlLaunchStats(C.Structure):
                 ("records", C.c_int64), ("record_capacity", C.c_int64), ("dda_steps", C.c_int64),
                 ("leaves_visited", C.c_int64), ("node_lookups", C.c_int64), ("surfel_tests", C.c_int64),
                 ("hits", C.c_int64), ("algo_bytes", C.c_int64), ("empty_leaf_steps", C.c_int64),
-                ("uniform_leaf_visits", C.c_int64), ("algo_bytes_bounce", C.c_int64 * (MAX_REFLECTIONS + 1)),
+                ("uniform_leaf_visits", C.c_int64), ("wave_dda_iters", C.c_int64), ("wave_test_iters", C.c_int64),
+                ("algo_bytes_bounce", C.c_int64 * (MAX_REFLECTIONS + 1)),
                 ("kernel_ms", C.c_float * (MAX_REFLECTIONS + 1)),
                 ("total_ms", C.c_float)]
 

@@ -102,8 +102,11 @@ __global__ __launch_bounds__(TILE_BLOCK) void k_batch_tiles(BatchCtl* c, int b) 
     }
 }
 
-template <bool FIRST, bool STATS>
+// One persistent kernel per group of queries with the same number of voxel
+// levels NL and overlay presence OV (the specialisations of the bounce body).
+template <bool FIRST, bool STATS, int NL, bool OV>
 __global__ __launch_bounds__(TRACE_BLOCK) void k_trace_batch(BatchCtl* c, int b) {
+    __shared__ LeafTestLds lds[TRACE_BLOCK / 64];
     stat_t cnt[ST_COUNT] = {};
     const uint32_t n_tiles = c->n_tiles;
     const uint32_t n_q = c->n_q;
@@ -126,7 +129,8 @@ __global__ __launch_bounds__(TRACE_BLOCK) void k_trace_batch(BatchCtl* c, int b)
         const bool ip = c->in_place[q] != 0u;
         const uint32_t start = (t - c->tile_off[q]) * tile;
         const uint32_t end = min(start + tile, range);
-        for (uint32_t base = start; base < end; base += 64) trace_chunk<FIRST, STATS>(a, b, base, range, ip, cnt);
+        for (uint32_t base = start; base < end; base += 64)
+            trace_chunk<FIRST, STATS, NL, OV>(a, lds[threadIdx.x >> 6], b, base, range, ip, cnt);
         if (STATS) flush_stats<STATS>(cnt, a.stats ? a.stats + (size_t)b * PCRL_NSTATS : nullptr);
     }
 }
@@ -146,43 +150,78 @@ struct BatchShared {
     }
 };
 
+// Queries of one kernel specialisation, contiguous in the query table.
+struct BatchGroup {
+    int nl;
+    bool ov;
+};
+
+template <bool FIRST, bool STATS, int NL>
+static void launch_group_nl(bool ov, BatchCtl* ctl, int b, unsigned grid, hipStream_t s) {
+    if (ov) hipLaunchKernelGGL((k_trace_batch<FIRST, STATS, NL, true>), dim3(grid), dim3(TRACE_BLOCK), 0, s, ctl, b);
+    else hipLaunchKernelGGL((k_trace_batch<FIRST, STATS, NL, false>), dim3(grid), dim3(TRACE_BLOCK), 0, s, ctl, b);
+}
+
+template <bool FIRST, bool STATS>
+static void launch_group(const BatchGroup& g, BatchCtl* ctl, int b, unsigned grid, hipStream_t s) {
+    static_assert(PCRL_MAX_LEVELS == 4, "one kernel specialisation per level count");
+    switch (g.nl) {
+    case 1: launch_group_nl<FIRST, STATS, 1>(g.ov, ctl, b, grid, s); break;
+    case 2: launch_group_nl<FIRST, STATS, 2>(g.ov, ctl, b, grid, s); break;
+    case 3: launch_group_nl<FIRST, STATS, 3>(g.ov, ctl, b, grid, s); break;
+    default: launch_group_nl<FIRST, STATS, 4>(g.ov, ctl, b, grid, s); break;
+    }
+}
+
 // A captured bounce loop: replayable for any batch with the same maximum K,
-// stream and launch shape; kernels read everything from `ctl`.
+// groups, stream and launch shape; kernels read everything from the groups'
+// control blocks.
 struct GraphEntry {
     hipGraphExec_t exec = nullptr;
-    BatchCtl* ctl = nullptr;
+    std::vector<BatchCtl*> ctl;
 };
 
 static std::mutex g_graph_mu;
 static std::map<std::string, GraphEntry> g_graphs;
 
 template <bool STATS>
-static void enqueue_bounces(BatchCtl* ctl, int kmax, unsigned grid, hipStream_t s, const std::vector<hipEvent_t>* ev) {
+static void enqueue_bounces(BatchCtl* const* ctl, const std::vector<BatchGroup>& groups, int kmax, unsigned grid,
+                            hipStream_t s, const std::vector<hipEvent_t>* ev) {
     for (int b = 0; b <= kmax; ++b) {
         if (ev) (void)hipEventRecord((*ev)[2 * b], s);
-        hipLaunchKernelGGL(k_batch_tiles, dim3(1), dim3(TILE_BLOCK), 0, s, ctl, b);
-        if (b == 0)
-            hipLaunchKernelGGL((k_trace_batch<true, STATS>), dim3(grid), dim3(TRACE_BLOCK), 0, s, ctl, b);
-        else
-            hipLaunchKernelGGL((k_trace_batch<false, STATS>), dim3(grid), dim3(TRACE_BLOCK), 0, s, ctl, b);
+        for (size_t g = 0; g < groups.size(); ++g) {
+            hipLaunchKernelGGL(k_batch_tiles, dim3(1), dim3(TILE_BLOCK), 0, s, ctl[g], b);
+            if (b == 0) launch_group<true, STATS>(groups[g], ctl[g], b, grid, s);
+            else launch_group<false, STATS>(groups[g], ctl[g], b, grid, s);
+        }
         if (ev) (void)hipEventRecord((*ev)[2 * b + 1], s);
     }
 }
 
-static int run_graph(const BatchCtl& host_ctl, int kmax, unsigned grid, bool stats, hipStream_t s) {
+static int run_graph(const std::vector<BatchCtl>& host_ctl, const std::vector<BatchGroup>& groups, int kmax,
+                     unsigned grid, bool stats, hipStream_t s) {
     int dev = 0;
     (void)hipGetDevice(&dev);
-    char key[128];
-    snprintf(key, sizeof key, "%d/%p/%d/%u/%d", dev, (void*)s, kmax, grid, stats ? 1 : 0);
+    std::string key;
+    {
+        char head[96];
+        snprintf(head, sizeof head, "%d/%p/%d/%u/%d", dev, (void*)s, kmax, grid, stats ? 1 : 0);
+        key = head;
+        for (const auto& g : groups) key += "/" + std::to_string(g.nl) + (g.ov ? "o" : "b");
+    }
     std::lock_guard<std::mutex> lock(g_graph_mu);
     GraphEntry& e = g_graphs[key];
     if (!e.exec) {
-        // the control block outlives the process's batches (one per graph)
-        if (hipMalloc((void**)&e.ctl, sizeof(BatchCtl)) != hipSuccess) {
-            g_graphs.erase(key);
-            set_error("launch_batch: control block allocation failed");
-            return PCRL_ENOMEM;
-        }
+        // the control blocks outlive the process's batches (one set per graph)
+        e.ctl.assign(groups.size(), nullptr);
+        for (auto& c : e.ctl)
+            if (hipMalloc((void**)&c, sizeof(BatchCtl)) != hipSuccess) {
+                for (auto& x : e.ctl)
+                    if (x) (void)hipFree(x);
+                g_graphs.erase(key);
+                set_error("launch_batch: control block allocation failed");
+                return PCRL_ENOMEM;
+            }
         // capture on a private stream (the caller's may be the legacy null
         // stream, which cannot be captured); the graph is launched on `s`
         hipStream_t cap = nullptr;
@@ -190,8 +229,8 @@ static int run_graph(const BatchCtl& host_ctl, int kmax, unsigned grid, bool sta
         hipGraph_t g = nullptr;
         hipError_t ce = hipStreamBeginCapture(cap, hipStreamCaptureModeThreadLocal);
         if (ce == hipSuccess) {
-            if (stats) enqueue_bounces<true>(e.ctl, kmax, grid, cap, nullptr);
-            else enqueue_bounces<false>(e.ctl, kmax, grid, cap, nullptr);
+            if (stats) enqueue_bounces<true>(e.ctl.data(), groups, kmax, grid, cap, nullptr);
+            else enqueue_bounces<false>(e.ctl.data(), groups, kmax, grid, cap, nullptr);
             ce = hipStreamEndCapture(cap, &g);
         }
         (void)hipStreamDestroy(cap);
@@ -207,7 +246,8 @@ static int run_graph(const BatchCtl& host_ctl, int kmax, unsigned grid, bool sta
             return PCRL_EHIP;
         }
     }
-    PCRL_TRY_HIP(hipMemcpyAsync(e.ctl, &host_ctl, sizeof host_ctl, hipMemcpyHostToDevice, s));
+    for (size_t g = 0; g < groups.size(); ++g)
+        PCRL_TRY_HIP(hipMemcpyAsync(e.ctl[g], &host_ctl[g], sizeof(BatchCtl), hipMemcpyHostToDevice, s));
     PCRL_TRY_HIP(hipGraphLaunch(e.exec, s));
     return PCRL_OK;
 }
@@ -235,30 +275,56 @@ static int batch_impl(const PcrlQuery* q, int32_t n_q, const PcrlBatchParams* bp
             set_error("%s", msg);
         }
     }
+    // query table ordered by kernel specialisation (levels, overlay); one group per run
+    std::vector<BatchGroup> groups;
+    std::vector<uint32_t> g_first, g_count;
+    if (!rc) {
+        std::vector<int> order((size_t)n_q);
+        for (int i = 0; i < n_q; ++i) order[(size_t)i] = i;
+        auto cls = [&](int i) { return args[(size_t)i].v.nlev * 2 + (args[(size_t)i].has_ov ? 1 : 0); };
+        std::stable_sort(order.begin(), order.end(), [&](int x, int y) { return cls(x) < cls(y); });
+        std::vector<TraceArgs> sorted((size_t)n_q);
+        for (int k = 0; k < n_q; ++k) {
+            const TraceArgs& a = args[(size_t)order[(size_t)k]];
+            sorted[(size_t)k] = a;
+            if (k == 0 || cls(order[(size_t)k]) != cls(order[(size_t)k - 1])) {
+                groups.push_back(BatchGroup{a.v.nlev, a.has_ov != 0});
+                g_first.push_back((uint32_t)k);
+                g_count.push_back(0);
+            }
+            ++g_count.back();
+        }
+        args.swap(sorted);
+    }
+    const size_t n_g = groups.size();
     TraceArgs* qs = nullptr;
     uint32_t *tile_off = nullptr, *range = nullptr, *inpl = nullptr, *prev = nullptr;
     BatchCtl* ctl = nullptr;
     if (!rc) rc = shared->bufs.alloc(&qs, (size_t)n_q);
-    if (!rc) rc = shared->bufs.alloc(&tile_off, (size_t)n_q + 1);
+    if (!rc) rc = shared->bufs.alloc(&tile_off, (size_t)n_q + n_g);
     if (!rc) rc = shared->bufs.alloc(&range, (size_t)n_q);
     if (!rc) rc = shared->bufs.alloc(&inpl, (size_t)n_q);
     if (!rc) rc = shared->bufs.alloc(&prev, (size_t)n_q);
-    if (!rc) rc = shared->bufs.alloc(&ctl, 1);
+    if (!rc) rc = shared->bufs.alloc(&ctl, n_g);
     if (!rc) rc = fill_u32(inpl, 0u, n_q, s);
     if (!rc) rc = fill_u32(prev, 0u, n_q, s);
     if (!rc && hipMemcpyAsync(qs, args.data(), sizeof(TraceArgs) * (size_t)n_q, hipMemcpyHostToDevice, s) != hipSuccess) {
         set_error("launch_batch: query table upload failed");
         rc = PCRL_EHIP;
     }
-    BatchCtl hc{};
-    hc.qs = qs;
-    hc.n_q = (uint32_t)n_q;
-    hc.tile = (uint32_t)std::max(64, (bp->tile_rays / 64) * 64);
-    hc.theta = bp->compact_threshold;
-    hc.tile_off = tile_off;
-    hc.range = range;
-    hc.in_place = inpl;
-    hc.prev_live = prev;
+    std::vector<BatchCtl> hc(n_g);
+    for (size_t g = 0; g < n_g; ++g) {
+        const uint32_t f = g_first[g];
+        BatchCtl& c = hc[g];
+        c.qs = qs + f;
+        c.n_q = g_count[g];
+        c.tile = (uint32_t)std::max(64, (bp->tile_rays / 64) * 64);
+        c.theta = bp->compact_threshold;
+        c.tile_off = tile_off + f + g;  // n_q + 1 entries per group
+        c.range = range + f;
+        c.in_place = inpl + f;
+        c.prev_live = prev + f;
+    }
     const int wpc = bp->waves_per_cu > 0 ? bp->waves_per_cu : 16;
     const unsigned grid = (unsigned)std::max(1, device_cus() * wpc / (TRACE_BLOCK / 64));
     if (!rc && timing) {
@@ -269,15 +335,17 @@ static int batch_impl(const PcrlQuery* q, int32_t n_q, const PcrlBatchParams* bp
     }
     if (!rc) {
         if (bp->use_graph && !timing) {
-            rc = run_graph(hc, kmax, grid, stats, s);
+            rc = run_graph(hc, groups, kmax, grid, stats, s);
         } else {
-            if (hipMemcpyAsync(ctl, &hc, sizeof hc, hipMemcpyHostToDevice, s) != hipSuccess) {
+            if (hipMemcpyAsync(ctl, hc.data(), sizeof(BatchCtl) * n_g, hipMemcpyHostToDevice, s) != hipSuccess) {
                 set_error("launch_batch: control block upload failed");
                 rc = PCRL_EHIP;
             } else {
+                std::vector<BatchCtl*> dctl(n_g);
+                for (size_t g = 0; g < n_g; ++g) dctl[g] = ctl + g;
                 const std::vector<hipEvent_t>* ev = timing ? &shared->events : nullptr;
-                if (stats) enqueue_bounces<true>(ctl, kmax, grid, s, ev);
-                else enqueue_bounces<false>(ctl, kmax, grid, s, ev);
+                if (stats) enqueue_bounces<true>(dctl.data(), groups, kmax, grid, s, ev);
+                else enqueue_bounces<false>(dctl.data(), groups, kmax, grid, s, ev);
                 if (hipGetLastError() != hipSuccess) {
                     set_error("launch_batch: kernel launch failed");
                     rc = PCRL_EHIP;

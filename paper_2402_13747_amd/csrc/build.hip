@@ -650,8 +650,10 @@ static int overlay_impl(PcrlScene* S, const uint32_t* gid, const float* xyz, con
     int rc;
     if ((rc = ingest(xyz, nrm, label, n, s, T, &unit_nrm, io, "update_points"))) return fail(rc);
     const SceneView& bv = S->view;
+    // every dynamic disk, dilated as in disk_leaf_box, must lie inside the base grid (no leaf clamped)
     for (int a = 0; a < 3; ++a) {
-        if (n > 0 && (io.lo[a] < bv.org[a] + bv.r_s + bv.h || io.hi[a] > bv.hi[a] - bv.r_s - bv.h)) {
+        const float m = bv.r_s + 2.f * bv.pad;
+        if (n > 0 && (io.lo[a] - m <= bv.org[a] || io.hi[a] + m >= bv.hi[a])) {
             set_error("update_points: dynamic points leave the scene grid along axis %d ([%g, %g] vs grid [%g, %g])", a,
                       io.lo[a], io.hi[a], bv.org[a], bv.hi[a]);
             return fail(PCRL_EINVAL);

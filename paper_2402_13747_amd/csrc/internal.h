@@ -236,7 +236,7 @@ struct PcrlLaunch {
     float4* hist = nullptr;         // [K][n_total]: interaction point, label (bits)
     uint4* rec = nullptr;           // [rec_cap]: ray, rx | b << 16, len_poly, len_unf
     uint32_t* counters = nullptr;   // [0..K+1] active rays per bounce, [K+2] records
-    unsigned long long* stats = nullptr;  // [8] device counters (PCRL_LAUNCH_STATS)
+    unsigned long long* stats = nullptr;  // [K+1][PCRL_NSTATS] device counters (PCRL_LAUNCH_STATS)
     std::vector<hipEvent_t> events; // 2 per bounce (PCRL_LAUNCH_TIMING)
     bool owns_events = false;       // false: events belong to a batch (shared)
     std::shared_ptr<void> shared;   // batch-level state kept alive by every query of a batch

@@ -22,15 +22,38 @@
 
 namespace pcrl {
 
-template <bool FIRST, bool STATS>
+// Specialised on the number of voxel levels NL and on the presence of an
+// overlay OV, so every level index in the traversal is a compile-time constant.
+// Each wave traces 64 consecutive slots in lockstep (neighbouring slots hold
+// coherent rays: their lookups share cache lines), grid-stride over the
+// active slots; with an overlay, the base hierarchy and then the overlay.
+template <bool FIRST, bool STATS, int NL, bool OV>
 __global__ __launch_bounds__(TRACE_BLOCK) void k_trace(TraceArgs a, int b) {
     const uint32_t n_act = FIRST ? a.n_total : a.counters[b];
     const uint32_t wave = xcd_block() * (TRACE_BLOCK / 64) + (threadIdx.x >> 6);
     const uint32_t n_waves = gridDim.x * (TRACE_BLOCK / 64);
+    __shared__ LeafTestLds lds[TRACE_BLOCK / 64];
     stat_t cnt[ST_COUNT] = {};
     for (uint32_t base = wave * 64; base < n_act; base += n_waves * 64)
-        trace_chunk<FIRST, STATS>(a, b, base, n_act, false, cnt);
+        trace_chunk<FIRST, STATS, NL, OV>(a, lds[threadIdx.x >> 6], b, base, n_act, false, cnt);
     flush_stats<STATS>(cnt, a.stats ? a.stats + (size_t)b * PCRL_NSTATS : nullptr);
+}
+
+// Fibonacci-lattice direction j of n (FP64, rounded to FP32).
+__device__ __forceinline__ void fib_dir(uint32_t j, uint32_t n, float& x, float& y, float& z) {
+#pragma clang fp contract(off)
+    const double g = (3.0 - sqrt(5.0)) / 2.0;
+    const double two_pi = 6.283185307179586476925286766559;
+    const double zz = 1.0 - (double)(2ull * j + 1ull) / (double)n;
+    const double r = sqrt(fmax(0.0, 1.0 - zz * zz));
+    const double jg = (double)j * g;
+    const double f = jg - floor(jg);
+    const double phi = two_pi * f;
+    double s, c;
+    sincos(phi, &s, &c);
+    x = (float)(r * c);
+    y = (float)(r * s);
+    z = (float)zz;
 }
 
 __global__ void k_fib(uint32_t n, float* out) {
@@ -57,14 +80,7 @@ __device__ __forceinline__ uint32_t spread_bits16(uint32_t x) {
 __global__ void k_dir_keys(const float* dirs, uint32_t n, uint32_t* keys, uint32_t* idx) {
     const uint32_t j = blockIdx.x * blockDim.x + threadIdx.x;
     if (j >= n) return;
-    float x, y, z;
-    if (dirs) {
-        x = dirs[3 * (size_t)j];
-        y = dirs[3 * (size_t)j + 1];
-        z = dirs[3 * (size_t)j + 2];
-    } else {
-        fib_dir(j, n, x, y, z);
-    }
+    const float x = dirs[3 * (size_t)j], y = dirs[3 * (size_t)j + 1], z = dirs[3 * (size_t)j + 2];
     const float s = fabsf(x) + fabsf(y) + fabsf(z);
     float u = s > 0.f ? x / s : 0.f, w = s > 0.f ? y / s : 0.f;
     if (z < 0.f) {
@@ -75,7 +91,8 @@ __global__ void k_dir_keys(const float* dirs, uint32_t n, uint32_t* keys, uint32
     }
     const uint32_t qu = (uint32_t)fminf(fmaxf((u * 0.5f + 0.5f) * 65535.f, 0.f), 65535.f);
     const uint32_t qw = (uint32_t)fminf(fmaxf((w * 0.5f + 0.5f) * 65535.f, 0.f), 65535.f);
-    keys[j] = spread_bits16(qu) | (spread_bits16(qw) << 1);
+    // 256 x 256 cells of the octahedral map: a 16-bit key, two radix passes
+    keys[j] = spread_bits16(qu >> 8) | (spread_bits16(qw >> 8) << 1);
     idx[j] = j;
 }
 
@@ -103,9 +120,21 @@ __global__ void k_unpack_records(const uint4* rec, const uint32_t* count, uint32
 // host side
 // ---------------------------------------------------------------------------
 
+template <bool FIRST, bool STATS, int NL>
+static void launch_trace_nl(const TraceArgs& a, int b, unsigned grid, hipStream_t s) {
+    if (a.has_ov) hipLaunchKernelGGL((k_trace<FIRST, STATS, NL, true>), dim3(grid), dim3(TRACE_BLOCK), 0, s, a, b);
+    else hipLaunchKernelGGL((k_trace<FIRST, STATS, NL, false>), dim3(grid), dim3(TRACE_BLOCK), 0, s, a, b);
+}
+
 template <bool FIRST, bool STATS>
 static void launch_trace(const TraceArgs& a, int b, unsigned grid, hipStream_t s) {
-    hipLaunchKernelGGL((k_trace<FIRST, STATS>), dim3(grid), dim3(TRACE_BLOCK), 0, s, a, b);
+    static_assert(PCRL_MAX_LEVELS == 4, "one kernel specialisation per level count");
+    switch (a.v.nlev) {
+    case 1: launch_trace_nl<FIRST, STATS, 1>(a, b, grid, s); break;
+    case 2: launch_trace_nl<FIRST, STATS, 2>(a, b, grid, s); break;
+    case 3: launch_trace_nl<FIRST, STATS, 3>(a, b, grid, s); break;
+    default: launch_trace_nl<FIRST, STATS, 4>(a, b, grid, s); break;
+    }
 }
 
 void destroy_launch(PcrlLaunch* L) {
@@ -191,12 +220,23 @@ int launch_prepare(const PcrlScene* scene, const float* tx, int32_t n_tx, const 
                            p->hit_log_t, n);
         if (hipGetLastError() != hipSuccess) rc = PCRL_EHIP;
     }
+    // the Fibonacci lattice is materialised once per launch (the trace kernels only read directions)
+    const float* dirs = p->directions;
+    if (!rc && !dirs) {
+        const uint32_t nr = (uint32_t)L->n_rays;
+        float* fd = nullptr;
+        if (!(rc = B.alloc(&fd, (size_t)3 * nr))) {
+            hipLaunchKernelGGL(k_fib, dim3((nr + 255) / 256), dim3(256), 0, s, nr, fd);
+            if (hipGetLastError() != hipSuccess) rc = PCRL_EHIP;
+        }
+        dirs = fd;
+    }
     if (!rc && (p->flags & PCRL_LAUNCH_COHERENT)) {
         const uint32_t nr = (uint32_t)L->n_rays;
         uint32_t* keys = nullptr;
         if (!(rc = B.alloc(&keys, nr)) && !(rc = B.alloc(&perm, nr))) {
-            hipLaunchKernelGGL(k_dir_keys, dim3((nr + 255) / 256), dim3(256), 0, s, p->directions, nr, keys, perm);
-            rc = hipGetLastError() == hipSuccess ? radix_sort_u32(keys, perm, nr, 32, s) : PCRL_EHIP;
+            hipLaunchKernelGGL(k_dir_keys, dim3((nr + 255) / 256), dim3(256), 0, s, dirs, nr, keys, perm);
+            rc = hipGetLastError() == hipSuccess ? radix_sort_u32(keys, perm, nr, 16, s) : PCRL_EHIP;
         }
     }
     if (!rc && timing_events && (p->flags & PCRL_LAUNCH_TIMING)) {
@@ -227,7 +267,7 @@ int launch_prepare(const PcrlScene* scene, const float* tx, int32_t n_tx, const 
     }
     a.tx = tx;
     a.rx = rx;
-    a.dirs = p->directions;
+    a.dirs = dirs;
     a.perm = perm;
     a.n_rx = n_rx;
     a.K = K;
@@ -349,6 +389,8 @@ extern "C" int launch_stats(PcrlLaunch* L, PcrlLaunchStats* out) {
     out->algo_bytes = (int64_t)st[ST_BYTES];
     out->empty_leaf_steps = (int64_t)st[ST_EMPTY_LEAF];
     out->uniform_leaf_visits = (int64_t)st[ST_UNIFORM];
+    out->wave_dda_iters = (int64_t)st[ST_WAVE_DDA];
+    out->wave_test_iters = (int64_t)st[ST_WAVE_TESTS];
     if (!L->events.empty()) {
         float total = 0.f;
         for (int b = 0; b <= K; ++b) {

@@ -18,7 +18,8 @@ constexpr uint32_t NO_HIT = 0xFFFFFFFFu;
 // per surfel tested, 36 B of ray state read per segment after the first,
 // 36 B of ray state + 16 B of history per reflection, 16 B per record.
 enum StatSlot {
-    ST_SEGMENTS = 0, ST_DDA, ST_LEAVES, ST_NODES, ST_TESTS, ST_HITS, ST_BYTES, ST_EMPTY_LEAF, ST_UNIFORM, ST_COUNT
+    ST_SEGMENTS = 0, ST_DDA, ST_LEAVES, ST_NODES, ST_TESTS, ST_HITS, ST_BYTES, ST_EMPTY_LEAF, ST_UNIFORM,
+    ST_WAVE_DDA, ST_WAVE_TESTS, ST_COUNT
 };
 typedef unsigned long long stat_t;
 static_assert(ST_COUNT <= PCRL_NSTATS, "device statistics buffer too small");
@@ -29,7 +30,7 @@ struct TraceArgs {
     int32_t has_ov;
     const float* tx;
     const float* rx;
-    const float* dirs;      // null: Fibonacci lattice
+    const float* dirs;      // [n_rays][3] launch directions (the caller's, or the materialised Fibonacci lattice)
     const uint32_t* perm;   // null, or bounce-0 order of the directions
     int32_t n_rx;
     int32_t K;
@@ -55,28 +56,32 @@ struct Hit {
     float nx, ny, nz;
 };
 
-// Fibonacci-lattice direction j of n (FP64, rounded to FP32).
-__device__ __forceinline__ void fib_dir(uint32_t j, uint32_t n, float& x, float& y, float& z) {
-#pragma clang fp contract(off)
-    const double g = (3.0 - sqrt(5.0)) / 2.0;
-    const double two_pi = 6.283185307179586476925286766559;
-    const double zz = 1.0 - (double)(2ull * j + 1ull) / (double)n;
-    const double r = sqrt(fmax(0.0, 1.0 - zz * zz));
-    const double jg = (double)j * g;
-    const double f = jg - floor(jg);
-    const double phi = two_pi * f;
-    double s, c;
-    sincos(phi, &s, &c);
-    x = (float)(r * c);
-    y = (float)(r * s);
-    z = (float)zz;
+// Level-indexed constants for a per-lane level index, unrolled over the NL
+// levels of the kernel's specialisation (no dynamic indexing of kernel
+// arguments).
+template <int NL>
+__device__ __forceinline__ int span_at(const SceneView& v, int lvl) {
+    int s = v.span[0];
+#pragma unroll
+    for (int i = 1; i < NL; ++i)
+        if (lvl == i) s = v.span[i];
+    return s;
 }
 
-// Descend from level 0 to level `to` (< nlev) for leaf cell c.  Returns the
-// level at which the path is empty, or to + 1 when the level-`to` node exists
+template <int NL>
+__device__ __forceinline__ uint64_t mspan_at(const SceneView& v, int lvl) {
+    uint64_t m = v.mspan[0];
+#pragma unroll
+    for (int i = 1; i < NL; ++i)
+        if (lvl == i) m = v.mspan[i];
+    return m;
+}
+
+// Descend from level 0 to level TO (< nlev) for leaf cell c.  Returns the
+// level at which the path is empty, or TO + 1 when the level-TO node exists
 // (its index in `node`).  Quotients c / span[i] use the precomputed magics.
-template <bool STATS>
-__device__ __forceinline__ int descend(const SceneView& v, const int c[3], int to, uint32_t& node, stat_t* cnt) {
+template <bool STATS, int TO>
+__device__ __forceinline__ int descend(const SceneView& v, const int c[3], uint32_t& node, stat_t* cnt) {
     int p[3] = {span_div(c[0], v.mspan[0]), span_div(c[1], v.mspan[0]), span_div(c[2], v.mspan[0])};
     const int32_t n0 = v.map0[p[0] + v.dim0[0] * (p[1] + v.dim0[1] * p[2])];
     if (STATS) {
@@ -85,7 +90,8 @@ __device__ __forceinline__ int descend(const SceneView& v, const int c[3], int t
     }
     if (n0 < 0 || (uint32_t)n0 >= v.nn[0]) return 0;
     uint32_t n = (uint32_t)n0;
-    for (int i = 1; i <= to; ++i) {
+#pragma unroll
+    for (int i = 1; i <= TO; ++i) {
         const int q[3] = {span_div(c[0], v.mspan[i]), span_div(c[1], v.mspan[i]), span_div(c[2], v.mspan[i])};
         const int r = v.ratio[i - 1];
         const int loc = (q[0] - r * p[0]) + r * ((q[1] - r * p[1]) + r * (q[2] - r * p[2]));
@@ -104,59 +110,185 @@ __device__ __forceinline__ int descend(const SceneView& v, const int c[3], int t
         p[2] = q[2];
     }
     node = n;
-    return to + 1;
+    return TO + 1;
 }
 
-template <bool STATS>
-__device__ void trace_segment(const SceneView& v, const float o[3], const float d[3], uint32_t last, Hit& hit,
-                              stat_t cnt[ST_COUNT], bool keep = false) {
-    if (!keep) {  // keep: continue from a hit found in another hierarchy (overlay)
-        hit.id = NO_HIT;
-        hit.t = INFINITY;
-        hit.lab = 0;
-        hit.nx = hit.ny = hit.nz = 0.f;
+// Per-wave LDS of the cooperative leaf test: the rays of the wave's lanes and,
+// per lane, the pending leaf, its running nearest hit and the hit's normal.
+struct alignas(16) LeafTestLds {
+    float4 hn[64];                 // normal + label bits of a new nearest hit
+    unsigned long long best[64];   // (t bits << 32) | point id: lexicographic min = nearest, ties by id
+    float ox[64], oy[64], oz[64], dx[64], dy[64], dz[64];
+    uint32_t last[64];             // point the ray left (excluded)
+    uint32_t begin[64];            // first entry of the lane's pending leaf
+    uint32_t excl[64];             // exclusive prefix of the pending entry counts over lanes
+    uint32_t win[64];              // a test of this pass found a new nearest hit for the lane
+    int32_t mark[64];              // lane whose entries start at this position of the current chunk
+};
+
+__device__ __forceinline__ void wave_sync() {
+    __builtin_amdgcn_fence(__ATOMIC_SEQ_CST, "wavefront");
+    __builtin_amdgcn_wave_barrier();
+}
+
+__device__ __forceinline__ int wave_incl_max(int x) {
+#pragma unroll
+    for (int off = 1; off < 64; off <<= 1) {
+        const int y = __shfl_up(x, off, 64);
+        if ((int)lane_id() >= off) x = max(x, y);
     }
-    float inv[3];
-    int step[3];
+    return x;
+}
+
+// Test the pending leaves of all lanes of the wave together: the wave's
+// (lane, entry) pairs are dealt out 64 at a time, so every lane tests a
+// surfel in every pass whatever the leaves' sizes, and consecutive lanes read
+// consecutive entries of a leaf.  Each pair is tested against its owner
+// lane's ray and the owner's nearest hit is the minimum of (t, id) over its
+// previous hit and all accepted pairs: the same result as testing the
+// leaf's entries one after another in the owner's lane.  Called by every
+// lane of the wave; `has` marks lanes with a pending leaf (entries r).
+template <bool STATS>
+__device__ __forceinline__ void leaf_tests(const SceneView& v, LeafTestLds& W, bool has, uint2 r, Hit& hit,
+                                           stat_t cnt[ST_COUNT]) {
+    const uint32_t lane = lane_id();
+    const uint32_t n = has ? r.y : 0u;
+    const uint32_t incl = wave_incl_scan(n);
+    const uint32_t total = __builtin_amdgcn_readfirstlane(__shfl(incl, 63, 64));
+    const uint32_t excl = incl - n;
+    W.begin[lane] = r.x;
+    W.excl[lane] = excl;
+    W.best[lane] = ((unsigned long long)__float_as_uint(hit.t) << 32) | hit.id;
+    W.win[lane] = 0u;
+    for (uint32_t base = 0; base < total; base += 64) {
+        if (STATS && lane == 0) ++cnt[ST_WAVE_TESTS];
+        W.mark[lane] = -1;
+        wave_sync();
+        if (n && excl < base + 64 && incl > base) W.mark[excl > base ? excl - base : 0] = (int)lane;
+        wave_sync();
+        const int own = wave_incl_max(W.mark[lane]);
+        const uint32_t pi = base + lane;
+        bool ok = false;
+        unsigned long long cand = 0;
+        float4 N = make_float4(0.f, 0.f, 0.f, 0.f);
+        if (pi < total && own >= 0) {  // own >= 0 always: the pair at `base` has an owner
+            const uint32_t k = W.begin[own] + (pi - W.excl[own]);
+            const float4 P4 = v.spos[k];
+            N = v.snrm[k];
+            const float o0 = W.ox[own], o1 = W.oy[own], o2 = W.oz[own];
+            const float d0 = W.dx[own], d1 = W.dy[own], d2 = W.dz[own];
+            const uint32_t id = __float_as_uint(P4.w);
+            const float wx = P4.x - o0, wy = P4.y - o1, wz = P4.z - o2;
+            const float den = d0 * N.x + d1 * N.y + d2 * N.z;
+            const float num = wx * N.x + wy * N.y + wz * N.z;
+            const float t = num * __builtin_amdgcn_rcpf(den);
+            const float qx = t * d0 - wx, qy = t * d1 - wy, qz = t * d2 - wz;
+            const float dist2 = qx * qx + qy * qy + qz * qz;
+            ok = fabsf(den) > 1e-7f && t > v.t_eps && id != W.last[own] && dist2 <= v.rs2;
+            if (ok) {
+                cand = ((unsigned long long)__float_as_uint(t) << 32) | id;
+                atomicMin(&W.best[own], cand);
+            }
+        }
+        wave_sync();
+        // the pair that holds the minimum publishes the hit's normal and label
+        // (pairs with equal (t, id) are the same point: same normal)
+        if (ok && W.best[own] == cand) {
+            W.hn[own] = N;
+            W.win[own] = 1u;
+        }
+        wave_sync();
+    }
+    if (has && W.win[lane]) {
+        const unsigned long long b = W.best[lane];
+        const float4 hn = W.hn[lane];
+        hit.t = __uint_as_float((uint32_t)(b >> 32));
+        hit.id = (uint32_t)b;
+        hit.nx = hn.x;
+        hit.ny = hn.y;
+        hit.nz = hn.z;
+        hit.lab = __float_as_uint(hn.w);
+    }
+    wave_sync();
+}
+
+// DDA state of one lane's segment.
+struct Seg {
+    float inv[3];   // 1 / d (0 on axes the ray does not move along)
+    int c[3];       // current leaf cell
+    int cq[3];      // parent cell of the cached descent
+    int cres;       // cached descent result
+    uint32_t cnode; // cached parent node
+    int it;         // DDA steps taken
+};
+
+__device__ __forceinline__ int dir_step(float x) { return x > 0.f ? 1 : (x < 0.f ? -1 : 0); }
+
+// Start a segment from o along d: clip to the grid and find the first cell.
+// Returns false when the ray misses the grid.
+__device__ __forceinline__ bool seg_begin(const SceneView& v, const float o[3], const float d[3], Seg& S) {
     float t0 = 0.f, t1 = INFINITY;
 #pragma unroll
     for (int a = 0; a < 3; ++a) {
         if (d[a] > 0.f) {
-            step[a] = 1;
-            inv[a] = 1.0f / d[a];
-            t0 = fmaxf(t0, (v.org[a] - o[a]) * inv[a]);
-            t1 = fminf(t1, (v.hi[a] - o[a]) * inv[a]);
+            S.inv[a] = 1.0f / d[a];
+            t0 = fmaxf(t0, (v.org[a] - o[a]) * S.inv[a]);
+            t1 = fminf(t1, (v.hi[a] - o[a]) * S.inv[a]);
         } else if (d[a] < 0.f) {
-            step[a] = -1;
-            inv[a] = 1.0f / d[a];
-            t0 = fmaxf(t0, (v.hi[a] - o[a]) * inv[a]);
-            t1 = fminf(t1, (v.org[a] - o[a]) * inv[a]);
+            S.inv[a] = 1.0f / d[a];
+            t0 = fmaxf(t0, (v.hi[a] - o[a]) * S.inv[a]);
+            t1 = fminf(t1, (v.org[a] - o[a]) * S.inv[a]);
         } else {
-            step[a] = 0;
-            inv[a] = 0.f;
+            S.inv[a] = 0.f;
             if (o[a] < v.org[a] || o[a] > v.hi[a]) t1 = -1.f;
         }
     }
-    if (!(t0 <= t1)) return;
-    int c[3];
 #pragma unroll
     for (int a = 0; a < 3; ++a) {
         const int ci = (int)floorf((o[a] + t0 * d[a] - v.org[a]) * v.inv_h);
-        c[a] = min(max(ci, 0), v.dim[a] - 1);
+        S.c[a] = min(max(ci, 0), v.dim[a] - 1);
+        S.cq[a] = -1;
     }
-    const int max_iter = v.dim[0] + v.dim[1] + v.dim[2] + 8;
-    const int L = v.nlev;
-    const int P = L - 2;  // level of the leaves' parents (-1: single-level grid)
-    // Cache of the parent lookup: consecutive leaves mostly share a parent, so
-    // the descent from level 0 runs only when the parent cell changes.
-    int cq[3] = {-1, -1, -1};
-    int cres = 0;
-    uint32_t cnode = 0;
-    for (int it = 0; it < max_iter; ++it) {
-        uint32_t node = 0;
-        int skip = 1;  // > 1: an empty cube of 2 skip - 1 leaves centred on c
-        int lvl;       // level of the empty cell containing c, or L for an occupied leaf
-        if (P < 0) {
+    S.cres = 0;
+    S.cnode = 0;
+    S.it = 0;
+    return t0 <= t1;
+}
+
+__device__ __forceinline__ void stage_ray(LeafTestLds& W, const float o[3], const float d[3], uint32_t last) {
+    const uint32_t lane = lane_id();
+    W.ox[lane] = o[0];
+    W.oy[lane] = o[1];
+    W.oz[lane] = o[2];
+    W.dx[lane] = d[0];
+    W.dy[lane] = d[1];
+    W.dz[lane] = d[2];
+    W.last[lane] = last;
+}
+
+__device__ __forceinline__ void hit_reset(Hit& hit) {
+    hit.id = NO_HIT;
+    hit.t = INFINITY;
+    hit.lab = 0;
+    hit.nx = hit.ny = hit.nz = 0.f;
+}
+
+// One DDA step of every walking lane through a hierarchy of NL levels
+// (NL == v.nlev): look the current cell up top-down, test an occupied leaf
+// (cooperatively, with the other lanes' leaves), then move to the next cell
+// or stop.  Called by every lane of the wave; `walking` is cleared when the
+// lane's segment ends.  The lane's ray must be staged in W.
+template <bool STATS, int NL>
+__device__ __forceinline__ void dda_step(const SceneView& v, LeafTestLds& W, bool& walking, const float o[3],
+                                         const float d[3], Hit& hit, Seg& S, stat_t cnt[ST_COUNT]) {
+    constexpr int L = NL;
+    constexpr int P = L - 2;  // level of the leaves' parents (-1: single-level grid)
+    int* c = S.c;
+    uint32_t node = 0;
+    int skip = 1;  // > 1: an empty cube of 2 skip - 1 leaves centred on c
+    int lvl = 0;   // level of the empty cell containing c, or L for an occupied leaf
+    if (walking) {
+        if constexpr (P < 0) {
             const int32_t n0 = v.map0[c[0] + v.dim0[0] * (c[1] + v.dim0[1] * c[2])];
             if (STATS) {
                 ++cnt[ST_NODES];
@@ -165,19 +297,20 @@ __device__ void trace_segment(const SceneView& v, const float o[3], const float 
             lvl = (n0 < 0 || (uint32_t)n0 >= v.nn[0]) ? 0 : L;
             node = (uint32_t)n0;
         } else {
+            // the descent from level 0 runs only when the parent cell changes
             const int q[3] = {span_div(c[0], v.mspan[P]), span_div(c[1], v.mspan[P]), span_div(c[2], v.mspan[P])};
-            if (q[0] != cq[0] || q[1] != cq[1] || q[2] != cq[2]) {
-                cq[0] = q[0];
-                cq[1] = q[1];
-                cq[2] = q[2];
-                cres = descend<STATS>(v, c, P, cnode, cnt);
+            if (q[0] != S.cq[0] || q[1] != S.cq[1] || q[2] != S.cq[2]) {
+                S.cq[0] = q[0];
+                S.cq[1] = q[1];
+                S.cq[2] = q[2];
+                S.cres = descend<STATS, P>(v, c, S.cnode, cnt);
             }
-            if (cres <= P) {
-                lvl = cres;
+            if (S.cres <= P) {
+                lvl = S.cres;
             } else {
                 const int r = v.ratio[P];
                 const int loc = (c[0] - r * q[0]) + r * ((c[1] - r * q[1]) + r * (c[2] - r * q[2]));
-                const size_t wi = (size_t)cnode * v.nw[P] + (loc >> 6);
+                const size_t wi = (size_t)S.cnode * v.nw[P] + (loc >> 6);
                 const uint64_t w = v.mask[P][wi];
                 const uint64_t bit = uint64_t(1) << (loc & 63);
                 if (STATS) {
@@ -190,54 +323,39 @@ __device__ void trace_segment(const SceneView& v, const float o[3], const float 
                     if (node < v.nn[L - 1]) lvl = L;
                 } else if (v.ldist) {
                     // empty leaf: the whole cube of radius skip - 1 around it is empty
-                    skip = max(1, (int)v.ldist[(size_t)cnode * (size_t)(r * r * r) + loc]);
+                    skip = max(1, (int)v.ldist[(size_t)S.cnode * (size_t)(r * r * r) + loc]);
                     if (STATS) cnt[ST_BYTES] += 1;
                 }
             }
         }
-        if (STATS) {
+    }
+    const bool at_leaf = walking && lvl == L;
+    if (STATS) {
+        const uint64_t m_walk = __ballot(walking);
+        if (walking) {
             ++cnt[ST_DDA];
             if (lvl == L - 1 && L > 1) ++cnt[ST_EMPTY_LEAF];
-            // leaf visits where every lane of the wave still walking is in the same leaf
-            const uint64_t m_leaf = __ballot(lvl == L);
-            const int first = m_leaf ? __ffsll((long long)m_leaf) - 1 : 0;
-            const uint32_t lead = __shfl(node, first, 64);
-            const uint64_t m_walk = __ballot(true);
-            if (lvl == L && __ballot(lvl == L && node == lead) == m_walk) ++cnt[ST_UNIFORM];
         }
-        int S = 1;
-        if (lvl == L) {
-            const uint2 r = v.leaf[node];
-            if (STATS) {
-                ++cnt[ST_LEAVES];
-                cnt[ST_TESTS] += r.y;
-                cnt[ST_BYTES] += 8 + 32ull * r.y;
-            }
-            for (uint32_t k = r.x; k < r.x + r.y; ++k) {
-                const float4 P4 = v.spos[k];
-                const float4 N = v.snrm[k];
-                const uint32_t id = __float_as_uint(P4.w);
-                const float wx = P4.x - o[0], wy = P4.y - o[1], wz = P4.z - o[2];
-                const float den = d[0] * N.x + d[1] * N.y + d[2] * N.z;
-                const float num = wx * N.x + wy * N.y + wz * N.z;
-                const float t = num * __builtin_amdgcn_rcpf(den);
-                const float qx = t * d[0] - wx, qy = t * d[1] - wy, qz = t * d[2] - wz;
-                const float dist2 = qx * qx + qy * qy + qz * qz;
-                const bool ok = fabsf(den) > 1e-7f && t > v.t_eps && id != last && dist2 <= v.rs2 &&
-                                (t < hit.t || (t == hit.t && id < hit.id));
-                if (ok) {
-                    hit.id = id;
-                    hit.t = t;
-                    hit.nx = N.x;
-                    hit.ny = N.y;
-                    hit.nz = N.z;
-                    hit.lab = __float_as_uint(N.w);
-                }
-            }
-        } else {
-            S = v.span[lvl];
+        // leaf visits where every lane of the wave still walking is in the same leaf
+        const uint64_t m_leaf = __ballot(at_leaf);
+        const int first = m_leaf ? __ffsll((long long)m_leaf) - 1 : 0;
+        const uint32_t lead = __shfl(node, first, 64);
+        if (at_leaf && __ballot(at_leaf && node == lead) == m_walk) ++cnt[ST_UNIFORM];
+        if (lane_id() == 0) ++cnt[ST_WAVE_DDA];
+    }
+    uint2 r = make_uint2(0u, 0u);
+    if (at_leaf) {
+        r = v.leaf[node];
+        if (STATS) {
+            ++cnt[ST_LEAVES];
+            cnt[ST_TESTS] += r.y;
+            cnt[ST_BYTES] += 8 + 32ull * r.y;
         }
-        // exit of the current cell (size S leaves)
+    }
+    if (__ballot(at_leaf && r.y != 0u)) leaf_tests<STATS>(v, W, at_leaf, r, hit, cnt);
+    if (walking) {
+        const int Sz = at_leaf ? 1 : span_at<NL>(v, lvl);
+        // exit of the current cell (size Sz leaves)
         int lo[3], hi[3];
         float te = INFINITY;
         int axis = 0;
@@ -247,100 +365,109 @@ __device__ void trace_segment(const SceneView& v, const float o[3], const float 
                 lo[a] = c[a] - (skip - 1);
                 hi[a] = c[a] + skip;
             } else {
-                lo[a] = (S == 1) ? c[a] : span_div(c[a], v.mspan[lvl]) * S;
-                hi[a] = lo[a] + S;
+                lo[a] = (Sz == 1) ? c[a] : span_div(c[a], mspan_at<NL>(v, lvl)) * Sz;
+                hi[a] = lo[a] + Sz;
             }
             float ta = INFINITY;
-            if (step[a] > 0)
-                ta = ((float)hi[a] * v.h + v.org[a] - o[a]) * inv[a];
-            else if (step[a] < 0)
-                ta = ((float)lo[a] * v.h + v.org[a] - o[a]) * inv[a];
+            if (d[a] > 0.f)
+                ta = ((float)hi[a] * v.h + v.org[a] - o[a]) * S.inv[a];
+            else if (d[a] < 0.f)
+                ta = ((float)lo[a] * v.h + v.org[a] - o[a]) * S.inv[a];
             if (ta < te) {
                 te = ta;
                 axis = a;
             }
         }
-        // no later cell can hold a nearer hit
-        if (te > hit.t + (hit.t * 4e-6f + 1e-3f * v.h)) break;
-        const int nc = step[axis] > 0 ? hi[axis] : lo[axis] - 1;
-        if (nc < 0 || nc >= v.dim[axis]) break;
+        // next cell along the exit axis (selects, no dynamic indexing of private arrays)
+        int nc = 0, dim_ax = 0;
 #pragma unroll
-        for (int a = 0; a < 3; ++a) {
-            if (a == axis || step[a] == 0) continue;
-            int j = (int)floorf((o[a] + te * d[a] - v.org[a]) * v.inv_h);
-            j = min(max(j, lo[a]), hi[a] - 1);
-            j = step[a] > 0 ? max(j, c[a]) : min(j, c[a]);
-            c[a] = j;
+        for (int a = 0; a < 3; ++a)
+            if (a == axis) {
+                nc = d[a] > 0.f ? hi[a] : lo[a] - 1;
+                dim_ax = v.dim[a];
+            }
+        const int max_iter = v.dim[0] + v.dim[1] + v.dim[2] + 8;
+        // no later cell can hold a nearer hit; or the ray leaves the grid
+        if (te > hit.t + (hit.t * 4e-6f + 1e-3f * v.h) || nc < 0 || nc >= dim_ax || ++S.it >= max_iter) {
+            walking = false;
+        } else {
+#pragma unroll
+            for (int a = 0; a < 3; ++a) {
+                if (a == axis) {
+                    c[a] = nc;
+                    continue;
+                }
+                const int sg = dir_step(d[a]);
+                if (sg == 0) continue;
+                int j = (int)floorf((o[a] + te * d[a] - v.org[a]) * v.inv_h);
+                j = min(max(j, lo[a]), hi[a] - 1);
+                j = sg > 0 ? max(j, c[a]) : min(j, c[a]);
+                c[a] = j;
+            }
         }
-        c[axis] = nc;
     }
 }
 
+// One whole segment of every active lane (lanes with `active` false only
+// help with the cooperative leaf tests).  Called by every lane of the wave.
+template <bool STATS, int NL>
+__device__ __forceinline__ void trace_segment(const SceneView& v, LeafTestLds& W, bool active, const float o[3],
+                                              const float d[3], Hit& hit, stat_t cnt[ST_COUNT]) {
+    Seg S;
+    bool walking = seg_begin(v, o, d, S) && active;
+    while (__ballot(walking)) dda_step<STATS, NL>(v, W, walking, o, d, hit, S, cnt);
+}
 
-// One wave's 64 consecutive slots [base, base + 64) of bounce b of one query.
-// Slots at or past `range` are idle; a slot whose ray id is NO_HIT (left by
-// an in-place bounce) is idle too.  Survivors go to the other ping-pong
-// buffer, compacted with one atomic per wave, or at their own slot when
-// `in_place` (dead slots then get NO_HIT).  Every lane of the wave must call
-// this (ballots).
+// Load slot i of bounce b: the ray, its global id, polyline length and the
+// point it left.  Returns false for an empty slot (left by an in-place
+// bounce), which an in-place bounce b < K marks empty in its output too.
+template <bool FIRST>
+__device__ __forceinline__ bool load_ray(const TraceArgs& a, int b, uint32_t i, bool in_place, float o[3], float d[3],
+                                         float& L, uint32_t& last, uint32_t& g) {
+    L = 0.f;
+    last = NO_HIT;
+    if (FIRST) {
+        const uint32_t ti = i / a.n_rays;
+        const uint32_t jl = i - ti * a.n_rays;
+        const uint32_t j = a.perm ? a.perm[jl] : jl;  // direction-coherent order
+        g = ti * a.n_rays + j;
+        o[0] = a.tx[3 * ti];
+        o[1] = a.tx[3 * ti + 1];
+        o[2] = a.tx[3 * ti + 2];
+        d[0] = a.dirs[3 * (size_t)j];
+        d[1] = a.dirs[3 * (size_t)j + 1];
+        d[2] = a.dirs[3 * (size_t)j + 2];
+        const float inv = 1.0f / sqrtf(d[0] * d[0] + d[1] * d[1] + d[2] * d[2]);
+        d[0] *= inv;
+        d[1] *= inv;
+        d[2] *= inv;
+        return true;
+    }
+    g = a.buf_g[(b & 1) ^ 1][i];
+    if (g == NO_HIT) {
+        // the last bounce (b == K) has no output buffers (they may be unallocated)
+        if (in_place && b < a.K) a.buf_g[b & 1][i] = NO_HIT;
+        return false;
+    }
+    const float4 o4 = a.buf_o[(b & 1) ^ 1][i];
+    const float4 d4 = a.buf_d[(b & 1) ^ 1][i];
+    o[0] = o4.x; o[1] = o4.y; o[2] = o4.z; L = o4.w;
+    d[0] = d4.x; d[1] = d4.y; d[2] = d4.z; last = __float_as_uint(d4.w);
+    return true;
+}
+
+// End of the segments of lanes with `done`: log the hit, test every RX on
+// [0, t_hit] (rho grows with the unfolded length), reflect at the hit and
+// write the survivor (at its own slot i when `in_place`, else compacted with
+// one atomic per wave); an in-place bounce marks a dead slot empty.  Called
+// by every lane of the wave (ballots).
 template <bool FIRST, bool STATS>
-__device__ __forceinline__ void trace_chunk(const TraceArgs& a, int b, uint32_t base, uint32_t range, bool in_place,
-                                            stat_t cnt[ST_COUNT]) {
+__device__ __forceinline__ void finish_segment(const TraceArgs& a, int b, bool done, bool in_place, uint32_t i,
+                                               uint32_t g, float o[3], float d[3], float L, uint32_t last,
+                                               const Hit& hit, stat_t cnt[ST_COUNT]) {
     const uint32_t lane = lane_id();
     const uint64_t lt = lanemask_lt();
-    const float4* in_o = a.buf_o[(b & 1) ^ 1];
-    const float4* in_d = a.buf_d[(b & 1) ^ 1];
-    const uint32_t* in_g = a.buf_g[(b & 1) ^ 1];
-    float4* out_o = a.buf_o[b & 1];
-    float4* out_d = a.buf_d[b & 1];
-    uint32_t* out_g = a.buf_g[b & 1];
-    uint32_t* rec_counter = &a.counters[PCRL_CNT_REC(a.K)];
-    const uint32_t i = base + lane;
-    const bool in_range = i < range;
-    bool act = in_range;
-    float o[3] = {0.f, 0.f, 0.f}, d[3] = {1.f, 0.f, 0.f};
-    float L = 0.f;
-    uint32_t last = NO_HIT, g = NO_HIT;
-    if (act) {
-        if (FIRST) {
-            const uint32_t ti = i / a.n_rays;
-            const uint32_t jl = i - ti * a.n_rays;
-            const uint32_t j = a.perm ? a.perm[jl] : jl;  // direction-coherent order
-            g = ti * a.n_rays + j;
-            o[0] = a.tx[3 * ti];
-            o[1] = a.tx[3 * ti + 1];
-            o[2] = a.tx[3 * ti + 2];
-            if (a.dirs) {
-                d[0] = a.dirs[3 * (size_t)j];
-                d[1] = a.dirs[3 * (size_t)j + 1];
-                d[2] = a.dirs[3 * (size_t)j + 2];
-            } else {
-                fib_dir(j, a.n_rays, d[0], d[1], d[2]);
-            }
-            const float inv = 1.0f / sqrtf(d[0] * d[0] + d[1] * d[1] + d[2] * d[2]);
-            d[0] *= inv;
-            d[1] *= inv;
-            d[2] *= inv;
-        } else {
-            g = in_g[i];
-            if (g == NO_HIT) {
-                act = false;
-            } else {
-                const float4 o4 = in_o[i];
-                const float4 d4 = in_d[i];
-                o[0] = o4.x; o[1] = o4.y; o[2] = o4.z; L = o4.w;
-                d[0] = d4.x; d[1] = d4.y; d[2] = d4.z; last = __float_as_uint(d4.w);
-            }
-        }
-    }
-    Hit hit;
-    hit.id = NO_HIT;
-    hit.t = INFINITY;
-    if (act) {
-        trace_segment<STATS>(a.v, o, d, last, hit, cnt);
-        // dynamic points: the nearest hit over base and overlay is the nearest
-        // hit of the union (ties again by point id)
-        if (a.has_ov) trace_segment<STATS>(a.ov, o, d, last, hit, cnt, true);
+    if (done) {
         if (STATS) {
             ++cnt[ST_SEGMENTS];
             if (hit.id != NO_HIT) ++cnt[ST_HITS];
@@ -352,13 +479,13 @@ __device__ __forceinline__ void trace_chunk(const TraceArgs& a, int b, uint32_t 
             a.hit_t[idx] = hit.id == NO_HIT ? NAN : hit.t;
         }
     }
-    // reception on [0, t_hit]
+    uint32_t* rec_counter = &a.counters[PCRL_CNT_REC(a.K)];
     for (int r = 0; r < a.n_rx; ++r) {
         const float rx0 = a.rx[3 * r], rx1 = a.rx[3 * r + 1], rx2 = a.rx[3 * r + 2];
         const float vx = rx0 - o[0], vy = rx1 - o[1], vz = rx2 - o[2];
         const float s = vx * d[0] + vy * d[1] + vz * d[2];
         bool got = false;
-        if (act && s > 0.f && s <= hit.t) {
+        if (done && s > 0.f && s <= hit.t) {
             const float cx = vx - s * d[0], cy = vy - s * d[1], cz = vz - s * d[2];
             const float rho = a.sig_c * (L + s);
             got = cx * cx + cy * cy + cz * cz <= rho * rho;
@@ -378,7 +505,7 @@ __device__ __forceinline__ void trace_chunk(const TraceArgs& a, int b, uint32_t 
         }
     }
     // reflect and keep survivors
-    const bool surv = act && hit.id != NO_HIT && b < a.K;
+    const bool surv = done && hit.id != NO_HIT && b < a.K;
     if (surv) {
         const float qx = o[0] + hit.t * d[0], qy = o[1] + hit.t * d[1], qz = o[2] + hit.t * d[2];
         a.hist[(size_t)b * a.n_total + g] = make_float4(qx, qy, qz, __uint_as_float(hit.lab));
@@ -402,12 +529,35 @@ __device__ __forceinline__ void trace_chunk(const TraceArgs& a, int b, uint32_t 
     }
     if (STATS && surv) cnt[ST_BYTES] += 52;
     if (surv) {
-        out_o[slot] = make_float4(o[0], o[1], o[2], L);
-        out_d[slot] = make_float4(d[0], d[1], d[2], __uint_as_float(last));
-        out_g[slot] = g;
-    } else if (in_place && in_range) {
-        out_g[i] = NO_HIT;
+        a.buf_o[b & 1][slot] = make_float4(o[0], o[1], o[2], L);
+        a.buf_d[b & 1][slot] = make_float4(d[0], d[1], d[2], __uint_as_float(last));
+        a.buf_g[b & 1][slot] = g;
+    } else if (done && in_place) {
+        a.buf_g[b & 1][i] = NO_HIT;
     }
+}
+
+// One wave's 64 consecutive slots [base, base + 64) of bounce b of one query,
+// traced in lockstep (base hierarchy, then the overlay).  Slots at or past
+// `range` are idle; a slot whose ray id is NO_HIT (left by an in-place
+// bounce) is idle too.  Every lane of the wave must call this (ballots).
+template <bool FIRST, bool STATS, int NL, bool OV>
+__device__ __forceinline__ void trace_chunk(const TraceArgs& a, LeafTestLds& W, int b, uint32_t base, uint32_t range,
+                                            bool in_place, stat_t cnt[ST_COUNT]) {
+    const uint32_t i = base + lane_id();
+    float o[3] = {0.f, 0.f, 0.f}, d[3] = {1.f, 0.f, 0.f};
+    float L = 0.f;
+    uint32_t last = NO_HIT, g = NO_HIT;
+    const bool act = i < range && load_ray<FIRST>(a, b, i, in_place, o, d, L, last, g);
+    Hit hit;
+    hit_reset(hit);
+    stage_ray(W, o, d, last);
+    trace_segment<STATS, NL>(a.v, W, act, o, d, hit, cnt);
+    // dynamic points: the nearest hit over base and overlay is the nearest
+    // hit of the union (ties again by point id); the overlay shares the
+    // base's frame and levels
+    if (OV) trace_segment<STATS, NL>(a.ov, W, act, o, d, hit, cnt);
+    finish_segment<FIRST, STATS>(a, b, act, in_place, i, g, o, d, L, last, hit, cnt);
 }
 
 template <bool STATS>

@@ -70,6 +70,14 @@ def test_overlay_equals_full_rebuild(env, world):
         hits = inc.hit_log[0].cpu().numpy()
         assert np.isin(hits, idx.astype(np.int64)).any()          # the moving boxes are actually hit
     assert base.info()["epoch"] >= 3 and base.info()["n_dynamic"] == len(idx)
+    # a dynamic disk reaching outside the base grid is refused and the current overlay stays
+    info = base.info()
+    far = xyz.copy()
+    far[0, 0] = info["origin"][0] + 0.5 * r_s
+    with pytest.raises(pcrl.PcrlError) as e:
+        base.update_points(idx.astype(np.uint32), far, nrm, lab)
+    assert e.value.status == -1 and "grid" in e.value.message
+    assert base.info()["epoch"] == info["epoch"] and base.info()["n_dynamic"] == len(idx)
 
 
 def _queries(sc, rng, n):
