@@ -303,6 +303,33 @@ __global__ __launch_bounds__(BUILD_BLOCK) void k_brick_dist(const uint64_t* mask
     }
 }
 
+// Empty-space skip radii of the level-0 grid: for every cell the Chebyshev
+// distance (in cells, at most DIST0_CAP + 1) to the nearest occupied cell, so
+// the cube of radius d - 1 around an empty cell holds no occupied cell.  The
+// same march distance as inside the bricks, one level up.  Separable: one
+// pass per axis of out(c) = min over |t| <= DIST0_CAP of max(|t|, in(c + t e)),
+// starting from 0 (occupied) / 255 (empty).  A window that misses the
+// nearest occupied cell only lowers the result (conservative).
+constexpr int DIST0_CAP = 15;
+
+__global__ void k_dist0_pass(const int32_t* map0, const uint8_t* in, uint8_t* out, int dx, int dy, int dz, int axis) {
+    const int64_t c = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    const int64_t n = (int64_t)dx * dy * dz;
+    if (c >= n) return;
+    const int x = (int)(c % dx), y = (int)((c / dx) % dy), z = (int)(c / ((int64_t)dx * dy));
+    const int pos = axis == 0 ? x : (axis == 1 ? y : z);
+    const int len = axis == 0 ? dx : (axis == 1 ? dy : dz);
+    const int64_t stride = axis == 0 ? 1 : (axis == 1 ? dx : (int64_t)dx * dy);
+    int m = 255;
+    const int t0 = max(-DIST0_CAP, -pos), t1 = min(DIST0_CAP, len - 1 - pos);
+    for (int t = t0; t <= t1; ++t) {
+        const int64_t q = c + t * stride;
+        const int a = map0 ? (map0[q] >= 0 ? 0 : 255) : (int)in[q];
+        m = min(m, max(abs(t), a));
+    }
+    out[c] = (uint8_t)min(m, DIST0_CAP + 1);
+}
+
 __global__ void k_leaf_counts(uint2* leaf, int64_t n_leaves, int64_t m) {
     int64_t l = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
     if (l >= n_leaves) return;
@@ -541,6 +568,21 @@ static int build_hierarchy(const float* xyz, const float4* unit_nrm, const uint3
         hb.bytes += (int64_t)host_nodes[L - 2] * (int64_t)n3;
     }
 
+    // empty-space skip radii of the level-0 grid
+    {
+        uint8_t *d0 = nullptr, *tmp = nullptr;
+        if ((rc = B.alloc(&d0, (size_t)cells0)) || (rc = T.alloc(&tmp, (size_t)cells0))) return rc;
+        const unsigned g0 = (unsigned)blocks_for((int64_t)cells0);
+        hipLaunchKernelGGL(k_dist0_pass, dim3(g0), dim3(BUILD_BLOCK), 0, s, (const int32_t*)map0,
+                           (const uint8_t*)nullptr, d0, v.dim0[0], v.dim0[1], v.dim0[2], 0);
+        hipLaunchKernelGGL(k_dist0_pass, dim3(g0), dim3(BUILD_BLOCK), 0, s, (const int32_t*)nullptr,
+                           (const uint8_t*)d0, tmp, v.dim0[0], v.dim0[1], v.dim0[2], 1);
+        hipLaunchKernelGGL(k_dist0_pass, dim3(g0), dim3(BUILD_BLOCK), 0, s, (const int32_t*)nullptr,
+                           (const uint8_t*)tmp, d0, v.dim0[0], v.dim0[1], v.dim0[2], 2);
+        v.dist0 = d0;
+        hb.bytes += (int64_t)cells0;
+    }
+
     // surfel streams in leaf order
     float4 *spos = nullptr, *snrm = nullptr;
     if ((rc = B.alloc(&spos, (size_t)m)) || (rc = B.alloc(&snrm, (size_t)m))) return rc;
@@ -667,6 +709,7 @@ static int overlay_impl(PcrlScene* S, const uint32_t* gid, const float* xyz, con
     }
     v.leaf = nullptr;
     v.ldist = nullptr;
+    v.dist0 = nullptr;
     v.spos = v.snrm = nullptr;
     HierBuild hb;
     if ((rc = build_hierarchy(xyz, unit_nrm, label, gid, n, s, v, ov->bufs, T, hb))) return fail(rc);

@@ -82,6 +82,15 @@ int scan_u32(const uint32_t* in, uint32_t* out, int64_t n, uint32_t* total, hipS
 int radix_sort_u64(uint64_t* keys, uint32_t* vals, int64_t n, int bits, hipStream_t s);
 int radix_sort_u32(uint32_t* keys, uint32_t* vals, int64_t n, int bits, hipStream_t s);
 
+// order[0 .. n) = the indices j < n of `keys` grouped by key (ascending
+// buckets, any order inside a bucket: one counting pass with atomics), where
+// n = min(*n_dev, n_max) when n_dev (device) is given, else n_max.
+int bucket_order_u16(const uint16_t* keys, int64_t n_max, const uint32_t* n_dev, uint32_t* order, hipStream_t s);
+// The second half of bucket_order_u16 when the 65536 bucket counts `cnt` were
+// accumulated elsewhere (with wave_bucket_add): scan them in place, then place.
+int bucket_place_u16(const uint16_t* keys, int64_t n_max, const uint32_t* n_dev, uint32_t* cnt, uint32_t* order,
+                     hipStream_t s);
+
 // Fill helpers.
 int fill_u32(uint32_t* p, uint32_t v, int64_t n, hipStream_t s);
 int fill_u64(uint64_t* p, uint64_t v, int64_t n, hipStream_t s);
@@ -129,6 +138,28 @@ __device__ __forceinline__ uint32_t wave_append(uint32_t* counter, uint32_t want
     return base + incl - want;
 }
 
+// Add this lane's item to the count of its bucket with one atomic per
+// distinct key of the wave (keys of neighbouring items often repeat); returns
+// the item's position among the bucket's items added so far.  Every lane of
+// the wave must call this.
+__device__ __forceinline__ uint32_t wave_bucket_add(uint32_t* cnt, uint32_t key, bool valid) {
+    const uint32_t lane = lane_id();
+    const uint64_t lt = lanemask_lt();
+    uint64_t todo = __ballot(valid);
+    uint32_t pos = 0;
+    while (todo) {
+        const int l = __ffsll((long long)todo) - 1;
+        const uint32_t k = __shfl(key, l, 64);
+        const uint64_t m = __ballot(valid && key == k) & todo;
+        uint32_t base = 0;
+        if ((int)lane == l) base = atomicAdd(&cnt[k], (uint32_t)__popcll(m));
+        base = __shfl(base, l, 64);
+        if ((m >> lane) & 1ull) pos = base + (uint32_t)__popcll(m & lt);
+        todo &= ~m;
+    }
+    return pos;
+}
+
 __device__ __forceinline__ float as_float(uint32_t u) { return __uint_as_float(u); }
 __device__ __forceinline__ uint32_t as_uint(float f) { return __float_as_uint(f); }
 
@@ -160,6 +191,7 @@ struct SceneView {
     const uint32_t* base[PCRL_MAX_LEVELS - 1];  // child index of the first set bit of each word
     const uint2* leaf;               // per leaf: (first entry, entry count)
     const uint8_t* ldist;            // null, or per leaf cell of each parent brick its empty-space skip radius
+    const uint8_t* dist0;            // null, or per level-0 cell its empty-space skip radius (level-0 cells)
     const float4* spos;              // per entry: x, y, z, point id (bits)
     const float4* snrm;              // per entry: unit normal, label (bits)
 };

@@ -75,25 +75,15 @@ __device__ __forceinline__ uint32_t spread_bits16(uint32_t x) {
     return x;
 }
 
-// Sort key of a launch direction: Morton code of its octahedral map, so rays
-// that are close on the sphere are close in the bounce-0 order.
-__global__ void k_dir_keys(const float* dirs, uint32_t n, uint32_t* keys, uint32_t* idx) {
+// Bucket of a launch direction: Morton code of its cell in a 256 x 256 grid
+// over the octahedral map, so rays that are close on the sphere are close in
+// the bounce-0 order.
+__global__ void k_dir_keys(const float* dirs, uint32_t n, uint16_t* keys) {
     const uint32_t j = blockIdx.x * blockDim.x + threadIdx.x;
     if (j >= n) return;
-    const float x = dirs[3 * (size_t)j], y = dirs[3 * (size_t)j + 1], z = dirs[3 * (size_t)j + 2];
-    const float s = fabsf(x) + fabsf(y) + fabsf(z);
-    float u = s > 0.f ? x / s : 0.f, w = s > 0.f ? y / s : 0.f;
-    if (z < 0.f) {
-        const float uu = (1.f - fabsf(w)) * (u >= 0.f ? 1.f : -1.f);
-        const float ww = (1.f - fabsf(u)) * (w >= 0.f ? 1.f : -1.f);
-        u = uu;
-        w = ww;
-    }
-    const uint32_t qu = (uint32_t)fminf(fmaxf((u * 0.5f + 0.5f) * 65535.f, 0.f), 65535.f);
-    const uint32_t qw = (uint32_t)fminf(fmaxf((w * 0.5f + 0.5f) * 65535.f, 0.f), 65535.f);
-    // 256 x 256 cells of the octahedral map: a 16-bit key, two radix passes
-    keys[j] = spread_bits16(qu >> 8) | (spread_bits16(qw >> 8) << 1);
-    idx[j] = j;
+    float u, w;
+    octahedral(dirs[3 * (size_t)j], dirs[3 * (size_t)j + 1], dirs[3 * (size_t)j + 2], u, w);
+    keys[j] = (uint16_t)(spread_bits16(cell_of(u, 256)) | (spread_bits16(cell_of(w, 256)) << 1));
 }
 
 __global__ void k_fill_logs(int32_t* id, float* t, size_t n) {
@@ -233,10 +223,10 @@ int launch_prepare(const PcrlScene* scene, const float* tx, int32_t n_tx, const 
     }
     if (!rc && (p->flags & PCRL_LAUNCH_COHERENT)) {
         const uint32_t nr = (uint32_t)L->n_rays;
-        uint32_t* keys = nullptr;
+        uint16_t* keys = nullptr;
         if (!(rc = B.alloc(&keys, nr)) && !(rc = B.alloc(&perm, nr))) {
-            hipLaunchKernelGGL(k_dir_keys, dim3((nr + 255) / 256), dim3(256), 0, s, dirs, nr, keys, perm);
-            rc = hipGetLastError() == hipSuccess ? radix_sort_u32(keys, perm, nr, 16, s) : PCRL_EHIP;
+            hipLaunchKernelGGL(k_dir_keys, dim3((nr + 255) / 256), dim3(256), 0, s, dirs, nr, keys);
+            rc = hipGetLastError() == hipSuccess ? bucket_order_u16(keys, nr, nullptr, perm, s) : PCRL_EHIP;
         }
     }
     if (!rc && timing_events && (p->flags & PCRL_LAUNCH_TIMING)) {
@@ -291,7 +281,12 @@ int launch_prepare(const PcrlScene* scene, const float* tx, int32_t n_tx, const 
     return PCRL_OK;
 }
 
-// The bounce loop of one query: K + 1 kernel launches, no host synchronisation.
+// Launches at least this large re-sort the survivors of every bounce for coherence.
+constexpr int64_t RESORT_MIN_RAYS = 1 << 16;
+
+// The bounce loop of one query: K + 1 kernel launches (plus, with `order`,
+// a key kernel and a radix sort of the survivors between bounces), no host
+// synchronisation.
 static int launch_run(PcrlLaunch* L, const TraceArgs& a) {
     hipStream_t s = L->stream;
     const int K = L->K;
@@ -311,6 +306,11 @@ static int launch_run(PcrlLaunch* L, const TraceArgs& a) {
         }
         PCRL_TRY_HIP(hipGetLastError());
         if (timing) PCRL_TRY_HIP(hipEventRecord(L->events[2 * b + 1], s));
+        if (a.order && b < K) {
+            // the bounce kernel wrote each survivor's bucket and counted the buckets
+            PCRL_TRY(bucket_place_u16(a.okeys, n_total, a.counters + b + 1, a.ocnt + (size_t)b * 65536,
+                                      const_cast<uint32_t*>(a.order), s));
+        }
     }
     return PCRL_OK;
 }
@@ -330,7 +330,20 @@ extern "C" int launch_rays(const PcrlScene* scene, const float* tx, int32_t n_tx
     PcrlLaunch* L = nullptr;
     TraceArgs a;
     PCRL_TRY(launch_prepare(scene, tx, n_tx, rx, n_rx, p, (hipStream_t)stream, true, &L, &a));
-    const int rc = launch_run(L, a);
+    // coherence order of the later bounces (results do not depend on it)
+    int rc = PCRL_OK;
+    if (L->K > 0 && (p->flags & PCRL_LAUNCH_COHERENT) && L->n_total >= RESORT_MIN_RAYS) {
+        uint32_t* order = nullptr;
+        rc = L->bufs.alloc(&order, (size_t)L->n_total);
+        if (!rc) rc = L->bufs.alloc(&a.okeys, (size_t)L->n_total);
+        if (!rc) rc = L->bufs.alloc(&a.ocnt, (size_t)L->K * 65536);
+        if (!rc) rc = fill_u32(a.ocnt, 0u, (int64_t)L->K * 65536, L->stream);
+        const SceneView& v = a.v;
+        a.klo = make_float3(v.org[0], v.org[1], v.org[2]);
+        a.kscale = make_float3(16.f / (v.hi[0] - v.org[0]), 16.f / (v.hi[1] - v.org[1]), 16.f / (v.hi[2] - v.org[2]));
+        a.order = order;
+    }
+    if (!rc) rc = launch_run(L, a);
     if (rc) {
         destroy_launch(L);
         return rc;

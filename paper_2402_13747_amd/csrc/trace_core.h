@@ -32,6 +32,10 @@ struct TraceArgs {
     const float* rx;
     const float* dirs;      // [n_rays][3] launch directions (the caller's, or the materialised Fibonacci lattice)
     const uint32_t* perm;   // null, or bounce-0 order of the directions
+    const uint32_t* order;  // null, or for bounces >= 1: slot i reads the previous bounce's output order[i]
+    uint16_t* okeys;        // with order: coherence bucket of each survivor written by a bounce
+    uint32_t* ocnt;         // with order: [K][65536] survivors per bucket, per bounce
+    float3 klo, kscale;     // bucket grid: origin and cells per metre (16 per axis over the grid)
     int32_t n_rx;
     int32_t K;
     uint32_t n_rays;
@@ -81,14 +85,21 @@ __device__ __forceinline__ uint64_t mspan_at(const SceneView& v, int lvl) {
 // level at which the path is empty, or TO + 1 when the level-TO node exists
 // (its index in `node`).  Quotients c / span[i] use the precomputed magics.
 template <bool STATS, int TO>
-__device__ __forceinline__ int descend(const SceneView& v, const int c[3], uint32_t& node, stat_t* cnt) {
+__device__ __forceinline__ int descend(const SceneView& v, const int c[3], uint32_t& node, int& skip0,
+                                       stat_t* cnt) {
     int p[3] = {span_div(c[0], v.mspan[0]), span_div(c[1], v.mspan[0]), span_div(c[2], v.mspan[0])};
-    const int32_t n0 = v.map0[p[0] + v.dim0[0] * (p[1] + v.dim0[1] * p[2])];
+    const size_t i0 = (size_t)p[0] + (size_t)v.dim0[0] * ((size_t)p[1] + (size_t)v.dim0[1] * p[2]);
+    // the level-0 node and the cell's skip radius are loaded together
+    const int32_t n0 = v.map0[i0];
+    const int d0 = v.dist0 ? (int)v.dist0[i0] : 1;
     if (STATS) {
         ++cnt[ST_NODES];
-        cnt[ST_BYTES] += 4;
+        cnt[ST_BYTES] += (n0 < 0 && v.dist0) ? 5 : 4;
     }
-    if (n0 < 0 || (uint32_t)n0 >= v.nn[0]) return 0;
+    if (n0 < 0 || (uint32_t)n0 >= v.nn[0]) {
+        skip0 = d0;
+        return 0;
+    }
     uint32_t n = (uint32_t)n0;
 #pragma unroll
     for (int i = 1; i <= TO; ++i) {
@@ -131,12 +142,27 @@ __device__ __forceinline__ void wave_sync() {
     __builtin_amdgcn_wave_barrier();
 }
 
-__device__ __forceinline__ int wave_incl_max(int x) {
-#pragma unroll
-    for (int off = 1; off < 64; off <<= 1) {
-        const int y = __shfl_up(x, off, 64);
-        if ((int)lane_id() >= off) x = max(x, y);
-    }
+// Inclusive wave64 scans on the VALU through DPP row shifts and row
+// broadcasts (no LDS round trips).  Every lane of the wave must be active.
+// Lanes shifted in from outside a row read 0, the identity of both scans
+// (max is used on non-negative values only).
+__device__ __forceinline__ uint32_t wave_scan_add_dpp(uint32_t x) {
+    x += (uint32_t)__builtin_amdgcn_update_dpp(0, (int)x, 0x111, 0xf, 0xf, true);   // row_shr:1
+    x += (uint32_t)__builtin_amdgcn_update_dpp(0, (int)x, 0x112, 0xf, 0xf, true);   // row_shr:2
+    x += (uint32_t)__builtin_amdgcn_update_dpp(0, (int)x, 0x114, 0xf, 0xf, true);   // row_shr:4
+    x += (uint32_t)__builtin_amdgcn_update_dpp(0, (int)x, 0x118, 0xf, 0xf, true);   // row_shr:8
+    x += (uint32_t)__builtin_amdgcn_update_dpp(0, (int)x, 0x142, 0xa, 0xf, false);  // row_bcast:15 -> rows 1, 3
+    x += (uint32_t)__builtin_amdgcn_update_dpp(0, (int)x, 0x143, 0xc, 0xf, false);  // row_bcast:31 -> rows 2, 3
+    return x;
+}
+
+__device__ __forceinline__ int wave_scan_max_dpp(int x) {
+    x = max(x, __builtin_amdgcn_update_dpp(0, x, 0x111, 0xf, 0xf, true));
+    x = max(x, __builtin_amdgcn_update_dpp(0, x, 0x112, 0xf, 0xf, true));
+    x = max(x, __builtin_amdgcn_update_dpp(0, x, 0x114, 0xf, 0xf, true));
+    x = max(x, __builtin_amdgcn_update_dpp(0, x, 0x118, 0xf, 0xf, true));
+    x = max(x, __builtin_amdgcn_update_dpp(0, x, 0x142, 0xa, 0xf, false));
+    x = max(x, __builtin_amdgcn_update_dpp(0, x, 0x143, 0xc, 0xf, false));
     return x;
 }
 
@@ -153,7 +179,7 @@ __device__ __forceinline__ void leaf_tests(const SceneView& v, LeafTestLds& W, b
                                            stat_t cnt[ST_COUNT]) {
     const uint32_t lane = lane_id();
     const uint32_t n = has ? r.y : 0u;
-    const uint32_t incl = wave_incl_scan(n);
+    const uint32_t incl = wave_scan_add_dpp(n);
     const uint32_t total = __builtin_amdgcn_readfirstlane(__shfl(incl, 63, 64));
     const uint32_t excl = incl - n;
     W.begin[lane] = r.x;
@@ -166,7 +192,7 @@ __device__ __forceinline__ void leaf_tests(const SceneView& v, LeafTestLds& W, b
         wave_sync();
         if (n && excl < base + 64 && incl > base) W.mark[excl > base ? excl - base : 0] = (int)lane;
         wave_sync();
-        const int own = wave_incl_max(W.mark[lane]);
+        const int own = wave_scan_max_dpp(W.mark[lane] + 1) - 1;  // marks + 1 >= 0
         const uint32_t pi = base + lane;
         bool ok = false;
         unsigned long long cand = 0;
@@ -218,6 +244,7 @@ struct Seg {
     int c[3];       // current leaf cell
     int cq[3];      // parent cell of the cached descent
     int cres;       // cached descent result
+    int cskip0;     // cached skip radius of an empty level-0 cell (cres == 0)
     uint32_t cnode; // cached parent node
     int it;         // DDA steps taken
 };
@@ -250,6 +277,7 @@ __device__ __forceinline__ bool seg_begin(const SceneView& v, const float o[3], 
         S.cq[a] = -1;
     }
     S.cres = 0;
+    S.cskip0 = 1;
     S.cnode = 0;
     S.it = 0;
     return t0 <= t1;
@@ -285,17 +313,21 @@ __device__ __forceinline__ void dda_step(const SceneView& v, LeafTestLds& W, boo
     constexpr int P = L - 2;  // level of the leaves' parents (-1: single-level grid)
     int* c = S.c;
     uint32_t node = 0;
-    int skip = 1;  // > 1: an empty cube of 2 skip - 1 leaves centred on c
-    int lvl = 0;   // level of the empty cell containing c, or L for an occupied leaf
+    int skip = 1;   // > 1: an empty cube of 2 skip - 1 units centred on the unit holding c
+    int unit = 1;   // edge of a skip unit in leaves (1, or a level-0 cell)
+    int lvl = 0;    // level of the empty cell containing c, or L for an occupied leaf
     if (walking) {
         if constexpr (P < 0) {
-            const int32_t n0 = v.map0[c[0] + v.dim0[0] * (c[1] + v.dim0[1] * c[2])];
+            const size_t i0 = (size_t)c[0] + (size_t)v.dim0[0] * ((size_t)c[1] + (size_t)v.dim0[1] * c[2]);
+            const int32_t n0 = v.map0[i0];
+            const int d0 = v.dist0 ? (int)v.dist0[i0] : 1;
             if (STATS) {
                 ++cnt[ST_NODES];
-                cnt[ST_BYTES] += 4;
+                cnt[ST_BYTES] += (n0 < 0 && v.dist0) ? 5 : 4;
             }
             lvl = (n0 < 0 || (uint32_t)n0 >= v.nn[0]) ? 0 : L;
             node = (uint32_t)n0;
+            if (lvl == 0) skip = max(1, d0);
         } else {
             // the descent from level 0 runs only when the parent cell changes
             const int q[3] = {span_div(c[0], v.mspan[P]), span_div(c[1], v.mspan[P]), span_div(c[2], v.mspan[P])};
@@ -303,28 +335,36 @@ __device__ __forceinline__ void dda_step(const SceneView& v, LeafTestLds& W, boo
                 S.cq[0] = q[0];
                 S.cq[1] = q[1];
                 S.cq[2] = q[2];
-                S.cres = descend<STATS, P>(v, c, S.cnode, cnt);
+                S.cres = descend<STATS, P>(v, c, S.cnode, S.cskip0, cnt);
             }
             if (S.cres <= P) {
                 lvl = S.cres;
+                if (lvl == 0) {
+                    // empty level-0 cell: the cube of radius cskip0 - 1 level-0 cells around it is empty
+                    skip = max(1, S.cskip0);
+                    unit = v.span[0];
+                }
             } else {
                 const int r = v.ratio[P];
                 const int loc = (c[0] - r * q[0]) + r * ((c[1] - r * q[1]) + r * (c[2] - r * q[2]));
                 const size_t wi = (size_t)S.cnode * v.nw[P] + (loc >> 6);
+                // the mask word, the word's child base and the leaf's skip radius are
+                // loaded together (one memory round trip); only one of the last two is used
                 const uint64_t w = v.mask[P][wi];
+                const uint32_t wbase = v.base[P][wi];
+                const int ld = v.ldist ? (int)v.ldist[(size_t)S.cnode * (size_t)(r * r * r) + loc] : 1;
                 const uint64_t bit = uint64_t(1) << (loc & 63);
                 if (STATS) {
                     ++cnt[ST_NODES];
-                    cnt[ST_BYTES] += (w & bit) ? 12 : 8;
+                    cnt[ST_BYTES] += (w & bit) ? 12 : (v.ldist ? 9 : 8);
                 }
                 lvl = L - 1;
                 if (w & bit) {
-                    node = v.base[P][wi] + (uint32_t)__popcll(w & (bit - 1));
+                    node = wbase + (uint32_t)__popcll(w & (bit - 1));
                     if (node < v.nn[L - 1]) lvl = L;
-                } else if (v.ldist) {
+                } else {
                     // empty leaf: the whole cube of radius skip - 1 around it is empty
-                    skip = max(1, (int)v.ldist[(size_t)S.cnode * (size_t)(r * r * r) + loc]);
-                    if (STATS) cnt[ST_BYTES] += 1;
+                    skip = max(1, ld);
                 }
             }
         }
@@ -362,8 +402,10 @@ __device__ __forceinline__ void dda_step(const SceneView& v, LeafTestLds& W, boo
 #pragma unroll
         for (int a = 0; a < 3; ++a) {
             if (skip > 1) {
-                lo[a] = c[a] - (skip - 1);
-                hi[a] = c[a] + skip;
+                // the skip cube, clipped to the grid (beyond it the ray leaves)
+                const int uc = (unit == 1) ? c[a] : span_div(c[a], v.mspan[0]);
+                lo[a] = max((uc - (skip - 1)) * unit, 0);
+                hi[a] = min((uc + skip) * unit, v.dim[a]);
             } else {
                 lo[a] = (Sz == 1) ? c[a] : span_div(c[a], mspan_at<NL>(v, lvl)) * Sz;
                 hi[a] = lo[a] + Sz;
@@ -443,17 +485,55 @@ __device__ __forceinline__ bool load_ray(const TraceArgs& a, int b, uint32_t i, 
         d[2] *= inv;
         return true;
     }
-    g = a.buf_g[(b & 1) ^ 1][i];
+    const uint32_t src = a.order ? a.order[i] : i;  // coherence order (never with in-place bounces)
+    g = a.buf_g[(b & 1) ^ 1][src];
     if (g == NO_HIT) {
         // the last bounce (b == K) has no output buffers (they may be unallocated)
         if (in_place && b < a.K) a.buf_g[b & 1][i] = NO_HIT;
         return false;
     }
-    const float4 o4 = a.buf_o[(b & 1) ^ 1][i];
-    const float4 d4 = a.buf_d[(b & 1) ^ 1][i];
+    const float4 o4 = a.buf_o[(b & 1) ^ 1][src];
+    const float4 d4 = a.buf_d[(b & 1) ^ 1][src];
     o[0] = o4.x; o[1] = o4.y; o[2] = o4.z; L = o4.w;
     d[0] = d4.x; d[1] = d4.y; d[2] = d4.z; last = __float_as_uint(d4.w);
     return true;
+}
+
+// Octahedral map of a unit direction onto [-1, 1]^2.
+__device__ __forceinline__ void octahedral(float x, float y, float z, float& u, float& w) {
+    const float s = fabsf(x) + fabsf(y) + fabsf(z);
+    u = s > 0.f ? x / s : 0.f;
+    w = s > 0.f ? y / s : 0.f;
+    if (z < 0.f) {
+        const float uu = (1.f - fabsf(w)) * (u >= 0.f ? 1.f : -1.f);
+        const float ww = (1.f - fabsf(u)) * (w >= 0.f ? 1.f : -1.f);
+        u = uu;
+        w = ww;
+    }
+}
+
+__device__ __forceinline__ uint32_t cell_of(float u, int cells) {
+    return (uint32_t)fminf(fmaxf((u * 0.5f + 0.5f) * (float)cells, 0.f), (float)(cells - 1));
+}
+
+__device__ __forceinline__ uint32_t spread_bits4x3(uint32_t x) {
+    x &= 15u;
+    x = (x | (x << 4)) & 0x0C3u;
+    x = (x | (x << 2)) & 0x249u;
+    return x;
+}
+
+// Coherence bucket of a ray: Morton code of its origin on a 16^3 grid over the
+// scene (12 bits), then the 4 x 4 octahedral cell of its direction (4 bits).
+// Rays that start close together in similar directions walk the same cells.
+__device__ __forceinline__ uint32_t ray_bucket(const TraceArgs& a, const float o[3], const float d[3]) {
+    const uint32_t cx = (uint32_t)fminf(fmaxf((o[0] - a.klo.x) * a.kscale.x, 0.f), 15.f);
+    const uint32_t cy = (uint32_t)fminf(fmaxf((o[1] - a.klo.y) * a.kscale.y, 0.f), 15.f);
+    const uint32_t cz = (uint32_t)fminf(fmaxf((o[2] - a.klo.z) * a.kscale.z, 0.f), 15.f);
+    float u, w;
+    octahedral(d[0], d[1], d[2], u, w);
+    const uint32_t m = spread_bits4x3(cx) | (spread_bits4x3(cy) << 1) | (spread_bits4x3(cz) << 2);
+    return (m << 4) | (cell_of(u, 4) << 2) | cell_of(w, 4);
 }
 
 // End of the segments of lanes with `done`: log the hit, test every RX on
@@ -534,6 +614,11 @@ __device__ __forceinline__ void finish_segment(const TraceArgs& a, int b, bool d
         a.buf_g[b & 1][slot] = g;
     } else if (done && in_place) {
         a.buf_g[b & 1][i] = NO_HIT;
+    }
+    if (a.okeys && m) {  // compacted survivors only (never in place)
+        const uint32_t key = surv ? ray_bucket(a, o, d) : 0u;
+        if (surv) a.okeys[slot] = (uint16_t)key;
+        (void)wave_bucket_add(a.ocnt + (size_t)b * 65536, key, surv);
     }
 }
 

@@ -243,6 +243,23 @@ def test_stats_per_bounce(env):
     assert st["hits"] <= st["segments"] and st["leaves_visited"] <= st["dda_steps"]
 
 
+def test_coherence_order_invariance(env):
+    """Large launches trace their bounces in re-sorted coherent orders; results equal the plain order's."""
+    torch, pcrl, oracle = env
+    s = scenes.furnished_room(n_points=200_000, seed=7, n_rx=6, n_rays=150_000, K=3)
+    scene = pcrl.build_voxels(s.xyz, s.normal, s.label, s.levels, _f32(s.surfel_radius), t_eps=_f32(parity.t_eps_of(s)))
+    runs = []
+    for coherent in (True, False):
+        L = pcrl.launch_rays(scene, s.tx, s.rx, n_rays=s.n_rays, max_reflections=3, coherent=coherent, hit_log=True)
+        p = parity.to_numpy(pcrl.collect_paths(L, kappa=1 << 30))
+        runs.append((L.hit_log[0].cpu().numpy(), L.hit_log[1].cpu().numpy(), p, L.stats()["active"]))
+    (h1, t1, p1, a1), (h2, t2, p2, a2) = runs
+    assert a1 == a2 and a1[3] > 0
+    assert np.array_equal(h1, h2) and np.array_equal(t1, t2, equal_nan=True)
+    for k in ("tx", "rx", "n_refl", "key", "count", "rank", "ray", "len_poly", "len_unf", "points"):
+        assert np.array_equal(np.asarray(p1[k]), np.asarray(p2[k]), equal_nan=True), k
+
+
 def test_determinism_and_permutation(env):
     torch, pcrl, oracle = env
     s = scenes.random_scene(7, tilt_sigma=0.05, n_rays=4000)
