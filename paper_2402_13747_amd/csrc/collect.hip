@@ -194,6 +194,188 @@ __global__ void k_write_rows(const uint4* rec, const float4* hist, const uint64_
     }
 }
 
+// ---------------------------------------------------------------------------
+// small record sets: the whole collection in one workgroup
+// ---------------------------------------------------------------------------
+//
+// A launch usually yields few reception records (hundreds to a few
+// thousand).  Then keys, the (key, len_poly, ray) sort (bitonic, in LDS),
+// key boundaries, counts, ranks and the row compaction run in one kernel of
+// one workgroup: one launch instead of some fifty small ones.
+
+constexpr int SMALL_N = 2048;      // records (power of two)
+constexpr int SMALL_BLOCK = 1024;  // threads; each owns positions 2t and 2t + 1
+constexpr int SMALL_W = 2;         // key words
+
+__device__ __forceinline__ uint32_t block_incl_scan_small(uint32_t x, uint32_t* wsum, uint32_t* total) {
+    const int w = threadIdx.x >> 6;
+    const uint32_t incl = wave_incl_scan(x);
+    if (lane_id() == 63) wsum[w] = incl;
+    __syncthreads();
+    uint32_t off = 0, tot = 0;
+#pragma unroll
+    for (int k = 0; k < SMALL_BLOCK / 64; ++k) {
+        const uint32_t v = wsum[k];
+        off += (k < w) ? v : 0u;
+        tot += v;
+    }
+    __syncthreads();
+    *total = tot;
+    return off + incl;
+}
+
+__global__ __launch_bounds__(SMALL_BLOCK) void k_collect_small(const uint4* rec, uint32_t n, const float4* hist,
+                                                               KeySpec ks, int32_t kappa, int64_t capacity,
+                                                               OutArrays o, uint32_t* tots) {
+    __shared__ uint64_t sw[SMALL_W][SMALL_N];
+    __shared__ uint32_t slp[SMALL_N];
+    __shared__ uint32_t sray[SMALL_N];
+    __shared__ uint16_t sidx[SMALL_N];
+    __shared__ uint16_t sstart[SMALL_N];
+    __shared__ uint32_t wsum[SMALL_BLOCK / 64];
+    const uint32_t t = threadIdx.x;
+    uint32_t n2 = 1;
+    while (n2 < n) n2 <<= 1;
+    // 1. keys (as k_path_keys)
+    for (uint32_t i = t; i < n2; i += SMALL_BLOCK) {
+        sidx[i] = (uint16_t)i;
+        if (i >= n) continue;
+        const uint4 r = rec[i];
+        const uint32_t g = r.x;
+        const uint32_t b = r.y >> 16;
+        uint64_t w[MAXW] = {0, 0, 0, 0, 0, 0};
+        for (int k = 0; k < ks.K; ++k) {
+            uint64_t val = 0;
+            if ((uint32_t)k < b) {
+                const float4 h = hist[(size_t)k * ks.n_total + g];
+                if (ks.mode == PCRL_KEY_LABELS) {
+                    val = (uint64_t)__float_as_uint(h.w) + 1;
+                } else {
+                    const float pp[3] = {h.x, h.y, h.z};
+                    int64_t c[3];
+                    for (int a = 0; a < 3; ++a) {
+                        int ci = (int)floorf((pp[a] - ks.org[a]) * ks.inv_h);
+                        c[a] = min(max(ci, 0), ks.dim[a] - 1);
+                    }
+                    val = (uint64_t)(c[0] + (int64_t)ks.dim[0] * (c[1] + (int64_t)ks.dim[1] * c[2])) + 1;
+                }
+            }
+            put_bits(w, (ks.K - 1 - k) * ks.bl, ks.bl, val);
+        }
+        int pos = ks.K * ks.bl;
+        put_bits(w, pos, ks.bb, b);
+        pos += ks.bb;
+        put_bits(w, pos, ks.br, r.y & 0xFFFFu);
+        pos += ks.br;
+        put_bits(w, pos, ks.bt, g / ks.n_rays);
+        sw[0][i] = w[0];
+        sw[1][i] = w[1];
+        slp[i] = r.z;
+        sray[i] = g;
+    }
+    __syncthreads();
+    // 2. bitonic sort of the record indices by (key words, len_poly bits, ray); padding last
+    auto less = [&](uint32_t a, uint32_t b) -> bool {
+        if (a >= n) return false;
+        if (b >= n) return true;
+        for (int q = ks.W - 1; q >= 0; --q)
+            if (sw[q][a] != sw[q][b]) return sw[q][a] < sw[q][b];
+        if (slp[a] != slp[b]) return slp[a] < slp[b];
+        return sray[a] < sray[b];
+    };
+    for (uint32_t k = 2; k <= n2; k <<= 1) {
+        for (uint32_t j = k >> 1; j > 0; j >>= 1) {
+            for (uint32_t i = t; i < n2; i += SMALL_BLOCK) {
+                const uint32_t l = i ^ j;
+                if (l > i) {
+                    const uint32_t a = sidx[i], b = sidx[l];
+                    const bool up = (i & k) == 0;
+                    if (up ? less(b, a) : less(a, b)) {
+                        sidx[i] = (uint16_t)b;
+                        sidx[l] = (uint16_t)a;
+                    }
+                }
+            }
+            __syncthreads();
+        }
+    }
+    // 3. key boundaries, key index, first position of each key
+    auto same_key = [&](uint32_t p) -> bool {  // sorted position p (> 0) has the key of p - 1
+        const uint32_t a = sidx[p], b = sidx[p - 1];
+        for (int q = 0; q < ks.W; ++q)
+            if (sw[q][a] != sw[q][b]) return false;
+        return true;
+    };
+    const uint32_t p0 = 2 * t, p1 = 2 * t + 1;
+    const bool f0 = p0 < n && (p0 == 0 || !same_key(p0));
+    const bool f1 = p1 < n && !same_key(p1);
+    uint32_t n_keys = 0;
+    const uint32_t kin = block_incl_scan_small((f0 ? 1u : 0u) + (f1 ? 1u : 0u), wsum, &n_keys);
+    const uint32_t key1 = kin - 1;                     // key index of p1
+    const uint32_t key0 = kin - (f1 ? 1u : 0u) - 1;    // key index of p0
+    if (f0) sstart[key0] = (uint16_t)p0;
+    if (f1) sstart[key1] = (uint16_t)p1;
+    __syncthreads();
+    // 4. ranks inside keys, kept rows
+    const bool k0 = p0 < n && p0 - sstart[key0] < (uint32_t)kappa;
+    const bool k1 = p1 < n && p1 - sstart[key1] < (uint32_t)kappa;
+    uint32_t n_rows = 0;
+    const uint32_t rin = block_incl_scan_small((k0 ? 1u : 0u) + (k1 ? 1u : 0u), wsum, &n_rows);
+    if (t == 0) {
+        tots[0] = n_keys;
+        tots[1] = n_rows;
+    }
+    if ((int64_t)n_rows > capacity) return;  // the host reports the overflow
+    // 5. rows (rows before this thread's: rin minus its own kept rows)
+    const uint32_t rbase = rin - (k0 ? 1u : 0u) - (k1 ? 1u : 0u);
+    for (int e = 0; e < 2; ++e) {
+        const uint32_t p = e ? p1 : p0;
+        const bool keep = e ? k1 : k0;
+        if (!keep) continue;
+        const uint32_t key = e ? key1 : key0;
+        const uint32_t row = e ? rbase + (k0 ? 1u : 0u) : rbase;
+        const uint32_t first = sstart[key];
+        const uint32_t end = (key + 1 < n_keys) ? sstart[key + 1] : n;
+        const uint4 r = rec[sidx[p]];
+        const uint32_t g = r.x;
+        const uint32_t b = r.y >> 16;
+        if (o.tx) o.tx[row] = (int32_t)(g / ks.n_rays);
+        if (o.rx) o.rx[row] = (int32_t)(r.y & 0xFFFFu);
+        if (o.n_refl) o.n_refl[row] = (int32_t)b;
+        if (o.count) o.count[row] = (int64_t)(end - first);
+        if (o.rank) o.rank[row] = (int32_t)(p - first);
+        if (o.ray) o.ray[row] = (int64_t)g;
+        if (o.len_poly) o.len_poly[row] = __uint_as_float(r.z);
+        if (o.len_unf) o.len_unf[row] = __uint_as_float(r.w);
+        for (int k = 0; k < ks.K; ++k) {
+            float4 h = make_float4(NAN, NAN, NAN, 0.f);
+            if ((uint32_t)k < b) h = hist[(size_t)k * ks.n_total + g];
+            if (o.key) {
+                int64_t kv = -1;
+                if ((uint32_t)k < b) {
+                    if (ks.mode == PCRL_KEY_LABELS) {
+                        kv = (int64_t)__float_as_uint(h.w);
+                    } else {
+                        int64_t c[3];
+                        const float pp[3] = {h.x, h.y, h.z};
+                        for (int a = 0; a < 3; ++a) {
+                            int ci = (int)floorf((pp[a] - ks.org[a]) * ks.inv_h);
+                            c[a] = min(max(ci, 0), ks.dim[a] - 1);
+                        }
+                        kv = c[0] + (int64_t)ks.dim[0] * (c[1] + (int64_t)ks.dim[1] * c[2]);
+                    }
+                }
+                o.key[(size_t)row * ks.K + k] = kv;
+            }
+            if (o.points) {
+                o.points[((size_t)row * ks.K + k) * 3 + 0] = h.x;
+                o.points[((size_t)row * ks.K + k) * 3 + 1] = h.y;
+                o.points[((size_t)row * ks.K + k) * 3 + 2] = h.z;
+            }
+        }
+    }
+}
+
 static int bits_for(uint64_t max_value) {
     int b = 1;
     while (b < 64 && (max_value >> b) != 0) ++b;
@@ -254,6 +436,29 @@ static int collect_impl(PcrlLaunch* L, int32_t kappa, int32_t key_mode, PcrlPath
     DevBufs T;
     T.stream = s;
     auto fail = [&](int code) { T.release(); return code; };
+    OutArrays oa{out->tx, out->rx, out->n_refl, out->key, out->count, out->rank, out->ray, out->len_poly, out->len_unf,
+                 out->points};
+    if (n <= (uint32_t)SMALL_N && ks.W <= SMALL_W) {
+        uint32_t* tots = nullptr;
+        int rc = T.alloc(&tots, 2);
+        if (rc) return fail(rc);
+        hipLaunchKernelGGL(k_collect_small, dim3(1), dim3(SMALL_BLOCK), 0, s, L->rec, n, L->hist, ks, kappa,
+                           out->capacity, oa, tots);
+        uint32_t host[2] = {0, 0};
+        if (hipGetLastError() != hipSuccess || hipMemcpyAsync(host, tots, 8, hipMemcpyDeviceToHost, s) != hipSuccess ||
+            hipStreamSynchronize(s) != hipSuccess) {
+            set_error("collect_paths: kernel failed: %s", hipGetErrorString(hipGetLastError()));
+            return fail(PCRL_EHIP);
+        }
+        out->n_keys = host[0];
+        out->n_rows = host[1];
+        T.release();
+        if ((int64_t)host[1] > out->capacity) {
+            set_error("collect_paths: %u rows do not fit in capacity %lld", host[1], (long long)out->capacity);
+            return PCRL_EOVERFLOW;
+        }
+        return PCRL_OK;
+    }
     uint64_t *words = nullptr, *tmp64 = nullptr;
     uint32_t *lp = nullptr, *ray = nullptr, *perm = nullptr, *tmp32 = nullptr, *kscan = nullptr, *start = nullptr,
              *keep = nullptr, *tots = nullptr;
@@ -291,8 +496,6 @@ static int collect_impl(PcrlLaunch* L, int32_t kappa, int32_t key_mode, PcrlPath
         set_error("collect_paths: %u rows do not fit in capacity %lld", host[1], (long long)out->capacity);
         return fail(PCRL_EOVERFLOW);
     }
-    OutArrays oa{out->tx, out->rx, out->n_refl, out->key, out->count, out->rank, out->ray, out->len_poly, out->len_unf,
-                 out->points};
     hipLaunchKernelGGL(k_write_rows, dim3(nblk(n)), dim3(256), 0, s, L->rec, L->hist, words, ks.W, perm, n, kscan,
                        start, tots, keep, kappa, ks, oa);
     if (hipGetLastError() != hipSuccess || hipStreamSynchronize(s) != hipSuccess) {
