@@ -427,21 +427,57 @@ static int radix_sort_impl(K* keys, uint32_t* vals, int64_t n, int bits, hipStre
 // bucket order: items grouped by a 16-bit key, any order inside a bucket
 // ---------------------------------------------------------------------------
 
+// Counting pass: one atomic per item (neighbouring keys rarely repeat here);
+// pos[j] = the item's position among its bucket's items.
 __global__ __launch_bounds__(256) void k_bucket_count(const uint16_t* keys, uint32_t n_max, const uint32_t* n_dev,
-                                                      uint32_t* cnt) {
+                                                      uint32_t* cnt, uint32_t* pos) {
     const uint32_t j = blockIdx.x * blockDim.x + threadIdx.x;
     const uint32_t n = n_dev ? min(*n_dev, n_max) : n_max;
-    const bool valid = j < n;
-    (void)wave_bucket_add(cnt, valid ? keys[j] : 0u, valid);
+    if (j < n) pos[j] = atomicAdd(&cnt[keys[j]], 1u);
 }
 
-__global__ __launch_bounds__(256) void k_bucket_place(const uint16_t* keys, uint32_t n_max, const uint32_t* n_dev,
-                                                      uint32_t* cursor, uint32_t* order) {
+// In-place exclusive scan of the 65536 bucket counts in one workgroup.
+constexpr int BUCKET_SCAN_BLOCK = 1024;
+__global__ __launch_bounds__(BUCKET_SCAN_BLOCK) void k_bucket_scan(uint32_t* cnt) {
+    constexpr int PER = 65536 / BUCKET_SCAN_BLOCK;
+    __shared__ uint32_t wsum[BUCKET_SCAN_BLOCK / 64];
+    uint32_t v[PER];
+    uint32_t acc = 0;
+    const size_t first = (size_t)threadIdx.x * PER;
+#pragma unroll
+    for (int k = 0; k < PER; ++k) {
+        v[k] = cnt[first + k];
+        acc += v[k];
+    }
+    const int w = threadIdx.x >> 6;
+    const uint32_t incl = wave_incl_scan(acc);
+    if (lane_id() == 63) wsum[w] = incl;
+    __syncthreads();
+    uint32_t run = incl - acc;
+    for (int k = 0; k < w; ++k) run += wsum[k];
+#pragma unroll
+    for (int k = 0; k < PER; ++k) {
+        cnt[first + k] = run;
+        run += v[k];
+    }
+}
+
+__global__ __launch_bounds__(256) void k_bucket_scatter(const uint16_t* keys, const uint32_t* pos, uint32_t n_max,
+                                                        const uint32_t* n_dev, const uint32_t* start,
+                                                        uint32_t* order) {
     const uint32_t j = blockIdx.x * blockDim.x + threadIdx.x;
     const uint32_t n = n_dev ? min(*n_dev, n_max) : n_max;
-    const bool valid = j < n;
-    const uint32_t pos = wave_bucket_add(cursor, valid ? keys[j] : 0u, valid);
-    if (valid) order[pos] = j;
+    if (j < n) order[start[keys[j]] + pos[j]] = j;
+}
+
+int bucket_place_u16(const uint16_t* keys, const uint32_t* pos, int64_t n_max, const uint32_t* n_dev, uint32_t* cnt,
+                     uint32_t* order, hipStream_t s) {
+    if (n_max <= 0) return PCRL_OK;
+    hipLaunchKernelGGL(k_bucket_scan, dim3(1), dim3(BUCKET_SCAN_BLOCK), 0, s, cnt);
+    hipLaunchKernelGGL(k_bucket_scatter, dim3((unsigned)((n_max + 255) / 256)), dim3(256), 0, s, keys, pos,
+                       (uint32_t)n_max, n_dev, (const uint32_t*)cnt, order);
+    PCRL_TRY_HIP(hipGetLastError());
+    return PCRL_OK;
 }
 
 int bucket_order_u16(const uint16_t* keys, int64_t n_max, const uint32_t* n_dev, uint32_t* order, hipStream_t s) {
@@ -450,32 +486,20 @@ int bucket_order_u16(const uint16_t* keys, int64_t n_max, const uint32_t* n_dev,
         set_error("bucket order of %lld items exceeds the 32-bit index range", (long long)n_max);
         return PCRL_EINVAL;
     }
-    uint32_t* cnt = nullptr;
+    uint32_t *cnt = nullptr, *pos = nullptr;
     PCRL_TRY(dalloc((void**)&cnt, (size_t)65536 * sizeof(uint32_t), s));
-    const unsigned grid = (unsigned)((n_max + 255) / 256);
-    int rc = fill_u32(cnt, 0u, 65536, s);
+    int rc = dalloc((void**)&pos, (size_t)n_max * sizeof(uint32_t), s);
+    if (!rc) rc = fill_u32(cnt, 0u, 65536, s);
     if (!rc) {
-        hipLaunchKernelGGL(k_bucket_count, dim3(grid), dim3(256), 0, s, keys, (uint32_t)n_max, n_dev, cnt);
+        hipLaunchKernelGGL(k_bucket_count, dim3((unsigned)((n_max + 255) / 256)), dim3(256), 0, s, keys,
+                           (uint32_t)n_max, n_dev, cnt, pos);
         rc = hipGetLastError() == hipSuccess ? PCRL_OK : PCRL_EHIP;
     }
-    if (!rc) rc = scan_u32(cnt, cnt, 65536, nullptr, s);
-    if (!rc) {
-        hipLaunchKernelGGL(k_bucket_place, dim3(grid), dim3(256), 0, s, keys, (uint32_t)n_max, n_dev, cnt, order);
-        rc = hipGetLastError() == hipSuccess ? PCRL_OK : PCRL_EHIP;
-    }
+    if (!rc) rc = bucket_place_u16(keys, pos, n_max, n_dev, cnt, order, s);
     if (rc == PCRL_EHIP) set_error("bucket order kernel failed: %s", hipGetErrorString(hipGetLastError()));
+    dfree(pos, s);
     dfree(cnt, s);
     return rc;
-}
-
-int bucket_place_u16(const uint16_t* keys, int64_t n_max, const uint32_t* n_dev, uint32_t* cnt, uint32_t* order,
-                     hipStream_t s) {
-    if (n_max <= 0) return PCRL_OK;
-    PCRL_TRY(scan_u32(cnt, cnt, 65536, nullptr, s));
-    hipLaunchKernelGGL(k_bucket_place, dim3((unsigned)((n_max + 255) / 256)), dim3(256), 0, s, keys, (uint32_t)n_max,
-                       n_dev, cnt, order);
-    PCRL_TRY_HIP(hipGetLastError());
-    return PCRL_OK;
 }
 
 int radix_sort_u64(uint64_t* keys, uint32_t* vals, int64_t n, int bits, hipStream_t s) {

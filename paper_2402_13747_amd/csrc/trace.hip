@@ -308,7 +308,7 @@ static int launch_run(PcrlLaunch* L, const TraceArgs& a) {
         if (timing) PCRL_TRY_HIP(hipEventRecord(L->events[2 * b + 1], s));
         if (a.order && b < K) {
             // the bounce kernel wrote each survivor's bucket and counted the buckets
-            PCRL_TRY(bucket_place_u16(a.okeys, n_total, a.counters + b + 1, a.ocnt + (size_t)b * 65536,
+            PCRL_TRY(bucket_place_u16(a.okeys, a.opos, n_total, a.counters + b + 1, a.ocnt + (size_t)b * 65536,
                                       const_cast<uint32_t*>(a.order), s));
         }
     }
@@ -336,6 +336,7 @@ extern "C" int launch_rays(const PcrlScene* scene, const float* tx, int32_t n_tx
         uint32_t* order = nullptr;
         rc = L->bufs.alloc(&order, (size_t)L->n_total);
         if (!rc) rc = L->bufs.alloc(&a.okeys, (size_t)L->n_total);
+        if (!rc) rc = L->bufs.alloc(&a.opos, (size_t)L->n_total);
         if (!rc) rc = L->bufs.alloc(&a.ocnt, (size_t)L->K * 65536);
         if (!rc) rc = fill_u32(a.ocnt, 0u, (int64_t)L->K * 65536, L->stream);
         const SceneView& v = a.v;

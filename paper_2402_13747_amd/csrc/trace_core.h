@@ -34,6 +34,7 @@ struct TraceArgs {
     const uint32_t* perm;   // null, or bounce-0 order of the directions
     const uint32_t* order;  // null, or for bounces >= 1: slot i reads the previous bounce's output order[i]
     uint16_t* okeys;        // with order: coherence bucket of each survivor written by a bounce
+    uint32_t* opos;         // with order: the survivor's position among its bucket's survivors
     uint32_t* ocnt;         // with order: [K][65536] survivors per bucket, per bounce
     float3 klo, kscale;     // bucket grid: origin and cells per metre (16 per axis over the grid)
     int32_t n_rx;
@@ -617,8 +618,11 @@ __device__ __forceinline__ void finish_segment(const TraceArgs& a, int b, bool d
     }
     if (a.okeys && m) {  // compacted survivors only (never in place)
         const uint32_t key = surv ? ray_bucket(a, o, d) : 0u;
-        if (surv) a.okeys[slot] = (uint16_t)key;
-        (void)wave_bucket_add(a.ocnt + (size_t)b * 65536, key, surv);
+        const uint32_t pos = wave_bucket_add(a.ocnt + (size_t)b * 65536, key, surv);
+        if (surv) {
+            a.okeys[slot] = (uint16_t)key;
+            a.opos[slot] = pos;
+        }
     }
 }
 
