@@ -501,7 +501,9 @@ def main():
     if algo is not None:
         out["trace_stats"] = {k: algo[k] for k in ("segments", "dda_steps", "leaves_visited", "node_lookups",
                                                    "surfel_tests", "hits", "records", "active", "empty_leaf_steps",
-                                                   "uniform_leaf_visits", "wave_dda_iters", "wave_test_iters")}
+                                                   "uniform_leaf_visits", "wave_dda_iters", "wave_test_iters",
+                                                   "dda_steps_bounce", "surfel_tests_bounce", "wave_dda_bounce",
+                                                   "algo_bytes_bounce")}
         out["trace_stats"]["dda_lane_efficiency"] = round(algo["dda_steps"] / max(64 * algo["wave_dda_iters"], 1), 4)
         out["trace_stats"]["test_lane_efficiency"] = round(algo["surfel_tests"] / max(64 * algo["wave_test_iters"], 1), 4)
     print(json.dumps(out), flush=True)

@@ -171,6 +171,9 @@ typedef struct {
     int64_t wave_dda_iters;                        /* DDA loop iterations per wave, summed over waves */
     int64_t wave_test_iters;                       /* surfel-test loop iterations per wave, summed over waves */
     int64_t algo_bytes_bounce[PCRL_MAX_REFLECTIONS + 1];  /* algo_bytes of each bounce kernel */
+    int64_t dda_steps_bounce[PCRL_MAX_REFLECTIONS + 1];   /* dda_steps of each bounce */
+    int64_t surfel_tests_bounce[PCRL_MAX_REFLECTIONS + 1];  /* surfel_tests of each bounce */
+    int64_t wave_dda_bounce[PCRL_MAX_REFLECTIONS + 1];    /* wave_dda_iters of each bounce */
     /* PCRL_LAUNCH_TIMING only (else 0) */
     float   kernel_ms[PCRL_MAX_REFLECTIONS + 1];   /* trace kernel time per bounce */
     float   total_ms;                              /* first to last trace kernel */

@@ -180,7 +180,8 @@ class Launch:
             out[name] = list(v) if hasattr(v, "__len__") else v
         out["active"] = out["active"][: self.K + 1]
         out["kernel_ms"] = out["kernel_ms"][: self.K + 1]
-        out["algo_bytes_bounce"] = out["algo_bytes_bounce"][: self.K + 1]
+        for k in ("algo_bytes_bounce", "dda_steps_bounce", "surfel_tests_bounce", "wave_dda_bounce"):
+            out[k] = out[k][: self.K + 1]
         return out
 
     def records(self) -> dict:

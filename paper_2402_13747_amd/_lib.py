@@ -63,6 +63,9 @@ class PcrlLaunchStats(C.Structure):
                 ("hits", C.c_int64), ("algo_bytes", C.c_int64), ("empty_leaf_steps", C.c_int64),
                 ("uniform_leaf_visits", C.c_int64), ("wave_dda_iters", C.c_int64), ("wave_test_iters", C.c_int64),
                 ("algo_bytes_bounce", C.c_int64 * (MAX_REFLECTIONS + 1)),
+                ("dda_steps_bounce", C.c_int64 * (MAX_REFLECTIONS + 1)),
+                ("surfel_tests_bounce", C.c_int64 * (MAX_REFLECTIONS + 1)),
+                ("wave_dda_bounce", C.c_int64 * (MAX_REFLECTIONS + 1)),
                 ("kernel_ms", C.c_float * (MAX_REFLECTIONS + 1)),
                 ("total_ms", C.c_float)]
 

@@ -384,6 +384,9 @@ extern "C" int launch_stats(PcrlLaunch* L, PcrlLaunchStats* out) {
     for (int b = 0; b <= K; ++b) {
         for (int k = 0; k < PCRL_NSTATS; ++k) st[k] += stb[b][k];
         out->algo_bytes_bounce[b] = (int64_t)stb[b][ST_BYTES];
+        out->dda_steps_bounce[b] = (int64_t)stb[b][ST_DDA];
+        out->surfel_tests_bounce[b] = (int64_t)stb[b][ST_TESTS];
+        out->wave_dda_bounce[b] = (int64_t)stb[b][ST_WAVE_DDA];
     }
     out->rays = L->n_total;
     out->active[0] = L->n_total;
