@@ -312,6 +312,9 @@ __global__ __launch_bounds__(BUILD_BLOCK) void k_brick_dist(const uint64_t* mask
 // nearest occupied cell only lowers the result (conservative).
 constexpr int DIST0_CAP = 15;
 
+// Largest dense cell table built (beyond it the traversal reads the bricks' masks).
+constexpr int64_t CELL_TABLE_MAX_BYTES = (int64_t)16 << 30;
+
 __global__ void k_dist0_pass(const int32_t* map0, const uint8_t* in, uint8_t* out, int dx, int dy, int dz, int axis) {
     const int64_t c = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
     const int64_t n = (int64_t)dx * dy * dz;
@@ -328,6 +331,24 @@ __global__ void k_dist0_pass(const int32_t* map0, const uint8_t* in, uint8_t* ou
         m = min(m, max(abs(t), a));
     }
     out[c] = (uint8_t)min(m, DIST0_CAP + 1);
+}
+
+// Dense cell table of the leaves' parent bricks: one 8-byte load per DDA
+// step gives an occupied leaf's entry range, or an empty leaf's skip radius.
+__global__ void k_brick_cells(const uint64_t* mask, const uint32_t* base, const uint2* leaf, const uint8_t* ldist,
+                              int nw, int r3, int64_t n_bricks, uint2* cells) {
+    const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (i >= n_bricks * r3) return;
+    const int64_t P = i / r3;
+    const int c = (int)(i - P * r3);
+    const size_t wi = (size_t)P * nw + (c >> 6);
+    const uint64_t w = mask[wi];
+    const uint64_t bit = uint64_t(1) << (c & 63);
+    if (w & bit) {
+        cells[i] = leaf[base[wi] + (uint32_t)__popcll(w & (bit - 1))];
+    } else {
+        cells[i] = make_uint2(ldist ? (uint32_t)ldist[i] : 1u, 0u);
+    }
 }
 
 __global__ void k_leaf_counts(uint2* leaf, int64_t n_leaves, int64_t m) {
@@ -568,6 +589,23 @@ static int build_hierarchy(const float* xyz, const float4* unit_nrm, const uint3
         hb.bytes += (int64_t)host_nodes[L - 2] * (int64_t)n3;
     }
 
+    // dense cell table of the leaves' parent bricks (needs the leaf ranges: after k_leaf_counts)
+    v.cells = nullptr;
+    if (L >= 2 && host_nodes[L - 2] > 0) {
+        const int r = v.ratio[L - 2];
+        const int64_t r3 = (int64_t)r * r * r;
+        const int64_t n_cells = (int64_t)host_nodes[L - 2] * r3;
+        if (n_cells * 8 <= CELL_TABLE_MAX_BYTES) {
+            uint2* cells = nullptr;
+            if ((rc = B.alloc(&cells, (size_t)n_cells))) return rc;
+            hipLaunchKernelGGL(k_brick_cells, dim3(blocks_for(n_cells)), dim3(BUILD_BLOCK), 0, s, ho.mask[L - 2],
+                               (const uint32_t*)v.base[L - 2], (const uint2*)leaf, v.ldist, v.nw[L - 2], (int)r3,
+                               (int64_t)host_nodes[L - 2], cells);
+            v.cells = cells;
+            hb.bytes += n_cells * 8;
+        }
+    }
+
     // empty-space skip radii of the level-0 grid
     {
         uint8_t *d0 = nullptr, *tmp = nullptr;
@@ -710,6 +748,7 @@ static int overlay_impl(PcrlScene* S, const uint32_t* gid, const float* xyz, con
     v.leaf = nullptr;
     v.ldist = nullptr;
     v.dist0 = nullptr;
+    v.cells = nullptr;
     v.spos = v.snrm = nullptr;
     HierBuild hb;
     if ((rc = build_hierarchy(xyz, unit_nrm, label, gid, n, s, v, ov->bufs, T, hb))) return fail(rc);

@@ -193,6 +193,8 @@ struct SceneView {
     const uint2* leaf;               // per leaf: (first entry, entry count)
     const uint8_t* ldist;            // null, or per leaf cell of each parent brick its empty-space skip radius
     const uint8_t* dist0;            // null, or per level-0 cell its empty-space skip radius (level-0 cells)
+    const uint2* cells;              // null, or per leaf cell of every parent brick: (first entry, count) of
+                                     // an occupied leaf, or (skip radius, 0) of an empty one
     const float4* spos;              // per entry: x, y, z, point id (bits)
     const float4* snrm;              // per entry: unit normal, label (bits)
 };

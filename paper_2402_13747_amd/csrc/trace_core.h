@@ -314,6 +314,7 @@ __device__ __forceinline__ void dda_step(const SceneView& v, LeafTestLds& W, boo
     constexpr int P = L - 2;  // level of the leaves' parents (-1: single-level grid)
     int* c = S.c;
     uint32_t node = 0;
+    uint2 range = make_uint2(0u, 0u);  // entries of an occupied leaf
     int skip = 1;   // > 1: an empty cube of 2 skip - 1 units centred on the unit holding c
     int unit = 1;   // edge of a skip unit in leaves (1, or a level-0 cell)
     int lvl = 0;    // level of the empty cell containing c, or L for an occupied leaf
@@ -329,6 +330,10 @@ __device__ __forceinline__ void dda_step(const SceneView& v, LeafTestLds& W, boo
             lvl = (n0 < 0 || (uint32_t)n0 >= v.nn[0]) ? 0 : L;
             node = (uint32_t)n0;
             if (lvl == 0) skip = max(1, d0);
+            if (lvl == L) {
+                range = v.leaf[node];
+                if (STATS) cnt[ST_BYTES] += 8;
+            }
         } else {
             // the descent from level 0 runs only when the parent cell changes
             const int q[3] = {span_div(c[0], v.mspan[P]), span_div(c[1], v.mspan[P]), span_div(c[2], v.mspan[P])};
@@ -344,6 +349,23 @@ __device__ __forceinline__ void dda_step(const SceneView& v, LeafTestLds& W, boo
                     // empty level-0 cell: the cube of radius cskip0 - 1 level-0 cells around it is empty
                     skip = max(1, S.cskip0);
                     unit = v.span[0];
+                }
+            } else if (v.cells) {
+                // one load: the leaf's entry range, or its skip radius
+                const int r = v.ratio[P];
+                const int loc = (c[0] - r * q[0]) + r * ((c[1] - r * q[1]) + r * (c[2] - r * q[2]));
+                const uint2 cl = v.cells[(size_t)S.cnode * (size_t)(r * r * r) + loc];
+                if (STATS) {
+                    ++cnt[ST_NODES];
+                    cnt[ST_BYTES] += 8;
+                }
+                if (cl.y) {
+                    lvl = L;
+                    range = cl;
+                    node = cl.x;
+                } else {
+                    lvl = L - 1;
+                    skip = max(1, (int)cl.x);
                 }
             } else {
                 const int r = v.ratio[P];
@@ -362,7 +384,11 @@ __device__ __forceinline__ void dda_step(const SceneView& v, LeafTestLds& W, boo
                 lvl = L - 1;
                 if (w & bit) {
                     node = wbase + (uint32_t)__popcll(w & (bit - 1));
-                    if (node < v.nn[L - 1]) lvl = L;
+                    if (node < v.nn[L - 1]) {
+                        lvl = L;
+                        range = v.leaf[node];
+                        if (STATS) cnt[ST_BYTES] += 8;
+                    }
                 } else {
                     // empty leaf: the whole cube of radius skip - 1 around it is empty
                     skip = max(1, ld);
@@ -384,16 +410,12 @@ __device__ __forceinline__ void dda_step(const SceneView& v, LeafTestLds& W, boo
         if (at_leaf && __ballot(at_leaf && node == lead) == m_walk) ++cnt[ST_UNIFORM];
         if (lane_id() == 0) ++cnt[ST_WAVE_DDA];
     }
-    uint2 r = make_uint2(0u, 0u);
-    if (at_leaf) {
-        r = v.leaf[node];
-        if (STATS) {
-            ++cnt[ST_LEAVES];
-            cnt[ST_TESTS] += r.y;
-            cnt[ST_BYTES] += 8 + 32ull * r.y;
-        }
+    if (STATS && at_leaf) {
+        ++cnt[ST_LEAVES];
+        cnt[ST_TESTS] += range.y;
+        cnt[ST_BYTES] += 32ull * range.y;
     }
-    if (__ballot(at_leaf && r.y != 0u)) leaf_tests<STATS>(v, W, at_leaf, r, hit, cnt);
+    if (__ballot(at_leaf && range.y != 0u)) leaf_tests<STATS>(v, W, at_leaf, range, hit, cnt);
     if (walking) {
         const int Sz = at_leaf ? 1 : span_at<NL>(v, lvl);
         // exit of the current cell (size Sz leaves)
