@@ -67,8 +67,15 @@ typedef struct {
                                              multiple (within 1e-4 relative) of the next */
     float   surfel_radius;                /* r_s > 0: every point is a two-sided disk of this radius */
     float   t_eps;                        /* self-intersection distance; <= 0 selects 1e-5 x AABB diagonal */
-    int32_t flags;                        /* reserved, must be 0 */
+    int32_t flags;                        /* 0, or PCRL_VOXEL_COMPACT */
 } PcrlVoxelParams;
+
+/* PcrlVoxelParams.flags: keep no dense cell table of the leaves' parent bricks
+ * (8 bytes per leaf cell of every occupied parent); the traversal then reads
+ * the bricks' occupancy masks (less device memory, slower).  The table is
+ * also left out when the parent-to-leaf ratio exceeds 16 or it would exceed
+ * 16 GiB. */
+#define PCRL_VOXEL_COMPACT 1
 
 typedef struct {
     int64_t n_points;                     /* input points */
@@ -134,7 +141,9 @@ int release_scene(PcrlScene* scene);
 
 #define PCRL_LAUNCH_STATS   1   /* count DDA steps, leaves, surfel tests (slower kernel variant) */
 #define PCRL_LAUNCH_TIMING  2   /* time every bounce kernel with HIP events */
-#define PCRL_LAUNCH_COHERENT 4  /* trace the first bounce in a direction-coherent ray order */
+#define PCRL_LAUNCH_COHERENT 4  /* trace the first bounce in a direction-coherent ray order and (launches of
+                                   >= 65536 rays) every later bounce in a coherent order of its survivors;
+                                   results do not depend on it */
 
 typedef struct {
     int64_t n_rays;            /* rays per TX (> 0) */

@@ -124,8 +124,11 @@ class Scene:
             pass
 
 
-def build_voxels(xyz, normal, label, levels, surfel_radius, t_eps=0.0, device=None) -> Scene:
-    """Voxelise a labeled point cloud (positions [N,3], normals [N,3], labels [N])."""
+def build_voxels(xyz, normal, label, levels, surfel_radius, t_eps=0.0, device=None, compact=False) -> Scene:
+    """Voxelise a labeled point cloud (positions [N,3], normals [N,3], labels [N]).
+
+    ``compact`` keeps no dense cell table of the leaves' parent bricks (less
+    device memory, slower traversal)."""
     device = _dev(device)
     xyz = _as_tensor(xyz, torch.float32, device, 3)
     normal = _as_tensor(normal, torch.float32, device, 3)
@@ -144,7 +147,7 @@ def build_voxels(xyz, normal, label, levels, surfel_radius, t_eps=0.0, device=No
         p.level_size[i] = float(s)
     p.surfel_radius = float(surfel_radius)
     p.t_eps = float(t_eps)
-    p.flags = 0
+    p.flags = _lib.VOXEL_COMPACT if compact else 0
     h = C.c_void_p()
     with torch.cuda.device(device):
         check("build_voxels", lib.build_voxels(_ptr(xyz) if n else None, _ptr(normal) if n else None,

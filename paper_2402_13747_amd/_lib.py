@@ -28,6 +28,7 @@ MAX_REFLECTIONS = 8
 LAUNCH_STATS = 1
 LAUNCH_TIMING = 2
 LAUNCH_COHERENT = 4
+VOXEL_COMPACT = 1
 KEY_LABELS = 0
 KEY_LEAVES = 1
 

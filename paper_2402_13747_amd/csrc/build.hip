@@ -334,20 +334,73 @@ __global__ void k_dist0_pass(const int32_t* map0, const uint8_t* in, uint8_t* ou
 }
 
 // Dense cell table of the leaves' parent bricks: one 8-byte load per DDA
-// step gives an occupied leaf's entry range, or an empty leaf's skip radius.
-__global__ void k_brick_cells(const uint64_t* mask, const uint32_t* base, const uint2* leaf, const uint8_t* ldist,
-                              int nw, int r3, int64_t n_bricks, uint2* cells) {
-    const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
-    if (i >= n_bricks * r3) return;
-    const int64_t P = i / r3;
-    const int c = (int)(i - P * r3);
-    const size_t wi = (size_t)P * nw + (c >> 6);
-    const uint64_t w = mask[wi];
-    const uint64_t bit = uint64_t(1) << (c & 63);
-    if (w & bit) {
-        cells[i] = leaf[base[wi] + (uint32_t)__popcll(w & (bit - 1))];
-    } else {
-        cells[i] = make_uint2(ldist ? (uint32_t)ldist[i] : 1u, 0u);
+// step gives an occupied leaf's entry range, or, for an empty leaf, its skip
+// radii per direction octant.  Radius s of octant (sx, sy, sz) (bit a set:
+// the ray's component a is negative) means the box of s x s x s cells that
+// starts at the cell and extends along the octant's signs is empty and inside
+// the brick; a ray whose direction lies in that octant crosses the box in one
+// step.  s is the octant-restricted Chebyshev distance to the nearest
+// occupied cell (separable: one-sided 1D distances along x, then
+// min over t of max(t, .) along y and z), capped by the brick's far faces and
+// by 15 (4 bits per octant, 8 octants in the first word).
+// The one-sided passes are shared between octants: x distances for the two
+// signs of x, then y for the four (x, y) sign pairs, then z for all eight.
+__global__ __launch_bounds__(BUILD_BLOCK) void k_brick_cells(const uint64_t* mask, const uint32_t* base,
+                                                            const uint2* leaf, int nw, int r, uint2* cells) {
+    extern __shared__ uint8_t sm[];
+    const int n3 = r * r * r;
+    uint8_t* occ = sm;
+    uint8_t* A = sm + n3;       // [2][n3]  x sign
+    uint8_t* Bf = A + 2 * n3;   // [4][n3]  (x sign, y sign)
+    const size_t P = blockIdx.x;
+    for (int c = threadIdx.x; c < n3; c += BUILD_BLOCK)
+        occ[c] = (uint8_t)((mask[P * nw + (c >> 6)] >> (c & 63)) & 1ull);
+    __syncthreads();
+    for (int it = threadIdx.x; it < 2 * n3; it += BUILD_BLOCK) {
+        const int sx = (it / n3) ? -1 : 1, c = it % n3;
+        const int x = c % r, row = c - x;
+        int m = 255;
+        for (int t = 0, xx = x; xx >= 0 && xx < r; ++t, xx += sx)
+            if (occ[row + xx]) {
+                m = t;
+                break;
+            }
+        A[it] = (uint8_t)m;
+    }
+    __syncthreads();
+    for (int it = threadIdx.x; it < 4 * n3; it += BUILD_BLOCK) {
+        const int q = it / n3, c = it % n3;  // q: bit 0 x sign, bit 1 y sign
+        const int sy = (q & 2) ? -1 : 1;
+        const int x = c % r, y = (c / r) % r, z = c / (r * r);
+        const uint8_t* Ao = A + (size_t)(q & 1) * n3;
+        int m = 255;
+        for (int t = 0, yy = y; yy >= 0 && yy < r && t < m; ++t, yy += sy)
+            m = min(m, max(t, (int)Ao[x + r * (yy + r * z)]));
+        Bf[it] = (uint8_t)m;
+    }
+    __syncthreads();
+    for (int c = threadIdx.x; c < n3; c += BUILD_BLOCK) {
+        const size_t i = P * (size_t)n3 + c;
+        if (occ[c]) {
+            const size_t wi = P * nw + (c >> 6);
+            const uint64_t w = mask[wi];
+            cells[i] = leaf[base[wi] + (uint32_t)__popcll(w & ((uint64_t(1) << (c & 63)) - 1))];
+            continue;
+        }
+        const int x = c % r, y = (c / r) % r, z = c / (r * r);
+        uint32_t packed = 0;
+        for (int o = 0; o < 8; ++o) {
+            const int sx = (o & 1) ? -1 : 1, sy = (o & 2) ? -1 : 1, sz = (o & 4) ? -1 : 1;
+            const uint8_t* Bo = Bf + (size_t)(o & 3) * n3;
+            int m = 255;
+            for (int t = 0, zz = z; zz >= 0 && zz < r && t < m; ++t, zz += sz)
+                m = min(m, max(t, (int)Bo[x + r * (y + r * zz)]));
+            // cells left inside the brick along each signed axis, this one included
+            const int fx = sx > 0 ? r - x : x + 1, fy = sy > 0 ? r - y : y + 1, fz = sz > 0 ? r - z : z + 1;
+            const int sr = min(min(m, 15), min(fx, min(fy, fz)));
+            packed |= (uint32_t)max(sr, 1) << (4 * o);
+        }
+        cells[i] = make_uint2(packed, 0u);
     }
 }
 
@@ -387,7 +440,10 @@ static int validate_params(const PcrlVoxelParams* p, int32_t ratio[PCRL_MAX_LEVE
         set_error("build_voxels: n_levels must be in [1, %d], got %d", PCRL_MAX_LEVELS, p->n_levels);
         return PCRL_EINVAL;
     }
-    if (p->flags != 0) { set_error("build_voxels: flags must be 0"); return PCRL_EINVAL; }
+    if (p->flags & ~PCRL_VOXEL_COMPACT) {
+        set_error("build_voxels: unknown flags 0x%x", (unsigned)p->flags);
+        return PCRL_EINVAL;
+    }
     if (!(p->surfel_radius > 0.f) || !std::isfinite(p->surfel_radius)) {
         set_error("build_voxels: surfel_radius must be positive and finite");
         return PCRL_EINVAL;
@@ -484,7 +540,8 @@ struct HierBuild {
 // Voxelise n ingested points into the frame already set in v (level-0 map,
 // bricks, leaves, surfel streams).  gid: global point ids (null: 0..n-1).
 static int build_hierarchy(const float* xyz, const float4* unit_nrm, const uint32_t* label, const uint32_t* gid,
-                           int64_t n, hipStream_t s, SceneView& v, DevBufs& B, DevBufs& T, HierBuild& hb) {
+                           int64_t n, hipStream_t s, bool compact, SceneView& v, DevBufs& B, DevBufs& T,
+                           HierBuild& hb) {
     const int L = v.nlev;
     int rc = PCRL_OK;
     LevelShifts ls{};
@@ -576,33 +633,32 @@ static int build_hierarchy(const float* xyz, const float4* unit_nrm, const uint3
     v.leaf = leaf;
     hb.leaf_range = leaf;
     hb.leaf_key = lkey;
-    // empty-space skip radii inside the leaves' parent bricks
+    // Leaf level of the traversal: a dense cell table of the leaves' parent
+    // bricks (entry ranges and octant skip radii; needs the leaf ranges, so
+    // after k_leaf_counts), or, when it would be too large, per-cell isotropic
+    // skip radii beside the bricks' masks.
     v.ldist = nullptr;
-    if (L >= 2 && v.ratio[L - 2] >= 3 && v.ratio[L - 2] <= 16 && host_nodes[L - 2] > 0) {
-        const int r = v.ratio[L - 2];
-        const size_t n3 = (size_t)r * r * r;
-        uint8_t* ld = nullptr;
-        if ((rc = B.alloc(&ld, (size_t)host_nodes[L - 2] * n3))) return rc;
-        hipLaunchKernelGGL(k_brick_dist, dim3(host_nodes[L - 2]), dim3(BUILD_BLOCK), 2 * n3, s, ho.mask[L - 2],
-                           v.nw[L - 2], r, ld);
-        v.ldist = ld;
-        hb.bytes += (int64_t)host_nodes[L - 2] * (int64_t)n3;
-    }
-
-    // dense cell table of the leaves' parent bricks (needs the leaf ranges: after k_leaf_counts)
     v.cells = nullptr;
     if (L >= 2 && host_nodes[L - 2] > 0) {
         const int r = v.ratio[L - 2];
         const int64_t r3 = (int64_t)r * r * r;
         const int64_t n_cells = (int64_t)host_nodes[L - 2] * r3;
-        if (n_cells * 8 <= CELL_TABLE_MAX_BYTES) {
+        if (!compact && r <= 16 && n_cells * 8 <= CELL_TABLE_MAX_BYTES) {
             uint2* cells = nullptr;
             if ((rc = B.alloc(&cells, (size_t)n_cells))) return rc;
-            hipLaunchKernelGGL(k_brick_cells, dim3(blocks_for(n_cells)), dim3(BUILD_BLOCK), 0, s, ho.mask[L - 2],
-                               (const uint32_t*)v.base[L - 2], (const uint2*)leaf, v.ldist, v.nw[L - 2], (int)r3,
-                               (int64_t)host_nodes[L - 2], cells);
+            const size_t lds = (size_t)r3 * 7;
+            hipLaunchKernelGGL(k_brick_cells, dim3((unsigned)host_nodes[L - 2]), dim3(BUILD_BLOCK), lds, s,
+                               ho.mask[L - 2], (const uint32_t*)v.base[L - 2], (const uint2*)leaf, v.nw[L - 2], r,
+                               cells);
             v.cells = cells;
             hb.bytes += n_cells * 8;
+        } else if (r >= 3 && r <= 16) {
+            uint8_t* ld = nullptr;
+            if ((rc = B.alloc(&ld, (size_t)n_cells))) return rc;
+            hipLaunchKernelGGL(k_brick_dist, dim3(host_nodes[L - 2]), dim3(BUILD_BLOCK), 2 * r3, s, ho.mask[L - 2],
+                               v.nw[L - 2], r, ld);
+            v.ldist = ld;
+            hb.bytes += n_cells;
         }
     }
 
@@ -687,7 +743,8 @@ static int build_impl(const float* xyz, const float* nrm, const uint32_t* label,
     SceneView& v = S->view;
     if ((rc = make_frame(params, ratio, io, v))) return fail(rc);
     HierBuild hb;
-    if ((rc = build_hierarchy(xyz, unit_nrm, label, nullptr, n, s, v, S->bufs, T, hb))) return fail(rc);
+    S->compact = (params->flags & PCRL_VOXEL_COMPACT) != 0;
+    if ((rc = build_hierarchy(xyz, unit_nrm, label, nullptr, n, s, S->compact, v, S->bufs, T, hb))) return fail(rc);
     S->max_label = io.max_label;
     S->leaf_key = hb.leaf_key;
     S->entry_point = hb.entry_point;
@@ -751,7 +808,7 @@ static int overlay_impl(PcrlScene* S, const uint32_t* gid, const float* xyz, con
     v.cells = nullptr;
     v.spos = v.snrm = nullptr;
     HierBuild hb;
-    if ((rc = build_hierarchy(xyz, unit_nrm, label, gid, n, s, v, ov->bufs, T, hb))) return fail(rc);
+    if ((rc = build_hierarchy(xyz, unit_nrm, label, gid, n, s, S->compact, v, ov->bufs, T, hb))) return fail(rc);
     ov->view = v;
     ov->n_points = n;
     ov->n_entries = hb.n_entries;

@@ -254,6 +254,7 @@ struct PcrlScene {
     uint32_t* entry_point = nullptr;  // per entry: point id (leaf order)
     uint2* leaf_range = nullptr;
     uint32_t max_label = 0;
+    bool compact = false;             // PCRL_VOXEL_COMPACT: no dense cell tables (base and overlays)
     std::shared_ptr<pcrl::Overlay> overlay;  // current epoch of dynamic points (may be null)
 };
 

@@ -248,6 +248,7 @@ struct Seg {
     int cskip0;     // cached skip radius of an empty level-0 cell (cres == 0)
     uint32_t cnode; // cached parent node
     int it;         // DDA steps taken
+    int oct_shift;  // 4 x the ray's direction octant (bit a: component a negative)
 };
 
 __device__ __forceinline__ int dir_step(float x) { return x > 0.f ? 1 : (x < 0.f ? -1 : 0); }
@@ -279,6 +280,7 @@ __device__ __forceinline__ bool seg_begin(const SceneView& v, const float o[3], 
     }
     S.cres = 0;
     S.cskip0 = 1;
+    S.oct_shift = 4 * ((d[0] < 0.f ? 1 : 0) | (d[1] < 0.f ? 2 : 0) | (d[2] < 0.f ? 4 : 0));
     S.cnode = 0;
     S.it = 0;
     return t0 <= t1;
@@ -316,6 +318,7 @@ __device__ __forceinline__ void dda_step(const SceneView& v, LeafTestLds& W, boo
     uint32_t node = 0;
     uint2 range = make_uint2(0u, 0u);  // entries of an occupied leaf
     int skip = 1;   // > 1: an empty cube of 2 skip - 1 units centred on the unit holding c
+    int oct = 1;    // > 1: an empty box of oct leaves from c along the ray's octant
     int unit = 1;   // edge of a skip unit in leaves (1, or a level-0 cell)
     int lvl = 0;    // level of the empty cell containing c, or L for an occupied leaf
     if (walking) {
@@ -364,8 +367,9 @@ __device__ __forceinline__ void dda_step(const SceneView& v, LeafTestLds& W, boo
                     range = cl;
                     node = cl.x;
                 } else {
+                    // empty leaf: the box of oct cells from it along the ray's octant is empty
                     lvl = L - 1;
-                    skip = max(1, (int)cl.x);
+                    oct = (int)((cl.x >> S.oct_shift) & 15u);
                 }
             } else {
                 const int r = v.ratio[P];
@@ -424,7 +428,11 @@ __device__ __forceinline__ void dda_step(const SceneView& v, LeafTestLds& W, boo
         int axis = 0;
 #pragma unroll
         for (int a = 0; a < 3; ++a) {
-            if (skip > 1) {
+            if (oct > 1) {
+                // the octant box (inside its brick)
+                lo[a] = d[a] < 0.f ? c[a] - (oct - 1) : c[a];
+                hi[a] = d[a] < 0.f ? c[a] + 1 : c[a] + oct;
+            } else if (skip > 1) {
                 // the skip cube, clipped to the grid (beyond it the ray leaves)
                 const int uc = (unit == 1) ? c[a] : span_div(c[a], v.mspan[0]);
                 lo[a] = max((uc - (skip - 1)) * unit, 0);

@@ -43,6 +43,19 @@ def test_library_exports_every_declared_symbol(pcrl):
     assert not missing, missing
 
 
+def test_header_constants_match_binding(pcrl):
+    from paper_2402_13747_amd import _lib
+    src = "".join(open(h).read() for h in HEADERS)
+    defs = {m.group(1): int(m.group(2)) for m in re.finditer(r"#define\s+(PCRL_[A-Z_]+)\s+(-?\d+)", src)}
+    assert defs["PCRL_VOXEL_COMPACT"] == _lib.VOXEL_COMPACT
+    assert defs["PCRL_LAUNCH_STATS"] == _lib.LAUNCH_STATS and defs["PCRL_LAUNCH_TIMING"] == _lib.LAUNCH_TIMING
+    assert defs["PCRL_LAUNCH_COHERENT"] == _lib.LAUNCH_COHERENT
+    assert defs["PCRL_KEY_LABELS"] == _lib.KEY_LABELS and defs["PCRL_KEY_LEAVES"] == _lib.KEY_LEAVES
+    assert defs["PCRL_MAX_LEVELS"] == _lib.MAX_LEVELS and defs["PCRL_MAX_REFLECTIONS"] == _lib.MAX_REFLECTIONS
+    for name in ("OK", "EINVAL", "ENOMEM", "EOVERFLOW", "EHIP", "EBUSY"):
+        assert defs["PCRL_" + name] == getattr(_lib, "PCRL_" + name)
+
+
 def test_binding_covers_header(pcrl):
     from paper_2402_13747_amd import _lib
     assert set(_lib.SIGNATURES) == _declared_functions()
@@ -75,6 +88,10 @@ def test_version_and_validation_without_gpu(pcrl):
     assert b"integer multiple" in lib.last_error()
     p.n_levels = 5
     assert lib.build_voxels(None, None, None, 0, C.byref(p), None, C.byref(out)) == _lib.PCRL_EINVAL
+    p.n_levels = 1
+    p.flags = 2                     # unknown flag
+    assert lib.build_voxels(None, None, None, 0, C.byref(p), None, C.byref(out)) == _lib.PCRL_EINVAL
+    assert b"flags" in lib.last_error()
     lp = _lib.PcrlLaunchParams()
     lp.n_rays = 10
     lp.max_reflections = 9          # K > 8

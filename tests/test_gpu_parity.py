@@ -204,6 +204,30 @@ def test_random_scene_parity(env, seed, levels, n_rays, K, coherent):
         assert key in dev
 
 
+@pytest.mark.parametrize("seed", [11, 12])
+def test_traversal_variants_agree(env, seed):
+    """The dense cell table with octant skips, the compact brick masks with isotropic skip radii and a
+    parent ratio above 16 (masks only) give bitwise the same hits and paths, and match the oracle."""
+    torch, pcrl, oracle = env
+    s = scenes.random_scene(seed, tilt_sigma=0.03, pos_sigma=0.002, n_tx=2, n_rx=4)
+    t_eps, r_s = _f32(parity.t_eps_of(s)), _f32(s.surfel_radius)
+    runs = []
+    for levels, compact in (((1.0, 0.1), False), ((1.0, 0.1), True), ((2.5, 0.1), False), ((0.5,), False)):
+        scene = pcrl.build_voxels(s.xyz, s.normal, s.label, levels, r_s, t_eps=t_eps, compact=compact)
+        L = pcrl.launch_rays(scene, s.tx, s.rx, n_rays=4000, max_reflections=3, hit_log=True)
+        runs.append((L.hit_log[0].cpu().numpy(), L.hit_log[1].cpu().numpy(),
+                     parity.to_numpy(pcrl.collect_paths(L, kappa=1 << 30))))
+    h0, t0, p0 = runs[0]
+    for h, t, p in runs[1:]:
+        assert np.array_equal(h, h0) and np.array_equal(t, t0, equal_nan=True)
+        for k in ("tx", "rx", "n_refl", "key", "count", "rank", "ray", "len_poly", "len_unf"):
+            assert np.array_equal(np.asarray(p[k]), np.asarray(p0[k])), k
+    scene, launch, paths, rec, ids, orc = _run(env, s, 4000, 3, levels=(1.0, 0.1))
+    rep = parity.compare(orc, ids, rec, s.xyz, s.normal, s.label, 3)
+    print(rep.summary())
+    assert rep.ok()
+
+
 def test_kappa_and_counts(env):
     torch, pcrl, oracle = env
     s = scenes.box_room()
