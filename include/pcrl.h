@@ -74,7 +74,7 @@ typedef struct {
  * (8 bytes per leaf cell of every occupied parent); the traversal then reads
  * the bricks' occupancy masks (less device memory, slower).  The table is
  * also left out when the parent-to-leaf ratio exceeds 16 or it would exceed
- * 16 GiB. */
+ * 256 MiB (beyond the last-level cache it slows the traversal down). */
 #define PCRL_VOXEL_COMPACT 1
 
 typedef struct {

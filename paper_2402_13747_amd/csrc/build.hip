@@ -312,8 +312,11 @@ __global__ __launch_bounds__(BUILD_BLOCK) void k_brick_dist(const uint64_t* mask
 // nearest occupied cell only lowers the result (conservative).
 constexpr int DIST0_CAP = 15;
 
-// Largest dense cell table built (beyond it the traversal reads the bricks' masks).
-constexpr int64_t CELL_TABLE_MAX_BYTES = (int64_t)16 << 30;
+// Largest dense cell table built: the table pays off while it stays resident
+// in the 256 MB last-level (MALL) cache; a larger one (3.3 GB for a 20M-point
+// street canyon) turns every DDA step into an HBM round trip and doubled that
+// scene's trace time.  Beyond it the traversal reads the bricks' masks.
+constexpr int64_t CELL_TABLE_MAX_BYTES = (int64_t)256 << 20;
 
 __global__ void k_dist0_pass(const int32_t* map0, const uint8_t* in, uint8_t* out, int dx, int dy, int dz, int axis) {
     const int64_t c = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
@@ -340,67 +343,96 @@ __global__ void k_dist0_pass(const int32_t* map0, const uint8_t* in, uint8_t* ou
 // starts at the cell and extends along the octant's signs is empty and inside
 // the brick; a ray whose direction lies in that octant crosses the box in one
 // step.  s is the octant-restricted Chebyshev distance to the nearest
-// occupied cell (separable: one-sided 1D distances along x, then
-// min over t of max(t, .) along y and z), capped by the brick's far faces and
-// by 15 (4 bits per octant, 8 octants in the first word).
-// The one-sided passes are shared between octants: x distances for the two
-// signs of x, then y for the four (x, y) sign pairs, then z for all eight.
+// occupied cell, capped by the brick's far faces and by 15 (4 bits per
+// octant, 8 octants in the first word).
+// Computed on bit rows (the r <= 16 cells of a brick row along x in one
+// 16-bit word), per octant: E_1 = empty cells; E_{s+1}(c) = AND of E_s over the
+// 8 cells c + delta, delta in {0, 1}^3 along the octant's signs (a box of s + 1
+// is the union of 8 boxes of s), cells outside the brick counting as not
+// empty.  The radius of a cell is the number of s <= 15 with E_s(c), kept as a
+// 4-bit counter in bit planes.
+constexpr int OCT_ITEMS = 8;  // (octant, row) items per thread: 8 * r^2 <= OCT_ITEMS * BUILD_BLOCK for r <= 16
+
 __global__ __launch_bounds__(BUILD_BLOCK) void k_brick_cells(const uint64_t* mask, const uint32_t* base,
                                                             const uint2* leaf, int nw, int r, uint2* cells) {
-    extern __shared__ uint8_t sm[];
-    const int n3 = r * r * r;
-    uint8_t* occ = sm;
-    uint8_t* A = sm + n3;       // [2][n3]  x sign
-    uint8_t* Bf = A + 2 * n3;   // [4][n3]  (x sign, y sign)
+    extern __shared__ uint16_t rows[];  // [2][8][r^2]: E_s and E_{s+1} per octant and row; then the radii
+    __shared__ uint64_t wmask[64];      // the brick's occupancy words (nw <= 64 for r <= 16)
+    const int r2 = r * r, n3 = r2 * r;
+    const int items = 8 * r2;
+    const uint32_t full = (1u << r) - 1u;
     const size_t P = blockIdx.x;
-    for (int c = threadIdx.x; c < n3; c += BUILD_BLOCK)
-        occ[c] = (uint8_t)((mask[P * nw + (c >> 6)] >> (c & 63)) & 1ull);
+    uint16_t* Ecur = rows;
+    uint16_t* Enext = rows + items;
+    for (int k = threadIdx.x; k < nw; k += BUILD_BLOCK) wmask[k] = mask[P * nw + k];
     __syncthreads();
-    for (int it = threadIdx.x; it < 2 * n3; it += BUILD_BLOCK) {
-        const int sx = (it / n3) ? -1 : 1, c = it % n3;
-        const int x = c % r, row = c - x;
-        int m = 255;
-        for (int t = 0, xx = x; xx >= 0 && xx < r; ++t, xx += sx)
-            if (occ[row + xx]) {
-                m = t;
-                break;
-            }
-        A[it] = (uint8_t)m;
+    // E_1: empty cells of every row, the same for all octants
+    for (int row = threadIdx.x; row < r2; row += BUILD_BLOCK) {
+        uint32_t e = 0;
+        for (int x = 0; x < r; ++x) {
+            const int c = x + r * row;
+            if (!((wmask[c >> 6] >> (c & 63)) & 1ull)) e |= 1u << x;
+        }
+        for (int o = 0; o < 8; ++o) Ecur[o * r2 + row] = (uint16_t)e;
     }
     __syncthreads();
-    for (int it = threadIdx.x; it < 4 * n3; it += BUILD_BLOCK) {
-        const int q = it / n3, c = it % n3;  // q: bit 0 x sign, bit 1 y sign
-        const int sy = (q & 2) ? -1 : 1;
-        const int x = c % r, y = (c / r) % r, z = c / (r * r);
-        const uint8_t* Ao = A + (size_t)(q & 1) * n3;
-        int m = 255;
-        for (int t = 0, yy = y; yy >= 0 && yy < r && t < m; ++t, yy += sy)
-            m = min(m, max(t, (int)Ao[x + r * (yy + r * z)]));
-        Bf[it] = (uint8_t)m;
+    uint16_t plane[OCT_ITEMS][4];
+    for (int k = 0; k < OCT_ITEMS; ++k)
+        for (int b = 0; b < 4; ++b) plane[k][b] = 0;
+    for (int sz = 1; sz <= 15; ++sz) {
+        for (int k = 0; k < OCT_ITEMS; ++k) {
+            const int it = threadIdx.x + k * BUILD_BLOCK;
+            if (it >= items) break;
+            const int o = it / r2, row = it % r2;
+            const uint32_t e = Ecur[it];
+            // count this s (4-bit ripple add of the bits of E_s)
+            uint32_t carry = e;
+            for (int b = 0; b < 4; ++b) {
+                const uint32_t pb = plane[k][b];
+                plane[k][b] = (uint16_t)(pb ^ carry);
+                carry &= pb;
+            }
+            if (sz == 15) continue;
+            const int y = row % r, z = row / r;
+            const int sy = (o & 2) ? -1 : 1, szn = (o & 4) ? -1 : 1;
+            const bool negx = (o & 1) != 0;
+            const uint16_t* Eo = Ecur + (size_t)o * r2;
+            auto get = [&](int yy, int zz) -> uint32_t {
+                if (yy < 0 || yy >= r || zz < 0 || zz >= r) return 0u;
+                const uint32_t v = Eo[yy + r * zz];
+                const uint32_t sh = negx ? ((v << 1) & full) : (v >> 1);  // the neighbour along x
+                return v & sh;
+            };
+            Enext[it] = (uint16_t)(get(y, z) & get(y + sy, z) & get(y, z + szn) & get(y + sy, z + szn));
+        }
+        __syncthreads();
+        uint16_t* t = Ecur;
+        Ecur = Enext;
+        Enext = t;
+    }
+    // radii packed per cell (octant o in bits 4o..4o+3), written with the occupied leaves' ranges
+    __syncthreads();
+    uint32_t* packed = reinterpret_cast<uint32_t*>(rows + 2 * items);  // [n3]
+    for (int c = threadIdx.x; c < n3; c += BUILD_BLOCK) packed[c] = 0u;
+    __syncthreads();
+    for (int k = 0; k < OCT_ITEMS; ++k) {
+        const int it = threadIdx.x + k * BUILD_BLOCK;
+        if (it >= items) break;
+        const int o = it / r2, row = it % r2;
+        for (int x = 0; x < r; ++x) {
+            const uint32_t n = ((plane[k][0] >> x) & 1u) | (((plane[k][1] >> x) & 1u) << 1) |
+                               (((plane[k][2] >> x) & 1u) << 2) | (((plane[k][3] >> x) & 1u) << 3);
+            if (n) atomicOr(&packed[x + r * row], n << (4 * o));
+        }
     }
     __syncthreads();
     for (int c = threadIdx.x; c < n3; c += BUILD_BLOCK) {
         const size_t i = P * (size_t)n3 + c;
-        if (occ[c]) {
-            const size_t wi = P * nw + (c >> 6);
-            const uint64_t w = mask[wi];
-            cells[i] = leaf[base[wi] + (uint32_t)__popcll(w & ((uint64_t(1) << (c & 63)) - 1))];
-            continue;
-        }
-        const int x = c % r, y = (c / r) % r, z = c / (r * r);
-        uint32_t packed = 0;
-        for (int o = 0; o < 8; ++o) {
-            const int sx = (o & 1) ? -1 : 1, sy = (o & 2) ? -1 : 1, sz = (o & 4) ? -1 : 1;
-            const uint8_t* Bo = Bf + (size_t)(o & 3) * n3;
-            int m = 255;
-            for (int t = 0, zz = z; zz >= 0 && zz < r && t < m; ++t, zz += sz)
-                m = min(m, max(t, (int)Bo[x + r * (y + r * zz)]));
-            // cells left inside the brick along each signed axis, this one included
-            const int fx = sx > 0 ? r - x : x + 1, fy = sy > 0 ? r - y : y + 1, fz = sz > 0 ? r - z : z + 1;
-            const int sr = min(min(m, 15), min(fx, min(fy, fz)));
-            packed |= (uint32_t)max(sr, 1) << (4 * o);
-        }
-        cells[i] = make_uint2(packed, 0u);
+        const uint64_t w = wmask[c >> 6];
+        const uint64_t bit = uint64_t(1) << (c & 63);
+        if (w & bit)
+            cells[i] = leaf[base[P * nw + (c >> 6)] + (uint32_t)__popcll(w & (bit - 1))];
+        else
+            cells[i] = make_uint2(packed[c], 0u);
     }
 }
 
@@ -646,7 +678,7 @@ static int build_hierarchy(const float* xyz, const float4* unit_nrm, const uint3
         if (!compact && r <= 16 && n_cells * 8 <= CELL_TABLE_MAX_BYTES) {
             uint2* cells = nullptr;
             if ((rc = B.alloc(&cells, (size_t)n_cells))) return rc;
-            const size_t lds = (size_t)r3 * 7;
+            const size_t lds = (size_t)2 * 8 * r * r * 2 + (size_t)r3 * 4;
             hipLaunchKernelGGL(k_brick_cells, dim3((unsigned)host_nodes[L - 2]), dim3(BUILD_BLOCK), lds, s,
                                ho.mask[L - 2], (const uint32_t*)v.base[L - 2], (const uint2*)leaf, v.nw[L - 2], r,
                                cells);

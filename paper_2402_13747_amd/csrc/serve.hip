@@ -7,9 +7,11 @@
 //     queries in flight is below max_inflight and its memory estimate fits
 //     the device budget (queries larger than the whole budget are refused with
 //     PCRL_EBUSY at submission);
-//   * continuous batching: every admission round packs all admissible pending
-//     queries into one launch_batch on a free stream, while earlier rounds are
-//     still running on the other streams, so their work overlaps on the GPU;
+//   * continuous batching: every admission round takes all admissible pending
+//     queries onto a free stream, while earlier rounds are still running on
+//     the other streams, so their work overlaps on the GPU; a round of small
+//     queries shares one launch_batch, a round of large ones (>= 65536 rays
+//     per query on average) launches them one by one (launch_rays);
 //   * completion: when a round's event has fired its queries are deduplicated
 //     (collect_paths) and copied to host memory; latency = completion time -
 //     submission time.
@@ -32,6 +34,9 @@
 namespace pcrl {
 
 using clk = std::chrono::steady_clock;
+
+// Mean rays per query from which a round launches its queries one by one.
+constexpr int64_t SOLO_MIN_RAYS = 65536;
 
 struct ServeReq {
     int64_t ticket = 0;
@@ -269,7 +274,18 @@ static bool admit(PcrlServer* S) {
     if (!rc) {
         std::lock_guard<std::mutex> sl(S->scene_mu);
         epoch = S->scene->info.epoch;
-        rc = launch_batch(q.data(), (int32_t)q.size(), &S->prm.batch, s, R.launches.data());
+        // Rounds of large queries launch each query on its own (the launch's
+        // coherence order of later bounces pays off from 65536 rays on); rounds
+        // of small ones share one persistent batch kernel per bounce.
+        int64_t rays = 0;
+        for (const PcrlQuery& x : q) rays += x.params.n_rays * x.n_tx;
+        if (rays >= SOLO_MIN_RAYS * (int64_t)q.size()) {
+            for (size_t k = 0; k < q.size() && !rc; ++k)
+                rc = launch_rays(q[k].scene, q[k].tx, q[k].n_tx, q[k].rx, q[k].n_rx, &q[k].params, s,
+                                 &R.launches[k]);
+        } else {
+            rc = launch_batch(q.data(), (int32_t)q.size(), &S->prm.batch, s, R.launches.data());
+        }
     }
     if (!rc && hipEventCreateWithFlags(&R.done, hipEventDisableTiming) != hipSuccess) rc = PCRL_EHIP;
     if (!rc && hipEventRecord(R.done, s) != hipSuccess) rc = PCRL_EHIP;

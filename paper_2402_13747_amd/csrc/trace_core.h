@@ -54,6 +54,12 @@ struct TraceArgs {
     unsigned long long* stats;
 };
 
+// Ping-pong ray buffers of bounce b, chosen by selects: a runtime index into
+// the argument struct's arrays would force the whole struct into scratch.
+__device__ __forceinline__ float4* ray_o(const TraceArgs& a, int k) { return (k & 1) ? a.buf_o[1] : a.buf_o[0]; }
+__device__ __forceinline__ float4* ray_d(const TraceArgs& a, int k) { return (k & 1) ? a.buf_d[1] : a.buf_d[0]; }
+__device__ __forceinline__ uint32_t* ray_g(const TraceArgs& a, int k) { return (k & 1) ? a.buf_g[1] : a.buf_g[0]; }
+
 struct Hit {
     uint32_t id;
     uint32_t lab;
@@ -61,24 +67,23 @@ struct Hit {
     float nx, ny, nz;
 };
 
-// Level-indexed constants for a per-lane level index, unrolled over the NL
-// levels of the kernel's specialisation (no dynamic indexing of kernel
-// arguments).
+// Level-indexed constants for a per-lane level index.  The values are
+// selected arithmetically after loading all NL of them: a select between
+// loads of argument fields would become a pointer select into the argument
+// struct and keep the struct in scratch memory.
 template <int NL>
 __device__ __forceinline__ int span_at(const SceneView& v, int lvl) {
-    int s = v.span[0];
+    int s = 0;
 #pragma unroll
-    for (int i = 1; i < NL; ++i)
-        if (lvl == i) s = v.span[i];
+    for (int i = 0; i < NL; ++i) s += v.span[i] * (int)(lvl == i);
     return s;
 }
 
 template <int NL>
 __device__ __forceinline__ uint64_t mspan_at(const SceneView& v, int lvl) {
-    uint64_t m = v.mspan[0];
+    uint64_t m = 0;
 #pragma unroll
-    for (int i = 1; i < NL; ++i)
-        if (lvl == i) m = v.mspan[i];
+    for (int i = 0; i < NL; ++i) m += v.mspan[i] * (uint64_t)(lvl == i);
     return m;
 }
 
@@ -257,19 +262,20 @@ __device__ __forceinline__ int dir_step(float x) { return x > 0.f ? 1 : (x < 0.f
 // Returns false when the ray misses the grid.
 __device__ __forceinline__ bool seg_begin(const SceneView& v, const float o[3], const float d[3], Seg& S) {
     float t0 = 0.f, t1 = INFINITY;
+    // slab test; both faces are read on every path (a choice between two
+    // argument fields would be turned into a pointer select into the argument
+    // struct, which then stays in scratch memory)
 #pragma unroll
     for (int a = 0; a < 3; ++a) {
-        if (d[a] > 0.f) {
+        const float lo_a = v.org[a], hi_a = v.hi[a];
+        if (d[a] != 0.f) {
             S.inv[a] = 1.0f / d[a];
-            t0 = fmaxf(t0, (v.org[a] - o[a]) * S.inv[a]);
-            t1 = fminf(t1, (v.hi[a] - o[a]) * S.inv[a]);
-        } else if (d[a] < 0.f) {
-            S.inv[a] = 1.0f / d[a];
-            t0 = fmaxf(t0, (v.hi[a] - o[a]) * S.inv[a]);
-            t1 = fminf(t1, (v.org[a] - o[a]) * S.inv[a]);
+            const float ta = (lo_a - o[a]) * S.inv[a], tb = (hi_a - o[a]) * S.inv[a];
+            t0 = fmaxf(t0, fminf(ta, tb));
+            t1 = fminf(t1, fmaxf(ta, tb));
         } else {
             S.inv[a] = 0.f;
-            if (o[a] < v.org[a] || o[a] > v.hi[a]) t1 = -1.f;
+            if (o[a] < lo_a || o[a] > hi_a) t1 = -1.f;
         }
     }
 #pragma unroll
@@ -482,10 +488,15 @@ __device__ __forceinline__ void dda_step(const SceneView& v, LeafTestLds& W, boo
 }
 
 // One whole segment of every active lane (lanes with `active` false only
-// help with the cooperative leaf tests).  Called by every lane of the wave.
-template <bool STATS, int NL>
-__device__ __forceinline__ void trace_segment(const SceneView& v, LeafTestLds& W, bool active, const float o[3],
+// help with the cooperative leaf tests) through the base hierarchy, or the
+// overlay when OVL.  The hierarchy is picked by a compile-time member, never
+// by a runtime reference: two such calls merged over a reference would keep
+// the whole argument struct in scratch memory.  Called by every lane of the
+// wave.
+template <bool STATS, int NL, bool OVL>
+__device__ __forceinline__ void trace_segment(const TraceArgs& a, LeafTestLds& W, bool active, const float o[3],
                                               const float d[3], Hit& hit, stat_t cnt[ST_COUNT]) {
+    const SceneView& v = OVL ? a.ov : a.v;
     Seg S;
     bool walking = seg_begin(v, o, d, S) && active;
     while (__ballot(walking)) dda_step<STATS, NL>(v, W, walking, o, d, hit, S, cnt);
@@ -517,14 +528,14 @@ __device__ __forceinline__ bool load_ray(const TraceArgs& a, int b, uint32_t i, 
         return true;
     }
     const uint32_t src = a.order ? a.order[i] : i;  // coherence order (never with in-place bounces)
-    g = a.buf_g[(b & 1) ^ 1][src];
+    g = ray_g(a, b + 1)[src];
     if (g == NO_HIT) {
         // the last bounce (b == K) has no output buffers (they may be unallocated)
-        if (in_place && b < a.K) a.buf_g[b & 1][i] = NO_HIT;
+        if (in_place && b < a.K) ray_g(a, b)[i] = NO_HIT;
         return false;
     }
-    const float4 o4 = a.buf_o[(b & 1) ^ 1][src];
-    const float4 d4 = a.buf_d[(b & 1) ^ 1][src];
+    const float4 o4 = ray_o(a, b + 1)[src];
+    const float4 d4 = ray_d(a, b + 1)[src];
     o[0] = o4.x; o[1] = o4.y; o[2] = o4.z; L = o4.w;
     d[0] = d4.x; d[1] = d4.y; d[2] = d4.z; last = __float_as_uint(d4.w);
     return true;
@@ -640,11 +651,11 @@ __device__ __forceinline__ void finish_segment(const TraceArgs& a, int b, bool d
     }
     if (STATS && surv) cnt[ST_BYTES] += 52;
     if (surv) {
-        a.buf_o[b & 1][slot] = make_float4(o[0], o[1], o[2], L);
-        a.buf_d[b & 1][slot] = make_float4(d[0], d[1], d[2], __uint_as_float(last));
-        a.buf_g[b & 1][slot] = g;
+        ray_o(a, b)[slot] = make_float4(o[0], o[1], o[2], L);
+        ray_d(a, b)[slot] = make_float4(d[0], d[1], d[2], __uint_as_float(last));
+        ray_g(a, b)[slot] = g;
     } else if (done && in_place) {
-        a.buf_g[b & 1][i] = NO_HIT;
+        ray_g(a, b)[i] = NO_HIT;
     }
     if (a.okeys && m) {  // compacted survivors only (never in place)
         const uint32_t key = surv ? ray_bucket(a, o, d) : 0u;
@@ -671,11 +682,11 @@ __device__ __forceinline__ void trace_chunk(const TraceArgs& a, LeafTestLds& W, 
     Hit hit;
     hit_reset(hit);
     stage_ray(W, o, d, last);
-    trace_segment<STATS, NL>(a.v, W, act, o, d, hit, cnt);
+    trace_segment<STATS, NL, false>(a, W, act, o, d, hit, cnt);
     // dynamic points: the nearest hit over base and overlay is the nearest
     // hit of the union (ties again by point id); the overlay shares the
     // base's frame and levels
-    if (OV) trace_segment<STATS, NL>(a.ov, W, act, o, d, hit, cnt);
+    if (OV) trace_segment<STATS, NL, true>(a, W, act, o, d, hit, cnt);
     finish_segment<FIRST, STATS>(a, b, act, in_place, i, g, o, d, L, last, hit, cnt);
 }
 

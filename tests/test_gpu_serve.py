@@ -95,12 +95,16 @@ def _served_paths(res):
     return {k: res[k] for k in keys}
 
 
-def test_served_equals_alone(env, world):
+@pytest.mark.parametrize("large", [False, True])
+def test_served_equals_alone(env, world, large):
+    """Small queries share batched rounds; large ones (>= 65536 rays) are launched one by one in a round."""
     torch, pcrl = env
     sc, mover, base, n_static, r_s, t_eps = world
     idx, xyz, nrm = mover(11)
     base.update_points(idx.astype(np.uint32), xyz, nrm, sc.label[idx])
     qs = _queries(sc, np.random.default_rng(0), 14)
+    if large:
+        qs = [dict(q, n_rays=q["n_rays"] + 70_000) for q in qs[:6]]
     alone = []
     for q in qs:
         L = pcrl.launch_rays(base, **q)
