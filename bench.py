@@ -360,8 +360,8 @@ def main():
     ap.add_argument("--no-stats", action="store_true")
     args = ap.parse_args()
     if args.gpus != 1 or int(os.environ.get("WORLD_SIZE", "1")) != 1:
-        print("bench.py runs on exactly one GPU: this build has no multi-GPU path "
-              "(rays shard trivially; see DESIGN.md for the sharding design)", file=sys.stderr)
+        print("bench.py measures one GPU only: the library has no multi-GPU path (the rays of a launch "
+              "would shard over GPUs by TX or ray range, each GPU holding the whole scene)", file=sys.stderr)
         sys.exit(2)
 
     import torch
