@@ -110,6 +110,30 @@ def test_directions_match_oracle(env):
         assert np.mean(np.all(d == ref, axis=1)) > 0.999
 
 
+@pytest.mark.parametrize("levels", [(1.0, 0.1), (0.5,), (2.5, 0.1)])
+def test_axis_aligned_directions(env, levels):
+    """Caller directions with zero components (axes, face and body diagonals) and near-axis ones, traced
+    through the cell table, a single-level grid and the brick masks, match the brute-force oracle."""
+    torch, pcrl, oracle = env
+    s = scenes.random_scene(31, tilt_sigma=0.0, pos_sigma=0.0, n_tx=2, n_rx=4)
+    dirs = []
+    for x in (-1, 0, 1):
+        for y in (-1, 0, 1):
+            for z in (-1, 0, 1):
+                if (x, y, z) != (0, 0, 0):
+                    dirs.append((x, y, z))
+    rng = np.random.default_rng(3)
+    d = np.asarray(dirs, np.float64)
+    near = d[rng.integers(0, len(d), 200)] + rng.normal(0, 1e-6, (200, 3))  # tiny instead of zero components
+    d = np.concatenate([d, near, rng.normal(size=(300, 3))])
+    d = (d / np.linalg.norm(d, axis=1, keepdims=True)).astype(np.float32)
+    scene, launch, paths, rec, ids, orc = _run(env, s, len(d), 3, levels=levels, directions=d)
+    rep = parity.compare(orc, ids, rec, s.xyz, s.normal, s.label, 3)
+    print(rep.summary())
+    assert rep.ok(), (rep.mismatch[:5], rep.record_missing[:5], rep.record_extra[:5], rep.length_bad[:5])
+    assert rep.exact + rep.equivalent >= 0.97 * rep.segments
+
+
 def test_leaf_table_properties(env):
     """Every entry's point disk overlaps its leaf; every overlapped leaf lists the point; order is stable."""
     torch, pcrl, oracle = env
