@@ -168,29 +168,64 @@ __device__ __forceinline__ void disk_leaf_box(const KeyParams& kp, const float* 
     }
 }
 
+// Whether the disk of point i (radius r_s) may meet leaf (x, y, z), the leaf
+// grown by the rounding pad: both the disk's sphere and its plane must reach
+// the box.  Both are necessary conditions of an intersection, so no leaf the
+// disk touches is dropped; the corner leaves of the disk's bounding box
+// (sphere test) and, for tilted disks, off-plane leaves (plane test) are.
+__device__ __forceinline__ bool disk_meets_leaf(const KeyParams& kp, const float p[3], const float nv[3], int x, int y,
+                                                int z) {
+    const float hh = 0.5f * kp.v.h + kp.pad;
+    const int c[3] = {x, y, z};
+    float d2 = 0.f, pr = 0.f, dn = 0.f;
+#pragma unroll
+    for (int a = 0; a < 3; ++a) {
+        const float ca = kp.v.org[a] + ((float)c[a] + 0.5f) * kp.v.h;  // leaf centre
+        const float q = fabsf(p[a] - ca) - hh;
+        if (q > 0.f) d2 += q * q;
+        pr += fabsf(nv[a]) * hh;
+        dn += nv[a] * (ca - p[a]);
+    }
+    const float r = kp.r_s + kp.pad;
+    return d2 <= r * r && fabsf(dn) <= pr + kp.pad;
+}
+
+template <bool EMIT>
+__device__ __forceinline__ uint32_t disk_leaves(const KeyParams& kp, const float* xyz, const float4* un, int64_t i,
+                                                uint64_t* keys, uint32_t* ids, uint32_t o) {
+    int lo[3], hi[3];
+    disk_leaf_box(kp, xyz, un, i, lo, hi);
+    const float p[3] = {xyz[3 * i], xyz[3 * i + 1], xyz[3 * i + 2]};
+    const float4 nn = un[i];
+    const float nv[3] = {nn.x, nn.y, nn.z};
+    uint32_t k = 0;
+    for (int z = lo[2]; z <= hi[2]; ++z)
+        for (int y = lo[1]; y <= hi[1]; ++y)
+            for (int x = lo[0]; x <= hi[0]; ++x) {
+                // a disk inside a single leaf keeps it without the test
+                const bool one = lo[0] == hi[0] && lo[1] == hi[1] && lo[2] == hi[2];
+                if (!one && !disk_meets_leaf(kp, p, nv, x, y, z)) continue;
+                if (EMIT) {
+                    keys[o + k] = leaf_key_of(kp.v, x, y, z);
+                    ids[o + k] = (uint32_t)i;
+                }
+                ++k;
+            }
+    return k;
+}
+
 __global__ __launch_bounds__(BUILD_BLOCK) void k_key_count(KeyParams kp, const float* xyz, const float4* un, int64_t n,
                                                            uint32_t* cnt) {
     int64_t i = (int64_t)blockIdx.x * BUILD_BLOCK + threadIdx.x;
     if (i >= n) return;
-    int lo[3], hi[3];
-    disk_leaf_box(kp, xyz, un, i, lo, hi);
-    cnt[i] = (uint32_t)((hi[0] - lo[0] + 1) * (hi[1] - lo[1] + 1) * (hi[2] - lo[2] + 1));
+    cnt[i] = disk_leaves<false>(kp, xyz, un, i, nullptr, nullptr, 0);
 }
 
 __global__ __launch_bounds__(BUILD_BLOCK) void k_key_emit(KeyParams kp, const float* xyz, const float4* un, int64_t n,
                                                           const uint32_t* off, uint64_t* keys, uint32_t* ids) {
     int64_t i = (int64_t)blockIdx.x * BUILD_BLOCK + threadIdx.x;
     if (i >= n) return;
-    int lo[3], hi[3];
-    disk_leaf_box(kp, xyz, un, i, lo, hi);
-    uint32_t o = off[i];
-    for (int z = lo[2]; z <= hi[2]; ++z)
-        for (int y = lo[1]; y <= hi[1]; ++y)
-            for (int x = lo[0]; x <= hi[0]; ++x) {
-                keys[o] = leaf_key_of(kp.v, x, y, z);
-                ids[o] = (uint32_t)i;
-                ++o;
-            }
+    (void)disk_leaves<true>(kp, xyz, un, i, keys, ids, off[i]);
 }
 
 // ---------------------------------------------------------------------------

@@ -135,7 +135,7 @@ def test_axis_aligned_directions(env, levels):
 
 
 def test_leaf_table_properties(env):
-    """Every entry's point disk overlaps its leaf; every overlapped leaf lists the point; order is stable."""
+    """Every entry's leaf lies in its disk's box; every leaf holding a point of a disk lists it; order is stable."""
     torch, pcrl, oracle = env
     s = scenes.random_scene(11, tilt_sigma=0.1, pos_sigma=0.01, h=0.2)
     scene = pcrl.build_voxels(s.xyz, s.normal, s.label, (0.8, 0.4, 0.2), s.surfel_radius)
@@ -171,13 +171,24 @@ def test_leaf_table_properties(env):
     # soundness: the leaf of every entry lies within the point's disk box (+-1 for the rounding pad)
     lc = leaf_xyz[entry_leaf]
     assert np.all(lc >= lo[ids] - 1) and np.all(lc <= hi[ids] + 1)
-    # completeness: every leaf of the unpadded box lists the point
+    # completeness: every leaf that holds a point of the disk lists the point (the disk is sampled on
+    # rings out to its rim; samples within 1e-5 h of a leaf face are skipped as ambiguous)
     listed = set(zip(ids.tolist(), map(tuple, lc.tolist())))
+    r_s = float(np.float32(s.surfel_radius))
+    ang = np.linspace(0, 2 * np.pi, 24, endpoint=False)
+    n_checked = 0
     for i in range(0, len(p), 7):
-        for x in range(lo[i, 0], hi[i, 0] + 1):
-            for y in range(lo[i, 1], hi[i, 1] + 1):
-                for z in range(lo[i, 2], hi[i, 2] + 1):
-                    assert (i, (x, y, z)) in listed
+        a = np.cross(n[i], [1.0, 0.0, 0.0] if abs(n[i, 0]) < 0.9 else [0.0, 1.0, 0.0])
+        a /= np.linalg.norm(a)
+        b = np.cross(n[i], a)
+        for rr in (0.0, 0.4, 0.8, 0.999):
+            q = p[i] + rr * r_s * (np.cos(ang)[:, None] * a + np.sin(ang)[:, None] * b)
+            f = (q - org) / h
+            ok = np.all(np.abs(f - np.round(f)) > 1e-5, axis=1)
+            for cell in np.floor(f[ok]).astype(np.int64):
+                assert (i, tuple(cell.tolist())) in listed
+                n_checked += 1
+    assert n_checked > 1000
     # stability: point ids ascend within each leaf
     for a, c in zip(begin[:200], count[:200]):
         assert np.all(np.diff(ids[a:a + c]) > 0)
