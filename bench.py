@@ -31,9 +31,10 @@ if ROOT not in sys.path:
     sys.path.insert(0, ROOT)
 
 HBM_PEAK_GBS = 8000.0
-# sources the bounce kernel is compiled from: a PMC traffic figure is valid only for these exact bytes
+# sources of the bounce kernel and of the hierarchy it reads: a PMC traffic figure is valid only for
+# these exact bytes
 TRACE_SOURCES = ("paper_2402_13747_amd/csrc/trace.hip", "paper_2402_13747_amd/csrc/trace_core.h",
-                 "paper_2402_13747_amd/csrc/internal.h", "include/pcrl.h")
+                 "paper_2402_13747_amd/csrc/internal.h", "paper_2402_13747_amd/csrc/build.hip", "include/pcrl.h")
 
 
 def log(*a):
@@ -320,6 +321,23 @@ def bench_serve(args, pcrl, torch):
     print(json.dumps(out), flush=True)
 
 
+def copy_rate_gbs(torch, mib=1024, reps=5):
+    """Achievable HBM rate on this machine: a plain 1 GiB device-to-device copy (read + write bytes per second)."""
+    dev = torch.device("cuda", 0)
+    x = torch.ones(mib * (1 << 20) // 4, dtype=torch.float32, device=dev)
+    y = torch.empty_like(x)
+    y.copy_(x)
+    e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+    e0.record()
+    for _ in range(reps):
+        y.copy_(x)
+    e1.record()
+    torch.cuda.synchronize()
+    ms = e0.elapsed_time(e1) / reps
+    del x, y
+    return 2.0 * mib * (1 << 20) / (ms * 1e-3) / 1e9
+
+
 def bench_copy(args, torch):
     """Calibration for the HBM traffic counters: a plain device copy of known size."""
     dev = torch.device("cuda", 0)
@@ -455,6 +473,7 @@ def main():
         launch_bytes = float(np.mean([st_stats["algo_bytes_bounce"][b] for b in bl]))
         achieved = launch_bytes / (launch_ms * 1e-3) / 1e9
         traffic = measured_traffic(args.workload)
+        copy_gbs = copy_rate_gbs(torch)
         avg_ms = float(np.mean(kern_ms))
         bytes_per_step = float(st_stats["algo_bytes"])
         roof = {"bound": "hbm", "achieved": round(achieved, 2), "peak": HBM_PEAK_GBS, "unit": "GB/s",
@@ -462,6 +481,7 @@ def main():
                 "traffic": None if traffic is None else round(traffic),
                 "traffic_unit": "HBM bytes per launch (rocprofv3 FETCH_SIZE + WRITE_SIZE, copy-calibrated)",
                 "kernel": "k_trace<false,false> (bounce kernel, one launch per bounce 1..K)",
+                "copy_gbs": round(copy_gbs, 1), "frac_of_copy": round(achieved / copy_gbs, 4),
                 "launches_per_step": len(bl), "algo_bytes_per_launch": int(launch_bytes),
                 "bounce_ms": [round(float(np.mean([m[k] for m in kern_b])), 4) for k in range(K + 1)],
                 "launch_ms": round(launch_ms, 4), "source_hash": trace_source_hash(),
