@@ -190,9 +190,9 @@ __device__ __forceinline__ bool disk_meets_leaf(const KeyParams& kp, const float
     return d2 <= r * r && fabsf(dn) <= pr + kp.pad;
 }
 
-template <bool EMIT>
+template <bool EMIT, typename K>
 __device__ __forceinline__ uint32_t disk_leaves(const KeyParams& kp, const float* xyz, const float4* un, int64_t i,
-                                                uint64_t* keys, uint32_t* ids, uint32_t o) {
+                                                K* keys, uint32_t* ids, uint32_t o) {
     int lo[3], hi[3];
     disk_leaf_box(kp, xyz, un, i, lo, hi);
     const float p[3] = {xyz[3 * i], xyz[3 * i + 1], xyz[3 * i + 2]};
@@ -206,7 +206,7 @@ __device__ __forceinline__ uint32_t disk_leaves(const KeyParams& kp, const float
                 const bool one = lo[0] == hi[0] && lo[1] == hi[1] && lo[2] == hi[2];
                 if (!one && !disk_meets_leaf(kp, p, nv, x, y, z)) continue;
                 if (EMIT) {
-                    keys[o + k] = leaf_key_of(kp.v, x, y, z);
+                    keys[o + k] = (K)leaf_key_of(kp.v, x, y, z);
                     ids[o + k] = (uint32_t)i;
                 }
                 ++k;
@@ -218,14 +218,16 @@ __global__ __launch_bounds__(BUILD_BLOCK) void k_key_count(KeyParams kp, const f
                                                            uint32_t* cnt) {
     int64_t i = (int64_t)blockIdx.x * BUILD_BLOCK + threadIdx.x;
     if (i >= n) return;
-    cnt[i] = disk_leaves<false>(kp, xyz, un, i, nullptr, nullptr, 0);
+    cnt[i] = disk_leaves<false, uint64_t>(kp, xyz, un, i, nullptr, nullptr, 0);
 }
 
+// Keys are 32-bit when the hierarchical key fits (less sort traffic), else 64-bit.
+template <typename K>
 __global__ __launch_bounds__(BUILD_BLOCK) void k_key_emit(KeyParams kp, const float* xyz, const float4* un, int64_t n,
-                                                          const uint32_t* off, uint64_t* keys, uint32_t* ids) {
+                                                          const uint32_t* off, K* keys, uint32_t* ids) {
     int64_t i = (int64_t)blockIdx.x * BUILD_BLOCK + threadIdx.x;
     if (i >= n) return;
-    (void)disk_leaves<true>(kp, xyz, un, i, keys, ids, off[i]);
+    (void)disk_leaves<true, K>(kp, xyz, un, i, keys, ids, off[i]);
 }
 
 // ---------------------------------------------------------------------------
@@ -238,7 +240,8 @@ struct LevelShifts {
 };
 
 // flag[l][e] = entry e starts a new node of level l
-__global__ void k_level_flags(const uint64_t* keys, int64_t m, LevelShifts ls, uint32_t* flags) {
+template <typename K>
+__global__ void k_level_flags(const K* keys, int64_t m, LevelShifts ls, uint32_t* flags) {
     int64_t e = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
     if (e >= m) return;
     const uint64_t k = keys[e];
@@ -258,7 +261,8 @@ struct HierOut {
 // For every entry that opens a node: register the node with its parent.
 // scans[l][e] is the exclusive scan of the level-l flags, so the node index
 // of entry e at level l is scans[l][e] + flag - 1.
-__global__ void k_hier_link(const uint64_t* keys, int64_t m, LevelShifts ls, SceneView v, const uint32_t* scans,
+template <typename K>
+__global__ void k_hier_link(const K* keys, int64_t m, LevelShifts ls, SceneView v, const uint32_t* scans,
                             HierOut h) {
     int64_t e = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
     if (e >= m) return;
@@ -646,18 +650,32 @@ static int build_hierarchy(const float* xyz, const float4* unit_nrm, const uint3
     const int64_t m = host_tot;
     hb.n_entries = m;
 
-    // emit and sort (key, local point index)
+    // emit and sort (key, local point index); 32-bit keys when they fit
+    const bool narrow = v.key_bits <= 32;
     uint64_t* keys = nullptr;
+    uint32_t* keys32 = nullptr;
     uint32_t* ids = nullptr;
-    if ((rc = T.alloc(&keys, (size_t)m)) || (rc = B.alloc(&ids, (size_t)m))) return rc;
-    hipLaunchKernelGGL(k_key_emit, dim3(blocks_for(n)), dim3(BUILD_BLOCK), 0, s, kp, xyz, unit_nrm, n, cnt, keys, ids);
-    if ((rc = radix_sort_u64(keys, ids, m, v.key_bits, s))) return rc;
+    if ((rc = B.alloc(&ids, (size_t)m))) return rc;
+    if (narrow) {
+        if ((rc = T.alloc(&keys32, (size_t)m))) return rc;
+        hipLaunchKernelGGL(k_key_emit<uint32_t>, dim3(blocks_for(n)), dim3(BUILD_BLOCK), 0, s, kp, xyz, unit_nrm, n,
+                           cnt, keys32, ids);
+        if ((rc = radix_sort_u32(keys32, ids, m, v.key_bits, s))) return rc;
+    } else {
+        if ((rc = T.alloc(&keys, (size_t)m))) return rc;
+        hipLaunchKernelGGL(k_key_emit<uint64_t>, dim3(blocks_for(n)), dim3(BUILD_BLOCK), 0, s, kp, xyz, unit_nrm, n,
+                           cnt, keys, ids);
+        if ((rc = radix_sort_u64(keys, ids, m, v.key_bits, s))) return rc;
+    }
     hb.entry_point = ids;
 
     // per-level node boundaries
     uint32_t *scans = nullptr, *ltot = nullptr;
     if ((rc = T.alloc(&scans, (size_t)L * m)) || (rc = T.alloc(&ltot, PCRL_MAX_LEVELS))) return rc;
-    hipLaunchKernelGGL(k_level_flags, dim3(blocks_for(m)), dim3(BUILD_BLOCK), 0, s, keys, m, ls, scans);
+    if (narrow)
+        hipLaunchKernelGGL(k_level_flags<uint32_t>, dim3(blocks_for(m)), dim3(BUILD_BLOCK), 0, s, keys32, m, ls, scans);
+    else
+        hipLaunchKernelGGL(k_level_flags<uint64_t>, dim3(blocks_for(m)), dim3(BUILD_BLOCK), 0, s, keys, m, ls, scans);
     for (int l = 0; l < L; ++l)
         if ((rc = scan_u32(scans + (size_t)l * m, scans + (size_t)l * m, m, ltot + l, s))) return rc;
     uint32_t host_nodes[PCRL_MAX_LEVELS] = {0, 0, 0, 0};
@@ -692,7 +710,12 @@ static int build_hierarchy(const float* xyz, const float4* unit_nrm, const uint3
     if ((rc = B.alloc(&leaf, (size_t)n_leaves)) || (rc = B.alloc(&lkey, (size_t)n_leaves))) return rc;
     ho.leaf = leaf;
     ho.leaf_key = lkey;
-    hipLaunchKernelGGL(k_hier_link, dim3(blocks_for(m)), dim3(BUILD_BLOCK), 0, s, keys, m, ls, v, scans, ho);
+    if (narrow)
+        hipLaunchKernelGGL(k_hier_link<uint32_t>, dim3(blocks_for(m)), dim3(BUILD_BLOCK), 0, s, keys32, m, ls, v, scans,
+                           ho);
+    else
+        hipLaunchKernelGGL(k_hier_link<uint64_t>, dim3(blocks_for(m)), dim3(BUILD_BLOCK), 0, s, keys, m, ls, v, scans,
+                           ho);
     for (int l = 0; l + 1 < L; ++l)
         hipLaunchKernelGGL(k_brick_base, dim3(blocks_for(host_nodes[l])), dim3(BUILD_BLOCK), 0, s, ho.mask[l],
                            ho.first_child[l], (int64_t)host_nodes[l], v.nw[l], (uint32_t*)v.base[l]);
