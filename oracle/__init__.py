@@ -12,6 +12,11 @@ definition of what the HIP path computes and shares no code with it.
                          with the kappa shortest kept (Section 2.2.3)
 * ``image_method``       closed-form image-source paths in a box room
                          (the refinement reference of Section 2.3)
+* ``refine(...)``        path refinement (Section 2.3, Eq. 2): gradient
+                         descent on the path length with re-tracing, brute
+                         force (``oracle.c``)
+* ``refine_dedup(...)``  refined-path dedup: shortest per label sequence,
+                         then first-Fresnel-zone uniqueness (Section 2.3)
 
 Parity unpinned: sigma (reception sphere scale), r_s (surfel radius) and
 t_eps (self-intersection distance) are conventions the paper does not fix;
@@ -62,6 +67,25 @@ class OracleArgs(C.Structure):
     ]
 
 
+class OracleRefineArgs(C.Structure):
+    _fields_ = [
+        ("xyz", C.c_void_p), ("nrm", C.c_void_p), ("label", C.c_void_p), ("n_pts", C.c_int64),
+        ("r_s", C.c_double), ("t_eps", C.c_double), ("n_paths", C.c_int64), ("K", C.c_int32),
+        ("tx", C.c_void_p), ("rx", C.c_void_p), ("n_refl", C.c_void_p), ("pts", C.c_void_p),
+        ("max_iters", C.c_int32), ("grad_tol", C.c_double), ("step", C.c_double), ("n_threads", C.c_int32),
+        ("status", C.c_void_p), ("iters", C.c_void_p), ("grad", C.c_void_p), ("length", C.c_void_p),
+        ("out_pts", C.c_void_p), ("out_id", C.c_void_p), ("out_label", C.c_void_p),
+    ]
+
+
+# refinement outcome of a path
+REF_VALID, REF_NOT_CONVERGED, REF_MISS, REF_WRONG_SIDE, REF_OCCLUDED, REF_DEGENERATE = range(6)
+# Table 1: convergence threshold delta and refinement iterations rho; carrier 60 GHz
+REF_GRAD_TOL = 1e-4
+REF_MAX_ITERS = 2000
+CARRIER_HZ = 60e9
+LIGHT_SPEED = 299_792_458.0
+
 _lib = None
 
 
@@ -77,6 +101,8 @@ def _load():
         lib.oracle_ray_spacing.restype = C.c_double
         lib.oracle_launch.argtypes = [C.POINTER(OracleArgs)]
         lib.oracle_launch.restype = C.c_int
+        lib.oracle_refine.argtypes = [C.POINTER(OracleRefineArgs)]
+        lib.oracle_refine.restype = C.c_int
         _lib = lib
     return _lib
 
@@ -213,3 +239,102 @@ def dedup(res, K, kappa=1, include_ambiguous=False):
         rows.sort(key=lambda x: (x[0], x[2]))
         paths[key] = {"count": len(rows), "rows": rows[:kappa], "all": rows}
     return paths, sorted(paths.keys()), amb_keys
+
+
+def refine(xyz, normal, label, r_s, t_eps, tx, rx, n_refl, pts, max_iters=REF_MAX_ITERS, grad_tol=REF_GRAD_TOL,
+           step=0.5, n_threads=None):
+    """Refine coarse paths into exact paths (Section 2.3, Eq. 2), FP64 brute force.
+
+    Per path p: ``tx[p]``, ``rx[p]`` (positions), ``n_refl[p]`` = N and the
+    coarse interaction points ``pts[p, :N]`` ([n, K, 3]).  Returns a dict:
+    ``status`` (REF_*), ``iters`` (gradient steps), ``grad`` (final norm of
+    the tangent-plane gradient), ``length`` (f of Eq. 2), ``points``
+    [n, K, 3] (NaN past N), ``ids`` and ``labels`` [n, K] (-1 past N).
+    """
+    lib = _load()
+    xyz = np.ascontiguousarray(xyz, np.float32)
+    normal = np.ascontiguousarray(normal, np.float32)
+    label = np.ascontiguousarray(label, np.uint32)
+    tx = np.ascontiguousarray(np.asarray(tx, np.float64).reshape(-1, 3))
+    rx = np.ascontiguousarray(np.asarray(rx, np.float64).reshape(-1, 3))
+    n_refl = np.ascontiguousarray(n_refl, np.int32)
+    pts = np.ascontiguousarray(pts, np.float64)
+    n = n_refl.shape[0]
+    K = pts.shape[1] if pts.ndim == 3 else 0
+    out = {"status": np.empty(n, np.int32), "iters": np.empty(n, np.int32), "grad": np.empty(n),
+           "length": np.empty(n), "points": np.empty((n, max(K, 1), 3)), "ids": np.empty((n, max(K, 1)), np.int64),
+           "labels": np.empty((n, max(K, 1)), np.int64)}
+    a = OracleRefineArgs()
+    a.xyz, a.nrm, a.label, a.n_pts = _p(xyz), _p(normal), _p(label), xyz.shape[0]
+    a.r_s, a.t_eps, a.n_paths, a.K = float(r_s), float(t_eps), n, K
+    a.tx, a.rx, a.n_refl, a.pts = _p(tx), _p(rx), _p(n_refl), _p(pts)
+    a.max_iters, a.grad_tol, a.step = int(max_iters), float(grad_tol), float(step)
+    a.n_threads = int(n_threads or default_threads())
+    a.status, a.iters, a.grad, a.length = _p(out["status"]), _p(out["iters"]), _p(out["grad"]), _p(out["length"])
+    a.out_pts, a.out_id, a.out_label = _p(out["points"]), _p(out["ids"]), _p(out["labels"])
+    rc = lib.oracle_refine(C.byref(a))
+    if rc != 0:
+        raise RuntimeError(f"oracle_refine failed with status {rc}")
+    out["points"] = out["points"][:, :K]
+    out["ids"] = out["ids"][:, :K]
+    out["labels"] = out["labels"][:, :K]
+    return out
+
+
+def fresnel_radius(d1, d2, wavelength):
+    """Radius of the first Fresnel zone at distances d1, d2 from the two ends."""
+    return float(np.sqrt(wavelength * d1 * d2 / (d1 + d2)))
+
+
+def refine_dedup(group, n_refl, labels, points, length, status, tx, carrier_hz=CARRIER_HZ):
+    """Unique exact paths among refined ones (Section 2.3, last paragraph).
+
+    ``group[p]`` identifies the (TX, RX) pair of path p; ``tx[p]`` is its TX
+    position.  Paths are compared only within one (TX, RX) pair and one
+    number of interactions (reflections only: the chain of interactions is
+    their number).  In order of increasing length (ties: smaller index):
+      1. a valid path whose label sequence already occurred is dropped (the
+         shortest path of every label sequence is kept);
+      2. a path is dropped if every interaction point lies within the first
+         Fresnel zone of the corresponding point of an already kept path
+         (radius sqrt(lambda d1 d2 / (d1 + d2)), d1 and d2 the kept path's
+         lengths from the TX to the point and from the point to the RX).
+    ``carrier_hz <= 0`` skips step 2.  Returns a bool array ``kept``.
+    """
+    n = len(n_refl)
+    kept = np.zeros(n, bool)
+    lam = LIGHT_SPEED / carrier_hz if carrier_hz > 0 else 0.0
+    by_group = defaultdict(list)
+    for p in range(n):
+        if status[p] == REF_VALID:
+            by_group[(int(group[p]), int(n_refl[p]))].append(p)
+    for (_, N), rows in by_group.items():
+        rows.sort(key=lambda p: (float(length[p]), p))
+        seen = set()
+        kept_rows = []
+        for p in rows:
+            lab = tuple(int(x) for x in labels[p][:N])
+            if lab in seen:
+                continue
+            seen.add(lab)
+            dup = False
+            if lam > 0:
+                for q in kept_rows:
+                    d1 = 0.0
+                    prev = np.asarray(tx[q], np.float64)
+                    close = True
+                    for k in range(N):
+                        cq = np.asarray(points[q][k], np.float64)
+                        d1 += float(np.linalg.norm(cq - prev))
+                        prev = cq
+                        r_f = fresnel_radius(d1, float(length[q]) - d1, lam)
+                        if np.linalg.norm(np.asarray(points[p][k], np.float64) - cq) > r_f:
+                            close = False
+                            break
+                    if close:
+                        dup = True
+                        break
+            if not dup:
+                kept_rows.append(p)
+                kept[p] = True
+    return kept

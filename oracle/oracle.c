@@ -44,6 +44,7 @@
 
 #define ORACLE_MAXACC 16
 #define ORACLE_DEN_SKIP 1e-12
+#define ORACLE_MAXN 8           /* most reflections of a refined path */
 
 typedef struct {
     /* scene */
@@ -427,6 +428,245 @@ int oracle_launch(OracleArgs* a)
         }
     }
     for (int k = 0; W && k < nt; ++k) rec_free(&W[k].rec);
+    free(W); free(T);
+    free(P.px); free(P.py); free(P.pz); free(P.nx); free(P.ny); free(P.nz);
+    return status;
+}
+
+/* ------------------------------------------------------------------------ */
+/* path refinement (Section 2.3, Eq. 2)                                      */
+/* ------------------------------------------------------------------------ */
+
+/*
+ * Each coarse path (TX, interaction points q_1..q_N, RX) is refined into an
+ * exact path by minimising its length f = sum_k |I_k - I_{k+1}| (Eq. 2),
+ * I_0 = TX, I_{N+1} = RX.  An interaction point I_k = c_k + r_k u_k + s_k v_k
+ * moves in the tangent plane of the surface at its current position c_k
+ * (u_k, v_k orthonormal to the normal n_k there); r_k u_k + s_k v_k is the
+ * projection of the step onto that plane, so no explicit basis is needed.
+ * One iteration:
+ *   1. G_k = (I_k - I_{k-1})/|I_k - I_{k-1}| + (I_k - I_{k+1})/|I_k - I_{k+1}|,
+ *      the derivative of the local length f_k with respect to I_k;
+ *      g_k = G_k - (G_k . n_k) n_k = (df_k/dr_k) u_k + (df_k/ds_k) v_k;
+ *   2. stop (converged) when |(g_1 .. g_N)| < delta;
+ *   3. every point takes the gradient step R_k = c_k - a_k g_k at once;
+ *   4. for k = 1..N a ray is traced from the (new) I_{k-1} towards R_k; its
+ *      nearest hit gives the new c_k and n_k (the hit surfel's normal); a
+ *      ray that hits nothing ends the refinement (invalid path).
+ * After rho iterations without convergence the path is invalid.  The step
+ * size is not given in the paper: a_k = eta / (1/|c_k - I_{k-1}| +
+ * 1/|c_k - I_{k+1}|) scales the step by the inverse of the largest curvature
+ * of f_k in the tangent plane.  The initial c_k are found the same way as in
+ * step 4, tracing towards the coarse points q_k.  A converged path is valid
+ * if both neighbours of every interaction lie on the same side of its
+ * surface (a reflection, not a crossing) and the last segment to the RX is
+ * not blocked (the segments before it end at nearest hits by construction).
+ */
+
+#define ORACLE_REF_VALID 0
+#define ORACLE_REF_NOT_CONVERGED 1
+#define ORACLE_REF_MISS 2
+#define ORACLE_REF_WRONG_SIDE 3
+#define ORACLE_REF_OCCLUDED 4
+#define ORACLE_REF_DEGENERATE 5
+
+typedef struct {
+    const float* xyz;          /* [n_pts*3] */
+    const float* nrm;          /* [n_pts*3] */
+    const uint32_t* label;     /* [n_pts] */
+    int64_t n_pts;
+    double r_s, t_eps;
+    int64_t n_paths;
+    int32_t K;                 /* stride of the per-path point arrays */
+    const double* tx;          /* [n_paths*3] TX of each path */
+    const double* rx;          /* [n_paths*3] RX of each path */
+    const int32_t* n_refl;     /* [n_paths] N */
+    const double* pts;         /* [n_paths*K*3] coarse interaction points */
+    int32_t max_iters;         /* rho */
+    double grad_tol;           /* delta */
+    double step;               /* eta */
+    int32_t n_threads;
+    int32_t* status;           /* ORACLE_REF_* */
+    int32_t* iters;            /* gradient steps taken */
+    double* grad;              /* final |g| */
+    double* length;            /* f of the final points */
+    double* out_pts;           /* [n_paths*K*3], NaN past N */
+    int64_t* out_id;           /* [n_paths*K] surfel of each interaction, -1 past N */
+    int64_t* out_label;        /* [n_paths*K], -1 past N */
+} OracleRefineArgs;
+
+typedef struct {
+    const OracleRefineArgs* a;
+    const Pts64* P;
+    int64_t lo, hi;
+} RefWork;
+
+static double dist3(const double* p, const double* q)
+{
+    double e[3] = {p[0] - q[0], p[1] - q[1], p[2] - q[2]};
+    return sqrt(dot3(e, e));
+}
+
+/* Nearest hit of the ray from o towards target (excluding surfel `last`).
+ * Returns 1 with the hit point, normal and surfel, 0 on a miss, -1 if the
+ * target coincides with o. */
+static int trace_towards(const OracleArgs* A, const Pts64* P, const double* o, const double* target, int64_t last,
+                         double* c, double* n, int64_t* m, double* t_out)
+{
+    double d[3] = {target[0] - o[0], target[1] - o[1], target[2] - o[2]};
+    double len = sqrt(dot3(d, d));
+    if (!(len > 0.0)) return -1;
+    d[0] /= len; d[1] /= len; d[2] /= len;
+    int64_t best;
+    double tb;
+    int32_t na;
+    int64_t acc[ORACLE_MAXACC];
+    nearest_hit(A, P, o, d, last, 0, &best, &tb, &na, acc);
+    if (t_out) *t_out = tb;
+    if (best < 0) return 0;
+    c[0] = o[0] + tb * d[0]; c[1] = o[1] + tb * d[1]; c[2] = o[2] + tb * d[2];
+    n[0] = P->nx[best]; n[1] = P->ny[best]; n[2] = P->nz[best];
+    *m = best;
+    return 1;
+}
+
+static void refine_one(const OracleRefineArgs* a, const OracleArgs* A, const Pts64* P, int64_t p)
+{
+    const int32_t K = a->K;
+    const int32_t N = a->n_refl[p];
+    const double* T = a->tx + 3 * p;
+    const double* R = a->rx + 3 * p;
+    double c[ORACLE_MAXN][3], n[ORACLE_MAXN][3], g[ORACLE_MAXN][3], tgt[ORACLE_MAXN][3];
+    int64_t m[ORACLE_MAXN];
+    int32_t status = ORACLE_REF_VALID, it = 0;
+    double gnorm = 0.0;
+    for (int32_t k = 0; k < K; ++k) {
+        a->out_id[p * K + k] = -1;
+        a->out_label[p * K + k] = -1;
+        a->out_pts[(p * K + k) * 3] = a->out_pts[(p * K + k) * 3 + 1] = a->out_pts[(p * K + k) * 3 + 2] = NAN;
+    }
+    for (int32_t k = 0; k < N; ++k)
+        for (int j = 0; j < 3; ++j) tgt[k][j] = a->pts[(p * K + k) * 3 + j];
+    /* I(k) for k = 0..N+1 */
+#define IPT(k) ((k) == 0 ? T : ((k) == N + 1 ? R : c[(k) - 1]))
+    for (;;) {
+        /* trace towards the targets: the coarse points first, then the gradient steps */
+        int64_t last = -1;
+        for (int32_t k = 0; k < N && status == ORACLE_REF_VALID; ++k) {
+            int r = trace_towards(A, P, IPT(k), tgt[k], last, c[k], n[k], &m[k], NULL);
+            if (r < 0) status = ORACLE_REF_DEGENERATE;
+            else if (r == 0) status = ORACLE_REF_MISS;
+            last = m[k];
+        }
+        if (status != ORACLE_REF_VALID) break;
+        /* gradient of the path length in the tangent planes */
+        double gg = 0.0;
+        for (int32_t k = 1; k <= N; ++k) {
+            const double* I = IPT(k);
+            const double* Ip = IPT(k - 1);
+            const double* In = IPT(k + 1);
+            double lp = dist3(I, Ip), ln = dist3(I, In);
+            if (!(lp > 0.0) || !(ln > 0.0)) { status = ORACLE_REF_DEGENERATE; break; }
+            double G[3];
+            for (int j = 0; j < 3; ++j) G[j] = (I[j] - Ip[j]) / lp + (I[j] - In[j]) / ln;
+            double gn = dot3(G, n[k - 1]);
+            for (int j = 0; j < 3; ++j) g[k - 1][j] = G[j] - gn * n[k - 1][j];
+            gg += dot3(g[k - 1], g[k - 1]);
+        }
+        if (status != ORACLE_REF_VALID) break;
+        gnorm = sqrt(gg);
+        if (gnorm < a->grad_tol) break;
+        if (it == a->max_iters) { status = ORACLE_REF_NOT_CONVERGED; break; }
+        /* simultaneous gradient step of every point */
+        for (int32_t k = 1; k <= N; ++k) {
+            const double* I = IPT(k);
+            double step = a->step / (1.0 / dist3(I, IPT(k - 1)) + 1.0 / dist3(I, IPT(k + 1)));
+            for (int j = 0; j < 3; ++j) tgt[k - 1][j] = I[j] - step * g[k - 1][j];
+        }
+        ++it;
+    }
+    if (status == ORACLE_REF_VALID) {
+        /* a reflection keeps both neighbours on one side of the surface */
+        for (int32_t k = 1; k <= N; ++k) {
+            const double* I = IPT(k);
+            double sp = 0.0, sn = 0.0;
+            for (int j = 0; j < 3; ++j) {
+                sp += (IPT(k - 1)[j] - I[j]) * n[k - 1][j];
+                sn += (IPT(k + 1)[j] - I[j]) * n[k - 1][j];
+            }
+            if (!(sp * sn > 0.0)) { status = ORACLE_REF_WRONG_SIDE; break; }
+        }
+    }
+    if (status == ORACLE_REF_VALID) {
+        /* the last segment must reach the RX unblocked */
+        double cc[3], nn[3], tb;
+        int64_t mm;
+        int r = trace_towards(A, P, IPT(N), R, N > 0 ? m[N - 1] : -1, cc, nn, &mm, &tb);
+        if (r < 0) status = ORACLE_REF_DEGENERATE;
+        else if (r > 0 && tb < dist3(IPT(N), R)) status = ORACLE_REF_OCCLUDED;
+    }
+    double f = 0.0;
+    int finite = (status != ORACLE_REF_MISS && status != ORACLE_REF_DEGENERATE);
+    for (int32_t k = 0; k <= N && finite; ++k) f += dist3(IPT(k), IPT(k + 1));
+    a->length[p] = finite ? f : NAN;
+    a->status[p] = status;
+    a->iters[p] = it;
+    a->grad[p] = finite ? gnorm : NAN;
+    if (finite)
+        for (int32_t k = 0; k < N; ++k) {
+            a->out_id[p * K + k] = m[k];
+            a->out_label[p * K + k] = (int64_t)a->label[m[k]];
+            for (int j = 0; j < 3; ++j) a->out_pts[(p * K + k) * 3 + j] = c[k][j];
+        }
+#undef IPT
+}
+
+static void* refine_worker(void* q)
+{
+    RefWork* w = (RefWork*)q;
+    OracleArgs A;
+    memset(&A, 0, sizeof(A));
+    A.n_pts = w->a->n_pts;
+    A.r_s = w->a->r_s;
+    A.t_eps = w->a->t_eps;
+    for (int64_t p = w->lo; p < w->hi; ++p) refine_one(w->a, &A, w->P, p);
+    return NULL;
+}
+
+/* Returns 0, -1 on bad arguments, -2 out of host memory. */
+int oracle_refine(OracleRefineArgs* a)
+{
+    if (!a || a->n_pts < 0 || (a->n_pts > 0 && (!a->xyz || !a->nrm || !a->label)) || a->n_paths < 0 ||
+        a->K < 0 || a->K > ORACLE_MAXN || !(a->r_s > 0.0) || a->max_iters < 0 || !(a->step > 0.0))
+        return -1;
+    for (int64_t p = 0; p < a->n_paths; ++p)
+        if (a->n_refl[p] < 0 || a->n_refl[p] > a->K) return -1;
+    Pts64 P;
+    size_t nb = (size_t)(a->n_pts > 0 ? a->n_pts : 1) * sizeof(double);
+    P.px = malloc(nb); P.py = malloc(nb); P.pz = malloc(nb);
+    P.nx = malloc(nb); P.ny = malloc(nb); P.nz = malloc(nb);
+    int status = (!P.px || !P.py || !P.pz || !P.nx || !P.ny || !P.nz) ? -2 : 0;
+    for (int64_t q = 0; q < a->n_pts && !status; ++q) {
+        P.px[q] = a->xyz[3 * q]; P.py[q] = a->xyz[3 * q + 1]; P.pz[q] = a->xyz[3 * q + 2];
+        double nx = a->nrm[3 * q], ny = a->nrm[3 * q + 1], nz = a->nrm[3 * q + 2];
+        double len = sqrt(nx * nx + ny * ny + nz * nz);
+        if (!(len > 0.0) || !isfinite(len)) status = -1;
+        else { P.nx[q] = nx / len; P.ny[q] = ny / len; P.nz[q] = nz / len; }
+    }
+    int nt = a->n_threads > 0 ? a->n_threads : 1;
+    if (nt > a->n_paths) nt = (int)(a->n_paths > 0 ? a->n_paths : 1);
+    RefWork* W = calloc((size_t)nt, sizeof(RefWork));
+    pthread_t* T = calloc((size_t)nt, sizeof(pthread_t));
+    if (!status && (!W || !T)) status = -2;
+    if (!status) {
+        for (int k = 0; k < nt; ++k) {
+            W[k].a = a; W[k].P = &P;
+            W[k].lo = a->n_paths * k / nt; W[k].hi = a->n_paths * (k + 1) / nt;
+        }
+        for (int k = 1; k < nt; ++k) pthread_create(&T[k], NULL, refine_worker, &W[k]);
+        refine_worker(&W[0]);
+        for (int k = 1; k < nt; ++k) pthread_join(T[k], NULL);
+    }
     free(W); free(T);
     free(P.px); free(P.py); free(P.pz); free(P.nx); free(P.ny); free(P.nz);
     return status;

@@ -1,0 +1,233 @@
+"""Pins of the oracle's path refinement (Section 2.3, Eq. 2) and refined-path dedup.
+
+The refinement is pinned against closed forms that do not use the oracle's
+own arithmetic:
+  * the image method: in the empty box room every coarse path refines to the
+    image-source path of its reflection sequence, whose squared lengths are
+    the fixtures of tests/golden/box_room_image_paths.txt, and the dedup
+    leaves exactly those 25 sequences;
+  * a single tilted plane: the exact reflection point is where the line from
+    the mirrored TX to the RX crosses the plane;
+  * outcomes that geometry decides: a straight crossing of a free plate is
+    not a reflection, a plate over the last segment blocks it, a specular
+    point off a finite plate makes the re-traced ray miss.
+The dedup is pinned on hand-made paths with the first Fresnel zone radius
+sqrt(lambda d1 d2 / (d1 + d2)) worked out by hand at 60 GHz.
+"""
+import math
+import os
+
+import numpy as np
+import pytest
+
+import oracle
+import scenes
+from oracle import image_method
+
+HERE = os.path.dirname(os.path.abspath(__file__))
+
+
+def _golden():
+    out = {}
+    for line in open(os.path.join(HERE, "golden", "box_room_image_paths.txt")):
+        if line.startswith("#"):
+            continue
+        name, l2 = line.split()
+        seq = () if name == "-" else tuple(int(x) for x in name.split(","))
+        out[seq] = float(l2)
+    return out
+
+
+def _scene(faces, h):
+    xyz, nrm, lab = scenes._sample_faces(faces, h)
+    return xyz.astype(np.float32), nrm.astype(np.float32), lab.astype(np.uint32)
+
+
+def _refine_one(xyz, nrm, lab, r_s, tx, rx, pts, **kw):
+    pts = np.asarray(pts, np.float64).reshape(1, -1, 3)
+    n_refl = np.array([pts.shape[1]], np.int32)
+    return oracle.refine(xyz, nrm, lab, r_s, 1e-5, np.asarray(tx, np.float64)[None], np.asarray(rx, np.float64)[None],
+                         n_refl, pts, **kw)
+
+
+@pytest.fixture(scope="module")
+def box_refined():
+    s = scenes.box_room()
+    K = 2
+    t_eps = 1e-5 * math.sqrt(10 ** 2 + 8 ** 2 + 3 ** 2)
+    res = oracle.launch(s.xyz, s.normal, s.label, s.tx, s.rx, oracle.fibonacci(s.n_rays), K, s.surfel_radius, t_eps)
+    paths, keys, _ = oracle.dedup(res, K, kappa=5)
+    rows = [(key, r) for key in keys for r in paths[key]["rows"]]
+    n = len(rows)
+    pts = np.full((n, K, 3), np.nan)
+    for i, (key, r) in enumerate(rows):
+        pts[i, :key[2]] = res["pts"][r[3], :key[2]].astype(np.float32)  # the coarse points, as FP32 records hold them
+    txp = np.repeat(s.tx.astype(np.float64), n, 0)
+    rxp = np.repeat(s.rx.astype(np.float64), n, 0)
+    nr = np.array([key[2] for key, _ in rows], np.int32)
+    out = oracle.refine(s.xyz, s.normal, s.label, s.surfel_radius, t_eps, txp, rxp, nr, pts, step=0.75)
+    return s, rows, nr, txp, out
+
+
+def test_box_room_refines_to_image_paths(box_refined):
+    s, rows, nr, _, out = box_refined
+    gold = _golden()
+    assert (out["status"] == oracle.REF_VALID).all()
+    assert (out["grad"] < oracle.REF_GRAD_TOL).all()
+    img = image_method.box_room_paths(s.tx[0], s.rx[0], (10.0, 8.0, 3.0), 2)
+    for i, (key, _) in enumerate(rows):
+        seq = tuple(int(x) for x in out["labels"][i, :nr[i]])
+        assert seq == key[3], (i, seq, key)        # refinement keeps the walls of the coarse path
+        L_img = math.sqrt(gold[seq])
+        # the image path is the shortest path through its planes: f >= L_img, and at
+        # a gradient below 1e-4 the excess is second order (below 1e-7 relative)
+        assert L_img * (1 - 1e-12) <= out["length"][i] <= L_img * (1 + 1e-7), (seq, out["length"][i], L_img)
+        # the points converge only to within |g| / (smallest tangent curvature of f),
+        # a few mm where a segment grazes its wall
+        for k, q in enumerate(img[seq][1]):
+            assert np.linalg.norm(out["points"][i, k] - q) < 1e-2, (seq, k)
+
+
+def test_box_room_dedup_leaves_the_image_sequences(box_refined):
+    s, rows, nr, txp, out = box_refined
+    kept = oracle.refine_dedup(np.zeros(len(rows)), nr, out["labels"], out["points"], out["length"], out["status"],
+                               txp)
+    got = sorted(tuple(int(x) for x in out["labels"][i, :nr[i]]) for i in np.nonzero(kept)[0])
+    assert got == sorted(_golden())
+    assert len(got) == 25
+
+
+def _mirror(p, c, n):
+    p = np.asarray(p, np.float64)
+    return p - 2.0 * np.dot(p - c, n) * n
+
+
+def test_tilted_plane_reflection_point():
+    rng = np.random.default_rng(5)
+    q, _ = np.linalg.qr(rng.normal(size=(3, 3)))
+    u, v, n = q[:, 0] * 4.0, q[:, 1] * 4.0, q[:, 2]
+    c = np.array([1.0, 2.0, 0.5])
+    xyz, nrm, lab = _scene([(c - 0.5 * u - 0.5 * v, u, v, n, 7)], 0.05)
+    r_s = 0.75 * 0.05
+    tx = c + 1.5 * n + 0.4 * q[:, 0]
+    rx = c + 1.0 * n - 0.5 * q[:, 1]
+    img = _mirror(tx, c, n)
+    lam = np.dot(c - img, n) / np.dot(rx - img, n)
+    spec = img + lam * (rx - img)
+    coarse = spec + 0.3 * q[:, 0] - 0.2 * q[:, 1]     # a point of the plane, 36 cm off
+    out = _refine_one(xyz, nrm, lab, r_s, tx, rx, [coarse])
+    assert out["status"][0] == oracle.REF_VALID and out["labels"][0, 0] == 7
+    L = np.linalg.norm(rx - img)
+    # the surfels hold the plane rounded to FP32 (a few 1e-7 m off the exact plane)
+    assert abs(out["length"][0] - L) <= 1e-6 * L
+    assert np.linalg.norm(out["points"][0, 0] - spec) < 2e-3
+    assert 0 < out["iters"][0] < 200
+
+
+def test_crossing_a_free_plate_is_not_a_reflection():
+    # TX above, RX below a horizontal plate: the length is smallest where the
+    # straight line crosses the plate, which is a stationary point but no reflection
+    xyz, nrm, lab = _scene([((-1.0, -1.0, 0.0), (2.0, 0, 0), (0, 2.0, 0), (0, 0, 1.0), 1)], 0.05)
+    out = _refine_one(xyz, nrm, lab, 0.0375, (0.0, 0.0, 1.0), (0.4, 0.2, -1.0), [(0.5, -0.3, 0.0)])
+    assert out["status"][0] == oracle.REF_WRONG_SIDE
+    assert np.linalg.norm(out["points"][0, 0] - (0.2, 0.1, 0.0)) < 2e-3
+
+
+def test_plate_over_last_segment_occludes():
+    floor = ((-3.0, -3.0, 0.0), (10.0, 0, 0), (0, 6.0, 0), (0, 0, 1.0), 0)
+    plate = ((2.8, -0.2, 1.0), (0.4, 0, 0), (0, 0.4, 0), (0, 0, 1.0), 1)   # over (3, 0, 1)
+    xyz, nrm, lab = _scene([floor, plate], 0.05)
+    tx, rx = (0.0, 0.0, 2.0), (4.0, 0.0, 2.0)
+    out = _refine_one(xyz, nrm, lab, 0.0375, tx, rx, [(1.7, 0.3, 0.0)])
+    assert out["status"][0] == oracle.REF_OCCLUDED
+    assert np.linalg.norm(out["points"][0, 0] - (2.0, 0.0, 0.0)) < 2e-3
+    # without the plate the same path is valid, of length |TX' - RX|
+    xyz, nrm, lab = _scene([floor], 0.05)
+    out = _refine_one(xyz, nrm, lab, 0.0375, tx, rx, [(1.7, 0.3, 0.0)])
+    assert out["status"][0] == oracle.REF_VALID
+    assert abs(out["length"][0] - math.sqrt(4 ** 2 + 4 ** 2)) < 1e-6
+
+
+def test_specular_point_off_the_plate_misses():
+    xyz, nrm, lab = _scene([((-0.5, -0.5, 0.0), (1.0, 0, 0), (0, 1.0, 0), (0, 0, 1.0), 2)], 0.05)
+    out = _refine_one(xyz, nrm, lab, 0.0375, (3.0, 0.0, 1.0), (5.0, 0.0, 1.0), [(0.4, 0.0, 0.0)])
+    assert out["status"][0] == oracle.REF_MISS
+    assert np.isnan(out["length"][0]) and out["ids"][0, 0] == -1
+
+
+def test_iteration_limit():
+    xyz, nrm, lab = _scene([((-3.0, -3.0, 0.0), (6.0, 0, 0), (0, 6.0, 0), (0, 0, 1.0), 0)], 0.05)
+    out = _refine_one(xyz, nrm, lab, 0.0375, (0.0, 0.0, 1.0), (2.0, 0.0, 1.0), [(-1.0, 1.0, 0.0)], max_iters=3)
+    assert out["status"][0] == oracle.REF_NOT_CONVERGED and out["iters"][0] == 3
+    assert out["grad"][0] >= oracle.REF_GRAD_TOL
+    full = _refine_one(xyz, nrm, lab, 0.0375, (0.0, 0.0, 1.0), (2.0, 0.0, 1.0), [(-1.0, 1.0, 0.0)])
+    assert full["status"][0] == oracle.REF_VALID and full["iters"][0] > 3
+    assert np.linalg.norm(full["points"][0, 0] - (1.0, 0.0, 0.0)) < 2e-3
+
+
+def test_line_of_sight_paths_need_no_iteration():
+    xyz, nrm, lab = _scene([((-3.0, -3.0, 0.0), (6.0, 0, 0), (0, 6.0, 0), (0, 0, 1.0), 0)], 0.05)
+    out = oracle.refine(xyz, nrm, lab, 0.0375, 1e-5, np.array([[0.0, 0.0, 1.0]]), np.array([[3.0, 4.0, 1.0]]),
+                        np.array([0], np.int32), np.zeros((1, 2, 3)))
+    assert out["status"][0] == oracle.REF_VALID and out["iters"][0] == 0
+    assert out["length"][0] == 5.0 and (out["ids"][0] == -1).all()
+
+
+# ---------------------------------------------------------------------------
+# dedup of refined paths
+# ---------------------------------------------------------------------------
+
+LAM = oracle.LIGHT_SPEED / 60e9   # 4.9965 mm
+
+
+def _one_bounce_paths(points, lengths, labels, groups=None):
+    n = len(points)
+    pts = np.asarray(points, np.float64).reshape(n, 1, 3)
+    tx = np.tile([0.0, 0.0, 3.0], (n, 1))
+    return dict(group=np.zeros(n) if groups is None else np.asarray(groups), n_refl=np.ones(n, np.int32),
+                labels=np.asarray(labels).reshape(n, 1), points=pts, length=np.asarray(lengths, np.float64),
+                status=np.zeros(n, np.int32), tx=tx)
+
+
+def _dedup(d, carrier_hz=oracle.CARRIER_HZ):
+    return oracle.refine_dedup(d["group"], d["n_refl"], d["labels"], d["points"], d["length"], d["status"], d["tx"],
+                               carrier_hz=carrier_hz)
+
+
+def test_fresnel_radius_by_hand():
+    # lambda = c / 60 GHz; at d1 = d2 = 3 m the first zone has radius sqrt(lambda * 1.5)
+    assert abs(LAM - 0.0049965409) < 1e-9
+    assert abs(oracle.fresnel_radius(3.0, 3.0, LAM) - 0.0865726) < 1e-6
+
+
+def test_shortest_per_label_sequence():
+    # same labels, points far apart (no Fresnel overlap): only the shorter stays
+    d = _one_bounce_paths([(0, 0, 0), (2, 0, 0)], [6.2, 6.0], [4, 4])
+    assert _dedup(d).tolist() == [False, True]
+    d = _one_bounce_paths([(0, 0, 0), (2, 0, 0)], [6.2, 6.0], [4, 5])
+    assert _dedup(d).tolist() == [True, True]
+
+
+def test_fresnel_zone_merges_nearby_paths():
+    # TX (0,0,3), point (0,0,0), path length 6: d1 = 3, d2 = 3, radius 8.657 cm
+    d = _one_bounce_paths([(0, 0, 0), (0.05, 0, 0)], [6.0, 6.001], [1, 2])
+    assert _dedup(d).tolist() == [True, False]
+    d = _one_bounce_paths([(0, 0, 0), (0.09, 0, 0)], [6.0, 6.001], [1, 2])
+    assert _dedup(d).tolist() == [True, True]
+    assert _dedup(_one_bounce_paths([(0, 0, 0), (0.05, 0, 0)], [6.0, 6.001], [1, 2]), carrier_hz=-1).tolist() == \
+        [True, True]
+    # other (TX, RX) pairs never merge
+    d = _one_bounce_paths([(0, 0, 0), (0.05, 0, 0)], [6.0, 6.001], [1, 2], groups=[0, 1])
+    assert _dedup(d).tolist() == [True, True]
+
+
+def test_fresnel_sweep_is_greedy_in_length_order():
+    # b lies in a's zone, c in b's but not in a's: b goes, c stays (only kept paths absorb)
+    d = _one_bounce_paths([(0, 0, 0), (0.06, 0, 0), (0.12, 0, 0)], [6.0, 6.001, 6.002], [1, 2, 3])
+    assert _dedup(d).tolist() == [True, False, True]
+
+
+def test_invalid_paths_never_kept():
+    d = _one_bounce_paths([(0, 0, 0), (2, 0, 0)], [6.0, 6.1], [1, 2])
+    d["status"][0] = oracle.REF_NOT_CONVERGED
+    assert _dedup(d).tolist() == [False, True]
