@@ -17,7 +17,9 @@
  *                  (Section 2.2.3, propagation phase) and are received by RX
  *                  spheres;
  *   collect_paths  coarse paths as label sequences deduplicated with the
- *                  duplicate limit kappa (Section 2.2.3).
+ *                  duplicate limit kappa (Section 2.2.3);
+ *   refine_paths   exact paths from coarse ones by gradient descent on the
+ *                  path length (Section 2.3, Eq. 2), then their dedup.
  *
  * Conventions for every entry point
  *   - Return value: PCRL_OK (0) or a negative status below; the message of
@@ -290,6 +292,65 @@ typedef struct {
  * if the launch dropped records (then launch_stats().records is the record
  * capacity to relaunch with). */
 int collect_paths(PcrlLaunch* launch, int32_t kappa, int32_t key_mode, PcrlPaths* out, pcrl_stream_t stream);
+
+/* ------------------------------------------------------------------------ */
+/* path refinement (Section 2.3, Eq. 2)                                      */
+/* ------------------------------------------------------------------------ */
+
+/* Outcome of a refined path (PcrlRefined.status). */
+#define PCRL_REFINE_VALID          0   /* converged, a reflection at every point, last segment unblocked */
+#define PCRL_REFINE_NOT_CONVERGED  1   /* gradient norm still >= grad_tol after max_iters steps */
+#define PCRL_REFINE_MISS           2   /* a ray towards an updated point hit nothing */
+#define PCRL_REFINE_WRONG_SIDE     3   /* converged, but a point has its neighbours on both sides of its surfel */
+#define PCRL_REFINE_OCCLUDED       4   /* converged, but a surfel blocks the last segment to the RX */
+#define PCRL_REFINE_DEGENERATE     5   /* a segment of zero length */
+
+typedef struct {
+    int32_t max_iters;   /* rho: gradient steps before a path is given up; <= 0 -> 2000 (Table 1) */
+    float   grad_tol;    /* delta: convergence threshold on the norm of the tangent-plane gradient of the
+                            path length (all points together); <= 0 -> 1e-4 (Table 1) */
+    float   step;        /* eta in (0, 1]: point k steps by eta / (1/|I_k - I_k-1| + 1/|I_k - I_k+1|) times
+                            its gradient; <= 0 -> 0.75 */
+    float   carrier_hz;  /* frequency of the first-Fresnel-zone dedup; 0 -> 60e9 (Table 1); < 0 skips it */
+    int32_t flags;       /* 0 */
+    int32_t reserved;
+} PcrlRefineParams;
+
+typedef struct {
+    int64_t  n_kept;     /* out: paths with kept[i] = 1 */
+    /* caller device arrays, one entry per input row (same order) */
+    int32_t* status;     /* PCRL_REFINE_* */
+    int32_t* iters;      /* gradient steps taken */
+    float*   grad;       /* final gradient norm (NaN after a miss) */
+    float*   length;     /* f of Eq. 2 over the final points (NaN after a miss) */
+    float*   points;     /* [n*K*3] final interaction points, NaN for k >= n_refl */
+    int32_t* point_id;   /* [n*K] point (surfel) of each interaction, -1 for k >= n_refl */
+    int64_t* key;        /* [n*K] label of each interaction, -1 for k >= n_refl */
+    int32_t* kept;       /* 1 for the unique exact paths: valid, shortest of its label sequence within its
+                            (tx, rx, n_refl) group, and not inside the first Fresnel zones of a shorter kept
+                            path of that group (every point within sqrt(lambda d1 d2 / (d1 + d2)) of the
+                            shorter path's corresponding point, d1 / d2 its path lengths from TX / to RX) */
+} PcrlRefined;
+
+/* Refine coarse paths into exact paths (Section 2.3): per path, gradient
+ * descent on the path length of Eq. 2 with every interaction point moving in
+ * the tangent plane of its surfel, a ray traced through the voxel hierarchy
+ * from the previous point towards each updated point to find the new point
+ * and surfel, for at most max_iters steps; then the dedup of refined paths
+ * (shortest per label sequence, then first-Fresnel-zone uniqueness in order
+ * of increasing length).
+ *   scene  the scene the paths were traced in (its current overlay epoch is used)
+ *   tx, rx device [n_tx,3] / [n_rx,3] float32, the arrays of the launch
+ *   paths  a collect_paths result (device arrays; n_rows rows sorted by
+ *          (tx, rx, n_refl), as collect_paths returns them): tx, rx, n_refl
+ *          and points are read
+ *   k_stride  K of the launch (points has k_stride entries per row)
+ * Synchronous.  PCRL_EINVAL on a row with an index out of range or rows out
+ * of order; PCRL_EOVERFLOW if one (tx, rx, n_refl) group keeps more than
+ * 2048 paths (the per-path outputs are still written). */
+int refine_paths(const PcrlScene* scene, const float* tx, int32_t n_tx, const float* rx, int32_t n_rx,
+                 const PcrlPaths* paths, int32_t k_stride, const PcrlRefineParams* params, PcrlRefined* out,
+                 pcrl_stream_t stream);
 
 /* ------------------------------------------------------------------------ */
 /* serving: a request loop over one device-resident, incrementally           */

@@ -83,6 +83,8 @@ REF_VALID, REF_NOT_CONVERGED, REF_MISS, REF_WRONG_SIDE, REF_OCCLUDED, REF_DEGENE
 # Table 1: convergence threshold delta and refinement iterations rho; carrier 60 GHz
 REF_GRAD_TOL = 1e-4
 REF_MAX_ITERS = 2000
+# step scale eta (the paper gives no step size)
+REF_STEP = 0.75
 CARRIER_HZ = 60e9
 LIGHT_SPEED = 299_792_458.0
 
@@ -242,7 +244,7 @@ def dedup(res, K, kappa=1, include_ambiguous=False):
 
 
 def refine(xyz, normal, label, r_s, t_eps, tx, rx, n_refl, pts, max_iters=REF_MAX_ITERS, grad_tol=REF_GRAD_TOL,
-           step=0.5, n_threads=None):
+           step=REF_STEP, n_threads=None):
     """Refine coarse paths into exact paths (Section 2.3, Eq. 2), FP64 brute force.
 
     Per path p: ``tx[p]``, ``rx[p]`` (positions), ``n_refl[p]`` = N and the

@@ -20,10 +20,13 @@ import torch
 
 from . import _lib
 from ._lib import (KEY_LABELS, KEY_LEAVES, LAUNCH_COHERENT, LAUNCH_STATS, LAUNCH_TIMING, PCRL_EOVERFLOW,
-                   PcrlError, check, lib)
+                   REFINE_DEGENERATE, REFINE_MISS, REFINE_NOT_CONVERGED, REFINE_OCCLUDED, REFINE_VALID,
+                   REFINE_WRONG_SIDE, PcrlError, check, lib)
 
-__all__ = ["build_voxels", "launch_rays", "launch_batch", "batch_autotune", "launch_directions", "collect_paths", "Scene", "Launch", "Server", "PcrlError", "KEY_LABELS",
-           "KEY_LEAVES", "version", "library_path"]
+__all__ = ["build_voxels", "launch_rays", "launch_batch", "batch_autotune", "launch_directions", "collect_paths",
+           "refine_paths", "Scene", "Launch", "Server", "PcrlError", "KEY_LABELS", "KEY_LEAVES", "REFINE_VALID",
+           "REFINE_NOT_CONVERGED", "REFINE_MISS", "REFINE_WRONG_SIDE", "REFINE_OCCLUDED", "REFINE_DEGENERATE",
+           "version", "library_path"]
 
 
 def version() -> str:
@@ -377,6 +380,50 @@ def collect_paths(launch: Launch, kappa=1, key_mode=KEY_LABELS, capacity=None) -
         res["n_keys"] = int(out.n_keys)
         return res
     raise PcrlError("collect_paths", PCRL_EOVERFLOW, "capacity retries exhausted")
+
+
+def refine_paths(scene: Scene, tx, rx, paths: dict, max_iters=2000, grad_tol=1e-4, step=0.75,
+                 carrier_hz=60e9) -> dict:
+    """Exact paths from coarse ones (Section 2.3): gradient descent on the path
+    length with re-tracing, then the dedup of refined paths.
+
+    ``paths`` is a ``collect_paths`` result of a launch with these ``tx`` and
+    ``rx`` in ``scene``.  Returns per input row: ``status`` (REFINE_*),
+    ``iters``, ``grad``, ``length``, ``points`` [n, K, 3], ``point_id`` and
+    ``key`` [n, K], ``kept`` (the unique exact paths), plus ``n_kept``.
+    ``carrier_hz < 0`` skips the Fresnel-zone step.
+    """
+    device = scene.device
+    txt = _as_tensor(tx, torch.float32, device, 3)
+    rxt = _as_tensor(rx, torch.float32, device, 3)
+    n = int(paths["n_rows"])
+    K = int(paths["points"].shape[1]) if paths["points"].dim() == 3 else 0
+    res = {
+        "status": torch.empty(n, dtype=torch.int32, device=device),
+        "iters": torch.empty(n, dtype=torch.int32, device=device),
+        "grad": torch.empty(n, dtype=torch.float32, device=device),
+        "length": torch.empty(n, dtype=torch.float32, device=device),
+        "points": torch.empty((n, K, 3), dtype=torch.float32, device=device),
+        "point_id": torch.empty((n, K), dtype=torch.int32, device=device),
+        "key": torch.empty((n, K), dtype=torch.int64, device=device),
+        "kept": torch.empty(n, dtype=torch.int32, device=device),
+    }
+    pp = _lib.PcrlPaths()
+    pp.capacity = n
+    pp.n_rows = n
+    for k in ("tx", "rx", "n_refl", "points"):
+        t = paths[k]
+        assert t.is_contiguous() and t.device == device, k
+        setattr(pp, k, t.data_ptr() if t.numel() else None)
+    out = _lib.PcrlRefined()
+    for k, t in res.items():
+        setattr(out, k, t.data_ptr() if t.numel() else None)
+    prm = _lib.PcrlRefineParams(int(max_iters), float(grad_tol), float(step), float(carrier_hz), 0, 0)
+    with torch.cuda.device(device):
+        check("refine_paths", lib.refine_paths(scene.handle, _ptr(txt), txt.shape[0], _ptr(rxt), rxt.shape[0],
+                                               C.byref(pp), K, C.byref(prm), C.byref(out), _stream(device)))
+    res["n_kept"] = int(out.n_kept)
+    return res
 
 
 def _relaunch(launch: Launch, record_capacity: int):

@@ -31,6 +31,12 @@ LAUNCH_COHERENT = 4
 VOXEL_COMPACT = 1
 KEY_LABELS = 0
 KEY_LEAVES = 1
+REFINE_VALID = 0
+REFINE_NOT_CONVERGED = 1
+REFINE_MISS = 2
+REFINE_WRONG_SIDE = 3
+REFINE_OCCLUDED = 4
+REFINE_DEGENERATE = 5
 
 STATUS_NAMES = {0: "PCRL_OK", -1: "PCRL_EINVAL", -2: "PCRL_ENOMEM", -3: "PCRL_EOVERFLOW", -4: "PCRL_EHIP",
                 -5: "PCRL_EBUSY"}
@@ -78,6 +84,17 @@ class PcrlPaths(C.Structure):
                 ("points", C.c_void_p)]
 
 
+class PcrlRefineParams(C.Structure):
+    _fields_ = [("max_iters", C.c_int32), ("grad_tol", C.c_float), ("step", C.c_float), ("carrier_hz", C.c_float),
+                ("flags", C.c_int32), ("reserved", C.c_int32)]
+
+
+class PcrlRefined(C.Structure):
+    _fields_ = [("n_kept", C.c_int64), ("status", C.c_void_p), ("iters", C.c_void_p), ("grad", C.c_void_p),
+                ("length", C.c_void_p), ("points", C.c_void_p), ("point_id", C.c_void_p), ("key", C.c_void_p),
+                ("kept", C.c_void_p)]
+
+
 class PcrlQuery(C.Structure):
     _fields_ = [("scene", C.c_void_p), ("tx", C.c_void_p), ("n_tx", C.c_int32), ("n_rx", C.c_int32),
                 ("rx", C.c_void_p), ("params", PcrlLaunchParams)]
@@ -122,6 +139,8 @@ SIGNATURES = {
                                  C.c_void_p, C.POINTER(C.c_int64)]),
     "release_launch": (C.c_int, [C.c_void_p]),
     "collect_paths": (C.c_int, [C.c_void_p, C.c_int32, C.c_int32, C.POINTER(PcrlPaths), C.c_void_p]),
+    "refine_paths": (C.c_int, [C.c_void_p, C.c_void_p, C.c_int32, C.c_void_p, C.c_int32, C.POINTER(PcrlPaths),
+                               C.c_int32, C.POINTER(PcrlRefineParams), C.POINTER(PcrlRefined), C.c_void_p]),
     "launch_batch": (C.c_int, [C.POINTER(PcrlQuery), C.c_int32, C.POINTER(PcrlBatchParams), C.c_void_p,
                                C.POINTER(C.c_void_p)]),
     "batch_autotune": (C.c_int, [C.POINTER(PcrlQuery), C.c_int32, C.c_void_p, C.POINTER(PcrlBatchParams)]),

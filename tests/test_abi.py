@@ -54,6 +54,8 @@ def test_header_constants_match_binding(pcrl):
     assert defs["PCRL_MAX_LEVELS"] == _lib.MAX_LEVELS and defs["PCRL_MAX_REFLECTIONS"] == _lib.MAX_REFLECTIONS
     for name in ("OK", "EINVAL", "ENOMEM", "EOVERFLOW", "EHIP", "EBUSY"):
         assert defs["PCRL_" + name] == getattr(_lib, "PCRL_" + name)
+    for name in ("VALID", "NOT_CONVERGED", "MISS", "WRONG_SIDE", "OCCLUDED", "DEGENERATE"):
+        assert defs["PCRL_REFINE_" + name] == getattr(_lib, "REFINE_" + name)
 
 
 def test_binding_covers_header(pcrl):
@@ -68,6 +70,8 @@ def test_struct_sizes(pcrl):
     assert C.sizeof(_lib.PcrlLaunchParams) == 64
     assert C.sizeof(_lib.PcrlSceneInfo) == 168
     assert C.sizeof(_lib.PcrlPaths) == 13 * 8
+    assert C.sizeof(_lib.PcrlRefineParams) == 24
+    assert C.sizeof(_lib.PcrlRefined) == 9 * 8
 
 
 def test_version_and_validation_without_gpu(pcrl):
@@ -98,6 +102,9 @@ def test_version_and_validation_without_gpu(pcrl):
     assert lib.launch_rays(C.c_void_p(1), C.c_void_p(1), 1, None, 0, C.byref(lp), None, C.byref(out)) == \
         _lib.PCRL_EINVAL
     assert lib.collect_paths(None, 1, 0, None, None) == _lib.PCRL_EINVAL
+    ro = _lib.PcrlRefined()
+    assert lib.refine_paths(None, None, 0, None, 0, None, 0, None, C.byref(ro), None) == _lib.PCRL_EINVAL
+    assert b"refine_paths" in lib.last_error()
     assert lib.release_scene(None) == 0 and lib.release_launch(None) == 0
 
 
