@@ -376,6 +376,7 @@ def main():
     ap.add_argument("--cpu-seconds", type=float, default=12.0)
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--no-stats", action="store_true")
+    ap.add_argument("--no-refine", action="store_true", help="skip the path-refinement leg (run after the timed steps)")
     args = ap.parse_args()
     if args.gpus != 1 or int(os.environ.get("WORLD_SIZE", "1")) != 1:
         print("bench.py measures one GPU only: the library has no multi-GPU path (the rays of a launch "
@@ -489,6 +490,32 @@ def main():
                                 "achieved_gbs": round(bytes_per_step / (avg_ms * 1e-3) / 1e9, 2),
                                 "algo_bytes_per_segment": round(bytes_per_step / max(st_stats["segments"], 1), 1)}}
 
+    refine = None
+    if not args.no_refine:
+        # path refinement of the step's coarse paths (Section 2.3): outside the timed
+        # step; refine_paths is synchronous, so the wall clock brackets it
+        scene = pcrl.build_voxels(xyz, nrm, lab, s.levels, r_s, t_eps=t_eps, device=dev)
+        launch = pcrl.launch_rays(scene, tx, rx, n_rays=s.n_rays, max_reflections=K)
+        rpaths = pcrl.collect_paths(launch, kappa=args.kappa, capacity=cap[0])
+        times = []
+        for _ in range(3):
+            torch.cuda.synchronize()
+            t1 = time.perf_counter()
+            ref = pcrl.refine_paths(scene, tx, rx, rpaths)
+            times.append(time.perf_counter() - t1)
+        rst = ref["status"].cpu().numpy()
+        rit = ref["iters"].cpu().numpy()
+        names = ("valid", "not_converged", "miss", "wrong_side", "occluded", "degenerate")
+        rows = int(rpaths["n_rows"])
+        r_ms = 1e3 * float(np.median(times))
+        refine = {"rows": rows, "ms": round(r_ms, 3), "paths_per_s": round(rows / (r_ms * 1e-3), 1),
+                  "status": {nm: int((rst == i).sum()) for i, nm in enumerate(names)}, "kept": int(ref["n_kept"]),
+                  "iters_mean": round(float(rit.mean()), 1) if rows else 0.0, "iters_max": int(rit.max(initial=0)),
+                  "max_iters": 2000, "grad_tol": 1e-4}
+        log(f"[bench] refine: {refine}")
+        launch.release()
+        scene.release()
+
     cpu = None
     if not args.no_cpu_baseline:
         log("[bench] timing the CPU oracle on a ray sample")
@@ -517,6 +544,7 @@ def main():
         "paths": {"rows": int(paths["n_rows"]), "keys": int(paths["n_keys"])},
         "roofline": roof,
         "cpu_baseline": cpu,
+        "refine": refine,
     }
     if algo is not None:
         out["trace_stats"] = {k: algo[k] for k in ("segments", "dda_steps", "leaves_visited", "node_lookups",
