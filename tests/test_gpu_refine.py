@@ -217,6 +217,26 @@ def test_furnished_room_full_size(env):
         _compare_rows(s, p, R20, o, slow)
 
 
+def test_canyon_three_levels_brick_masks(env):
+    # three voxel levels and the brick-mask traversal (no dense cell table)
+    torch, pcrl, oracle = env
+    s = scenes.street_canyon(n_points=1_000_000, scale=0.25, n_tx=2, n_rx=16, n_rays=200_000, K=3,
+                             levels=(4.0, 0.5, 0.1))
+    print(f"[refine] small canyon: {s.n_points} pts, spacing {s.spacing:.3f}", flush=True)
+    r_s, t_eps = float(np.float32(s.surfel_radius)), float(np.float32(parity.t_eps_of(s)))
+    scene = pcrl.build_voxels(s.xyz, s.normal, s.label, s.levels, r_s, t_eps=t_eps, compact=True)
+    launch = pcrl.launch_rays(scene, s.tx, s.rx, n_rays=s.n_rays, max_reflections=3)
+    P = pcrl.collect_paths(launch, kappa=3)
+    p, r = parity.to_numpy(P), parity.to_numpy(pcrl.refine_paths(scene, s.tx, s.rx, P))
+    print(f"[refine] small canyon: {p['n_rows']} rows, status {np.bincount(r['status'], minlength=6)}", flush=True)
+    assert p["n_rows"] > 20 and (r["status"] == pcrl.REFINE_VALID).sum() > 10
+    work = (r["iters"] + 1) * np.maximum(p["n_refl"], 1)
+    rows = np.argsort(work, kind="stable")[:40]
+    o = _oracle_refine(oracle, s, p, rows)
+    assert _compare_rows(s, p, r, o, rows) > 10
+    _check_kept(oracle, s, p, r)
+
+
 def test_edge_cases(env):
     torch, pcrl, oracle = env
     s = scenes.box_room()
