@@ -312,9 +312,16 @@ typedef struct {
     float   step;        /* eta in (0, 1]: point k steps by eta / (1/|I_k - I_k-1| + 1/|I_k - I_k+1|) times
                             its gradient; <= 0 -> 0.75 */
     float   carrier_hz;  /* frequency of the first-Fresnel-zone dedup; 0 -> 60e9 (Table 1); < 0 skips it */
-    int32_t flags;       /* 0 */
-    int32_t reserved;
+    int32_t flags;       /* 0 or PCRL_REFINE_SMOOTH */
+    float   smooth_radius;  /* PCRL_REFINE_SMOOTH: radius h of the normal average, surfel radius < h <= 0.98 x
+                               leaf edge (PCRL_EINVAL otherwise); <= 0 -> 0.95 x leaf edge */
 } PcrlRefineParams;
+
+/* PcrlRefineParams.flags: the surface normal at an interaction point is the
+ * weighted average of the normals of the points within smooth_radius of it
+ * (weights (1 - d^2/h^2)^4, each normal oriented like the hit surfel's: the
+ * smooth normal n(x) of Eq. 1) instead of the hit surfel's own normal. */
+#define PCRL_REFINE_SMOOTH 1
 
 typedef struct {
     int64_t  n_kept;     /* out: paths with kept[i] = 1 */

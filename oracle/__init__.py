@@ -72,7 +72,8 @@ class OracleRefineArgs(C.Structure):
         ("xyz", C.c_void_p), ("nrm", C.c_void_p), ("label", C.c_void_p), ("n_pts", C.c_int64),
         ("r_s", C.c_double), ("t_eps", C.c_double), ("n_paths", C.c_int64), ("K", C.c_int32),
         ("tx", C.c_void_p), ("rx", C.c_void_p), ("n_refl", C.c_void_p), ("pts", C.c_void_p),
-        ("max_iters", C.c_int32), ("grad_tol", C.c_double), ("step", C.c_double), ("n_threads", C.c_int32),
+        ("max_iters", C.c_int32), ("grad_tol", C.c_double), ("step", C.c_double), ("smooth_h", C.c_double),
+        ("n_threads", C.c_int32),
         ("status", C.c_void_p), ("iters", C.c_void_p), ("grad", C.c_void_p), ("length", C.c_void_p),
         ("out_pts", C.c_void_p), ("out_id", C.c_void_p), ("out_label", C.c_void_p),
     ]
@@ -244,11 +245,14 @@ def dedup(res, K, kappa=1, include_ambiguous=False):
 
 
 def refine(xyz, normal, label, r_s, t_eps, tx, rx, n_refl, pts, max_iters=REF_MAX_ITERS, grad_tol=REF_GRAD_TOL,
-           step=REF_STEP, n_threads=None):
+           step=REF_STEP, smooth_radius=0.0, n_threads=None):
     """Refine coarse paths into exact paths (Section 2.3, Eq. 2), FP64 brute force.
 
     Per path p: ``tx[p]``, ``rx[p]`` (positions), ``n_refl[p]`` = N and the
-    coarse interaction points ``pts[p, :N]`` ([n, K, 3]).  Returns a dict:
+    coarse interaction points ``pts[p, :N]`` ([n, K, 3]).  ``smooth_radius`` > 0
+    takes the surface normal at each point as the weighted average of the
+    normals within that radius (Eq. 1's n(x)) instead of the hit surfel's.
+    Returns a dict:
     ``status`` (REF_*), ``iters`` (gradient steps), ``grad`` (final norm of
     the tangent-plane gradient), ``length`` (f of Eq. 2), ``points``
     [n, K, 3] (NaN past N), ``ids`` and ``labels`` [n, K] (-1 past N).
@@ -270,7 +274,7 @@ def refine(xyz, normal, label, r_s, t_eps, tx, rx, n_refl, pts, max_iters=REF_MA
     a.xyz, a.nrm, a.label, a.n_pts = _p(xyz), _p(normal), _p(label), xyz.shape[0]
     a.r_s, a.t_eps, a.n_paths, a.K = float(r_s), float(t_eps), n, K
     a.tx, a.rx, a.n_refl, a.pts = _p(tx), _p(rx), _p(n_refl), _p(pts)
-    a.max_iters, a.grad_tol, a.step = int(max_iters), float(grad_tol), float(step)
+    a.max_iters, a.grad_tol, a.step, a.smooth_h = int(max_iters), float(grad_tol), float(step), float(smooth_radius)
     a.n_threads = int(n_threads or default_threads())
     a.status, a.iters, a.grad, a.length = _p(out["status"]), _p(out["iters"]), _p(out["grad"]), _p(out["length"])
     a.out_pts, a.out_id, a.out_label = _p(out["points"]), _p(out["ids"]), _p(out["labels"])

@@ -453,7 +453,10 @@ int oracle_launch(OracleArgs* a)
  *   4. for k = 1..N a ray is traced from the (new) I_{k-1} towards R_k; its
  *      nearest hit gives the new c_k and n_k (the hit surfel's normal); a
  *      ray that hits nothing ends the refinement (invalid path).
- * After rho iterations without convergence the path is invalid.  The step
+ * After rho iterations without convergence the path is invalid.  With
+ * smooth_h > 0 the normal n_k is the weighted average of the normals of the
+ * points within smooth_h of c_k (the smooth surface normal of Eq. 1) instead
+ * of the hit surfel's own.  The step
  * size is not given in the paper: a_k = eta / (1/|c_k - I_{k-1}| +
  * 1/|c_k - I_{k+1}|) scales the step by the inverse of the largest curvature
  * of f_k in the tangent plane.  The initial c_k are found the same way as in
@@ -485,6 +488,7 @@ typedef struct {
     int32_t max_iters;         /* rho */
     double grad_tol;           /* delta */
     double step;               /* eta */
+    double smooth_h;           /* > 0: surface normal = weighted average of normals within this radius */
     int32_t n_threads;
     int32_t* status;           /* ORACLE_REF_* */
     int32_t* iters;            /* gradient steps taken */
@@ -505,6 +509,31 @@ static double dist3(const double* p, const double* q)
 {
     double e[3] = {p[0] - q[0], p[1] - q[1], p[2] - q[2]};
     return sqrt(dot3(e, e));
+}
+
+/* Surface normal at c as the weighted average of the nearby points' normals
+ * (the n(x) of Eq. 1): weights (1 - |c - p|^2 / h^2)^4 for |c - p| < h (the
+ * paper gives no kernel; this one is smooth and vanishes at h), each normal
+ * oriented to agree with the hit surfel's normal `nh`.  Replaces nh unless
+ * no point lies within h. */
+static void smooth_normal(const Pts64* P, int64_t n_pts, double h, const double* c, double* nh)
+{
+    const double h2 = h * h;
+    double s[3] = {0.0, 0.0, 0.0};
+    for (int64_t q = 0; q < n_pts; ++q) {
+        double dx = P->px[q] - c[0], dy = P->py[q] - c[1], dz = P->pz[q] - c[2];
+        double d2 = dx * dx + dy * dy + dz * dz;
+        if (!(d2 < h2)) continue;
+        double w = 1.0 - d2 / h2;
+        w = w * w;
+        w = w * w;
+        double sg = (P->nx[q] * nh[0] + P->ny[q] * nh[1] + P->nz[q] * nh[2]) < 0.0 ? -w : w;
+        s[0] += sg * P->nx[q];
+        s[1] += sg * P->ny[q];
+        s[2] += sg * P->nz[q];
+    }
+    double l = sqrt(s[0] * s[0] + s[1] * s[1] + s[2] * s[2]);
+    if (l > 0.0) { nh[0] = s[0] / l; nh[1] = s[1] / l; nh[2] = s[2] / l; }
 }
 
 /* Nearest hit of the ray from o towards target (excluding surfel `last`).
@@ -554,6 +583,7 @@ static void refine_one(const OracleRefineArgs* a, const OracleArgs* A, const Pts
         int64_t last = -1;
         for (int32_t k = 0; k < N && status == ORACLE_REF_VALID; ++k) {
             int r = trace_towards(A, P, IPT(k), tgt[k], last, c[k], n[k], &m[k], NULL);
+            if (r > 0 && a->smooth_h > 0.0) smooth_normal(P, a->n_pts, a->smooth_h, c[k], n[k]);
             if (r < 0) status = ORACLE_REF_DEGENERATE;
             else if (r == 0) status = ORACLE_REF_MISS;
             last = m[k];

@@ -383,7 +383,7 @@ def collect_paths(launch: Launch, kappa=1, key_mode=KEY_LABELS, capacity=None) -
 
 
 def refine_paths(scene: Scene, tx, rx, paths: dict, max_iters=2000, grad_tol=1e-4, step=0.75,
-                 carrier_hz=60e9) -> dict:
+                 carrier_hz=60e9, smooth_radius=0.0) -> dict:
     """Exact paths from coarse ones (Section 2.3): gradient descent on the path
     length with re-tracing, then the dedup of refined paths.
 
@@ -391,7 +391,9 @@ def refine_paths(scene: Scene, tx, rx, paths: dict, max_iters=2000, grad_tol=1e-
     ``rx`` in ``scene``.  Returns per input row: ``status`` (REFINE_*),
     ``iters``, ``grad``, ``length``, ``points`` [n, K, 3], ``point_id`` and
     ``key`` [n, K], ``kept`` (the unique exact paths), plus ``n_kept``.
-    ``carrier_hz < 0`` skips the Fresnel-zone step.
+    ``carrier_hz < 0`` skips the Fresnel-zone step.  ``smooth_radius > 0``
+    takes the surface normal at each point as the weighted average of the
+    normals within that radius (between the surfel radius and the leaf edge).
     """
     device = scene.device
     txt = _as_tensor(tx, torch.float32, device, 3)
@@ -418,7 +420,9 @@ def refine_paths(scene: Scene, tx, rx, paths: dict, max_iters=2000, grad_tol=1e-
     out = _lib.PcrlRefined()
     for k, t in res.items():
         setattr(out, k, t.data_ptr() if t.numel() else None)
-    prm = _lib.PcrlRefineParams(int(max_iters), float(grad_tol), float(step), float(carrier_hz), 0, 0)
+    smooth = _lib.REFINE_SMOOTH if smooth_radius > 0 else 0
+    prm = _lib.PcrlRefineParams(int(max_iters), float(grad_tol), float(step), float(carrier_hz), smooth,
+                                float(smooth_radius))
     with torch.cuda.device(device):
         check("refine_paths", lib.refine_paths(scene.handle, _ptr(txt), txt.shape[0], _ptr(rxt), rxt.shape[0],
                                                C.byref(pp), K, C.byref(prm), C.byref(out), _stream(device)))

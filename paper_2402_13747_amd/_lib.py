@@ -37,6 +37,7 @@ REFINE_MISS = 2
 REFINE_WRONG_SIDE = 3
 REFINE_OCCLUDED = 4
 REFINE_DEGENERATE = 5
+REFINE_SMOOTH = 1
 
 STATUS_NAMES = {0: "PCRL_OK", -1: "PCRL_EINVAL", -2: "PCRL_ENOMEM", -3: "PCRL_EOVERFLOW", -4: "PCRL_EHIP",
                 -5: "PCRL_EBUSY"}
@@ -86,7 +87,7 @@ class PcrlPaths(C.Structure):
 
 class PcrlRefineParams(C.Structure):
     _fields_ = [("max_iters", C.c_int32), ("grad_tol", C.c_float), ("step", C.c_float), ("carrier_hz", C.c_float),
-                ("flags", C.c_int32), ("reserved", C.c_int32)]
+                ("flags", C.c_int32), ("smooth_radius", C.c_float)]
 
 
 class PcrlRefined(C.Structure):

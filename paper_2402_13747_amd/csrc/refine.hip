@@ -15,6 +15,8 @@
 //   - for k = 1..N a ray from the new I_{k-1} towards R_k finds the new c_k
 //     and its normal (the hit surfel's) through the voxel hierarchy, exactly
 //     as a launched ray; a ray that hits nothing ends the path (invalid).
+// With PCRL_REFINE_SMOOTH the normal at c_k is instead the weighted average
+// of the normals of the points near c_k (the smooth normal of Eq. 1).
 // The first c_k come from the same tracing towards the coarse points.  A
 // converged path is kept if every interaction has both neighbours on one
 // side of its surfel and the last segment reaches the RX unblocked.
@@ -54,6 +56,7 @@ struct RefineArgs {
     int32_t max_iters;
     float grad_tol;
     float step;
+    float smooth_h2;            // > 0: surface normals averaged over this squared radius
     float4* cpos;               // [K][n] current point, surfel id (bits)
     float4* cnrm;               // [K][n] its surfel's normal, label (bits)
     float4* tgt;                // [K][n] point the next trace aims at
@@ -101,6 +104,49 @@ __device__ __forceinline__ void trace_towards(const RefineArgs& a, LeafTestLds& 
     stage_ray(W, o, d, last);
     trace_segment<false, NL, false>(a.t, W, go, o, d, hit, cnt);
     if (OV) trace_segment<false, NL, true>(a.t, W, go, o, d, hit, cnt);
+}
+
+// Add the weighted normals of the points of hierarchy v within sqrt(h2) of c
+// (the n(x) of Eq. 1; weights (1 - d^2/h2)^4, each normal turned to agree
+// with nh).  h2 is below one leaf edge squared, so the points lie in the 27
+// leaves around c's; a point is taken from the leaf holding its centre only
+// (every leaf its disk meets lists it).
+template <int NL>
+__device__ __forceinline__ void gather_normals(const SceneView& v, const float c[3], float h2, const float nh[3],
+                                               float acc[3]) {
+    int lc[3];
+#pragma unroll
+    for (int a = 0; a < 3; ++a) lc[a] = (int)floorf((c[a] - v.org[a]) * v.inv_h);
+    for (int dz = -1; dz <= 1; ++dz)
+        for (int dy = -1; dy <= 1; ++dy)
+            for (int dx = -1; dx <= 1; ++dx) {
+                const int cell[3] = {lc[0] + dx, lc[1] + dy, lc[2] + dz};
+                if (cell[0] < 0 || cell[1] < 0 || cell[2] < 0 || cell[0] >= v.dim[0] || cell[1] >= v.dim[1] ||
+                    cell[2] >= v.dim[2])
+                    continue;
+                uint32_t node = 0;
+                int skip0 = 0;
+                if (descend<false, NL - 1>(v, cell, node, skip0, nullptr) != NL) continue;
+                const uint2 r = v.leaf[node];
+                for (uint32_t e = r.x; e < r.x + r.y; ++e) {
+                    const float4 P = v.spos[e];
+                    const float x = P.x - c[0], y = P.y - c[1], z = P.z - c[2];
+                    const float d2 = x * x + y * y + z * z;
+                    if (!(d2 < h2)) continue;
+                    if ((int)floorf((P.x - v.org[0]) * v.inv_h) != cell[0] ||
+                        (int)floorf((P.y - v.org[1]) * v.inv_h) != cell[1] ||
+                        (int)floorf((P.z - v.org[2]) * v.inv_h) != cell[2])
+                        continue;
+                    const float4 N = v.snrm[e];
+                    float w = 1.0f - d2 / h2;
+                    w *= w;
+                    w *= w;
+                    if (N.x * nh[0] + N.y * nh[1] + N.z * nh[2] < 0.f) w = -w;
+                    acc[0] += w * N.x;
+                    acc[1] += w * N.y;
+                    acc[2] += w * N.z;
+                }
+            }
 }
 
 __device__ __forceinline__ void load3(const float4* p, float x[3]) {
@@ -160,8 +206,20 @@ __global__ __launch_bounds__(REFINE_BLOCK) void k_refine(RefineArgs a) {
                     o[1] = o[1] + hit.t * d[1];
                     o[2] = o[2] + hit.t * d[2];
                     last = hit.id;
+                    float nr[3] = {hit.nx, hit.ny, hit.nz};
+                    if (a.smooth_h2 > 0.f) {
+                        float acc[3] = {0.f, 0.f, 0.f};
+                        gather_normals<NL>(a.t.v, o, a.smooth_h2, nr, acc);
+                        if (OV) gather_normals<NL>(a.t.ov, o, a.smooth_h2, nr, acc);
+                        const float l = sqrtf(acc[0] * acc[0] + acc[1] * acc[1] + acc[2] * acc[2]);
+                        if (l > 0.f) {
+                            nr[0] = acc[0] / l;
+                            nr[1] = acc[1] / l;
+                            nr[2] = acc[2] / l;
+                        }
+                    }
                     a.cpos[k * n + p] = make_float4(o[0], o[1], o[2], __uint_as_float(hit.id));
-                    a.cnrm[k * n + p] = make_float4(hit.nx, hit.ny, hit.nz, __uint_as_float(hit.lab));
+                    a.cnrm[k * n + p] = make_float4(nr[0], nr[1], nr[2], __uint_as_float(hit.lab));
                 }
             }
         }
@@ -436,9 +494,19 @@ extern "C" int refine_paths(const PcrlScene* scene, const float* tx, int32_t n_t
     const float grad_tol = P.grad_tol > 0.f ? P.grad_tol : 1e-4f;
     const float step = P.step > 0.f ? P.step : 0.75f;
     const double carrier = P.carrier_hz == 0.f ? 60e9 : (double)P.carrier_hz;
-    if (!(step <= 1.0f) || P.flags != 0 || !std::isfinite(carrier)) {
-        set_error("refine_paths: need 0 < step <= 1, flags 0 and a finite carrier");
+    if (!(step <= 1.0f) || (P.flags & ~PCRL_REFINE_SMOOTH) || !std::isfinite(carrier)) {
+        set_error("refine_paths: need 0 < step <= 1, known flags and a finite carrier");
         return PCRL_EINVAL;
+    }
+    float smooth_h = 0.f;
+    if (P.flags & PCRL_REFINE_SMOOTH) {
+        const float leaf = scene->view.h, rs = scene->view.r_s;
+        smooth_h = P.smooth_radius > 0.f ? P.smooth_radius : 0.95f * leaf;
+        if (!(smooth_h > rs) || !(smooth_h <= 0.98f * leaf)) {
+            set_error("refine_paths: the smoothing radius %g must exceed the surfel radius %g and stay within 0.98 "
+                      "leaf edges (%g)", (double)smooth_h, (double)rs, (double)leaf);
+            return PCRL_EINVAL;
+        }
     }
     hipStream_t s = (hipStream_t)stream;
     // the path table is small: validate its indices on the host
@@ -482,6 +550,7 @@ extern "C" int refine_paths(const PcrlScene* scene, const float* tx, int32_t n_t
     a.max_iters = max_iters;
     a.grad_tol = grad_tol;
     a.step = step;
+    a.smooth_h2 = smooth_h * smooth_h;
     a.status = out->status;
     a.iters = out->iters;
     a.grad = out->grad;

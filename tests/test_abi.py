@@ -54,7 +54,7 @@ def test_header_constants_match_binding(pcrl):
     assert defs["PCRL_MAX_LEVELS"] == _lib.MAX_LEVELS and defs["PCRL_MAX_REFLECTIONS"] == _lib.MAX_REFLECTIONS
     for name in ("OK", "EINVAL", "ENOMEM", "EOVERFLOW", "EHIP", "EBUSY"):
         assert defs["PCRL_" + name] == getattr(_lib, "PCRL_" + name)
-    for name in ("VALID", "NOT_CONVERGED", "MISS", "WRONG_SIDE", "OCCLUDED", "DEGENERATE"):
+    for name in ("VALID", "NOT_CONVERGED", "MISS", "WRONG_SIDE", "OCCLUDED", "DEGENERATE", "SMOOTH"):
         assert defs["PCRL_REFINE_" + name] == getattr(_lib, "REFINE_" + name)
 
 

@@ -237,6 +237,36 @@ def test_canyon_three_levels_brick_masks(env):
     _check_kept(oracle, s, p, r)
 
 
+@pytest.mark.parametrize("seed", [11, 12])
+def test_smoothed_normals_match_oracle(env, seed):
+    # random planes and boxes with tilted normals and jittered points
+    torch, pcrl, oracle = env
+    s = scenes.random_scene(seed, n_rays=20_000, n_rx=4, pos_sigma=0.002, tilt_sigma=0.02, h=0.1)
+    h = 0.9 * float(np.float32(s.levels[-1]))
+    scene, launch, P, p, r = _device_refine(env, s, 3, 3, smooth_radius=h)
+    rows = np.arange(p["n_rows"])
+    o = _oracle_refine(oracle, s, p, rows, smooth_radius=h)
+    _compare_rows(s, p, r, o, rows)
+    _check_kept(oracle, s, p, r)
+
+
+def test_furnished_room_smoothed_normals(env):
+    torch, pcrl, oracle = env
+    s = scenes.furnished_room()
+    scene, launch, P, p, r = _device_refine(env, s, 3, 100, smooth_radius=0.045)
+    st = r["status"]
+    print(f"[refine] furnished room, smoothed normals: status counts {np.bincount(st, minlength=6)}, "
+          f"kept {r['kept'].sum()}", flush=True)
+    rows = np.argsort((r["iters"] + 1) * np.maximum(p["n_refl"], 1), kind="stable")[:32]
+    o = _oracle_refine(oracle, s, p, rows, smooth_radius=0.045)
+    assert _compare_rows(s, p, r, o, rows) > 10
+    _check_kept(oracle, s, p, r)
+    # an invalid radius is refused
+    with pytest.raises(pcrl.PcrlError) as e:
+        pcrl.refine_paths(scene, s.tx, s.rx, P, smooth_radius=0.06)
+    assert e.value.status == -1 and "smoothing radius" in e.value.message
+
+
 def test_edge_cases(env):
     torch, pcrl, oracle = env
     s = scenes.box_room()

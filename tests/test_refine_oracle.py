@@ -173,6 +173,50 @@ def test_line_of_sight_paths_need_no_iteration():
     assert out["length"][0] == 5.0 and (out["ids"][0] == -1).all()
 
 
+def test_smoothing_keeps_the_box_room_image_paths(box_refined):
+    # flat walls: the averaged normal is the wall's own wherever the exact points lie
+    # (>= 0.35 m from every edge, beyond the 0.24 m radius)
+    s, rows, nr, txp, out = box_refined
+    t_eps = 1e-5 * math.sqrt(10 ** 2 + 8 ** 2 + 3 ** 2)
+    pts = np.full((len(rows), 2, 3), np.nan)
+    for i, (key, r) in enumerate(rows):
+        pts[i, :key[2]] = out["points"][i, :key[2]]
+    sm = oracle.refine(s.xyz, s.normal, s.label, s.surfel_radius, t_eps, txp, np.repeat(s.rx.astype(np.float64),
+                       len(rows), 0), nr, pts, smooth_radius=0.24)
+    gold = _golden()
+    assert (sm["status"] == oracle.REF_VALID).all()
+    for i in range(len(rows)):
+        seq = tuple(int(x) for x in sm["labels"][i, :nr[i]])
+        L = math.sqrt(gold[seq])
+        assert L * (1 - 1e-12) <= sm["length"][i] <= L * (1 + 1e-7)
+
+
+def test_smoothing_finds_the_specular_point_of_a_noisy_plane():
+    # a plane sampled exactly, normals tilted by N(0, 0.02 rad): with each surfel's
+    # own normal the refinement stops wherever a surfel's tilted mirror condition
+    # holds (centimetres off); the averaged normal recovers the plane's specular point
+    h = 0.05
+    xyz, nrm, lab = scenes._sample_faces([((-3.0, -3.0, 0.0), (6.0, 0, 0), (0, 6.0, 0), (0, 0, 1.0), 0)], h)
+    rng = np.random.default_rng(3)
+    _, nrm = scenes._jitter(rng, xyz, nrm, 0.0, 0.02)
+    xyz, nrm, lab = xyz.astype(np.float32), nrm.astype(np.float32), lab.astype(np.uint32)
+    tx, rx = np.array([0.0, 0.0, 1.0]), np.array([2.0, 0.5, 1.5])
+    img = np.array([0.0, 0.0, -1.0])
+    spec = img + (rx - img) / 2.5
+    starts = spec + rng.uniform(-0.3, 0.3, size=(40, 3)) * [1, 1, 0]
+    n = len(starts)
+    args = (xyz, nrm, lab, 0.75 * h, 1e-5, np.tile(tx, (n, 1)), np.tile(rx, (n, 1)), np.ones(n, np.int32),
+            starts[:, None, :])
+    own = oracle.refine(*args)
+    avg = oracle.refine(*args, smooth_radius=0.09)
+    assert (own["status"] == oracle.REF_VALID).all() and (avg["status"] == oracle.REF_VALID).all()
+    assert np.linalg.norm(own["points"][:, 0] - spec, axis=1).max() > 0.01
+    assert np.linalg.norm(avg["points"][:, 0] - spec, axis=1).max() < 0.005
+    # the disks are tilted, so a hit lies up to r_s * 0.02 off the plane
+    L = np.linalg.norm(rx - img)
+    assert np.abs(avg["length"] - L).max() < 1e-3 * L
+
+
 # ---------------------------------------------------------------------------
 # dedup of refined paths
 # ---------------------------------------------------------------------------
