@@ -418,6 +418,7 @@ __global__ __launch_bounds__(BUILD_BLOCK) void k_brick_cells(const uint64_t* mas
     for (int k = 0; k < OCT_ITEMS; ++k)
         for (int b = 0; b < 4; ++b) plane[k][b] = 0;
     for (int sz = 1; sz <= 15; ++sz) {
+        int any = 0;  // some E_{s+1} is not empty
         for (int k = 0; k < OCT_ITEMS; ++k) {
             const int it = threadIdx.x + k * BUILD_BLOCK;
             if (it >= items) break;
@@ -441,9 +442,12 @@ __global__ __launch_bounds__(BUILD_BLOCK) void k_brick_cells(const uint64_t* mas
                 const uint32_t sh = negx ? ((v << 1) & full) : (v >> 1);  // the neighbour along x
                 return v & sh;
             };
-            Enext[it] = (uint16_t)(get(y, z) & get(y + sy, z) & get(y, z + szn) & get(y + sy, z + szn));
+            const uint16_t en = (uint16_t)(get(y, z) & get(y + sy, z) & get(y, z + szn) & get(y + sy, z + szn));
+            Enext[it] = en;
+            any |= en;
         }
-        __syncthreads();
+        // once every E_{s+1} is empty, no later size counts anything
+        if (!__syncthreads_or(any)) break;
         uint16_t* t = Ecur;
         Ecur = Enext;
         Enext = t;

@@ -88,9 +88,9 @@ int radix_sort_u32(uint32_t* keys, uint32_t* vals, int64_t n, int bits, hipStrea
 int bucket_order_u16(const uint16_t* keys, int64_t n_max, const uint32_t* n_dev, uint32_t* order, hipStream_t s);
 // The second half of bucket_order_u16 when the 65536 bucket counts `cnt` and
 // every item's position inside its bucket `pos` were produced elsewhere (with
-// wave_bucket_add): scan the counts in place, then scatter.
-int bucket_place_u16(const uint16_t* keys, const uint32_t* pos, int64_t n_max, const uint32_t* n_dev, uint32_t* cnt,
-                     uint32_t* order, hipStream_t s);
+// wave_bucket_add): scan the counts (into a temporary), then scatter.
+int bucket_place_u16(const uint16_t* keys, const uint32_t* pos, int64_t n_max, const uint32_t* n_dev,
+                     const uint32_t* cnt, uint32_t* order, hipStream_t s);
 
 // Fill helpers.
 int fill_u32(uint32_t* p, uint32_t v, int64_t n, hipStream_t s);

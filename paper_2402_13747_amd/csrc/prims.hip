@@ -261,28 +261,63 @@ __global__ __launch_bounds__(SCAN_BLOCK) void k_scan_reduce(const uint32_t* in, 
     if (threadIdx.x == 0) sums[blockIdx.x] = tot;
 }
 
-// Each thread owns SCAN_ITEMS consecutive values of the tile.
+// Each thread owns SCAN_ITEMS consecutive values of the tile, moved as
+// 16-byte vectors when VEC (both arrays 16-byte aligned) and the thread's
+// values lie inside the array.
+template <bool VEC>
 __global__ __launch_bounds__(SCAN_BLOCK) void k_scan_apply(const uint32_t* in, uint32_t* out, int64_t n,
                                                            const uint32_t* offs, uint32_t* total) {
     const int64_t tile = (int64_t)blockIdx.x * SCAN_TILE;
     const int64_t first = tile + (int64_t)threadIdx.x * SCAN_ITEMS;
+    const bool whole = VEC && first + SCAN_ITEMS <= n;
     uint32_t v[SCAN_ITEMS];
     uint32_t acc = 0;
+    if (whole) {
+        const uint4* q = reinterpret_cast<const uint4*>(in + first);
 #pragma unroll
-    for (int k = 0; k < SCAN_ITEMS; ++k) {
-        int64_t i = first + k;
-        v[k] = (i < n) ? in[i] : 0u;
-        acc += v[k];
+        for (int k = 0; k < SCAN_ITEMS / 4; ++k) {
+            const uint4 u = q[k];
+            v[4 * k] = u.x;
+            v[4 * k + 1] = u.y;
+            v[4 * k + 2] = u.z;
+            v[4 * k + 3] = u.w;
+        }
+    } else {
+#pragma unroll
+        for (int k = 0; k < SCAN_ITEMS; ++k) {
+            int64_t i = first + k;
+            v[k] = (i < n) ? in[i] : 0u;
+        }
     }
+#pragma unroll
+    for (int k = 0; k < SCAN_ITEMS; ++k) acc += v[k];
     uint32_t tot;
     uint32_t run = block_excl_scan(acc, &tot) + (offs ? offs[blockIdx.x] : 0u);
+    uint32_t r[SCAN_ITEMS];
 #pragma unroll
     for (int k = 0; k < SCAN_ITEMS; ++k) {
-        int64_t i = first + k;
-        if (i < n) out[i] = run;
+        r[k] = run;
         run += v[k];
     }
+    if (whole) {
+        uint4* q = reinterpret_cast<uint4*>(out + first);
+#pragma unroll
+        for (int k = 0; k < SCAN_ITEMS / 4; ++k) q[k] = make_uint4(r[4 * k], r[4 * k + 1], r[4 * k + 2], r[4 * k + 3]);
+    } else {
+#pragma unroll
+        for (int k = 0; k < SCAN_ITEMS; ++k) {
+            int64_t i = first + k;
+            if (i < n) out[i] = r[k];
+        }
+    }
     if (total && blockIdx.x == gridDim.x - 1 && threadIdx.x == SCAN_BLOCK - 1) *total = run;
+}
+
+static void launch_scan_apply(unsigned grid, const uint32_t* in, uint32_t* out, int64_t n, const uint32_t* offs,
+                              uint32_t* total, hipStream_t s) {
+    const bool vec = (((uintptr_t)in | (uintptr_t)out) & 15u) == 0;
+    if (vec) hipLaunchKernelGGL(k_scan_apply<true>, dim3(grid), dim3(SCAN_BLOCK), 0, s, in, out, n, offs, total);
+    else hipLaunchKernelGGL(k_scan_apply<false>, dim3(grid), dim3(SCAN_BLOCK), 0, s, in, out, n, offs, total);
 }
 
 int scan_u32(const uint32_t* in, uint32_t* out, int64_t n, uint32_t* total, hipStream_t s) {
@@ -292,8 +327,7 @@ int scan_u32(const uint32_t* in, uint32_t* out, int64_t n, uint32_t* total, hipS
     }
     const int64_t nb = (n + SCAN_TILE - 1) / SCAN_TILE;
     if (nb == 1) {
-        hipLaunchKernelGGL(k_scan_apply, dim3(1), dim3(SCAN_BLOCK), 0, s, in, out, n, (const uint32_t*)nullptr,
-                           total);
+        launch_scan_apply(1, in, out, n, nullptr, total, s);
         PCRL_TRY_HIP(hipGetLastError());
         return PCRL_OK;
     }
@@ -303,7 +337,7 @@ int scan_u32(const uint32_t* in, uint32_t* out, int64_t n, uint32_t* total, hipS
     int rc = hipGetLastError() == hipSuccess ? PCRL_OK : PCRL_EHIP;
     if (rc == PCRL_OK) rc = scan_u32(sums, sums, nb, nullptr, s);
     if (rc == PCRL_OK) {
-        hipLaunchKernelGGL(k_scan_apply, dim3((unsigned)nb), dim3(SCAN_BLOCK), 0, s, in, out, n, sums, total);
+        launch_scan_apply((unsigned)nb, in, out, n, sums, total, s);
         if (hipGetLastError() != hipSuccess) rc = PCRL_EHIP;
     }
     dfree(sums, s);
@@ -436,30 +470,31 @@ __global__ __launch_bounds__(256) void k_bucket_count(const uint16_t* keys, uint
     if (j < n) pos[j] = atomicAdd(&cnt[keys[j]], 1u);
 }
 
-// In-place exclusive scan of the 65536 bucket counts in one workgroup.
+// Exclusive scan of the 65536 bucket counts into start[]: 64 workgroups of
+// 1024 buckets, each adding the counts of the buckets before its own range
+// (read coalesced from cnt, which nothing writes meanwhile).
 constexpr int BUCKET_SCAN_BLOCK = 1024;
-__global__ __launch_bounds__(BUCKET_SCAN_BLOCK) void k_bucket_scan(uint32_t* cnt) {
-    constexpr int PER = 65536 / BUCKET_SCAN_BLOCK;
+__global__ __launch_bounds__(BUCKET_SCAN_BLOCK) void k_bucket_scan(const uint32_t* cnt, uint32_t* start) {
     __shared__ uint32_t wsum[BUCKET_SCAN_BLOCK / 64];
-    uint32_t v[PER];
-    uint32_t acc = 0;
-    const size_t first = (size_t)threadIdx.x * PER;
-#pragma unroll
-    for (int k = 0; k < PER; ++k) {
-        v[k] = cnt[first + k];
-        acc += v[k];
+    __shared__ uint32_t wprev[BUCKET_SCAN_BLOCK / 64];
+    const uint32_t b = blockIdx.x, t = threadIdx.x, w = t >> 6;
+    uint32_t prev = 0;
+    for (uint32_t i = t; i < (uint32_t)BUCKET_SCAN_BLOCK * b; i += BUCKET_SCAN_BLOCK) prev += cnt[i];
+    const uint32_t x = cnt[(size_t)BUCKET_SCAN_BLOCK * b + t];
+    const uint32_t incl = wave_incl_scan(x);
+    const uint32_t pincl = wave_incl_scan(prev);
+    if (lane_id() == 63) {
+        wsum[w] = incl;
+        wprev[w] = pincl;
     }
-    const int w = threadIdx.x >> 6;
-    const uint32_t incl = wave_incl_scan(acc);
-    if (lane_id() == 63) wsum[w] = incl;
     __syncthreads();
-    uint32_t run = incl - acc;
-    for (int k = 0; k < w; ++k) run += wsum[k];
+    uint32_t off = 0, base = 0;
 #pragma unroll
-    for (int k = 0; k < PER; ++k) {
-        cnt[first + k] = run;
-        run += v[k];
+    for (int k = 0; k < BUCKET_SCAN_BLOCK / 64; ++k) {
+        off += ((uint32_t)k < w) ? wsum[k] : 0u;
+        base += wprev[k];
     }
+    start[(size_t)BUCKET_SCAN_BLOCK * b + t] = base + off + incl - x;
 }
 
 __global__ __launch_bounds__(256) void k_bucket_scatter(const uint16_t* keys, const uint32_t* pos, uint32_t n_max,
@@ -470,13 +505,20 @@ __global__ __launch_bounds__(256) void k_bucket_scatter(const uint16_t* keys, co
     if (j < n) order[start[keys[j]] + pos[j]] = j;
 }
 
-int bucket_place_u16(const uint16_t* keys, const uint32_t* pos, int64_t n_max, const uint32_t* n_dev, uint32_t* cnt,
-                     uint32_t* order, hipStream_t s) {
+int bucket_place_u16(const uint16_t* keys, const uint32_t* pos, int64_t n_max, const uint32_t* n_dev,
+                     const uint32_t* cnt, uint32_t* order, hipStream_t s) {
     if (n_max <= 0) return PCRL_OK;
-    hipLaunchKernelGGL(k_bucket_scan, dim3(1), dim3(BUCKET_SCAN_BLOCK), 0, s, cnt);
+    uint32_t* start = nullptr;
+    PCRL_TRY(dalloc((void**)&start, (size_t)65536 * sizeof(uint32_t), s));
+    hipLaunchKernelGGL(k_bucket_scan, dim3(65536 / BUCKET_SCAN_BLOCK), dim3(BUCKET_SCAN_BLOCK), 0, s, cnt, start);
     hipLaunchKernelGGL(k_bucket_scatter, dim3((unsigned)((n_max + 255) / 256)), dim3(256), 0, s, keys, pos,
-                       (uint32_t)n_max, n_dev, (const uint32_t*)cnt, order);
-    PCRL_TRY_HIP(hipGetLastError());
+                       (uint32_t)n_max, n_dev, (const uint32_t*)start, order);
+    const hipError_t e = hipGetLastError();
+    dfree(start, s);
+    if (e != hipSuccess) {
+        set_error("bucket placement kernel failed: %s", hipGetErrorString(e));
+        return PCRL_EHIP;
+    }
     return PCRL_OK;
 }
 
