@@ -478,8 +478,15 @@ __global__ __launch_bounds__(BUCKET_SCAN_BLOCK) void k_bucket_scan(const uint32_
     __shared__ uint32_t wsum[BUCKET_SCAN_BLOCK / 64];
     __shared__ uint32_t wprev[BUCKET_SCAN_BLOCK / 64];
     const uint32_t b = blockIdx.x, t = threadIdx.x, w = t >> 6;
+    // the buckets before this range as 16-byte vectors (cnt is 16-byte aligned):
+    // at most 16 per thread, eight loads in flight at a time
+    const uint4* c4 = reinterpret_cast<const uint4*>(cnt);
     uint32_t prev = 0;
-    for (uint32_t i = t; i < (uint32_t)BUCKET_SCAN_BLOCK * b; i += BUCKET_SCAN_BLOCK) prev += cnt[i];
+#pragma unroll 8
+    for (uint32_t i = t; i < (uint32_t)(BUCKET_SCAN_BLOCK / 4) * b; i += BUCKET_SCAN_BLOCK) {
+        const uint4 u = c4[i];
+        prev += u.x + u.y + u.z + u.w;
+    }
     const uint32_t x = cnt[(size_t)BUCKET_SCAN_BLOCK * b + t];
     const uint32_t incl = wave_incl_scan(x);
     const uint32_t pincl = wave_incl_scan(prev);
@@ -508,6 +515,10 @@ __global__ __launch_bounds__(256) void k_bucket_scatter(const uint16_t* keys, co
 int bucket_place_u16(const uint16_t* keys, const uint32_t* pos, int64_t n_max, const uint32_t* n_dev,
                      const uint32_t* cnt, uint32_t* order, hipStream_t s) {
     if (n_max <= 0) return PCRL_OK;
+    if ((uintptr_t)cnt & 15u) {
+        set_error("bucket counts must be 16-byte aligned");
+        return PCRL_EINVAL;
+    }
     uint32_t* start = nullptr;
     PCRL_TRY(dalloc((void**)&start, (size_t)65536 * sizeof(uint32_t), s));
     hipLaunchKernelGGL(k_bucket_scan, dim3(65536 / BUCKET_SCAN_BLOCK), dim3(BUCKET_SCAN_BLOCK), 0, s, cnt, start);
