@@ -60,6 +60,33 @@ typedef struct PcrlLaunch PcrlLaunch;
 typedef void* pcrl_stream_t; /* a hipStream_t */
 
 /* ------------------------------------------------------------------------ */
+/* device memory                                                             */
+/* ------------------------------------------------------------------------ */
+
+/* Where the library's device buffers (scene hierarchies, ray state, records,
+ * temporaries) come from.  alloc returns `bytes` of device memory of the
+ * current device usable in stream order on `stream` (NULL on failure, which
+ * the calling entry point reports as PCRL_ENOMEM); free releases a block in
+ * stream order on `stream` (work enqueued there before may still use it).
+ * ctx is passed back unchanged.  Both run on whichever thread calls into the
+ * library (the serving worker included) and must be thread-safe. */
+typedef struct {
+    void* (*alloc)(size_t bytes, pcrl_stream_t stream, void* ctx);
+    void  (*free)(void* ptr, pcrl_stream_t stream, void* ctx);
+    void* ctx;
+} PcrlAllocator;
+
+/* Route all later device allocations of the library to `a` (copied), e.g. a
+ * framework's caching allocator; NULL returns to the library's own caching
+ * allocator (per-device free lists by size class, reuse in stream order or
+ * after an event).  Blocks are always freed through the allocator that made
+ * them, so objects created before a switch stay valid; the callbacks must
+ * therefore stay callable until every block they made is freed (release the
+ * objects made under them, or keep them for the life of the process).
+ * PCRL_EINVAL if a callback is missing. */
+int set_allocator(const PcrlAllocator* a);
+
+/* ------------------------------------------------------------------------ */
 /* voxelisation (Section 2.1)                                                */
 /* ------------------------------------------------------------------------ */
 

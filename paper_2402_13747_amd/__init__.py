@@ -24,9 +24,36 @@ from ._lib import (KEY_LABELS, KEY_LEAVES, LAUNCH_COHERENT, LAUNCH_STATS, LAUNCH
                    REFINE_WRONG_SIDE, PcrlError, check, lib)
 
 __all__ = ["build_voxels", "launch_rays", "launch_batch", "batch_autotune", "launch_directions", "collect_paths",
-           "refine_paths", "Scene", "Launch", "Server", "PcrlError", "KEY_LABELS", "KEY_LEAVES", "REFINE_VALID",
-           "REFINE_NOT_CONVERGED", "REFINE_MISS", "REFINE_WRONG_SIDE", "REFINE_OCCLUDED", "REFINE_DEGENERATE",
-           "version", "library_path"]
+           "refine_paths", "use_torch_allocator", "Scene", "Launch", "Server", "PcrlError", "KEY_LABELS",
+           "KEY_LEAVES", "REFINE_VALID", "REFINE_NOT_CONVERGED", "REFINE_MISS", "REFINE_WRONG_SIDE",
+           "REFINE_OCCLUDED", "REFINE_DEGENERATE", "version", "library_path"]
+
+
+# Every installed allocator's ctypes callbacks, kept for the life of the
+# process: the library frees each block through the allocator that made it,
+# also after a switch back, so the callbacks must outlive every such block.
+_allocators = []
+
+
+def use_torch_allocator(enable: bool = True) -> None:
+    """Route the library's device allocations through torch's caching allocator
+    (set_allocator); ``enable=False`` returns to the library's own."""
+    if not enable:
+        check("set_allocator", lib.set_allocator(None))
+        return
+
+    def _alloc(nbytes, stream, ctx):
+        try:
+            return torch.cuda.caching_allocator_alloc(int(nbytes), torch.cuda.current_device(), int(stream or 0))
+        except Exception:  # reported by the library as PCRL_ENOMEM
+            return None
+
+    def _free(ptr, stream, ctx):
+        torch.cuda.caching_allocator_delete(int(ptr))
+
+    a = _lib.PcrlAllocator(_lib.ALLOC_FN(_alloc), _lib.FREE_FN(_free), None)
+    _allocators.append(a)
+    check("set_allocator", lib.set_allocator(C.byref(a)))
 
 
 def version() -> str:

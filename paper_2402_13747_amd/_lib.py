@@ -43,6 +43,14 @@ STATUS_NAMES = {0: "PCRL_OK", -1: "PCRL_EINVAL", -2: "PCRL_ENOMEM", -3: "PCRL_EO
                 -5: "PCRL_EBUSY"}
 
 
+ALLOC_FN = C.CFUNCTYPE(C.c_void_p, C.c_size_t, C.c_void_p, C.c_void_p)
+FREE_FN = C.CFUNCTYPE(None, C.c_void_p, C.c_void_p, C.c_void_p)
+
+
+class PcrlAllocator(C.Structure):
+    _fields_ = [("alloc", ALLOC_FN), ("free", FREE_FN), ("ctx", C.c_void_p)]
+
+
 class PcrlVoxelParams(C.Structure):
     _fields_ = [("n_levels", C.c_int32), ("level_size", C.c_float * MAX_LEVELS), ("surfel_radius", C.c_float),
                 ("t_eps", C.c_float), ("flags", C.c_int32)]
@@ -126,6 +134,7 @@ class PcrlServeStats(C.Structure):
 
 # name -> (restype, argtypes); every symbol declared in include/pcrl.h
 SIGNATURES = {
+    "set_allocator": (C.c_int, [C.POINTER(PcrlAllocator)]),
     "build_voxels": (C.c_int, [C.c_void_p, C.c_void_p, C.c_void_p, C.c_int64, C.POINTER(PcrlVoxelParams),
                                C.c_void_p, C.POINTER(C.c_void_p)]),
     "scene_info": (C.c_int, [C.c_void_p, C.POINTER(PcrlSceneInfo)]),

@@ -100,11 +100,48 @@ void trim_locked(Pool& P) {
 
 }  // namespace
 
+// A caller's allocator (set_allocator) replaces the pool for new blocks;
+// every block remembers the allocator that made it, so switching is safe
+// while blocks are alive.  The callbacks run with no lock of the library
+// held (they may re-enter it, e.g. a framework's collector releasing a
+// scene).
+namespace {
+struct UserAlloc {
+    std::mutex mu;
+    PcrlAllocator a{};
+    bool on = false;
+    std::unordered_map<void*, PcrlAllocator> live;
+};
+UserAlloc& user_alloc() {
+    static UserAlloc* u = new UserAlloc();
+    return *u;
+}
+}  // namespace
+
 int dalloc(void** p, size_t bytes, hipStream_t s) {
     *p = nullptr;
     int dev = 0;
     (void)hipGetDevice(&dev);
     const size_t cls = size_class(bytes == 0 ? 1 : bytes);
+    UserAlloc& U = user_alloc();
+    PcrlAllocator ua{};
+    bool use_user = false;
+    {
+        std::lock_guard<std::mutex> lock(U.mu);
+        use_user = U.on;
+        ua = U.a;
+    }
+    if (use_user) {
+        void* q = ua.alloc(cls, (pcrl_stream_t)s, ua.ctx);
+        if (!q) {
+            set_error("device allocation of %zu bytes failed in the caller's allocator", bytes);
+            return PCRL_ENOMEM;
+        }
+        std::lock_guard<std::mutex> lock(U.mu);
+        U.live[q] = ua;
+        *p = q;
+        return PCRL_OK;
+    }
     Pool& P = pool();
     std::lock_guard<std::mutex> lock(P.mu);
     auto it = P.free_.find({dev, cls});
@@ -139,6 +176,24 @@ int dalloc(void** p, size_t bytes, hipStream_t s) {
 
 void dfree(void* p, hipStream_t s) {
     if (!p) return;
+    {
+        UserAlloc& U = user_alloc();
+        PcrlAllocator ua{};
+        bool found = false;
+        {
+            std::lock_guard<std::mutex> lock(U.mu);
+            auto u = U.live.find(p);
+            if (u != U.live.end()) {
+                ua = u->second;
+                U.live.erase(u);
+                found = true;
+            }
+        }
+        if (found) {
+            ua.free(p, (pcrl_stream_t)s, ua.ctx);
+            return;
+        }
+    }
     Pool& P = pool();
     std::lock_guard<std::mutex> lock(P.mu);
     auto it = P.live.find(p);
@@ -568,3 +623,16 @@ int radix_sort_u32(uint32_t* keys, uint32_t* vals, int64_t n, int bits, hipStrea
 extern "C" const char* last_error(void) { return pcrl::get_error(); }
 
 extern "C" const char* pcrl_version(void) { return "pcrl 0.1.0 (gfx950)"; }
+
+extern "C" int set_allocator(const PcrlAllocator* a) {
+    pcrl::clear_error();
+    if (a && (!a->alloc || !a->free)) {
+        pcrl::set_error("set_allocator: alloc and free must both be given");
+        return PCRL_EINVAL;
+    }
+    pcrl::UserAlloc& u = pcrl::user_alloc();
+    std::lock_guard<std::mutex> lock(u.mu);
+    u.on = a != nullptr;
+    u.a = a ? *a : PcrlAllocator{};
+    return PCRL_OK;
+}

@@ -106,6 +106,12 @@ def test_version_and_validation_without_gpu(pcrl):
     assert lib.refine_paths(None, None, 0, None, 0, None, 0, None, C.byref(ro), None) == _lib.PCRL_EINVAL
     assert b"refine_paths" in lib.last_error()
     assert lib.release_scene(None) == 0 and lib.release_launch(None) == 0
+    # the library's own allocator is the default and can always be restored
+    assert lib.set_allocator(None) == _lib.PCRL_OK
+    half = _lib.PcrlAllocator()
+    half.alloc = _lib.ALLOC_FN(lambda n, s, c: None)
+    assert lib.set_allocator(C.byref(half)) == _lib.PCRL_EINVAL
+    assert b"alloc and free" in lib.last_error()
 
 
 def test_no_cpu_fallback(tmp_path, monkeypatch):
