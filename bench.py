@@ -83,6 +83,12 @@ def make_workload(name):
         return scenes.box_room()
     if name == "street_canyon":
         return scenes.street_canyon()
+    # the literal grid steps of the two configurations (1 cm and 5 cm) instead of
+    # their point counts: 5.7 M and about 156 M points
+    if name == "furnished_room_dense":
+        return scenes.furnished_room(h=0.01)
+    if name == "street_canyon_dense":
+        return scenes.street_canyon(h=0.05)
     raise SystemExit(f"unknown workload {name}")
 
 
@@ -363,7 +369,8 @@ def main():
     ap.add_argument("--steps", type=int, default=10)
     ap.add_argument("--warmup", type=int, default=3)
     ap.add_argument("--workload", default="furnished_room",
-                    choices=["furnished_room", "box_room", "street_canyon", "batch", "serve", "copy"])
+                    choices=["furnished_room", "box_room", "street_canyon", "furnished_room_dense",
+                             "street_canyon_dense", "batch", "serve", "copy"])
     ap.add_argument("--copy-mib", type=int, default=1024)
     ap.add_argument("--batch-scenes", type=int, default=256)
     ap.add_argument("--batch-point-scale", type=float, default=1.0)

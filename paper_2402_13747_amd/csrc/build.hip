@@ -214,11 +214,18 @@ __device__ __forceinline__ uint32_t disk_leaves(const KeyParams& kp, const float
     return k;
 }
 
+// Per point, the number of leaves its disk meets; `total` receives their sum
+// in 64 bits (the 32-bit scan of the counts must not wrap).
 __global__ __launch_bounds__(BUILD_BLOCK) void k_key_count(KeyParams kp, const float* xyz, const float4* un, int64_t n,
-                                                           uint32_t* cnt) {
+                                                           uint32_t* cnt, unsigned long long* total) {
     int64_t i = (int64_t)blockIdx.x * BUILD_BLOCK + threadIdx.x;
-    if (i >= n) return;
-    cnt[i] = disk_leaves<false, uint64_t>(kp, xyz, un, i, nullptr, nullptr, 0);
+    uint32_t c = 0;
+    if (i < n) {
+        c = disk_leaves<false, uint64_t>(kp, xyz, un, i, nullptr, nullptr, 0);
+        cnt[i] = c;
+    }
+    const unsigned long long w = wave_sum_u64(c);
+    if (lane_id() == 0 && w) atomicAdd(total, w);
 }
 
 // Keys are 32-bit when the hierarchical key fits (less sort traffic), else 64-bit.
@@ -643,15 +650,24 @@ static int build_hierarchy(const float* xyz, const float4* unit_nrm, const uint3
     kp.r_s = v.r_s;
     kp.pad = v.pad;
     uint32_t *cnt = nullptr, *tot = nullptr;
-    if ((rc = T.alloc(&cnt, (size_t)n)) || (rc = T.alloc(&tot, 1))) return rc;
-    hipLaunchKernelGGL(k_key_count, dim3(blocks_for(n)), dim3(BUILD_BLOCK), 0, s, kp, xyz, unit_nrm, n, cnt);
+    unsigned long long* tot64 = nullptr;
+    if ((rc = T.alloc(&cnt, (size_t)n)) || (rc = T.alloc(&tot, 1)) || (rc = T.alloc(&tot64, 1))) return rc;
+    if ((rc = fill_u64((uint64_t*)tot64, 0ull, 1, s))) return rc;
+    hipLaunchKernelGGL(k_key_count, dim3(blocks_for(n)), dim3(BUILD_BLOCK), 0, s, kp, xyz, unit_nrm, n, cnt, tot64);
     if ((rc = scan_u32(cnt, cnt, n, tot, s))) return rc;
-    uint32_t host_tot = 0;
-    if (hipMemcpyAsync(&host_tot, tot, 4, hipMemcpyDeviceToHost, s) != hipSuccess || hipStreamSynchronize(s) != hipSuccess) {
+    unsigned long long host_tot = 0;
+    if (hipMemcpyAsync(&host_tot, tot64, 8, hipMemcpyDeviceToHost, s) != hipSuccess ||
+        hipStreamSynchronize(s) != hipSuccess) {
         set_error("build_voxels: key count failed: %s", hipGetErrorString(hipGetLastError()));
         return PCRL_EHIP;
     }
-    const int64_t m = host_tot;
+    // entries are indexed with 32 bits throughout (ranges, sort values, surfel ids)
+    if (host_tot > 0xFFFFFFF0ull) {
+        set_error("build_voxels: %llu (leaf, point) entries exceed the 32-bit entry index; use a larger leaf size "
+                  "or fewer points", host_tot);
+        return PCRL_EINVAL;
+    }
+    const int64_t m = (int64_t)host_tot;
     hb.n_entries = m;
 
     // emit and sort (key, local point index); 32-bit keys when they fit
