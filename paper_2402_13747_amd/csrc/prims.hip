@@ -11,6 +11,7 @@
 // tile keys are ranked in input order, so the whole sort is stable.
 #include "internal.h"
 
+#include <algorithm>
 #include <cstdio>
 #include <map>
 #include <mutex>
@@ -404,33 +405,36 @@ int scan_u32(const uint32_t* in, uint32_t* out, int64_t n, uint32_t* total, hipS
 // LSD radix sort, 8-bit digits
 // ---------------------------------------------------------------------------
 
-constexpr int RADIX_BITS = 8;
-constexpr int RADIX = 1 << RADIX_BITS;
+// Digits of DB bits (4..8): a sort of `bits` key bits takes ceil(bits / 8)
+// passes, with the digit width spread evenly over them (fewer digits mean
+// longer runs per digit in a tile: better-coalesced scatter writes).
 constexpr int SORT_WAVE = 64;
 constexpr int SORT_ITEMS = 32;
 constexpr int SORT_TILE = SORT_WAVE * SORT_ITEMS;  // 2048 keys per one-wave block
 
-template <typename K>
+template <typename K, int DB>
 __global__ __launch_bounds__(SORT_WAVE) void k_radix_hist(const K* keys, int64_t n, int shift, uint32_t* hist,
                                                           uint32_t n_tiles) {
-    __shared__ uint32_t h[RADIX];
-    for (int d = threadIdx.x; d < RADIX; d += SORT_WAVE) h[d] = 0;
+    constexpr int R = 1 << DB;
+    __shared__ uint32_t h[R];
+    for (int d = threadIdx.x; d < R; d += SORT_WAVE) h[d] = 0;
     __syncthreads();
     const int64_t tile = (int64_t)blockIdx.x * SORT_TILE;
     for (int k = 0; k < SORT_ITEMS; ++k) {
         int64_t i = tile + (int64_t)k * SORT_WAVE + threadIdx.x;
-        if (i < n) atomicAdd(&h[(uint32_t)(keys[i] >> shift) & (RADIX - 1)], 1u);
+        if (i < n) atomicAdd(&h[(uint32_t)(keys[i] >> shift) & (R - 1)], 1u);
     }
     __syncthreads();
-    for (int d = threadIdx.x; d < RADIX; d += SORT_WAVE) hist[(size_t)d * n_tiles + blockIdx.x] = h[d];
+    for (int d = threadIdx.x; d < R; d += SORT_WAVE) hist[(size_t)d * n_tiles + blockIdx.x] = h[d];
 }
 
-template <typename K>
+template <typename K, int DB>
 __global__ __launch_bounds__(SORT_WAVE) void k_radix_scatter(const K* keys_in, const uint32_t* vals_in, K* keys_out,
                                                              uint32_t* vals_out, int64_t n, int shift,
                                                              const uint32_t* offs, uint32_t n_tiles) {
-    __shared__ uint32_t run[RADIX];
-    for (int d = threadIdx.x; d < RADIX; d += SORT_WAVE) run[d] = offs[(size_t)d * n_tiles + blockIdx.x];
+    constexpr int R = 1 << DB;
+    __shared__ uint32_t run[R];
+    for (int d = threadIdx.x; d < R; d += SORT_WAVE) run[d] = offs[(size_t)d * n_tiles + blockIdx.x];
     __syncthreads();
     const int64_t tile = (int64_t)blockIdx.x * SORT_TILE;
     const uint64_t lt = lanemask_lt();
@@ -439,10 +443,10 @@ __global__ __launch_bounds__(SORT_WAVE) void k_radix_scatter(const K* keys_in, c
         const bool valid = i < n;
         K key = valid ? keys_in[i] : K(0);
         uint32_t val = (valid && vals_in) ? vals_in[i] : 0u;
-        const uint32_t digit = (uint32_t)(key >> shift) & (RADIX - 1);
+        const uint32_t digit = (uint32_t)(key >> shift) & (R - 1);
         uint64_t peers = __ballot(valid);
 #pragma unroll
-        for (int b = 0; b < RADIX_BITS; ++b) {
+        for (int b = 0; b < DB; ++b) {
             const bool bit = (digit >> b) & 1u;
             const uint64_t m = __ballot(bit);
             peers &= bit ? m : ~m;
@@ -461,6 +465,17 @@ __global__ __launch_bounds__(SORT_WAVE) void k_radix_scatter(const K* keys_in, c
     }
 }
 
+template <typename K, int DB>
+static int radix_pass(const K* ka, const uint32_t* va, K* kb, uint32_t* vb, int64_t n, int shift, uint32_t* hist,
+                      uint32_t n_tiles, hipStream_t s) {
+    hipLaunchKernelGGL((k_radix_hist<K, DB>), dim3(n_tiles), dim3(SORT_WAVE), 0, s, ka, n, shift, hist, n_tiles);
+    if (hipGetLastError() != hipSuccess) return PCRL_EHIP;
+    PCRL_TRY(scan_u32(hist, hist, ((int64_t)1 << DB) * n_tiles, nullptr, s));
+    hipLaunchKernelGGL((k_radix_scatter<K, DB>), dim3(n_tiles), dim3(SORT_WAVE), 0, s, ka, va, kb, vb, n, shift, hist,
+                       n_tiles);
+    return hipGetLastError() == hipSuccess ? PCRL_OK : PCRL_EHIP;
+}
+
 template <typename K>
 static int radix_sort_impl(K* keys, uint32_t* vals, int64_t n, int bits, hipStream_t s) {
     if (n <= 1 || bits <= 0) return PCRL_OK;
@@ -470,31 +485,26 @@ static int radix_sort_impl(K* keys, uint32_t* vals, int64_t n, int bits, hipStre
     }
     const int64_t n_tiles64 = (n + SORT_TILE - 1) / SORT_TILE;
     const uint32_t n_tiles = (uint32_t)n_tiles64;
-    const int passes = (bits + RADIX_BITS - 1) / RADIX_BITS;
+    const int passes = (bits + 7) / 8;
+    const int db = std::max(4, (bits + passes - 1) / passes);  // 4..8
     K* k2 = nullptr;
     uint32_t* v2 = nullptr;
     uint32_t* hist = nullptr;
     int rc = dalloc((void**)&k2, (size_t)n * sizeof(K), s);
     if (rc == PCRL_OK && vals) rc = dalloc((void**)&v2, (size_t)n * sizeof(uint32_t), s);
-    if (rc == PCRL_OK) rc = dalloc((void**)&hist, (size_t)RADIX * n_tiles * sizeof(uint32_t), s);
+    if (rc == PCRL_OK) rc = dalloc((void**)&hist, ((size_t)1 << db) * n_tiles * sizeof(uint32_t), s);
     K* ka = keys;
     K* kb = k2;
     uint32_t* va = vals;
     uint32_t* vb = v2;
     for (int p = 0; p < passes && rc == PCRL_OK; ++p) {
-        const int shift = p * RADIX_BITS;
-        hipLaunchKernelGGL(k_radix_hist<K>, dim3(n_tiles), dim3(SORT_WAVE), 0, s, ka, n, shift, hist, n_tiles);
-        if (hipGetLastError() != hipSuccess) {
-            rc = PCRL_EHIP;
-            break;
-        }
-        rc = scan_u32(hist, hist, (int64_t)RADIX * n_tiles, nullptr, s);
-        if (rc != PCRL_OK) break;
-        hipLaunchKernelGGL(k_radix_scatter<K>, dim3(n_tiles), dim3(SORT_WAVE), 0, s, ka, va, kb, vb, n, shift, hist,
-                           n_tiles);
-        if (hipGetLastError() != hipSuccess) {
-            rc = PCRL_EHIP;
-            break;
+        const int shift = p * db;
+        switch (db) {
+        case 4: rc = radix_pass<K, 4>(ka, va, kb, vb, n, shift, hist, n_tiles, s); break;
+        case 5: rc = radix_pass<K, 5>(ka, va, kb, vb, n, shift, hist, n_tiles, s); break;
+        case 6: rc = radix_pass<K, 6>(ka, va, kb, vb, n, shift, hist, n_tiles, s); break;
+        case 7: rc = radix_pass<K, 7>(ka, va, kb, vb, n, shift, hist, n_tiles, s); break;
+        default: rc = radix_pass<K, 8>(ka, va, kb, vb, n, shift, hist, n_tiles, s); break;
         }
         K* tk = ka; ka = kb; kb = tk;
         uint32_t* tv = va; va = vb; vb = tv;
