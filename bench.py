@@ -117,6 +117,36 @@ def cpu_baseline(s, t_eps, seconds):
                       f"FP64 brute force over all {s.n_points} points, {dt2:.1f} s"}
 
 
+def cpu_dda_baseline(s, t_eps, seconds):
+    """The oracle's FP64 uniform-grid DDA (same hits as its brute force, bit for
+    bit) on all host threads: a CPU rate with an acceleration structure."""
+    import oracle
+    oracle.build(force=False)
+    dirs = oracle.fibonacci(s.n_rays)
+    threads = oracle.default_threads()
+    n_total = s.n_rays * len(s.tx)
+    cell = float(s.levels[-1])
+    t0 = time.perf_counter()
+    grid = oracle.Grid(s.xyz, float(np.float32(s.surfel_radius)), cell)
+    t_grid = time.perf_counter() - t0
+
+    def run(n):
+        sel = (np.arange(n, dtype=np.int64) * (n_total // n)).astype(np.int64)
+        t1 = time.perf_counter()
+        oracle.launch(s.xyz, s.normal, s.label, s.tx, s.rx, dirs, K=s.max_reflections,
+                      r_s=float(np.float32(s.surfel_radius)), t_eps=t_eps, sel=sel, n_threads=threads, grid=grid)
+        return time.perf_counter() - t1
+
+    n = max(threads * 2048, 16384)
+    dt = run(n)
+    n2 = int(min(n_total, max(n, n * seconds / max(dt, 1e-6))))
+    n2 = max(threads, (n2 // threads) * threads)
+    dt2 = run(n2)
+    return {"value": n2 / dt2, "unit": "rays/s", "cores": threads, "kind": "oracle uniform-grid DDA (FP64)",
+            "sample": f"{n2} of {n_total} rays (every {n_total // n2}-th), all {s.max_reflections + 1} segments, "
+                      f"{cell} m cells (grid built in {t_grid:.1f} s, not timed), {dt2:.1f} s"}
+
+
 def _gen_batch_scene(args):
     import scenes
     seed, point_scale, ray_scale = args
@@ -524,9 +554,12 @@ def main():
         scene.release()
 
     cpu = None
+    cpu_dda = None
     if not args.no_cpu_baseline:
         log("[bench] timing the CPU oracle on a ray sample")
         cpu = cpu_baseline(s, t_eps, args.cpu_seconds)
+        log("[bench] timing the oracle's CPU grid DDA on a ray sample")
+        cpu_dda = cpu_dda_baseline(s, t_eps, args.cpu_seconds / 2)
 
     out = {
         "metric": "rays/s and bounce-segments/s (HBM GB/s % peak); p50/p99 query latency, served vs plain",
@@ -551,6 +584,7 @@ def main():
         "paths": {"rows": int(paths["n_rows"]), "keys": int(paths["n_keys"])},
         "roofline": roof,
         "cpu_baseline": cpu,
+        "cpu_dda": cpu_dda,
         "refine": refine,
     }
     if algo is not None:

@@ -7,7 +7,9 @@ definition of what the HIP path computes and shares no code with it.
 * ``fibonacci(n)``       uniformly spaced launch directions (Fibonacci lattice)
 * ``ray_spacing(n)``     ideal angular spacing alpha of n directions
 * ``launch(...)``        brute force: every ray against every point
-                         (``oracle.c``), with parity bands on request
+                         (``oracle.c``), with parity bands on request; or,
+                         given a ``Grid``, a CPU uniform-grid DDA that must
+                         give the same hits bit for bit
 * ``dedup(...)``         coarse paths = records grouped by (tx, rx, b, labels)
                          with the kappa shortest kept (Section 2.2.3)
 * ``image_method``       closed-form image-source paths in a box room
@@ -64,6 +66,7 @@ class OracleArgs(C.Structure):
         ("rec_cap", C.c_int64), ("n_rec", C.c_int64),
         ("rec_sel", C.c_void_p), ("rec_g", C.c_void_p), ("rec_tx", C.c_void_p), ("rec_rx", C.c_void_p),
         ("rec_b", C.c_void_p), ("rec_lpoly", C.c_void_p), ("rec_lunf", C.c_void_p), ("rec_flags", C.c_void_p),
+        ("grid", C.c_void_p),
     ]
 
 
@@ -106,6 +109,10 @@ def _load():
         lib.oracle_launch.restype = C.c_int
         lib.oracle_refine.argtypes = [C.POINTER(OracleRefineArgs)]
         lib.oracle_refine.restype = C.c_int
+        lib.oracle_grid_build.argtypes = [C.c_void_p, C.c_int64, C.c_double, C.c_double]
+        lib.oracle_grid_build.restype = C.c_void_p
+        lib.oracle_grid_free.argtypes = [C.c_void_p]
+        lib.oracle_grid_free.restype = None
         _lib = lib
     return _lib
 
@@ -133,16 +140,39 @@ def default_threads() -> int:
         return os.cpu_count() or 1
 
 
+class Grid:
+    """Uniform grid of cubic cells listing every point whose disk's bounding
+    sphere meets the cell (``oracle_grid_build``); pass it to ``launch`` to
+    trace by DDA instead of brute force (same results, bit for bit)."""
+
+    def __init__(self, xyz, r_s, cell):
+        self._xyz = np.ascontiguousarray(xyz, np.float32)
+        self._h = _load().oracle_grid_build(_p(self._xyz), self._xyz.shape[0], float(r_s), float(cell))
+        if not self._h:
+            raise MemoryError("oracle_grid_build failed")
+
+    @property
+    def handle(self):
+        return self._h
+
+    def __del__(self):
+        if getattr(self, "_h", None):
+            _load().oracle_grid_free(self._h)
+            self._h = None
+
+
 def launch(xyz, normal, label, tx, rx, dirs, K, r_s, t_eps, sigma=1.25, alpha=0.0, sel=None,
            parity=False, tie_rel=1e-4, err_abs=0.0, err_dir=0.0, edge_rel=1e-4, den_amb=1e-6,
-           n_threads=None, want_segments=False, rec_cap=None):
+           n_threads=None, want_segments=False, rec_cap=None, grid=None):
     """Brute-force launch of ``len(dirs)`` rays from every TX (FP64).
 
     Returns a dict of numpy arrays.  Per traced ray r and segment b (index
     ``[r, b]``): ``hit_id`` (-1 none), ``hit_t``; in parity mode ``acc_n`` and
     ``acc_id`` (the acceptable answers, -1 = no hit).  Per reflection:
     ``seq`` labels and ``pts`` points.  Records: ``rec_*`` arrays in traced-ray
-    order (``rec_flags`` bit0 received, bit1 ambiguous).
+    order (``rec_flags`` bit0 received, bit1 ambiguous).  With ``grid`` (a
+    ``Grid`` over the same points) the nearest hits come from its DDA; parity
+    mode always uses the brute force.
     """
     lib = _load()
     xyz = np.ascontiguousarray(xyz, np.float32)
@@ -194,6 +224,7 @@ def launch(xyz, normal, label, tx, rx, dirs, K, r_s, t_eps, sigma=1.25, alpha=0.
         a.seq = _p(out["seq"]) if K > 0 else None
         a.pts = _p(out["pts"]) if K > 0 else None
         a.rec_cap = cap
+        a.grid = grid.handle if grid is not None else None
         for k, v in recs.items():
             setattr(a, k, _p(v))
         rc = lib.oracle_launch(C.byref(a))

@@ -96,7 +96,19 @@ typedef struct {
     double* rec_lpoly;         /* L + |rx - o| */
     double* rec_lunf;          /* L + s */
     int32_t* rec_flags;        /* bit0 received, bit1 ambiguous */
+    const struct OracleGrid* grid;  /* NULL: brute force; else the uniform-grid DDA (parity mode off) */
 } OracleArgs;
+
+/* A uniform grid of cubic cells over the points, each cell listing every
+ * point whose disk's bounding sphere meets it (the cell box padded by a
+ * rounding margin): a superset of the points a ray can hit inside the cell. */
+typedef struct OracleGrid {
+    double lo[3];
+    double cell;
+    int64_t dims[3];
+    int64_t* begin;            /* [cells + 1] CSR offsets */
+    int64_t* items;            /* point ids */
+} OracleGrid;
 
 /* ------------------------------------------------------------------------ */
 /* ray directions                                                            */
@@ -258,6 +270,153 @@ static void nearest_hit(const OracleArgs* a, const Pts64* P, const double* o, co
     }
 }
 
+/* The hit test of point m (same formula as the brute force). */
+static inline int surfel_hit(const OracleArgs* a, const Pts64* P, const double* o, const double* d, int64_t m,
+                             double* t_out)
+{
+    double den = d[0] * P->nx[m] + d[1] * P->ny[m] + d[2] * P->nz[m];
+    if (fabs(den) <= ORACLE_DEN_SKIP) return 0;
+    double wx = P->px[m] - o[0], wy = P->py[m] - o[1], wz = P->pz[m] - o[2];
+    double t = (wx * P->nx[m] + wy * P->ny[m] + wz * P->nz[m]) / den;
+    if (!(t > a->t_eps)) return 0;
+    double qx = o[0] + t * d[0] - P->px[m];
+    double qy = o[1] + t * d[1] - P->py[m];
+    double qz = o[2] + t * d[2] - P->pz[m];
+    if (!(qx * qx + qy * qy + qz * qz <= a->r_s * a->r_s)) return 0;
+    *t_out = t;
+    return 1;
+}
+
+/* Nearest hit by a 3D DDA over the grid (Amanatides and Woo): cells in ray
+ * order, every listed point tested, stop once the best hit lies before the
+ * current cell's exit.  Same (t, index) minimum as the brute force because
+ * every point a ray meets inside a cell is listed in that cell. */
+static void nearest_hit_grid(const OracleArgs* a, const Pts64* P, const OracleGrid* G, const double* o,
+                             const double* d, int64_t last, int64_t* best_out, double* tb_out)
+{
+    int64_t best = -1;
+    double tb = INFINITY;
+    double t0 = 0.0, t1 = INFINITY;
+    for (int ax = 0; ax < 3; ++ax) {
+        double lo = G->lo[ax], hi = G->lo[ax] + (double)G->dims[ax] * G->cell;
+        if (d[ax] != 0.0) {
+            double ta = (lo - o[ax]) / d[ax], tc = (hi - o[ax]) / d[ax];
+            t0 = fmax(t0, fmin(ta, tc));
+            t1 = fmin(t1, fmax(ta, tc));
+        } else if (o[ax] < lo || o[ax] > hi) {
+            t1 = -1.0;
+        }
+    }
+    if (t0 <= t1) {
+        int64_t c[3], step[3];
+        double tmax[3], tdelta[3];
+        for (int ax = 0; ax < 3; ++ax) {
+            double x = o[ax] + t0 * d[ax];
+            int64_t ci = (int64_t)floor((x - G->lo[ax]) / G->cell);
+            if (ci < 0) ci = 0;
+            if (ci >= G->dims[ax]) ci = G->dims[ax] - 1;
+            c[ax] = ci;
+            if (d[ax] > 0.0) {
+                step[ax] = 1;
+                tmax[ax] = (G->lo[ax] + (double)(ci + 1) * G->cell - o[ax]) / d[ax];
+                tdelta[ax] = G->cell / d[ax];
+            } else if (d[ax] < 0.0) {
+                step[ax] = -1;
+                tmax[ax] = (G->lo[ax] + (double)ci * G->cell - o[ax]) / d[ax];
+                tdelta[ax] = -G->cell / d[ax];
+            } else {
+                step[ax] = 0;
+                tmax[ax] = INFINITY;
+                tdelta[ax] = INFINITY;
+            }
+        }
+        for (;;) {
+            int64_t cell = c[0] + G->dims[0] * (c[1] + G->dims[1] * c[2]);
+            for (int64_t e = G->begin[cell]; e < G->begin[cell + 1]; ++e) {
+                int64_t m = G->items[e];
+                double t;
+                if (m == last || !surfel_hit(a, P, o, d, m, &t)) continue;
+                if (t < tb || (t == tb && m < best)) {
+                    tb = t;
+                    best = m;
+                }
+            }
+            int ax = tmax[0] <= tmax[1] ? (tmax[0] <= tmax[2] ? 0 : 2) : (tmax[1] <= tmax[2] ? 1 : 2);
+            if (best >= 0 && tb < tmax[ax]) break;
+            c[ax] += step[ax];
+            if (c[ax] < 0 || c[ax] >= G->dims[ax]) break;
+            tmax[ax] += tdelta[ax];
+        }
+    }
+    *best_out = best;
+    *tb_out = tb;
+}
+
+/* Build the grid of cubic cells of edge `cell` over n points with disks of
+ * radius r_s.  Returns NULL when out of memory or on bad arguments. */
+OracleGrid* oracle_grid_build(const float* xyz, int64_t n, double r_s, double cell)
+{
+    if (n < 0 || (n > 0 && !xyz) || !(r_s > 0.0) || !(cell > 0.0)) return NULL;
+    OracleGrid* G = calloc(1, sizeof(OracleGrid));
+    if (!G) return NULL;
+    double lo[3] = {INFINITY, INFINITY, INFINITY}, hi[3] = {-INFINITY, -INFINITY, -INFINITY};
+    for (int64_t i = 0; i < n; ++i)
+        for (int ax = 0; ax < 3; ++ax) {
+            lo[ax] = fmin(lo[ax], (double)xyz[3 * i + ax]);
+            hi[ax] = fmax(hi[ax], (double)xyz[3 * i + ax]);
+        }
+    if (n == 0)
+        for (int ax = 0; ax < 3; ++ax) lo[ax] = hi[ax] = 0.0;
+    double scale = 0.0;
+    for (int ax = 0; ax < 3; ++ax) scale = fmax(scale, fmax(fabs(lo[ax]), fabs(hi[ax])));
+    const double pad = 1e-9 * fmax(scale, cell) + 1e-12;   /* covers the DDA's rounding */
+    int64_t total = 1;
+    for (int ax = 0; ax < 3; ++ax) {
+        G->lo[ax] = lo[ax] - r_s - 2.0 * pad;
+        G->dims[ax] = (int64_t)ceil((hi[ax] + r_s + 2.0 * pad - G->lo[ax]) / cell) + 1;
+        total *= G->dims[ax];
+    }
+    G->cell = cell;
+    G->begin = calloc((size_t)total + 1, sizeof(int64_t));
+    if (!G->begin) { free(G); return NULL; }
+    for (int pass = 0; pass < 2; ++pass) {
+        for (int64_t i = 0; i < n; ++i) {
+            int64_t a0[3], a1[3];
+            for (int ax = 0; ax < 3; ++ax) {
+                double x = (double)xyz[3 * i + ax];
+                a0[ax] = (int64_t)floor((x - r_s - pad - G->lo[ax]) / cell);
+                a1[ax] = (int64_t)floor((x + r_s + pad - G->lo[ax]) / cell);
+                if (a0[ax] < 0) a0[ax] = 0;
+                if (a1[ax] >= G->dims[ax]) a1[ax] = G->dims[ax] - 1;
+            }
+            for (int64_t z = a0[2]; z <= a1[2]; ++z)
+                for (int64_t y = a0[1]; y <= a1[1]; ++y)
+                    for (int64_t x = a0[0]; x <= a1[0]; ++x) {
+                        int64_t cidx = x + G->dims[0] * (y + G->dims[1] * z);
+                        if (pass == 0) G->begin[cidx + 1]++;
+                        else G->items[G->begin[cidx]++] = i;
+                    }
+        }
+        if (pass == 0) {
+            for (int64_t k = 0; k < total; ++k) G->begin[k + 1] += G->begin[k];
+            G->items = malloc((size_t)(G->begin[total] > 0 ? G->begin[total] : 1) * sizeof(int64_t));
+            if (!G->items) { free(G->begin); free(G); return NULL; }
+        } else {
+            for (int64_t k = total; k > 0; --k) G->begin[k] = G->begin[k - 1];
+            G->begin[0] = 0;
+        }
+    }
+    return G;
+}
+
+void oracle_grid_free(OracleGrid* G)
+{
+    if (!G) return;
+    free(G->begin);
+    free(G->items);
+    free(G);
+}
+
 static void trace_range(Work* w)
 {
     const OracleArgs* a = w->a;
@@ -293,7 +452,8 @@ static void trace_range(Work* w)
             double tb;
             int32_t na = 1;
             int64_t acc[ORACLE_MAXACC];
-            nearest_hit(a, P, o, d, last, b, &best, &tb, &na, acc);
+            if (a->grid && !a->parity) nearest_hit_grid(a, P, a->grid, o, d, last, &best, &tb);
+            else nearest_hit(a, P, o, d, last, b, &best, &tb, &na, acc);
             if (a->hit_id) a->hit_id[s_idx] = best;
             if (a->hit_t) a->hit_t[s_idx] = tb;
             if (a->seg_o) { a->seg_o[3 * s_idx] = o[0]; a->seg_o[3 * s_idx + 1] = o[1]; a->seg_o[3 * s_idx + 2] = o[2]; }

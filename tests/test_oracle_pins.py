@@ -337,3 +337,40 @@ def test_parity_sets_contain_exact_answer(oracle_lib):
         assert r["hit_id"][ray, b] in acc
     # the bands are narrow: most segments have a single admissible answer
     assert np.mean(r["acc_n"][traced] == 1) > 0.8
+
+
+# --------------------------------------------------------------------------- acceleration exactness
+
+def _axis_and_diagonal_dirs():
+    d = [(1, 0, 0), (-1, 0, 0), (0, 1, 0), (0, -1, 0), (0, 0, 1), (0, 0, -1),
+         (1, 1, 0), (1, -1, 0), (0, 1, 1), (1, 0, -1), (1, 1, 1), (-1, 1, -1), (1e-9, 1, 0), (1, 1e-12, 1e-12)]
+    d = np.asarray(d, np.float64)
+    return (d / np.linalg.norm(d, axis=1, keepdims=True)).astype(np.float32)
+
+
+@pytest.mark.parametrize("seed", [0, 1, 2, 3, 4, 5])
+@pytest.mark.parametrize("cell_over_rs", [0.3, 1.0, 2.5])
+def test_grid_dda_equals_brute_force(oracle_lib, seed, cell_over_rs):
+    # the acceleration logic (every point listed in each cell its disk can be hit
+    # in, cells in ray order, stop once the best hit precedes the cell's exit)
+    # must reproduce the brute force bit for bit: same hit ids, same distances
+    s = scenes.random_scene(seed, n_rays=2000, n_rx=3, pos_sigma=0.01, tilt_sigma=0.05)
+    r_s = float(np.float32(s.surfel_radius))
+    t_eps = 1e-4
+    grid = oracle_lib.Grid(s.xyz, r_s, cell_over_rs * r_s)
+    for dirs in (oracle_lib.fibonacci(s.n_rays), _axis_and_diagonal_dirs()):
+        a = oracle_lib.launch(s.xyz, s.normal, s.label, s.tx, s.rx, dirs, 3, r_s, t_eps)
+        b = oracle_lib.launch(s.xyz, s.normal, s.label, s.tx, s.rx, dirs, 3, r_s, t_eps, grid=grid)
+        assert np.array_equal(a["hit_id"], b["hit_id"])
+        assert np.array_equal(a["hit_t"], b["hit_t"], equal_nan=True)
+        assert a["n_rec"] == b["n_rec"] and np.array_equal(a["rec_lpoly"], b["rec_lpoly"])
+
+
+def test_grid_dda_on_the_box_room(box_run, oracle_lib):
+    # axis-aligned walls on cell boundaries (0.25 m cells, walls at 0, 3, 8, 10 m)
+    s, d, r = box_run
+    grid = oracle_lib.Grid(s.xyz, s.surfel_radius, 0.25)
+    g = oracle_lib.launch(s.xyz, s.normal, s.label, s.tx, s.rx, d, K=2, r_s=s.surfel_radius, t_eps=_box_t_eps(),
+                          grid=grid)
+    assert np.array_equal(r["hit_id"], g["hit_id"])
+    assert np.array_equal(r["hit_t"], g["hit_t"], equal_nan=True)
