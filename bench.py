@@ -554,12 +554,11 @@ def main():
         scene.release()
 
     cpu = None
-    cpu_dda = None
     if not args.no_cpu_baseline:
         log("[bench] timing the CPU oracle on a ray sample")
         cpu = cpu_baseline(s, t_eps, args.cpu_seconds)
         log("[bench] timing the oracle's CPU grid DDA on a ray sample")
-        cpu_dda = cpu_dda_baseline(s, t_eps, args.cpu_seconds / 2)
+        cpu["grid_dda"] = cpu_dda_baseline(s, t_eps, args.cpu_seconds / 2)
 
     out = {
         "metric": "rays/s and bounce-segments/s (HBM GB/s % peak); p50/p99 query latency, served vs plain",
@@ -584,7 +583,6 @@ def main():
         "paths": {"rows": int(paths["n_rows"]), "keys": int(paths["n_keys"])},
         "roofline": roof,
         "cpu_baseline": cpu,
-        "cpu_dda": cpu_dda,
         "refine": refine,
     }
     if algo is not None:
