@@ -51,6 +51,7 @@ extern "C" {
 #define PCRL_EOVERFLOW -3   /* results exceed a capacity; the size needed is reported (see each call) */
 #define PCRL_EHIP      -4   /* HIP runtime error */
 #define PCRL_EBUSY     -5   /* admission refused (serving) */
+#define PCRL_ECANCELED -6   /* the query was cancelled (serving) */
 
 #define PCRL_MAX_LEVELS 4
 #define PCRL_MAX_REFLECTIONS 8
@@ -457,6 +458,13 @@ int serve_poll(PcrlServer* server, int64_t ticket, double timeout_s, PcrlServeRe
 /* Copy a finished query's coarse paths (rows as in collect_paths) into HOST
  * arrays of out->capacity rows.  PCRL_EOVERFLOW if they do not fit. */
 int serve_result(PcrlServer* server, int64_t ticket, PcrlPaths* out);
+
+/* Cancel a query.  A pending one leaves the queue at once; a running one
+ * finishes its kernels (they cannot be interrupted) but its result is not
+ * collected.  Either way serve_poll then reports status PCRL_ECANCELED; the
+ * other queries are unaffected.  A finished query is left as it is.
+ * PCRL_EINVAL for an unknown ticket. */
+int serve_cancel(PcrlServer* server, int64_t ticket);
 
 /* Forget a finished ticket (frees its host result). */
 int serve_release(PcrlServer* server, int64_t ticket);

@@ -550,6 +550,10 @@ class Server:
         out["epoch"] = info["epoch"]
         return out
 
+    def cancel(self, ticket):
+        """Cancel a pending or running query (its poll then reports PCRL_ECANCELED)."""
+        check("serve_cancel", lib.serve_cancel(self._h, int(ticket)))
+
     def release(self, ticket):
         check("serve_release", lib.serve_release(self._h, int(ticket)))
         self._K.pop(int(ticket), None)

@@ -22,6 +22,7 @@ PCRL_ENOMEM = -2
 PCRL_EOVERFLOW = -3
 PCRL_EHIP = -4
 PCRL_EBUSY = -5
+PCRL_ECANCELED = -6
 MAX_LEVELS = 4
 MAX_REFLECTIONS = 8
 
@@ -40,7 +41,7 @@ REFINE_DEGENERATE = 5
 REFINE_SMOOTH = 1
 
 STATUS_NAMES = {0: "PCRL_OK", -1: "PCRL_EINVAL", -2: "PCRL_ENOMEM", -3: "PCRL_EOVERFLOW", -4: "PCRL_EHIP",
-                -5: "PCRL_EBUSY"}
+                -5: "PCRL_EBUSY", -6: "PCRL_ECANCELED"}
 
 
 ALLOC_FN = C.CFUNCTYPE(C.c_void_p, C.c_size_t, C.c_void_p, C.c_void_p)
@@ -160,6 +161,7 @@ SIGNATURES = {
     "serve_update": (C.c_int, [C.c_void_p, C.c_void_p, C.c_void_p, C.c_void_p, C.c_void_p, C.c_int64]),
     "serve_poll": (C.c_int, [C.c_void_p, C.c_int64, C.c_double, C.POINTER(PcrlServeResult)]),
     "serve_result": (C.c_int, [C.c_void_p, C.c_int64, C.POINTER(PcrlPaths)]),
+    "serve_cancel": (C.c_int, [C.c_void_p, C.c_int64]),
     "serve_release": (C.c_int, [C.c_void_p, C.c_int64]),
     "serve_stats": (C.c_int, [C.c_void_p, C.POINTER(PcrlServeStats)]),
     "serve_destroy": (C.c_int, [C.c_void_p]),

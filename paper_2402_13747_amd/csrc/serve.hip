@@ -46,6 +46,7 @@ struct ServeReq {
     int64_t bytes = 0;
     clk::time_point t_submit, t_admit, t_done;
     int status = 0;  // 0 pending, 1 running, 2 done, < 0 failed (PCRL status)
+    bool cancel = false;  // serve_cancel while running: drop the result when the round retires
     int64_t epoch = 0;
     int32_t K = 0;
     // results, host
@@ -177,9 +178,16 @@ static void retire(PcrlServer* S) {
         hipStream_t s = S->streams[(size_t)R.stream];
         for (size_t k = 0; k < R.reqs.size(); ++k) {
             ServeReq* r = R.reqs[k];
+            bool cancelled = false;
+            {
+                std::lock_guard<std::mutex> lock(S->mu);
+                cancelled = r->cancel;
+            }
             // PCRL_EOVERFLOW here means the query's records exceeded its record
             // capacity; the message names the capacity to resubmit with
-            const int rc = collect_one(S, R.launches[k], r, s);
+            int rc = PCRL_ECANCELED;
+            if (!cancelled) rc = collect_one(S, R.launches[k], r, s);
+            else set_error("serve: ticket %lld was cancelled", (long long)r->ticket);
             destroy_launch(R.launches[k]);
             const clk::time_point now = clk::now();
             std::lock_guard<std::mutex> lock(S->mu);
@@ -493,6 +501,36 @@ extern "C" int serve_result(PcrlServer* S, int64_t ticket, PcrlPaths* out) {
     if (out->len_poly) std::memcpy(out->len_poly, r->len_poly.data(), n * 4);
     if (out->len_unf) std::memcpy(out->len_unf, r->len_unf.data(), n * 4);
     if (out->points && K) std::memcpy(out->points, r->points.data(), n * K * 12);
+    return PCRL_OK;
+}
+
+extern "C" int serve_cancel(PcrlServer* S, int64_t ticket) {
+    clear_error();
+    if (!S) {
+        set_error("serve_cancel: NULL server");
+        return PCRL_EINVAL;
+    }
+    std::lock_guard<std::mutex> lock(S->mu);
+    auto it = S->reqs.find(ticket);
+    if (it == S->reqs.end()) {
+        set_error("serve_cancel: unknown ticket %lld", (long long)ticket);
+        return PCRL_EINVAL;
+    }
+    ServeReq* r = it->second;
+    if (r->status == 0) {
+        // not admitted yet: leave the queue now
+        for (auto q = S->pending.begin(); q != S->pending.end(); ++q)
+            if (*q == r) {
+                S->pending.erase(q);
+                break;
+            }
+        r->status = PCRL_ECANCELED;
+        r->error = "serve: ticket was cancelled before admission";
+        r->t_admit = r->t_done = clk::now();
+        S->cv.notify_all();
+    } else if (r->status == 1) {
+        r->cancel = true;  // its kernels finish; the result is not collected
+    }
     return PCRL_OK;
 }
 

@@ -52,7 +52,7 @@ def test_header_constants_match_binding(pcrl):
     assert defs["PCRL_LAUNCH_COHERENT"] == _lib.LAUNCH_COHERENT
     assert defs["PCRL_KEY_LABELS"] == _lib.KEY_LABELS and defs["PCRL_KEY_LEAVES"] == _lib.KEY_LEAVES
     assert defs["PCRL_MAX_LEVELS"] == _lib.MAX_LEVELS and defs["PCRL_MAX_REFLECTIONS"] == _lib.MAX_REFLECTIONS
-    for name in ("OK", "EINVAL", "ENOMEM", "EOVERFLOW", "EHIP", "EBUSY"):
+    for name in ("OK", "EINVAL", "ENOMEM", "EOVERFLOW", "EHIP", "EBUSY", "ECANCELED"):
         assert defs["PCRL_" + name] == getattr(_lib, "PCRL_" + name)
     for name in ("VALID", "NOT_CONVERGED", "MISS", "WRONG_SIDE", "OCCLUDED", "DEGENERATE", "SMOOTH"):
         assert defs["PCRL_REFINE_" + name] == getattr(_lib, "REFINE_" + name)

@@ -341,6 +341,28 @@ def test_determinism_and_permutation(env):
     assert len(common) >= 0.95 * max(len(p1), len(p2))
 
 
+def test_translation_invariance(env):
+    # a box room on a dyadic grid (0.25 m cells, centres at 0.125 + 0.25 k) moved by an
+    # exactly representable offset: the same coarse paths with the same counts, and
+    # lengths equal up to FP32 rounding of the larger coordinates
+    torch, pcrl, oracle = env
+    off = np.array([16.0, 32.0, 8.0], np.float32)
+    res = []
+    for shift in (np.zeros(3, np.float32), off):
+        s = scenes.box_room(h=0.25, tx=tuple(np.array([2.0, 2.0, 1.5]) + shift),
+                            rx=tuple(np.array([7.0, 5.0, 1.5]) + shift))
+        xyz = (s.xyz + shift).astype(np.float32)
+        assert np.array_equal(xyz - shift, s.xyz)       # the move is exact
+        scene = pcrl.build_voxels(xyz, s.normal, s.label, s.levels, _f32(s.surfel_radius), t_eps=1e-4)
+        launch = pcrl.launch_rays(scene, s.tx, s.rx, n_rays=10_000, max_reflections=2)
+        res.append(parity.device_paths(parity.to_numpy(pcrl.collect_paths(launch, kappa=1))))
+    a, b = res
+    assert set(a) == set(b) and len(a) == 25
+    for key in a:
+        assert a[key][0]["count"] == b[key][0]["count"], key
+        assert abs(a[key][0]["len_poly"] - b[key][0]["len_poly"]) <= 1e-5 * a[key][0]["len_poly"], key
+
+
 def test_edge_cases(env):
     torch, pcrl, oracle = env
     z = np.zeros((0, 3), np.float32)

@@ -162,3 +162,29 @@ def test_serve_budget(env, world):
         srv.submit(sc.tx, sc.rx[:2], n_rays=2_000_000, max_reflections=3)
     assert e.value.status == -5
     srv.close()
+
+
+def test_serve_cancel(env, world):
+    torch, pcrl = env
+    sc, mover, base, n_static, r_s, t_eps = world
+    rays, K, n_rx = 20_000, 3, 2
+    one = rays * 72 + rays * 16 * K + (rays * (K + 1) * n_rx // 16 + 65536) * 16 + rays * 8 + 4096
+    # room for one query at a time: the last two are still queued when cancelled
+    srv = pcrl.Server(base, n_streams=4, max_batch=8, hbm_budget_bytes=int(1.5 * one))
+    tickets = [srv.submit(sc.tx, sc.rx[:2], n_rays=rays, max_reflections=K) for _ in range(6)]
+    srv.cancel(tickets[4])
+    srv.cancel(tickets[5])
+    for t in tickets[:4]:
+        assert srv.poll(t, timeout=60.0)["status"] == 2
+    for t in tickets[4:]:
+        with pytest.raises(pcrl.PcrlError) as e:
+            srv.poll(t, timeout=60.0)
+        assert e.value.status == -6
+        srv.release(t)
+    srv.cancel(tickets[0])                      # finished: left as it is
+    assert srv.poll(tickets[0])["status"] == 2 and srv.result(tickets[0])["n_rows"] >= 0
+    with pytest.raises(pcrl.PcrlError) as e:
+        srv.cancel(1 << 40)
+    assert e.value.status == -1
+    assert srv.stats()["completed"] == 4
+    srv.close()
