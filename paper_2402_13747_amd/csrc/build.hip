@@ -214,18 +214,22 @@ __device__ __forceinline__ uint32_t disk_leaves(const KeyParams& kp, const float
     return k;
 }
 
-// Per point, the number of leaves its disk meets; `total` receives their sum
-// in 64 bits (the 32-bit scan of the counts must not wrap).
+// Per point, the number of leaves its disk meets.
 __global__ __launch_bounds__(BUILD_BLOCK) void k_key_count(KeyParams kp, const float* xyz, const float4* un, int64_t n,
-                                                           uint32_t* cnt, unsigned long long* total) {
+                                                           uint32_t* cnt) {
     int64_t i = (int64_t)blockIdx.x * BUILD_BLOCK + threadIdx.x;
-    uint32_t c = 0;
-    if (i < n) {
-        c = disk_leaves<false, uint64_t>(kp, xyz, un, i, nullptr, nullptr, 0);
-        cnt[i] = c;
-    }
-    const unsigned long long w = wave_sum_u64(c);
-    if (lane_id() == 0 && w) atomicAdd(total, w);
+    if (i >= n) return;
+    cnt[i] = disk_leaves<false, uint64_t>(kp, xyz, un, i, nullptr, nullptr, 0);
+}
+
+// The counts' sum in 64 bits, for inputs whose 32-bit scan might wrap: a
+// grid-stride sum per thread, one atomic per wave.
+__global__ __launch_bounds__(BUILD_BLOCK) void k_count_total(const uint32_t* cnt, int64_t n, unsigned long long* total) {
+    unsigned long long acc = 0;
+    for (int64_t i = (int64_t)blockIdx.x * BUILD_BLOCK + threadIdx.x; i < n; i += (int64_t)gridDim.x * BUILD_BLOCK)
+        acc += cnt[i];
+    acc = wave_sum_u64(acc);
+    if (lane_id() == 0 && acc) atomicAdd(total, acc);
 }
 
 // Keys are 32-bit when the hierarchical key fits (less sort traffic), else 64-bit.
@@ -650,17 +654,28 @@ static int build_hierarchy(const float* xyz, const float4* unit_nrm, const uint3
     kp.r_s = v.r_s;
     kp.pad = v.pad;
     uint32_t *cnt = nullptr, *tot = nullptr;
+    if ((rc = T.alloc(&cnt, (size_t)n)) || (rc = T.alloc(&tot, 1))) return rc;
+    hipLaunchKernelGGL(k_key_count, dim3(blocks_for(n)), dim3(BUILD_BLOCK), 0, s, kp, xyz, unit_nrm, n, cnt);
+    // a disk meets at most (ceil(2 (r_s + pad) / leaf) + 1)^3 leaves: when n times
+    // that could reach 2^32, the counts are also summed in 64 bits
+    const double span = std::ceil(2.0 * ((double)v.r_s + (double)v.pad) / (double)v.h) + 1.0;
+    const bool may_wrap = (double)n * span * span * span >= 4294967280.0;
     unsigned long long* tot64 = nullptr;
-    if ((rc = T.alloc(&cnt, (size_t)n)) || (rc = T.alloc(&tot, 1)) || (rc = T.alloc(&tot64, 1))) return rc;
-    if ((rc = fill_u64((uint64_t*)tot64, 0ull, 1, s))) return rc;
-    hipLaunchKernelGGL(k_key_count, dim3(blocks_for(n)), dim3(BUILD_BLOCK), 0, s, kp, xyz, unit_nrm, n, cnt, tot64);
+    if (may_wrap) {
+        if ((rc = T.alloc(&tot64, 1)) || (rc = fill_u64((uint64_t*)tot64, 0ull, 1, s))) return rc;
+        hipLaunchKernelGGL(k_count_total, dim3(std::min<unsigned>(blocks_for(n), 4096u)), dim3(BUILD_BLOCK), 0, s, cnt,
+                           n, tot64);
+    }
     if ((rc = scan_u32(cnt, cnt, n, tot, s))) return rc;
     unsigned long long host_tot = 0;
-    if (hipMemcpyAsync(&host_tot, tot64, 8, hipMemcpyDeviceToHost, s) != hipSuccess ||
-        hipStreamSynchronize(s) != hipSuccess) {
+    uint32_t host_tot32 = 0;
+    const bool copied = may_wrap ? hipMemcpyAsync(&host_tot, tot64, 8, hipMemcpyDeviceToHost, s) == hipSuccess
+                                 : hipMemcpyAsync(&host_tot32, tot, 4, hipMemcpyDeviceToHost, s) == hipSuccess;
+    if (!copied || hipStreamSynchronize(s) != hipSuccess) {
         set_error("build_voxels: key count failed: %s", hipGetErrorString(hipGetLastError()));
         return PCRL_EHIP;
     }
+    if (!may_wrap) host_tot = host_tot32;
     // entries are indexed with 32 bits throughout (ranges, sort values, surfel ids)
     if (host_tot > 0xFFFFFFF0ull) {
         set_error("build_voxels: %llu (leaf, point) entries exceed the 32-bit entry index; use a larger leaf size "
