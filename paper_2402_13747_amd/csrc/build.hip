@@ -669,9 +669,9 @@ static int build_hierarchy(const float* xyz, const float4* unit_nrm, const uint3
     if ((rc = scan_u32(cnt, cnt, n, tot, s))) return rc;
     unsigned long long host_tot = 0;
     uint32_t host_tot32 = 0;
-    const bool copied = may_wrap ? hipMemcpyAsync(&host_tot, tot64, 8, hipMemcpyDeviceToHost, s) == hipSuccess
-                                 : hipMemcpyAsync(&host_tot32, tot, 4, hipMemcpyDeviceToHost, s) == hipSuccess;
-    if (!copied || hipStreamSynchronize(s) != hipSuccess) {
+    const bool copied = may_wrap ? read_back(&host_tot, tot64, 8, s) == PCRL_OK
+                                 : read_back(&host_tot32, tot, 4, s) == PCRL_OK;
+    if (!copied) {
         set_error("build_voxels: key count failed: %s", hipGetErrorString(hipGetLastError()));
         return PCRL_EHIP;
     }
@@ -714,8 +714,7 @@ static int build_hierarchy(const float* xyz, const float4* unit_nrm, const uint3
     for (int l = 0; l < L; ++l)
         if ((rc = scan_u32(scans + (size_t)l * m, scans + (size_t)l * m, m, ltot + l, s))) return rc;
     uint32_t host_nodes[PCRL_MAX_LEVELS] = {0, 0, 0, 0};
-    if (hipMemcpyAsync(host_nodes, ltot, 4 * L, hipMemcpyDeviceToHost, s) != hipSuccess ||
-        hipStreamSynchronize(s) != hipSuccess) {
+    if (read_back(host_nodes, ltot, 4 * L, s) != PCRL_OK) {
         set_error("build_voxels: level scan failed: %s", hipGetErrorString(hipGetLastError()));
         return PCRL_EHIP;
     }
@@ -834,8 +833,7 @@ static int ingest(const float* xyz, const float* nrm, const uint32_t* label, int
     if ((rc = T.alloc(&partial, nb)) || (rc = T.alloc(&res, 1))) return rc;
     hipLaunchKernelGGL(k_ingest, dim3(nb), dim3(BUILD_BLOCK), 0, s, xyz, nrm, label, n, *unit_nrm, partial);
     hipLaunchKernelGGL(k_ingest_final, dim3(1), dim3(BUILD_BLOCK), 0, s, partial, (int)nb, res);
-    if (hipGetLastError() != hipSuccess || hipMemcpyAsync(&io, res, sizeof io, hipMemcpyDeviceToHost, s) != hipSuccess ||
-        hipStreamSynchronize(s) != hipSuccess) {
+    if (hipGetLastError() != hipSuccess || read_back(&io, res, sizeof io, s) != PCRL_OK) {
         set_error("%s: ingest failed: %s", fn, hipGetErrorString(hipGetLastError()));
         return PCRL_EHIP;
     }

@@ -389,8 +389,10 @@ static int collect_impl(PcrlLaunch* L, int32_t kappa, int32_t key_mode, PcrlPath
     const int K = L->K;
     uint32_t n_rec = 0;
     if (L->stream != s) PCRL_TRY_HIP(hipStreamSynchronize(L->stream));
-    PCRL_TRY_HIP(hipMemcpyAsync(&n_rec, L->counters + PCRL_CNT_REC(K), 4, hipMemcpyDeviceToHost, s));
-    PCRL_TRY_HIP(hipStreamSynchronize(s));
+    if (read_back(&n_rec, L->counters + PCRL_CNT_REC(K), 4, s) != PCRL_OK) {
+        set_error("collect_paths: reading the record count failed: %s", hipGetErrorString(hipGetLastError()));
+        return PCRL_EHIP;
+    }
     out->n_rows = 0;
     out->n_keys = 0;
     if ((int64_t)n_rec > L->rec_cap) {
@@ -445,8 +447,7 @@ static int collect_impl(PcrlLaunch* L, int32_t kappa, int32_t key_mode, PcrlPath
         hipLaunchKernelGGL(k_collect_small, dim3(1), dim3(SMALL_BLOCK), 0, s, L->rec, n, L->hist, ks, kappa,
                            out->capacity, oa, tots);
         uint32_t host[2] = {0, 0};
-        if (hipGetLastError() != hipSuccess || hipMemcpyAsync(host, tots, 8, hipMemcpyDeviceToHost, s) != hipSuccess ||
-            hipStreamSynchronize(s) != hipSuccess) {
+        if (hipGetLastError() != hipSuccess || read_back(host, tots, 8, s) != PCRL_OK) {
             set_error("collect_paths: kernel failed: %s", hipGetErrorString(hipGetLastError()));
             return fail(PCRL_EHIP);
         }
@@ -486,7 +487,7 @@ static int collect_impl(PcrlLaunch* L, int32_t kappa, int32_t key_mode, PcrlPath
     hipLaunchKernelGGL(k_keep_flags, dim3(nblk(n)), dim3(256), 0, s, words, ks.W, perm, n, kscan, start, kappa, keep);
     if ((rc = scan_u32(keep, keep, n, tots + 1, s))) return fail(rc);
     uint32_t host[2] = {0, 0};
-    if (hipMemcpyAsync(host, tots, 8, hipMemcpyDeviceToHost, s) != hipSuccess || hipStreamSynchronize(s) != hipSuccess) {
+    if (read_back(host, tots, 8, s) != PCRL_OK) {
         set_error("collect_paths: kernels failed: %s", hipGetErrorString(hipGetLastError()));
         return fail(PCRL_EHIP);
     }

@@ -92,6 +92,10 @@ int bucket_order_u16(const uint16_t* keys, int64_t n_max, const uint32_t* n_dev,
 int bucket_place_u16(const uint16_t* keys, const uint32_t* pos, int64_t n_max, const uint32_t* n_dev,
                      const uint32_t* cnt, uint32_t* order, hipStream_t s);
 
+// Copy `bytes` from device memory to host memory and wait for the stream
+// (used for the few sizes the host needs before it can continue).
+int read_back(void* host, const void* dev, size_t bytes, hipStream_t s);
+
 // Fill helpers.
 int fill_u32(uint32_t* p, uint32_t v, int64_t n, hipStream_t s);
 int fill_u64(uint64_t* p, uint64_t v, int64_t n, hipStream_t s);

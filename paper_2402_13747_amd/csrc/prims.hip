@@ -13,6 +13,7 @@
 
 #include <algorithm>
 #include <cstdio>
+#include <cstring>
 #include <map>
 #include <mutex>
 #include <unordered_map>
@@ -633,6 +634,41 @@ int radix_sort_u32(uint32_t* keys, uint32_t* vals, int64_t n, int bits, hipStrea
 extern "C" const char* last_error(void) { return pcrl::get_error(); }
 
 extern "C" const char* pcrl_version(void) { return "pcrl 0.1.0 (gfx950)"; }
+
+namespace pcrl {
+
+// Small device-to-host reads (sizes the host needs before it can go on)
+// through a per-thread pinned buffer: the copy goes straight to host memory
+// without a pageable staging step.
+int read_back(void* host, const void* dev, size_t bytes, hipStream_t s) {
+    static thread_local void* pinned = nullptr;
+    static thread_local size_t cap = 0;
+    if (bytes > cap) {
+        if (pinned) (void)hipHostFree(pinned);
+        pinned = nullptr;
+        cap = 0;
+        const size_t want = std::max<size_t>(bytes, 4096);
+        if (hipHostMalloc(&pinned, want, hipHostMallocDefault) != hipSuccess) {
+            (void)hipGetLastError();
+            pinned = nullptr;
+        } else {
+            cap = want;
+        }
+    }
+    if (!pinned) {  // no pinned memory: plain pageable copy
+        if (hipMemcpyAsync(host, dev, bytes, hipMemcpyDeviceToHost, s) != hipSuccess ||
+            hipStreamSynchronize(s) != hipSuccess)
+            return PCRL_EHIP;
+        return PCRL_OK;
+    }
+    if (hipMemcpyAsync(pinned, dev, bytes, hipMemcpyDeviceToHost, s) != hipSuccess ||
+        hipStreamSynchronize(s) != hipSuccess)
+        return PCRL_EHIP;
+    std::memcpy(host, pinned, bytes);
+    return PCRL_OK;
+}
+
+}  // namespace pcrl
 
 extern "C" int set_allocator(const PcrlAllocator* a) {
     pcrl::clear_error();
