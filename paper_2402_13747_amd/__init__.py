@@ -12,6 +12,7 @@ in HIP kernels; this module only marshals arguments.
 """
 from __future__ import annotations
 
+import contextlib
 import ctypes as C
 import math
 
@@ -89,6 +90,16 @@ def _ptr(t):
 
 def _stream(device):
     return C.c_void_p(torch.cuda.current_stream(device).cuda_stream)
+
+
+_NO_SWITCH = contextlib.nullcontext()
+
+
+def _on(device):
+    """Make `device` current for a library call (no switch when it already is)."""
+    if device.index is None or device.index == torch.cuda.current_device():
+        return _NO_SWITCH
+    return torch.cuda.device(device)
 
 
 class Scene:
@@ -179,7 +190,7 @@ def build_voxels(xyz, normal, label, levels, surfel_radius, t_eps=0.0, device=No
     p.t_eps = float(t_eps)
     p.flags = _lib.VOXEL_COMPACT if compact else 0
     h = C.c_void_p()
-    with torch.cuda.device(device):
+    with _on(device):
         check("build_voxels", lib.build_voxels(_ptr(xyz) if n else None, _ptr(normal) if n else None,
                                                _ptr(label) if n else None, n, C.byref(p), _stream(device),
                                                C.byref(h)))
@@ -254,7 +265,7 @@ def launch_rays(scene: Scene, tx, rx, n_rays, max_reflections, directions=None, 
                stats, timing, coherent, hit_log)
     h = C.c_void_p()
     device = scene.device
-    with torch.cuda.device(device):
+    with _on(device):
         check("launch_rays", lib.launch_rays(scene.handle, _ptr(q["tx"]), q["tx"].shape[0],
                                              _ptr(q["rx"]) if q["rx"].shape[0] else None, q["rx"].shape[0],
                                              C.byref(q["params"]), _stream(device), C.byref(h)))
@@ -321,7 +332,7 @@ def launch_batch(queries, tile_rays=0, compact_threshold=-1.0, waves_per_cu=0, u
         arr[i].params = q["params"]
     bp = _batch_params(tile_rays, compact_threshold, waves_per_cu, use_graph, autotune)
     out = (C.c_void_p * len(qs))()
-    with torch.cuda.device(device):
+    with _on(device):
         check("launch_batch", lib.launch_batch(arr, len(qs), C.byref(bp), _stream(device), out))
     return [_make_launch(C.c_void_p(out[i]), q) for i, q in enumerate(qs)]
 
@@ -350,7 +361,7 @@ def batch_autotune(queries, use_graph=False) -> dict:
         arr[i].n_rx = q["rx"].shape[0]
         arr[i].params = q["params"]
     bp = _batch_params(use_graph=use_graph)
-    with torch.cuda.device(device):
+    with _on(device):
         check("batch_autotune", lib.batch_autotune(arr, len(qs), _stream(device), C.byref(bp)))
     return {"tile_rays": bp.tile_rays, "compact_threshold": bp.compact_threshold, "waves_per_cu": bp.waves_per_cu}
 
@@ -359,7 +370,7 @@ def launch_directions(n_rays, device=None):
     """[n_rays, 3] float32 Fibonacci-lattice directions computed by the library."""
     device = _dev(device)
     out = torch.empty((int(n_rays), 3), dtype=torch.float32, device=device)
-    with torch.cuda.device(device):
+    with _on(device):
         check("launch_directions", lib.launch_directions(int(n_rays), _ptr(out), _stream(device)))
     return out
 
@@ -390,7 +401,7 @@ def collect_paths(launch: Launch, kappa=1, key_mode=KEY_LABELS, capacity=None) -
         out.capacity = cap
         for k, t in bufs.items():
             setattr(out, k, t.data_ptr() if not (K == 0 and k in ("key", "points")) else None)
-        with torch.cuda.device(device):
+        with _on(device):
             st = lib.collect_paths(launch.handle, int(kappa), int(key_mode), C.byref(out), _stream(device))
         if st == PCRL_EOVERFLOW and out.n_rows == -1:
             need = launch.stats()["records"]
@@ -450,7 +461,7 @@ def refine_paths(scene: Scene, tx, rx, paths: dict, max_iters=2000, grad_tol=1e-
     smooth = _lib.REFINE_SMOOTH if smooth_radius > 0 else 0
     prm = _lib.PcrlRefineParams(int(max_iters), float(grad_tol), float(step), float(carrier_hz), smooth,
                                 float(smooth_radius))
-    with torch.cuda.device(device):
+    with _on(device):
         check("refine_paths", lib.refine_paths(scene.handle, _ptr(txt), txt.shape[0], _ptr(rxt), rxt.shape[0],
                                                C.byref(pp), K, C.byref(prm), C.byref(out), _stream(device)))
     res["n_kept"] = int(out.n_kept)
