@@ -151,6 +151,7 @@ struct KeyParams {
     SceneView v;
     float r_s;
     float pad;
+    int32_t id_bits;   // packed 64-bit items: bits of the point index below the key
 };
 
 __device__ __forceinline__ void disk_leaf_box(const KeyParams& kp, const float* xyz, const float4* un, int64_t i,
@@ -206,8 +207,13 @@ __device__ __forceinline__ uint32_t disk_leaves(const KeyParams& kp, const float
                 const bool one = lo[0] == hi[0] && lo[1] == hi[1] && lo[2] == hi[2];
                 if (!one && !disk_meets_leaf(kp, p, nv, x, y, z)) continue;
                 if (EMIT) {
-                    keys[o + k] = (K)leaf_key_of(kp.v, x, y, z);
-                    ids[o + k] = (uint32_t)i;
+                    if (ids) {
+                        keys[o + k] = (K)leaf_key_of(kp.v, x, y, z);
+                        ids[o + k] = (uint32_t)i;
+                    } else {
+                        // packed: the key above the point index (one 8-byte item to sort)
+                        keys[o + k] = (K)((leaf_key_of(kp.v, x, y, z) << kp.id_bits) | (uint64_t)i);
+                    }
                 }
                 ++k;
             }
@@ -274,7 +280,7 @@ struct HierOut {
 // of entry e at level l is scans[l][e] + flag - 1.
 template <typename K>
 __global__ void k_hier_link(const K* keys, int64_t m, LevelShifts ls, SceneView v, const uint32_t* scans,
-                            HierOut h) {
+                            HierOut h, int id_bits) {
     int64_t e = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
     if (e >= m) return;
     const uint64_t k = keys[e];
@@ -287,7 +293,7 @@ __global__ void k_hier_link(const K* keys, int64_t m, LevelShifts ls, SceneView 
         if (l == 0) h.map0[k >> ls.sh[0]] = (int32_t)node;
         if (l == L - 1) {
             h.leaf[node].x = (uint32_t)e;
-            h.leaf_key[node] = k;
+            h.leaf_key[node] = k >> id_bits;
         }
         if (l > 0) {
             const uint32_t parent = scans[(size_t)(l - 1) * m + e] +
@@ -505,11 +511,20 @@ __global__ void k_split_leaf(const uint2* r, int64_t n, uint32_t* b, uint32_t* c
     if (c) c[i] = x.y;
 }
 
-__global__ void k_gather_surfels(const uint32_t* ids, int64_t m, const float* xyz, const float4* un,
-                                 const uint32_t* label, const uint32_t* gid, float4* spos, float4* snrm) {
+// With packed items (`packed` non-null) the point index is taken from their
+// low id_bits and also written to ids (the scene's entry -> point table).
+__global__ void k_gather_surfels(uint32_t* ids, const uint64_t* packed, int id_bits, int64_t m, const float* xyz,
+                                 const float4* un, const uint32_t* label, const uint32_t* gid, float4* spos,
+                                 float4* snrm) {
     int64_t e = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
     if (e >= m) return;
-    const uint32_t i = ids[e];
+    uint32_t i;
+    if (packed) {
+        i = (uint32_t)(packed[e] & ((uint64_t(1) << id_bits) - 1));
+        ids[e] = i;
+    } else {
+        i = ids[e];
+    }
     const uint32_t g = gid ? gid[i] : i;
     spos[e] = make_float4(xyz[3 * (size_t)i], xyz[3 * (size_t)i + 1], xyz[3 * (size_t)i + 2], __uint_as_float(g));
     const float4 nn = un[i];
@@ -649,7 +664,7 @@ static int build_hierarchy(const float* xyz, const float4* unit_nrm, const uint3
     if (n == 0) return PCRL_OK;
 
     // dilated key counts and their total
-    KeyParams kp;
+    KeyParams kp{};
     kp.v = v;
     kp.r_s = v.r_s;
     kp.pad = v.pad;
@@ -685,8 +700,14 @@ static int build_hierarchy(const float* xyz, const float4* unit_nrm, const uint3
     const int64_t m = (int64_t)host_tot;
     hb.n_entries = m;
 
-    // emit and sort (key, local point index); 32-bit keys when they fit
+    // emit and sort (key, local point index); 32-bit keys when they fit; wider
+    // keys with the point index packed below them in one 64-bit item when both
+    // fit (the stable sort on the key bits then moves 8 bytes per entry, not 12)
     const bool narrow = v.key_bits <= 32;
+    int id_bits = 1;
+    while (id_bits < 32 && ((uint64_t)(n > 0 ? n - 1 : 0) >> id_bits)) ++id_bits;
+    const bool packed = !narrow && v.key_bits + id_bits <= 64;
+    kp.id_bits = packed ? id_bits : 0;
     uint64_t* keys = nullptr;
     uint32_t* keys32 = nullptr;
     uint32_t* ids = nullptr;
@@ -696,6 +717,12 @@ static int build_hierarchy(const float* xyz, const float4* unit_nrm, const uint3
         hipLaunchKernelGGL(k_key_emit<uint32_t>, dim3(blocks_for(n)), dim3(BUILD_BLOCK), 0, s, kp, xyz, unit_nrm, n,
                            cnt, keys32, ids);
         if ((rc = radix_sort_u32(keys32, ids, m, v.key_bits, s))) return rc;
+    } else if (packed) {
+        if ((rc = T.alloc(&keys, (size_t)m))) return rc;
+        hipLaunchKernelGGL(k_key_emit<uint64_t>, dim3(blocks_for(n)), dim3(BUILD_BLOCK), 0, s, kp, xyz, unit_nrm, n,
+                           cnt, keys, (uint32_t*)nullptr);
+        if ((rc = radix_sort_u64_bits(keys, nullptr, m, id_bits, v.key_bits, s))) return rc;
+        for (int l = 0; l < L; ++l) ls.sh[l] += id_bits;
     } else {
         if ((rc = T.alloc(&keys, (size_t)m))) return rc;
         hipLaunchKernelGGL(k_key_emit<uint64_t>, dim3(blocks_for(n)), dim3(BUILD_BLOCK), 0, s, kp, xyz, unit_nrm, n,
@@ -746,10 +773,10 @@ static int build_hierarchy(const float* xyz, const float4* unit_nrm, const uint3
     ho.leaf_key = lkey;
     if (narrow)
         hipLaunchKernelGGL(k_hier_link<uint32_t>, dim3(blocks_for(m)), dim3(BUILD_BLOCK), 0, s, keys32, m, ls, v, scans,
-                           ho);
+                           ho, 0);
     else
         hipLaunchKernelGGL(k_hier_link<uint64_t>, dim3(blocks_for(m)), dim3(BUILD_BLOCK), 0, s, keys, m, ls, v, scans,
-                           ho);
+                           ho, packed ? id_bits : 0);
     for (int l = 0; l + 1 < L; ++l)
         hipLaunchKernelGGL(k_brick_base, dim3(blocks_for(host_nodes[l])), dim3(BUILD_BLOCK), 0, s, ho.mask[l],
                            ho.first_child[l], (int64_t)host_nodes[l], v.nw[l], (uint32_t*)v.base[l]);
@@ -804,8 +831,9 @@ static int build_hierarchy(const float* xyz, const float4* unit_nrm, const uint3
     // surfel streams in leaf order
     float4 *spos = nullptr, *snrm = nullptr;
     if ((rc = B.alloc(&spos, (size_t)m)) || (rc = B.alloc(&snrm, (size_t)m))) return rc;
-    hipLaunchKernelGGL(k_gather_surfels, dim3(blocks_for(m)), dim3(BUILD_BLOCK), 0, s, ids, m, xyz, unit_nrm, label,
-                       gid, spos, snrm);
+    hipLaunchKernelGGL(k_gather_surfels, dim3(blocks_for(m)), dim3(BUILD_BLOCK), 0, s, ids,
+                       packed ? (const uint64_t*)keys : (const uint64_t*)nullptr, packed ? id_bits : 0, m, xyz,
+                       unit_nrm, label, gid, spos, snrm);
     v.spos = spos;
     v.snrm = snrm;
     if (hipGetLastError() != hipSuccess) {

@@ -81,6 +81,8 @@ int scan_u32(const uint32_t* in, uint32_t* out, int64_t n, uint32_t* total, hipS
 // vals may be null (keys only).
 int radix_sort_u64(uint64_t* keys, uint32_t* vals, int64_t n, int bits, hipStream_t s);
 int radix_sort_u32(uint32_t* keys, uint32_t* vals, int64_t n, int bits, hipStream_t s);
+// The same on key bits [lo_bit, lo_bit + bits) only (lower bits ride along).
+int radix_sort_u64_bits(uint64_t* keys, uint32_t* vals, int64_t n, int lo_bit, int bits, hipStream_t s);
 
 // order[0 .. n) = the indices j < n of `keys` grouped by key (ascending
 // buckets, any order inside a bucket: one counting pass with atomics), where

@@ -478,7 +478,7 @@ static int radix_pass(const K* ka, const uint32_t* va, K* kb, uint32_t* vb, int6
 }
 
 template <typename K>
-static int radix_sort_impl(K* keys, uint32_t* vals, int64_t n, int bits, hipStream_t s) {
+static int radix_sort_impl(K* keys, uint32_t* vals, int64_t n, int bits, hipStream_t s, int lo_bit = 0) {
     if (n <= 1 || bits <= 0) return PCRL_OK;
     if (n > (int64_t)0xFFFFFFF0ll) {
         set_error("radix sort of %lld items exceeds the 32-bit index range", (long long)n);
@@ -499,7 +499,7 @@ static int radix_sort_impl(K* keys, uint32_t* vals, int64_t n, int bits, hipStre
     uint32_t* va = vals;
     uint32_t* vb = v2;
     for (int p = 0; p < passes && rc == PCRL_OK; ++p) {
-        const int shift = p * db;
+        const int shift = lo_bit + p * db;
         switch (db) {
         case 4: rc = radix_pass<K, 4>(ka, va, kb, vb, n, shift, hist, n_tiles, s); break;
         case 5: rc = radix_pass<K, 5>(ka, va, kb, vb, n, shift, hist, n_tiles, s); break;
@@ -623,6 +623,14 @@ int bucket_order_u16(const uint16_t* keys, int64_t n_max, const uint32_t* n_dev,
 
 int radix_sort_u64(uint64_t* keys, uint32_t* vals, int64_t n, int bits, hipStream_t s) {
     return radix_sort_impl<uint64_t>(keys, vals, n, bits > 64 ? 64 : bits, s);
+}
+
+int radix_sort_u64_bits(uint64_t* keys, uint32_t* vals, int64_t n, int lo_bit, int bits, hipStream_t s) {
+    if (lo_bit < 0 || bits < 0 || lo_bit + bits > 64) {
+        set_error("radix sort of bits [%d, %d) of 64-bit keys", lo_bit, lo_bit + bits);
+        return PCRL_EINVAL;
+    }
+    return radix_sort_impl<uint64_t>(keys, vals, n, bits, s, lo_bit);
 }
 
 int radix_sort_u32(uint32_t* keys, uint32_t* vals, int64_t n, int bits, hipStream_t s) {
