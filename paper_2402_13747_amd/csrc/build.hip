@@ -257,14 +257,15 @@ struct LevelShifts {
 };
 
 // flag[l][e] = entry e starts a new node of level l
+// Levels of `flags` are `stride` apart (m rounded up to 4: 16-byte aligned rows).
 template <typename K>
-__global__ void k_level_flags(const K* keys, int64_t m, LevelShifts ls, uint32_t* flags) {
+__global__ void k_level_flags(const K* keys, int64_t m, int64_t stride, LevelShifts ls, uint32_t* flags) {
     int64_t e = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
     if (e >= m) return;
     const uint64_t k = keys[e];
     const uint64_t kp = e > 0 ? keys[e - 1] : 0;
     for (int l = 0; l < ls.nlev; ++l)
-        flags[(size_t)l * m + e] = (e == 0 || (k >> ls.sh[l]) != (kp >> ls.sh[l])) ? 1u : 0u;
+        flags[(size_t)l * stride + e] = (e == 0 || (k >> ls.sh[l]) != (kp >> ls.sh[l])) ? 1u : 0u;
 }
 
 struct HierOut {
@@ -279,8 +280,8 @@ struct HierOut {
 // scans[l][e] is the exclusive scan of the level-l flags, so the node index
 // of entry e at level l is scans[l][e] + flag - 1.
 template <typename K>
-__global__ void k_hier_link(const K* keys, int64_t m, LevelShifts ls, SceneView v, const uint32_t* scans,
-                            HierOut h, int id_bits) {
+__global__ void k_hier_link(const K* keys, int64_t m, int64_t stride, LevelShifts ls, SceneView v,
+                            const uint32_t* scans, HierOut h, int id_bits) {
     int64_t e = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
     if (e >= m) return;
     const uint64_t k = keys[e];
@@ -289,14 +290,14 @@ __global__ void k_hier_link(const K* keys, int64_t m, LevelShifts ls, SceneView 
     for (int l = 0; l < L; ++l) {
         const bool f = (e == 0 || (k >> ls.sh[l]) != (kp >> ls.sh[l]));
         if (!f) continue;
-        const uint32_t node = scans[(size_t)l * m + e];  // exclusive scan at a flagged entry = node index
+        const uint32_t node = scans[(size_t)l * stride + e];  // exclusive scan at a flagged entry = node index
         if (l == 0) h.map0[k >> ls.sh[0]] = (int32_t)node;
         if (l == L - 1) {
             h.leaf[node].x = (uint32_t)e;
             h.leaf_key[node] = k >> id_bits;
         }
         if (l > 0) {
-            const uint32_t parent = scans[(size_t)(l - 1) * m + e] +
+            const uint32_t parent = scans[(size_t)(l - 1) * stride + e] +
                                     (((k >> ls.sh[l - 1]) != (kp >> ls.sh[l - 1]) || e == 0) ? 1u : 0u) - 1u;
             const uint32_t local = (uint32_t)((k >> ls.sh[l]) & ((uint64_t(1) << v.lbits[l]) - 1));
             atomicOr((unsigned long long*)&h.mask[l - 1][(size_t)parent * v.nw[l - 1] + (local >> 6)],
@@ -733,13 +734,16 @@ static int build_hierarchy(const float* xyz, const float4* unit_nrm, const uint3
 
     // per-level node boundaries
     uint32_t *scans = nullptr, *ltot = nullptr;
-    if ((rc = T.alloc(&scans, (size_t)L * m)) || (rc = T.alloc(&ltot, PCRL_MAX_LEVELS))) return rc;
+    const int64_t stride = (m + 3) & ~(int64_t)3;  // 16-byte aligned levels: vector loads in the scans
+    if ((rc = T.alloc(&scans, (size_t)L * stride)) || (rc = T.alloc(&ltot, PCRL_MAX_LEVELS))) return rc;
     if (narrow)
-        hipLaunchKernelGGL(k_level_flags<uint32_t>, dim3(blocks_for(m)), dim3(BUILD_BLOCK), 0, s, keys32, m, ls, scans);
+        hipLaunchKernelGGL(k_level_flags<uint32_t>, dim3(blocks_for(m)), dim3(BUILD_BLOCK), 0, s, keys32, m, stride, ls,
+                           scans);
     else
-        hipLaunchKernelGGL(k_level_flags<uint64_t>, dim3(blocks_for(m)), dim3(BUILD_BLOCK), 0, s, keys, m, ls, scans);
+        hipLaunchKernelGGL(k_level_flags<uint64_t>, dim3(blocks_for(m)), dim3(BUILD_BLOCK), 0, s, keys, m, stride, ls,
+                           scans);
     for (int l = 0; l < L; ++l)
-        if ((rc = scan_u32(scans + (size_t)l * m, scans + (size_t)l * m, m, ltot + l, s))) return rc;
+        if ((rc = scan_u32(scans + (size_t)l * stride, scans + (size_t)l * stride, m, ltot + l, s))) return rc;
     uint32_t host_nodes[PCRL_MAX_LEVELS] = {0, 0, 0, 0};
     if (read_back(host_nodes, ltot, 4 * L, s) != PCRL_OK) {
         set_error("build_voxels: level scan failed: %s", hipGetErrorString(hipGetLastError()));
@@ -772,11 +776,11 @@ static int build_hierarchy(const float* xyz, const float4* unit_nrm, const uint3
     ho.leaf = leaf;
     ho.leaf_key = lkey;
     if (narrow)
-        hipLaunchKernelGGL(k_hier_link<uint32_t>, dim3(blocks_for(m)), dim3(BUILD_BLOCK), 0, s, keys32, m, ls, v, scans,
-                           ho, 0);
+        hipLaunchKernelGGL(k_hier_link<uint32_t>, dim3(blocks_for(m)), dim3(BUILD_BLOCK), 0, s, keys32, m, stride, ls, v,
+                           scans, ho, 0);
     else
-        hipLaunchKernelGGL(k_hier_link<uint64_t>, dim3(blocks_for(m)), dim3(BUILD_BLOCK), 0, s, keys, m, ls, v, scans,
-                           ho, packed ? id_bits : 0);
+        hipLaunchKernelGGL(k_hier_link<uint64_t>, dim3(blocks_for(m)), dim3(BUILD_BLOCK), 0, s, keys, m, stride, ls, v,
+                           scans, ho, packed ? id_bits : 0);
     for (int l = 0; l + 1 < L; ++l)
         hipLaunchKernelGGL(k_brick_base, dim3(blocks_for(host_nodes[l])), dim3(BUILD_BLOCK), 0, s, ho.mask[l],
                            ho.first_child[l], (int64_t)host_nodes[l], v.nw[l], (uint32_t*)v.base[l]);
