@@ -327,14 +327,20 @@ __global__ void k_brick_base(const uint64_t* mask, const uint32_t* first_child, 
 // (the longest per-axis distance to the closest voxel with content), limited
 // to the brick.  The L-infinity distance transform is separable: 1D distances
 // along x, then min over y' of max(|y - y'|, .), then the same along z.
-__global__ __launch_bounds__(BUILD_BLOCK) void k_brick_dist(const uint64_t* mask, int nw, int r, uint8_t* dist) {
+// RC > 0: the ratio is the compile-time constant RC (index arithmetic by
+// constants); RC = 0: the runtime r.
+template <int RC>
+__global__ __launch_bounds__(BUILD_BLOCK) void k_brick_dist(const uint64_t* mask, int nw, int r_rt, uint8_t* dist) {
     extern __shared__ uint8_t sm[];
+    __shared__ uint64_t wm[64];  // the brick's occupancy words (nw <= 64 for r <= 16)
+    const int r = RC > 0 ? RC : r_rt;
     const int n3 = r * r * r;
     uint8_t* A = sm;
     uint8_t* B = sm + n3;
     const size_t P = blockIdx.x;
-    for (int c = threadIdx.x; c < n3; c += BUILD_BLOCK)
-        A[c] = ((mask[P * nw + (c >> 6)] >> (c & 63)) & 1ull) ? 0 : 255;
+    for (int k = threadIdx.x; k < nw; k += BUILD_BLOCK) wm[k] = mask[P * nw + k];
+    __syncthreads();
+    for (int c = threadIdx.x; c < n3; c += BUILD_BLOCK) A[c] = ((wm[c >> 6] >> (c & 63)) & 1ull) ? 0 : 255;
     __syncthreads();
     for (int c = threadIdx.x; c < n3; c += BUILD_BLOCK) {
         const int x = c % r, row = c - x;
@@ -810,8 +816,13 @@ static int build_hierarchy(const float* xyz, const float4* unit_nrm, const uint3
         } else if (r >= 3 && r <= 16) {
             uint8_t* ld = nullptr;
             if ((rc = B.alloc(&ld, (size_t)n_cells))) return rc;
-            hipLaunchKernelGGL(k_brick_dist, dim3(host_nodes[L - 2]), dim3(BUILD_BLOCK), 2 * r3, s, ho.mask[L - 2],
-                               v.nw[L - 2], r, ld);
+            const dim3 g((unsigned)host_nodes[L - 2]);
+            if (r == 10)
+                hipLaunchKernelGGL(k_brick_dist<10>, g, dim3(BUILD_BLOCK), 2 * r3, s, ho.mask[L - 2], v.nw[L - 2], r, ld);
+            else if (r == 8)
+                hipLaunchKernelGGL(k_brick_dist<8>, g, dim3(BUILD_BLOCK), 2 * r3, s, ho.mask[L - 2], v.nw[L - 2], r, ld);
+            else
+                hipLaunchKernelGGL(k_brick_dist<0>, g, dim3(BUILD_BLOCK), 2 * r3, s, ho.mask[L - 2], v.nw[L - 2], r, ld);
             v.ldist = ld;
             hb.bytes += n_cells;
         }
