@@ -19,6 +19,9 @@ definition of what the HIP path computes and shares no code with it.
                          force (``oracle.c``)
 * ``refine_dedup(...)``  refined-path dedup: shortest per label sequence,
                          then first-Fresnel-zone uniqueness (Section 2.3)
+* ``sdf_intersect(...)`` ray intersection with the implicit surface of Eq. 1
+                         by marching line segments through occupied leaves
+                         (``sdf.c``)
 
 Parity unpinned: sigma (reception sphere scale), r_s (surfel radius) and
 t_eps (self-intersection distance) are conventions the paper does not fix;
@@ -38,15 +41,20 @@ from . import image_method  # noqa: F401  (closed forms)
 _HERE = os.path.dirname(os.path.abspath(__file__))
 _SO = os.path.join(_HERE, "liboracle.so")
 _SRC = os.path.join(_HERE, "oracle.c")
+_SRCS = [_SRC, os.path.join(_HERE, "sdf.c")]
 MAXACC = 16
 
 
+def _stale() -> bool:
+    return not os.path.exists(_SO) or any(os.path.getmtime(_SO) < os.path.getmtime(f) for f in _SRCS)
+
+
 def build(force: bool = True) -> str:
-    """Compile oracle.c with gcc (plain FP64, no FMA contraction)."""
-    if force or not os.path.exists(_SO) or os.path.getmtime(_SO) < os.path.getmtime(_SRC):
+    """Compile oracle.c and sdf.c with gcc (plain FP64, no FMA contraction)."""
+    if force or _stale():
         tmp = _SO + ".tmp"
         subprocess.check_call(["gcc", "-O2", "-std=c11", "-D_GNU_SOURCE", "-ffp-contract=off",
-                               "-fno-fast-math", "-fPIC", "-shared", "-pthread", _SRC, "-o", tmp, "-lm"])
+                               "-fno-fast-math", "-fPIC", "-shared", "-pthread", *_SRCS, "-o", tmp, "-lm"])
         os.replace(tmp, _SO)
     return _SO
 
@@ -82,6 +90,24 @@ class OracleRefineArgs(C.Structure):
     ]
 
 
+class OracleSdfArgs(C.Structure):
+    _fields_ = [
+        ("xyz", C.c_void_p), ("nrm", C.c_void_p), ("n_pts", C.c_int64),
+        ("origin", C.c_float * 3), ("leaf", C.c_float),
+        ("o", C.c_void_p), ("d", C.c_void_p), ("trange", C.c_void_p), ("n_rays", C.c_int64),
+        ("h", C.c_double), ("eps", C.c_double), ("max_steps", C.c_int32), ("n_threads", C.c_int32),
+        ("diam_scale", C.c_double), ("cross_margin", C.c_double),
+        ("t", C.c_void_p), ("point", C.c_void_p), ("normal", C.c_void_p), ("leaf_cell", C.c_void_p),
+    ]
+
+
+# SDF intersection (Eq. 1) conventions the paper does not fix: neighbourhood
+# radius h and near-zero threshold eps as fractions of the finest edge, and
+# the evaluations a leaf's march may take
+SDF_H_SCALE = 0.95
+SDF_EPS_SCALE = 1e-3
+SDF_MAX_STEPS = 64
+
 # refinement outcome of a path
 REF_VALID, REF_NOT_CONVERGED, REF_MISS, REF_WRONG_SIDE, REF_OCCLUDED, REF_DEGENERATE = range(6)
 # Table 1: convergence threshold delta and refinement iterations rho; carrier 60 GHz
@@ -98,7 +124,7 @@ _lib = None
 def _load():
     global _lib
     if _lib is None:
-        if not os.path.exists(_SO) or os.path.getmtime(_SO) < os.path.getmtime(_SRC):
+        if _stale():
             build(force=True)
         lib = C.CDLL(_SO)
         lib.oracle_fibonacci.argtypes = [C.c_int64, C.c_void_p]
@@ -109,6 +135,8 @@ def _load():
         lib.oracle_launch.restype = C.c_int
         lib.oracle_refine.argtypes = [C.POINTER(OracleRefineArgs)]
         lib.oracle_refine.restype = C.c_int
+        lib.oracle_sdf_intersect.argtypes = [C.POINTER(OracleSdfArgs)]
+        lib.oracle_sdf_intersect.restype = C.c_int
         lib.oracle_grid_build.argtypes = [C.c_void_p, C.c_int64, C.c_double, C.c_double]
         lib.oracle_grid_build.restype = C.c_void_p
         lib.oracle_grid_free.argtypes = [C.c_void_p]
@@ -375,3 +403,44 @@ def refine_dedup(group, n_refl, labels, points, length, status, tx, carrier_hz=C
                 kept_rows.append(p)
                 kept[p] = True
     return kept
+
+
+def sdf_intersect(xyz, normal, origin, leaf, o, d, trange=None, h=None, eps=None, max_steps=SDF_MAX_STEPS,
+                  diam_scale=1.0, cross_margin=0.0, n_threads=None):
+    """First intersection of each ray with the implicit surface of Eq. 1
+    (``sdf.c``, FP64, brute force over leaves).
+
+    ``origin``/``leaf`` are the scene's FP32 grid origin and finest edge (the
+    leaves' point sets are taken in FP32 like the kernels').  ``h`` and
+    ``eps`` default to SDF_H_SCALE and SDF_EPS_SCALE times ``leaf``.
+    ``diam_scale`` and ``cross_margin`` perturb the segment length and the
+    leaf-crossing test (1 and 0 give the definition).  Returns a dict of
+    ``t`` (+inf for none), ``point``, ``normal`` and ``leaf_cell`` (-1 none).
+    """
+    xyz = np.ascontiguousarray(xyz, np.float32).reshape(-1, 3)
+    normal = np.ascontiguousarray(normal, np.float32).reshape(-1, 3)
+    o = np.ascontiguousarray(np.asarray(o, np.float32).reshape(-1, 3))
+    d = np.ascontiguousarray(np.asarray(d, np.float32).reshape(-1, 3))
+    if o.shape != d.shape:
+        raise ValueError("o and d must have the same shape")
+    n = o.shape[0]
+    tr = None if trange is None else np.ascontiguousarray(np.asarray(trange, np.float32).reshape(n, 2))
+    leaf = float(np.float32(leaf))
+    h = SDF_H_SCALE * leaf if h is None else float(h)
+    eps = SDF_EPS_SCALE * leaf if eps is None else float(eps)
+    out = dict(t=np.empty(n), point=np.empty((n, 3)), normal=np.empty((n, 3)),
+               leaf_cell=np.empty((n, 3), np.int32))
+    a = OracleSdfArgs()
+    a.xyz, a.nrm, a.n_pts = _p(xyz), _p(normal), xyz.shape[0]
+    a.origin[:] = [float(v) for v in np.asarray(origin, np.float32).reshape(3)]
+    a.leaf = leaf
+    a.o, a.d, a.trange, a.n_rays = _p(o), _p(d), (_p(tr) if tr is not None else None), n
+    a.h, a.eps, a.max_steps = h, eps, int(max_steps)
+    a.n_threads = default_threads() if n_threads is None else int(n_threads)
+    a.diam_scale, a.cross_margin = float(diam_scale), float(cross_margin)
+    a.t, a.point, a.normal, a.leaf_cell = (_p(out["t"]), _p(out["point"]), _p(out["normal"]),
+                                           _p(out["leaf_cell"]))
+    rc = _load().oracle_sdf_intersect(C.byref(a))
+    if rc != 0:
+        raise ValueError(f"oracle_sdf_intersect failed ({rc})")
+    return out
