@@ -388,6 +388,48 @@ int refine_paths(const PcrlScene* scene, const float* tx, int32_t n_tx, const fl
                  pcrl_stream_t stream);
 
 /* ------------------------------------------------------------------------ */
+/* intersection with the implicit surface of Eq. 1 (Section 2.2.1)           */
+/* ------------------------------------------------------------------------ */
+
+typedef struct {
+    float     h;          /* neighbourhood radius of the averages, 0 < h <= 0.98 leaf edges;
+                             <= 0 selects 0.95 leaf edges */
+    float     eps;        /* |f| at or below this is an intersection; <= 0 selects 1e-3 leaf edges */
+    int32_t   max_steps;  /* evaluations of f per leaf segment, <= 2^20; <= 0 selects 64 */
+    int32_t   flags;      /* 0 */
+    uint64_t* stats;      /* NULL, or device [2] to which the call adds the evaluations of f and the
+                             leaf entries read (the caller zeroes it) */
+} PcrlSdfParams;
+
+/* First intersection of each ray with the point cloud's implicit surface
+ * f(x) = (x - p(x)) . n(x) of Eq. 1 (Section 2.2.1): p and n are the averages
+ * of the positions and (normalised, consistently oriented) normals of the
+ * points within h of x, with weights (1 - |x - q|^2 / h^2)^4.  For every
+ * occupied leaf the ray crosses within [0, t_hi], a segment one leaf diagonal
+ * long is centred on the projection onto the ray of the centre of the box
+ * around the points whose centre lies in that leaf, and clipped to
+ * [t_lo, t_hi]; from its near end the position advances by |f| until
+ * |f| <= eps (intersection there), or f changes sign between two samples
+ * (intersection at the zero of their linear interpolation), or the segment
+ * ends, or max_steps evaluations were spent.  Where no point lies within h
+ * the position advances by h / 2 and no sign is compared across it.  The
+ * result is the nearest intersection over all such leaves.
+ *   o, d      device [n_rays,3] float32 origins and directions (any non-zero length)
+ *   t_range   device [n_rays,2] float32 (t_lo, t_hi) per ray, or NULL for (0, inf)
+ * Outputs (device, caller-owned):
+ *   t         [n_rays] distance along the normalised direction, +inf if none
+ *   point     [n_rays,3] o + t d (NaN if none)
+ *   normal    [n_rays,3] n at the intersection (0 if none)
+ *   leaf_cell [n_rays,3] int32 leaf cell whose segment held it (-1 if none), or NULL
+ * A ray with a zero or non-finite direction or origin, or t_lo > t_hi, has
+ * no intersection.  Asynchronous on `stream`.  PCRL_EINVAL on NULL arrays,
+ * out-of-range parameters, or a scene holding dynamic points (update_points):
+ * the surface is defined over the static points. */
+int sdf_intersect(const PcrlScene* scene, const float* o, const float* d, const float* t_range, int64_t n_rays,
+                  const PcrlSdfParams* params, float* t, float* point, float* normal, int32_t* leaf_cell,
+                  pcrl_stream_t stream);
+
+/* ------------------------------------------------------------------------ */
 /* serving: a request loop over one device-resident, incrementally           */
 /* re-voxelised scene                                                         */
 /* ------------------------------------------------------------------------ */

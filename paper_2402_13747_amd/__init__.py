@@ -25,7 +25,7 @@ from ._lib import (KEY_LABELS, KEY_LEAVES, LAUNCH_COHERENT, LAUNCH_STATS, LAUNCH
                    REFINE_WRONG_SIDE, PcrlError, check, lib)
 
 __all__ = ["build_voxels", "launch_rays", "launch_batch", "batch_autotune", "launch_directions", "collect_paths",
-           "refine_paths", "use_torch_allocator", "Scene", "Launch", "Server", "PcrlError", "KEY_LABELS",
+           "refine_paths", "sdf_intersect", "use_torch_allocator", "Scene", "Launch", "Server", "PcrlError", "KEY_LABELS",
            "KEY_LEAVES", "REFINE_VALID", "REFINE_NOT_CONVERGED", "REFINE_MISS", "REFINE_WRONG_SIDE",
            "REFINE_OCCLUDED", "REFINE_DEGENERATE", "version", "library_path"]
 
@@ -465,6 +465,47 @@ def refine_paths(scene: Scene, tx, rx, paths: dict, max_iters=2000, grad_tol=1e-
         check("refine_paths", lib.refine_paths(scene.handle, _ptr(txt), txt.shape[0], _ptr(rxt), rxt.shape[0],
                                                C.byref(pp), K, C.byref(prm), C.byref(out), _stream(device)))
     res["n_kept"] = int(out.n_kept)
+    return res
+
+
+def sdf_intersect(scene: Scene, o, d, t_range=None, h=0.0, eps=0.0, max_steps=0, with_stats=False) -> dict:
+    """First intersection of each ray with the implicit surface of Eq. 1
+    (Section 2.2.1): signed distances f(x) = (x - p(x)) . n(x) of weighted
+    neighbourhood averages, marched along line segments through the occupied
+    leaves the ray crosses.
+
+    ``o`` and ``d`` are [n, 3] origins and directions, ``t_range`` an optional
+    [n, 2] (t_lo, t_hi).  ``h`` (neighbourhood radius), ``eps`` (near-zero
+    threshold) and ``max_steps`` (evaluations per leaf) select the defaults
+    0.95 and 1e-3 leaf edges and 64 when not positive.  Returns ``t`` (+inf
+    for none), ``point``, ``normal`` and ``leaf_cell`` (-1 for none); with
+    ``with_stats`` also ``evals`` and ``reads`` (evaluations of f and leaf
+    entries read, summed over the rays).
+    """
+    device = scene.device
+    ot = _as_tensor(o, torch.float32, device, 3)
+    dt = _as_tensor(d, torch.float32, device, 3)
+    if ot.shape != dt.shape:
+        raise ValueError("o and d must have the same shape")
+    n = ot.shape[0]
+    tr = None if t_range is None else _as_tensor(t_range, torch.float32, device, 2)
+    if tr is not None and tr.shape[0] != n:
+        raise ValueError("t_range must have one row per ray")
+    res = {
+        "t": torch.empty(n, dtype=torch.float32, device=device),
+        "point": torch.empty((n, 3), dtype=torch.float32, device=device),
+        "normal": torch.empty((n, 3), dtype=torch.float32, device=device),
+        "leaf_cell": torch.empty((n, 3), dtype=torch.int32, device=device),
+    }
+    stats = torch.zeros(2, dtype=torch.int64, device=device) if with_stats else None
+    prm = _lib.PcrlSdfParams(float(h), float(eps), int(max_steps), 0, _ptr(stats) if with_stats else None)
+    with _on(device):
+        check("sdf_intersect", lib.sdf_intersect(scene.handle, _ptr(ot), _ptr(dt), _ptr(tr) if tr is not None
+                                                 else None, n, C.byref(prm), _ptr(res["t"]), _ptr(res["point"]),
+                                                 _ptr(res["normal"]), _ptr(res["leaf_cell"]), _stream(device)))
+    if with_stats:
+        st = stats.cpu()
+        res["evals"], res["reads"] = int(st[0]), int(st[1])
     return res
 
 

@@ -105,6 +105,11 @@ class PcrlRefined(C.Structure):
                 ("kept", C.c_void_p)]
 
 
+class PcrlSdfParams(C.Structure):
+    _fields_ = [("h", C.c_float), ("eps", C.c_float), ("max_steps", C.c_int32), ("flags", C.c_int32),
+                ("stats", C.c_void_p)]
+
+
 class PcrlQuery(C.Structure):
     _fields_ = [("scene", C.c_void_p), ("tx", C.c_void_p), ("n_tx", C.c_int32), ("n_rx", C.c_int32),
                 ("rx", C.c_void_p), ("params", PcrlLaunchParams)]
@@ -152,6 +157,9 @@ SIGNATURES = {
     "collect_paths": (C.c_int, [C.c_void_p, C.c_int32, C.c_int32, C.POINTER(PcrlPaths), C.c_void_p]),
     "refine_paths": (C.c_int, [C.c_void_p, C.c_void_p, C.c_int32, C.c_void_p, C.c_int32, C.POINTER(PcrlPaths),
                                C.c_int32, C.POINTER(PcrlRefineParams), C.POINTER(PcrlRefined), C.c_void_p]),
+    "sdf_intersect": (C.c_int, [C.c_void_p, C.c_void_p, C.c_void_p, C.c_void_p, C.c_int64,
+                                C.POINTER(PcrlSdfParams), C.c_void_p, C.c_void_p, C.c_void_p, C.c_void_p,
+                                C.c_void_p]),
     "launch_batch": (C.c_int, [C.POINTER(PcrlQuery), C.c_int32, C.POINTER(PcrlBatchParams), C.c_void_p,
                                C.POINTER(C.c_void_p)]),
     "batch_autotune": (C.c_int, [C.POINTER(PcrlQuery), C.c_int32, C.c_void_p, C.POINTER(PcrlBatchParams)]),

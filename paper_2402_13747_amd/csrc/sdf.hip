@@ -1,0 +1,301 @@
+// sdf.hip -- ray intersection with the implicit surface of Eq. 1 (paper,
+// Section 2.2.1 "Intersections"): the signed distance
+//   f(x) = (x - p(x)) . n(x),
+// p and n the weighted averages of the positions and normals of the points
+// within h of x (weights (1 - |x - q|^2 / h^2)^4; n normalised), is marched
+// along the ray: for every occupied leaf the ray crosses, a line segment one
+// leaf diagonal long is centred on the projection onto the ray of the centre
+// of the box around the leaf's own points (points whose centre lies in the
+// leaf); from its near end the march moves by |f(s_i)| and stops at a sample
+// with |f| <= eps, or between two samples of opposite sign (at the zero of
+// the linear interpolation), or at the segment's far end, or after max_steps
+// evaluations.  Where no point lies within h, f is undefined: the march moves
+// by h / 2 and compares no sign across that sample.  The ray's intersection is
+// the nearest over the leaves; its normal is n at the final sample.
+//
+// Lane = ray.  The leaves come from the launcher's hierarchical DDA
+// (trace_core.h), walked per lane; the walk stops once the next cell starts
+// more than 1.5 leaf diagonals beyond the nearest intersection found (no
+// later leaf's segment starts before that).  The neighbours of x are the
+// entries of the 27 leaves around x's leaf (h is at most 0.98 leaf edges)
+// whose centre lies in that leaf, so each point is counted once.
+#include "trace_core.h"
+
+#include <cmath>
+
+namespace pcrl {
+
+constexpr int SDF_BLOCK = 256;
+
+struct SdfArgs {
+    SceneView v;
+    const float* o;        // [n][3]
+    const float* d;        // [n][3]
+    const float* tr;       // [n][2] (t_lo, t_hi), or null for (0, inf)
+    uint32_t n;
+    int32_t max_steps;
+    float h2;              // h^2
+    float half_h;          // step over an undefined sample
+    float eps;
+    float half_diam;       // half the segment length (half a leaf diagonal)
+    float reach;           // 1.5 leaf diagonals and a rounding margin
+    int32_t empty;         // the scene holds no point
+    float* t;              // [n]
+    float* pt;             // [n][3]
+    float* nrm;            // [n][3]
+    int32_t* cell;         // [n][3] or null
+    unsigned long long* stats;  // null, or [2]: evaluations of f, entries read
+};
+
+// Entries of leaf `cell` (a count of 0 when it is empty).
+template <int NL>
+__device__ __forceinline__ uint2 leaf_entries(const SceneView& v, const int cell[3]) {
+    uint32_t node = 0;
+    int skip0 = 0;
+    if (descend<false, NL - 1>(v, cell, node, skip0, nullptr) != NL) return make_uint2(0u, 0u);
+    return v.leaf[node];
+}
+
+__device__ __forceinline__ bool in_leaf(const SceneView& v, const float4& P, const int cell[3]) {
+    return (int)floorf((P.x - v.org[0]) * v.inv_h) == cell[0] && (int)floorf((P.y - v.org[1]) * v.inv_h) == cell[1] &&
+           (int)floorf((P.z - v.org[2]) * v.inv_h) == cell[2];
+}
+
+// f(x) of Eq. 1 and the unit normal n(x); false where f is undefined.  The
+// offset p(x) - x is accumulated relative to x.
+template <int NL>
+__device__ __forceinline__ bool sdf_eval(const SceneView& v, const float x[3], float h2, float& f, float n[3],
+                                         uint32_t& reads) {
+    int lc[3];
+#pragma unroll
+    for (int a = 0; a < 3; ++a) lc[a] = (int)floorf((x[a] - v.org[a]) * v.inv_h);
+    float sw = 0.f, sp0 = 0.f, sp1 = 0.f, sp2 = 0.f, sn0 = 0.f, sn1 = 0.f, sn2 = 0.f;
+    for (int dz = -1; dz <= 1; ++dz)
+        for (int dy = -1; dy <= 1; ++dy)
+            for (int dx = -1; dx <= 1; ++dx) {
+                const int cell[3] = {lc[0] + dx, lc[1] + dy, lc[2] + dz};
+                if (cell[0] < 0 || cell[1] < 0 || cell[2] < 0 || cell[0] >= v.dim[0] || cell[1] >= v.dim[1] ||
+                    cell[2] >= v.dim[2])
+                    continue;
+                const uint2 r = leaf_entries<NL>(v, cell);
+                reads += r.y;
+                for (uint32_t e = r.x; e < r.x + r.y; ++e) {
+                    const float4 P = v.spos[e];
+                    const float ex = P.x - x[0], ey = P.y - x[1], ez = P.z - x[2];
+                    const float d2 = ex * ex + ey * ey + ez * ez;
+                    if (!(d2 < h2) || !in_leaf(v, P, cell)) continue;
+                    const float4 N = v.snrm[e];
+                    float w = 1.0f - d2 / h2;
+                    w *= w;
+                    w *= w;
+                    sw += w;
+                    sp0 += w * ex;
+                    sp1 += w * ey;
+                    sp2 += w * ez;
+                    sn0 += w * N.x;
+                    sn1 += w * N.y;
+                    sn2 += w * N.z;
+                }
+            }
+    const float ln = sqrtf(sn0 * sn0 + sn1 * sn1 + sn2 * sn2);
+    if (!(sw > 0.f) || !(ln > 0.f)) return false;
+    const float inv = 1.0f / ln;
+    n[0] = sn0 * inv;
+    n[1] = sn1 * inv;
+    n[2] = sn2 * inv;
+    f = -(sp0 * n[0] + sp1 * n[1] + sp2 * n[2]) / sw;
+    return true;
+}
+
+// Centre of the box around the entries of range r whose centre lies in leaf
+// `cell`; false when there is none.
+__device__ __forceinline__ bool own_box_centre(const SceneView& v, uint2 r, const int cell[3], float c[3]) {
+    float lo0 = INFINITY, lo1 = INFINITY, lo2 = INFINITY, hi0 = -INFINITY, hi1 = -INFINITY, hi2 = -INFINITY;
+    for (uint32_t e = r.x; e < r.x + r.y; ++e) {
+        const float4 P = v.spos[e];
+        if (!in_leaf(v, P, cell)) continue;
+        lo0 = fminf(lo0, P.x);
+        lo1 = fminf(lo1, P.y);
+        lo2 = fminf(lo2, P.z);
+        hi0 = fmaxf(hi0, P.x);
+        hi1 = fmaxf(hi1, P.y);
+        hi2 = fmaxf(hi2, P.z);
+    }
+    if (!(lo0 <= hi0)) return false;
+    c[0] = 0.5f * (lo0 + hi0);
+    c[1] = 0.5f * (lo1 + hi1);
+    c[2] = 0.5f * (lo2 + hi2);
+    return true;
+}
+
+template <int NL>
+__global__ __launch_bounds__(SDF_BLOCK) void k_sdf(SdfArgs a) {
+    const uint32_t i = blockIdx.x * SDF_BLOCK + threadIdx.x;
+    if (i >= a.n) return;
+    const SceneView& v = a.v;
+    float o[3] = {a.o[3 * i], a.o[3 * i + 1], a.o[3 * i + 2]};
+    float d[3] = {a.d[3 * i], a.d[3 * i + 1], a.d[3 * i + 2]};
+    const float t_lo = a.tr ? a.tr[2 * i] : 0.f;
+    const float t_hi = a.tr ? a.tr[2 * i + 1] : INFINITY;
+    const float len = sqrtf(d[0] * d[0] + d[1] * d[1] + d[2] * d[2]);
+    float best = INFINITY, bn[3] = {0.f, 0.f, 0.f};
+    int bc[3] = {-1, -1, -1};
+    uint32_t evals = 0, reads = 0;
+    const bool ok = !a.empty && len > 0.f && isfinite(len) && isfinite(o[0]) && isfinite(o[1]) && isfinite(o[2]) &&
+                    t_lo <= t_hi;
+    Seg S;
+    bool walking = false;
+    float t_in = 0.f;  // where the ray enters the current cell
+    if (ok) {
+        const float il = 1.0f / len;
+        d[0] *= il;
+        d[1] *= il;
+        d[2] *= il;
+        walking = seg_begin(v, o, d, S);
+        if (walking) {
+#pragma unroll
+            for (int ax = 0; ax < 3; ++ax) {
+                float tf = -INFINITY;
+                if (d[ax] > 0.f) tf = ((float)S.c[ax] * v.h + v.org[ax] - o[ax]) * S.inv[ax];
+                else if (d[ax] < 0.f) tf = ((float)(S.c[ax] + 1) * v.h + v.org[ax] - o[ax]) * S.inv[ax];
+                t_in = fmaxf(t_in, tf);
+            }
+        }
+    }
+    while (walking) {
+        DdaCell k;
+        dda_cell_reset(k);
+        dda_locate<false, NL>(v, S, k, nullptr);
+        const bool at_leaf = k.lvl == NL;
+        float c[3];
+        if (at_leaf && t_in <= t_hi && own_box_centre(v, k.range, S.c, c)) {
+            reads += k.range.y;
+            const float tc = (c[0] - o[0]) * d[0] + (c[1] - o[1]) * d[1] + (c[2] - o[2]) * d[2];
+            float t = fmaxf(tc - a.half_diam, t_lo);
+            const float tb = fminf(tc + a.half_diam, t_hi);
+            float fp = 0.f, tp = 0.f;
+            bool prev = false;
+            for (int s = 0; s < a.max_steps && t <= tb; ++s) {
+                // every later result of this leaf lies at or beyond t
+                if (t >= best && !(prev && tp < best)) break;
+                const float x[3] = {o[0] + t * d[0], o[1] + t * d[1], o[2] + t * d[2]};
+                float f, n[3];
+                ++evals;
+                if (!sdf_eval<NL>(v, x, a.h2, f, n, reads)) {
+                    prev = false;
+                    t += a.half_h;
+                    continue;
+                }
+                float th = t;
+                bool found = fabsf(f) <= a.eps;
+                if (!found && prev && ((f < 0.f) != (fp < 0.f))) {
+                    th = tp + (t - tp) * fp / (fp - f);
+                    found = true;
+                }
+                if (found) {
+                    if (th < best) {
+                        best = th;
+                        bn[0] = n[0];
+                        bn[1] = n[1];
+                        bn[2] = n[2];
+                        bc[0] = S.c[0];
+                        bc[1] = S.c[1];
+                        bc[2] = S.c[2];
+                    }
+                    break;
+                }
+                prev = true;
+                fp = f;
+                tp = t;
+                t += fabsf(f);
+            }
+        }
+        float te;
+        dda_advance<NL>(v, walking, o, d, S, k, at_leaf, fminf(best + a.reach, t_hi), te);
+        t_in = te;
+    }
+    a.t[i] = best;
+    const bool hit = bc[0] >= 0;
+#pragma unroll
+    for (int ax = 0; ax < 3; ++ax) {
+        a.pt[3 * i + ax] = hit ? o[ax] + best * d[ax] : NAN;
+        a.nrm[3 * i + ax] = bn[ax];
+        if (a.cell) a.cell[3 * i + ax] = bc[ax];
+    }
+    if (a.stats) {
+        atomicAdd(&a.stats[0], (unsigned long long)evals);
+        atomicAdd(&a.stats[1], (unsigned long long)reads);
+    }
+}
+
+template <int NL>
+static void launch_sdf_nl(const SdfArgs& a, hipStream_t s) {
+    const unsigned grid = (a.n + SDF_BLOCK - 1) / SDF_BLOCK;
+    hipLaunchKernelGGL((k_sdf<NL>), dim3(grid), dim3(SDF_BLOCK), 0, s, a);
+}
+
+}  // namespace pcrl
+
+using namespace pcrl;
+
+extern "C" int sdf_intersect(const PcrlScene* scene, const float* o, const float* d, const float* t_range,
+                             int64_t n_rays, const PcrlSdfParams* params, float* t, float* point, float* normal,
+                             int32_t* leaf_cell, pcrl_stream_t stream) {
+    clear_error();
+    if (!scene || n_rays < 0 || n_rays >= ((int64_t)1 << 31)) {
+        set_error("sdf_intersect: invalid scene or ray count (0 <= n_rays < 2^31)");
+        return PCRL_EINVAL;
+    }
+    if (n_rays > 0 && (!o || !d || !t || !point || !normal)) {
+        set_error("sdf_intersect: a ray or output array is NULL");
+        return PCRL_EINVAL;
+    }
+    if (scene->overlay && scene->overlay->n_entries > 0) {
+        set_error("sdf_intersect: the scene has dynamic points (update_points); the implicit surface is defined "
+                  "over the static points only");
+        return PCRL_EINVAL;
+    }
+    PcrlSdfParams P{};
+    if (params) P = *params;
+    const float leaf = scene->view.h;
+    const float h = P.h > 0.f ? P.h : 0.95f * leaf;
+    const float eps = P.eps > 0.f ? P.eps : 1e-3f * leaf;
+    const int32_t max_steps = P.max_steps > 0 ? P.max_steps : 64;
+    if (!(h <= 0.98f * leaf) || !std::isfinite(eps) || max_steps > (1 << 20) || P.flags != 0) {
+        set_error("sdf_intersect: need 0 < h <= 0.98 leaf edges (h %g, leaf %g), a finite eps, max_steps <= 2^20 "
+                  "and flags 0", (double)h, (double)leaf);
+        return PCRL_EINVAL;
+    }
+    if (n_rays == 0) return PCRL_OK;
+    SdfArgs a{};
+    a.v = scene->view;
+    a.o = o;
+    a.d = d;
+    a.tr = t_range;
+    a.n = (uint32_t)n_rays;
+    a.max_steps = max_steps;
+    a.h2 = h * h;
+    a.half_h = 0.5f * h;
+    a.eps = eps;
+    const float diag = sqrtf(3.0f) * leaf;
+    a.half_diam = 0.5f * diag;
+    a.reach = 1.5f * diag * (1.0f + 1e-5f) + 1e-3f * leaf;
+    a.empty = scene->info.n_points == 0;
+    a.t = t;
+    a.pt = point;
+    a.nrm = normal;
+    a.cell = leaf_cell;
+    a.stats = (unsigned long long*)P.stats;
+    hipStream_t s = (hipStream_t)stream;
+    switch (scene->view.nlev) {
+    case 1: launch_sdf_nl<1>(a, s); break;
+    case 2: launch_sdf_nl<2>(a, s); break;
+    case 3: launch_sdf_nl<3>(a, s); break;
+    default: launch_sdf_nl<4>(a, s); break;
+    }
+    if (hipGetLastError() != hipSuccess) {
+        set_error("sdf_intersect: kernel launch failed");
+        return PCRL_EHIP;
+    }
+    return PCRL_OK;
+}

@@ -310,6 +310,180 @@ __device__ __forceinline__ void hit_reset(Hit& hit) {
     hit.nx = hit.ny = hit.nz = 0.f;
 }
 
+// What the DDA found at the current cell: an occupied leaf (lvl == NL, its
+// node and entry range) or an empty cell of level lvl with the empty region
+// around it that the ray may skip.
+struct DdaCell {
+    uint32_t node;
+    uint2 range;    // entries of an occupied leaf
+    int skip;       // > 1: an empty cube of 2 skip - 1 units centred on the unit holding c
+    int oct;        // > 1: an empty box of oct leaves from c along the ray's octant
+    int unit;       // edge of a skip unit in leaves (1, or a level-0 cell)
+    int lvl;        // level of the empty cell containing c, or NL for an occupied leaf
+};
+
+__device__ __forceinline__ void dda_cell_reset(DdaCell& k) {
+    k.node = 0;
+    k.range = make_uint2(0u, 0u);
+    k.skip = 1;
+    k.oct = 1;
+    k.unit = 1;
+    k.lvl = 0;
+}
+
+// Look the lane's current cell S.c up top-down through a hierarchy of NL
+// levels (NL == v.nlev).  Per lane; no cross-lane operations.
+template <bool STATS, int NL>
+__device__ __forceinline__ void dda_locate(const SceneView& v, Seg& S, DdaCell& k, stat_t* cnt) {
+    constexpr int L = NL;
+    constexpr int P = L - 2;  // level of the leaves' parents (-1: single-level grid)
+    const int* c = S.c;
+    if constexpr (P < 0) {
+        const size_t i0 = (size_t)c[0] + (size_t)v.dim0[0] * ((size_t)c[1] + (size_t)v.dim0[1] * c[2]);
+        const int32_t n0 = v.map0[i0];
+        const int d0 = v.dist0 ? (int)v.dist0[i0] : 1;
+        if (STATS) {
+            ++cnt[ST_NODES];
+            cnt[ST_BYTES] += (n0 < 0 && v.dist0) ? 5 : 4;
+        }
+        k.lvl = (n0 < 0 || (uint32_t)n0 >= v.nn[0]) ? 0 : L;
+        k.node = (uint32_t)n0;
+        if (k.lvl == 0) k.skip = max(1, d0);
+        if (k.lvl == L) {
+            k.range = v.leaf[k.node];
+            if (STATS) cnt[ST_BYTES] += 8;
+        }
+    } else {
+        // the descent from level 0 runs only when the parent cell changes
+        const int q[3] = {span_div(c[0], v.mspan[P]), span_div(c[1], v.mspan[P]), span_div(c[2], v.mspan[P])};
+        if (q[0] != S.cq[0] || q[1] != S.cq[1] || q[2] != S.cq[2]) {
+            S.cq[0] = q[0];
+            S.cq[1] = q[1];
+            S.cq[2] = q[2];
+            S.cres = descend<STATS, P>(v, c, S.cnode, S.cskip0, cnt);
+        }
+        if (S.cres <= P) {
+            k.lvl = S.cres;
+            if (k.lvl == 0) {
+                // empty level-0 cell: the cube of radius cskip0 - 1 level-0 cells around it is empty
+                k.skip = max(1, S.cskip0);
+                k.unit = v.span[0];
+            }
+        } else if (v.cells) {
+            // one load: the leaf's entry range, or its skip radius
+            const int r = v.ratio[P];
+            const int loc = (c[0] - r * q[0]) + r * ((c[1] - r * q[1]) + r * (c[2] - r * q[2]));
+            const uint2 cl = v.cells[(size_t)S.cnode * (size_t)(r * r * r) + loc];
+            if (STATS) {
+                ++cnt[ST_NODES];
+                cnt[ST_BYTES] += 8;
+            }
+            if (cl.y) {
+                k.lvl = L;
+                k.range = cl;
+                k.node = cl.x;
+            } else {
+                // empty leaf: the box of oct cells from it along the ray's octant is empty
+                k.lvl = L - 1;
+                k.oct = (int)((cl.x >> S.oct_shift) & 15u);
+            }
+        } else {
+            const int r = v.ratio[P];
+            const int loc = (c[0] - r * q[0]) + r * ((c[1] - r * q[1]) + r * (c[2] - r * q[2]));
+            const size_t wi = (size_t)S.cnode * v.nw[P] + (loc >> 6);
+            // the mask word, the word's child base and the leaf's skip radius are
+            // loaded together (one memory round trip); only one of the last two is used
+            const uint64_t w = v.mask[P][wi];
+            const uint32_t wbase = v.base[P][wi];
+            const int ld = v.ldist ? (int)v.ldist[(size_t)S.cnode * (size_t)(r * r * r) + loc] : 1;
+            const uint64_t bit = uint64_t(1) << (loc & 63);
+            if (STATS) {
+                ++cnt[ST_NODES];
+                cnt[ST_BYTES] += (w & bit) ? 12 : (v.ldist ? 9 : 8);
+            }
+            k.lvl = L - 1;
+            if (w & bit) {
+                k.node = wbase + (uint32_t)__popcll(w & (bit - 1));
+                if (k.node < v.nn[L - 1]) {
+                    k.lvl = L;
+                    k.range = v.leaf[k.node];
+                    if (STATS) cnt[ST_BYTES] += 8;
+                }
+            } else {
+                // empty leaf: the whole cube of radius skip - 1 around it is empty
+                k.skip = max(1, ld);
+            }
+        }
+    }
+}
+
+// Move the lane past the cell (or empty region) `k` describes: S.c becomes
+// the next cell along the ray, and `te` the distance at which the ray enters
+// it.  Clears `walking` when the next cell starts beyond t_stop or the ray
+// leaves the grid.  Per lane; no cross-lane operations.
+template <int NL>
+__device__ __forceinline__ void dda_advance(const SceneView& v, bool& walking, const float o[3], const float d[3],
+                                            Seg& S, const DdaCell& k, bool at_leaf, float t_stop, float& te) {
+    int* c = S.c;
+    const int Sz = at_leaf ? 1 : span_at<NL>(v, k.lvl);
+    // exit of the current cell (size Sz leaves)
+    int lo[3], hi[3];
+    te = INFINITY;
+    int axis = 0;
+#pragma unroll
+    for (int a = 0; a < 3; ++a) {
+        if (k.oct > 1) {
+            // the octant box (inside its brick)
+            lo[a] = d[a] < 0.f ? c[a] - (k.oct - 1) : c[a];
+            hi[a] = d[a] < 0.f ? c[a] + 1 : c[a] + k.oct;
+        } else if (k.skip > 1) {
+            // the skip cube, clipped to the grid (beyond it the ray leaves)
+            const int uc = (k.unit == 1) ? c[a] : span_div(c[a], v.mspan[0]);
+            lo[a] = max((uc - (k.skip - 1)) * k.unit, 0);
+            hi[a] = min((uc + k.skip) * k.unit, v.dim[a]);
+        } else {
+            lo[a] = (Sz == 1) ? c[a] : span_div(c[a], mspan_at<NL>(v, k.lvl)) * Sz;
+            hi[a] = lo[a] + Sz;
+        }
+        float ta = INFINITY;
+        if (d[a] > 0.f)
+            ta = ((float)hi[a] * v.h + v.org[a] - o[a]) * S.inv[a];
+        else if (d[a] < 0.f)
+            ta = ((float)lo[a] * v.h + v.org[a] - o[a]) * S.inv[a];
+        if (ta < te) {
+            te = ta;
+            axis = a;
+        }
+    }
+    // next cell along the exit axis (selects, no dynamic indexing of private arrays)
+    int nc = 0, dim_ax = 0;
+#pragma unroll
+    for (int a = 0; a < 3; ++a)
+        if (a == axis) {
+            nc = d[a] > 0.f ? hi[a] : lo[a] - 1;
+            dim_ax = v.dim[a];
+        }
+    const int max_iter = v.dim[0] + v.dim[1] + v.dim[2] + 8;
+    // no later cell can hold a nearer hit; or the ray leaves the grid
+    if (te > t_stop || nc < 0 || nc >= dim_ax || ++S.it >= max_iter) {
+        walking = false;
+    } else {
+#pragma unroll
+        for (int a = 0; a < 3; ++a) {
+            if (a == axis) {
+                c[a] = nc;
+                continue;
+            }
+            const int sg = dir_step(d[a]);
+            if (sg == 0) continue;
+            int j = (int)floorf((o[a] + te * d[a] - v.org[a]) * v.inv_h);
+            j = min(max(j, lo[a]), hi[a] - 1);
+            j = sg > 0 ? max(j, c[a]) : min(j, c[a]);
+            c[a] = j;
+        }
+    }
+}
+
 // One DDA step of every walking lane through a hierarchy of NL levels
 // (NL == v.nlev): look the current cell up top-down, test an occupied leaf
 // (cooperatively, with the other lanes' leaves), then move to the next cell
@@ -319,171 +493,32 @@ template <bool STATS, int NL>
 __device__ __forceinline__ void dda_step(const SceneView& v, LeafTestLds& W, bool& walking, const float o[3],
                                          const float d[3], Hit& hit, Seg& S, stat_t cnt[ST_COUNT]) {
     constexpr int L = NL;
-    constexpr int P = L - 2;  // level of the leaves' parents (-1: single-level grid)
-    int* c = S.c;
-    uint32_t node = 0;
-    uint2 range = make_uint2(0u, 0u);  // entries of an occupied leaf
-    int skip = 1;   // > 1: an empty cube of 2 skip - 1 units centred on the unit holding c
-    int oct = 1;    // > 1: an empty box of oct leaves from c along the ray's octant
-    int unit = 1;   // edge of a skip unit in leaves (1, or a level-0 cell)
-    int lvl = 0;    // level of the empty cell containing c, or L for an occupied leaf
-    if (walking) {
-        if constexpr (P < 0) {
-            const size_t i0 = (size_t)c[0] + (size_t)v.dim0[0] * ((size_t)c[1] + (size_t)v.dim0[1] * c[2]);
-            const int32_t n0 = v.map0[i0];
-            const int d0 = v.dist0 ? (int)v.dist0[i0] : 1;
-            if (STATS) {
-                ++cnt[ST_NODES];
-                cnt[ST_BYTES] += (n0 < 0 && v.dist0) ? 5 : 4;
-            }
-            lvl = (n0 < 0 || (uint32_t)n0 >= v.nn[0]) ? 0 : L;
-            node = (uint32_t)n0;
-            if (lvl == 0) skip = max(1, d0);
-            if (lvl == L) {
-                range = v.leaf[node];
-                if (STATS) cnt[ST_BYTES] += 8;
-            }
-        } else {
-            // the descent from level 0 runs only when the parent cell changes
-            const int q[3] = {span_div(c[0], v.mspan[P]), span_div(c[1], v.mspan[P]), span_div(c[2], v.mspan[P])};
-            if (q[0] != S.cq[0] || q[1] != S.cq[1] || q[2] != S.cq[2]) {
-                S.cq[0] = q[0];
-                S.cq[1] = q[1];
-                S.cq[2] = q[2];
-                S.cres = descend<STATS, P>(v, c, S.cnode, S.cskip0, cnt);
-            }
-            if (S.cres <= P) {
-                lvl = S.cres;
-                if (lvl == 0) {
-                    // empty level-0 cell: the cube of radius cskip0 - 1 level-0 cells around it is empty
-                    skip = max(1, S.cskip0);
-                    unit = v.span[0];
-                }
-            } else if (v.cells) {
-                // one load: the leaf's entry range, or its skip radius
-                const int r = v.ratio[P];
-                const int loc = (c[0] - r * q[0]) + r * ((c[1] - r * q[1]) + r * (c[2] - r * q[2]));
-                const uint2 cl = v.cells[(size_t)S.cnode * (size_t)(r * r * r) + loc];
-                if (STATS) {
-                    ++cnt[ST_NODES];
-                    cnt[ST_BYTES] += 8;
-                }
-                if (cl.y) {
-                    lvl = L;
-                    range = cl;
-                    node = cl.x;
-                } else {
-                    // empty leaf: the box of oct cells from it along the ray's octant is empty
-                    lvl = L - 1;
-                    oct = (int)((cl.x >> S.oct_shift) & 15u);
-                }
-            } else {
-                const int r = v.ratio[P];
-                const int loc = (c[0] - r * q[0]) + r * ((c[1] - r * q[1]) + r * (c[2] - r * q[2]));
-                const size_t wi = (size_t)S.cnode * v.nw[P] + (loc >> 6);
-                // the mask word, the word's child base and the leaf's skip radius are
-                // loaded together (one memory round trip); only one of the last two is used
-                const uint64_t w = v.mask[P][wi];
-                const uint32_t wbase = v.base[P][wi];
-                const int ld = v.ldist ? (int)v.ldist[(size_t)S.cnode * (size_t)(r * r * r) + loc] : 1;
-                const uint64_t bit = uint64_t(1) << (loc & 63);
-                if (STATS) {
-                    ++cnt[ST_NODES];
-                    cnt[ST_BYTES] += (w & bit) ? 12 : (v.ldist ? 9 : 8);
-                }
-                lvl = L - 1;
-                if (w & bit) {
-                    node = wbase + (uint32_t)__popcll(w & (bit - 1));
-                    if (node < v.nn[L - 1]) {
-                        lvl = L;
-                        range = v.leaf[node];
-                        if (STATS) cnt[ST_BYTES] += 8;
-                    }
-                } else {
-                    // empty leaf: the whole cube of radius skip - 1 around it is empty
-                    skip = max(1, ld);
-                }
-            }
-        }
-    }
-    const bool at_leaf = walking && lvl == L;
+    DdaCell k;
+    dda_cell_reset(k);
+    if (walking) dda_locate<STATS, NL>(v, S, k, cnt);
+    const bool at_leaf = walking && k.lvl == L;
     if (STATS) {
         const uint64_t m_walk = __ballot(walking);
         if (walking) {
             ++cnt[ST_DDA];
-            if (lvl == L - 1 && L > 1) ++cnt[ST_EMPTY_LEAF];
+            if (k.lvl == L - 1 && L > 1) ++cnt[ST_EMPTY_LEAF];
         }
         // leaf visits where every lane of the wave still walking is in the same leaf
         const uint64_t m_leaf = __ballot(at_leaf);
         const int first = m_leaf ? __ffsll((long long)m_leaf) - 1 : 0;
-        const uint32_t lead = __shfl(node, first, 64);
-        if (at_leaf && __ballot(at_leaf && node == lead) == m_walk) ++cnt[ST_UNIFORM];
+        const uint32_t lead = __shfl(k.node, first, 64);
+        if (at_leaf && __ballot(at_leaf && k.node == lead) == m_walk) ++cnt[ST_UNIFORM];
         if (lane_id() == 0) ++cnt[ST_WAVE_DDA];
     }
     if (STATS && at_leaf) {
         ++cnt[ST_LEAVES];
-        cnt[ST_TESTS] += range.y;
-        cnt[ST_BYTES] += 32ull * range.y;
+        cnt[ST_TESTS] += k.range.y;
+        cnt[ST_BYTES] += 32ull * k.range.y;
     }
-    if (__ballot(at_leaf && range.y != 0u)) leaf_tests<STATS>(v, W, at_leaf, range, hit, cnt);
+    if (__ballot(at_leaf && k.range.y != 0u)) leaf_tests<STATS>(v, W, at_leaf, k.range, hit, cnt);
     if (walking) {
-        const int Sz = at_leaf ? 1 : span_at<NL>(v, lvl);
-        // exit of the current cell (size Sz leaves)
-        int lo[3], hi[3];
-        float te = INFINITY;
-        int axis = 0;
-#pragma unroll
-        for (int a = 0; a < 3; ++a) {
-            if (oct > 1) {
-                // the octant box (inside its brick)
-                lo[a] = d[a] < 0.f ? c[a] - (oct - 1) : c[a];
-                hi[a] = d[a] < 0.f ? c[a] + 1 : c[a] + oct;
-            } else if (skip > 1) {
-                // the skip cube, clipped to the grid (beyond it the ray leaves)
-                const int uc = (unit == 1) ? c[a] : span_div(c[a], v.mspan[0]);
-                lo[a] = max((uc - (skip - 1)) * unit, 0);
-                hi[a] = min((uc + skip) * unit, v.dim[a]);
-            } else {
-                lo[a] = (Sz == 1) ? c[a] : span_div(c[a], mspan_at<NL>(v, lvl)) * Sz;
-                hi[a] = lo[a] + Sz;
-            }
-            float ta = INFINITY;
-            if (d[a] > 0.f)
-                ta = ((float)hi[a] * v.h + v.org[a] - o[a]) * S.inv[a];
-            else if (d[a] < 0.f)
-                ta = ((float)lo[a] * v.h + v.org[a] - o[a]) * S.inv[a];
-            if (ta < te) {
-                te = ta;
-                axis = a;
-            }
-        }
-        // next cell along the exit axis (selects, no dynamic indexing of private arrays)
-        int nc = 0, dim_ax = 0;
-#pragma unroll
-        for (int a = 0; a < 3; ++a)
-            if (a == axis) {
-                nc = d[a] > 0.f ? hi[a] : lo[a] - 1;
-                dim_ax = v.dim[a];
-            }
-        const int max_iter = v.dim[0] + v.dim[1] + v.dim[2] + 8;
-        // no later cell can hold a nearer hit; or the ray leaves the grid
-        if (te > hit.t + (hit.t * 4e-6f + 1e-3f * v.h) || nc < 0 || nc >= dim_ax || ++S.it >= max_iter) {
-            walking = false;
-        } else {
-#pragma unroll
-            for (int a = 0; a < 3; ++a) {
-                if (a == axis) {
-                    c[a] = nc;
-                    continue;
-                }
-                const int sg = dir_step(d[a]);
-                if (sg == 0) continue;
-                int j = (int)floorf((o[a] + te * d[a] - v.org[a]) * v.inv_h);
-                j = min(max(j, lo[a]), hi[a] - 1);
-                j = sg > 0 ? max(j, c[a]) : min(j, c[a]);
-                c[a] = j;
-            }
-        }
+        float te;
+        dda_advance<NL>(v, walking, o, d, S, k, at_leaf, hit.t + (hit.t * 4e-6f + 1e-3f * v.h), te);
     }
 }
 

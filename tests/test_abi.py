@@ -72,6 +72,7 @@ def test_struct_sizes(pcrl):
     assert C.sizeof(_lib.PcrlPaths) == 13 * 8
     assert C.sizeof(_lib.PcrlRefineParams) == 24
     assert C.sizeof(_lib.PcrlRefined) == 9 * 8
+    assert C.sizeof(_lib.PcrlSdfParams) == 24
 
 
 def test_version_and_validation_without_gpu(pcrl):
@@ -105,6 +106,8 @@ def test_version_and_validation_without_gpu(pcrl):
     ro = _lib.PcrlRefined()
     assert lib.refine_paths(None, None, 0, None, 0, None, 0, None, C.byref(ro), None) == _lib.PCRL_EINVAL
     assert b"refine_paths" in lib.last_error()
+    assert lib.sdf_intersect(None, None, None, None, 1, None, None, None, None, None, None) == _lib.PCRL_EINVAL
+    assert b"sdf_intersect" in lib.last_error()
     assert lib.release_scene(None) == 0 and lib.release_launch(None) == 0
     # the library's own allocator is the default and can always be restored
     assert lib.set_allocator(None) == _lib.PCRL_OK

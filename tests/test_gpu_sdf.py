@@ -1,0 +1,199 @@
+"""GPU intersection with the implicit surface of Eq. 1 (sdf_intersect) against
+the FP64 oracle, through the C ABI.
+
+Both sides march the same segments (the leaves' point sets are taken in FP32
+on both), so a ray's intersection is the oracle's up to the rounding of the
+march.  Bar, per ray whose oracle answer is stable (unchanged, within the
+tolerance below, when h, eps, the segment length and the leaf-crossing test
+are perturbed by a few units of rounding, and max_steps by one):
+  * hit or miss as the oracle;
+  * |t - t_ref| <= 2 eps / max(|d . n|, 0.05) + 4e-6 (1 + |o| + t): both stop
+    once |f| <= eps, i.e. within eps / |d . n| before the zero along the
+    ray, so they may stop one step apart; FP32 positions add ~1e-6
+    relative;
+  * the normal within 0.05 (n(x) at points that far apart differs by about
+    |dx| / h); the leaf cell is one whose segment reaches the hit (the
+    segments of neighbouring leaves overlap, and where several marches meet
+    the same zero any of them may be named: the cell is not unique).
+Unstable rays are excused (their count is bounded).  Scenes: the empty box
+room (rays from the TX), random tilted planes and boxes with noise, the
+furnished room at full size (a sample of rays), plus edge cases.
+"""
+import math
+
+import numpy as np
+import pytest
+
+import scenes
+
+pytestmark = pytest.mark.gpu
+
+
+@pytest.fixture(scope="module")
+def env():
+    import torch
+    if not torch.cuda.is_available():
+        pytest.skip("no GPU")
+    import oracle
+    import paper_2402_13747_amd as pcrl
+    oracle.build(force=False)
+    return torch, pcrl, oracle
+
+
+def _build(env, s, levels=None):
+    _, pcrl, _ = env
+    lv = levels or s.levels
+    print(f"[sdf] {s.name}: {s.n_points} pts, levels={lv}", flush=True)
+    return pcrl.build_voxels(s.xyz, s.normal, s.label, lv, float(np.float32(s.surfel_radius)))
+
+
+def _oracle(env, s, info, o, d, tr=None, **kw):
+    _, _, oracle = env
+    return oracle.sdf_intersect(s.xyz, s.normal, np.asarray(info["origin"], np.float32), info["leaf_size"], o, d,
+                                trange=tr, **kw)
+
+
+def _compare(env, s, scene, o, d, tr=None, h=None, eps=None, max_steps=None, max_excused=0.05):
+    _, pcrl, oracle = env
+    info = scene.info()
+    leaf = float(info["leaf_size"])
+    h = oracle.SDF_H_SCALE * leaf if h is None else h
+    eps = oracle.SDF_EPS_SCALE * leaf if eps is None else eps
+    ms = oracle.SDF_MAX_STEPS if max_steps is None else max_steps
+    g = pcrl.sdf_intersect(scene, o, d, t_range=tr, h=h, eps=eps, max_steps=ms)
+    gt = g["t"].cpu().numpy().astype(np.float64)
+    gp = g["point"].cpu().numpy().astype(np.float64)
+    gn = g["normal"].cpu().numpy().astype(np.float64)
+    gc = g["leaf_cell"].cpu().numpy()
+    ref = _oracle(env, s, info, o, d, tr, h=h, eps=eps, max_steps=ms)
+    pa = _oracle(env, s, info, o, d, tr, h=h * (1 + 1e-4), eps=eps * (1 + 1e-2), max_steps=ms + 1,
+                 diam_scale=1 + 1e-5, cross_margin=1e-5 * leaf)
+    pb = _oracle(env, s, info, o, d, tr, h=h * (1 - 1e-4), eps=eps * (1 - 1e-2), max_steps=max(ms - 1, 1),
+                 diam_scale=1 - 1e-5, cross_margin=-1e-5 * leaf)
+    dd = np.asarray(d, np.float64)
+    dd = dd / np.linalg.norm(dd, axis=1, keepdims=True)
+    on = np.linalg.norm(np.asarray(o, np.float64), axis=1)
+    rt = ref["t"]
+    cos = np.abs((dd * ref["normal"]).sum(1))
+    fin = np.isfinite(rt)
+    tol = 2 * eps / np.maximum(cos, 0.05) + 4e-6 * (1 + on + np.where(fin, rt, 0.0))
+
+    def agree(a, b):
+        fa, fb = np.isfinite(a), np.isfinite(b)
+        return (fa == fb) & (~fa | (np.abs(np.where(fa, a, 0) - np.where(fb, b, 0)) <= tol))
+
+    stable = agree(pa["t"], rt) & agree(pb["t"], rt)
+    ok = agree(gt, rt)
+    bad = stable & ~ok
+    n = len(rt)
+    excused = int((~stable).sum())
+    hits = stable & fin & np.isfinite(gt)
+    n_err = np.linalg.norm(gn[hits] - ref["normal"][hits], axis=1)
+    p_err = np.linalg.norm(gp[hits] - ref["point"][hits], axis=1)
+    same_cell = (gc[hits] == ref["leaf_cell"][hits]).all(1)
+    print(f"  rays={n} hits={int(fin.sum())} stable={int(stable.sum())} excused={excused} mismatch={int(bad.sum())} "
+          f"max|dn|={n_err.max(initial=0):.2e} max|dp|={p_err.max(initial=0):.2e} "
+          f"cell_agree={same_cell.mean() if len(same_cell) else 1:.4f}", flush=True)
+    if bad.any():
+        i = int(np.nonzero(bad)[0][0])
+        raise AssertionError(f"ray {i}: gpu t={gt[i]!r} oracle t={rt[i]!r} tol={tol[i]:.3g} o={o[i]} d={d[i]}")
+    assert excused <= max_excused * n + 2
+    assert np.all(n_err <= 0.05)
+    assert np.all(p_err <= tol[hits] + 1e-5 * (1 + on[hits]))
+    if len(same_cell):
+        # where two leaves' marches reach the same zero, either may be named:
+        # the cell must at least be one whose segment reaches the hit
+        lo = np.asarray(info["origin"], np.float64) + gc[hits] * leaf
+        gap = np.linalg.norm(np.maximum(np.maximum(lo - gp[hits], gp[hits] - (lo + leaf)), 0.0), axis=1)
+        assert np.all(gap <= 1.5 * math.sqrt(3.0) * leaf + 1e-6)
+    # misses carry the documented empty outputs
+    miss = ~np.isfinite(gt)
+    assert np.all(np.isnan(gp[miss])) and np.all(gn[miss] == 0) and np.all(gc[miss] == -1)
+    return fin, stable
+
+
+def test_box_room_rays_from_tx(env):
+    _, _, oracle = env
+    s = scenes.box_room()
+    scene = _build(env, s)
+    d = oracle.fibonacci(3000)
+    o = np.repeat(s.tx.astype(np.float32), len(d), axis=0)
+    fin, _ = _compare(env, s, scene, o, d)
+    assert fin.mean() > 0.99  # a closed room: every ray meets a wall
+
+
+@pytest.mark.parametrize("seed", [1, 2, 3])
+def test_random_scenes(env, seed):
+    rng = np.random.default_rng(100 + seed)
+    s = scenes.random_scene(seed, extent=2.0, h=0.05, levels=(0.4, 0.2, 0.1) if seed != 2 else (0.1,),
+                            pos_sigma=0.002, tilt_sigma=0.03)
+    scene = _build(env, s)
+    n = 2000
+    o = rng.uniform(0.0, 2.0, size=(n, 3)).astype(np.float32)
+    d = rng.normal(size=(n, 3)).astype(np.float32)
+    fin, _ = _compare(env, s, scene, o, d)
+    assert fin.sum() > 200
+
+
+def test_ranges_and_parameters(env):
+    rng = np.random.default_rng(7)
+    s = scenes.random_scene(4, extent=2.0, h=0.05, levels=(0.4, 0.2), pos_sigma=0.002, tilt_sigma=0.03)
+    scene = _build(env, s)
+    n = 1500
+    o = rng.uniform(0.0, 2.0, size=(n, 3)).astype(np.float32)
+    d = rng.normal(size=(n, 3)).astype(np.float32)
+    t_lo = rng.uniform(0.0, 0.5, size=n)
+    tr = np.column_stack([t_lo, t_lo + rng.uniform(0.0, 1.5, size=n)]).astype(np.float32)
+    _compare(env, s, scene, o, d, tr=tr)
+    # a smaller neighbourhood, a tighter threshold and a short budget
+    _compare(env, s, scene, o, d, h=0.12, eps=2e-5, max_steps=12, max_excused=0.08)
+
+
+def test_furnished_room_full_size_sampled(env):
+    torch, pcrl, oracle = env
+    s = scenes.furnished_room()
+    scene = _build(env, s)
+    rng = np.random.default_rng(5)
+    d = oracle.fibonacci(1_000_000)[rng.choice(1_000_000, 400, replace=False)]
+    o = np.repeat(s.tx[:1].astype(np.float32), len(d), axis=0)
+    fin, _ = _compare(env, s, scene, o, d)
+    assert fin.mean() > 0.95
+    # the full launch-sized batch runs and reports its work
+    dd = torch.from_numpy(oracle.fibonacci(1_000_000)).cuda()
+    oo = torch.from_numpy(s.tx[:1].astype(np.float32)).cuda().expand(1_000_000, 3).contiguous()
+    r = pcrl.sdf_intersect(scene, oo, dd, with_stats=True)
+    torch.cuda.synchronize()
+    sel = torch.from_numpy(rng.choice(1_000_000, 400, replace=False)).cuda()
+    assert torch.equal(r["t"][sel].cpu(), pcrl.sdf_intersect(scene, oo[sel], dd[sel])["t"].cpu())
+    assert r["evals"] > 1_000_000 and r["reads"] > r["evals"]
+
+
+def test_edge_cases(env):
+    torch, pcrl, oracle = env
+    s = scenes.box_room()
+    scene = _build(env, s)
+    o = np.array([[2.0, 2.0, 1.5]] * 5, np.float32)
+    d = np.array([[1, 0, 0], [0, 0, 0], [np.nan, 0, 1], [0, 1, 0], [0, 0, -1]], np.float32)
+    tr = np.array([[0, np.inf], [0, np.inf], [0, np.inf], [1.0, 0.5], [0, np.inf]], np.float32)
+    r = pcrl.sdf_intersect(scene, o, d, t_range=tr)
+    t = r["t"].cpu().numpy()
+    assert np.isfinite(t[0]) and np.isfinite(t[4])
+    assert np.all(np.isinf(t[1:4]))  # zero direction, NaN direction, empty range
+    # no rays
+    r = pcrl.sdf_intersect(scene, np.zeros((0, 3), np.float32), np.zeros((0, 3), np.float32))
+    assert r["t"].numel() == 0
+    # parameters out of range
+    leaf = scene.info()["leaf_size"]
+    for kw in (dict(h=0.99 * leaf), dict(max_steps=(1 << 20) + 1)):
+        with pytest.raises(pcrl.PcrlError):
+            pcrl.sdf_intersect(scene, o, d, **kw)
+    # an empty cloud: every ray misses
+    e = np.zeros((0, 3), np.float32)
+    es = pcrl.build_voxels(e, e, np.zeros(0, np.uint32), (0.5,), 0.1)
+    r = pcrl.sdf_intersect(es, o, d)
+    assert torch.isinf(r["t"]).all()
+    # dynamic points are not part of the surface
+    ids = torch.arange(s.n_points, s.n_points + 4, dtype=torch.int32)
+    scene.update_points(ids, s.xyz[:4], s.normal[:4], s.label[:4])
+    with pytest.raises(pcrl.PcrlError):
+        pcrl.sdf_intersect(scene, o, d)
