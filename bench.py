@@ -414,6 +414,8 @@ def main():
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--no-stats", action="store_true")
     ap.add_argument("--no-refine", action="store_true", help="skip the path-refinement leg (run after the timed steps)")
+    ap.add_argument("--no-sdf", action="store_true",
+                    help="skip the implicit-surface intersection leg (run after the timed steps)")
     args = ap.parse_args()
     if args.gpus != 1 or int(os.environ.get("WORLD_SIZE", "1")) != 1:
         print("bench.py measures one GPU only: the library has no multi-GPU path (the rays of a launch "
@@ -553,6 +555,51 @@ def main():
         launch.release()
         scene.release()
 
+    sdf = None
+    if not args.no_sdf:
+        # first intersections of the step's launch directions from the first TX with
+        # the implicit surface of Eq. 1 (Section 2.2.1): outside the timed step
+        scene = pcrl.build_voxels(xyz, nrm, lab, s.levels, r_s, t_eps=t_eps, device=dev)
+        n_sdf = s.n_rays
+        dirs = pcrl.launch_directions(n_sdf, device=dev)
+        org = torch.as_tensor(np.asarray(s.tx[:1], np.float32), device=dev).expand(n_sdf, 3).contiguous()
+        st = pcrl.sdf_intersect(scene, org, dirs, with_stats=True)
+        stream = torch.cuda.current_stream(dev)
+        ev0, ev1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+        reps = 5
+        torch.cuda.synchronize()
+        ev0.record(stream)
+        for _ in range(reps):
+            res = pcrl.sdf_intersect(scene, org, dirs)
+        ev1.record(stream)
+        torch.cuda.synchronize()
+        s_ms = ev0.elapsed_time(ev1) / reps
+        hit = float(torch.isfinite(res["t"]).float().mean())
+        sdf = {"rays": n_sdf, "ms": round(s_ms, 3), "rays_per_s": round(n_sdf / (s_ms * 1e-3), 1),
+               "hit_fraction": round(hit, 4), "evals_per_ray": round(st["evals"] / n_sdf, 2),
+               "entries_per_ray": round(st["reads"] / n_sdf, 1),
+               "entry_gbs": round(32.0 * st["reads"] / (s_ms * 1e-3) / 1e9, 1),
+               "h_leaf": 0.95, "eps_leaf": 1e-3, "max_steps": 64, "kernel": "k_sdf"}
+        if not args.no_cpu_baseline:
+            import oracle
+            inf_ = scene.info()
+            d_np = dirs.cpu().numpy()
+            rng = np.random.default_rng(0)
+            n_cpu = 64
+            while True:
+                pick = rng.choice(n_sdf, n_cpu, replace=False)
+                t1 = time.perf_counter()
+                oracle.sdf_intersect(s.xyz, s.normal, np.asarray(inf_["origin"], np.float32), inf_["leaf_size"],
+                                     np.repeat(np.asarray(s.tx[:1], np.float32), n_cpu, axis=0), d_np[pick])
+                dt = time.perf_counter() - t1
+                if dt > 2.0 or n_cpu >= 8192:
+                    break
+                n_cpu *= 4
+            sdf["cpu_baseline"] = {"value": round(n_cpu / dt, 1), "unit": "rays/s", "cores": oracle.default_threads(),
+                                   "kind": "oracle", "sample": f"{n_cpu} of the {n_sdf} directions"}
+        log(f"[bench] sdf: {sdf}")
+        scene.release()
+
     cpu = None
     if not args.no_cpu_baseline:
         log("[bench] timing the CPU oracle on a ray sample")
@@ -584,6 +631,7 @@ def main():
         "roofline": roof,
         "cpu_baseline": cpu,
         "refine": refine,
+        "sdf": sdf,
     }
     if algo is not None:
         out["trace_stats"] = {k: algo[k] for k in ("segments", "dda_steps", "leaves_visited", "node_lookups",

@@ -26,12 +26,14 @@
 namespace pcrl {
 
 constexpr int SDF_BLOCK = 256;
+constexpr int64_t SDF_ORDER_MIN = 65536;  // rays from which a call sorts them into a coherent order
 
 struct SdfArgs {
     SceneView v;
     const float* o;        // [n][3]
     const float* d;        // [n][3]
     const float* tr;       // [n][2] (t_lo, t_hi), or null for (0, inf)
+    const uint32_t* order; // null, or lane -> ray (a coherent order of the rays)
     uint32_t n;
     int32_t max_steps;
     float h2;              // h^2
@@ -47,63 +49,99 @@ struct SdfArgs {
     unsigned long long* stats;  // null, or [2]: evaluations of f, entries read
 };
 
-// Entries of leaf `cell` (a count of 0 when it is empty).
-template <int NL>
-__device__ __forceinline__ uint2 leaf_entries(const SceneView& v, const int cell[3]) {
-    uint32_t node = 0;
-    int skip0 = 0;
-    if (descend<false, NL - 1>(v, cell, node, skip0, nullptr) != NL) return make_uint2(0u, 0u);
-    return v.leaf[node];
-}
-
 __device__ __forceinline__ bool in_leaf(const SceneView& v, const float4& P, const int cell[3]) {
     return (int)floorf((P.x - v.org[0]) * v.inv_h) == cell[0] && (int)floorf((P.y - v.org[1]) * v.inv_h) == cell[1] &&
            (int)floorf((P.z - v.org[2]) * v.inv_h) == cell[2];
 }
 
+// Accumulate the weighted sums of f(x) over the entries [e0, e1) of `cell`
+// that lie within h of x and whose centre lies in that leaf.  Four entries'
+// positions are loaded before any is used (more loads in flight per lane).
+__device__ __forceinline__ void sdf_accumulate(const SceneView& v, const float x[3], float h2, const int cell[3],
+                                               uint32_t e0, uint32_t e1, float& sw, float sp[3], float sn[3]) {
+    uint32_t e = e0;
+    for (; e + 4 <= e1; e += 4) {
+        float4 P[4];
+#pragma unroll
+        for (int k = 0; k < 4; ++k) P[k] = v.spos[e + k];
+#pragma unroll
+        for (int k = 0; k < 4; ++k) {
+            const float ex = P[k].x - x[0], ey = P[k].y - x[1], ez = P[k].z - x[2];
+            const float d2 = ex * ex + ey * ey + ez * ez;
+            if (!(d2 < h2) || !in_leaf(v, P[k], cell)) continue;
+            const float4 N = v.snrm[e + k];
+            float w = 1.0f - d2 / h2;
+            w *= w;
+            w *= w;
+            sw += w;
+            sp[0] += w * ex;
+            sp[1] += w * ey;
+            sp[2] += w * ez;
+            sn[0] += w * N.x;
+            sn[1] += w * N.y;
+            sn[2] += w * N.z;
+        }
+    }
+    for (; e < e1; ++e) {
+        const float4 P = v.spos[e];
+        const float ex = P.x - x[0], ey = P.y - x[1], ez = P.z - x[2];
+        const float d2 = ex * ex + ey * ey + ez * ez;
+        if (!(d2 < h2) || !in_leaf(v, P, cell)) continue;
+        const float4 N = v.snrm[e];
+        float w = 1.0f - d2 / h2;
+        w *= w;
+        w *= w;
+        sw += w;
+        sp[0] += w * ex;
+        sp[1] += w * ey;
+        sp[2] += w * ez;
+        sn[0] += w * N.x;
+        sn[1] += w * N.y;
+        sn[2] += w * N.z;
+    }
+}
+
 // f(x) of Eq. 1 and the unit normal n(x); false where f is undefined.  The
-// offset p(x) - x is accumulated relative to x.
+// offset p(x) - x is accumulated relative to x.  The 27 leaves are looked up
+// with the DDA's own cell lookup (the cell table where the scene has one),
+// whose descent is cached per parent cell: neighbouring leaves mostly share
+// their parent.
 template <int NL>
 __device__ __forceinline__ bool sdf_eval(const SceneView& v, const float x[3], float h2, float& f, float n[3],
                                          uint32_t& reads) {
     int lc[3];
 #pragma unroll
     for (int a = 0; a < 3; ++a) lc[a] = (int)floorf((x[a] - v.org[a]) * v.inv_h);
-    float sw = 0.f, sp0 = 0.f, sp1 = 0.f, sp2 = 0.f, sn0 = 0.f, sn1 = 0.f, sn2 = 0.f;
-    for (int dz = -1; dz <= 1; ++dz)
-        for (int dy = -1; dy <= 1; ++dy)
-            for (int dx = -1; dx <= 1; ++dx) {
-                const int cell[3] = {lc[0] + dx, lc[1] + dy, lc[2] + dz};
-                if (cell[0] < 0 || cell[1] < 0 || cell[2] < 0 || cell[0] >= v.dim[0] || cell[1] >= v.dim[1] ||
-                    cell[2] >= v.dim[2])
-                    continue;
-                const uint2 r = leaf_entries<NL>(v, cell);
-                reads += r.y;
-                for (uint32_t e = r.x; e < r.x + r.y; ++e) {
-                    const float4 P = v.spos[e];
-                    const float ex = P.x - x[0], ey = P.y - x[1], ez = P.z - x[2];
-                    const float d2 = ex * ex + ey * ey + ez * ez;
-                    if (!(d2 < h2) || !in_leaf(v, P, cell)) continue;
-                    const float4 N = v.snrm[e];
-                    float w = 1.0f - d2 / h2;
-                    w *= w;
-                    w *= w;
-                    sw += w;
-                    sp0 += w * ex;
-                    sp1 += w * ey;
-                    sp2 += w * ez;
-                    sn0 += w * N.x;
-                    sn1 += w * N.y;
-                    sn2 += w * N.z;
-                }
-            }
-    const float ln = sqrtf(sn0 * sn0 + sn1 * sn1 + sn2 * sn2);
+    float sw = 0.f, sp[3] = {0.f, 0.f, 0.f}, sn[3] = {0.f, 0.f, 0.f};
+    Seg N;
+    N.cq[0] = N.cq[1] = N.cq[2] = -1;
+    N.cres = 0;
+    N.cskip0 = 1;
+    N.cnode = 0;
+    N.oct_shift = 0;
+    // one rolled loop over the 27 leaves (unrolled, the lookups would multiply the registers)
+#pragma unroll 1
+    for (int q = 0; q < 27; ++q) {
+        N.c[0] = lc[0] + q % 3 - 1;
+        N.c[1] = lc[1] + (q / 3) % 3 - 1;
+        N.c[2] = lc[2] + q / 9 - 1;
+        if (N.c[0] < 0 || N.c[1] < 0 || N.c[2] < 0 || N.c[0] >= v.dim[0] || N.c[1] >= v.dim[1] ||
+            N.c[2] >= v.dim[2])
+            continue;
+        DdaCell k;
+        dda_cell_reset(k);
+        dda_locate<false, NL>(v, N, k, nullptr);
+        if (k.lvl != NL || k.range.y == 0u) continue;
+        reads += k.range.y;
+        sdf_accumulate(v, x, h2, N.c, k.range.x, k.range.x + k.range.y, sw, sp, sn);
+    }
+    const float ln = sqrtf(sn[0] * sn[0] + sn[1] * sn[1] + sn[2] * sn[2]);
     if (!(sw > 0.f) || !(ln > 0.f)) return false;
     const float inv = 1.0f / ln;
-    n[0] = sn0 * inv;
-    n[1] = sn1 * inv;
-    n[2] = sn2 * inv;
-    f = -(sp0 * n[0] + sp1 * n[1] + sp2 * n[2]) / sw;
+    n[0] = sn[0] * inv;
+    n[1] = sn[1] * inv;
+    n[2] = sn[2] * inv;
+    f = -(sp[0] * n[0] + sp[1] * n[1] + sp[2] * n[2]) / sw;
     return true;
 }
 
@@ -128,10 +166,41 @@ __device__ __forceinline__ bool own_box_centre(const SceneView& v, uint2 r, cons
     return true;
 }
 
+// 8 bits spread to the even bits of 16.
+__device__ __forceinline__ uint32_t spread_bits8(uint32_t x) {
+    x &= 0xFFu;
+    x = (x | (x << 4)) & 0x0F0Fu;
+    x = (x | (x << 2)) & 0x3333u;
+    x = (x | (x << 1)) & 0x5555u;
+    return x;
+}
+
+// Coherence key of a ray: Morton code of its origin on a 16^3 grid over the
+// scene (12 bits) above the Morton code of its direction's cell on a 256 x 256
+// octahedral grid (16 bits).  Sorting by it puts rays that start close
+// together in close directions into the same waves, which then march the same
+// leaves (shared cache lines, similar step counts).
+__global__ void k_sdf_keys(const float* o, const float* d, uint32_t n, float3 lo, float3 scale, uint64_t* keys,
+                           uint32_t* idx) {
+    const uint32_t j = blockIdx.x * blockDim.x + threadIdx.x;
+    if (j >= n) return;
+    const float x = d[3 * (size_t)j], y = d[3 * (size_t)j + 1], z = d[3 * (size_t)j + 2];
+    float u = 0.f, w = 0.f;
+    octahedral(x, y, z, u, w);  // the map only needs the direction's signs and ratios
+    const uint32_t dk = spread_bits8(cell_of(u, 256)) | (spread_bits8(cell_of(w, 256)) << 1);
+    const uint32_t cx = (uint32_t)fminf(fmaxf((o[3 * (size_t)j] - lo.x) * scale.x, 0.f), 15.f);
+    const uint32_t cy = (uint32_t)fminf(fmaxf((o[3 * (size_t)j + 1] - lo.y) * scale.y, 0.f), 15.f);
+    const uint32_t cz = (uint32_t)fminf(fmaxf((o[3 * (size_t)j + 2] - lo.z) * scale.z, 0.f), 15.f);
+    const uint32_t m = spread_bits4x3(cx) | (spread_bits4x3(cy) << 1) | (spread_bits4x3(cz) << 2);
+    keys[j] = ((uint64_t)m << 16) | dk;
+    idx[j] = j;
+}
+
 template <int NL>
 __global__ __launch_bounds__(SDF_BLOCK) void k_sdf(SdfArgs a) {
-    const uint32_t i = blockIdx.x * SDF_BLOCK + threadIdx.x;
-    if (i >= a.n) return;
+    const uint32_t lane_ray = blockIdx.x * SDF_BLOCK + threadIdx.x;
+    if (lane_ray >= a.n) return;
+    const uint32_t i = a.order ? a.order[lane_ray] : lane_ray;
     const SceneView& v = a.v;
     float o[3] = {a.o[3 * i], a.o[3 * i + 1], a.o[3 * i + 2]};
     float d[3] = {a.d[3 * i], a.d[3 * i + 1], a.d[3 * i + 2]};
@@ -287,13 +356,41 @@ extern "C" int sdf_intersect(const PcrlScene* scene, const float* o, const float
     a.cell = leaf_cell;
     a.stats = (unsigned long long*)P.stats;
     hipStream_t s = (hipStream_t)stream;
+    DevBufs T;
+    T.stream = s;
+    // large batches run in a coherent order (the outputs keep the callers')
+    if (n_rays >= SDF_ORDER_MIN && !a.empty) {
+        uint64_t* keys = nullptr;
+        uint32_t* idx = nullptr;
+        int rc = T.alloc(&keys, (size_t)n_rays);
+        if (!rc) rc = T.alloc(&idx, (size_t)n_rays);
+        if (rc) {
+            T.release();
+            return rc;
+        }
+        const SceneView& v = scene->view;
+        const float3 lo = make_float3(v.org[0], v.org[1], v.org[2]);
+        const float3 sc = make_float3(16.f / (v.hi[0] - v.org[0]), 16.f / (v.hi[1] - v.org[1]),
+                                      16.f / (v.hi[2] - v.org[2]));
+        hipLaunchKernelGGL(k_sdf_keys, dim3((unsigned)((n_rays + 255) / 256)), dim3(256), 0, s, o, d,
+                           (uint32_t)n_rays, lo, sc, keys, idx);
+        rc = hipGetLastError() == hipSuccess ? radix_sort_u64_bits(keys, idx, n_rays, 0, 28, s) : PCRL_EHIP;
+        if (rc) {
+            T.release();
+            set_error("sdf_intersect: ordering the rays failed");
+            return rc;
+        }
+        a.order = idx;
+    }
     switch (scene->view.nlev) {
     case 1: launch_sdf_nl<1>(a, s); break;
     case 2: launch_sdf_nl<2>(a, s); break;
     case 3: launch_sdf_nl<3>(a, s); break;
     default: launch_sdf_nl<4>(a, s); break;
     }
-    if (hipGetLastError() != hipSuccess) {
+    const bool ok = hipGetLastError() == hipSuccess;
+    T.release();  // stream-ordered: the buffers stay valid for the kernel
+    if (!ok) {
         set_error("sdf_intersect: kernel launch failed");
         return PCRL_EHIP;
     }
