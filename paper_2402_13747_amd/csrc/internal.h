@@ -11,6 +11,7 @@
 #include <cstdarg>
 #include <cstdint>
 #include <memory>
+#include <mutex>
 #include <string>
 #include <vector>
 
@@ -262,6 +263,12 @@ struct PcrlScene {
     uint32_t max_label = 0;
     bool compact = false;             // PCRL_VOXEL_COMPACT: no dense cell tables (base and overlays)
     std::shared_ptr<pcrl::Overlay> overlay;  // current epoch of dynamic points (may be null)
+    // own-point index of the implicit-surface intersection (sdf_intersect), built
+    // on first use: every point once, in the leaf holding its centre, in leaf order
+    std::mutex own_mu;
+    uint32_t* own_scan = nullptr;     // [n_entries + 1] own entries before each entry
+    float4* own_pos = nullptr;        // [n_points] positions (w: point id bits)
+    float4* own_nrm = nullptr;        // [n_points] unit normals (w: label bits)
 };
 
 struct PcrlLaunch {

@@ -34,6 +34,9 @@ struct SdfArgs {
     const float* d;        // [n][3]
     const float* tr;       // [n][2] (t_lo, t_hi), or null for (0, inf)
     const uint32_t* order; // null, or lane -> ray (a coherent order of the rays)
+    const uint32_t* oscan; // [n_entries + 1] own entries before each entry of the hierarchy
+    const float4* opos;    // own entries (each point once, in the leaf of its centre), leaf order
+    const float4* onrm;
     uint32_t n;
     int32_t max_steps;
     float h2;              // h^2
@@ -54,22 +57,23 @@ __device__ __forceinline__ bool in_leaf(const SceneView& v, const float4& P, con
            (int)floorf((P.z - v.org[2]) * v.inv_h) == cell[2];
 }
 
-// Accumulate the weighted sums of f(x) over the entries [e0, e1) of `cell`
-// that lie within h of x and whose centre lies in that leaf.  Four entries'
-// positions are loaded before any is used (more loads in flight per lane).
-__device__ __forceinline__ void sdf_accumulate(const SceneView& v, const float x[3], float h2, const int cell[3],
-                                               uint32_t e0, uint32_t e1, float& sw, float sp[3], float sn[3]) {
+// Accumulate the weighted sums of f(x) over the own entries [e0, e1) that
+// lie within h of x.  Four entries' positions are loaded before any is used
+// (more loads in flight per lane).
+__device__ __forceinline__ void sdf_accumulate(const SdfArgs& a, const float x[3], uint32_t e0, uint32_t e1,
+                                               float& sw, float sp[3], float sn[3]) {
+    const float h2 = a.h2;
     uint32_t e = e0;
-    for (; e + 4 <= e1; e += 4) {
+    for (; e < e1; e += 4) {
         float4 P[4];
 #pragma unroll
-        for (int k = 0; k < 4; ++k) P[k] = v.spos[e + k];
+        for (int k = 0; k < 4; ++k) P[k] = a.opos[min(e + k, e1 - 1)];
 #pragma unroll
         for (int k = 0; k < 4; ++k) {
             const float ex = P[k].x - x[0], ey = P[k].y - x[1], ez = P[k].z - x[2];
             const float d2 = ex * ex + ey * ey + ez * ez;
-            if (!(d2 < h2) || !in_leaf(v, P[k], cell)) continue;
-            const float4 N = v.snrm[e + k];
+            if (e + k >= e1 || !(d2 < h2)) continue;
+            const float4 N = a.onrm[e + k];
             float w = 1.0f - d2 / h2;
             w *= w;
             w *= w;
@@ -82,23 +86,6 @@ __device__ __forceinline__ void sdf_accumulate(const SceneView& v, const float x
             sn[2] += w * N.z;
         }
     }
-    for (; e < e1; ++e) {
-        const float4 P = v.spos[e];
-        const float ex = P.x - x[0], ey = P.y - x[1], ez = P.z - x[2];
-        const float d2 = ex * ex + ey * ey + ez * ez;
-        if (!(d2 < h2) || !in_leaf(v, P, cell)) continue;
-        const float4 N = v.snrm[e];
-        float w = 1.0f - d2 / h2;
-        w *= w;
-        w *= w;
-        sw += w;
-        sp[0] += w * ex;
-        sp[1] += w * ey;
-        sp[2] += w * ez;
-        sn[0] += w * N.x;
-        sn[1] += w * N.y;
-        sn[2] += w * N.z;
-    }
 }
 
 // f(x) of Eq. 1 and the unit normal n(x); false where f is undefined.  The
@@ -107,8 +94,8 @@ __device__ __forceinline__ void sdf_accumulate(const SceneView& v, const float x
 // whose descent is cached per parent cell: neighbouring leaves mostly share
 // their parent.
 template <int NL>
-__device__ __forceinline__ bool sdf_eval(const SceneView& v, const float x[3], float h2, float& f, float n[3],
-                                         uint32_t& reads) {
+__device__ __forceinline__ bool sdf_eval(const SdfArgs& a, const float x[3], float& f, float n[3], uint32_t& reads) {
+    const SceneView& v = a.v;
     int lc[3];
 #pragma unroll
     for (int a = 0; a < 3; ++a) lc[a] = (int)floorf((x[a] - v.org[a]) * v.inv_h);
@@ -132,8 +119,9 @@ __device__ __forceinline__ bool sdf_eval(const SceneView& v, const float x[3], f
         dda_cell_reset(k);
         dda_locate<false, NL>(v, N, k, nullptr);
         if (k.lvl != NL || k.range.y == 0u) continue;
-        reads += k.range.y;
-        sdf_accumulate(v, x, h2, N.c, k.range.x, k.range.x + k.range.y, sw, sp, sn);
+        const uint32_t e0 = a.oscan[k.range.x], e1 = a.oscan[k.range.x + k.range.y];
+        reads += e1 - e0;
+        sdf_accumulate(a, x, e0, e1, sw, sp, sn);
     }
     const float ln = sqrtf(sn[0] * sn[0] + sn[1] * sn[1] + sn[2] * sn[2]);
     if (!(sw > 0.f) || !(ln > 0.f)) return false;
@@ -145,13 +133,12 @@ __device__ __forceinline__ bool sdf_eval(const SceneView& v, const float x[3], f
     return true;
 }
 
-// Centre of the box around the entries of range r whose centre lies in leaf
-// `cell`; false when there is none.
-__device__ __forceinline__ bool own_box_centre(const SceneView& v, uint2 r, const int cell[3], float c[3]) {
+// Centre of the box around the own entries [e0, e1) of a leaf; false when
+// there is none.
+__device__ __forceinline__ bool own_box_centre(const SdfArgs& a, uint32_t e0, uint32_t e1, float c[3]) {
     float lo0 = INFINITY, lo1 = INFINITY, lo2 = INFINITY, hi0 = -INFINITY, hi1 = -INFINITY, hi2 = -INFINITY;
-    for (uint32_t e = r.x; e < r.x + r.y; ++e) {
-        const float4 P = v.spos[e];
-        if (!in_leaf(v, P, cell)) continue;
+    for (uint32_t e = e0; e < e1; ++e) {
+        const float4 P = a.opos[e];
         lo0 = fminf(lo0, P.x);
         lo1 = fminf(lo1, P.y);
         lo2 = fminf(lo2, P.z);
@@ -159,11 +146,48 @@ __device__ __forceinline__ bool own_box_centre(const SceneView& v, uint2 r, cons
         hi1 = fmaxf(hi1, P.y);
         hi2 = fmaxf(hi2, P.z);
     }
-    if (!(lo0 <= hi0)) return false;
+    if (!(e0 < e1)) return false;
     c[0] = 0.5f * (lo0 + hi0);
     c[1] = 0.5f * (lo1 + hi1);
     c[2] = 0.5f * (lo2 + hi2);
     return true;
+}
+
+// 1 for each entry of the hierarchy listed in the leaf that holds its point's
+// centre (the cell taken in FP32 as everywhere else), else 0.
+template <int NL>
+__global__ void k_own_flags(SceneView v, uint32_t m, uint32_t* flag) {
+    const uint32_t e = blockIdx.x * blockDim.x + threadIdx.x;
+    if (e >= m) return;
+    const float4 P = v.spos[e];
+    Seg N;
+    N.c[0] = (int)floorf((P.x - v.org[0]) * v.inv_h);
+    N.c[1] = (int)floorf((P.y - v.org[1]) * v.inv_h);
+    N.c[2] = (int)floorf((P.z - v.org[2]) * v.inv_h);
+    uint32_t own = 0u;
+    if (N.c[0] >= 0 && N.c[1] >= 0 && N.c[2] >= 0 && N.c[0] < v.dim[0] && N.c[1] < v.dim[1] && N.c[2] < v.dim[2]) {
+        N.cq[0] = N.cq[1] = N.cq[2] = -1;
+        N.cres = 0;
+        N.cskip0 = 1;
+        N.cnode = 0;
+        N.oct_shift = 0;
+        DdaCell k;
+        dda_cell_reset(k);
+        dda_locate<false, NL>(v, N, k, nullptr);
+        own = (k.lvl == NL && k.range.x <= e && e - k.range.x < k.range.y) ? 1u : 0u;
+    }
+    flag[e] = own;
+}
+
+// Copy the own entries to their compacted slots.
+__global__ void k_own_scatter(const float4* spos, const float4* snrm, const uint32_t* scan, uint32_t m,
+                              uint32_t cap, float4* opos, float4* onrm) {
+    const uint32_t e = blockIdx.x * blockDim.x + threadIdx.x;
+    if (e >= m) return;
+    const uint32_t j = scan[e];
+    if (scan[e + 1] == j || j >= cap) return;
+    opos[j] = spos[e];
+    onrm[j] = snrm[e];
 }
 
 // 8 bits spread to the even bits of 16.
@@ -237,8 +261,13 @@ __global__ __launch_bounds__(SDF_BLOCK) void k_sdf(SdfArgs a) {
         dda_locate<false, NL>(v, S, k, nullptr);
         const bool at_leaf = k.lvl == NL;
         float c[3];
-        if (at_leaf && t_in <= t_hi && own_box_centre(v, k.range, S.c, c)) {
-            reads += k.range.y;
+        uint32_t o0 = 0u, o1 = 0u;
+        if (at_leaf && t_in <= t_hi) {
+            o0 = a.oscan[k.range.x];
+            o1 = a.oscan[k.range.x + k.range.y];
+        }
+        if (at_leaf && t_in <= t_hi && own_box_centre(a, o0, o1, c)) {
+            reads += o1 - o0;
             const float tc = (c[0] - o[0]) * d[0] + (c[1] - o[1]) * d[1] + (c[2] - o[2]) * d[2];
             float t = fmaxf(tc - a.half_diam, t_lo);
             const float tb = fminf(tc + a.half_diam, t_hi);
@@ -250,7 +279,7 @@ __global__ __launch_bounds__(SDF_BLOCK) void k_sdf(SdfArgs a) {
                 const float x[3] = {o[0] + t * d[0], o[1] + t * d[1], o[2] + t * d[2]};
                 float f, n[3];
                 ++evals;
-                if (!sdf_eval<NL>(v, x, a.h2, f, n, reads)) {
+                if (!sdf_eval<NL>(a, x, f, n, reads)) {
                     prev = false;
                     t += a.half_h;
                     continue;
@@ -301,6 +330,53 @@ template <int NL>
 static void launch_sdf_nl(const SdfArgs& a, hipStream_t s) {
     const unsigned grid = (a.n + SDF_BLOCK - 1) / SDF_BLOCK;
     hipLaunchKernelGGL((k_sdf<NL>), dim3(grid), dim3(SDF_BLOCK), 0, s, a);
+}
+
+template <int NL>
+static void launch_own_flags(const SceneView& v, uint32_t m, uint32_t* flag, hipStream_t s) {
+    hipLaunchKernelGGL((k_own_flags<NL>), dim3((m + 255) / 256), dim3(256), 0, s, v, m, flag);
+}
+
+// The scene's own-point index, built on the first call (under the scene's
+// lock) and kept with the scene.  The build waits for its stream, so calls on
+// any stream find the index complete.
+static int own_index(PcrlScene* S, hipStream_t s) {
+    std::lock_guard<std::mutex> lock(S->own_mu);
+    if (S->own_scan) return PCRL_OK;
+    const int64_t m = S->info.n_entries, np = S->info.n_points;
+    uint32_t* scan = nullptr;
+    float4 *pos = nullptr, *nrm = nullptr;
+    int rc = dalloc((void**)&scan, (size_t)(m + 1) * sizeof(uint32_t), s);
+    if (!rc) rc = dalloc((void**)&pos, (size_t)(np > 0 ? np : 1) * sizeof(float4), s);
+    if (!rc) rc = dalloc((void**)&nrm, (size_t)(np > 0 ? np : 1) * sizeof(float4), s);
+    if (!rc) {
+        switch (S->view.nlev) {
+        case 1: launch_own_flags<1>(S->view, (uint32_t)m, scan, s); break;
+        case 2: launch_own_flags<2>(S->view, (uint32_t)m, scan, s); break;
+        case 3: launch_own_flags<3>(S->view, (uint32_t)m, scan, s); break;
+        default: launch_own_flags<4>(S->view, (uint32_t)m, scan, s); break;
+        }
+        rc = hipGetLastError() == hipSuccess ? scan_u32(scan, scan, m, scan + m, s) : PCRL_EHIP;
+    }
+    if (!rc) {
+        hipLaunchKernelGGL(k_own_scatter, dim3((unsigned)((m + 255) / 256)), dim3(256), 0, s, S->view.spos,
+                           S->view.snrm, scan, (uint32_t)m, (uint32_t)np, pos, nrm);
+        rc = hipGetLastError() == hipSuccess && hipStreamSynchronize(s) == hipSuccess ? PCRL_OK : PCRL_EHIP;
+    }
+    if (rc) {
+        dfree(scan, s);
+        dfree(pos, s);
+        dfree(nrm, s);
+        if (rc == PCRL_EHIP) set_error("sdf_intersect: building the own-point index failed");
+        return rc;
+    }
+    S->bufs.ptrs.push_back(scan);
+    S->bufs.ptrs.push_back(pos);
+    S->bufs.ptrs.push_back(nrm);
+    S->own_scan = scan;
+    S->own_pos = pos;
+    S->own_nrm = nrm;
+    return PCRL_OK;
 }
 
 }  // namespace pcrl
@@ -356,6 +432,14 @@ extern "C" int sdf_intersect(const PcrlScene* scene, const float* o, const float
     a.cell = leaf_cell;
     a.stats = (unsigned long long*)P.stats;
     hipStream_t s = (hipStream_t)stream;
+    if (!a.empty) {
+        // the index is a cache of the scene's data: building it does not change the scene
+        const int rc = own_index(const_cast<PcrlScene*>(scene), s);
+        if (rc) return rc;
+        a.oscan = scene->own_scan;
+        a.opos = scene->own_pos;
+        a.onrm = scene->own_nrm;
+    }
     DevBufs T;
     T.stream = s;
     // large batches run in a coherent order (the outputs keep the callers')
