@@ -422,9 +422,13 @@ typedef struct {
  *   normal    [n_rays,3] n at the intersection (0 if none)
  *   leaf_cell [n_rays,3] int32 leaf cell whose segment held it (-1 if none), or NULL
  * A ray with a zero or non-finite direction or origin, or t_lo > t_hi, has
- * no intersection.  Asynchronous on `stream`.  PCRL_EINVAL on NULL arrays,
- * out-of-range parameters, or a scene holding dynamic points (update_points):
- * the surface is defined over the static points. */
+ * no intersection.  Asynchronous on `stream`, except that the first call on
+ * a scene builds and keeps with the scene an index of each point in the leaf
+ * of its centre (16 B per point twice, 4 B per entry) and waits for it.  Calls
+ * of 65536 rays or more sort the rays by origin and direction first (outputs
+ * stay in the caller's order).  PCRL_EINVAL on NULL arrays, out-of-range
+ * parameters, or a scene holding dynamic points (update_points): the surface
+ * is defined over the static points. */
 int sdf_intersect(const PcrlScene* scene, const float* o, const float* d, const float* t_range, int64_t n_rays,
                   const PcrlSdfParams* params, float* t, float* point, float* normal, int32_t* leaf_cell,
                   pcrl_stream_t stream);
