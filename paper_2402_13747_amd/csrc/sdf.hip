@@ -40,6 +40,7 @@ struct SdfArgs {
     uint32_t n;
     int32_t max_steps;
     float h2;              // h^2
+    float hl2;             // (h / leaf edge + 1e-3)^2: leaves farther than this from x hold no neighbour
     float half_h;          // step over an undefined sample
     float eps;
     float half_diam;       // half the segment length (half a leaf diagonal)
@@ -97,8 +98,13 @@ template <int NL>
 __device__ __forceinline__ bool sdf_eval(const SdfArgs& a, const float x[3], float& f, float n[3], uint32_t& reads) {
     const SceneView& v = a.v;
     int lc[3];
+    float fr[3];  // position of x inside its leaf, in leaf edges
 #pragma unroll
-    for (int a = 0; a < 3; ++a) lc[a] = (int)floorf((x[a] - v.org[a]) * v.inv_h);
+    for (int k = 0; k < 3; ++k) {
+        const float u = (x[k] - v.org[k]) * v.inv_h;
+        lc[k] = (int)floorf(u);
+        fr[k] = u - (float)lc[k];
+    }
     float sw = 0.f, sp[3] = {0.f, 0.f, 0.f}, sn[3] = {0.f, 0.f, 0.f};
     Seg N;
     N.cq[0] = N.cq[1] = N.cq[2] = -1;
@@ -109,9 +115,15 @@ __device__ __forceinline__ bool sdf_eval(const SdfArgs& a, const float x[3], flo
     // one rolled loop over the 27 leaves (unrolled, the lookups would multiply the registers)
 #pragma unroll 1
     for (int q = 0; q < 27; ++q) {
-        N.c[0] = lc[0] + q % 3 - 1;
-        N.c[1] = lc[1] + (q / 3) % 3 - 1;
-        N.c[2] = lc[2] + q / 9 - 1;
+        const int dx = q % 3 - 1, dy = (q / 3) % 3 - 1, dz = q / 9 - 1;
+        // distance (in leaf edges) from x to the neighbour leaf: skip leaves beyond h
+        const float gx = dx < 0 ? fr[0] : (dx > 0 ? 1.f - fr[0] : 0.f);
+        const float gy = dy < 0 ? fr[1] : (dy > 0 ? 1.f - fr[1] : 0.f);
+        const float gz = dz < 0 ? fr[2] : (dz > 0 ? 1.f - fr[2] : 0.f);
+        if (gx * gx + gy * gy + gz * gz >= a.hl2) continue;
+        N.c[0] = lc[0] + dx;
+        N.c[1] = lc[1] + dy;
+        N.c[2] = lc[2] + dz;
         if (N.c[0] < 0 || N.c[1] < 0 || N.c[2] < 0 || N.c[0] >= v.dim[0] || N.c[1] >= v.dim[1] ||
             N.c[2] >= v.dim[2])
             continue;
@@ -420,6 +432,7 @@ extern "C" int sdf_intersect(const PcrlScene* scene, const float* o, const float
     a.n = (uint32_t)n_rays;
     a.max_steps = max_steps;
     a.h2 = h * h;
+    a.hl2 = (h / leaf + 1e-3f) * (h / leaf + 1e-3f);
     a.half_h = 0.5f * h;
     a.eps = eps;
     const float diag = sqrtf(3.0f) * leaf;

@@ -17,7 +17,8 @@ are perturbed by a few units of rounding, and max_steps by one):
     the same zero any of them may be named: the cell is not unique).
 Unstable rays are excused (their count is bounded).  Scenes: the empty box
 room (rays from the TX), random tilted planes and boxes with noise, the
-furnished room at full size (a sample of rays), plus edge cases.
+furnished room and the street canyon at full size (samples of rays), plus
+edge cases.
 """
 import math
 
@@ -166,6 +167,55 @@ def test_furnished_room_full_size_sampled(env):
     sel = torch.from_numpy(rng.choice(1_000_000, 400, replace=False)).cuda()
     assert torch.equal(r["t"][sel].cpu(), pcrl.sdf_intersect(scene, oo[sel], dd[sel])["t"].cpu())
     assert r["evals"] > 1_000_000 and r["reads"] > r["evals"]
+
+
+def test_street_canyon_full_size_sampled(env):
+    """Three-level hierarchy over 20 M points (no dense cell table): 200
+    directions from the four TXs against the oracle."""
+    _, _, oracle = env
+    s = scenes.street_canyon()
+    scene = _build(env, s)
+    rng = np.random.default_rng(9)
+    d = oracle.fibonacci(s.n_rays)[rng.choice(s.n_rays, 200, replace=False)]
+    o = np.repeat(s.tx.astype(np.float32), 50, axis=0)
+    fin, _ = _compare(env, s, scene, o, d)
+    assert fin.mean() > 0.4
+
+
+def test_concurrent_first_calls(env):
+    """The own-point index is built once, under the scene's lock, when two
+    threads on two streams make the first calls on a fresh scene together;
+    both get the single-call results."""
+    import threading
+    torch, pcrl, oracle = env
+    s = scenes.random_scene(5, extent=2.0, h=0.05, levels=(0.4, 0.2), pos_sigma=0.002, tilt_sigma=0.03)
+    rng = np.random.default_rng(13)
+    n = 70_000  # above the coherent-order threshold
+    o = torch.from_numpy(rng.uniform(0.0, 2.0, size=(n, 3)).astype(np.float32)).cuda()
+    d = torch.from_numpy(rng.normal(size=(n, 3)).astype(np.float32)).cuda()
+    ref = pcrl.sdf_intersect(_build(env, s), o, d)["t"].cpu()
+    scene = _build(env, s)
+    out, errs = [None, None], []
+    streams = [torch.cuda.Stream(), torch.cuda.Stream()]
+    barrier = threading.Barrier(2)
+
+    def work(i):
+        try:
+            with torch.cuda.stream(streams[i]):
+                barrier.wait()
+                r = pcrl.sdf_intersect(scene, o, d)
+                streams[i].synchronize()
+                out[i] = r["t"].cpu()
+        except Exception as e:  # pragma: no cover - reported below
+            errs.append(e)
+
+    th = [threading.Thread(target=work, args=(i,)) for i in range(2)]
+    for t in th:
+        t.start()
+    for t in th:
+        t.join()
+    assert not errs, errs
+    assert torch.equal(out[0], ref) and torch.equal(out[1], ref)
 
 
 def test_edge_cases(env):
