@@ -195,6 +195,7 @@ def test_concurrent_first_calls(env):
     d = torch.from_numpy(rng.normal(size=(n, 3)).astype(np.float32)).cuda()
     ref = pcrl.sdf_intersect(_build(env, s), o, d)["t"].cpu()
     scene = _build(env, s)
+    torch.cuda.synchronize()  # the inputs and the scene are complete before the side streams start
     out, errs = [None, None], []
     streams = [torch.cuda.Stream(), torch.cuda.Stream()]
     barrier = threading.Barrier(2)
