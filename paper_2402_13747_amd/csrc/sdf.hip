@@ -238,10 +238,11 @@ __global__ __launch_bounds__(SDF_BLOCK) void k_sdf(SdfArgs a) {
     if (lane_ray >= a.n) return;
     const uint32_t i = a.order ? a.order[lane_ray] : lane_ray;
     const SceneView& v = a.v;
-    float o[3] = {a.o[3 * i], a.o[3 * i + 1], a.o[3 * i + 2]};
-    float d[3] = {a.d[3 * i], a.d[3 * i + 1], a.d[3 * i + 2]};
-    const float t_lo = a.tr ? a.tr[2 * i] : 0.f;
-    const float t_hi = a.tr ? a.tr[2 * i + 1] : INFINITY;
+    const size_t i3 = 3 * (size_t)i, i2 = 2 * (size_t)i;  // n may exceed 2^32 / 3
+    float o[3] = {a.o[i3], a.o[i3 + 1], a.o[i3 + 2]};
+    float d[3] = {a.d[i3], a.d[i3 + 1], a.d[i3 + 2]};
+    const float t_lo = a.tr ? a.tr[i2] : 0.f;
+    const float t_hi = a.tr ? a.tr[i2 + 1] : INFINITY;
     const float len = sqrtf(d[0] * d[0] + d[1] * d[1] + d[2] * d[2]);
     float best = INFINITY, bn[3] = {0.f, 0.f, 0.f};
     int bc[3] = {-1, -1, -1};
@@ -328,9 +329,9 @@ __global__ __launch_bounds__(SDF_BLOCK) void k_sdf(SdfArgs a) {
     const bool hit = bc[0] >= 0;
 #pragma unroll
     for (int ax = 0; ax < 3; ++ax) {
-        a.pt[3 * i + ax] = hit ? o[ax] + best * d[ax] : NAN;
-        a.nrm[3 * i + ax] = bn[ax];
-        if (a.cell) a.cell[3 * i + ax] = bc[ax];
+        a.pt[i3 + ax] = hit ? o[ax] + best * d[ax] : NAN;
+        a.nrm[i3 + ax] = bn[ax];
+        if (a.cell) a.cell[i3 + ax] = bc[ax];
     }
     if (a.stats) {
         atomicAdd(&a.stats[0], (unsigned long long)evals);
