@@ -347,7 +347,7 @@ static void launch_sdf_nl(const SdfArgs& a, hipStream_t s) {
 
 template <int NL>
 static void launch_own_flags(const SceneView& v, uint32_t m, uint32_t* flag, hipStream_t s) {
-    hipLaunchKernelGGL((k_own_flags<NL>), dim3((m + 255) / 256), dim3(256), 0, s, v, m, flag);
+    hipLaunchKernelGGL((k_own_flags<NL>), dim3((unsigned)(((uint64_t)m + 255) / 256)), dim3(256), 0, s, v, m, flag);
 }
 
 // The scene's own-point index, built on the first call (under the scene's
