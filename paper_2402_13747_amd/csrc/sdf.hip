@@ -25,7 +25,7 @@
 
 namespace pcrl {
 
-constexpr int SDF_BLOCK = 256;
+constexpr int SDF_BLOCK = 64;  // one wave per block: the lanes finish unevenly, small blocks refill the CUs sooner
 constexpr int64_t SDF_ORDER_MIN = 65536;  // rays from which a call sorts them into a coherent order
 
 struct SdfArgs {
