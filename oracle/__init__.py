@@ -30,6 +30,7 @@ they are pinned only by the shared definition.
 from __future__ import annotations
 
 import ctypes as C
+import math
 import os
 import subprocess
 from collections import defaultdict
@@ -98,6 +99,7 @@ class OracleSdfArgs(C.Structure):
         ("h", C.c_double), ("eps", C.c_double), ("max_steps", C.c_int32), ("n_threads", C.c_int32),
         ("diam_scale", C.c_double), ("cross_margin", C.c_double),
         ("t", C.c_void_p), ("point", C.c_void_p), ("normal", C.c_void_p), ("leaf_cell", C.c_void_p),
+        ("o64", C.c_void_p), ("d64", C.c_void_p), ("trange64", C.c_void_p),
     ]
 
 
@@ -419,12 +421,15 @@ def sdf_intersect(xyz, normal, origin, leaf, o, d, trange=None, h=None, eps=None
     """
     xyz = np.ascontiguousarray(xyz, np.float32).reshape(-1, 3)
     normal = np.ascontiguousarray(normal, np.float32).reshape(-1, 3)
-    o = np.ascontiguousarray(np.asarray(o, np.float32).reshape(-1, 3))
-    d = np.ascontiguousarray(np.asarray(d, np.float32).reshape(-1, 3))
+    # float64 rays are taken as they are (reflected rays carry FP64 state)
+    wide = isinstance(o, np.ndarray) and o.dtype == np.float64
+    ft = np.float64 if wide else np.float32
+    o = np.ascontiguousarray(np.asarray(o, ft).reshape(-1, 3))
+    d = np.ascontiguousarray(np.asarray(d, ft).reshape(-1, 3))
     if o.shape != d.shape:
         raise ValueError("o and d must have the same shape")
     n = o.shape[0]
-    tr = None if trange is None else np.ascontiguousarray(np.asarray(trange, np.float32).reshape(n, 2))
+    tr = None if trange is None else np.ascontiguousarray(np.asarray(trange, ft).reshape(n, 2))
     leaf = float(np.float32(leaf))
     h = SDF_H_SCALE * leaf if h is None else float(h)
     eps = SDF_EPS_SCALE * leaf if eps is None else float(eps)
@@ -434,7 +439,11 @@ def sdf_intersect(xyz, normal, origin, leaf, o, d, trange=None, h=None, eps=None
     a.xyz, a.nrm, a.n_pts = _p(xyz), _p(normal), xyz.shape[0]
     a.origin[:] = [float(v) for v in np.asarray(origin, np.float32).reshape(3)]
     a.leaf = leaf
-    a.o, a.d, a.trange, a.n_rays = _p(o), _p(d), (_p(tr) if tr is not None else None), n
+    if wide:
+        a.o64, a.d64, a.trange64 = _p(o), _p(d), (_p(tr) if tr is not None else None)
+    else:
+        a.o, a.d, a.trange = _p(o), _p(d), (_p(tr) if tr is not None else None)
+    a.n_rays = n
     a.h, a.eps, a.max_steps = h, eps, int(max_steps)
     a.n_threads = default_threads() if n_threads is None else int(n_threads)
     a.diam_scale, a.cross_margin = float(diam_scale), float(cross_margin)
@@ -444,3 +453,112 @@ def sdf_intersect(xyz, normal, origin, leaf, o, d, trange=None, h=None, eps=None
     if rc != 0:
         raise ValueError(f"oracle_sdf_intersect failed ({rc})")
     return out
+
+
+def sdf_launch(xyz, normal, label, origin, leaf, tx, rx, dirs, K, sigma=1.25, alpha=0.0, h=None, eps=None,
+               max_steps=SDF_MAX_STEPS, diam_scale=1.0, cross_margin=0.0, band=1e-5, n_threads=None):
+    """Coarse launch whose segments end at the implicit surface of Eq. 1 (FP64;
+    the definition behind PCRL_LAUNCH_SDF).
+
+    Every ray (global id g = tx index * n_rays + direction index) runs
+    segments b = 0..K: the first intersection of ``sdf_intersect`` from
+    t_lo (0 from the TX; after a reflection 4 eps / max(|d.n|, 0.05), just
+    outside the |f| <= eps band the ray leaves); the interaction's label and
+    id are those of the nearest point (a miss if none lies within h); every
+    RX sphere is tested on [0, t] as in ``launch`` (reading R8); the ray
+    reflects about n(x).  Returns per ray and segment ``t`` (+inf miss, NaN
+    not traced), ``pid``, ``label`` and ``label_margin`` (distance to the
+    second-nearest point minus the nearest), ``cos`` = |d.n| at the hit, and
+    the records ``rec_*`` with
+    ``rec_band`` set where the reception test lies within ``band`` of its
+    threshold.
+    """
+    from scipy.spatial import cKDTree
+    xyz32 = np.ascontiguousarray(xyz, np.float32).reshape(-1, 3)
+    lab = np.asarray(label, np.uint32).reshape(-1)
+    tx = np.asarray(tx, np.float32).reshape(-1, 3).astype(np.float64)
+    rx = np.asarray(rx, np.float32).reshape(-1, 3).astype(np.float64)
+    dirs = np.asarray(dirs, np.float32).reshape(-1, 3).astype(np.float64)
+    n_rays = dirs.shape[0]
+    n = tx.shape[0] * n_rays
+    leaf32 = float(np.float32(leaf))
+    h = SDF_H_SCALE * leaf32 if h is None else float(h)
+    eps = SDF_EPS_SCALE * leaf32 if eps is None else float(eps)
+    if alpha <= 0.0:
+        alpha = math.sqrt(8.0 * math.pi / (math.sqrt(3.0) * n_rays))
+    sig_c = sigma * alpha / math.sqrt(3.0)
+    tree = cKDTree(xyz32.astype(np.float64)) if len(xyz32) else None
+    o = np.repeat(tx, n_rays, axis=0)
+    d = np.tile(dirs, (tx.shape[0], 1))
+    d /= np.linalg.norm(d, axis=1, keepdims=True)
+    L = np.zeros(n)
+    t_lo = np.zeros(n)
+    alive = np.ones(n, bool)
+    T = np.full((n, K + 1), np.nan)
+    PID = np.full((n, K + 1), -1, np.int64)
+    LAB = np.full((n, K + 1), -1, np.int64)
+    MARG = np.full((n, K + 1), np.inf)
+    COS = np.full((n, K + 1), np.nan)
+    recs = []
+    for b in range(K + 1):
+        idx = np.nonzero(alive)[0]
+        if len(idx) == 0:
+            break
+        tr = np.column_stack([t_lo[idx], np.full(len(idx), np.inf)])
+        r = sdf_intersect(xyz32, normal, origin, leaf, o[idx], d[idx], trange=tr, h=h, eps=eps,
+                          max_steps=max_steps, diam_scale=diam_scale, cross_margin=cross_margin,
+                          n_threads=n_threads)
+        t = r["t"].copy()
+        hit = np.isfinite(t)
+        q = o[idx] + np.where(hit, t, 0.0)[:, None] * d[idx]
+        if tree is not None and hit.any():
+            dist, nn = tree.query(q[hit], k=2 if len(xyz32) > 1 else 1)
+            dist = dist.reshape(len(nn), -1)
+            nn = nn.reshape(len(nn), -1)
+            first = nn[:, 0].copy()
+            if dist.shape[1] > 1:
+                tie = dist[:, 1] == dist[:, 0]
+                first[tie] = np.minimum(nn[tie, 0], nn[tie, 1])
+                marg = dist[:, 1] - dist[:, 0]
+            else:
+                marg = np.full(len(first), np.inf)
+            near = dist[:, 0] < h
+            hi_idx = np.nonzero(hit)[0]
+            PID[idx[hi_idx[near]], b] = first[near]
+            LAB[idx[hi_idx[near]], b] = lab[first[near]]
+            MARG[idx[hi_idx], b] = np.where(near, marg, np.inf)
+            hit[hi_idx[~near]] = False
+        t[~hit] = np.inf
+        T[idx, b] = t
+        COS[idx, b] = np.abs((d[idx] * r["normal"]).sum(1))
+        # reception on [0, t] (reading R8)
+        for ri in range(rx.shape[0]):
+            v = rx[ri] - o[idx]
+            s_ = (v * d[idx]).sum(1)
+            c = v - s_[:, None] * d[idx]
+            dist2 = (c * c).sum(1)
+            rho = sig_c * (L[idx] + s_)
+            inside = (s_ > 0) & (s_ <= t)
+            got = inside & (dist2 <= rho * rho)
+            near_thr = (np.abs(dist2 - rho * rho) <= band * np.maximum(rho * rho, 1e-30)) | \
+                (np.abs(s_) <= band * (1 + np.abs(s_))) | (np.isfinite(t) & (np.abs(s_ - t) <= band * (1 + t)))
+            for k in np.nonzero(got | (near_thr & (dist2 <= rho * rho * (1 + 2 * band))))[0]:
+                recs.append((idx[k], ri, b, L[idx[k]] + math.sqrt((v[k] ** 2).sum()), L[idx[k]] + s_[k],
+                             bool(got[k]), bool(near_thr[k])))
+        surv = hit & (b < K)
+        alive[idx[~surv]] = False
+        si = idx[surv]
+        if len(si):
+            n_ = r["normal"][surv]
+            dn = (d[si] * n_).sum(1)
+            dd = d[si] - 2.0 * dn[:, None] * n_
+            dd /= np.linalg.norm(dd, axis=1, keepdims=True)
+            L[si] += t[surv]
+            o[si] = q[surv]
+            d[si] = dd
+            t_lo[si] = 4.0 * eps / np.maximum(np.abs(dn), 0.05)
+    rec = np.array([x[:5] for x in recs], dtype=np.float64).reshape(-1, 5)
+    return dict(t=T, pid=PID, label=LAB, label_margin=MARG, cos=COS,
+                rec_g=rec[:, 0].astype(np.int64), rec_rx=rec[:, 1].astype(np.int64), rec_b=rec[:, 2].astype(np.int64),
+                rec_lpoly=rec[:, 3], rec_lunf=rec[:, 4],
+                rec_got=np.array([x[5] for x in recs], bool), rec_band=np.array([x[6] for x in recs], bool))

@@ -58,6 +58,9 @@ typedef struct {
     double* point;             /* [n_rays*3] */
     double* normal;            /* [n_rays*3] n at the intersection */
     int32_t* leaf_cell;        /* [n_rays*3] cell of the leaf whose march found it, -1 none */
+    const double* o64;         /* optional FP64 origins, directions and ranges (used instead of o, d, */
+    const double* d64;         /* trange when given): the state of rays that have already reflected */
+    const double* trange64;
 } OracleSdfArgs;
 
 typedef struct {
@@ -195,12 +198,15 @@ static int march(const Sdf* S, const double* o, const double* d, double ta, doub
 static void sdf_ray(const Sdf* S, int64_t r)
 {
     const OracleSdfArgs* a = S->a;
-    double o[3] = {a->o[3 * r], a->o[3 * r + 1], a->o[3 * r + 2]};
-    double d[3] = {a->d[3 * r], a->d[3 * r + 1], a->d[3 * r + 2]};
+    double o[3], d[3];
+    for (int k = 0; k < 3; ++k) {
+        o[k] = a->o64 ? a->o64[3 * r + k] : (double)a->o[3 * r + k];
+        d[k] = a->d64 ? a->d64[3 * r + k] : (double)a->d[3 * r + k];
+    }
     double dl = sqrt(d[0] * d[0] + d[1] * d[1] + d[2] * d[2]);
     d[0] /= dl; d[1] /= dl; d[2] /= dl;
-    double t_lo = a->trange ? a->trange[2 * r] : 0.0;
-    double t_hi = a->trange ? a->trange[2 * r + 1] : INFINITY;
+    double t_lo = a->trange64 ? a->trange64[2 * r] : (a->trange ? a->trange[2 * r] : 0.0);
+    double t_hi = a->trange64 ? a->trange64[2 * r + 1] : (a->trange ? a->trange[2 * r + 1] : INFINITY);
     const double L = a->leaf, D = a->diam_scale * sqrt(3.0) * L, m = a->cross_margin;
     double best = INFINITY, bn[3] = {0.0, 0.0, 0.0};
     int64_t bl = -1, bi = -1;
@@ -246,7 +252,8 @@ static void* sdf_worker(void* p)
 int oracle_sdf_intersect(OracleSdfArgs* a)
 {
     if (!a || a->n_pts < 0 || a->n_rays < 0 || !(a->h > 0.0) || !(a->eps >= 0.0) || a->max_steps < 0 ||
-        !(a->leaf > 0.0f) || !(a->diam_scale > 0.0) || (a->n_rays > 0 && (!a->o || !a->d || !a->t || !a->point || !a->normal || !a->leaf_cell)) ||
+        !(a->leaf > 0.0f) || !(a->diam_scale > 0.0) || (a->n_rays > 0 && ((!a->o && !a->o64) || (!a->d && !a->d64) || !a->t || !a->point || !a->normal ||
+                            !a->leaf_cell)) ||
         (a->n_pts > 0 && (!a->xyz || !a->nrm)))
         return -1;
     Sdf S;

@@ -261,3 +261,41 @@ def test_empty_cloud_and_bad_arguments():
     assert np.isinf(r["t"][0])
     with pytest.raises(ValueError):
         oracle.sdf_intersect(xyz, xyz, ORG, LEAF, [[0, 0, 1]], [[0, 0, -1]], h=-1.0)
+
+
+def test_sdf_launch_box_room_paths_are_image_paths():
+    """In the empty box room every wall's implicit surface is its plane, so the
+    oracle's SDF launch reflects on the walls: each interaction lies within
+    eps of a wall plane, and every received label sequence is one of the
+    image-method paths of tests/golden/ (line of sight included)."""
+    import os
+    import scenes
+    s = scenes.box_room()
+    golden = set()
+    here = os.path.dirname(os.path.abspath(__file__))
+    for line in open(os.path.join(here, "golden", "box_room_image_paths.txt")):
+        if line.startswith("#"):
+            continue
+        name = line.split()[0]
+        golden.add(() if name == "-" else tuple(int(x) for x in name.split(",")))
+    org = np.array([-0.5, -0.5, -0.5], np.float32)
+    leaf = 0.25
+    r = oracle.sdf_launch(s.xyz, s.normal, s.label, org, leaf, s.tx, s.rx, oracle.fibonacci(4000), K=2)
+    eps = oracle.SDF_EPS_SCALE * leaf
+    got = r["rec_got"] & ~r["rec_band"]
+    assert got.sum() > 10
+    seqs = set()
+    for g, b in zip(r["rec_g"][got], r["rec_b"][got]):
+        seqs.add(tuple(int(x) for x in r["label"][g, :b]))
+    assert () in seqs and seqs <= golden and len(seqs) >= 4
+    # first hits away from the room's edges (where the implicit surface rounds
+    # the corner) lie within eps of a wall plane: there f is the height above it
+    tx = np.asarray(s.tx[0], np.float64)
+    d = oracle.fibonacci(4000).astype(np.float64)
+    d /= np.linalg.norm(d, axis=1, keepdims=True)
+    p = tx + r["t"][:, 0:1] * d
+    planes = np.sort(np.stack([np.abs(p[:, 0]), np.abs(p[:, 0] - 10), np.abs(p[:, 1]), np.abs(p[:, 1] - 8),
+                               np.abs(p[:, 2]), np.abs(p[:, 2] - 3)], 1), axis=1)
+    face = planes[:, 1] > oracle.SDF_H_SCALE * leaf + 0.1
+    assert face.sum() > 3000
+    assert np.all(planes[face, 0] <= eps + 1e-9)
