@@ -174,6 +174,13 @@ int release_scene(PcrlScene* scene);
 #define PCRL_LAUNCH_COHERENT 4  /* trace the first bounce in a direction-coherent ray order and (launches of
                                    >= 65536 rays) every later bounce in a coherent order of its survivors;
                                    results do not depend on it */
+#define PCRL_LAUNCH_SDF      8  /* segments end at the implicit surface of Eq. 1 (Section 2.2.1), marched as
+                                   sdf_intersect does with its default h, eps and max_steps, instead of at
+                                   the surfels: the ray reflects about n(x), the interaction's label and
+                                   hit id are those of the nearest point, and a reflected segment starts at
+                                   t = 4 eps / |d.n| (outside the |f| <= eps band it left).  One kernel runs
+                                   all segments (TIMING reports it as bounce 0).  Not with
+                                   PCRL_LAUNCH_STATS, dynamic points or launch_batch / serving. */
 
 typedef struct {
     int64_t n_rays;            /* rays per TX (> 0) */

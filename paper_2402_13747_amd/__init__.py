@@ -20,7 +20,7 @@ import numpy as np
 import torch
 
 from . import _lib
-from ._lib import (KEY_LABELS, KEY_LEAVES, LAUNCH_COHERENT, LAUNCH_STATS, LAUNCH_TIMING, PCRL_EOVERFLOW,
+from ._lib import (KEY_LABELS, KEY_LEAVES, LAUNCH_COHERENT, LAUNCH_SDF, LAUNCH_STATS, LAUNCH_TIMING, PCRL_EOVERFLOW,
                    REFINE_DEGENERATE, REFINE_MISS, REFINE_NOT_CONVERGED, REFINE_OCCLUDED, REFINE_VALID,
                    REFINE_WRONG_SIDE, PcrlError, check, lib)
 
@@ -255,14 +255,15 @@ class Launch:
 
 
 def launch_rays(scene: Scene, tx, rx, n_rays, max_reflections, directions=None, rx_radius_scale=1.25,
-                ray_spacing=0.0, record_capacity=0, stats=False, timing=False, coherent=True, hit_log=False
-                ) -> Launch:
+                ray_spacing=0.0, record_capacity=0, stats=False, timing=False, coherent=True, hit_log=False,
+                sdf=False) -> Launch:
     """Launch ``n_rays`` rays from every TX (Fibonacci lattice unless ``directions``).
 
     ``coherent`` traces the first bounce in a direction-sorted ray order (same
-    results, better locality)."""
+    results, better locality).  ``sdf`` ends the segments at the implicit
+    surface of Eq. 1 instead of the surfels (PCRL_LAUNCH_SDF)."""
     q = _query(scene, tx, rx, n_rays, max_reflections, directions, rx_radius_scale, ray_spacing, record_capacity,
-               stats, timing, coherent, hit_log)
+               stats, timing, coherent, hit_log, sdf)
     h = C.c_void_p()
     device = scene.device
     with _on(device):
@@ -273,7 +274,7 @@ def launch_rays(scene: Scene, tx, rx, n_rays, max_reflections, directions=None, 
 
 
 def _query(scene, tx, rx, n_rays, max_reflections, directions=None, rx_radius_scale=1.25, ray_spacing=0.0,
-           record_capacity=0, stats=False, timing=False, coherent=True, hit_log=False):
+           record_capacity=0, stats=False, timing=False, coherent=True, hit_log=False, sdf=False):
     """Marshal one query: device tensors, PcrlLaunchParams and the optional hit log."""
     device = scene.device
     tx = _as_tensor(tx, torch.float32, device, 3)
@@ -289,7 +290,8 @@ def _query(scene, tx, rx, n_rays, max_reflections, directions=None, rx_radius_sc
     p.rx_radius_scale = float(rx_radius_scale)
     p.ray_spacing = float(ray_spacing)
     p.record_capacity = int(record_capacity)
-    p.flags = (LAUNCH_STATS if stats else 0) | (LAUNCH_TIMING if timing else 0) | (LAUNCH_COHERENT if coherent else 0)
+    p.flags = ((LAUNCH_STATS if stats else 0) | (LAUNCH_TIMING if timing else 0) | (LAUNCH_COHERENT if coherent else 0)
+               | (LAUNCH_SDF if sdf else 0))
     log = None
     if hit_log:
         n = tx.shape[0] * int(n_rays) * (K + 1)
@@ -298,7 +300,7 @@ def _query(scene, tx, rx, n_rays, max_reflections, directions=None, rx_radius_sc
         p.hit_log_t = log[1].data_ptr()
     args = dict(tx=tx, rx=rx, n_rays=n_rays, max_reflections=max_reflections, directions=dirs,
                 rx_radius_scale=rx_radius_scale, ray_spacing=ray_spacing, stats=stats, timing=timing,
-                coherent=coherent, hit_log=hit_log)
+                coherent=coherent, hit_log=hit_log, sdf=sdf)
     return {"scene": scene, "tx": tx, "rx": rx, "dirs": dirs, "params": p, "log": log, "args": args, "K": K,
             "n_rays": int(n_rays)}
 

@@ -29,6 +29,7 @@ MAX_REFLECTIONS = 8
 LAUNCH_STATS = 1
 LAUNCH_TIMING = 2
 LAUNCH_COHERENT = 4
+LAUNCH_SDF = 8
 VOXEL_COMPACT = 1
 KEY_LABELS = 0
 KEY_LEAVES = 1

@@ -254,6 +254,11 @@ static int run_graph(const std::vector<BatchCtl>& host_ctl, const std::vector<Ba
 
 static int batch_impl(const PcrlQuery* q, int32_t n_q, const PcrlBatchParams* bp, hipStream_t s, PcrlLaunch** out) {
     for (int i = 0; i < n_q; ++i) out[i] = nullptr;
+    for (int i = 0; i < n_q; ++i)
+        if (q[i].params.flags & PCRL_LAUNCH_SDF) {
+            set_error("launch_batch: query %d asks for PCRL_LAUNCH_SDF, which only launch_rays runs", i);
+            return PCRL_EINVAL;
+        }
     auto shared = std::make_shared<BatchShared>();
     shared->bufs.stream = s;
     std::vector<TraceArgs> args((size_t)n_q);

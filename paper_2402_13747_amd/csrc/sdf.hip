@@ -232,40 +232,26 @@ __global__ void k_sdf_keys(const float* o, const float* d, uint32_t n, float3 lo
     idx[j] = j;
 }
 
+// Nearest intersection of the ray o + t d (d unit) in [t_lo, t_hi]: best = t
+// (+inf if none), with the normal bn and the leaf cell bc (-1 if none).
 template <int NL>
-__global__ __launch_bounds__(SDF_BLOCK) void k_sdf(SdfArgs a) {
-    const uint32_t lane_ray = blockIdx.x * SDF_BLOCK + threadIdx.x;
-    if (lane_ray >= a.n) return;
-    const uint32_t i = a.order ? a.order[lane_ray] : lane_ray;
+__device__ __forceinline__ void sdf_first_hit(const SdfArgs& a, const float o[3], const float d[3], float t_lo,
+                                              float t_hi, float& best, float bn[3], int bc[3], uint32_t& evals,
+                                              uint32_t& reads) {
     const SceneView& v = a.v;
-    const size_t i3 = 3 * (size_t)i, i2 = 2 * (size_t)i;  // n may exceed 2^32 / 3
-    float o[3] = {a.o[i3], a.o[i3 + 1], a.o[i3 + 2]};
-    float d[3] = {a.d[i3], a.d[i3 + 1], a.d[i3 + 2]};
-    const float t_lo = a.tr ? a.tr[i2] : 0.f;
-    const float t_hi = a.tr ? a.tr[i2 + 1] : INFINITY;
-    const float len = sqrtf(d[0] * d[0] + d[1] * d[1] + d[2] * d[2]);
-    float best = INFINITY, bn[3] = {0.f, 0.f, 0.f};
-    int bc[3] = {-1, -1, -1};
-    uint32_t evals = 0, reads = 0;
-    const bool ok = !a.empty && len > 0.f && isfinite(len) && isfinite(o[0]) && isfinite(o[1]) && isfinite(o[2]) &&
-                    t_lo <= t_hi;
+    best = INFINITY;
+    bn[0] = bn[1] = bn[2] = 0.f;
+    bc[0] = bc[1] = bc[2] = -1;
     Seg S;
-    bool walking = false;
+    bool walking = !a.empty && t_lo <= t_hi && seg_begin(v, o, d, S);
     float t_in = 0.f;  // where the ray enters the current cell
-    if (ok) {
-        const float il = 1.0f / len;
-        d[0] *= il;
-        d[1] *= il;
-        d[2] *= il;
-        walking = seg_begin(v, o, d, S);
-        if (walking) {
+    if (walking) {
 #pragma unroll
-            for (int ax = 0; ax < 3; ++ax) {
-                float tf = -INFINITY;
-                if (d[ax] > 0.f) tf = ((float)S.c[ax] * v.h + v.org[ax] - o[ax]) * S.inv[ax];
-                else if (d[ax] < 0.f) tf = ((float)(S.c[ax] + 1) * v.h + v.org[ax] - o[ax]) * S.inv[ax];
-                t_in = fmaxf(t_in, tf);
-            }
+        for (int ax = 0; ax < 3; ++ax) {
+            float tf = -INFINITY;
+            if (d[ax] > 0.f) tf = ((float)S.c[ax] * v.h + v.org[ax] - o[ax]) * S.inv[ax];
+            else if (d[ax] < 0.f) tf = ((float)(S.c[ax] + 1) * v.h + v.org[ax] - o[ax]) * S.inv[ax];
+            t_in = fmaxf(t_in, tf);
         }
     }
     while (walking) {
@@ -325,6 +311,30 @@ __global__ __launch_bounds__(SDF_BLOCK) void k_sdf(SdfArgs a) {
         dda_advance<NL>(v, walking, o, d, S, k, at_leaf, fminf(best + a.reach, t_hi), te);
         t_in = te;
     }
+}
+
+template <int NL>
+__global__ __launch_bounds__(SDF_BLOCK) void k_sdf(SdfArgs a) {
+    const uint32_t lane_ray = blockIdx.x * SDF_BLOCK + threadIdx.x;
+    if (lane_ray >= a.n) return;
+    const uint32_t i = a.order ? a.order[lane_ray] : lane_ray;
+    const size_t i3 = 3 * (size_t)i, i2 = 2 * (size_t)i;  // n may exceed 2^32 / 3
+    const float o[3] = {a.o[i3], a.o[i3 + 1], a.o[i3 + 2]};
+    float d[3] = {a.d[i3], a.d[i3 + 1], a.d[i3 + 2]};
+    const float t_lo = a.tr ? a.tr[i2] : 0.f;
+    const float t_hi = a.tr ? a.tr[i2 + 1] : INFINITY;
+    const float len = sqrtf(d[0] * d[0] + d[1] * d[1] + d[2] * d[2]);
+    const bool ok = len > 0.f && isfinite(len) && isfinite(o[0]) && isfinite(o[1]) && isfinite(o[2]);
+    float best = INFINITY, bn[3] = {0.f, 0.f, 0.f};
+    int bc[3] = {-1, -1, -1};
+    uint32_t evals = 0, reads = 0;
+    if (ok) {
+        const float il = 1.0f / len;
+        d[0] *= il;
+        d[1] *= il;
+        d[2] *= il;
+        sdf_first_hit<NL>(a, o, d, t_lo, t_hi, best, bn, bc, evals, reads);
+    }
     a.t[i] = best;
     const bool hit = bc[0] >= 0;
 #pragma unroll
@@ -337,6 +347,176 @@ __global__ __launch_bounds__(SDF_BLOCK) void k_sdf(SdfArgs a) {
         atomicAdd(&a.stats[0], (unsigned long long)evals);
         atomicAdd(&a.stats[1], (unsigned long long)reads);
     }
+}
+
+// Id and label of the point nearest to x among those within h (smallest
+// distance, then smallest id); false if none.
+template <int NL>
+__device__ __forceinline__ bool nearest_own(const SdfArgs& a, const float x[3], uint32_t& id, uint32_t& label) {
+    const SceneView& v = a.v;
+    int lc[3];
+    float fr[3];
+#pragma unroll
+    for (int k = 0; k < 3; ++k) {
+        const float u = (x[k] - v.org[k]) * v.inv_h;
+        lc[k] = (int)floorf(u);
+        fr[k] = u - (float)lc[k];
+    }
+    float bd = a.h2;
+    bool found = false;
+    Seg N;
+    N.cq[0] = N.cq[1] = N.cq[2] = -1;
+    N.cres = 0;
+    N.cskip0 = 1;
+    N.cnode = 0;
+    N.oct_shift = 0;
+#pragma unroll 1
+    for (int q = 0; q < 27; ++q) {
+        const int dx = q % 3 - 1, dy = (q / 3) % 3 - 1, dz = q / 9 - 1;
+        const float gx = dx < 0 ? fr[0] : (dx > 0 ? 1.f - fr[0] : 0.f);
+        const float gy = dy < 0 ? fr[1] : (dy > 0 ? 1.f - fr[1] : 0.f);
+        const float gz = dz < 0 ? fr[2] : (dz > 0 ? 1.f - fr[2] : 0.f);
+        if (gx * gx + gy * gy + gz * gz >= a.hl2) continue;
+        N.c[0] = lc[0] + dx;
+        N.c[1] = lc[1] + dy;
+        N.c[2] = lc[2] + dz;
+        if (N.c[0] < 0 || N.c[1] < 0 || N.c[2] < 0 || N.c[0] >= v.dim[0] || N.c[1] >= v.dim[1] ||
+            N.c[2] >= v.dim[2])
+            continue;
+        DdaCell k;
+        dda_cell_reset(k);
+        dda_locate<false, NL>(v, N, k, nullptr);
+        if (k.lvl != NL || k.range.y == 0u) continue;
+        const uint32_t e1 = a.oscan[k.range.x + k.range.y];
+        for (uint32_t e = a.oscan[k.range.x]; e < e1; ++e) {
+            const float4 P = a.opos[e];
+            const float ex = P.x - x[0], ey = P.y - x[1], ez = P.z - x[2];
+            const float d2 = ex * ex + ey * ey + ez * ez;
+            const uint32_t pid = __float_as_uint(P.w);
+            if (d2 < bd || (d2 == bd && found && pid < id)) {
+                bd = d2;
+                id = pid;
+                label = __float_as_uint(a.onrm[e].w);
+                found = true;
+            }
+        }
+    }
+    return found;
+}
+
+// A launch whose intersections are those of the implicit surface (launch_rays
+// with PCRL_LAUNCH_SDF): one lane per ray runs all its segments.
+struct SdfLaunchArgs {
+    SdfArgs s;
+    const float* tx;
+    const float* rx;
+    const float* dirs;
+    const uint32_t* order;  // null, or lane -> global ray id
+    int32_t n_rx;
+    int32_t K;
+    uint32_t n_rays;
+    uint32_t n_total;
+    float sig_c;            // rho(u) = sig_c * u
+    float4* hist;
+    uint4* rec;
+    uint32_t rec_cap;
+    uint32_t* counters;
+    int32_t* hit_id;
+    float* hit_t;
+};
+
+// Add x (the same on every lane) to *p for each lane active here, with one
+// atomic per wave.
+__device__ __forceinline__ void wave_add(uint32_t* p, uint32_t x) {
+    const uint64_t m = __ballot(1);
+    const int leader = __ffsll((long long)m) - 1;
+    if ((int)lane_id() == leader) atomicAdd(p, (uint32_t)__popcll(m) * x);
+}
+
+// Every segment of a ray, as the launcher's bounce kernels do with surfels:
+// the segment from o along d ends at the implicit surface's first
+// intersection (from t_lo: 0 from the TX, after a reflection 4 eps / |d.n|
+// so that the march starts outside the |f| <= eps band it left); the RX
+// spheres are tested on [0, t]; at the intersection the ray reflects about
+// n(x) and records the label of the nearest point.
+template <int NL>
+__global__ __launch_bounds__(SDF_BLOCK) void k_sdf_launch(SdfLaunchArgs A) {
+    const uint32_t lane_ray = blockIdx.x * SDF_BLOCK + threadIdx.x;
+    if (lane_ray >= A.n_total) return;
+    const uint32_t g = A.order ? A.order[lane_ray] : lane_ray;
+    const SdfArgs& a = A.s;
+    const uint32_t ti = g / A.n_rays, j = g - ti * A.n_rays;
+    float o[3] = {A.tx[3 * ti], A.tx[3 * ti + 1], A.tx[3 * ti + 2]};
+    float d[3] = {A.dirs[3 * (size_t)j], A.dirs[3 * (size_t)j + 1], A.dirs[3 * (size_t)j + 2]};
+    {
+        const float il = 1.0f / sqrtf(d[0] * d[0] + d[1] * d[1] + d[2] * d[2]);
+        d[0] *= il;
+        d[1] *= il;
+        d[2] *= il;
+    }
+    float L = 0.f, t_lo = 0.f;
+    uint32_t* rec_counter = &A.counters[PCRL_CNT_REC(A.K)];
+    for (int b = 0; b <= A.K; ++b) {
+        wave_add(&A.counters[b], 1u);
+        float t, n[3];
+        int bc[3];
+        uint32_t ev = 0, rd = 0;
+        sdf_first_hit<NL>(a, o, d, t_lo, INFINITY, t, n, bc, ev, rd);
+        bool hit = bc[0] >= 0;
+        float q[3] = {o[0] + t * d[0], o[1] + t * d[1], o[2] + t * d[2]};
+        uint32_t pid = 0, lab = 0;
+        if (hit) hit = nearest_own<NL>(a, q, pid, lab);
+        if (!hit) t = INFINITY;
+        if (A.hit_id) {
+            const size_t idx = (size_t)g * (A.K + 1) + b;
+            A.hit_id[idx] = hit ? (int32_t)pid : -1;
+            A.hit_t[idx] = hit ? t : NAN;
+        }
+        for (int r = 0; r < A.n_rx; ++r) {
+            const float vx = A.rx[3 * r] - o[0], vy = A.rx[3 * r + 1] - o[1], vz = A.rx[3 * r + 2] - o[2];
+            const float sp = vx * d[0] + vy * d[1] + vz * d[2];
+            if (!(sp > 0.f && sp <= t)) continue;
+            const float cx = vx - sp * d[0], cy = vy - sp * d[1], cz = vz - sp * d[2];
+            const float rho = A.sig_c * (L + sp);
+            if (!(cx * cx + cy * cy + cz * cz <= rho * rho)) continue;
+            const uint32_t slot = atomicAdd(rec_counter, 1u);
+            if (slot < A.rec_cap) {
+                const float lp = L + sqrtf(vx * vx + vy * vy + vz * vz);
+                A.rec[slot] = make_uint4(g, (uint32_t)r | ((uint32_t)b << 16), __float_as_uint(lp),
+                                         __float_as_uint(L + sp));
+            }
+        }
+        if (!hit || b >= A.K) break;
+        A.hist[(size_t)b * A.n_total + g] = make_float4(q[0], q[1], q[2], __uint_as_float(lab));
+        L += t;
+        const float dn = d[0] * n[0] + d[1] * n[1] + d[2] * n[2];
+        const float ex = d[0] - 2.f * dn * n[0], ey = d[1] - 2.f * dn * n[1], ez = d[2] - 2.f * dn * n[2];
+        const float inv = 1.0f / sqrtf(ex * ex + ey * ey + ez * ez);
+        d[0] = ex * inv;
+        d[1] = ey * inv;
+        d[2] = ez * inv;
+        o[0] = q[0];
+        o[1] = q[1];
+        o[2] = q[2];
+        t_lo = 4.f * a.eps / fmaxf(fabsf(dn), 0.05f);
+    }
+}
+
+// Coherence key of global ray g (TX cell, direction cell; see k_sdf_keys).
+__global__ void k_sdf_launch_keys(const float* tx, const float* dirs, uint32_t n_rays, uint32_t n_total, float3 lo,
+                                  float3 scale, uint64_t* keys, uint32_t* idx) {
+    const uint32_t g = blockIdx.x * blockDim.x + threadIdx.x;
+    if (g >= n_total) return;
+    const uint32_t ti = g / n_rays, j = g - ti * n_rays;
+    float u = 0.f, w = 0.f;
+    octahedral(dirs[3 * (size_t)j], dirs[3 * (size_t)j + 1], dirs[3 * (size_t)j + 2], u, w);
+    const uint32_t dk = spread_bits8(cell_of(u, 256)) | (spread_bits8(cell_of(w, 256)) << 1);
+    const uint32_t cx = (uint32_t)fminf(fmaxf((tx[3 * ti] - lo.x) * scale.x, 0.f), 15.f);
+    const uint32_t cy = (uint32_t)fminf(fmaxf((tx[3 * ti + 1] - lo.y) * scale.y, 0.f), 15.f);
+    const uint32_t cz = (uint32_t)fminf(fmaxf((tx[3 * ti + 2] - lo.z) * scale.z, 0.f), 15.f);
+    const uint32_t m = spread_bits4x3(cx) | (spread_bits4x3(cy) << 1) | (spread_bits4x3(cz) << 2);
+    keys[g] = ((uint64_t)m << 16) | dk;
+    idx[g] = g;
 }
 
 template <int NL>
@@ -389,6 +569,90 @@ static int own_index(PcrlScene* S, hipStream_t s) {
     S->own_scan = scan;
     S->own_pos = pos;
     S->own_nrm = nrm;
+    return PCRL_OK;
+}
+
+// Defaults of the implicit surface for a scene (h, eps, max_steps as
+// sdf_intersect's when its parameters are not given).
+static void sdf_defaults(const PcrlScene* scene, SdfArgs& a) {
+    const float leaf = scene->view.h;
+    const float h = 0.95f * leaf;
+    a.v = scene->view;
+    a.max_steps = 64;
+    a.h2 = h * h;
+    a.hl2 = (h / leaf + 1e-3f) * (h / leaf + 1e-3f);
+    a.half_h = 0.5f * h;
+    a.eps = 1e-3f * leaf;
+    const float diag = sqrtf(3.0f) * leaf;
+    a.half_diam = 0.5f * diag;
+    a.reach = 1.5f * diag * (1.0f + 1e-5f) + 1e-3f * leaf;
+    a.empty = scene->info.n_points == 0;
+}
+
+template <int NL>
+static void launch_sdf_launch_nl(const SdfLaunchArgs& A, hipStream_t s) {
+    const unsigned grid = (A.n_total + SDF_BLOCK - 1) / SDF_BLOCK;
+    hipLaunchKernelGGL((k_sdf_launch<NL>), dim3(grid), dim3(SDF_BLOCK), 0, s, A);
+}
+
+int sdf_launch_run(PcrlLaunch* L, const TraceArgs& t) {
+    const PcrlScene* scene = L->scene;
+    hipStream_t s = L->stream;
+    if (L->stats || t.has_ov) {
+        set_error("launch_rays: PCRL_LAUNCH_SDF takes no PCRL_LAUNCH_STATS and no scene with dynamic points");
+        return PCRL_EINVAL;
+    }
+    SdfLaunchArgs A{};
+    sdf_defaults(scene, A.s);
+    if (!A.s.empty) {
+        PCRL_TRY(own_index(const_cast<PcrlScene*>(scene), s));
+        A.s.oscan = scene->own_scan;
+        A.s.opos = scene->own_pos;
+        A.s.onrm = scene->own_nrm;
+    }
+    A.tx = t.tx;
+    A.rx = t.rx;
+    A.dirs = t.dirs;
+    A.n_rx = t.n_rx;
+    A.K = t.K;
+    A.n_rays = t.n_rays;
+    A.n_total = t.n_total;
+    A.sig_c = t.sig_c;
+    A.hist = t.hist;
+    A.rec = t.rec;
+    A.rec_cap = t.rec_cap;
+    A.counters = t.counters;
+    A.hit_id = t.hit_id;
+    A.hit_t = t.hit_t;
+    if ((L->flags & PCRL_LAUNCH_COHERENT) && !A.s.empty) {
+        uint64_t* keys = nullptr;
+        uint32_t* idx = nullptr;
+        int rc = L->bufs.alloc(&keys, (size_t)A.n_total);
+        if (!rc) rc = L->bufs.alloc(&idx, (size_t)A.n_total);
+        if (rc) return rc;
+        const SceneView& v = scene->view;
+        const float3 lo = make_float3(v.org[0], v.org[1], v.org[2]);
+        const float3 sc = make_float3(16.f / (v.hi[0] - v.org[0]), 16.f / (v.hi[1] - v.org[1]),
+                                      16.f / (v.hi[2] - v.org[2]));
+        hipLaunchKernelGGL(k_sdf_launch_keys, dim3((A.n_total + 255) / 256), dim3(256), 0, s, A.tx, A.dirs, A.n_rays,
+                           A.n_total, lo, sc, keys, idx);
+        PCRL_TRY_HIP(hipGetLastError());
+        PCRL_TRY(radix_sort_u64_bits(keys, idx, (int64_t)A.n_total, 0, 28, s));
+        A.order = idx;
+    }
+    const bool timing = !L->events.empty();
+    if (timing) PCRL_TRY_HIP(hipEventRecord(L->events[0], s));
+    switch (scene->view.nlev) {
+    case 1: launch_sdf_launch_nl<1>(A, s); break;
+    case 2: launch_sdf_launch_nl<2>(A, s); break;
+    case 3: launch_sdf_launch_nl<3>(A, s); break;
+    default: launch_sdf_launch_nl<4>(A, s); break;
+    }
+    PCRL_TRY_HIP(hipGetLastError());
+    if (timing) {
+        // one kernel runs every segment: its time is reported as bounce 0's
+        for (size_t e = 1; e < L->events.size(); ++e) PCRL_TRY_HIP(hipEventRecord(L->events[e], s));
+    }
     return PCRL_OK;
 }
 

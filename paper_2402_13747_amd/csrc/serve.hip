@@ -392,8 +392,8 @@ extern "C" int serve_submit(PcrlServer* S, const float* tx, int32_t n_tx, const 
         return PCRL_EINVAL;
     }
     if (p->directions || p->hit_log_id || p->hit_log_t || p->n_rays < 1 || p->max_reflections < 0 ||
-        p->max_reflections > PCRL_MAX_REFLECTIONS) {
-        set_error("serve_submit: served queries use Fibonacci directions, no hit logs, 0 <= K <= 8");
+        p->max_reflections > PCRL_MAX_REFLECTIONS || (p->flags & PCRL_LAUNCH_SDF)) {
+        set_error("serve_submit: served queries use Fibonacci directions, surfels (no PCRL_LAUNCH_SDF), no hit logs, 0 <= K <= 8");
         return PCRL_EINVAL;
     }
     ServeReq* r = new (std::nothrow) ServeReq();

@@ -332,7 +332,8 @@ extern "C" int launch_rays(const PcrlScene* scene, const float* tx, int32_t n_tx
     PCRL_TRY(launch_prepare(scene, tx, n_tx, rx, n_rx, p, (hipStream_t)stream, true, &L, &a));
     // coherence order of the later bounces (results do not depend on it)
     int rc = PCRL_OK;
-    if (L->K > 0 && (p->flags & PCRL_LAUNCH_COHERENT) && L->n_total >= RESORT_MIN_RAYS) {
+    if (L->K > 0 && (p->flags & PCRL_LAUNCH_COHERENT) && !(p->flags & PCRL_LAUNCH_SDF) &&
+        L->n_total >= RESORT_MIN_RAYS) {
         uint32_t* order = nullptr;
         rc = L->bufs.alloc(&order, (size_t)L->n_total);
         if (!rc) rc = L->bufs.alloc(&a.okeys, (size_t)L->n_total);
@@ -344,7 +345,7 @@ extern "C" int launch_rays(const PcrlScene* scene, const float* tx, int32_t n_tx
         a.kscale = make_float3(16.f / (v.hi[0] - v.org[0]), 16.f / (v.hi[1] - v.org[1]), 16.f / (v.hi[2] - v.org[2]));
         a.order = order;
     }
-    if (!rc) rc = launch_run(L, a);
+    if (!rc) rc = (p->flags & PCRL_LAUNCH_SDF) ? sdf_launch_run(L, a) : launch_run(L, a);
     if (rc) {
         destroy_launch(L);
         return rc;

@@ -745,4 +745,8 @@ __device__ __forceinline__ uint32_t xcd_block() {
     return xcd * per + min(xcd, extra) + (bx >> 3);
 }
 
+// A launch whose segments end at the implicit surface of Eq. 1 instead of the
+// surfels (PCRL_LAUNCH_SDF; sdf.hip): runs every segment of every ray.
+int sdf_launch_run(PcrlLaunch* L, const TraceArgs& t);
+
 }  // namespace pcrl
