@@ -597,6 +597,23 @@ def main():
                 n_cpu *= 4
             sdf["cpu_baseline"] = {"value": round(n_cpu / dt, 1), "unit": "rays/s", "cores": oracle.default_threads(),
                                    "kind": "oracle", "sample": f"{n_cpu} of the {n_sdf} directions"}
+        # a whole coarse launch (every segment, K reflections) on the implicit surface,
+        # then its dedup: PCRL_LAUNCH_SDF
+        ltimes, lp = [], None
+        for _ in range(3):
+            torch.cuda.synchronize()
+            t1 = time.perf_counter()
+            sl = pcrl.launch_rays(scene, tx, rx, n_rays=s.n_rays, max_reflections=K, sdf=True)
+            lp = pcrl.collect_paths(sl, kappa=args.kappa)
+            torch.cuda.synchronize()
+            ltimes.append(time.perf_counter() - t1)
+            st_l = sl.stats()
+            sl.release()
+        l_ms = 1e3 * float(np.median(ltimes))
+        sdf["launch"] = {"rays": n_total, "max_reflections": K, "ms": round(l_ms, 3),
+                         "rays_per_s": round(n_total / (l_ms * 1e-3), 1), "active": st_l["active"][: K + 1],
+                         "records": int(st_l["records"]), "paths": {"rows": int(lp["n_rows"]), "keys": int(lp["n_keys"])},
+                         "step": "launch_rays(PCRL_LAUNCH_SDF) + collect_paths, wall clock"}
         log(f"[bench] sdf: {sdf}")
         scene.release()
 
