@@ -254,11 +254,6 @@ static int run_graph(const std::vector<BatchCtl>& host_ctl, const std::vector<Ba
 
 static int batch_impl(const PcrlQuery* q, int32_t n_q, const PcrlBatchParams* bp, hipStream_t s, PcrlLaunch** out) {
     for (int i = 0; i < n_q; ++i) out[i] = nullptr;
-    for (int i = 0; i < n_q; ++i)
-        if (q[i].params.flags & PCRL_LAUNCH_SDF) {
-            set_error("launch_batch: query %d asks for PCRL_LAUNCH_SDF, which only launch_rays runs", i);
-            return PCRL_EINVAL;
-        }
     auto shared = std::make_shared<BatchShared>();
     shared->bufs.stream = s;
     std::vector<TraceArgs> args((size_t)n_q);
@@ -460,11 +455,16 @@ static int validate_batch(const PcrlQuery* q, int32_t n_q, PcrlLaunch** out, con
         set_error("%s: need queries, n_q >= 1 and an output array", fn);
         return PCRL_EINVAL;
     }
-    for (int i = 0; i < n_q; ++i)
+    for (int i = 0; i < n_q; ++i) {
         if (!q[i].scene) {
             set_error("%s: query %d has no scene", fn, i);
             return PCRL_EINVAL;
         }
+        if (q[i].params.flags & PCRL_LAUNCH_SDF) {
+            set_error("%s: query %d asks for PCRL_LAUNCH_SDF, which only launch_rays runs", fn, i);
+            return PCRL_EINVAL;
+        }
+    }
     return PCRL_OK;
 }
 

@@ -108,6 +108,13 @@ def test_version_and_validation_without_gpu(pcrl):
     assert b"refine_paths" in lib.last_error()
     assert lib.sdf_intersect(None, None, None, None, 1, None, None, None, None, None, None) == _lib.PCRL_EINVAL
     assert b"sdf_intersect" in lib.last_error()
+    # the implicit-surface launch is launch_rays' only: batches refuse it before touching a scene
+    q = _lib.PcrlQuery()
+    q.scene = 1
+    q.params.flags = _lib.LAUNCH_SDF
+    outs = (C.c_void_p * 1)()
+    assert lib.launch_batch(C.byref(q), 1, None, None, outs) == _lib.PCRL_EINVAL
+    assert b"PCRL_LAUNCH_SDF" in lib.last_error()
     assert lib.release_scene(None) == 0 and lib.release_launch(None) == 0
     # the library's own allocator is the default and can always be restored
     assert lib.set_allocator(None) == _lib.PCRL_OK
