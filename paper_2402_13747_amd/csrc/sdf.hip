@@ -254,6 +254,15 @@ __device__ __forceinline__ void sdf_first_hit(const SdfArgs& a, const float o[3]
             t_in = fmaxf(t_in, tf);
         }
     }
+    // Every leaf whose segment starts at or before t_lo marches from t_lo: the
+    // same samples, cut at different far ends.  One shared march serves them
+    // all: a leaf whose far end it has already passed, or after it found an
+    // intersection or stopped (step limit, nothing nearer possible), adds
+    // nothing; a leaf reaching further resumes it.  Exact: the nearest over
+    // these leaves is unchanged.
+    float c_t = t_lo, c_fp = 0.f, c_tp = 0.f, c_tb = -INFINITY;
+    bool c_prev = false, c_done = false;
+    int c_s = 0;
     while (walking) {
         DdaCell k;
         dda_cell_reset(k);
@@ -268,13 +277,27 @@ __device__ __forceinline__ void sdf_first_hit(const SdfArgs& a, const float o[3]
         if (at_leaf && t_in <= t_hi && own_box_centre(a, o0, o1, c)) {
             reads += o1 - o0;
             const float tc = (c[0] - o[0]) * d[0] + (c[1] - o[1]) * d[1] + (c[2] - o[2]) * d[2];
+            const bool shared = tc - a.half_diam <= t_lo;
             float t = fmaxf(tc - a.half_diam, t_lo);
             const float tb = fminf(tc + a.half_diam, t_hi);
             float fp = 0.f, tp = 0.f;
             bool prev = false;
-            for (int s = 0; s < a.max_steps && t <= tb; ++s) {
+            int s = 0;
+            bool stop = false;  // the march ended by an intersection, the step limit or `best`
+            if (shared) {
+                if (c_done || tb <= c_tb) s = a.max_steps;  // nothing new from this leaf
+                t = c_t;
+                fp = c_fp;
+                tp = c_tp;
+                prev = c_prev;
+                if (s < a.max_steps) s = c_s;
+            }
+            for (; s < a.max_steps && t <= tb; ++s) {
                 // every later result of this leaf lies at or beyond t
-                if (t >= best && !(prev && tp < best)) break;
+                if (t >= best && !(prev && tp < best)) {
+                    stop = true;
+                    break;
+                }
                 const float x[3] = {o[0] + t * d[0], o[1] + t * d[1], o[2] + t * d[2]};
                 float f, n[3];
                 ++evals;
@@ -299,12 +322,22 @@ __device__ __forceinline__ void sdf_first_hit(const SdfArgs& a, const float o[3]
                         bc[1] = S.c[1];
                         bc[2] = S.c[2];
                     }
+                    stop = true;
                     break;
                 }
                 prev = true;
                 fp = f;
                 tp = t;
                 t += fabsf(f);
+            }
+            if (shared && !c_done && tb > c_tb) {
+                c_t = t;
+                c_fp = fp;
+                c_tp = tp;
+                c_prev = prev;
+                c_s = s;
+                c_tb = tb;
+                c_done = stop || s >= a.max_steps;
             }
         }
         float te;
