@@ -215,25 +215,30 @@ __device__ __forceinline__ uint32_t spread_bits8(uint32_t x) {
 // scene (12 bits) above the Morton code of its direction's cell on a 256 x 256
 // octahedral grid (16 bits).  Sorting by it puts rays that start close
 // together in close directions into the same waves, which then march the same
-// leaves (shared cache lines, similar step counts).
+// leaves (shared cache lines, similar step counts).  The octahedral map only
+// needs the direction's signs and ratios, so d need not be normalised.
+__device__ __forceinline__ uint64_t coherence_key(const float o[3], const float d[3], float3 lo, float3 scale) {
+    float u = 0.f, w = 0.f;
+    octahedral(d[0], d[1], d[2], u, w);
+    const uint32_t dk = spread_bits8(cell_of(u, 256)) | (spread_bits8(cell_of(w, 256)) << 1);
+    const uint32_t cx = (uint32_t)fminf(fmaxf((o[0] - lo.x) * scale.x, 0.f), 15.f);
+    const uint32_t cy = (uint32_t)fminf(fmaxf((o[1] - lo.y) * scale.y, 0.f), 15.f);
+    const uint32_t cz = (uint32_t)fminf(fmaxf((o[2] - lo.z) * scale.z, 0.f), 15.f);
+    const uint32_t m = spread_bits4x3(cx) | (spread_bits4x3(cy) << 1) | (spread_bits4x3(cz) << 2);
+    return ((uint64_t)m << 16) | dk;
+}
+
 __global__ void k_sdf_keys(const float* o, const float* d, uint32_t n, float3 lo, float3 scale, uint64_t* keys,
                            uint32_t* idx) {
     const uint32_t j = blockIdx.x * blockDim.x + threadIdx.x;
     if (j >= n) return;
-    const float x = d[3 * (size_t)j], y = d[3 * (size_t)j + 1], z = d[3 * (size_t)j + 2];
-    float u = 0.f, w = 0.f;
-    octahedral(x, y, z, u, w);  // the map only needs the direction's signs and ratios
-    const uint32_t dk = spread_bits8(cell_of(u, 256)) | (spread_bits8(cell_of(w, 256)) << 1);
-    const uint32_t cx = (uint32_t)fminf(fmaxf((o[3 * (size_t)j] - lo.x) * scale.x, 0.f), 15.f);
-    const uint32_t cy = (uint32_t)fminf(fmaxf((o[3 * (size_t)j + 1] - lo.y) * scale.y, 0.f), 15.f);
-    const uint32_t cz = (uint32_t)fminf(fmaxf((o[3 * (size_t)j + 2] - lo.z) * scale.z, 0.f), 15.f);
-    const uint32_t m = spread_bits4x3(cx) | (spread_bits4x3(cy) << 1) | (spread_bits4x3(cz) << 2);
-    keys[j] = ((uint64_t)m << 16) | dk;
+    const size_t j3 = 3 * (size_t)j;
+    const float oj[3] = {o[j3], o[j3 + 1], o[j3 + 2]};
+    const float dj[3] = {d[j3], d[j3 + 1], d[j3 + 2]};
+    keys[j] = coherence_key(oj, dj, lo, scale);
     idx[j] = j;
 }
 
-// Nearest intersection of the ray o + t d (d unit) in [t_lo, t_hi]: best = t
-// (+inf if none), with the normal bn and the leaf cell bc (-1 if none).
 template <int NL>
 __device__ __forceinline__ void sdf_first_hit(const SdfArgs& a, const float o[3], const float d[3], float t_lo,
                                               float t_hi, float& best, float bn[3], int bc[3], uint32_t& evals,
@@ -535,20 +540,15 @@ __global__ __launch_bounds__(SDF_BLOCK) void k_sdf_launch(SdfLaunchArgs A) {
     }
 }
 
-// Coherence key of global ray g (TX cell, direction cell; see k_sdf_keys).
+// Coherence key of global ray g of a launch (its TX and launch direction).
 __global__ void k_sdf_launch_keys(const float* tx, const float* dirs, uint32_t n_rays, uint32_t n_total, float3 lo,
                                   float3 scale, uint64_t* keys, uint32_t* idx) {
     const uint32_t g = blockIdx.x * blockDim.x + threadIdx.x;
     if (g >= n_total) return;
     const uint32_t ti = g / n_rays, j = g - ti * n_rays;
-    float u = 0.f, w = 0.f;
-    octahedral(dirs[3 * (size_t)j], dirs[3 * (size_t)j + 1], dirs[3 * (size_t)j + 2], u, w);
-    const uint32_t dk = spread_bits8(cell_of(u, 256)) | (spread_bits8(cell_of(w, 256)) << 1);
-    const uint32_t cx = (uint32_t)fminf(fmaxf((tx[3 * ti] - lo.x) * scale.x, 0.f), 15.f);
-    const uint32_t cy = (uint32_t)fminf(fmaxf((tx[3 * ti + 1] - lo.y) * scale.y, 0.f), 15.f);
-    const uint32_t cz = (uint32_t)fminf(fmaxf((tx[3 * ti + 2] - lo.z) * scale.z, 0.f), 15.f);
-    const uint32_t m = spread_bits4x3(cx) | (spread_bits4x3(cy) << 1) | (spread_bits4x3(cz) << 2);
-    keys[g] = ((uint64_t)m << 16) | dk;
+    const float o[3] = {tx[3 * ti], tx[3 * ti + 1], tx[3 * ti + 2]};
+    const float d[3] = {dirs[3 * (size_t)j], dirs[3 * (size_t)j + 1], dirs[3 * (size_t)j + 2]};
+    keys[g] = coherence_key(o, d, lo, scale);
     idx[g] = g;
 }
 
