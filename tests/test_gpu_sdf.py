@@ -123,11 +123,14 @@ def test_box_room_rays_from_tx(env):
     assert fin.mean() > 0.99  # a closed room: every ray meets a wall
 
 
-@pytest.mark.parametrize("seed", [1, 2, 3])
+RANDOM_LEVELS = {1: (0.4, 0.2, 0.1), 2: (0.1,), 3: (0.4, 0.2, 0.1), 7: (0.8, 0.4, 0.2, 0.1)}
+
+
+@pytest.mark.parametrize("seed", [1, 2, 3, 7])
 def test_random_scenes(env, seed):
+    """Hierarchies of 3, 1, 3 and 4 levels."""
     rng = np.random.default_rng(100 + seed)
-    s = scenes.random_scene(seed, extent=2.0, h=0.05, levels=(0.4, 0.2, 0.1) if seed != 2 else (0.1,),
-                            pos_sigma=0.002, tilt_sigma=0.03)
+    s = scenes.random_scene(seed, extent=2.0, h=0.05, levels=RANDOM_LEVELS[seed], pos_sigma=0.002, tilt_sigma=0.03)
     scene = _build(env, s)
     n = 2000
     o = rng.uniform(0.0, 2.0, size=(n, 3)).astype(np.float32)
@@ -223,12 +226,16 @@ def _launch_case(case):
     # (scene, rays per TX, K, reception sphere scale sigma)
     if case == "box_room":
         return scenes.box_room(), 3000, 2, 1.25
+    if case == "box_room_one_level":
+        s = scenes.box_room()
+        s.levels = (0.25,)
+        return s, 3000, 3, 1.25
     # seed 8: four of the six RX see the TX directly
     s = scenes.random_scene(8, extent=2.0, h=0.05, levels=(0.4, 0.2), pos_sigma=0.002, tilt_sigma=0.03, n_rx=6)
     return s, 6000, 3, 4.0
 
 
-@pytest.mark.parametrize("case", ["box_room", "random"])
+@pytest.mark.parametrize("case", ["box_room", "box_room_one_level", "random"])
 def test_sdf_launch_parity(env, case):
     """launch_rays with PCRL_LAUNCH_SDF against oracle.sdf_launch: per ray,
     segment by segment while the oracle's answer is stable (as in _compare,
