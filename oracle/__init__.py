@@ -22,10 +22,14 @@ definition of what the HIP path computes and shares no code with it.
 * ``sdf_intersect(...)`` ray intersection with the implicit surface of Eq. 1
                          by marching line segments through occupied leaves
                          (``sdf.c``)
+* ``sdf_launch(...)``    a coarse launch whose segments end at that surface
+                         (FP64 ray state, nearest-point labels, reception as
+                         in ``launch``)
 
 Parity unpinned: sigma (reception sphere scale), r_s (surfel radius) and
 t_eps (self-intersection distance) are conventions the paper does not fix;
-they are pinned only by the shared definition.
+they are pinned only by the shared definition.  Likewise the implicit surface's kernel
+weights, h, eps, max_steps and the restart offset after a reflection.
 """
 from __future__ import annotations
 
