@@ -30,6 +30,7 @@ constexpr int64_t SDF_ORDER_MIN = 65536;  // rays from which a call sorts them i
 
 struct SdfArgs {
     SceneView v;
+    SceneView ov;          // v with leaf and cell ranges into the own entries (neighbour lookups)
     const float* o;        // [n][3]
     const float* d;        // [n][3]
     const float* tr;       // [n][2] (t_lo, t_hi), or null for (0, inf)
@@ -129,11 +130,10 @@ __device__ __forceinline__ bool sdf_eval(const SdfArgs& a, const float x[3], flo
             continue;
         DdaCell k;
         dda_cell_reset(k);
-        dda_locate<false, NL>(v, N, k, nullptr);
+        dda_locate<false, NL>(a.ov, N, k, nullptr);
         if (k.lvl != NL || k.range.y == 0u) continue;
-        const uint32_t e0 = a.oscan[k.range.x], e1 = a.oscan[k.range.x + k.range.y];
-        reads += e1 - e0;
-        sdf_accumulate(a, x, e0, e1, sw, sp, sn);
+        reads += k.range.y;
+        sdf_accumulate(a, x, k.range.x, k.range.x + k.range.y, sw, sp, sn);
     }
     const float ln = sqrtf(sn[0] * sn[0] + sn[1] * sn[1] + sn[2] * sn[2]);
     if (!(sw > 0.f) || !(ln > 0.f)) return false;
@@ -423,10 +423,10 @@ __device__ __forceinline__ bool nearest_own(const SdfArgs& a, const float x[3], 
             continue;
         DdaCell k;
         dda_cell_reset(k);
-        dda_locate<false, NL>(v, N, k, nullptr);
+        dda_locate<false, NL>(a.ov, N, k, nullptr);
         if (k.lvl != NL || k.range.y == 0u) continue;
-        const uint32_t e1 = a.oscan[k.range.x + k.range.y];
-        for (uint32_t e = a.oscan[k.range.x]; e < e1; ++e) {
+        const uint32_t e1 = k.range.x + k.range.y;
+        for (uint32_t e = k.range.x; e < e1; ++e) {
             const float4 P = a.opos[e];
             const float ex = P.x - x[0], ey = P.y - x[1], ez = P.z - x[2];
             const float d2 = ex * ex + ey * ey + ez * ez;
@@ -558,6 +558,47 @@ static void launch_sdf_nl(const SdfArgs& a, hipStream_t s) {
     hipLaunchKernelGGL((k_sdf<NL>), dim3(grid), dim3(SDF_BLOCK), 0, s, a);
 }
 
+// Entry ranges (first, count) of a leaf table or a dense cell table turned
+// into ranges of own entries; an entry with count 0 (an empty cell's skip
+// radius) is kept as it is.
+__global__ void k_own_ranges(const uint2* in, uint32_t n, const uint32_t* scan, uint2* out) {
+    const uint32_t i = blockIdx.x * blockDim.x + threadIdx.x;
+    if (i >= n) return;
+    const uint2 r = in[i];
+    out[i] = r.y ? make_uint2(scan[r.x], scan[r.x + r.y] - scan[r.x]) : r;
+}
+
+// The integer block of the own-point index: the scan [n_entries + 1], then
+// (8-byte aligned) the own range of every leaf and, where the scene has a
+// dense cell table, that table with own ranges.
+struct OwnLayout {
+    size_t leaf_off, n_leaves, cells_off, n_cells, bytes;
+};
+
+static OwnLayout own_layout(const PcrlScene* S) {
+    const SceneView& v = S->view;
+    OwnLayout L{};
+    L.leaf_off = ((size_t)(S->info.n_entries + 1) * sizeof(uint32_t) + 7) / 8 * 8;
+    L.n_leaves = v.nn[v.nlev - 1];
+    L.cells_off = L.leaf_off + L.n_leaves * sizeof(uint2);
+    if (v.cells && v.nlev >= 2) {
+        const size_t r = (size_t)v.ratio[v.nlev - 2];
+        L.n_cells = (size_t)v.nn[v.nlev - 2] * r * r * r;
+    }
+    L.bytes = L.cells_off + L.n_cells * sizeof(uint2);
+    return L;
+}
+
+// The scene's view with its leaf and cell ranges pointing into the own entries.
+static SceneView own_view(const PcrlScene* S) {
+    const OwnLayout L = own_layout(S);
+    SceneView ov = S->view;
+    char* base = (char*)S->own_scan;
+    ov.leaf = (const uint2*)(base + L.leaf_off);
+    if (L.n_cells) ov.cells = (const uint2*)(base + L.cells_off);
+    return ov;
+}
+
 template <int NL>
 static void launch_own_flags(const SceneView& v, uint32_t m, uint32_t* flag, hipStream_t s) {
     hipLaunchKernelGGL((k_own_flags<NL>), dim3((unsigned)(((uint64_t)m + 255) / 256)), dim3(256), 0, s, v, m, flag);
@@ -570,9 +611,10 @@ static int own_index(PcrlScene* S, hipStream_t s) {
     std::lock_guard<std::mutex> lock(S->own_mu);
     if (S->own_scan) return PCRL_OK;
     const int64_t m = S->info.n_entries, np = S->info.n_points;
+    const OwnLayout lay = own_layout(S);
     uint32_t* scan = nullptr;
     float4 *pos = nullptr, *nrm = nullptr;
-    int rc = dalloc((void**)&scan, (size_t)(m + 1) * sizeof(uint32_t), s);
+    int rc = dalloc((void**)&scan, lay.bytes, s);
     if (!rc) rc = dalloc((void**)&pos, (size_t)(np > 0 ? np : 1) * sizeof(float4), s);
     if (!rc) rc = dalloc((void**)&nrm, (size_t)(np > 0 ? np : 1) * sizeof(float4), s);
     if (!rc) {
@@ -587,6 +629,12 @@ static int own_index(PcrlScene* S, hipStream_t s) {
     if (!rc) {
         hipLaunchKernelGGL(k_own_scatter, dim3((unsigned)((m + 255) / 256)), dim3(256), 0, s, S->view.spos,
                            S->view.snrm, scan, (uint32_t)m, (uint32_t)np, pos, nrm);
+        char* base = (char*)scan;
+        hipLaunchKernelGGL(k_own_ranges, dim3((unsigned)((lay.n_leaves + 255) / 256)), dim3(256), 0, s,
+                           S->view.leaf, (uint32_t)lay.n_leaves, scan, (uint2*)(base + lay.leaf_off));
+        if (lay.n_cells)
+            hipLaunchKernelGGL(k_own_ranges, dim3((unsigned)((lay.n_cells + 255) / 256)), dim3(256), 0, s,
+                               S->view.cells, (uint32_t)lay.n_cells, scan, (uint2*)(base + lay.cells_off));
         rc = hipGetLastError() == hipSuccess && hipStreamSynchronize(s) == hipSuccess ? PCRL_OK : PCRL_EHIP;
     }
     if (rc) {
@@ -642,6 +690,7 @@ int sdf_launch_run(PcrlLaunch* L, const TraceArgs& t) {
         A.s.oscan = scene->own_scan;
         A.s.opos = scene->own_pos;
         A.s.onrm = scene->own_nrm;
+        A.s.ov = own_view(scene);
     }
     A.tx = t.tx;
     A.rx = t.rx;
@@ -750,6 +799,7 @@ extern "C" int sdf_intersect(const PcrlScene* scene, const float* o, const float
         a.oscan = scene->own_scan;
         a.opos = scene->own_pos;
         a.onrm = scene->own_nrm;
+        a.ov = own_view(scene);
     }
     DevBufs T;
     T.stream = s;
