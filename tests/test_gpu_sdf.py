@@ -349,6 +349,11 @@ def test_edge_cases(env):
     assert torch.isinf(r["t"]).all()
     # dynamic points are not part of the surface
     ids = torch.arange(s.n_points, s.n_points + 4, dtype=torch.int32)
+    # the SDF launch takes no traversal statistics
+    with pytest.raises(pcrl.PcrlError):
+        pcrl.launch_rays(scene, s.tx, s.rx, n_rays=100, max_reflections=1, sdf=True, stats=True)
     scene.update_points(ids, s.xyz[:4], s.normal[:4], s.label[:4])
     with pytest.raises(pcrl.PcrlError):
         pcrl.sdf_intersect(scene, o, d)
+    with pytest.raises(pcrl.PcrlError):
+        pcrl.launch_rays(scene, s.tx, s.rx, n_rays=100, max_reflections=1, sdf=True)
