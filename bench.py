@@ -4,9 +4,11 @@
 One step is one pass of the whole hot path over a synthetic scene already
 resident in HBM: build_voxels (voxel hierarchy) -> launch_rays (all bounces)
 -> collect_paths (dedup, kappa = 100 as in the paper's Table 1).  The
-default workload is the furnished room: 12 x 10 x 3 m plus 30 boxes,
-~1M points, 20 labels, 1 TX, 16 RX, 1M Fibonacci rays, K = 3, voxel levels
-0.5 m / 0.05 m.
+default workload is the street canyon: 400 x 400 m ground plus 120 extruded
+buildings, ~20M points (a 6 GB voxelised scene, far beyond the caches), 50
+labels, 4 TX x 4M Fibonacci rays, 64 RX, K = 4, voxel levels 8 m / 1 m /
+0.1 m.  The furnished room (~1M points, 1M rays, K = 3) and the others are
+selected with --workload.
 
 Prints ONE JSON line: rays/s of whole steps, plus bounce-segments/s, the
 roofline of the dominant kernel (the bounce kernel: algorithmic bytes from
@@ -125,7 +127,10 @@ def cpu_dda_baseline(s, t_eps, seconds):
     dirs = oracle.fibonacci(s.n_rays)
     threads = oracle.default_threads()
     n_total = s.n_rays * len(s.tx)
-    cell = float(s.levels[-1])
+    # cubic cells of the finest level's edge, coarsened so that the dense grid
+    # holds at most 64M cells (the street canyon: 0.47 m instead of 0.1 m)
+    ext = (s.xyz.max(0).astype(np.float64) - s.xyz.min(0).astype(np.float64)) + 2 * float(s.surfel_radius)
+    cell = max(float(s.levels[-1]), float(np.prod(np.maximum(ext, 1e-3)) / 64e6) ** (1.0 / 3.0))
     t0 = time.perf_counter()
     grid = oracle.Grid(s.xyz, float(np.float32(s.surfel_radius)), cell)
     t_grid = time.perf_counter() - t0
@@ -161,13 +166,12 @@ def bench_batch(args, pcrl, torch):
     log(f"[batch] generating {n} scenes (point scale {args.batch_point_scale}, ray scale {args.batch_ray_scale})")
     with mp.get_context("fork").Pool(min(16, os.cpu_count() or 1)) as pool:
         specs = pool.map(_gen_batch_scene, [(s, args.batch_point_scale, args.batch_ray_scale) for s in range(n)])
-    from tests.parity import t_eps_of
     queries = []
     total_rays = 0
     total_points = 0
     for k, s in enumerate(specs):
         sc = pcrl.build_voxels(s.xyz, s.normal, s.label, s.levels, float(np.float32(s.surfel_radius)),
-                               t_eps=float(np.float32(t_eps_of(s))), device=dev)
+                               t_eps=float(np.float32(s.t_eps_value)), device=dev)
         sc._inputs = None
         queries.append(dict(scene=sc, tx=s.tx, rx=s.rx, n_rays=s.n_rays, max_reflections=s.max_reflections))
         total_rays += s.n_rays * len(s.tx)
@@ -398,7 +402,7 @@ def main():
     ap.add_argument("--gpus", type=int, default=1)
     ap.add_argument("--steps", type=int, default=10)
     ap.add_argument("--warmup", type=int, default=3)
-    ap.add_argument("--workload", default="furnished_room",
+    ap.add_argument("--workload", default="street_canyon",
                     choices=["furnished_room", "box_room", "street_canyon", "furnished_room_dense",
                              "street_canyon_dense", "batch", "serve", "copy"])
     ap.add_argument("--copy-mib", type=int, default=1024)
@@ -425,7 +429,6 @@ def main():
     import torch
 
     import paper_2402_13747_amd as pcrl
-    from tests.parity import t_eps_of
 
     dev = torch.device("cuda", 0)
     torch.cuda.set_device(dev)
@@ -439,7 +442,7 @@ def main():
     s = make_workload(args.workload)
     K = s.max_reflections
     n_total = s.n_rays * len(s.tx)
-    t_eps = float(np.float32(t_eps_of(s)))
+    t_eps = float(np.float32(s.t_eps_value))
     r_s = float(np.float32(s.surfel_radius))
     xyz = torch.from_numpy(s.xyz).to(dev)
     nrm = torch.from_numpy(s.normal).to(dev)
@@ -520,6 +523,8 @@ def main():
                 "frac": round(achieved / HBM_PEAK_GBS, 4),
                 "traffic": None if traffic is None else round(traffic),
                 "traffic_unit": "HBM bytes per launch (rocprofv3 FETCH_SIZE + WRITE_SIZE, copy-calibrated)",
+                "hbm_gbs": None if traffic is None else round(traffic / (launch_ms * 1e-3) / 1e9, 2),
+                "hbm_frac": None if traffic is None else round(traffic / (launch_ms * 1e-3) / 1e9 / HBM_PEAK_GBS, 4),
                 "kernel": "k_trace<false,false> (bounce kernel, one launch per bounce 1..K)",
                 "copy_gbs": round(copy_gbs, 1), "frac_of_copy": round(achieved / copy_gbs, 4),
                 "launches_per_step": len(bl), "algo_bytes_per_launch": int(launch_bytes),

@@ -47,7 +47,7 @@ _HERE = os.path.dirname(os.path.abspath(__file__))
 _SO = os.path.join(_HERE, "liboracle.so")
 _SRC = os.path.join(_HERE, "oracle.c")
 _SRCS = [_SRC, os.path.join(_HERE, "sdf.c")]
-MAXACC = 16
+MAXACC = 64
 
 
 def _stale() -> bool:

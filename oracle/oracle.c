@@ -42,7 +42,7 @@
 #include <stdlib.h>
 #include <string.h>
 
-#define ORACLE_MAXACC 16
+#define ORACLE_MAXACC 64
 #define ORACLE_DEN_SKIP 1e-12
 #define ORACLE_MAXN 8           /* most reflections of a refined path */
 
@@ -230,6 +230,9 @@ static void nearest_hit(const OracleArgs* a, const Pts64* P, const double* o, co
     double tc = INFINITY;
     for (int pass = 0; pass < 2; ++pass) {
         int32_t na = 0;
+        /* "no hit" is acceptable when no clear hit exists; it is stored
+         * first, so a set larger than the array never drops it */
+        if (pass == 1 && tc == INFINITY) acc_id[na++] = -1;
         for (int64_t m = 0; m < a->n_pts; ++m) {
             if (m == last) continue;
             double den = d[0] * P->nx[m] + d[1] * P->ny[m] + d[2] * P->nz[m];
@@ -260,13 +263,7 @@ static void nearest_hit(const OracleArgs* a, const Pts64* P, const double* o, co
                 }
             }
         }
-        if (pass == 1) {
-            if (tc == INFINITY) {
-                if (na < ORACLE_MAXACC) acc_id[na] = -1;
-                ++na;
-            }
-            *acc_n = na;
-        }
+        if (pass == 1) *acc_n = na;
     }
 }
 

@@ -58,6 +58,17 @@ class Scene:
     def n_points(self) -> int:
         return int(self.xyz.shape[0])
 
+    @property
+    def t_eps_value(self) -> float:
+        """The self-intersection distance a launch on this scene uses: the
+        scene's own, else 1e-5 x the diagonal of the points' bounding box."""
+        if self.t_eps > 0:
+            return float(self.t_eps)
+        if self.xyz.size == 0:
+            return 1e-6
+        lo, hi = self.xyz.min(0).astype(np.float64), self.xyz.max(0).astype(np.float64)
+        return max(1e-5 * math.sqrt(float(((hi - lo) ** 2).sum())), 1e-6)
+
 
 # ----------------------------------------------------------------------------
 # face sampling

@@ -1,10 +1,14 @@
-"""Batched launching: every query's result equals its solo launch, bitwise.
+"""Batched launching: every query's result matches the FP64 oracle and equals
+its solo launch, bitwise.
 
 Queries differ in scene (room, canyon, random planes; 1-3 voxel levels), ray
 count (ragged, not multiples of the tile), K, TX and RX counts.  The batch is
 run under several tile sizes, compaction thresholds (always in place, mixed,
 always compacted), occupancies, in graph mode (replayed several times with
-eager work in between) and with the autotuner.
+eager work in between) and with the autotuner.  Each query of a batched launch
+is also compared with the oracle directly (hit ids per ray and segment,
+reception records and lengths, coarse-path keys), with the rule of
+tests/parity.py.
 """
 import numpy as np
 import pytest
@@ -22,6 +26,11 @@ def env():
         pytest.skip("no GPU")
     import paper_2402_13747_amd as pcrl
     return torch, pcrl
+
+
+# rays of each query of the workload traced by the oracle: None = all of them,
+# else an evenly spaced sample of that many global ray ids
+ORACLE_SAMPLE = [1500, 1200, None, None, None, 2000]
 
 
 @pytest.fixture(scope="module")
@@ -49,13 +58,64 @@ def workload(env):
     for q in queries:
         L = pcrl.launch_rays(**q)
         solo.append(_result(pcrl, L))
-    return queries, solo
+    return queries, solo, [s for s, _ in built]
+
+
+@pytest.fixture(scope="module")
+def oracle_runs(workload):
+    """The oracle's launch of every query of the workload (parity mode)."""
+    import oracle
+    oracle.build(force=False)
+    _, _, specs = workload
+    out = []
+    for s, n_sel in zip(specs, ORACLE_SAMPLE):
+        n_total = s.n_rays * len(s.tx)
+        sel = None if n_sel is None else np.unique(np.linspace(0, n_total - 1, n_sel).astype(np.int64))
+        print(f"[batch] oracle for {s.name}: {n_total if sel is None else len(sel)} rays", flush=True)
+        out.append(oracle.launch(s.xyz, s.normal, s.label, s.tx, s.rx, oracle.fibonacci(s.n_rays),
+                                 K=s.max_reflections, r_s=float(np.float32(s.surfel_radius)),
+                                 t_eps=float(np.float32(s.t_eps_value)), sel=sel, parity=True,
+                                 **parity.fp32_bands(s.xyz, s.tx, s.rx)))
+    return out
 
 
 def _result(pcrl, L):
     p = parity.to_numpy(pcrl.collect_paths(L, kappa=1 << 30))
     return {"paths": p, "hits": L.hit_log[0].cpu().numpy(), "t": L.hit_log[1].cpu().numpy(),
-            "active": L.stats()["active"]}
+            "active": L.stats()["active"], "records": parity.to_numpy(L.records())}
+
+
+def _check_oracle(s, res, orc, full):
+    """One query's device result against the oracle: per-ray hits and records by
+    the parity rule; with every ray traced by the oracle, also the coarse-path
+    keys (each unambiguous oracle key is a device key, and each device key is an
+    oracle key, ambiguous ones included)."""
+    import oracle
+    K = s.max_reflections
+    n_total = s.n_rays * len(s.tx)
+    ids = res["hits"].reshape(n_total, K + 1)
+    rep = parity.compare(orc, ids, res["records"], s.xyz, s.normal, s.label, K)
+    print(f"  [batch vs oracle] {s.name}: {rep.summary()}", flush=True)
+    assert rep.ok(), (rep.mismatch[:5], rep.record_missing[:5], rep.record_extra[:5], rep.length_bad[:5],
+                      rep.overflow[:5])
+    assert rep.exact + rep.equivalent >= 0.95 * rep.segments
+    if not full:
+        return rep
+    dev = parity.device_paths(res["paths"])
+    _, keys_any, _ = oracle.dedup(orc, K, include_ambiguous=True)
+    live = set()
+    for q in range(orc["n_rec"]):
+        g, b = int(orc["rec_g"][q]), int(orc["rec_b"][q])
+        if orc["rec_flags"][q] == 1 and not (g in rep.diverged and b >= rep.diverged[g]):
+            r = int(orc["rec_sel"][q])
+            live.add((int(orc["rec_tx"][q]), int(orc["rec_rx"][q]), b, tuple(int(x) for x in orc["seq"][r, :b])))
+    assert live <= set(dev), sorted(live - set(dev))[:5]
+    # a device key the oracle never produced is carried only by rays that left
+    # the comparison (an excused near tie on another surface) by that bounce
+    for key in set(dev) - set(keys_any):
+        for row in dev[key]:
+            assert row["ray"] in rep.diverged and rep.diverged[row["ray"]] <= key[2], (key, row)
+    return rep
 
 
 def _same(a, b):
@@ -73,7 +133,7 @@ def _same(a, b):
                                               (192, 0.6, 1)])
 def test_batch_equals_solo(env, workload, tile, theta, waves):
     torch, pcrl = env
-    queries, solo = workload
+    queries, solo, _ = workload
     print(f"[batch] tile={tile} theta={theta} waves={waves}", flush=True)
     launches = pcrl.launch_batch(queries, tile_rays=tile, compact_threshold=theta, waves_per_cu=waves)
     for L, ref in zip(launches, solo):
@@ -82,7 +142,7 @@ def test_batch_equals_solo(env, workload, tile, theta, waves):
 
 def test_batch_graph_replays(env, workload):
     torch, pcrl = env
-    queries, solo = workload
+    queries, solo, _ = workload
     for rep in range(3):
         print(f"[batch] graph replay {rep}", flush=True)
         launches = pcrl.launch_batch(queries, tile_rays=512, compact_threshold=0.6, waves_per_cu=16, use_graph=True)
@@ -98,7 +158,7 @@ def test_batch_graph_replays(env, workload):
 
 def test_batch_autotune(env, workload):
     torch, pcrl = env
-    queries, solo = workload
+    queries, solo, _ = workload
     best = pcrl.batch_autotune(queries[:3])
     assert best["tile_rays"] in (256, 1024, 4096) and best["waves_per_cu"] in (8, 16, 32)
     launches = pcrl.launch_batch(queries, autotune=True)
@@ -108,7 +168,7 @@ def test_batch_autotune(env, workload):
 
 def test_batch_timing_and_stats(env, workload):
     torch, pcrl = env
-    queries, solo = workload
+    queries, solo, _ = workload
     qs = [dict(q, timing=True, stats=True) for q in queries]
     launches = pcrl.launch_batch(qs, tile_rays=256)
     st = [L.stats() for L in launches]
@@ -121,8 +181,28 @@ def test_batch_timing_and_stats(env, workload):
 
 def test_batch_errors(env, workload):
     torch, pcrl = env
-    queries, _ = workload
+    queries, _, _ = workload
     bad = dict(queries[0], max_reflections=9)
     with pytest.raises(pcrl.PcrlError) as e:
         pcrl.launch_batch([queries[1], bad])
     assert "query 1" in str(e.value)
+
+
+@pytest.mark.parametrize("tile,theta,waves,graph", [(256, 0.6, 16, False), (1024, 2.0, 8, True), (64, 0.0, 4, False)])
+def test_batch_matches_oracle(env, workload, oracle_runs, tile, theta, waves, graph):
+    """Every query of a batched launch (persistent work-queue kernel, in-place or
+    compacted survivors, graph replay) against the FP64 oracle: the box room and
+    the random scenes over all their rays, the rooms and the canyon on samples."""
+    torch, pcrl = env
+    queries, _, specs = workload
+    print(f"[batch] vs oracle: tile={tile} theta={theta} waves={waves} graph={graph}", flush=True)
+    launches = pcrl.launch_batch(queries, tile_rays=tile, compact_threshold=theta, waves_per_cu=waves,
+                                 use_graph=graph)
+    checked = 0
+    for L, s, orc, n_sel in zip(launches, specs, oracle_runs, ORACLE_SAMPLE):
+        rep = _check_oracle(s, _result(pcrl, L), orc, full=n_sel is None)
+        checked += rep.records_checked
+    # the box room's coarse paths are the 25 image-method sequences (<= 2 reflections)
+    box = _result(pcrl, launches[3])
+    assert len(parity.device_paths(box["paths"])) == 25
+    assert checked > 50

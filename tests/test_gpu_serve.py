@@ -1,7 +1,9 @@
 """Incremental re-voxelisation and the serving loop.
 
 * base (static points) + overlay (moving points) traces bitwise like a scene
-  rebuilt from all points, frame after frame;
+  rebuilt from all points, frame after frame, and matches the FP64 oracle run
+  over all points of that frame;
+* a served query's records match the oracle's on sampled rays;
 * every served query's result equals the same query launched alone on the
   same epoch, also when queries overlap on the device and when the scene
   changes between admission rounds;
@@ -187,4 +189,102 @@ def test_serve_cancel(env, world):
         srv.cancel(1 << 40)
     assert e.value.status == -1
     assert srv.stats()["completed"] == 4
+    srv.close()
+
+
+def _frame_points(sc, n_static, xyz, nrm):
+    """All points of a frame, indexed by their global ids (static, then moving)."""
+    return (np.ascontiguousarray(np.concatenate([sc.xyz[:n_static], xyz]), np.float32),
+            np.ascontiguousarray(np.concatenate([sc.normal[:n_static], nrm]), np.float32))
+
+
+def test_overlay_matches_oracle(env, world):
+    """The overlay kernel variant (base hierarchy, then the dynamic points' overlay)
+    against the oracle's brute force over all points of the frame, per ray and
+    segment on a sample of rays aimed at the moving boxes and at random."""
+    import oracle
+    oracle.build(force=False)
+    torch, pcrl = env
+    sc, mover, base, n_static, r_s, t_eps = world
+    idx, xyz, nrm = mover(5)
+    base.update_points(idx.astype(np.uint32), xyz, nrm, sc.label[idx])
+    n_rays, K = 30_000, 3
+    rx = sc.rx[:4]
+    L = pcrl.launch_rays(base, sc.tx, rx, n_rays=n_rays, max_reflections=K, hit_log=True)
+    ids = L.hit_log[0].cpu().numpy().reshape(n_rays * len(sc.tx), K + 1)
+    rec = parity.to_numpy(L.records())
+    # rays whose first hit is a moving point, plus an even sample
+    moving_first = np.nonzero(ids[:, 0] >= n_static)[0]
+    assert len(moving_first) > 20
+    sel = np.union1d(moving_first[:: max(1, len(moving_first) // 400)], np.linspace(0, n_rays - 1, 1200).astype(np.int64))
+    allx, alln = _frame_points(sc, n_static, xyz, nrm)
+    print(f"[serve] overlay vs oracle: {len(sel)} rays over {len(allx)} points", flush=True)
+    orc = oracle.launch(allx, alln, sc.label, sc.tx, rx, oracle.fibonacci(n_rays), K=K, r_s=r_s, t_eps=t_eps, sel=sel,
+                        parity=True, **parity.fp32_bands(allx, sc.tx, rx))
+    rep = parity.compare(orc, ids, rec, allx, alln, sc.label, K)
+    print(f"  [overlay vs oracle] {rep.summary()}", flush=True)
+    assert rep.ok(), (rep.mismatch[:5], rep.record_missing[:5], rep.record_extra[:5], rep.length_bad[:5],
+                      rep.overflow[:5])
+    assert rep.exact + rep.equivalent >= 0.95 * rep.segments
+    hit_moving = sum(int(np.any((orc["hit_id"][r] >= n_static))) for r in range(len(sel)))
+    assert hit_moving > 20
+
+
+def test_served_matches_oracle(env, world):
+    """Queries served together (overlapping rounds on the device) against the
+    oracle: on sampled rays whose every segment has a single acceptable answer
+    in the oracle, the served rows (every record, kappa unbounded) are exactly
+    the oracle's receptions, with the oracle's labels and lengths to 1e-5."""
+    import oracle
+    oracle.build(force=False)
+    torch, pcrl = env
+    sc, mover, base, n_static, r_s, t_eps = world
+    idx, xyz, nrm = mover(9)
+    allx, alln = _frame_points(sc, n_static, xyz, nrm)
+    srv = pcrl.Server(base, n_streams=3, max_batch=4, kappa=1 << 30)
+    srv.update(idx.astype(np.uint32), xyz, nrm, sc.label[idx])
+    rng = np.random.default_rng(4)
+    qs = _queries(sc, rng, 5) + [dict(tx=sc.tx, rx=sc.rx[:3], n_rays=70_001, max_reflections=3)]
+    tickets = [srv.submit(**q) for q in qs]
+    checked = 0
+    for t, q in zip(tickets, qs):
+        assert srv.poll(t, timeout=120.0)["status"] == 2
+        res = srv.result(t)
+        K, n_rays = q["max_reflections"], q["n_rays"]
+        sel = np.linspace(0, n_rays - 1, 600).astype(np.int64)
+        orc = oracle.launch(allx, alln, sc.label, q["tx"], q["rx"], oracle.fibonacci(n_rays), K=K, r_s=r_s,
+                            t_eps=t_eps, sel=sel, parity=True, **parity.fp32_bands(allx, q["tx"], q["rx"]))
+        stable = {}
+        for r, g in enumerate(sel):
+            traced = orc["hit_id"][r] != -2
+            stable[int(g)] = bool(np.all(orc["acc_n"][r][traced] == 1))
+        want = {}
+        for k in range(orc["n_rec"]):
+            g = int(orc["rec_g"][k])
+            if not stable[g]:
+                continue
+            b = int(orc["rec_b"][k])
+            key = (g, int(orc["rec_rx"][k]), b)
+            r = int(orc["rec_sel"][k])
+            want[key] = (int(orc["rec_flags"][k]), tuple(int(x) for x in orc["seq"][r, :b]),
+                         float(orc["rec_lpoly"][k]), float(orc["rec_lunf"][k]))
+        have = {}
+        for i in range(int(res["n_rows"])):
+            g = int(res["ray"][i])
+            if g in stable and stable[g]:
+                b = int(res["n_refl"][i])
+                have[(g, int(res["rx"][i]), b)] = (tuple(int(x) for x in np.asarray(res["key"][i])[:b]),
+                                                  float(res["len_poly"][i]), float(res["len_unf"][i]))
+        for key, (flags, seq, lp, lu) in want.items():
+            if flags == 1:
+                assert key in have, key
+            if key in have:
+                dseq, dlp, dlu = have[key]
+                assert dseq == seq, (key, dseq, seq)
+                assert abs(dlp - lp) <= 1e-5 * lp and abs(dlu - lu) <= 1e-5 * lu, (key, dlp, lp, dlu, lu)
+                checked += 1
+        assert set(have) <= set(want), sorted(set(have) - set(want))[:5]
+        print(f"  [served vs oracle] {n_rays} rays K={K}: stable {sum(stable.values())}/{len(sel)}, "
+              f"records {len(have)}", flush=True)
+    assert checked >= 10
     srv.close()
