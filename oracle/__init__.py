@@ -74,7 +74,7 @@ class OracleArgs(C.Structure):
         ("parity", C.c_int32), ("tie_rel", C.c_double), ("err_abs", C.c_double), ("err_dir", C.c_double),
         ("edge_rel", C.c_double), ("den_amb", C.c_double), ("n_threads", C.c_int32),
         ("hit_id", C.c_void_p), ("hit_t", C.c_void_p), ("acc_n", C.c_void_p), ("acc_id", C.c_void_p),
-        ("seg_o", C.c_void_p), ("seg_d", C.c_void_p),
+        ("acc_tc", C.c_void_p), ("seg_o", C.c_void_p), ("seg_d", C.c_void_p),
         ("seq", C.c_void_p), ("pts", C.c_void_p),
         ("rec_cap", C.c_int64), ("n_rec", C.c_int64),
         ("rec_sel", C.c_void_p), ("rec_g", C.c_void_p), ("rec_tx", C.c_void_p), ("rec_rx", C.c_void_p),
@@ -139,6 +139,9 @@ def _load():
         lib.oracle_ray_spacing.restype = C.c_double
         lib.oracle_launch.argtypes = [C.POINTER(OracleArgs)]
         lib.oracle_launch.restype = C.c_int
+        lib.oracle_accepts.argtypes = [C.POINTER(OracleArgs), C.c_void_p, C.c_void_p, C.c_int32, C.c_int64,
+                                       C.c_double, C.c_int64]
+        lib.oracle_accepts.restype = C.c_int
         lib.oracle_refine.argtypes = [C.POINTER(OracleRefineArgs)]
         lib.oracle_refine.restype = C.c_int
         lib.oracle_sdf_intersect.argtypes = [C.POINTER(OracleSdfArgs)]
@@ -231,7 +234,8 @@ def launch(xyz, normal, label, tx, rx, dirs, K, r_s, t_eps, sigma=1.25, alpha=0.
     if parity:
         out["acc_n"] = np.zeros((n_trace, S), np.int32)
         out["acc_id"] = np.full((n_trace, S, MAXACC), -3, np.int64)
-    if want_segments:
+        out["acc_tc"] = np.full((n_trace, S), np.nan)
+    if want_segments or parity:
         out["seg_o"] = np.full((n_trace, S, 3), np.nan)
         out["seg_d"] = np.full((n_trace, S, 3), np.nan)
     cap = rec_cap if rec_cap is not None else max(1024, 4 * n_trace)
@@ -254,6 +258,7 @@ def launch(xyz, normal, label, tx, rx, dirs, K, r_s, t_eps, sigma=1.25, alpha=0.
         a.hit_id, a.hit_t = _p(out["hit_id"]), _p(out["hit_t"])
         a.acc_n = _p(out.get("acc_n"))
         a.acc_id = _p(out.get("acc_id"))
+        a.acc_tc = _p(out.get("acc_tc"))
         a.seg_o, a.seg_d = _p(out.get("seg_o")), _p(out.get("seg_d"))
         a.seq = _p(out["seq"]) if K > 0 else None
         a.pts = _p(out["pts"]) if K > 0 else None
@@ -273,8 +278,33 @@ def launch(xyz, normal, label, tx, rx, dirs, K, r_s, t_eps, sigma=1.25, alpha=0.
         out["n_rec"] = n
         out["alpha"] = alpha if alpha > 0 else ray_spacing(n_rays)
         out["sel"] = sel if sel is not None else np.arange(n_trace, dtype=np.int64)
+        if parity:
+            out["_bands"] = dict(xyz=xyz, normal=normal, n_pts=xyz.shape[0], r_s=r_s, t_eps=t_eps,
+                                 tie_rel=tie_rel, err_abs=err_abs, err_dir=err_dir, edge_rel=edge_rel,
+                                 den_amb=den_amb)
         return out
     raise RuntimeError("record capacity retry failed")
+
+
+def accepts(res, r, b, m):
+    """Whether point m (or -1, no hit) is in the acceptable set of segment b
+    of traced ray r of a parity-mode ``launch`` result.  The result stores
+    only the first MAXACC members of each set; this decides membership for
+    any point with the same band test."""
+    lib = _load()
+    bd = res["_bands"]
+    a = OracleArgs()
+    a.xyz, a.nrm, a.n_pts = _p(bd["xyz"]), _p(bd["normal"]), bd["n_pts"]
+    a.r_s, a.t_eps = bd["r_s"], bd["t_eps"]
+    a.tie_rel, a.err_abs, a.err_dir = bd["tie_rel"], bd["err_abs"], bd["err_dir"]
+    a.edge_rel, a.den_amb = bd["edge_rel"], bd["den_amb"]
+    o = np.ascontiguousarray(res["seg_o"][r, b], np.float64)
+    d = np.ascontiguousarray(res["seg_d"][r, b], np.float64)
+    last = int(res["hit_id"][r, b - 1]) if b > 0 else -1
+    rc = lib.oracle_accepts(C.byref(a), _p(o), _p(d), int(b), last, float(res["acc_tc"][r, b]), int(m))
+    if rc < 0:
+        raise ValueError("oracle_accepts: bad arguments")
+    return bool(rc)
 
 
 def dedup(res, K, kappa=1, include_ambiguous=False):

@@ -80,6 +80,7 @@ typedef struct {
     double* hit_t;             /* +inf: no hit */
     int32_t* acc_n;            /* size of the acceptable set (parity) */
     int64_t* acc_id;           /* [.. * ORACLE_MAXACC], -1 stands for "no hit" */
+    double* acc_tc;            /* nearest clear hit of the segment (+inf: none), for oracle_accepts */
     double* seg_o;             /* optional [.. * 3] segment origin */
     double* seg_d;             /* optional [.. * 3] segment direction */
     /* per traced ray and reflection k = 0..K-1: index r*K + k */
@@ -192,11 +193,42 @@ typedef struct {
 
 static inline double dot3(const double* u, const double* v) { return u[0] * v[0] + u[1] * v[1] + u[2] * v[2]; }
 
+/* Parity bands of one surfel for the segment o + t d (segment index b,
+ * bb = b + 1).  A surfel is ambiguous when one of its thresholds (disk edge,
+ * t_eps, grazing incidence) lies within the error band of the compared
+ * implementation; it is a candidate when it is a hit by the definition.
+ * Returns 0 when the surfel is clearly not a hit under any band (then the
+ * outputs are unset). */
+static int surfel_class(const OracleArgs* a, const double* p, const double* n, const double* o,
+                        const double* d, double bb, double* t_out, double* band_out, int* cand, int* amb)
+{
+    double den = d[0] * n[0] + d[1] * n[1] + d[2] * n[2];
+    if (fabs(den) <= ORACLE_DEN_SKIP) return 0;
+    double wx = p[0] - o[0], wy = p[1] - o[1], wz = p[2] - o[2];
+    double t = (wx * n[0] + wy * n[1] + wz * n[2]) / den;
+    double qx = o[0] + t * d[0] - p[0];
+    double qy = o[1] + t * d[1] - p[1];
+    double qz = o[2] + t * d[2] - p[2];
+    double dist = sqrt(qx * qx + qy * qy + qz * qz);
+    /* position error of the compared ray at this distance, projected into
+     * the disk plane (grows as 1/|den| at grazing incidence) */
+    double band = bb * (a->err_abs + fabs(t) * a->err_dir) * (1.0 + 1.0 / fabs(den));
+    double band_r = band + a->edge_rel * a->r_s;
+    double band_t = band + a->edge_rel * a->t_eps;
+    if (dist > a->r_s + band_r) return 0;          /* clearly outside the disk */
+    if (t <= a->t_eps - band_t) return 0;          /* clearly behind / too close */
+    *cand = (t > a->t_eps) && (dist <= a->r_s);
+    *amb = (fabs(den) <= a->den_amb) || (fabs(dist - a->r_s) <= band_r) || (fabs(t - a->t_eps) <= band_t);
+    *t_out = t;
+    *band_out = band;
+    return 1;
+}
+
 /* One segment: the exact nearest hit (definition), and in parity mode the
  * set of answers compatible with the error bands. */
 static void nearest_hit(const OracleArgs* a, const Pts64* P, const double* o, const double* d,
                         int64_t last, int32_t b, int64_t* best_out, double* tb_out,
-                        int32_t* acc_n, int64_t* acc_id)
+                        int32_t* acc_n, int64_t* acc_id, double* acc_tc, double* acc_tlo, double* acc_thi)
 {
     const double rs2 = a->r_s * a->r_s;
     int64_t best = -1;
@@ -221,50 +253,41 @@ static void nearest_hit(const OracleArgs* a, const Pts64* P, const double* o, co
     *tb_out = tb;
     if (!a->parity) return;
 
-    /* Parity mode.  A surfel is ambiguous when one of its thresholds lies
-     * within the error band of the compared implementation; a clear
-     * candidate is a hit that no band can undo.  Acceptable answers: every
-     * clear or ambiguous surfel whose t does not exceed the nearest clear
-     * hit by more than the tie window, plus "no hit" if no clear hit. */
+    /* Parity mode: the acceptable set, its extent in t and the nearest clear
+     * hit.  Only the first ORACLE_MAXACC members are stored; membership of any
+     * other point is decided by oracle_accepts with the same tc. */
     const double bb = (double)(b + 1);
     double tc = INFINITY;
-    for (int pass = 0; pass < 2; ++pass) {
-        int32_t na = 0;
-        /* "no hit" is acceptable when no clear hit exists; it is stored
-         * first, so a set larger than the array never drops it */
-        if (pass == 1 && tc == INFINITY) acc_id[na++] = -1;
-        for (int64_t m = 0; m < a->n_pts; ++m) {
-            if (m == last) continue;
-            double den = d[0] * P->nx[m] + d[1] * P->ny[m] + d[2] * P->nz[m];
-            if (fabs(den) <= ORACLE_DEN_SKIP) continue;
-            double wx = P->px[m] - o[0], wy = P->py[m] - o[1], wz = P->pz[m] - o[2];
-            double t = (wx * P->nx[m] + wy * P->ny[m] + wz * P->nz[m]) / den;
-            double qx = o[0] + t * d[0] - P->px[m];
-            double qy = o[1] + t * d[1] - P->py[m];
-            double qz = o[2] + t * d[2] - P->pz[m];
-            double dist = sqrt(qx * qx + qy * qy + qz * qz);
-            /* position error of the compared ray at this distance, projected
-             * into the disk plane (grows as 1/|den| at grazing incidence) */
-            double band = bb * (a->err_abs + fabs(t) * a->err_dir) * (1.0 + 1.0 / fabs(den));
-            double band_r = band + a->edge_rel * a->r_s;
-            double band_t = band + a->edge_rel * a->t_eps;
-            if (dist > a->r_s + band_r) continue;         /* clearly outside the disk */
-            if (t <= a->t_eps - band_t) continue;         /* clearly behind / too close */
-            int cand = (t > a->t_eps) && (dist <= a->r_s);
-            int amb = (fabs(den) <= a->den_amb) || (fabs(dist - a->r_s) <= band_r) ||
-                      (fabs(t - a->t_eps) <= band_t);
-            if (pass == 0) {
-                if (cand && !amb && t < tc) tc = t;
-            } else {
-                double win = tc * (1.0 + a->tie_rel) + band;
-                if (t <= win && (cand || amb)) {
-                    if (na < ORACLE_MAXACC) acc_id[na] = m;
-                    ++na;
-                }
-            }
-        }
-        if (pass == 1) *acc_n = na;
+    for (int64_t m = 0; m < a->n_pts; ++m) {
+        if (m == last) continue;
+        const double pm[3] = {P->px[m], P->py[m], P->pz[m]}, nm[3] = {P->nx[m], P->ny[m], P->nz[m]};
+        double t, band;
+        int cand, amb;
+        if (!surfel_class(a, pm, nm, o, d, bb, &t, &band, &cand, &amb)) continue;
+        if (cand && !amb && t < tc) tc = t;
     }
+    int32_t na = 0;
+    double t_lo = INFINITY, t_hi = -INFINITY;
+    /* "no hit" is acceptable when no clear hit exists; it is stored first,
+     * so a set larger than the array never drops it */
+    if (tc == INFINITY) { acc_id[na++] = -1; t_hi = INFINITY; }
+    for (int64_t m = 0; m < a->n_pts; ++m) {
+        if (m == last) continue;
+        const double pm[3] = {P->px[m], P->py[m], P->pz[m]}, nm[3] = {P->nx[m], P->ny[m], P->nz[m]};
+        double t, band;
+        int cand, amb;
+        if (!surfel_class(a, pm, nm, o, d, bb, &t, &band, &cand, &amb)) continue;
+        if (t <= tc * (1.0 + a->tie_rel) + band && (cand || amb)) {
+            if (na < ORACLE_MAXACC) acc_id[na] = m;
+            ++na;
+            if (t < t_lo) t_lo = t;
+            if (t > t_hi) t_hi = t;
+        }
+    }
+    *acc_n = na;
+    *acc_tc = tc;
+    *acc_tlo = t_lo;
+    *acc_thi = t_hi;
 }
 
 /* The hit test of point m (same formula as the brute force). */
@@ -449,25 +472,20 @@ static void trace_range(Work* w)
             double tb;
             int32_t na = 1;
             int64_t acc[ORACLE_MAXACC];
+            double tc = INFINITY, t_lo = INFINITY, t_hi = -INFINITY;
             if (a->grid && !a->parity) nearest_hit_grid(a, P, a->grid, o, d, last, &best, &tb);
-            else nearest_hit(a, P, o, d, last, b, &best, &tb, &na, acc);
+            else nearest_hit(a, P, o, d, last, b, &best, &tb, &na, acc, &tc, &t_lo, &t_hi);
             if (a->hit_id) a->hit_id[s_idx] = best;
             if (a->hit_t) a->hit_t[s_idx] = tb;
             if (a->seg_o) { a->seg_o[3 * s_idx] = o[0]; a->seg_o[3 * s_idx + 1] = o[1]; a->seg_o[3 * s_idx + 2] = o[2]; }
             if (a->seg_d) { a->seg_d[3 * s_idx] = d[0]; a->seg_d[3 * s_idx + 1] = d[1]; a->seg_d[3 * s_idx + 2] = d[2]; }
-            double t_lo = tb, t_hi = tb;
             if (a->parity) {
+                if (t_lo > tb) t_lo = tb;
+                if (t_hi < tb) t_hi = tb;
                 if (a->acc_n) a->acc_n[s_idx] = na;
-                for (int32_t q = 0; q < na && q < ORACLE_MAXACC; ++q) {
+                if (a->acc_tc) a->acc_tc[s_idx] = tc;
+                for (int32_t q = 0; q < na && q < ORACLE_MAXACC; ++q)
                     if (a->acc_id) a->acc_id[s_idx * ORACLE_MAXACC + q] = acc[q];
-                    if (acc[q] < 0) { t_hi = INFINITY; continue; }
-                    int64_t m = acc[q];
-                    double den = d[0] * P->nx[m] + d[1] * P->ny[m] + d[2] * P->nz[m];
-                    double t = ((P->px[m] - o[0]) * P->nx[m] + (P->py[m] - o[1]) * P->ny[m] +
-                                (P->pz[m] - o[2]) * P->nz[m]) / den;
-                    if (t < t_lo) t_lo = t;
-                    if (t > t_hi) t_hi = t;
-                }
             }
             /* reception on [0, tb] */
             const double bb = (double)(b + 1);
@@ -590,6 +608,28 @@ int oracle_launch(OracleArgs* a)
     return status;
 }
 
+/* Membership of point m in the acceptable set of one segment (parity mode):
+ * the segment starts at o with unit direction d (FP64, as the oracle traced
+ * it), has index b, left point `last` and nearest clear hit tc (acc_tc).
+ * The same test as the set nearest_hit builds, for sets too large to store.
+ * Returns 1 or 0, -1 on bad arguments. */
+int oracle_accepts(const OracleArgs* a, const double* o, const double* d, int32_t b, int64_t last,
+                   double tc, int64_t m)
+{
+    if (!a || !o || !d || m < -1 || m >= a->n_pts || b < 0) return -1;
+    if (m == -1) return tc == INFINITY;
+    if (m == last) return 0;
+    double n[3] = {a->nrm[3 * m], a->nrm[3 * m + 1], a->nrm[3 * m + 2]};
+    double len = sqrt(n[0] * n[0] + n[1] * n[1] + n[2] * n[2]);
+    if (!(len > 0.0) || !isfinite(len)) return -1;
+    n[0] /= len; n[1] /= len; n[2] /= len;
+    const double p[3] = {a->xyz[3 * m], a->xyz[3 * m + 1], a->xyz[3 * m + 2]};
+    double t, band;
+    int cand, amb;
+    if (!surfel_class(a, p, n, o, d, (double)(b + 1), &t, &band, &cand, &amb)) return 0;
+    return t <= tc * (1.0 + a->tie_rel) + band && (cand || amb);
+}
+
 /* ------------------------------------------------------------------------ */
 /* path refinement (Section 2.3, Eq. 2)                                      */
 /* ------------------------------------------------------------------------ */
@@ -707,7 +747,8 @@ static int trace_towards(const OracleArgs* A, const Pts64* P, const double* o, c
     double tb;
     int32_t na;
     int64_t acc[ORACLE_MAXACC];
-    nearest_hit(A, P, o, d, last, 0, &best, &tb, &na, acc);
+    double tc, t_lo, t_hi;
+    nearest_hit(A, P, o, d, last, 0, &best, &tb, &na, acc, &tc, &t_lo, &t_hi);
     if (t_out) *t_out = tb;
     if (best < 0) return 0;
     c[0] = o[0] + tb * d[0]; c[1] = o[1] + tb * d[1]; c[2] = o[2] + tb * d[2];

@@ -339,6 +339,50 @@ def test_parity_sets_contain_exact_answer(oracle_lib):
     assert np.mean(r["acc_n"][traced] == 1) > 0.8
 
 
+def test_acceptable_set_beyond_the_stored_array(oracle_lib):
+    """A ray that grazes a row of 200 coplanar surfels at |d.n| = 1e-9: every surfel lies at the
+    same t and inside the projected error band, so every one of them, and "no hit" (no clear hit
+    exists), is acceptable: 201 members, more than the stored array holds.  oracle.accepts decides
+    the members that were not stored."""
+    n = 200
+    xyz = np.zeros((n, 3), np.float32)
+    xyz[:, 0] = 0.1 * np.arange(n, dtype=np.float32)
+    nrm = np.tile(np.array([0, 0, 1], np.float32), (n, 1))
+    lab = np.zeros(n, np.uint32)
+    d = np.array([[1.0, 0.0, -1e-9]], np.float32)
+    tx = np.array([[-1.0, 0.0, 1e-8]], np.float32)
+    r = oracle_lib.launch(xyz, nrm, lab, tx, np.zeros((0, 3), np.float32), d, K=0, r_s=0.075, t_eps=1e-5,
+                          parity=True, err_abs=1e-6, err_dir=1e-6)
+    assert r["acc_n"][0, 0] == n + 1
+    assert r["acc_id"][0, 0, 0] == -1
+    assert all(oracle_lib.accepts(r, 0, 0, m) for m in range(-1, n))
+    # a steep ray over the same row: one clear hit, nothing else acceptable
+    d2 = np.array([[0.6, 0.0, -0.8]], np.float32)
+    tx2 = np.array([[5.0, 0.0, 4.0]], np.float32)        # hits x = 8, the centre of surfel 80
+    r2 = oracle_lib.launch(xyz, nrm, lab, tx2, np.zeros((0, 3), np.float32), d2, K=0, r_s=0.075, t_eps=1e-5,
+                           parity=True, err_abs=1e-6, err_dir=1e-6)
+    assert r2["hit_id"][0, 0] == 80 and r2["acc_n"][0, 0] == 1
+    assert [m for m in range(-1, n) if oracle_lib.accepts(r2, 0, 0, m)] == [80]
+
+
+def test_accepts_equals_the_stored_sets(oracle_lib):
+    """Where a set fits the array, oracle.accepts agrees with it for every point and for "no hit"."""
+    s = scenes.random_scene(5, tilt_sigma=0.0, pos_sigma=0.0, n_rays=60)
+    d = oracle_lib.fibonacci(s.n_rays)
+    r = oracle_lib.launch(s.xyz, s.normal, s.label, s.tx, s.rx, d, K=2, r_s=s.surfel_radius, t_eps=1e-4,
+                          parity=True, err_abs=1e-5, err_dir=1e-5)
+    checked = 0
+    for ray, b in zip(*np.nonzero(r["hit_id"] > -2)):
+        na = int(r["acc_n"][ray, b])
+        if na > oracle_lib.MAXACC:
+            continue
+        stored = set(int(x) for x in r["acc_id"][ray, b, :na])
+        got = {m for m in range(-1, s.n_points) if oracle_lib.accepts(r, ray, b, m)}
+        assert got == stored, (ray, b)
+        checked += 1
+    assert checked > 50
+
+
 # --------------------------------------------------------------------------- acceleration exactness
 
 def _axis_and_diagonal_dirs():
