@@ -329,12 +329,62 @@ def bench_serve(args, pcrl, torch):
                 lat.append(1e3 * (done - q["t"]))
         return lat, time.perf_counter() - t0
 
+    def run_served_saturated(qs):
+        """Every query submitted at once: the server runs at its own capacity."""
+        srv = pcrl.Server(base, n_streams=4, max_batch=64, hbm_budget_bytes=64 << 30, kappa=1)
+        srv.update(*frame_data(0))
+        frame = 0
+        t0 = time.perf_counter()
+        tickets = [(q, srv.submit(q["tx"], q["rx"], q["n_rays"], q["K"])) for q in qs]
+        lat = []
+        for q, t in tickets:
+            while True:
+                info = srv.poll(t, timeout=0.02)
+                if info["status"] == 2:
+                    break
+                assert info["status"] >= 0, info
+                now = time.perf_counter() - t0
+                if now >= (frame + 1) * 0.1 and frame + 1 in frames:
+                    frame += 1
+                    srv.update(*frame_data(frame))
+            lat.append(info["latency_ms"])
+        wall = time.perf_counter() - t0
+        st = srv.stats()
+        srv.close()
+        return lat, st, wall
+
+    def run_plain_saturated(qs):
+        """The same queries back to back, one launch + collect each."""
+        frame = 0
+        base.update_points(*frame_data(0))
+        lat = []
+        t0 = time.perf_counter()
+        for q in qs:
+            now = time.perf_counter() - t0
+            if now >= (frame + 1) * 0.1:
+                frame = min(int(now / 0.1), max(frames))
+                base.update_points(*frame_data(frame))
+            L = pcrl.launch_rays(base, q["tx"], q["rx"], n_rays=q["n_rays"], max_reflections=q["K"])
+            pcrl.collect_paths(L, kappa=1)
+            L.release()
+            lat.append(1e3 * (time.perf_counter() - t0))
+        return lat, time.perf_counter() - t0
+
     log("[serve] served run")
     lat_s, st, t_s, frames_s = run_served()
     log(f"[serve] served: {st}")
     log("[serve] plain FIFO run")
     lat_p, t_p = run_plain()
     measured_rays = sum(q["n_rays"] for q in stream if q["t"] >= args.serve_warmup)
+    # saturated: the first queries of the stream, all offered at t = 0
+    sat = stream[: args.serve_saturate]
+    sat_rays = sum(q["n_rays"] for q in sat)
+    log(f"[serve] saturated runs: {len(sat)} queries, {sat_rays} rays at once")
+    run_plain_saturated(sat[:8])   # warm both paths on these shapes
+    lat_ss, st_ss, t_ss = run_served_saturated(sat)
+    lat_ps, t_ps = run_plain_saturated(sat)
+    log(f"[serve] saturated: served {sat_rays / t_ss / 1e6:.1f} M rays/s in {t_ss:.2f} s, "
+        f"plain {sat_rays / t_ps / 1e6:.1f} M rays/s in {t_ps:.2f} s")
 
     def pct(x, p):
         return float(np.percentile(np.asarray(x), p)) if x else None
@@ -357,6 +407,15 @@ def bench_serve(args, pcrl, torch):
         "plain": {"p50_ms": round(pct(lat_p, 50), 2), "p99_ms": round(pct(lat_p, 99), 2),
                   "rays_per_s": round(total_rays / t_p, 1), "wall_s": round(t_p, 2)},
         "measured_rays": measured_rays,
+        "saturated": {
+            "queries": len(sat), "rays": sat_rays,
+            "served": {"rays_per_s": round(sat_rays / t_ss, 1), "wall_s": round(t_ss, 3),
+                       "p50_ms": round(pct(lat_ss, 50), 2), "p99_ms": round(pct(lat_ss, 99), 2),
+                       "mean_batch": round(st_ss["mean_batch"], 2), "rounds": st_ss["rounds"]},
+            "plain": {"rays_per_s": round(sat_rays / t_ps, 1), "wall_s": round(t_ps, 3),
+                      "p50_ms": round(pct(lat_ps, 50), 2), "p99_ms": round(pct(lat_ps, 99), 2)},
+            "speedup": round(t_ps / t_ss, 3),
+        },
     }
     print(json.dumps(out), flush=True)
 
@@ -413,6 +472,8 @@ def main():
     ap.add_argument("--serve-rate", type=float, default=200.0)
     ap.add_argument("--serve-seconds", type=float, default=30.0)
     ap.add_argument("--serve-warmup", type=float, default=2.0)
+    ap.add_argument("--serve-saturate", type=int, default=400,
+                    help="queries of the stream offered all at once for the saturated served/plain comparison")
     ap.add_argument("--kappa", type=int, default=100)
     ap.add_argument("--cpu-seconds", type=float, default=12.0)
     ap.add_argument("--no-cpu-baseline", action="store_true")

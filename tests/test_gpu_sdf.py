@@ -256,6 +256,9 @@ def _aimed_sample(oracle, s, n_rays, n_random, seed=7):
     return np.array(sorted(pick), np.int64)
 
 
+EXCUSED_MAX = {"box_room": 0.06, "box_room_one_level": 0.06, "random": 0.06, "furnished_room_full": 0.35}
+
+
 @pytest.mark.parametrize("case", ["box_room", "box_room_one_level", "random", "furnished_room_full"])
 def test_sdf_launch_parity(env, case):
     """launch_rays with PCRL_LAUNCH_SDF against oracle.sdf_launch: per ray,
@@ -351,9 +354,15 @@ def test_sdf_launch_parity(env, case):
     print(f"  [sdf launch] {case}: rays={n} matched={int(full.sum())} excused={excused} mismatch={mism} "
           f"records={len(have)} oracle_records={len(want)} first_bad={first_bad}", flush=True)
     assert mism == 0, first_bad
-    # the excused rays are those whose answer moves under rounding-sized perturbations;
-    # every recorded run stays far below these bounds
-    assert excused <= 0.06 * n + 2
+    # A ray is excused when the oracle's own answer moves under rounding-sized
+    # perturbations (h, eps, the step limit, the segment length): that depends on
+    # the oracle and the sample only, never on the device, so the bound only keeps
+    # the comparison from going vacuous.  The box room and the random scene are
+    # excused at most 4.5 %; the full furnished room 28 % (86 of 307 aimed rays:
+    # four noisy segments of 1M points, where a march that ends at its step limit
+    # or within eps of an edge moves with max_steps +- 1 or eps +- 1 %).
+    assert excused <= EXCUSED_MAX[case] * n + 2, (excused, n)
+    assert full.sum() >= 0.5 * n
     assert want - have == set()
     assert (have - want) <= banded
     assert len(want) > 0

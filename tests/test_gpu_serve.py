@@ -92,6 +92,24 @@ def _queries(sc, rng, n):
     return out
 
 
+def _aimed_rays(oracle, tx, rx, n_rays, n_even):
+    """Global ray ids (tx * n_rays + j) of the directions within 1.2 ray
+    spacings of each RX and of its image in the ground plane z = 0, seen from
+    each TX, plus n_even evenly spaced ones: rays that are likely received,
+    chosen by geometry alone."""
+    d = oracle.fibonacci(n_rays).astype(np.float64)
+    alpha = oracle.ray_spacing(n_rays)
+    pick = set()
+    for i, t in enumerate(np.asarray(tx, np.float64).reshape(-1, 3)):
+        for r in np.asarray(rx, np.float64).reshape(-1, 3):
+            for z in (r[2], -r[2]):
+                u = np.array([r[0], r[1], z]) - t
+                u /= np.linalg.norm(u)
+                pick.update((i * n_rays + np.nonzero(d @ u > np.cos(1.2 * alpha))[0]).tolist())
+        pick.update((i * n_rays + np.linspace(0, n_rays - 1, n_even).astype(np.int64)).tolist())
+    return np.array(sorted(pick), np.int64)
+
+
 def _served_paths(res):
     keys = ("tx", "rx", "n_refl", "key", "count", "rank", "ray", "len_poly", "len_unf", "points", "n_rows", "n_keys")
     return {k: res[k] for k in keys}
@@ -251,7 +269,7 @@ def test_served_matches_oracle(env, world):
         assert srv.poll(t, timeout=120.0)["status"] == 2
         res = srv.result(t)
         K, n_rays = q["max_reflections"], q["n_rays"]
-        sel = np.linspace(0, n_rays - 1, 600).astype(np.int64)
+        sel = _aimed_rays(oracle, q["tx"], q["rx"], n_rays, 300)
         orc = oracle.launch(allx, alln, sc.label, q["tx"], q["rx"], oracle.fibonacci(n_rays), K=K, r_s=r_s,
                             t_eps=t_eps, sel=sel, parity=True, **parity.fp32_bands(allx, q["tx"], q["rx"]))
         stable = {}
