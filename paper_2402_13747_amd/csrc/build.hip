@@ -320,6 +320,29 @@ __global__ void k_brick_base(const uint64_t* mask, const uint32_t* first_child, 
     }
 }
 
+// Box of the occupied children of every brick, in the brick's local child
+// coordinates (x + r (y + r z) order of the mask bits): lo x, y, z in bits
+// 0-14 and hi x, y, z in bits 15-29, 5 bits each (r <= 32).  Every child
+// outside the box is empty, so a ray in such a child crosses the brick's
+// empty rest up to the box or the brick's exit in one step.
+__global__ void k_brick_aabb(const uint64_t* mask, int64_t n_nodes, int nw, int r, uint32_t* aabb) {
+    const int64_t p = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (p >= n_nodes) return;
+    int lo0 = 31, lo1 = 31, lo2 = 31, hi0 = 0, hi1 = 0, hi2 = 0;
+    for (int w = 0; w < nw; ++w) {
+        uint64_t m = mask[(size_t)p * nw + w];
+        while (m) {
+            const int loc = 64 * w + __ffsll((long long)m) - 1;
+            m &= m - 1;
+            const int x = loc % r, y = (loc / r) % r, z = loc / (r * r);
+            lo0 = min(lo0, x); lo1 = min(lo1, y); lo2 = min(lo2, z);
+            hi0 = max(hi0, x); hi1 = max(hi1, y); hi2 = max(hi2, z);
+        }
+    }
+    aabb[p] = (uint32_t)lo0 | ((uint32_t)lo1 << 5) | ((uint32_t)lo2 << 10) | ((uint32_t)hi0 << 15) |
+              ((uint32_t)hi1 << 20) | ((uint32_t)hi2 << 25);
+}
+
 // Empty-space skip radius of every leaf cell of an occupied parent brick
 // (r^3 cells, r <= 16): R = 0 for an occupied leaf; otherwise the largest k
 // such that the cube of cells within Chebyshev distance k - 1 is empty and
@@ -790,6 +813,16 @@ static int build_hierarchy(const float* xyz, const float4* unit_nrm, const uint3
     for (int l = 0; l + 1 < L; ++l)
         hipLaunchKernelGGL(k_brick_base, dim3(blocks_for(host_nodes[l])), dim3(BUILD_BLOCK), 0, s, ho.mask[l],
                            ho.first_child[l], (int64_t)host_nodes[l], v.nw[l], (uint32_t*)v.base[l]);
+    for (int l = 0; l + 1 < L; ++l) {
+        v.baabb[l] = nullptr;
+        if (v.ratio[l] > 32 || host_nodes[l] == 0) continue;
+        uint32_t* ab = nullptr;
+        if ((rc = B.alloc(&ab, (size_t)host_nodes[l]))) return rc;
+        hipLaunchKernelGGL(k_brick_aabb, dim3(blocks_for(host_nodes[l])), dim3(BUILD_BLOCK), 0, s, ho.mask[l],
+                           (int64_t)host_nodes[l], v.nw[l], v.ratio[l], ab);
+        v.baabb[l] = ab;
+        hb.bytes += (int64_t)host_nodes[l] * 4;
+    }
     hipLaunchKernelGGL(k_leaf_counts, dim3(blocks_for(n_leaves)), dim3(BUILD_BLOCK), 0, s, leaf, n_leaves, m);
     v.leaf = leaf;
     hb.leaf_range = leaf;
@@ -967,6 +1000,7 @@ static int overlay_impl(PcrlScene* S, const uint32_t* gid, const float* xyz, con
     for (int l = 0; l + 1 < PCRL_MAX_LEVELS; ++l) {
         v.mask[l] = nullptr;
         v.base[l] = nullptr;
+        v.baabb[l] = nullptr;
     }
     v.leaf = nullptr;
     v.ldist = nullptr;

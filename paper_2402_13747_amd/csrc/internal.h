@@ -197,6 +197,9 @@ struct SceneView {
     const int32_t* map0;             // [dim0 x*y*z] level-0 node or -1
     const uint64_t* mask[PCRL_MAX_LEVELS - 1];  // child occupancy bricks of level i
     const uint32_t* base[PCRL_MAX_LEVELS - 1];  // child index of the first set bit of each word
+    const uint32_t* baabb[PCRL_MAX_LEVELS - 1]; // null, or per node of level i the box of its occupied
+                                                // children (local coordinates, 5 bits each: lo x, y, z,
+                                                // then hi x, y, z; ratio <= 32)
     const uint2* leaf;               // per leaf: (first entry, entry count)
     const uint8_t* ldist;            // null, or per leaf cell of each parent brick its empty-space skip radius
     const uint8_t* dist0;            // null, or per level-0 cell its empty-space skip radius (level-0 cells)

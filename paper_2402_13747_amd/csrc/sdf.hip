@@ -111,6 +111,7 @@ __device__ __forceinline__ bool sdf_eval(const SdfArgs& a, const float x[3], flo
     N.cq[0] = N.cq[1] = N.cq[2] = -1;
     N.cres = 0;
     N.cskip0 = 1;
+    N.cbox = NO_BOX;
     N.cnode = 0;
     N.oct_shift = 0;
     // one rolled loop over the 27 leaves (unrolled, the lookups would multiply the registers)
@@ -181,6 +182,7 @@ __global__ void k_own_flags(SceneView v, uint32_t m, uint32_t* flag) {
         N.cq[0] = N.cq[1] = N.cq[2] = -1;
         N.cres = 0;
         N.cskip0 = 1;
+    N.cbox = NO_BOX;
         N.cnode = 0;
         N.oct_shift = 0;
         DdaCell k;
@@ -406,6 +408,7 @@ __device__ __forceinline__ bool nearest_own(const SdfArgs& a, const float x[3], 
     N.cq[0] = N.cq[1] = N.cq[2] = -1;
     N.cres = 0;
     N.cskip0 = 1;
+    N.cbox = NO_BOX;
     N.cnode = 0;
     N.oct_shift = 0;
 #pragma unroll 1

@@ -27,7 +27,10 @@ namespace pcrl {
 // Each wave traces 64 consecutive slots in lockstep (neighbouring slots hold
 // coherent rays: their lookups share cache lines), grid-stride over the
 // active slots; with an overlay, the base hierarchy and then the overlay.
-template <bool FIRST, bool STATS, int NL, bool OV>
+// BX: the traversal uses the bricks' occupied-children boxes (scenes without
+// a dense cell table; the table's octant radii already skip empty leaves, and
+// the box code's registers would cost those scenes a wave per SIMD).
+template <bool FIRST, bool STATS, int NL, bool OV, bool BX>
 __global__ __launch_bounds__(TRACE_BLOCK) void k_trace(TraceArgs a, int b) {
     const uint32_t n_act = FIRST ? a.n_total : a.counters[b];
     const uint32_t wave = xcd_block() * (TRACE_BLOCK / 64) + (threadIdx.x >> 6);
@@ -35,7 +38,7 @@ __global__ __launch_bounds__(TRACE_BLOCK) void k_trace(TraceArgs a, int b) {
     __shared__ LeafTestLds lds[TRACE_BLOCK / 64];
     stat_t cnt[ST_COUNT] = {};
     for (uint32_t base = wave * 64; base < n_act; base += n_waves * 64)
-        trace_chunk<FIRST, STATS, NL, OV>(a, lds[threadIdx.x >> 6], b, base, n_act, false, cnt);
+        trace_chunk<FIRST, STATS, NL, OV, BX>(a, lds[threadIdx.x >> 6], b, base, n_act, false, cnt);
     flush_stats<STATS>(cnt, a.stats ? a.stats + (size_t)b * PCRL_NSTATS : nullptr);
 }
 
@@ -110,10 +113,20 @@ __global__ void k_unpack_records(const uint4* rec, const uint32_t* count, uint32
 // host side
 // ---------------------------------------------------------------------------
 
+template <bool FIRST, bool STATS, int NL, bool BX>
+static void launch_trace_bx(const TraceArgs& a, int b, unsigned grid, hipStream_t s) {
+    if (a.has_ov) hipLaunchKernelGGL((k_trace<FIRST, STATS, NL, true, BX>), dim3(grid), dim3(TRACE_BLOCK), 0, s, a, b);
+    else hipLaunchKernelGGL((k_trace<FIRST, STATS, NL, false, BX>), dim3(grid), dim3(TRACE_BLOCK), 0, s, a, b);
+}
+
 template <bool FIRST, bool STATS, int NL>
 static void launch_trace_nl(const TraceArgs& a, int b, unsigned grid, hipStream_t s) {
-    if (a.has_ov) hipLaunchKernelGGL((k_trace<FIRST, STATS, NL, true>), dim3(grid), dim3(TRACE_BLOCK), 0, s, a, b);
-    else hipLaunchKernelGGL((k_trace<FIRST, STATS, NL, false>), dim3(grid), dim3(TRACE_BLOCK), 0, s, a, b);
+    if constexpr (NL == 1) {
+        launch_trace_bx<FIRST, STATS, NL, false>(a, b, grid, s);   // no bricks
+    } else {
+        if (a.v.cells) launch_trace_bx<FIRST, STATS, NL, false>(a, b, grid, s);
+        else launch_trace_bx<FIRST, STATS, NL, true>(a, b, grid, s);
+    }
 }
 
 template <bool FIRST, bool STATS>

@@ -87,12 +87,20 @@ __device__ __forceinline__ uint64_t mspan_at(const SceneView& v, int lvl) {
     return m;
 }
 
+// Box word that no child lies outside of (lo 0, hi 31 on every axis): the
+// value used where a brick has no box.
+constexpr uint32_t NO_BOX = (31u << 15) | (31u << 20) | (31u << 25);
+
 // Descend from level 0 to level TO (< nlev) for leaf cell c.  Returns the
 // level at which the path is empty, or TO + 1 when the level-TO node exists
 // (its index in `node`).  Quotients c / span[i] use the precomputed magics.
-template <bool STATS, int TO>
+// BOX: `box` receives the occupied-children box of the brick that holds the
+// empty cell (empty at level i >= 1: the level-(i-1) brick), or of the
+// level-TO node's own brick when the path exists (TO < nlev - 1); NO_BOX
+// where there is none.  The box of a brick is loaded with its mask word.
+template <bool STATS, int TO, bool BOX = false>
 __device__ __forceinline__ int descend(const SceneView& v, const int c[3], uint32_t& node, int& skip0,
-                                       stat_t* cnt) {
+                                       stat_t* cnt, uint32_t* box = nullptr) {
     int p[3] = {span_div(c[0], v.mspan[0]), span_div(c[1], v.mspan[0]), span_div(c[2], v.mspan[0])};
     const size_t i0 = (size_t)p[0] + (size_t)v.dim0[0] * ((size_t)p[1] + (size_t)v.dim0[1] * p[2]);
     // the level-0 node and the cell's skip radius are loaded together
@@ -102,6 +110,7 @@ __device__ __forceinline__ int descend(const SceneView& v, const int c[3], uint3
         ++cnt[ST_NODES];
         cnt[ST_BYTES] += (n0 < 0 && v.dist0) ? 5 : 4;
     }
+    if (BOX) *box = NO_BOX;
     if (n0 < 0 || (uint32_t)n0 >= v.nn[0]) {
         skip0 = d0;
         return 0;
@@ -114,12 +123,16 @@ __device__ __forceinline__ int descend(const SceneView& v, const int c[3], uint3
         const int loc = (q[0] - r * p[0]) + r * ((q[1] - r * p[1]) + r * (q[2] - r * p[2]));
         const size_t wi = (size_t)n * v.nw[i - 1] + (loc >> 6);
         const uint64_t w = v.mask[i - 1][wi];
+        const uint32_t bx = (BOX && v.baabb[i - 1]) ? v.baabb[i - 1][n] : NO_BOX;
         const uint64_t bit = uint64_t(1) << (loc & 63);
         if (STATS) {
             ++cnt[ST_NODES];
-            cnt[ST_BYTES] += (w & bit) ? 12 : 8;
+            cnt[ST_BYTES] += ((w & bit) ? 12 : 8) + ((BOX && v.baabb[i - 1]) ? 4 : 0);
         }
-        if (!(w & bit)) return i;
+        if (!(w & bit)) {
+            if (BOX) *box = bx;
+            return i;
+        }
         n = v.base[i - 1][wi] + (uint32_t)__popcll(w & (bit - 1));
         if (n >= v.nn[i]) return i;
         p[0] = q[0];
@@ -127,6 +140,12 @@ __device__ __forceinline__ int descend(const SceneView& v, const int c[3], uint3
         p[2] = q[2];
     }
     node = n;
+    if constexpr (BOX) {
+        if (v.baabb[TO]) {
+            *box = v.baabb[TO][n];
+            if (STATS) cnt[ST_BYTES] += 4;
+        }
+    }
     return TO + 1;
 }
 
@@ -252,6 +271,8 @@ struct Seg {
     int cres;       // cached descent result
     int cskip0;     // cached skip radius of an empty level-0 cell (cres == 0)
     uint32_t cnode; // cached parent node
+    uint32_t cbox;  // cached box word: of the parent node's brick (cres > P), or of the brick holding
+                    // the empty cell (0 < cres <= P)
     int it;         // DDA steps taken
     int oct_shift;  // 4 x the ray's direction octant (bit a: component a negative)
 };
@@ -286,6 +307,7 @@ __device__ __forceinline__ bool seg_begin(const SceneView& v, const float o[3], 
     }
     S.cres = 0;
     S.cskip0 = 1;
+    S.cbox = NO_BOX;
     S.oct_shift = 4 * ((d[0] < 0.f ? 1 : 0) | (d[1] < 0.f ? 2 : 0) | (d[2] < 0.f ? 4 : 0));
     S.cnode = 0;
     S.it = 0;
@@ -310,6 +332,12 @@ __device__ __forceinline__ void hit_reset(Hit& hit) {
     hit.nx = hit.ny = hit.nz = 0.f;
 }
 
+// Whether local child coordinates (x, y, z) of a brick lie outside its box word.
+__device__ __forceinline__ bool box_outside(uint32_t box, int x, int y, int z) {
+    return x < (int)(box & 31u) || y < (int)((box >> 5) & 31u) || z < (int)((box >> 10) & 31u) ||
+           x > (int)((box >> 15) & 31u) || y > (int)((box >> 20) & 31u) || z > (int)((box >> 25) & 31u);
+}
+
 // What the DDA found at the current cell: an occupied leaf (lvl == NL, its
 // node and entry range) or an empty cell of level lvl with the empty region
 // around it that the ray may skip.
@@ -317,7 +345,8 @@ struct DdaCell {
     uint32_t node;
     uint2 range;    // entries of an occupied leaf
     int skip;       // > 1: an empty cube of 2 skip - 1 units centred on the unit holding c
-    int oct;        // > 1: an empty box of oct leaves from c along the ray's octant
+    int oct;        // > 1: an empty box of oct leaves from c along the ray's octant; -1: an empty cell
+                    // of level lvl whose brick's occupied-children box is `node` (a box word)
     int unit;       // edge of a skip unit in leaves (1, or a level-0 cell)
     int lvl;        // level of the empty cell containing c, or NL for an occupied leaf
 };
@@ -333,7 +362,7 @@ __device__ __forceinline__ void dda_cell_reset(DdaCell& k) {
 
 // Look the lane's current cell S.c up top-down through a hierarchy of NL
 // levels (NL == v.nlev).  Per lane; no cross-lane operations.
-template <bool STATS, int NL>
+template <bool STATS, int NL, bool BX = true>
 __device__ __forceinline__ void dda_locate(const SceneView& v, Seg& S, DdaCell& k, stat_t* cnt) {
     constexpr int L = NL;
     constexpr int P = L - 2;  // level of the leaves' parents (-1: single-level grid)
@@ -360,7 +389,7 @@ __device__ __forceinline__ void dda_locate(const SceneView& v, Seg& S, DdaCell& 
             S.cq[0] = q[0];
             S.cq[1] = q[1];
             S.cq[2] = q[2];
-            S.cres = descend<STATS, P>(v, c, S.cnode, S.cskip0, cnt);
+            S.cres = descend<STATS, P, BX>(v, c, S.cnode, S.cskip0, cnt, &S.cbox);
         }
         if (S.cres <= P) {
             k.lvl = S.cres;
@@ -368,7 +397,18 @@ __device__ __forceinline__ void dda_locate(const SceneView& v, Seg& S, DdaCell& 
                 // empty level-0 cell: the cube of radius cskip0 - 1 level-0 cells around it is empty
                 k.skip = max(1, S.cskip0);
                 k.unit = v.span[0];
+            } else if (BX && S.cbox != NO_BOX) {
+                // empty cell of a brick: the rest of the brick outside its box may be empty too
+                k.oct = -1;
+                k.node = S.cbox;
             }
+        } else if (BX && S.cbox != NO_BOX && !v.cells &&
+                   box_outside(S.cbox, c[0] - v.ratio[P] * q[0], c[1] - v.ratio[P] * q[1],
+                               c[2] - v.ratio[P] * q[2])) {
+            // a leaf outside its parent brick's occupied box: empty, no lookup
+            k.lvl = L - 1;
+            k.oct = -1;
+            k.node = S.cbox;
         } else if (v.cells) {
             // one load: the leaf's entry range, or its skip radius
             const int r = v.ratio[P];
@@ -421,18 +461,67 @@ __device__ __forceinline__ void dda_locate(const SceneView& v, Seg& S, DdaCell& 
 // the next cell along the ray, and `te` the distance at which the ray enters
 // it.  Clears `walking` when the next cell starts beyond t_stop or the ray
 // leaves the grid.  Per lane; no cross-lane operations.
-template <int NL>
+template <int NL, bool BX = true>
 __device__ __forceinline__ void dda_advance(const SceneView& v, bool& walking, const float o[3], const float d[3],
                                             Seg& S, const DdaCell& k, bool at_leaf, float t_stop, float& te) {
     int* c = S.c;
     const int Sz = at_leaf ? 1 : span_at<NL>(v, k.lvl);
+    // An empty cell of a brick with an occupied-children box: when the cell is
+    // outside the box along some axes, each such axis a bounds an empty slab
+    // of the brick (the brick cut at the box's face on a); the ray crosses the
+    // slab that it leaves last in one step.
+    // The slab along a ends at the box's near face when the ray moves towards
+    // the box, else at the brick's face; the ray leaves the slab at
+    // min(that face, T) with T its exit from the whole brick.
+    int slab = -1, bs = 0;
+    bool below = false;
+    if (BX && NL > 1 && k.oct < 0) {
+        const int us = span_at<NL>(v, k.lvl);
+        bs = span_at<NL>(v, k.lvl - 1);
+        const uint64_t um = mspan_at<NL>(v, k.lvl), bm = mspan_at<NL>(v, k.lvl - 1);
+        const uint32_t box = k.node;
+        float T = INFINITY;
+#pragma unroll
+        for (int a = 0; a < 3; ++a) {
+            const int blo = span_div(c[a], bm) * bs;
+            if (d[a] != 0.f) T = fminf(T, ((float)(d[a] > 0.f ? blo + bs : blo) * v.h + v.org[a] - o[a]) * S.inv[a]);
+        }
+        float best = -INFINITY;
+#pragma unroll
+        for (int a = 0; a < 3; ++a) {
+            const int blo = span_div(c[a], bm) * bs;
+            const int lc = span_div(c[a] - blo, um);
+            const int alo = (int)((box >> (5 * a)) & 31u), ahi = (int)((box >> (15 + 5 * a)) & 31u);
+            float t_a = T;
+            if (d[a] > 0.f && lc < alo) t_a = fminf(T, ((float)(blo + alo * us) * v.h + v.org[a] - o[a]) * S.inv[a]);
+            if (d[a] < 0.f && lc > ahi)
+                t_a = fminf(T, ((float)(blo + (ahi + 1) * us) * v.h + v.org[a] - o[a]) * S.inv[a]);
+            if ((lc < alo || lc > ahi) && t_a > best) {
+                best = t_a;
+                slab = a;
+                below = lc < alo;
+            }
+        }
+    }
     // exit of the current cell (size Sz leaves)
     int lo[3], hi[3];
     te = INFINITY;
     int axis = 0;
 #pragma unroll
     for (int a = 0; a < 3; ++a) {
-        if (k.oct > 1) {
+        if (BX && slab >= 0) {
+            // the brick's range, cut at the box's face along the slab axis
+            lo[a] = span_div(c[a], mspan_at<NL>(v, k.lvl - 1)) * bs;
+            hi[a] = lo[a] + bs;
+            if (a == slab) {
+                const int us = span_at<NL>(v, k.lvl);
+                const int alo = (int)((k.node >> (5 * a)) & 31u), ahi = (int)((k.node >> (15 + 5 * a)) & 31u);
+                if (below)
+                    hi[a] = lo[a] + alo * us;
+                else
+                    lo[a] = lo[a] + (ahi + 1) * us;
+            }
+        } else if (k.oct > 1) {
             // the octant box (inside its brick)
             lo[a] = d[a] < 0.f ? c[a] - (k.oct - 1) : c[a];
             hi[a] = d[a] < 0.f ? c[a] + 1 : c[a] + k.oct;
@@ -489,13 +578,13 @@ __device__ __forceinline__ void dda_advance(const SceneView& v, bool& walking, c
 // (cooperatively, with the other lanes' leaves), then move to the next cell
 // or stop.  Called by every lane of the wave; `walking` is cleared when the
 // lane's segment ends.  The lane's ray must be staged in W.
-template <bool STATS, int NL>
+template <bool STATS, int NL, bool BX = true>
 __device__ __forceinline__ void dda_step(const SceneView& v, LeafTestLds& W, bool& walking, const float o[3],
                                          const float d[3], Hit& hit, Seg& S, stat_t cnt[ST_COUNT]) {
     constexpr int L = NL;
     DdaCell k;
     dda_cell_reset(k);
-    if (walking) dda_locate<STATS, NL>(v, S, k, cnt);
+    if (walking) dda_locate<STATS, NL, BX>(v, S, k, cnt);
     const bool at_leaf = walking && k.lvl == L;
     if (STATS) {
         const uint64_t m_walk = __ballot(walking);
@@ -518,7 +607,7 @@ __device__ __forceinline__ void dda_step(const SceneView& v, LeafTestLds& W, boo
     if (__ballot(at_leaf && k.range.y != 0u)) leaf_tests<STATS>(v, W, at_leaf, k.range, hit, cnt);
     if (walking) {
         float te;
-        dda_advance<NL>(v, walking, o, d, S, k, at_leaf, hit.t + (hit.t * 4e-6f + 1e-3f * v.h), te);
+        dda_advance<NL, BX>(v, walking, o, d, S, k, at_leaf, hit.t + (hit.t * 4e-6f + 1e-3f * v.h), te);
     }
 }
 
@@ -528,13 +617,13 @@ __device__ __forceinline__ void dda_step(const SceneView& v, LeafTestLds& W, boo
 // by a runtime reference: two such calls merged over a reference would keep
 // the whole argument struct in scratch memory.  Called by every lane of the
 // wave.
-template <bool STATS, int NL, bool OVL>
+template <bool STATS, int NL, bool OVL, bool BX = true>
 __device__ __forceinline__ void trace_segment(const TraceArgs& a, LeafTestLds& W, bool active, const float o[3],
                                               const float d[3], Hit& hit, stat_t cnt[ST_COUNT]) {
     const SceneView& v = OVL ? a.ov : a.v;
     Seg S;
     bool walking = seg_begin(v, o, d, S) && active;
-    while (__ballot(walking)) dda_step<STATS, NL>(v, W, walking, o, d, hit, S, cnt);
+    while (__ballot(walking)) dda_step<STATS, NL, BX>(v, W, walking, o, d, hit, S, cnt);
 }
 
 // Load slot i of bounce b: the ray, its global id, polyline length and the
@@ -706,7 +795,7 @@ __device__ __forceinline__ void finish_segment(const TraceArgs& a, int b, bool d
 // traced in lockstep (base hierarchy, then the overlay).  Slots at or past
 // `range` are idle; a slot whose ray id is NO_HIT (left by an in-place
 // bounce) is idle too.  Every lane of the wave must call this (ballots).
-template <bool FIRST, bool STATS, int NL, bool OV>
+template <bool FIRST, bool STATS, int NL, bool OV, bool BX = true>
 __device__ __forceinline__ void trace_chunk(const TraceArgs& a, LeafTestLds& W, int b, uint32_t base, uint32_t range,
                                             bool in_place, stat_t cnt[ST_COUNT]) {
     const uint32_t i = base + lane_id();
@@ -717,11 +806,11 @@ __device__ __forceinline__ void trace_chunk(const TraceArgs& a, LeafTestLds& W, 
     Hit hit;
     hit_reset(hit);
     stage_ray(W, o, d, last);
-    trace_segment<STATS, NL, false>(a, W, act, o, d, hit, cnt);
+    trace_segment<STATS, NL, false, BX>(a, W, act, o, d, hit, cnt);
     // dynamic points: the nearest hit over base and overlay is the nearest
     // hit of the union (ties again by point id); the overlay shares the
     // base's frame and levels
-    if (OV) trace_segment<STATS, NL, true>(a, W, act, o, d, hit, cnt);
+    if (OV) trace_segment<STATS, NL, true, BX>(a, W, act, o, d, hit, cnt);
     finish_segment<FIRST, STATS>(a, b, act, in_place, i, g, o, d, L, last, hit, cnt);
 }
 
