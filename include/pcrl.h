@@ -328,6 +328,19 @@ typedef struct {
  * capacity to relaunch with). */
 int collect_paths(PcrlLaunch* launch, int32_t kappa, int32_t key_mode, PcrlPaths* out, pcrl_stream_t stream);
 
+/* collect_paths for callers that cannot allocate (code that must not call the
+ * device allocator: tight serving loops, harnesses that forbid allocation):
+ * the same rows, bit for bit, computed with no device, pinned-host or
+ * caller-allocator allocation.  Its temporaries live in one fixed 64 MiB
+ * device array per GPU, held from the first call on that GPU until the
+ * process ends and shared by every call on that GPU: calls on one GPU must
+ * not overlap in time (overlapping calls race on the array and give wrong
+ * rows).  Enough for about 600k reception records with the longest keys
+ * (about 1.2M with single-word keys); a launch with more records is refused
+ * with PCRL_EINVAL before any work is enqueued.  Synchronises the stream. */
+int collect_paths_noalloc(PcrlLaunch* launch, int32_t kappa, int32_t key_mode, PcrlPaths* out,
+                          pcrl_stream_t stream);
+
 /* ------------------------------------------------------------------------ */
 /* path refinement (Section 2.3, Eq. 2)                                      */
 /* ------------------------------------------------------------------------ */

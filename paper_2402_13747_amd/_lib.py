@@ -156,6 +156,7 @@ SIGNATURES = {
                                  C.c_void_p, C.POINTER(C.c_int64)]),
     "release_launch": (C.c_int, [C.c_void_p]),
     "collect_paths": (C.c_int, [C.c_void_p, C.c_int32, C.c_int32, C.POINTER(PcrlPaths), C.c_void_p]),
+    "collect_paths_noalloc": (C.c_int, [C.c_void_p, C.c_int32, C.c_int32, C.POINTER(PcrlPaths), C.c_void_p]),
     "refine_paths": (C.c_int, [C.c_void_p, C.c_void_p, C.c_int32, C.c_void_p, C.c_int32, C.POINTER(PcrlPaths),
                                C.c_int32, C.POINTER(PcrlRefineParams), C.POINTER(PcrlRefined), C.c_void_p]),
     "sdf_intersect": (C.c_int, [C.c_void_p, C.c_void_p, C.c_void_p, C.c_void_p, C.c_int64,

@@ -384,7 +384,19 @@ static int bits_for(uint64_t max_value) {
 
 static unsigned nblk(uint32_t n) { return std::max(1u, (n + 255u) / 256u); }
 
-static int collect_impl(PcrlLaunch* L, int32_t kappa, int32_t key_mode, PcrlPaths* out, hipStream_t s) {
+// Scratch bytes collect_impl needs for n records with W-word keys: the
+// per-record arrays (W key words, a 64-bit and seven 32-bit arrays), the
+// radix sort's double buffer and tile histograms, the scan's block sums,
+// and 256-byte alignment of every block.
+static size_t collect_scratch_bytes(uint64_t n, int W) {
+    const uint64_t tiles = (n + 2047) / 2048;
+    return (size_t)(n * (8ull * W + 8 + 28) + n * 12 + tiles * 256 * 4 + (n / 512 + 64) * 4 + 64 * 256);
+}
+
+// scratch_limit > 0: the call may use at most that many bytes of temporaries
+// (checked before any is taken).
+static int collect_impl(PcrlLaunch* L, int32_t kappa, int32_t key_mode, PcrlPaths* out, hipStream_t s,
+                        size_t scratch_limit = 0) {
     const PcrlScene* S = L->scene;
     const int K = L->K;
     uint32_t n_rec = 0;
@@ -435,6 +447,12 @@ static int collect_impl(PcrlLaunch* L, int32_t kappa, int32_t key_mode, PcrlPath
         return PCRL_EINVAL;
     }
 
+    if (scratch_limit && collect_scratch_bytes(n, ks.W) > scratch_limit) {
+        set_error("collect_paths_noalloc: %u records with %d-word keys need %zu bytes of scratch, more than the "
+                  "%zu bytes of the fixed array; use collect_paths",
+                  n, ks.W, collect_scratch_bytes(n, ks.W), scratch_limit);
+        return PCRL_EINVAL;
+    }
     DevBufs T;
     T.stream = s;
     auto fail = [&](int code) { T.release(); return code; };
@@ -507,9 +525,62 @@ static int collect_impl(PcrlLaunch* L, int32_t kappa, int32_t key_mode, PcrlPath
     return PCRL_OK;
 }
 
+// ---------------------------------------------------------------------------
+// collect_paths without allocation: temporaries in a fixed device array
+// ---------------------------------------------------------------------------
+
+constexpr size_t NOALLOC_SCRATCH_BYTES = (size_t)64 << 20;
+constexpr int NOALLOC_MAX_DEVICES = 64;
+
+// Every no-allocation call on a device shares that device's copy of this
+// array (held until the process ends); host code reaches it only through
+// the address hipGetSymbolAddress returns for the device.
+static __device__ __align__(256) unsigned char scratch[NOALLOC_SCRATCH_BYTES];
+
+static std::mutex g_scratch_mu;
+static void* g_scratch_ptr[NOALLOC_MAX_DEVICES];
+
+static int scratch_of_current_device(void** out) {
+    int dev = 0;
+    PCRL_TRY_HIP(hipGetDevice(&dev));
+    if (dev < 0 || dev >= NOALLOC_MAX_DEVICES) {
+        set_error("collect_paths_noalloc: device ordinal %d beyond %d", dev, NOALLOC_MAX_DEVICES);
+        return PCRL_EINVAL;
+    }
+    std::lock_guard<std::mutex> lock(g_scratch_mu);
+    if (!g_scratch_ptr[dev]) {
+        void* ptr = nullptr;
+        const hipError_t e = hipGetSymbolAddress(&ptr, HIP_SYMBOL(scratch));
+        if (e != hipSuccess || !ptr) {
+            (void)hipGetLastError();
+            set_error("collect_paths_noalloc: address of the scratch array on device %d: %s", dev,
+                      hipGetErrorString(e));
+            return PCRL_EHIP;
+        }
+        g_scratch_ptr[dev] = ptr;
+    }
+    *out = g_scratch_ptr[dev];
+    return PCRL_OK;
+}
+
 }  // namespace pcrl
 
 using namespace pcrl;
+
+extern "C" int collect_paths_noalloc(PcrlLaunch* launch, int32_t kappa, int32_t key_mode, PcrlPaths* out,
+                                     pcrl_stream_t stream) {
+    clear_error();
+    if (!launch || !out || kappa < 1 || (key_mode != PCRL_KEY_LABELS && key_mode != PCRL_KEY_LEAVES) ||
+        out->capacity < 0) {
+        set_error("collect_paths_noalloc: invalid arguments (kappa >= 1, key_mode 0 or 1, capacity >= 0)");
+        return PCRL_EINVAL;
+    }
+    void* base = nullptr;
+    int rc = scratch_of_current_device(&base);
+    if (rc) return rc;
+    ArenaScope arena(base, NOALLOC_SCRATCH_BYTES);
+    return collect_impl(launch, kappa, key_mode, out, (hipStream_t)stream, NOALLOC_SCRATCH_BYTES);
+}
 
 extern "C" int collect_paths(PcrlLaunch* launch, int32_t kappa, int32_t key_mode, PcrlPaths* out,
                              pcrl_stream_t stream) {

@@ -50,6 +50,31 @@ const char* get_error();
 int dalloc(void** p, size_t bytes, hipStream_t s);
 void dfree(void* p, hipStream_t s);
 
+// While an ArenaScope lives on a thread, dalloc on that thread carves blocks
+// out of the given device range (256-byte aligned, last in first out: a block
+// is reclaimed once it and every block above it are freed) and never calls
+// the runtime or a caller's allocator; dalloc fails with PCRL_ENOMEM when the
+// range is exhausted.  read_back then copies without pinned staging memory.
+// Blocks are handed out again in stream order, so every user of one arena
+// must run on the stream of the scope's call.
+struct Arena {
+    static constexpr int kMaxBlocks = 64;
+    char* base = nullptr;
+    size_t cap = 0, top = 0, peak = 0;
+    int n = 0;                        // live blocks, in allocation order
+    size_t off[kMaxBlocks], end[kMaxBlocks];
+    bool freed[kMaxBlocks];
+};
+struct ArenaScope {
+    ArenaScope(void* base, size_t bytes);
+    ~ArenaScope();
+    size_t peak() const { return arena.peak; }   // most bytes in use at once
+    ArenaScope(const ArenaScope&) = delete;
+    ArenaScope& operator=(const ArenaScope&) = delete;
+    Arena arena;
+    Arena* prev;
+};
+
 // Owns a list of device allocations released together (stream ordered).
 struct DevBufs {
     std::vector<void*> ptrs;

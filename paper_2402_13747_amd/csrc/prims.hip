@@ -120,8 +120,57 @@ UserAlloc& user_alloc() {
 }
 }  // namespace
 
+namespace {
+thread_local Arena* t_arena = nullptr;
+
+int arena_alloc(Arena& A, void** p, size_t bytes) {
+    const size_t off = (A.top + 255) & ~(size_t)255;
+    const size_t want = bytes == 0 ? 1 : bytes;
+    if (A.n == Arena::kMaxBlocks) {
+        set_error("scratch memory: more than %d blocks in use at once", Arena::kMaxBlocks);
+        return PCRL_ENOMEM;
+    }
+    if (off > A.cap || want > A.cap - off) {
+        set_error("scratch memory exhausted: %zu more bytes needed at offset %zu of %zu", want, off, A.cap);
+        return PCRL_ENOMEM;
+    }
+    A.off[A.n] = off;
+    A.end[A.n] = off + want;
+    A.freed[A.n] = false;
+    ++A.n;
+    A.top = off + want;
+    A.peak = std::max(A.peak, A.top);
+    *p = A.base + off;
+    return PCRL_OK;
+}
+
+bool arena_free(Arena& A, void* p) {
+    char* c = static_cast<char*>(p);
+    if (c < A.base || c >= A.base + A.cap) return false;
+    const size_t off = (size_t)(c - A.base);
+    for (int i = A.n; i-- > 0;) {
+        if (A.off[i] == off && !A.freed[i]) {
+            A.freed[i] = true;
+            break;
+        }
+    }
+    while (A.n > 0 && A.freed[A.n - 1]) --A.n;
+    A.top = A.n ? A.end[A.n - 1] : 0;
+    return true;
+}
+}  // namespace
+
+ArenaScope::ArenaScope(void* base, size_t bytes) : prev(t_arena) {
+    arena.base = static_cast<char*>(base);
+    arena.cap = bytes;
+    t_arena = &arena;
+}
+
+ArenaScope::~ArenaScope() { t_arena = prev; }
+
 int dalloc(void** p, size_t bytes, hipStream_t s) {
     *p = nullptr;
+    if (t_arena) return arena_alloc(*t_arena, p, bytes);
     int dev = 0;
     (void)hipGetDevice(&dev);
     const size_t cls = size_class(bytes == 0 ? 1 : bytes);
@@ -178,6 +227,7 @@ int dalloc(void** p, size_t bytes, hipStream_t s) {
 
 void dfree(void* p, hipStream_t s) {
     if (!p) return;
+    if (t_arena && arena_free(*t_arena, p)) return;
     {
         UserAlloc& U = user_alloc();
         PcrlAllocator ua{};
@@ -651,6 +701,12 @@ namespace pcrl {
 int read_back(void* host, const void* dev, size_t bytes, hipStream_t s) {
     static thread_local void* pinned = nullptr;
     static thread_local size_t cap = 0;
+    if (t_arena) {  // no allocation of any kind: a pageable copy
+        if (hipMemcpyAsync(host, dev, bytes, hipMemcpyDeviceToHost, s) != hipSuccess ||
+            hipStreamSynchronize(s) != hipSuccess)
+            return PCRL_EHIP;
+        return PCRL_OK;
+    }
     if (bytes > cap) {
         if (pinned) (void)hipHostFree(pinned);
         pinned = nullptr;
