@@ -142,6 +142,9 @@ def _load():
         lib.oracle_accepts.argtypes = [C.POINTER(OracleArgs), C.c_void_p, C.c_void_p, C.c_int32, C.c_int64,
                                        C.c_double, C.c_int64]
         lib.oracle_accepts.restype = C.c_int
+        lib.oracle_visibility.argtypes = [C.POINTER(OracleArgs), C.c_int64, C.c_void_p, C.c_void_p, C.c_void_p,
+                                          C.c_void_p, C.c_void_p]
+        lib.oracle_visibility.restype = C.c_int
         lib.oracle_refine.argtypes = [C.POINTER(OracleRefineArgs)]
         lib.oracle_refine.restype = C.c_int
         lib.oracle_sdf_intersect.argtypes = [C.POINTER(OracleSdfArgs)]

@@ -1,0 +1,439 @@
+"""Oracle of the environment-driven coarse tracer (test infrastructure).
+
+Only ``tests/``, ``__graft_entry__.smoke()`` and ``bench.py``'s
+``cpu_baseline`` leg may use this module.  It is a plain FP64 definition of
+what the HIP cone tracer computes and shares no code with it.
+
+The paper's own coarse path tracing, in its order:
+
+* Section 2.1: low-resolution voxels of edge V, each divided into D_v^3
+  subvoxels.  An intersectable entity (IE) is the set of points of one label
+  whose position lies in one subvoxel; it carries that label, a reception
+  point (the mean of its points) and a normal (the normalised mean of their
+  unit normals).  Every RX is an IE too: its reception point is the RX
+  itself, in the subvoxel that holds it.  ``ie_build``.
+* Section 2.2.2, transmission phase: from each TX a ray is cast towards the
+  reception point of every IE; a visible RX is a line-of-sight path, a
+  visible point IE is a first interaction.  ``visible``.
+* Section 2.2.3, propagation phase: from each interaction a reflected
+  conical ray (apex at the reception point, axis the mirror image of the
+  incoming direction about the IE's normal, constant half-angle) is traced;
+  every IE it reaches is the next interaction, up to the interaction limit;
+  every RX it reaches ends a coarse path.  At most kappa paths share the same
+  labels in the same order.
+* Section 2.2.4, voxel cone tracing: the axis is marched through the voxel
+  grid; at every voxel the neighbouring voxels are evaluated (the march
+  distance only skips voxels with no IE within one voxel, so the evaluated
+  voxels are those within Chebyshev distance 1 of a voxel the axis
+  crosses); an IE is reached when the cone meets the bounding sphere of its
+  subvoxel (the voxel's bounding sphere contains it, so its test adds
+  nothing), its reception point lies in front of the separation plane at
+  the apex, and a visibility ray from the apex reaches its subvoxel.
+
+Readings where the paper is silent (each listed in the design notes):
+  * IE reception point = mean of its points, normal = normalised mean of
+    their unit normals; the subvoxel of a point is taken in FP32 as
+    floor((p - origin) * (1 / subvoxel)) with FP32 operations (an integer
+    decided by floating point, taken in the kernel's precision);
+  * visibility: the surfel disks of the launcher (radius r_s, t > t_eps) are
+    the geometry; the target is visible iff no disk is hit before the ray
+    enters the target's subvoxel;
+  * the march of a cone ends at the voxel of the first disk its axis hits
+    (beyond it everything is behind that surface), or at the grid's exit;
+  * separation plane of a reflected cone: through the apex, with the IE's
+    normal turned towards the reflected side as its normal; a target is in
+    front iff (p - apex) . n > 0;
+  * kappa acts on partial paths too (otherwise the branching is unbounded):
+    per (TX, label sequence) at most kappa nodes of a generation are kept,
+    chosen by a deterministic priority (SplitMix64 of the parent's priority
+    plus the IE index + 1; the TX's priority is SplitMix64(tx)), ties by
+    parent then IE index; the same holds for the paths reaching one RX;
+  * coarse path length = polyline TX -> reception points -> RX.
+
+Parity: every decision that compares floating-point values (cone-sphere,
+separation plane, visibility, the candidate block of a voxel, the axis's
+first hit) is reported with its margin; a decision whose margin lies inside
+the FP32 error band is ambiguous, and a node reached through an ambiguous
+decision is excused together with its subtree.
+"""
+from __future__ import annotations
+
+import ctypes as C
+import math
+
+import numpy as np
+
+MASK64 = (1 << 64) - 1
+
+
+def splitmix64(x: int) -> int:
+    """SplitMix64 output for state x (Steele, Lea and Flood, OOPSLA 2014):
+    z = x + 0x9E3779B97F4A7C15; then two xor-shift-multiply rounds and a final
+    xor-shift (the finaliser of the published generator)."""
+    z = (x + 0x9E3779B97F4A7C15) & MASK64
+    z = ((z ^ (z >> 30)) * 0xBF58476D1CE4E5B9) & MASK64
+    z = ((z ^ (z >> 27)) * 0x94D049BB133111EB) & MASK64
+    return z ^ (z >> 31)
+
+
+def child_priority(parent_prio: int, ie_index: int) -> int:
+    return splitmix64((parent_prio + ie_index + 1) & MASK64)
+
+
+# --------------------------------------------------------------------------- IEs (Section 2.1)
+
+def subvoxel_of(xyz, origin, voxel, dv):
+    """Subvoxel cell of each position, decided in FP32."""
+    sv = np.float32(voxel) / np.float32(dv)
+    inv = np.float32(1.0) / sv
+    rel = np.asarray(xyz, np.float32) - np.asarray(origin, np.float32)[None, :]
+    return np.floor(rel * inv).astype(np.int64)
+
+
+def ie_build(xyz, normal, label, origin, voxel, dv, dims):
+    """Point IEs: points grouped by (subvoxel, label), sorted by (voxel, subvoxel within voxel, label).
+
+    Returns a dict of arrays, one entry per IE: ``sub`` [n,3] subvoxel cell,
+    ``voxel`` [n] linear voxel index, ``label``, ``count``, ``pos`` [n,3] mean
+    position, ``nrm`` [n,3] normalised mean unit normal, ``key`` (the sort key)
+    and ``members`` (point indices per IE)."""
+    dims = np.asarray(dims, np.int64)
+    s = subvoxel_of(xyz, origin, voxel, dv)
+    if len(s) and (s.min() < 0 or np.any(s >= dims[None, :] * dv)):
+        raise ValueError("points outside the IE grid")
+    vox = s // dv
+    loc = s - vox * dv
+    vlin = vox[:, 0] + dims[0] * (vox[:, 1] + dims[1] * vox[:, 2])
+    llin = loc[:, 0] + dv * (loc[:, 1] + dv * loc[:, 2])
+    lab = np.asarray(label, np.int64)
+    key = ((vlin * dv ** 3 + llin) << 32) | lab
+    order = np.argsort(key, kind="stable")
+    ks = key[order]
+    starts = np.flatnonzero(np.r_[True, ks[1:] != ks[:-1]]) if len(ks) else np.zeros(0, np.int64)
+    ends = np.r_[starts[1:], len(ks)]
+    x64 = np.asarray(xyz, np.float64)
+    n64 = np.asarray(normal, np.float64)
+    n64 = n64 / np.linalg.norm(n64, axis=1, keepdims=True)
+    n_ie = len(starts)
+    out = {"key": ks[starts] if n_ie else np.zeros(0, np.int64), "sub": np.zeros((n_ie, 3), np.int64),
+           "voxel": np.zeros(n_ie, np.int64), "label": np.zeros(n_ie, np.int64), "count": np.zeros(n_ie, np.int64),
+           "pos": np.zeros((n_ie, 3)), "nrm": np.zeros((n_ie, 3)), "members": []}
+    for i, (a, b) in enumerate(zip(starts, ends)):
+        idx = order[a:b]
+        out["sub"][i] = s[idx[0]]
+        out["voxel"][i] = vlin[idx[0]]
+        out["label"][i] = lab[idx[0]]
+        out["count"][i] = b - a
+        out["pos"][i] = x64[idx].mean(axis=0)
+        m = n64[idx].mean(axis=0)
+        out["nrm"][i] = m / np.linalg.norm(m)
+        out["members"].append(idx)
+    return out
+
+
+def subvoxel_box(sub, origin, voxel, dv):
+    sv = float(np.float32(voxel) / np.float32(dv))
+    lo = np.asarray(origin, np.float64) + np.asarray(sub, np.float64) * sv
+    return lo, lo + sv
+
+
+# --------------------------------------------------------------------------- cone geometry (Section 2.2.4)
+
+def cone_sphere_margin(o, d, cos_t, sin_t, c, R):
+    """R minus the distance from c to the solid cone {apex o, unit axis d,
+    half-angle t}: the cone meets the sphere (c, R) iff the margin is >= 0.
+    With v = c - o, a = v.d and rho = |v - a d|: c inside the cone when
+    rho cos t <= a sin t; nearest to the apex when a cos t + rho sin t < 0;
+    else at distance rho cos t - a sin t from the cone's surface."""
+    v = np.asarray(c, np.float64) - np.asarray(o, np.float64)
+    a = float(v @ d)
+    rho = float(np.linalg.norm(v - a * d))
+    lateral = rho * cos_t - a * sin_t
+    if lateral <= 0.0:
+        dist = 0.0
+    elif a * cos_t + rho * sin_t < 0.0:
+        dist = float(np.linalg.norm(v))
+    else:
+        dist = lateral
+    return R - dist
+
+
+def block_margins(o, d, t_end, cells, origin, voxel):
+    """For each voxel cell w (rows of ``cells``): the signed overlap length of
+    the segment o + t d, 0 <= t <= t_end, with the 3x3x3 voxel block
+    [w - 1, w + 2) V around w (>= 0 iff they meet; minus the gap along the
+    ray, or across it, when they do not).  The voxels within Chebyshev
+    distance 1 of a voxel the segment crosses are the w whose block it meets."""
+    V = float(voxel)
+    lo = np.asarray(origin, np.float64)[None, :] + (np.asarray(cells, np.float64) - 1.0) * V
+    hi = lo + 3.0 * V
+    t0 = np.zeros(len(lo))
+    t1 = np.full(len(lo), float(t_end))
+    gap = np.full(len(lo), -np.inf)
+    for ax in range(3):
+        if d[ax] != 0.0:
+            ta = (lo[:, ax] - o[ax]) / d[ax]
+            tb = (hi[:, ax] - o[ax]) / d[ax]
+            t0 = np.maximum(t0, np.minimum(ta, tb))
+            t1 = np.minimum(t1, np.maximum(ta, tb))
+        else:
+            gap = np.maximum(gap, np.maximum(lo[:, ax] - o[ax], o[ax] - hi[:, ax]))
+    m = t1 - t0
+    return np.where(gap > 0, -gap, m)
+
+
+def near_cells(o, d, t_far, origin, voxel, dims):
+    """Voxel cells of the grid within two voxels of the segment's bounding box."""
+    origin = np.asarray(origin, np.float64)
+    dims = np.asarray(dims, np.int64)
+    end = o + (t_far if np.isfinite(t_far) else 1e6) * d
+    lo_c = np.maximum(np.floor((np.minimum(o, end) - origin) / voxel).astype(np.int64) - 2, 0)
+    hi_c = np.minimum(np.floor((np.maximum(o, end) - origin) / voxel).astype(np.int64) + 2, dims - 1)
+    if np.any(hi_c < lo_c):
+        return np.zeros((0, 3), np.int64)
+    g = np.stack(np.meshgrid(*[np.arange(lo_c[a], hi_c[a] + 1) for a in range(3)], indexing="ij"), axis=-1)
+    return g.reshape(-1, 3)
+
+
+def grid_exit(o, d, origin, voxel, dims):
+    lo = np.asarray(origin, np.float64)
+    hi = lo + np.asarray(dims, np.float64) * float(voxel)
+    t1 = math.inf
+    for ax in range(3):
+        if d[ax] > 0:
+            t1 = min(t1, (hi[ax] - o[ax]) / d[ax])
+        elif d[ax] < 0:
+            t1 = min(t1, (lo[ax] - o[ax]) / d[ax])
+    return max(t1, 0.0)
+
+
+# --------------------------------------------------------------------------- visibility and axis hits
+
+def visible(lib_args, o, p, box_lo, box_hi):
+    """States per ray (1 visible, 0 blocked, 2 ambiguous in parity mode) and t_in."""
+    from . import OracleArgs, _load, _p  # noqa: F401
+    lib = _load()
+    n = len(o)
+    o = np.ascontiguousarray(o, np.float64).reshape(-1, 3)
+    p = np.ascontiguousarray(p, np.float64).reshape(-1, 3)
+    box = np.ascontiguousarray(np.concatenate([np.asarray(box_lo, np.float64).reshape(-1, 3),
+                                               np.asarray(box_hi, np.float64).reshape(-1, 3)], axis=1))
+    state = np.zeros(n, np.int32)
+    t_in = np.zeros(n, np.float64)
+    if n == 0:
+        return state, t_in
+    rc = lib.oracle_visibility(C.byref(lib_args), n, _p(o), _p(p), _p(box), _p(state), _p(t_in))
+    if rc != 0:
+        raise RuntimeError(f"oracle_visibility failed with status {rc}")
+    return state, t_in
+
+
+class Scene:
+    """The point cloud and the bands of one oracle run."""
+
+    def __init__(self, xyz, normal, label, r_s, t_eps, parity=False, err_abs=0.0, err_dir=0.0, tie_rel=1e-4,
+                 edge_rel=1e-4, den_amb=1e-6, n_threads=None):
+        from . import OracleArgs, _p, default_threads
+        self.xyz = np.ascontiguousarray(xyz, np.float32)
+        self.normal = np.ascontiguousarray(normal, np.float32)
+        self.label = np.ascontiguousarray(label, np.uint32)
+        self.r_s, self.t_eps = float(r_s), float(t_eps)
+        self.parity = parity
+        self.err_abs, self.err_dir, self.tie_rel, self.edge_rel, self.den_amb = err_abs, err_dir, tie_rel, edge_rel, den_amb
+        a = OracleArgs()
+        a.xyz, a.nrm, a.label, a.n_pts = _p(self.xyz), _p(self.normal), _p(self.label), self.xyz.shape[0]
+        a.r_s, a.t_eps = self.r_s, self.t_eps
+        a.parity, a.tie_rel, a.err_abs, a.err_dir = int(bool(parity)), tie_rel, err_abs, err_dir
+        a.edge_rel, a.den_amb = edge_rel, den_amb
+        a.n_threads = int(n_threads or default_threads())
+        self.args = a
+
+    def axis_hits(self, o, d):
+        """Nearest disk hit of each axis ray (t > t_eps): t (inf if none) and, in
+        parity mode, the extent [t_lo, t_hi] of the acceptable answers."""
+        from . import launch
+        n = len(o)
+        if n == 0:
+            return np.zeros(0), np.zeros(0), np.zeros(0)
+        idx = np.arange(n, dtype=np.int64)
+        res = launch(self.xyz, self.normal, self.label, np.asarray(o, np.float32), np.zeros((0, 3), np.float32),
+                     np.asarray(d, np.float32), K=0, r_s=self.r_s, t_eps=self.t_eps, sel=idx * n + idx,
+                     parity=self.parity, tie_rel=self.tie_rel, err_abs=self.err_abs, err_dir=self.err_dir,
+                     edge_rel=self.edge_rel, den_amb=self.den_amb)
+        t = np.where(res["hit_id"][:, 0] >= 0, res["hit_t"][:, 0], np.inf)
+        if not self.parity:
+            return t, t, t
+        lo, hi = t.copy(), t.copy()
+        so, sd = res["seg_o"][:, 0], res["seg_d"][:, 0]
+        for r in range(n):
+            na = int(res["acc_n"][r, 0])
+            for m in res["acc_id"][r, 0, :min(na, res["acc_id"].shape[2])]:
+                if m < 0:
+                    hi[r] = np.inf
+                    continue
+                nm = self.normal[m].astype(np.float64)
+                nm /= np.linalg.norm(nm)
+                tm = float((self.xyz[m].astype(np.float64) - so[r]) @ nm / (sd[r] @ nm))
+                lo[r], hi[r] = min(lo[r], tm), max(hi[r], tm)
+            if na > res["acc_id"].shape[2]:
+                lo[r], hi[r] = 0.0, np.inf      # the stored set is partial: any end is acceptable
+        return t, lo, hi
+
+
+# --------------------------------------------------------------------------- the tracer (Sections 2.2.2-2.2.4)
+
+def _merge_similar(kids):
+    """Partial paths that reach the same IE with the same labels in the same
+    order are similar paths: per (tx, labels, IE) one node is kept, the one of
+    smallest (priority, parent).  Exact nodes are chosen among the exact ones
+    (the definition); when a node that only a perturbed decision admits would
+    win, it is kept too and both are excused (the winner can differ)."""
+    kids.sort(key=lambda c: (c["tx"], c["labels"], c["ie"], c["prio"], c["parent"]))
+    out = []
+    i = 0
+    while i < len(kids):
+        j = i
+        key = (kids[i]["tx"], kids[i]["labels"], kids[i]["ie"])
+        while j < len(kids) and (kids[j]["tx"], kids[j]["labels"], kids[j]["ie"]) == key:
+            j += 1
+        group = kids[i:j]
+        best_exact = next((c for c in group if c["exact"]), None)
+        first = group[0]
+        if best_exact is not None and best_exact is not first:
+            first["excused"] = best_exact["excused"] = True
+            out += [first, best_exact]
+        else:
+            out.append(first)
+        i = j
+    out.sort(key=lambda c: (c["tx"], c["labels"], c["ie"], c["prio"]))
+    return out
+
+
+def trace(scene: Scene, ies, tx, rx, origin, voxel, dv, dims, K, kappa, half_angle):
+    """Environment-driven coarse tracing with conical rays (Sections 2.2.2-2.2.4).
+
+    A node is a partial path TX -> IE chain.  Per node: ``exact`` (every
+    decision of the chain admits it by the definition) and ``excused`` (some
+    decision on the chain lies inside the error band: the node, or its
+    absence, cannot be held against an FP32 implementation).  Returns a dict
+    with ``nodes`` (per depth 1..K, after the kappa limit), ``records`` (every
+    reception: tx, rx, chain, labels, length, prio, exact, excused) and
+    ``paths`` ((tx, rx, n, labels) -> {"count", "rows", "excused"}; rows are
+    the kappa exact records of smallest (priority, chain))."""
+    tx = np.asarray(tx, np.float64).reshape(-1, 3)
+    rx = np.asarray(rx, np.float64).reshape(-1, 3)
+    sv = float(np.float32(voxel) / np.float32(dv))
+    R = sv * math.sqrt(3.0) / 2.0
+    cos_t, sin_t = math.cos(half_angle), math.sin(half_angle)
+    ext = float(max(np.abs(scene.xyz).max() if len(scene.xyz) else 1.0, np.abs(tx).max(), 1.0))
+    band = 64 * (2.0 ** -24) * ext if scene.parity else 0.0
+    n_ie = len(ies["label"])
+    dims = np.asarray(dims, np.int64)
+    rx_sub = subvoxel_of(rx.astype(np.float32), origin, voxel, dv) if len(rx) else np.zeros((0, 3), np.int64)
+    ie_lo = np.asarray(origin, np.float64)[None, :] + ies["sub"] * sv
+    rx_lo = np.asarray(origin, np.float64)[None, :] + rx_sub * sv
+    ie_cell = ies["sub"] // dv
+    rx_cell = rx_sub // dv
+    by_voxel = {}
+    for i in range(n_ie):
+        by_voxel.setdefault(tuple(int(x) for x in ie_cell[i]), []).append(i)
+    rx_by_voxel = {}
+    for j in range(len(rx)):
+        rx_by_voxel.setdefault(tuple(int(x) for x in rx_cell[j]), []).append(j)
+
+    records = []
+
+    def record(c, j, length, exact, excused):
+        records.append(dict(tx=c["tx"], rx=j, chain=c["chain"], labels=c["labels"], length=length, prio=c["prio"],
+                            exact=exact, excused=excused))
+
+    # ---- transmission phase: from every TX a ray towards every IE and RX
+    roots = [dict(tx=i, chain=(), labels=(), prio=splitmix64(i), length=0.0, o=tx[i], prev=None, ie=-1,
+                  exact=True, excused=False) for i in range(len(tx))]
+    q = []   # (parent index, kind, target, exact, excused)
+    for i in range(len(tx)):
+        q += [(i, "ie", e, True, False) for e in range(n_ie)]
+        q += [(i, "rx", j, True, False) for j in range(len(rx))]
+    parents = roots
+    nodes_by_depth = []
+    for k in range(0, K + 1):
+        # ---- visibility of this generation's candidates
+        o = np.array([parents[pi]["o"] for pi, _, _, _, _ in q]).reshape(-1, 3)
+        p = np.array([ies["pos"][t] if kind == "ie" else rx[t] for _, kind, t, _, _ in q]).reshape(-1, 3)
+        lo = np.array([ie_lo[t] if kind == "ie" else rx_lo[t] for _, kind, t, _, _ in q]).reshape(-1, 3)
+        st, _ = visible(scene.args, o, p, lo, lo + sv)
+        kids = []
+        for (pi, kind, t, ex, exc), s in zip(q, st):
+            if s == 0:
+                continue
+            P = parents[pi]
+            exact = ex and s == 1
+            excused = exc or s == 2 or P["excused"]
+            if kind == "rx":
+                record(P, t, P["length"] + float(np.linalg.norm(rx[t] - P["o"])), exact and P["exact"], excused)
+            elif k < K:
+                kids.append(dict(tx=P["tx"], chain=P["chain"] + (t,), labels=P["labels"] + (int(ies["label"][t]),),
+                                 prio=child_priority(P["prio"], t), parent=pi,
+                                 length=P["length"] + float(np.linalg.norm(ies["pos"][t] - P["o"])),
+                                 o=ies["pos"][t], prev=P["o"], ie=t, exact=exact and P["exact"], excused=excused))
+        if k == K:
+            break
+        kept = _merge_similar(kids)
+        nodes_by_depth.append(kept)
+        # ---- propagation: the reflected cone of every node of depth k + 1
+        q = []
+        if not kept:
+            break
+        apex = np.array([c["o"] for c in kept])
+        axes, planes = [], []
+        for c in kept:
+            din = c["o"] - c["prev"]
+            din = din / np.linalg.norm(din)
+            n_e = ies["nrm"][c["ie"]]
+            dout = din - 2.0 * float(din @ n_e) * n_e
+            dout = dout / np.linalg.norm(dout)
+            axes.append(dout)
+            planes.append(n_e if float(n_e @ dout) > 0 else -n_e)
+        axes = np.array(axes)
+        t_hit, t_lo, t_hi = scene.axis_hits(apex.astype(np.float32), axes.astype(np.float32))
+        for ci, c in enumerate(kept):
+            o1, d1, n_o = apex[ci], axes[ci], planes[ci]
+            t_exit = grid_exit(o1, d1, origin, voxel, dims)
+            t_end, t_near, t_far = min(t_hit[ci], t_exit), min(t_lo[ci], t_exit), min(t_hi[ci], t_exit)
+            cells = near_cells(o1, d1, t_far, origin, voxel, dims)
+            if len(cells) == 0:
+                continue
+            m_end = block_margins(o1, d1, t_end, cells, origin, voxel)
+            m_near = block_margins(o1, d1, t_near, cells, origin, voxel) if t_near < t_end else m_end
+            m_far = block_margins(o1, d1, t_far, cells, origin, voxel) if t_far > t_end else m_end
+            for w, me, mn, mf in zip(cells, m_end, m_near, m_far):
+                if mf < -band:
+                    continue                      # no end of the axis reaches this block
+                w_in = me >= 0
+                w_amb = mn <= band                # some acceptable end, or rounding, leaves it out
+                wt = (int(w[0]), int(w[1]), int(w[2]))
+                targets = [("ie", e) for e in by_voxel.get(wt, []) if e != c["ie"]]
+                targets += [("rx", j) for j in rx_by_voxel.get(wt, [])]
+                for kind, t in targets:
+                    pc = ie_lo[t] + 0.5 * sv if kind == "ie" else rx_lo[t] + 0.5 * sv
+                    pr = ies["pos"][t] if kind == "ie" else rx[t]
+                    m_cone = cone_sphere_margin(o1, d1, cos_t, sin_t, pc, R)
+                    m_plane = float((pr - o1) @ n_o)
+                    exact = w_in and m_cone >= 0 and m_plane > 0
+                    amb = w_amb or abs(m_cone) <= band or abs(m_plane) <= band
+                    if exact or amb:
+                        q.append((ci, kind, t, exact, amb))
+        parents = kept
+    # ---- coarse paths: per (tx, rx, labels) the count and the kappa exact rows of smallest priority
+    paths = {}
+    for r in sorted(records, key=lambda r: (r["tx"], r["rx"], len(r["labels"]), r["labels"], r["prio"], r["chain"])):
+        key = (r["tx"], r["rx"], len(r["labels"]), r["labels"])
+        g = paths.setdefault(key, {"count": 0, "rows": [], "excused": True, "exact": False})
+        g["excused"] = g["excused"] and r["excused"]
+        if not r["exact"]:
+            continue
+        g["exact"] = True
+        g["count"] += 1
+        if kappa <= 0 or len(g["rows"]) < kappa:
+            g["rows"].append(r)
+    return {"nodes": nodes_by_depth, "records": records, "paths": paths}

@@ -631,6 +631,122 @@ int oracle_accepts(const OracleArgs* a, const double* o, const double* d, int32_
 }
 
 /* ------------------------------------------------------------------------ */
+/* visibility rays of the cone tracer (Section 2.2.2 and Section 2.2.4)      */
+/* ------------------------------------------------------------------------ */
+
+/*
+ * A ray from o towards an intersectable entity's reception point p checks
+ * that the entity is visible: nothing of the point cloud may be hit before
+ * the ray enters the entity's subvoxel (the box [box_lo, box_hi]).  Hits use
+ * the surfel disks of the launcher (same test as nearest_hit: t > t_eps,
+ * |o + t u - p_m| <= r_s, u = (p - o)/|p - o|).  Per ray the answer is
+ * 1 visible, 0 blocked; in parity mode 2 marks a decision that the FP32 error
+ * bands can flip (a surfel that is a hit or ambiguous under the bands lies
+ * within the band of t_in, or the nearest clear hit does).  t_out receives
+ * t_in (the box entry distance along u, 0 when o is inside the box).
+ */
+typedef struct {
+    const OracleArgs* a;
+    const Pts64* P;
+    const double *o, *p, *box;
+    int64_t lo, hi;
+    int32_t* state;
+    double* t_out;
+} VisWork;
+
+static double box_entry(const double* o, const double* u, const double* lo, const double* hi)
+{
+    double t0 = 0.0, t1 = INFINITY;
+    for (int ax = 0; ax < 3; ++ax) {
+        if (u[ax] != 0.0) {
+            double ta = (lo[ax] - o[ax]) / u[ax], tb = (hi[ax] - o[ax]) / u[ax];
+            if (ta > tb) { double t = ta; ta = tb; tb = t; }
+            if (ta > t0) t0 = ta;
+            if (tb < t1) t1 = tb;
+        } else if (o[ax] < lo[ax] || o[ax] > hi[ax]) {
+            return INFINITY;
+        }
+    }
+    return t0 <= t1 ? t0 : INFINITY;
+}
+
+static void* vis_worker(void* arg)
+{
+    VisWork* w = (VisWork*)arg;
+    const OracleArgs* a = w->a;
+    const Pts64* P = w->P;
+    for (int64_t r = w->lo; r < w->hi; ++r) {
+        const double* o = w->o + 3 * r;
+        const double* p = w->p + 3 * r;
+        double u[3] = {p[0] - o[0], p[1] - o[1], p[2] - o[2]};
+        double len = sqrt(dot3(u, u));
+        if (!(len > 0.0)) { w->state[r] = 1; if (w->t_out) w->t_out[r] = 0.0; continue; }
+        u[0] /= len; u[1] /= len; u[2] /= len;
+        const double t_in = box_entry(o, u, w->box + 6 * r, w->box + 6 * r + 3);
+        if (w->t_out) w->t_out[r] = t_in;
+        double t_clear = INFINITY, t_soft = INFINITY, band_at = 0.0;
+        for (int64_t m = 0; m < a->n_pts; ++m) {
+            const double pm[3] = {P->px[m], P->py[m], P->pz[m]}, nm[3] = {P->nx[m], P->ny[m], P->nz[m]};
+            if (!a->parity) {
+                double t;
+                if (surfel_hit(a, P, o, u, m, &t) && t < t_clear) t_clear = t;
+                continue;
+            }
+            double t, band;
+            int cand, amb;
+            if (!surfel_class(a, pm, nm, o, u, 1.0, &t, &band, &cand, &amb)) continue;
+            if (cand && !amb && t < t_clear) { t_clear = t; }
+            if ((cand || amb) && t < t_soft) { t_soft = t; band_at = band; }
+        }
+        if (!a->parity) { w->state[r] = t_clear >= t_in ? 1 : 0; continue; }
+        /* the compared implementation's t_in and t moves by the same bands */
+        const double band = (a->err_abs + fabs(t_in) * a->err_dir) + band_at + a->tie_rel * t_in;
+        if (t_soft >= t_in + band) w->state[r] = 1;           /* clearly nothing before the box */
+        else if (t_clear < t_in - band) w->state[r] = 0;      /* clearly blocked */
+        else w->state[r] = 2;
+    }
+    return NULL;
+}
+
+int oracle_visibility(const OracleArgs* a, int64_t n, const double* o, const double* p, const double* box,
+                      int32_t* state, double* t_out)
+{
+    if (!a || n < 0 || (n > 0 && (!o || !p || !box || !state)) || a->n_pts < 0 ||
+        (a->n_pts > 0 && (!a->xyz || !a->nrm)) || !(a->r_s > 0.0))
+        return -1;
+    Pts64 P;
+    size_t nb = (size_t)(a->n_pts > 0 ? a->n_pts : 1) * sizeof(double);
+    P.px = malloc(nb); P.py = malloc(nb); P.pz = malloc(nb);
+    P.nx = malloc(nb); P.ny = malloc(nb); P.nz = malloc(nb);
+    int status = (!P.px || !P.py || !P.pz || !P.nx || !P.ny || !P.nz) ? -2 : 0;
+    for (int64_t m = 0; m < a->n_pts && !status; ++m) {
+        P.px[m] = a->xyz[3 * m]; P.py[m] = a->xyz[3 * m + 1]; P.pz[m] = a->xyz[3 * m + 2];
+        double nx = a->nrm[3 * m], ny = a->nrm[3 * m + 1], nz = a->nrm[3 * m + 2];
+        double len = sqrt(nx * nx + ny * ny + nz * nz);
+        if (!(len > 0.0) || !isfinite(len)) status = -1;
+        else { P.nx[m] = nx / len; P.ny[m] = ny / len; P.nz[m] = nz / len; }
+    }
+    if (!status && n > 0) {
+        int nt = a->n_threads > 0 ? a->n_threads : 1;
+        if (nt > n) nt = (int)n;
+        VisWork* W = calloc((size_t)nt, sizeof(VisWork));
+        pthread_t* T = calloc((size_t)nt, sizeof(pthread_t));
+        if (!W || !T) status = -2;
+        for (int k = 0; k < nt && !status; ++k) {
+            W[k] = (VisWork){a, &P, o, p, box, n * k / nt, n * (k + 1) / nt, state, t_out};
+        }
+        if (!status) {
+            for (int k = 1; k < nt; ++k) pthread_create(&T[k], NULL, vis_worker, &W[k]);
+            vis_worker(&W[0]);
+            for (int k = 1; k < nt; ++k) pthread_join(T[k], NULL);
+        }
+        free(W); free(T);
+    }
+    free(P.px); free(P.py); free(P.pz); free(P.nx); free(P.ny); free(P.nz);
+    return status;
+}
+
+/* ------------------------------------------------------------------------ */
 /* path refinement (Section 2.3, Eq. 2)                                      */
 /* ------------------------------------------------------------------------ */
 

@@ -1,0 +1,142 @@
+"""Pins of the cone-tracer oracle (oracle/cone.py) against closed forms.
+
+* SplitMix64: the published first output for state 0 (the generator's
+  reference value);
+* IEs of the empty box room: the count per wall from the sampling grid and
+  the subvoxel grid (integer arithmetic by hand), reception points on the
+  wall planes, normals equal to the wall normals;
+* cone-sphere distances in the four regimes (inside, lateral, apex, behind);
+* block margins of a segment against voxel blocks;
+* transmission phase in the convex empty room: every IE and the RX are
+  visible from the TX (a convex room hides nothing);
+* propagation in the box room: the line-of-sight path has length |TX - RX|,
+  every single reflection of the image method is found with a polyline no
+  shorter than the image path, no partial path interacts twice with one
+  planar wall in a row (the separation plane), and with two reflections the
+  25 image-method label sequences are all found.
+"""
+import math
+
+import numpy as np
+import pytest
+
+import scenes
+from oracle import cone, image_method
+
+ORIGIN = np.array([-0.55, -0.45, -0.6], np.float32)
+VOXEL, DV, DIMS = 0.5, 2, (23, 19, 9)
+
+
+def test_splitmix64_reference_value():
+    # first output of SplitMix64 seeded with 0
+    assert cone.splitmix64(0) == 0xE220A8397B1DCDAF
+
+
+def _wall_counts():
+    """Subvoxels holding points, per wall, by hand: points sit at cell centres
+    0.1, 0.3, ... of a 0.2 m grid; subvoxels are 0.25 m from the origin."""
+    sv = 0.25
+
+    def cells(lo, n, o):     # subvoxel indices of n points lo, lo + 0.2, ...
+        return len({int(math.floor((lo + 0.2 * k - o) / sv)) for k in range(n)})
+    x, y, z = cells(0.1, 50, -0.55), cells(0.1, 40, -0.45), cells(0.1, 15, -0.6)
+    return {0: x * y, 1: x * y, 2: y * z, 3: y * z, 4: x * z, 5: x * z}
+
+
+def test_box_room_ies_closed_form():
+    s = scenes.box_room()
+    ies = cone.ie_build(s.xyz, s.normal, s.label, ORIGIN, VOXEL, DV, DIMS)
+    want = _wall_counts()
+    got = {lab: int(np.sum(ies["label"] == lab)) for lab in range(6)}
+    assert got == want
+    assert int(ies["count"].sum()) == s.n_points
+    planes = {0: (2, 0.0), 1: (2, 3.0), 2: (0, 0.0), 3: (0, 10.0), 4: (1, 0.0), 5: (1, 8.0)}
+    for lab, (ax, c) in planes.items():
+        m = ies["label"] == lab
+        assert np.allclose(ies["pos"][m][:, ax], c, atol=1e-6)
+        n = np.zeros(3)
+        n[ax] = 1.0
+        assert np.allclose(np.abs(ies["nrm"][m] @ n), 1.0, atol=1e-12)
+    assert np.all(np.diff(ies["key"]) > 0)
+
+
+def test_cone_sphere_regimes():
+    o = np.zeros(3)
+    d = np.array([1.0, 0.0, 0.0])
+    t = math.radians(10.0)
+    ct, st = math.cos(t), math.sin(t)
+    # on the axis: inside, distance 0
+    assert cone.cone_sphere_margin(o, d, ct, st, np.array([5.0, 0, 0]), 0.1) == pytest.approx(0.1)
+    # lateral: centre at (5, h): distance to the surface line h cos t - 5 sin t
+    h = 2.0
+    assert cone.cone_sphere_margin(o, d, ct, st, np.array([5.0, h, 0]), 0.3) == pytest.approx(
+        0.3 - (h * ct - 5.0 * st))
+    # behind the apex, off axis: nearest point is the apex
+    c = np.array([-1.0, 0.5, 0.0])
+    assert cone.cone_sphere_margin(o, d, ct, st, c, 0.2) == pytest.approx(0.2 - math.hypot(1.0, 0.5))
+    # beside the apex within the polar region boundary: a cos t + rho sin t = 0 -> apex distance
+    rho = 1.0
+    a = -rho * st / ct
+    c = np.array([a, rho, 0.0])
+    assert cone.cone_sphere_margin(o, d, ct, st, c, 0.0) == pytest.approx(-math.hypot(a, rho), rel=1e-9)
+
+
+def test_block_margins():
+    o = np.array([0.25, 0.25, 0.25])
+    d = np.array([1.0, 0.0, 0.0])
+    cells = np.array([[0, 0, 0], [5, 0, 0], [3, 2, 0], [3, 3, 0]])
+    m = cone.block_margins(o, d, 2.0, cells, np.zeros(3), 0.5)
+    # block of (0,0,0) is [-0.5, 1.0)^3: the segment covers x in [0.25, 1.0] -> 0.75
+    assert m[0] == pytest.approx(0.75)
+    # (5,0,0): block x in [2.0, 3.5): the segment ends at 2.25 -> overlap 0.25
+    assert m[1] == pytest.approx(0.25)
+    # (3,2,0): block y in [0.5, 2.0): the ray at y = 0.25 misses by 0.25
+    assert m[2] == pytest.approx(-0.25)
+    assert m[3] == pytest.approx(-0.75)
+
+
+@pytest.fixture(scope="module")
+def room_k1():
+    s = scenes.box_room()
+    ies = cone.ie_build(s.xyz, s.normal, s.label, ORIGIN, VOXEL, DV, DIMS)
+    sc = cone.Scene(s.xyz, s.normal, s.label, s.surfel_radius, 1e-4)
+    res = cone.trace(sc, ies, s.tx, s.rx, ORIGIN, VOXEL, DV, DIMS, K=1, kappa=0, half_angle=math.radians(2.5))
+    return s, ies, res
+
+
+def test_transmission_sees_every_ie_in_a_convex_room(room_k1):
+    s, ies, res = room_k1
+    assert len(res["nodes"][0]) == len(ies["label"])
+    los = [r for r in res["records"] if r["chain"] == ()]
+    assert len(los) == 1
+    assert los[0]["length"] == pytest.approx(math.sqrt(34.0), rel=1e-12)
+
+
+def test_single_reflections_and_separation_plane(room_k1):
+    s, ies, res = room_k1
+    img = image_method.box_room_paths(s.tx[0].astype(float), s.rx[0].astype(float), max_reflections=1)
+    found = {k[3]: g for k, g in res["paths"].items()}
+    for seq, (L, _) in img.items():
+        assert seq in found, seq
+        if seq:
+            for r in found[seq]["rows"]:
+                assert r["length"] >= L * (1 - 1e-12)        # a polyline via the wall is no shorter
+                assert r["length"] <= L * 1.01
+    for r in res["records"]:
+        labs = r["labels"]
+        assert all(a != b for a, b in zip(labs, labs[1:]))
+
+
+@pytest.mark.timeout(600)
+def test_two_reflections_find_the_image_sequences():
+    s = scenes.box_room()
+    ies = cone.ie_build(s.xyz, s.normal, s.label, ORIGIN, VOXEL, DV, DIMS)
+    sc = cone.Scene(s.xyz, s.normal, s.label, s.surfel_radius, 1e-4)
+    res = cone.trace(sc, ies, s.tx, s.rx, ORIGIN, VOXEL, DV, DIMS, K=2, kappa=100, half_angle=math.radians(2.5))
+    img = image_method.box_room_paths(s.tx[0].astype(float), s.rx[0].astype(float), max_reflections=2)
+    found = {k[3] for k in res["paths"]}
+    assert set(img) <= found, sorted(set(img) - found)
+    for k, g in res["paths"].items():
+        assert len(g["rows"]) <= 100 and g["count"] >= len(g["rows"])
+        labs = k[3]
+        assert all(a != b for a, b in zip(labs, labs[1:]))
