@@ -454,6 +454,99 @@ int sdf_intersect(const PcrlScene* scene, const float* o, const float* d, const 
                   pcrl_stream_t stream);
 
 /* ------------------------------------------------------------------------ */
+/* environment-driven coarse tracing with conical rays (Sections 2.1-2.2.4)  */
+/* ------------------------------------------------------------------------ */
+
+/* Low-resolution voxel grid of the intersectable entities (IEs, Section 2.1):
+ * voxels of edge `voxel` from `origin`, dims voxels per axis, each divided
+ * into dv^3 subvoxels (Table 1: voxel 0.5 m, D_v = 2). */
+typedef struct {
+    float   origin[3];
+    float   voxel;
+    int32_t dv;           /* 1..8 */
+    int32_t dims[3];      /* voxels per axis; dims product * dv^3 < 2^31 */
+} PcrlIeGrid;
+
+typedef struct PcrlIes PcrlIes;           /* opaque: a scene's IE table (library-owned) */
+typedef struct PcrlConeLaunch PcrlConeLaunch;  /* opaque: one cone-traced query (library-owned) */
+
+typedef struct {
+    int64_t n_ies;        /* point IEs: (subvoxel, label) pairs holding points */
+    int64_t n_voxels;     /* voxels of the grid */
+    int64_t n_occupied;   /* voxels holding an IE */
+    int64_t device_bytes;
+} PcrlIeInfo;
+
+/* Point IEs of a scene's static points (Section 2.1): the points of one label
+ * whose position lies in one subvoxel, the subvoxel cell taken in FP32 as
+ * floor((p - origin) * (1 / (voxel / dv))).  Each IE keeps its label, the
+ * number of its points, a reception point (the mean of its positions) and a
+ * normal (the normalised mean of their unit normals).  IEs are ordered by
+ * (voxel, subvoxel within the voxel, label).  The scene must outlive the
+ * table.  Synchronous.  PCRL_EINVAL: a point outside the grid, bad grid
+ * parameters, a scene with dynamic points (update_points). */
+int ie_build(PcrlScene* scene, const PcrlIeGrid* grid, pcrl_stream_t stream, PcrlIes** out);
+int ie_info(const PcrlIes* ies, PcrlIeInfo* out);
+/* Copy the IE table into caller device arrays of at least n_ies entries
+ * (any may be NULL): key (voxel * dv^3 + local subvoxel) << 32 | label,
+ * sub [n,3] subvoxel cell, label, count, pos [n,3], nrm [n,3]. */
+int ie_table(const PcrlIes* ies, uint64_t* key, int32_t* sub, uint32_t* label, uint32_t* count, float* pos,
+             float* nrm, pcrl_stream_t stream);
+int release_ies(PcrlIes* ies);
+
+typedef struct {
+    int32_t max_interactions;  /* K in [0, 8] (Table 1: 5) */
+    float   half_angle;        /* cone half-angle in radians, (0, pi/4]; <= 0 -> 2.5 degrees */
+    int32_t flags;             /* 0 */
+    int32_t reserved;
+} PcrlConeParams;
+
+typedef struct {
+    int64_t nodes[PCRL_MAX_REFLECTIONS + 1];       /* [k]: partial paths with k interactions kept */
+    int64_t candidates[PCRL_MAX_REFLECTIONS + 1];  /* [k]: targets that passed the cone and plane tests
+                                                      ([0]: the transmission phase's rays) */
+    int64_t visible[PCRL_MAX_REFLECTIONS + 1];     /* [k]: of those, visible */
+    int64_t records;                               /* receptions (paths reaching an RX) */
+    double  ms_transmission, ms_propagation;       /* host wall clock of the two phases */
+} PcrlConeStats;
+
+/* Environment-driven coarse tracing of one query (Sections 2.2.2-2.2.4):
+ *   transmission: from every TX a visibility ray towards every IE's
+ *     reception point and every RX; a ray is blocked when a surfel disk
+ *     (radius r_s, t > t_eps) is hit before it enters the target's subvoxel;
+ *   propagation: every visible IE is an interaction; a conical ray leaves it
+ *     (apex the reception point, axis the incoming direction mirrored about
+ *     the IE's normal, half_angle); its axis is marched through the IE grid
+ *     up to the voxel of the axis's first surfel hit (or the grid's exit) and
+ *     every IE and RX in the voxels within one voxel of the march is a target
+ *     when the cone meets its subvoxel's bounding sphere, its reception
+ *     point lies in front of the separation plane at the apex (normal: the
+ *     IE's normal on the reflected side) and a visibility ray reaches it;
+ *   partial paths reaching the same IE with the same label sequence are
+ *     merged (the one of smallest SplitMix64 priority is kept), up to
+ *     max_interactions; an RX target ends a coarse path.
+ * tx, rx: device [n,3] float32 (1 <= n_tx <= 255, 0 <= n_rx <= 65535).
+ * Synchronous; PCRL_EINVAL for bad arguments or IEs of another scene. */
+int cone_launch(const PcrlIes* ies, const float* tx, int32_t n_tx, const float* rx, int32_t n_rx,
+                const PcrlConeParams* params, pcrl_stream_t stream, PcrlConeLaunch** out);
+int cone_stats(const PcrlConeLaunch* launch, PcrlConeStats* out);
+/* Partial paths with k (1..K) interactions, in their kept order (by TX,
+ * label sequence, IE, priority): device arrays of at least nodes[k] entries
+ * (any may be NULL): IE, parent (index in generation k-1, or the TX for
+ * k = 1), TX, priority, polyline length TX -> reception points. */
+int cone_nodes(const PcrlConeLaunch* launch, int32_t k, int32_t* ie, int32_t* parent, int32_t* tx,
+               uint64_t* prio, float* length, pcrl_stream_t stream);
+/* Coarse paths: receptions grouped by (tx, rx, number of interactions,
+ * labels), each group's count and its kappa rows of smallest priority
+ * (Section 2.2.3), rows sorted by (tx, rx, n, labels, priority).  `ray` holds
+ * k << 40 | node index of the row's last interaction (k = 0: the TX); len_poly
+ * = len_unf = the polyline length TX -> reception points -> RX; points are
+ * the reception points.  Synchronous; PCRL_EOVERFLOW with n_rows = rows
+ * needed when capacity is too small. */
+int cone_collect(PcrlConeLaunch* launch, int32_t kappa, PcrlPaths* out, pcrl_stream_t stream);
+int release_cone(PcrlConeLaunch* launch);
+
+/* ------------------------------------------------------------------------ */
 /* serving: a request loop over one device-resident, incrementally           */
 /* re-voxelised scene                                                         */
 /* ------------------------------------------------------------------------ */

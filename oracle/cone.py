@@ -285,9 +285,11 @@ class Scene:
 def _merge_similar(kids):
     """Partial paths that reach the same IE with the same labels in the same
     order are similar paths: per (tx, labels, IE) one node is kept, the one of
-    smallest (priority, parent).  Exact nodes are chosen among the exact ones
-    (the definition); when a node that only a perturbed decision admits would
-    win, it is kept too and both are excused (the winner can differ)."""
+    smallest (priority, parent).  The definition keeps the smallest exact
+    node.  A node admitted only through a banded decision may or may not
+    exist in an FP32 implementation, so every such node ordered before the
+    group's first certain node (exact, no banded decision on its chain) is
+    kept too, and all of them are excused: any of them can be the one kept."""
     kids.sort(key=lambda c: (c["tx"], c["labels"], c["ie"], c["prio"], c["parent"]))
     out = []
     i = 0
@@ -297,13 +299,22 @@ def _merge_similar(kids):
         while j < len(kids) and (kids[j]["tx"], kids[j]["labels"], kids[j]["ie"]) == key:
             j += 1
         group = kids[i:j]
+        head = []
+        for c in group:
+            head.append(c)
+            if c["exact"] and not c["excused"]:
+                break
+        if len(head) > 1 or not (head[0]["exact"] and not head[0]["excused"]):
+            for c in head:
+                c["excused"] = True
+        # the definition's own choice: the smallest exact node
         best_exact = next((c for c in group if c["exact"]), None)
-        first = group[0]
-        if best_exact is not None and best_exact is not first:
-            first["excused"] = best_exact["excused"] = True
-            out += [first, best_exact]
-        else:
-            out.append(first)
+        if best_exact is not None and best_exact not in head:
+            best_exact["excused"] = True
+            head.append(best_exact)
+        for c in head:
+            c["exact"] = c["exact"] and c is best_exact
+        out += head
         i = j
     out.sort(key=lambda c: (c["tx"], c["labels"], c["ie"], c["prio"]))
     return out
@@ -410,9 +421,10 @@ def trace(scene: Scene, ies, tx, rx, origin, voxel, dv, dims, K, kappa, half_ang
                 if mf < -band:
                     continue                      # no end of the axis reaches this block
                 w_in = me >= 0
-                w_amb = mn <= band                # some acceptable end, or rounding, leaves it out
+                w_amb = scene.parity and mn <= band   # some acceptable end, or rounding, leaves it out
                 wt = (int(w[0]), int(w[1]), int(w[2]))
-                targets = [("ie", e) for e in by_voxel.get(wt, []) if e != c["ie"]]
+                # the last generation's cones only end paths: no IE targets
+                targets = [("ie", e) for e in by_voxel.get(wt, []) if e != c["ie"]] if k + 1 < K else []
                 targets += [("rx", j) for j in rx_by_voxel.get(wt, [])]
                 for kind, t in targets:
                     pc = ie_lo[t] + 0.5 * sv if kind == "ie" else rx_lo[t] + 0.5 * sv
@@ -420,7 +432,7 @@ def trace(scene: Scene, ies, tx, rx, origin, voxel, dv, dims, K, kappa, half_ang
                     m_cone = cone_sphere_margin(o1, d1, cos_t, sin_t, pc, R)
                     m_plane = float((pr - o1) @ n_o)
                     exact = w_in and m_cone >= 0 and m_plane > 0
-                    amb = w_amb or abs(m_cone) <= band or abs(m_plane) <= band
+                    amb = scene.parity and (w_amb or abs(m_cone) <= band or abs(m_plane) <= band)
                     if exact or amb:
                         q.append((ci, kind, t, exact, amb))
         parents = kept

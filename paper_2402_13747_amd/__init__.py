@@ -24,7 +24,7 @@ from ._lib import (KEY_LABELS, KEY_LEAVES, LAUNCH_COHERENT, LAUNCH_SDF, LAUNCH_S
                    REFINE_DEGENERATE, REFINE_MISS, REFINE_NOT_CONVERGED, REFINE_OCCLUDED, REFINE_VALID,
                    REFINE_WRONG_SIDE, PcrlError, check, lib)
 
-__all__ = ["build_voxels", "launch_rays", "launch_batch", "batch_autotune", "launch_directions", "collect_paths",
+__all__ = ["ie_build", "cone_launch", "cone_collect", "IeTable", "ConeLaunch", "build_voxels", "launch_rays", "launch_batch", "batch_autotune", "launch_directions", "collect_paths",
            "refine_paths", "sdf_intersect", "use_torch_allocator", "Scene", "Launch", "Server", "PcrlError", "KEY_LABELS",
            "KEY_LEAVES", "REFINE_VALID", "REFINE_NOT_CONVERGED", "REFINE_MISS", "REFINE_WRONG_SIDE",
            "REFINE_OCCLUDED", "REFINE_DEGENERATE", "version", "library_path"]
@@ -509,6 +509,169 @@ def sdf_intersect(scene: Scene, o, d, t_range=None, h=0.0, eps=0.0, max_steps=0,
         st = stats.cpu()
         res["evals"], res["reads"] = int(st[0]), int(st[1])
     return res
+
+
+class IeTable:
+    """The intersectable entities of a scene on a voxel grid (owns a PcrlIes handle)."""
+
+    def __init__(self, handle, scene, grid):
+        self._h = handle
+        self.scene = scene
+        self.device = scene.device
+        self.grid = grid
+
+    @property
+    def handle(self):
+        return self._h
+
+    def info(self) -> dict:
+        inf = _lib.PcrlIeInfo()
+        check("ie_info", lib.ie_info(self._h, C.byref(inf)))
+        return {name: getattr(inf, name) for name, _ in inf._fields_}
+
+    def table(self) -> dict:
+        n = self.info()["n_ies"]
+        dev = self.device
+        out = {"key": torch.empty(max(n, 1), dtype=torch.int64, device=dev),
+               "sub": torch.empty((max(n, 1), 3), dtype=torch.int32, device=dev),
+               "label": torch.empty(max(n, 1), dtype=torch.int32, device=dev),
+               "count": torch.empty(max(n, 1), dtype=torch.int32, device=dev),
+               "pos": torch.empty((max(n, 1), 3), dtype=torch.float32, device=dev),
+               "nrm": torch.empty((max(n, 1), 3), dtype=torch.float32, device=dev)}
+        with _on(dev):
+            check("ie_table", lib.ie_table(self._h, *[_ptr(out[k]) for k in ("key", "sub", "label", "count", "pos",
+                                                                               "nrm")], _stream(dev)))
+        return {k: v[:n] for k, v in out.items()}
+
+    def release(self):
+        if self._h:
+            lib.release_ies(self._h)
+            self._h = None
+
+    def __del__(self):
+        try:
+            self.release()
+        except Exception:  # pragma: no cover - interpreter shutdown
+            pass
+
+
+def ie_build(scene: Scene, origin, voxel, dv, dims) -> IeTable:
+    """Intersectable entities (Section 2.1): the scene's static points grouped
+    by (subvoxel, label) on the grid of ``dims`` voxels of edge ``voxel`` from
+    ``origin``, each voxel divided into ``dv``^3 subvoxels."""
+    g = _lib.PcrlIeGrid()
+    for a in range(3):
+        g.origin[a] = float(origin[a])
+        g.dims[a] = int(dims[a])
+    g.voxel = float(voxel)
+    g.dv = int(dv)
+    h = C.c_void_p()
+    with _on(scene.device):
+        check("ie_build", lib.ie_build(scene.handle, C.byref(g), _stream(scene.device), C.byref(h)))
+    return IeTable(h, scene, dict(origin=tuple(float(x) for x in origin), voxel=float(voxel), dv=int(dv),
+                                  dims=tuple(int(x) for x in dims)))
+
+
+class ConeLaunch:
+    """One query of the environment-driven cone tracer (owns a PcrlConeLaunch handle)."""
+
+    def __init__(self, handle, ies, K, inputs):
+        self._h = handle
+        self.ies = ies
+        self.device = ies.device
+        self.K = K
+        self._inputs = inputs
+
+    @property
+    def handle(self):
+        return self._h
+
+    def stats(self) -> dict:
+        st = _lib.PcrlConeStats()
+        check("cone_stats", lib.cone_stats(self._h, C.byref(st)))
+        out = {}
+        for name, _ in st._fields_:
+            v = getattr(st, name)
+            out[name] = list(v)[: self.K + 1] if hasattr(v, "__len__") else v
+        return out
+
+    def nodes(self, k) -> dict:
+        n = self.stats()["nodes"][k]
+        dev = self.device
+        out = {"ie": torch.empty(max(n, 1), dtype=torch.int32, device=dev),
+               "parent": torch.empty(max(n, 1), dtype=torch.int32, device=dev),
+               "tx": torch.empty(max(n, 1), dtype=torch.int32, device=dev),
+               "prio": torch.empty(max(n, 1), dtype=torch.int64, device=dev),
+               "length": torch.empty(max(n, 1), dtype=torch.float32, device=dev)}
+        if n:
+            with _on(dev):
+                check("cone_nodes", lib.cone_nodes(self._h, int(k), *[_ptr(out[f]) for f in ("ie", "parent", "tx",
+                                                                                             "prio", "length")],
+                                                   _stream(dev)))
+        return {f: v[:n] for f, v in out.items()}
+
+    def release(self):
+        if self._h:
+            lib.release_cone(self._h)
+            self._h = None
+
+    def __del__(self):
+        try:
+            self.release()
+        except Exception:  # pragma: no cover - interpreter shutdown
+            pass
+
+
+def cone_launch(ies: IeTable, tx, rx, max_interactions, half_angle=0.0) -> ConeLaunch:
+    """Environment-driven coarse tracing with conical rays (Sections 2.2.2-2.2.4)."""
+    dev = ies.device
+    txt = _as_tensor(tx, torch.float32, dev, 3)
+    rxt = _as_tensor(np.zeros((0, 3), np.float32) if rx is None else rx, torch.float32, dev, 3)
+    p = _lib.PcrlConeParams(int(max_interactions), float(half_angle), 0, 0)
+    h = C.c_void_p()
+    with _on(dev):
+        check("cone_launch", lib.cone_launch(ies.handle, _ptr(txt), txt.shape[0],
+                                             _ptr(rxt) if rxt.shape[0] else None, rxt.shape[0], C.byref(p),
+                                             _stream(dev), C.byref(h)))
+    return ConeLaunch(h, ies, int(max_interactions), (txt, rxt))
+
+
+def cone_collect(launch: ConeLaunch, kappa=100, capacity=None) -> dict:
+    """Coarse paths of a cone launch: per (tx, rx, n, labels) the count and the
+    kappa rows of smallest priority (Section 2.2.3)."""
+    dev = launch.device
+    K = max(launch.K, 1)
+    cap = int(capacity) if capacity is not None else 4096
+    for _ in range(2):
+        bufs = {
+            "tx": torch.empty(cap, dtype=torch.int32, device=dev),
+            "rx": torch.empty(cap, dtype=torch.int32, device=dev),
+            "n_refl": torch.empty(cap, dtype=torch.int32, device=dev),
+            "key": torch.empty(max(cap * K, 1), dtype=torch.int64, device=dev),
+            "count": torch.empty(cap, dtype=torch.int64, device=dev),
+            "rank": torch.empty(cap, dtype=torch.int32, device=dev),
+            "ray": torch.empty(cap, dtype=torch.int64, device=dev),
+            "len_poly": torch.empty(cap, dtype=torch.float32, device=dev),
+            "len_unf": torch.empty(cap, dtype=torch.float32, device=dev),
+            "points": torch.empty(max(cap * K * 3, 1), dtype=torch.float32, device=dev),
+        }
+        out = _lib.PcrlPaths()
+        out.capacity = cap
+        for k, t in bufs.items():
+            setattr(out, k, t.data_ptr())
+        with _on(dev):
+            st = lib.cone_collect(launch.handle, int(kappa), C.byref(out), _stream(dev))
+        if st == PCRL_EOVERFLOW:
+            cap = int(out.n_rows)
+            continue
+        check("cone_collect", st)
+        n = int(out.n_rows)
+        res = {k: (t[: n * K].view(n, K) if k == "key" else t[: n * K * 3].view(n, K, 3) if k == "points"
+                   else t[:n]) for k, t in bufs.items()}
+        res["n_rows"] = n
+        res["n_keys"] = int(out.n_keys)
+        return res
+    raise PcrlError("cone_collect", PCRL_EOVERFLOW, "capacity retry failed")
 
 
 def _relaunch(launch: Launch, record_capacity: int):

@@ -139,6 +139,26 @@ class PcrlServeStats(C.Structure):
                 ("used_bytes", C.c_int64)]
 
 
+class PcrlIeGrid(C.Structure):
+    _fields_ = [("origin", C.c_float * 3), ("voxel", C.c_float), ("dv", C.c_int32), ("dims", C.c_int32 * 3)]
+
+
+class PcrlIeInfo(C.Structure):
+    _fields_ = [("n_ies", C.c_int64), ("n_voxels", C.c_int64), ("n_occupied", C.c_int64),
+                ("device_bytes", C.c_int64)]
+
+
+class PcrlConeParams(C.Structure):
+    _fields_ = [("max_interactions", C.c_int32), ("half_angle", C.c_float), ("flags", C.c_int32),
+                ("reserved", C.c_int32)]
+
+
+class PcrlConeStats(C.Structure):
+    _fields_ = [("nodes", C.c_int64 * (MAX_REFLECTIONS + 1)), ("candidates", C.c_int64 * (MAX_REFLECTIONS + 1)),
+                ("visible", C.c_int64 * (MAX_REFLECTIONS + 1)), ("records", C.c_int64),
+                ("ms_transmission", C.c_double), ("ms_propagation", C.c_double)]
+
+
 # name -> (restype, argtypes); every symbol declared in include/pcrl.h
 SIGNATURES = {
     "set_allocator": (C.c_int, [C.POINTER(PcrlAllocator)]),
@@ -165,6 +185,18 @@ SIGNATURES = {
     "launch_batch": (C.c_int, [C.POINTER(PcrlQuery), C.c_int32, C.POINTER(PcrlBatchParams), C.c_void_p,
                                C.POINTER(C.c_void_p)]),
     "batch_autotune": (C.c_int, [C.POINTER(PcrlQuery), C.c_int32, C.c_void_p, C.POINTER(PcrlBatchParams)]),
+    "ie_build": (C.c_int, [C.c_void_p, C.POINTER(PcrlIeGrid), C.c_void_p, C.POINTER(C.c_void_p)]),
+    "ie_info": (C.c_int, [C.c_void_p, C.POINTER(PcrlIeInfo)]),
+    "ie_table": (C.c_int, [C.c_void_p, C.c_void_p, C.c_void_p, C.c_void_p, C.c_void_p, C.c_void_p, C.c_void_p,
+                           C.c_void_p]),
+    "release_ies": (C.c_int, [C.c_void_p]),
+    "cone_launch": (C.c_int, [C.c_void_p, C.c_void_p, C.c_int32, C.c_void_p, C.c_int32, C.POINTER(PcrlConeParams),
+                              C.c_void_p, C.POINTER(C.c_void_p)]),
+    "cone_stats": (C.c_int, [C.c_void_p, C.POINTER(PcrlConeStats)]),
+    "cone_nodes": (C.c_int, [C.c_void_p, C.c_int32, C.c_void_p, C.c_void_p, C.c_void_p, C.c_void_p, C.c_void_p,
+                             C.c_void_p]),
+    "cone_collect": (C.c_int, [C.c_void_p, C.c_int32, C.POINTER(PcrlPaths), C.c_void_p]),
+    "release_cone": (C.c_int, [C.c_void_p]),
     "serve_create": (C.c_int, [C.c_void_p, C.POINTER(PcrlServeParams), C.POINTER(C.c_void_p)]),
     "serve_submit": (C.c_int, [C.c_void_p, C.c_void_p, C.c_int32, C.c_void_p, C.c_int32, C.POINTER(PcrlLaunchParams),
                                C.POINTER(C.c_int64)]),

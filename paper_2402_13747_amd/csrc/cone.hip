@@ -1,0 +1,1343 @@
+// cone.hip -- environment-driven coarse path tracing with conical rays
+// (paper, Section 2.1 intersectable entities; Section 2.2.2 transmission
+// phase; Section 2.2.3 propagation phase; Section 2.2.4 voxel cone tracing).
+//
+// Intersectable entities (IEs): the points of one label inside one subvoxel
+// of a low-resolution voxel grid (voxel edge V, subvoxel V / D_v), each with
+// a reception point (mean position) and a normal (normalised mean normal).
+// One query is traced generation by generation:
+//   transmission   a visibility ray from every TX towards every IE and RX;
+//   generation k   the kept partial paths with k interactions; each casts a
+//                  reflected cone whose axis is marched through the voxel
+//                  grid: the IEs and RX of the voxels within one voxel of the
+//                  march (the paper's neighbour evaluation) that meet the cone
+//                  (subvoxel bounding sphere), lie in front of the separation
+//                  plane and are visible become generation k + 1 or receptions;
+//   merge          partial paths reaching the same IE with the same labels in
+//                  the same order are one (the smallest SplitMix64 priority
+//                  wins), sorted by (TX, labels, IE, priority);
+//   collect        receptions grouped by (TX, RX, labels), kappa rows each.
+// Visibility and axis rays run through the launcher's hierarchy with its
+// wave-cooperative surfel tests.  Every step is a kernel; the host only reads
+// back the sizes of the next generation.
+#include "trace_core.h"
+
+#include <algorithm>
+#include <chrono>
+#include <cmath>
+#include <vector>
+
+namespace pcrl {
+
+constexpr uint32_t RX_BIT = 0x80000000u;  // candidate target: an RX (low bits its index)
+constexpr int CONE_BLOCK = 256;
+
+struct IeGrid {
+    float org[3];
+    float V;       // voxel edge
+    float sv;      // subvoxel edge (FP32 V / dv)
+    float inv_sv;  // 1 / sv (FP32)
+    int32_t dv;
+    int32_t dims[3];
+};
+
+}  // namespace pcrl
+
+struct PcrlIes {
+    const PcrlScene* scene = nullptr;
+    int device = 0;
+    pcrl::IeGrid g{};
+    pcrl::DevBufs bufs;
+    int64_t n_ie = 0, n_vox = 0, n_occ = 0, bytes = 0;
+    uint64_t* key = nullptr;
+    int32_t* sub = nullptr;      // [n,3]
+    uint32_t* label = nullptr;
+    uint32_t* count = nullptr;
+    float4* pos = nullptr;       // reception point
+    float4* nrm = nullptr;       // unit normal
+    uint2* vox = nullptr;        // per voxel: (first IE, count)
+    uint8_t* near = nullptr;     // per voxel: an IE within Chebyshev distance 1
+};
+
+namespace pcrl {
+
+// One generation of partial paths (nodes) with k interactions.
+struct Gen {
+    int64_t n = 0;
+    float4* apex = nullptr;      // reception point, polyline length in w
+    uint32_t* ie = nullptr;
+    uint32_t* parent = nullptr;
+    uint32_t* tx = nullptr;
+    uint32_t* gid = nullptr;     // label-sequence group (dense, in (tx, labels) order)
+    uint64_t* prio = nullptr;
+    float* t_end = nullptr;      // end of the axis march
+};
+
+struct Rec {                     // one reception
+    uint32_t node;               // node index in its generation (the TX for k = 0)
+    uint32_t rx;
+    uint32_t k;
+    float len;
+};
+
+}  // namespace pcrl
+
+struct PcrlConeLaunch {
+    const PcrlIes* ies = nullptr;
+    int32_t n_tx = 0, n_rx = 0, K = 0;
+    pcrl::DevBufs bufs;
+    std::vector<pcrl::Gen> gens;    // gens[k] for k = 1..K (gens[0] unused)
+    float4* tx = nullptr;           // TX positions (w = 0)
+    float4* rx = nullptr;
+    pcrl::Rec* rec = nullptr;
+    int64_t n_rec = 0;
+    PcrlConeStats stats{};
+};
+
+namespace pcrl {
+
+// ---------------------------------------------------------------------------
+// device helpers
+// ---------------------------------------------------------------------------
+
+// SplitMix64 (Steele, Lea and Flood, OOPSLA 2014): the output for state x.
+__host__ __device__ __forceinline__ uint64_t splitmix64(uint64_t x) {
+    uint64_t z = x + 0x9E3779B97F4A7C15ull;
+    z = (z ^ (z >> 30)) * 0xBF58476D1CE4E5B9ull;
+    z = (z ^ (z >> 27)) * 0x94D049BB133111EBull;
+    return z ^ (z >> 31);
+}
+
+__device__ __forceinline__ float dot3f(float ax, float ay, float az, float bx, float by, float bz) {
+    return ax * bx + ay * by + az * bz;
+}
+
+// Distance along the unit direction u at which the ray from o enters the box
+// [lo, lo + e]^3 (0 when o is inside); +inf when it misses.
+__device__ __forceinline__ float box_entry(const float o[3], const float u[3], const float lo[3], float e) {
+    float t0 = 0.f, t1 = INFINITY;
+#pragma unroll
+    for (int a = 0; a < 3; ++a) {
+        if (u[a] != 0.f) {
+            float ta = (lo[a] - o[a]) / u[a], tb = (lo[a] + e - o[a]) / u[a];
+            t0 = fmaxf(t0, fminf(ta, tb));
+            t1 = fminf(t1, fmaxf(ta, tb));
+        } else if (o[a] < lo[a] || o[a] > lo[a] + e) {
+            t1 = -1.f;
+        }
+    }
+    return t0 <= t1 ? t0 : INFINITY;
+}
+
+// ---------------------------------------------------------------------------
+// IE table (Section 2.1)
+// ---------------------------------------------------------------------------
+
+__global__ void k_ie_keys(const float4* pos, const float4* nrm, uint32_t n, IeGrid g, uint64_t* key, uint32_t* id,
+                          uint32_t* bad) {
+    const uint32_t i = blockIdx.x * blockDim.x + threadIdx.x;
+    if (i >= n) return;
+    const float4 p = pos[i];
+    const float pc[3] = {p.x, p.y, p.z};
+    int s[3];
+    bool ok = true;
+#pragma unroll
+    for (int a = 0; a < 3; ++a) {
+        const float u = floorf((pc[a] - g.org[a]) * g.inv_sv);
+        ok = ok && u >= 0.f && u < (float)(g.dims[a] * g.dv);
+        s[a] = ok ? (int)u : 0;
+    }
+    if (!ok) atomicAdd(bad, 1u);
+    const int dv = g.dv;
+    const uint64_t vox = (uint64_t)(s[0] / dv) + (uint64_t)g.dims[0] * ((uint64_t)(s[1] / dv) +
+                                                                       (uint64_t)g.dims[1] * (uint64_t)(s[2] / dv));
+    const uint64_t loc = (uint64_t)(s[0] % dv) + (uint64_t)dv * ((uint64_t)(s[1] % dv) + (uint64_t)dv * (s[2] % dv));
+    key[i] = ((vox * (uint64_t)(dv * dv * dv) + loc) << 32) | (uint64_t)__float_as_uint(nrm[i].w);
+    id[i] = i;
+}
+
+__global__ void k_ie_flags(const uint64_t* key, uint32_t n, uint32_t* flag) {
+    const uint32_t i = blockIdx.x * blockDim.x + threadIdx.x;
+    if (i >= n) return;
+    flag[i] = (i == 0 || key[i] != key[i - 1]) ? 1u : 0u;
+}
+
+// Per IE (one thread): its range of sorted points, the means in FP64.
+__global__ void k_ie_reduce(const uint64_t* key, const uint32_t* id, const uint32_t* scan, uint32_t n,
+                            const float4* pos, const float4* nrm, IeGrid g, uint32_t n_ie, uint64_t* ie_key,
+                            int32_t* sub, uint32_t* label, uint32_t* count, float4* ie_pos, float4* ie_nrm) {
+    const uint32_t i = blockIdx.x * blockDim.x + threadIdx.x;
+    if (i >= n) return;
+    if (!(i == 0 || key[i] != key[i - 1])) return;
+    const uint32_t e = scan[i];
+    if (e >= n_ie) return;
+    uint32_t j = i;
+    double px = 0, py = 0, pz = 0, nx = 0, ny = 0, nz = 0;
+    for (; j < n && key[j] == key[i]; ++j) {
+        const float4 p = pos[id[j]];
+        const float4 q = nrm[id[j]];
+        px += p.x; py += p.y; pz += p.z;
+        nx += q.x; ny += q.y; nz += q.z;
+    }
+    const double c = (double)(j - i);
+    const double ln = sqrt(nx * nx + ny * ny + nz * nz);
+    const uint64_t k = key[i];
+    ie_key[e] = k;
+    const int dv = g.dv;
+    const uint64_t cell = k >> 32;
+    const uint64_t vox = cell / (uint64_t)(dv * dv * dv);
+    const int loc = (int)(cell % (uint64_t)(dv * dv * dv));
+    const int vx = (int)(vox % (uint64_t)g.dims[0]);
+    const int vy = (int)((vox / (uint64_t)g.dims[0]) % (uint64_t)g.dims[1]);
+    const int vz = (int)(vox / ((uint64_t)g.dims[0] * (uint64_t)g.dims[1]));
+    sub[3 * (size_t)e] = vx * dv + loc % dv;
+    sub[3 * (size_t)e + 1] = vy * dv + (loc / dv) % dv;
+    sub[3 * (size_t)e + 2] = vz * dv + loc / (dv * dv);
+    label[e] = (uint32_t)(k & 0xFFFFFFFFull);
+    count[e] = j - i;
+    ie_pos[e] = make_float4((float)(px / c), (float)(py / c), (float)(pz / c), 0.f);
+    ie_nrm[e] = ln > 0 ? make_float4((float)(nx / ln), (float)(ny / ln), (float)(nz / ln), 0.f)
+                       : make_float4(0.f, 0.f, 1.f, 0.f);
+}
+
+__global__ void k_ie_voxels(const uint64_t* ie_key, uint32_t n_ie, int dv3, uint2* vox) {
+    const uint32_t e = blockIdx.x * blockDim.x + threadIdx.x;
+    if (e >= n_ie) return;
+    const uint64_t v = (ie_key[e] >> 32) / (uint64_t)dv3;
+    const bool first = e == 0 || ((ie_key[e - 1] >> 32) / (uint64_t)dv3) != v;
+    if (!first) return;
+    uint32_t j = e + 1;
+    while (j < n_ie && ((ie_key[j] >> 32) / (uint64_t)dv3) == v) ++j;
+    vox[v] = make_uint2(e, j - e);
+}
+
+__global__ void k_ie_near(const uint2* vox, IeGrid g, uint32_t n_vox, uint8_t* near) {
+    const uint32_t v = blockIdx.x * blockDim.x + threadIdx.x;
+    if (v >= n_vox) return;
+    const int x = (int)(v % (uint32_t)g.dims[0]);
+    const int y = (int)((v / (uint32_t)g.dims[0]) % (uint32_t)g.dims[1]);
+    const int z = (int)(v / ((uint32_t)g.dims[0] * (uint32_t)g.dims[1]));
+    uint8_t any = 0;
+    for (int dz = -1; dz <= 1; ++dz)
+        for (int dy = -1; dy <= 1; ++dy)
+            for (int dx = -1; dx <= 1; ++dx) {
+                const int a = x + dx, b = y + dy, c = z + dz;
+                if (a < 0 || b < 0 || c < 0 || a >= g.dims[0] || b >= g.dims[1] || c >= g.dims[2]) continue;
+                if (vox[(size_t)a + (size_t)g.dims[0] * ((size_t)b + (size_t)g.dims[1] * c)].y) any = 1;
+            }
+    near[v] = any;
+}
+
+// ---------------------------------------------------------------------------
+// visibility and axis rays (Sections 2.2.2 and 2.2.4)
+// ---------------------------------------------------------------------------
+
+struct VisArgs {
+    TraceArgs t;          // the scene's hierarchy (t.v)
+    IeGrid g;
+    const float4* origin; // per parent: TX (k = 0) or reception point
+    const uint32_t* cand_node;
+    const uint32_t* cand_target;
+    uint32_t n;
+    const float4* ie_pos;
+    const int32_t* ie_sub;
+    const float4* rx;
+    const int32_t* rx_sub;
+    uint32_t* visible;    // per candidate: 1 visible, 0 blocked
+};
+
+// One candidate per lane: a ray from the parent's point towards the target's
+// reception point; blocked when a surfel disk is hit before the ray enters
+// the target's subvoxel (the lane's nearest hit starts at that distance, so
+// only nearer hits register).
+template <int NL, bool BX>
+__global__ __launch_bounds__(TRACE_BLOCK) void k_visibility(VisArgs a) {
+    __shared__ LeafTestLds lds[TRACE_BLOCK / 64];
+    LeafTestLds& W = lds[threadIdx.x >> 6];
+    stat_t cnt[ST_COUNT] = {};
+    const uint32_t wave = blockIdx.x * (TRACE_BLOCK / 64) + (threadIdx.x >> 6);
+    const uint32_t n_waves = gridDim.x * (TRACE_BLOCK / 64);
+    for (uint32_t base = wave * 64; base < a.n; base += n_waves * 64) {
+        const uint32_t i = base + lane_id();
+        const bool act = i < a.n;
+        float o[3] = {0.f, 0.f, 0.f}, u[3] = {1.f, 0.f, 0.f};
+        Hit hit;
+        hit_reset(hit);
+        if (act) {
+            const float4 O = a.origin[a.cand_node[i]];
+            const uint32_t tg = a.cand_target[i];
+            float4 P;
+            int s0, s1, s2;
+            if (tg & RX_BIT) {
+                const uint32_t j = tg & ~RX_BIT;
+                P = a.rx[j];
+                s0 = a.rx_sub[3 * j]; s1 = a.rx_sub[3 * j + 1]; s2 = a.rx_sub[3 * j + 2];
+            } else {
+                P = a.ie_pos[tg];
+                s0 = a.ie_sub[3 * (size_t)tg]; s1 = a.ie_sub[3 * (size_t)tg + 1]; s2 = a.ie_sub[3 * (size_t)tg + 2];
+            }
+            o[0] = O.x; o[1] = O.y; o[2] = O.z;
+            u[0] = P.x - O.x; u[1] = P.y - O.y; u[2] = P.z - O.z;
+            const float len = sqrtf(u[0] * u[0] + u[1] * u[1] + u[2] * u[2]);
+            if (len > 0.f) {
+                const float inv = 1.0f / len;
+                u[0] *= inv; u[1] *= inv; u[2] *= inv;
+                const float lo[3] = {a.g.org[0] + (float)s0 * a.g.sv, a.g.org[1] + (float)s1 * a.g.sv,
+                                     a.g.org[2] + (float)s2 * a.g.sv};
+                hit.t = box_entry(o, u, lo, a.g.sv);
+            } else {
+                u[0] = 1.f; u[1] = 0.f; u[2] = 0.f;
+                hit.t = 0.f;
+            }
+        }
+        stage_ray(W, o, u, NO_HIT);
+        trace_segment<false, NL, false, BX>(a.t, W, act && hit.t > 0.f, o, u, hit, cnt);
+        if (act) a.visible[i] = hit.id == NO_HIT ? 1u : 0u;
+    }
+}
+
+struct AxisArgs {
+    TraceArgs t;
+    Gen gen;
+    const float4* parent_pos;   // previous generation's apex (or the TX)
+    const float4* ie_nrm;
+    float4* axis;               // out: reflected direction (w: unused)
+    float4* plane;              // out: separation plane normal
+};
+
+// The reflected axis of every node and its first surfel hit (t > t_eps): the
+// end of the march.
+template <int NL, bool BX>
+__global__ __launch_bounds__(TRACE_BLOCK) void k_axis(AxisArgs a) {
+    __shared__ LeafTestLds lds[TRACE_BLOCK / 64];
+    LeafTestLds& W = lds[threadIdx.x >> 6];
+    stat_t cnt[ST_COUNT] = {};
+    const uint32_t wave = blockIdx.x * (TRACE_BLOCK / 64) + (threadIdx.x >> 6);
+    const uint32_t n_waves = gridDim.x * (TRACE_BLOCK / 64);
+    const uint32_t n = (uint32_t)a.gen.n;
+    for (uint32_t base = wave * 64; base < n; base += n_waves * 64) {
+        const uint32_t i = base + lane_id();
+        const bool act = i < n;
+        float o[3] = {0.f, 0.f, 0.f}, d[3] = {1.f, 0.f, 0.f};
+        Hit hit;
+        hit_reset(hit);
+        if (act) {
+            const float4 A = a.gen.apex[i];
+            const float4 Pp = a.parent_pos[a.gen.parent[i]];
+            const float4 N = a.ie_nrm[a.gen.ie[i]];
+            float di[3] = {A.x - Pp.x, A.y - Pp.y, A.z - Pp.z};
+            const float li = 1.0f / sqrtf(di[0] * di[0] + di[1] * di[1] + di[2] * di[2]);
+            di[0] *= li; di[1] *= li; di[2] *= li;
+            const float dn = di[0] * N.x + di[1] * N.y + di[2] * N.z;
+            d[0] = di[0] - 2.f * dn * N.x;
+            d[1] = di[1] - 2.f * dn * N.y;
+            d[2] = di[2] - 2.f * dn * N.z;
+            const float lo = 1.0f / sqrtf(d[0] * d[0] + d[1] * d[1] + d[2] * d[2]);
+            d[0] *= lo; d[1] *= lo; d[2] *= lo;
+            o[0] = A.x; o[1] = A.y; o[2] = A.z;
+            const float side = d[0] * N.x + d[1] * N.y + d[2] * N.z > 0.f ? 1.f : -1.f;
+            a.axis[i] = make_float4(d[0], d[1], d[2], 0.f);
+            a.plane[i] = make_float4(side * N.x, side * N.y, side * N.z, 0.f);
+        }
+        stage_ray(W, o, d, NO_HIT);
+        trace_segment<false, NL, false, BX>(a.t, W, act, o, d, hit, cnt);
+        if (act) a.gen.t_end[i] = hit.id == NO_HIT ? INFINITY : hit.t;
+    }
+}
+
+// ---------------------------------------------------------------------------
+// cones (Section 2.2.4)
+// ---------------------------------------------------------------------------
+
+struct ConeArgs {
+    IeGrid g;
+    Gen gen;
+    const float4* axis;
+    const float4* plane;
+    const uint2* vox;
+    const uint8_t* near;
+    const float4* ie_pos;
+    const int32_t* ie_sub;
+    const float4* rx;
+    const int32_t* rx_sub;
+    int32_t n_rx;
+    int32_t want_ie;      // 0 at the last generation: RX targets only
+    float cos_t, sin_t, R;
+    uint32_t cap;
+    uint32_t* n_cand;     // counts every candidate, also beyond cap
+    uint32_t* cand_node;
+    uint32_t* cand_target;
+};
+
+// Whether the cone (apex o, unit axis d, half-angle t) meets the sphere
+// (c, R): distance from c to the solid cone against R.
+__device__ __forceinline__ bool cone_meets(const ConeArgs& a, const float o[3], const float d[3], float cx, float cy,
+                                           float cz) {
+    const float vx = cx - o[0], vy = cy - o[1], vz = cz - o[2];
+    const float ax = vx * d[0] + vy * d[1] + vz * d[2];
+    const float wx = vx - ax * d[0], wy = vy - ax * d[1], wz = vz - ax * d[2];
+    const float rho = sqrtf(wx * wx + wy * wy + wz * wz);
+    const float lateral = rho * a.cos_t - ax * a.sin_t;
+    float dist;
+    if (lateral <= 0.f) dist = 0.f;
+    else if (ax * a.cos_t + rho * a.sin_t < 0.f) dist = sqrtf(vx * vx + vy * vy + vz * vz);
+    else dist = lateral;
+    return dist <= a.R;
+}
+
+__device__ __forceinline__ void cone_emit(const ConeArgs& a, uint32_t node, uint32_t target) {
+    const uint32_t slot = atomicAdd(a.n_cand, 1u);
+    if (slot < a.cap) {
+        a.cand_node[slot] = node;
+        a.cand_target[slot] = target;
+    }
+}
+
+// The targets of voxel w (in the grid) for node i's cone.
+__device__ __forceinline__ void cone_voxel(const ConeArgs& a, uint32_t i, uint32_t own_ie, const float o[3],
+                                           const float d[3], const float n[3], int wx, int wy, int wz) {
+    const IeGrid& g = a.g;
+    if (wx < 0 || wy < 0 || wz < 0 || wx >= g.dims[0] || wy >= g.dims[1] || wz >= g.dims[2]) return;
+    const size_t w = (size_t)wx + (size_t)g.dims[0] * ((size_t)wy + (size_t)g.dims[1] * wz);
+    if (a.want_ie) {
+        const uint2 r = a.vox[w];
+        for (uint32_t e = r.x; e < r.x + r.y; ++e) {
+            if (e == own_ie) continue;
+            const int s0 = a.ie_sub[3 * (size_t)e], s1 = a.ie_sub[3 * (size_t)e + 1], s2 = a.ie_sub[3 * (size_t)e + 2];
+            const float cx = g.org[0] + ((float)s0 + 0.5f) * g.sv;
+            const float cy = g.org[1] + ((float)s1 + 0.5f) * g.sv;
+            const float cz = g.org[2] + ((float)s2 + 0.5f) * g.sv;
+            if (!cone_meets(a, o, d, cx, cy, cz)) continue;
+            const float4 P = a.ie_pos[e];
+            if (!((P.x - o[0]) * n[0] + (P.y - o[1]) * n[1] + (P.z - o[2]) * n[2] > 0.f)) continue;
+            cone_emit(a, i, e);
+        }
+    }
+}
+
+// The RX of voxel w (in the grid) for node i's cone.
+__device__ __forceinline__ void cone_voxel_rx(const ConeArgs& a, uint32_t i, const float o[3], const float d[3],
+                                              const float n[3], int wx, int wy, int wz) {
+    const IeGrid& g = a.g;
+    for (int j = 0; j < a.n_rx; ++j) {
+        const int s0 = a.rx_sub[3 * j], s1 = a.rx_sub[3 * j + 1], s2 = a.rx_sub[3 * j + 2];
+        if (s0 / g.dv != wx || s1 / g.dv != wy || s2 / g.dv != wz) continue;
+        const float cx = g.org[0] + ((float)s0 + 0.5f) * g.sv;
+        const float cy = g.org[1] + ((float)s1 + 0.5f) * g.sv;
+        const float cz = g.org[2] + ((float)s2 + 0.5f) * g.sv;
+        if (!cone_meets(a, o, d, cx, cy, cz)) continue;
+        const float4 P = a.rx[j];
+        if (!((P.x - o[0]) * n[0] + (P.y - o[1]) * n[1] + (P.z - o[2]) * n[2] > 0.f)) continue;
+        cone_emit(a, i, RX_BIT | (uint32_t)j);
+    }
+}
+
+// One node per thread: march the axis voxel by voxel (Amanatides and Woo;
+// every boundary distance computed from the origin, no accumulation) up to
+// the voxel holding t_end; at every voxel the neighbours it adds to the
+// union of 3x3x3 blocks along the march are evaluated (all 27 at the first
+// voxel, then the 9 of the block's leading face along the step's axis).
+// Voxels with no IE within one voxel add nothing and are only crossed.
+__global__ __launch_bounds__(CONE_BLOCK) void k_cones(ConeArgs a) {
+    const uint32_t i = blockIdx.x * blockDim.x + threadIdx.x;
+    if (i >= (uint32_t)a.gen.n) return;
+    const IeGrid& g = a.g;
+    const float4 A = a.gen.apex[i];
+    const float4 D = a.axis[i];
+    const float4 N = a.plane[i];
+    const float o[3] = {A.x, A.y, A.z}, d[3] = {D.x, D.y, D.z}, n[3] = {N.x, N.y, N.z};
+    const uint32_t own = a.gen.ie[i];
+    const float t_end = a.gen.t_end[i];
+    int c[3];
+#pragma unroll
+    for (int k = 0; k < 3; ++k) c[k] = min(max((int)floorf((o[k] - g.org[k]) / g.V), 0), g.dims[k] - 1);
+    int step_axis = -1;
+    for (int it = 0; it < g.dims[0] + g.dims[1] + g.dims[2] + 3; ++it) {
+        const size_t cv = (size_t)c[0] + (size_t)g.dims[0] * ((size_t)c[1] + (size_t)g.dims[1] * c[2]);
+        // IEs only where the block holds some (the march distance); the RX always
+        const bool ies_near = a.want_ie && a.near[cv];
+        if (ies_near || a.n_rx > 0) {
+            if (step_axis < 0) {
+                for (int dz = -1; dz <= 1; ++dz)
+                    for (int dy = -1; dy <= 1; ++dy)
+                        for (int dx = -1; dx <= 1; ++dx) {
+                            if (ies_near) cone_voxel(a, i, own, o, d, n, c[0] + dx, c[1] + dy, c[2] + dz);
+                            cone_voxel_rx(a, i, o, d, n, c[0] + dx, c[1] + dy, c[2] + dz);
+                        }
+            } else {
+                // the block's leading face along the step: the voxels the previous blocks did not hold
+                const int sg = d[step_axis] > 0.f ? 1 : -1;
+                const int a1 = step_axis == 0 ? 1 : 0, a2 = step_axis == 2 ? 1 : 2;
+                for (int p = -1; p <= 1; ++p)
+                    for (int q = -1; q <= 1; ++q) {
+                        int w[3] = {c[0], c[1], c[2]};
+                        w[step_axis] += sg;
+                        w[a1] += p;
+                        w[a2] += q;
+                        if (ies_near) cone_voxel(a, i, own, o, d, n, w[0], w[1], w[2]);
+                        cone_voxel_rx(a, i, o, d, n, w[0], w[1], w[2]);
+                    }
+            }
+        }
+        // next voxel: the nearest boundary along the ray
+        float tn = INFINITY;
+        int ax = -1;
+#pragma unroll
+        for (int k = 0; k < 3; ++k) {
+            if (d[k] == 0.f) continue;
+            const float b = g.org[k] + (float)(d[k] > 0.f ? c[k] + 1 : c[k]) * g.V;
+            const float t = (b - o[k]) / d[k];
+            if (t < tn) {
+                tn = t;
+                ax = k;
+            }
+        }
+        if (ax < 0 || !(tn <= t_end)) break;
+        c[ax] += d[ax] > 0.f ? 1 : -1;
+        if (c[ax] < 0 || c[ax] >= g.dims[ax]) break;
+        step_axis = ax;
+    }
+}
+
+// ---------------------------------------------------------------------------
+// generations: children, merge of similar partial paths, receptions
+// ---------------------------------------------------------------------------
+
+struct SplitArgs {
+    uint32_t n;
+    const uint32_t* cand_node;
+    const uint32_t* cand_target;
+    const uint32_t* visible;
+    uint32_t* child_count;   // [1]
+    uint32_t* child_node;
+    uint32_t* child_ie;
+    uint32_t* rec_count;     // [1]
+    Rec* rec;
+    uint32_t rec_cap;
+    uint32_t k;              // interactions of the parents
+    const float4* parent_pos;
+    const float4* rx;
+};
+
+__global__ void k_split(SplitArgs a) {
+    const uint32_t i = blockIdx.x * blockDim.x + threadIdx.x;
+    const bool v = i < a.n && a.visible[i];
+    const uint32_t tg = v ? a.cand_target[i] : 0u;
+    const bool is_rx = v && (tg & RX_BIT);
+    const bool is_ie = v && !(tg & RX_BIT);
+    const uint32_t cs = wave_append(a.child_count, is_ie ? 1u : 0u);
+    const uint32_t rs = wave_append(a.rec_count, is_rx ? 1u : 0u);
+    if (is_ie) {
+        a.child_node[cs] = a.cand_node[i];
+        a.child_ie[cs] = tg;
+    }
+    if (is_rx && rs < a.rec_cap) {
+        const uint32_t node = a.cand_node[i];
+        const float4 P = a.parent_pos[node];
+        const float4 R = a.rx[tg & ~RX_BIT];
+        const float dx = R.x - P.x, dy = R.y - P.y, dz = R.z - P.z;
+        Rec r;
+        r.node = node;
+        r.rx = tg & ~RX_BIT;
+        r.k = a.k;
+        r.len = P.w + sqrtf(dx * dx + dy * dy + dz * dz);
+        a.rec[rs] = r;
+    }
+}
+
+struct ChildArgs {
+    uint32_t n;
+    const uint32_t* node;        // parent index
+    const uint32_t* ie;
+    const uint32_t* parent_gid;  // the TX index for k = 0
+    const uint64_t* parent_prio;
+    const uint32_t* ie_label;
+    uint64_t* key;               // out: parent gid << 32 | label
+    uint64_t* prio;              // out
+};
+
+__global__ void k_child_keys(ChildArgs a) {
+    const uint32_t i = blockIdx.x * blockDim.x + threadIdx.x;
+    if (i >= a.n) return;
+    const uint32_t p = a.node[i], e = a.ie[i];
+    a.key[i] = ((uint64_t)a.parent_gid[p] << 32) | a.ie_label[e];
+    a.prio[i] = splitmix64(a.parent_prio[p] + (uint64_t)e + 1ull);
+}
+
+template <typename T>
+__global__ void k_gather_by(const T* src, const uint32_t* perm, uint32_t n, T* dst) {
+    const uint32_t i = blockIdx.x * blockDim.x + threadIdx.x;
+    if (i < n) dst[i] = src[perm[i]];
+}
+
+// In sorted order (key, IE, priority, parent): flags of the first child of
+// every (key, IE) group (kept) and of every key group (new label group).
+__global__ void k_merge_flags(const uint64_t* key, const uint32_t* ie, const uint32_t* perm, uint32_t n,
+                              uint32_t* keep, uint32_t* newgroup) {
+    const uint32_t i = blockIdx.x * blockDim.x + threadIdx.x;
+    if (i >= n) return;
+    const uint32_t c = perm[i];
+    bool first_key = i == 0, first_ie = i == 0;
+    if (i > 0) {
+        const uint32_t b = perm[i - 1];
+        first_key = key[b] != key[c];
+        first_ie = first_key || ie[b] != ie[c];
+    }
+    keep[i] = first_ie ? 1u : 0u;
+    newgroup[i] = (first_key && first_ie) ? 1u : 0u;
+}
+
+struct NodeArgs {
+    uint32_t n;
+    const uint32_t* perm;
+    const uint32_t* keep;        // exclusive scan of the keep flags ([n + 1])
+    const uint32_t* group;       // exclusive scan of the new-group flags
+    const uint32_t* newgroup;
+    const uint32_t* node;
+    const uint32_t* ie;
+    const uint64_t* prio;
+    const float4* parent_pos;
+    const uint32_t* parent_tx;   // null for k = 0 (the parent is the TX)
+    const float4* ie_pos;
+    Gen out;
+};
+
+__global__ void k_make_nodes(NodeArgs a) {
+    const uint32_t i = blockIdx.x * blockDim.x + threadIdx.x;
+    if (i >= a.n) return;
+    if (a.keep[i + 1] == a.keep[i]) return;
+    const uint32_t s = a.keep[i];
+    const uint32_t c = a.perm[i];
+    const uint32_t p = a.node[c], e = a.ie[c];
+    const float4 P = a.parent_pos[p];
+    const float4 Q = a.ie_pos[e];
+    const float dx = Q.x - P.x, dy = Q.y - P.y, dz = Q.z - P.z;
+    a.out.apex[s] = make_float4(Q.x, Q.y, Q.z, P.w + sqrtf(dx * dx + dy * dy + dz * dz));
+    a.out.ie[s] = e;
+    a.out.parent[s] = p;
+    a.out.tx[s] = a.parent_tx ? a.parent_tx[p] : p;
+    a.out.gid[s] = a.group[i] + a.newgroup[i] - 1u;
+    a.out.prio[s] = a.prio[c];
+}
+
+// ---------------------------------------------------------------------------
+// host side
+// ---------------------------------------------------------------------------
+
+static unsigned blocks(int64_t n, int b = 256) { return (unsigned)std::max<int64_t>(1, (n + b - 1) / b); }
+
+static int read_u32(uint32_t* dev, uint32_t* host, hipStream_t s) { return read_back(host, dev, 4, s); }
+
+static int grid_of(const PcrlIeGrid* p, IeGrid& g) {
+    if (!p || p->dv < 1 || p->dv > 8 || !(p->voxel > 0.f) || !std::isfinite(p->voxel)) return PCRL_EINVAL;
+    int64_t nv = 1;
+    for (int a = 0; a < 3; ++a) {
+        if (p->dims[a] < 1 || !std::isfinite(p->origin[a])) return PCRL_EINVAL;
+        nv *= p->dims[a];
+    }
+    if (nv * p->dv * p->dv * p->dv >= ((int64_t)1 << 31)) return PCRL_EINVAL;
+    for (int a = 0; a < 3; ++a) {
+        g.org[a] = p->origin[a];
+        g.dims[a] = p->dims[a];
+    }
+    g.V = p->voxel;
+    g.dv = p->dv;
+    g.sv = p->voxel / (float)p->dv;
+    g.inv_sv = 1.0f / g.sv;
+    return PCRL_OK;
+}
+
+static int64_t n_voxels(const IeGrid& g) { return (int64_t)g.dims[0] * g.dims[1] * g.dims[2]; }
+
+static int ie_build_impl(PcrlScene* S, const PcrlIeGrid* params, hipStream_t s, PcrlIes** out) {
+    std::unique_ptr<PcrlIes> I(new PcrlIes());
+    I->scene = S;
+    I->device = S->device;
+    if (grid_of(params, I->g)) {
+        set_error("ie_build: need dv in 1..8, voxel > 0, dims >= 1 and dims product * dv^3 < 2^31");
+        return PCRL_EINVAL;
+    }
+    if (S->overlay && S->overlay->n_entries > 0) {
+        set_error("ie_build: the scene has dynamic points (update_points); IEs are built from the static points");
+        return PCRL_EINVAL;
+    }
+    const int64_t np = S->info.n_points;
+    if (np >= ((int64_t)1 << 31)) {
+        set_error("ie_build: at most 2^31 - 1 points");
+        return PCRL_EINVAL;
+    }
+    I->bufs.stream = s;
+    DevBufs T;
+    T.stream = s;
+    auto fail = [&](int rc) { T.release(); I->bufs.release(); return rc; };
+    const IeGrid g = I->g;
+    I->n_vox = n_voxels(g);
+    int rc;
+    if ((rc = I->bufs.alloc(&I->vox, (size_t)I->n_vox)) || (rc = I->bufs.alloc(&I->near, (size_t)I->n_vox)))
+        return fail(rc);
+    if ((rc = fill_u32((uint32_t*)I->vox, 0u, 2 * I->n_vox, s))) return fail(rc);
+    const uint32_t n = (uint32_t)np;
+    if (n > 0) {
+        if ((rc = scene_own_index(S, s))) return fail(rc);
+        uint64_t* key = nullptr;
+        uint32_t *id = nullptr, *flag = nullptr, *bad = nullptr;
+        if ((rc = T.alloc(&key, n)) || (rc = T.alloc(&id, n)) || (rc = T.alloc(&flag, (size_t)n + 1)) ||
+            (rc = T.alloc(&bad, 1)))
+            return fail(rc);
+        if ((rc = fill_u32(bad, 0u, 1, s))) return fail(rc);
+        hipLaunchKernelGGL(k_ie_keys, dim3(blocks(n)), dim3(256), 0, s, S->own_pos, S->own_nrm, n, g, key, id, bad);
+        uint32_t h_bad = 0;
+        if ((rc = read_u32(bad, &h_bad, s))) return fail(rc);
+        if (h_bad) {
+            set_error("ie_build: %u points lie outside the IE grid", h_bad);
+            return fail(PCRL_EINVAL);
+        }
+        int bits = 1;
+        const uint64_t max_cell = (uint64_t)I->n_vox * (uint64_t)(g.dv * g.dv * g.dv);
+        while (bits < 32 && (max_cell >> bits)) ++bits;
+        if ((rc = radix_sort_u64(key, id, n, 32 + bits, s))) return fail(rc);
+        hipLaunchKernelGGL(k_ie_flags, dim3(blocks(n)), dim3(256), 0, s, key, n, flag);
+        if ((rc = scan_u32(flag, flag, n, flag + n, s))) return fail(rc);
+        uint32_t n_ie = 0;
+        if ((rc = read_u32(flag + n, &n_ie, s))) return fail(rc);
+        I->n_ie = n_ie;
+        if ((rc = I->bufs.alloc(&I->key, n_ie)) || (rc = I->bufs.alloc(&I->sub, (size_t)n_ie * 3)) ||
+            (rc = I->bufs.alloc(&I->label, n_ie)) || (rc = I->bufs.alloc(&I->count, n_ie)) ||
+            (rc = I->bufs.alloc(&I->pos, n_ie)) || (rc = I->bufs.alloc(&I->nrm, n_ie)))
+            return fail(rc);
+        hipLaunchKernelGGL(k_ie_reduce, dim3(blocks(n)), dim3(256), 0, s, key, id, flag, n, S->own_pos, S->own_nrm, g,
+                           n_ie, I->key, I->sub, I->label, I->count, I->pos, I->nrm);
+        hipLaunchKernelGGL(k_ie_voxels, dim3(blocks(n_ie)), dim3(256), 0, s, I->key, n_ie, g.dv * g.dv * g.dv,
+                           I->vox);
+    }
+    hipLaunchKernelGGL(k_ie_near, dim3(blocks(I->n_vox)), dim3(256), 0, s, I->vox, g, (uint32_t)I->n_vox, I->near);
+    if (hipGetLastError() != hipSuccess || hipStreamSynchronize(s) != hipSuccess) {
+        set_error("ie_build: kernels failed: %s", hipGetErrorString(hipGetLastError()));
+        return fail(PCRL_EHIP);
+    }
+    T.release();
+    // occupied voxels (host count from the table)
+    std::vector<uint2> hv((size_t)I->n_vox);
+    if (hipMemcpy(hv.data(), I->vox, hv.size() * sizeof(uint2), hipMemcpyDeviceToHost) != hipSuccess) {
+        set_error("ie_build: reading the voxel table failed");
+        return fail(PCRL_EHIP);
+    }
+    for (const uint2& r : hv) I->n_occ += r.y ? 1 : 0;
+    I->bytes = I->n_ie * (8 + 12 + 4 + 4 + 32) + I->n_vox * 9;
+    *out = I.release();
+    return PCRL_OK;
+}
+
+template <int NL, bool BX>
+static void launch_vis(const VisArgs& a, hipStream_t s) {
+    const unsigned grid = (unsigned)std::min<int64_t>(blocks(a.n, TRACE_BLOCK), (int64_t)device_cus() * 16);
+    hipLaunchKernelGGL((k_visibility<NL, BX>), dim3(grid), dim3(TRACE_BLOCK), 0, s, a);
+}
+
+template <int NL, bool BX>
+static void launch_axis(const AxisArgs& a, hipStream_t s) {
+    const unsigned grid = (unsigned)std::min<int64_t>(blocks(a.gen.n, TRACE_BLOCK), (int64_t)device_cus() * 16);
+    hipLaunchKernelGGL((k_axis<NL, BX>), dim3(grid), dim3(TRACE_BLOCK), 0, s, a);
+}
+
+template <int NL>
+static void dispatch_vis(const VisArgs& a, hipStream_t s) {
+    if (NL > 1 && !a.t.v.cells) launch_vis<NL, true>(a, s);
+    else launch_vis<NL, false>(a, s);
+}
+
+template <int NL>
+static void dispatch_axis(const AxisArgs& a, hipStream_t s) {
+    if (NL > 1 && !a.t.v.cells) launch_axis<NL, true>(a, s);
+    else launch_axis<NL, false>(a, s);
+}
+
+static void run_vis(const VisArgs& a, hipStream_t s) {
+    if (a.n == 0) return;
+    switch (a.t.v.nlev) {
+    case 1: dispatch_vis<1>(a, s); break;
+    case 2: dispatch_vis<2>(a, s); break;
+    case 3: dispatch_vis<3>(a, s); break;
+    default: dispatch_vis<4>(a, s); break;
+    }
+}
+
+static void run_axis(const AxisArgs& a, hipStream_t s) {
+    if (a.gen.n == 0) return;
+    switch (a.t.v.nlev) {
+    case 1: dispatch_axis<1>(a, s); break;
+    case 2: dispatch_axis<2>(a, s); break;
+    case 3: dispatch_axis<3>(a, s); break;
+    default: dispatch_axis<4>(a, s); break;
+    }
+}
+
+__global__ void k_pairs(uint32_t n_tx, uint32_t n_t, uint32_t n_ie, uint32_t* node, uint32_t* target) {
+    const uint64_t i = (uint64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (i >= (uint64_t)n_tx * n_t) return;
+    const uint32_t t = (uint32_t)(i % n_t);
+    node[i] = (uint32_t)(i / n_t);
+    target[i] = t < n_ie ? t : (RX_BIT | (t - n_ie));
+}
+
+__global__ void k_pack_antennas(const float* p, int32_t n, IeGrid g, float4* out, int32_t* sub, uint32_t* bad) {
+    const int32_t i = blockIdx.x * blockDim.x + threadIdx.x;
+    if (i >= n) return;
+    const float c[3] = {p[3 * i], p[3 * i + 1], p[3 * i + 2]};
+    out[i] = make_float4(c[0], c[1], c[2], 0.f);
+    if (!sub) return;
+#pragma unroll
+    for (int a = 0; a < 3; ++a) {
+        const float u = floorf((c[a] - g.org[a]) * g.inv_sv);
+        if (!(u >= 0.f && u < (float)(g.dims[a] * g.dv))) {
+            atomicAdd(bad, 1u);
+            sub[3 * i + a] = 0;
+        } else {
+            sub[3 * i + a] = (int)u;
+        }
+    }
+}
+
+__global__ void k_root_prio(uint32_t n_tx, uint64_t* prio, uint32_t* gid) {
+    const uint32_t i = blockIdx.x * blockDim.x + threadIdx.x;
+    if (i >= n_tx) return;
+    prio[i] = splitmix64(i);
+    gid[i] = i;
+}
+
+// Children of the visible IE candidates -> merged, sorted generation.
+static int make_generation(PcrlConeLaunch* L, uint32_t n_child, const uint32_t* child_node, const uint32_t* child_ie,
+                           const uint32_t* parent_gid, const uint64_t* parent_prio, const float4* parent_pos,
+                           const uint32_t* parent_tx, Gen& out, hipStream_t s) {
+    const PcrlIes* I = L->ies;
+    DevBufs T;
+    T.stream = s;
+    auto fail = [&](int rc) { T.release(); return rc; };
+    out.n = 0;
+    if (n_child == 0) return PCRL_OK;
+    const uint32_t n = n_child;
+    uint64_t *key = nullptr, *prio = nullptr, *tmp64 = nullptr;
+    uint32_t *perm = nullptr, *tmp32 = nullptr, *keep = nullptr, *grp = nullptr, *newg = nullptr;
+    int rc;
+    if ((rc = T.alloc(&key, n)) || (rc = T.alloc(&prio, n)) || (rc = T.alloc(&tmp64, n)) || (rc = T.alloc(&perm, n)) ||
+        (rc = T.alloc(&tmp32, n)) || (rc = T.alloc(&keep, (size_t)n + 1)) || (rc = T.alloc(&grp, (size_t)n + 1)) ||
+        (rc = T.alloc(&newg, n)))
+        return fail(rc);
+    ChildArgs ca{n, child_node, child_ie, parent_gid, parent_prio, I->label, key, prio};
+    hipLaunchKernelGGL(k_child_keys, dim3(blocks(n)), dim3(256), 0, s, ca);
+    if ((rc = iota_u32(perm, n, s))) return fail(rc);
+    // LSD by parent, priority, IE, key: sorted by (key, IE, priority, parent)
+    hipLaunchKernelGGL(k_gather_by<uint32_t>, dim3(blocks(n)), dim3(256), 0, s, child_node, perm, n, tmp32);
+    if ((rc = radix_sort_u32(tmp32, perm, n, 32, s))) return fail(rc);
+    hipLaunchKernelGGL(k_gather_by<uint64_t>, dim3(blocks(n)), dim3(256), 0, s, prio, perm, n, tmp64);
+    if ((rc = radix_sort_u64(tmp64, perm, n, 64, s))) return fail(rc);
+    hipLaunchKernelGGL(k_gather_by<uint32_t>, dim3(blocks(n)), dim3(256), 0, s, child_ie, perm, n, tmp32);
+    if ((rc = radix_sort_u32(tmp32, perm, n, 32, s))) return fail(rc);
+    hipLaunchKernelGGL(k_gather_by<uint64_t>, dim3(blocks(n)), dim3(256), 0, s, key, perm, n, tmp64);
+    if ((rc = radix_sort_u64(tmp64, perm, n, 64, s))) return fail(rc);
+    hipLaunchKernelGGL(k_merge_flags, dim3(blocks(n)), dim3(256), 0, s, key, child_ie, perm, n, keep, newg);
+    if ((rc = scan_u32(keep, keep, n, keep + n, s))) return fail(rc);
+    if ((rc = scan_u32(newg, grp, n, grp + n, s))) return fail(rc);
+    uint32_t n_keep = 0;
+    if ((rc = read_u32(keep + n, &n_keep, s))) return fail(rc);
+    DevBufs& B = L->bufs;
+    if ((rc = B.alloc(&out.apex, n_keep)) || (rc = B.alloc(&out.ie, n_keep)) || (rc = B.alloc(&out.parent, n_keep)) ||
+        (rc = B.alloc(&out.tx, n_keep)) || (rc = B.alloc(&out.gid, n_keep)) || (rc = B.alloc(&out.prio, n_keep)) ||
+        (rc = B.alloc(&out.t_end, n_keep)))
+        return fail(rc);
+    out.n = n_keep;
+    NodeArgs na{n, perm, keep, grp, newg, child_node, child_ie, prio, parent_pos, parent_tx, I->pos, out};
+    hipLaunchKernelGGL(k_make_nodes, dim3(blocks(n)), dim3(256), 0, s, na);
+    if (hipGetLastError() != hipSuccess) {
+        set_error("cone_launch: merge kernels failed");
+        return fail(PCRL_EHIP);
+    }
+    T.release();
+    return PCRL_OK;
+}
+
+static double now_ms() {
+    return std::chrono::duration<double, std::milli>(std::chrono::steady_clock::now().time_since_epoch()).count();
+}
+
+static int cone_launch_impl(const PcrlIes* I, const float* tx, int32_t n_tx, const float* rx, int32_t n_rx,
+                            const PcrlConeParams* P, hipStream_t s, PcrlConeLaunch** out) {
+    const PcrlScene* S = I->scene;
+    std::unique_ptr<PcrlConeLaunch> L(new PcrlConeLaunch());
+    L->ies = I;
+    L->n_tx = n_tx;
+    L->n_rx = n_rx;
+    L->K = P->max_interactions;
+    L->bufs.stream = s;
+    const int K = L->K;
+    const float half = P->half_angle > 0.f ? P->half_angle : (float)(2.5 * M_PI / 180.0);
+    DevBufs T;
+    T.stream = s;
+    auto fail = [&](int rc) { T.release(); L->bufs.release(); return rc; };
+    int rc;
+    int32_t* rx_sub = nullptr;
+    uint32_t *bad = nullptr, *counters = nullptr;
+    uint64_t* root_prio = nullptr;
+    uint32_t* root_gid = nullptr;
+    if ((rc = L->bufs.alloc(&L->tx, n_tx)) || (rc = L->bufs.alloc(&L->rx, std::max(n_rx, 1))) ||
+        (rc = T.alloc(&rx_sub, (size_t)std::max(n_rx, 1) * 3)) || (rc = T.alloc(&bad, 1)) ||
+        (rc = T.alloc(&counters, 4)) || (rc = T.alloc(&root_prio, n_tx)) || (rc = T.alloc(&root_gid, n_tx)))
+        return fail(rc);
+    if ((rc = fill_u32(bad, 0u, 1, s))) return fail(rc);
+    hipLaunchKernelGGL(k_pack_antennas, dim3(blocks(n_tx)), dim3(256), 0, s, tx, n_tx, I->g, L->tx, (int32_t*)nullptr,
+                       bad);
+    if (n_rx > 0)
+        hipLaunchKernelGGL(k_pack_antennas, dim3(blocks(n_rx)), dim3(256), 0, s, rx, n_rx, I->g, L->rx, rx_sub, bad);
+    hipLaunchKernelGGL(k_root_prio, dim3(blocks(n_tx)), dim3(256), 0, s, (uint32_t)n_tx, root_prio, root_gid);
+    uint32_t h_bad = 0;
+    if ((rc = read_u32(bad, &h_bad, s))) return fail(rc);
+    if (h_bad) {
+        set_error("cone_launch: an RX lies outside the IE grid");
+        return fail(PCRL_EINVAL);
+    }
+    TraceArgs ta{};
+    ta.v = S->view;
+    VisArgs va{};
+    va.t = ta;
+    va.g = I->g;
+    va.ie_pos = I->pos;
+    va.ie_sub = I->sub;
+    va.rx = L->rx;
+    va.rx_sub = rx_sub;
+    L->gens.assign((size_t)K + 2, Gen{});
+    std::vector<Rec> recs;
+    auto add_records = [&](uint32_t n_rec, Rec* dev) -> int {
+        const size_t at = recs.size();
+        recs.resize(at + n_rec);
+        if (n_rec && hipMemcpy(recs.data() + at, dev, (size_t)n_rec * sizeof(Rec), hipMemcpyDeviceToHost) != hipSuccess)
+            return PCRL_EHIP;
+        return PCRL_OK;
+    };
+    const double t0 = now_ms();
+    // ---- transmission phase: every TX towards every IE and RX
+    const uint64_t n_t = (uint64_t)I->n_ie + (uint64_t)n_rx;
+    const uint64_t n_pairs = (uint64_t)n_tx * n_t;
+    if (n_pairs >= ((uint64_t)1 << 31)) {
+        set_error("cone_launch: %llu transmission rays exceed 2^31", (unsigned long long)n_pairs);
+        return fail(PCRL_EINVAL);
+    }
+    uint32_t n_child = 0;
+    uint32_t *child_node = nullptr, *child_ie = nullptr;
+    {
+        const uint32_t n = (uint32_t)n_pairs;
+        uint32_t *node = nullptr, *target = nullptr, *vis = nullptr;
+        Rec* rec = nullptr;
+        if ((rc = T.alloc(&node, std::max(n, 1u))) || (rc = T.alloc(&target, std::max(n, 1u))) ||
+            (rc = T.alloc(&vis, std::max(n, 1u))) || (rc = T.alloc(&child_node, std::max(n, 1u))) ||
+            (rc = T.alloc(&child_ie, std::max(n, 1u))) || (rc = T.alloc(&rec, std::max<uint32_t>(n_tx * n_rx, 1u))))
+            return fail(rc);
+        if (n) hipLaunchKernelGGL(k_pairs, dim3(blocks(n)), dim3(256), 0, s, (uint32_t)n_tx, (uint32_t)n_t,
+                                  (uint32_t)I->n_ie, node, target);
+        va.origin = L->tx;
+        va.cand_node = node;
+        va.cand_target = target;
+        va.n = n;
+        va.visible = vis;
+        run_vis(va, s);
+        if ((rc = fill_u32(counters, 0u, 4, s))) return fail(rc);
+        SplitArgs sa{n, node, target, vis, counters, child_node, child_ie, counters + 1, rec,
+                     (uint32_t)std::max(n_tx * n_rx, 1), 0u, L->tx, L->rx};
+        if (n) hipLaunchKernelGGL(k_split, dim3(blocks(n)), dim3(256), 0, s, sa);
+        uint32_t h[2] = {0, 0};
+        if (hipGetLastError() != hipSuccess || read_back(h, counters, 8, s)) {
+            set_error("cone_launch: transmission kernels failed: %s", hipGetErrorString(hipGetLastError()));
+            return fail(PCRL_EHIP);
+        }
+        n_child = h[0];
+        if ((rc = add_records(h[1], rec))) return fail(rc);
+        L->stats.candidates[0] = n;
+        L->stats.visible[0] = (int64_t)h[0] + h[1];
+    }
+    L->stats.ms_transmission = now_ms() - t0;
+    const double t1 = now_ms();
+    // ---- propagation: generations 1..K
+    const uint32_t* p_gid = root_gid;
+    const uint64_t* p_prio = root_prio;
+    const float4* p_pos = L->tx;
+    const uint32_t* p_tx = nullptr;
+    const float cos_t = cosf(half), sin_t = sinf(half);
+    const float R = I->g.sv * sqrtf(3.0f) * 0.5f;
+    for (int k = 1; k <= K; ++k) {
+        Gen& G = L->gens[k];
+        if ((rc = make_generation(L.get(), n_child, child_node, child_ie, p_gid, p_prio, p_pos, p_tx, G, s)))
+            return fail(rc);
+        L->stats.nodes[k] = G.n;
+        if (G.n == 0) break;
+        float4 *axis = nullptr, *plane = nullptr;
+        if ((rc = T.alloc(&axis, G.n)) || (rc = T.alloc(&plane, G.n))) return fail(rc);
+        AxisArgs aa{ta, G, p_pos, I->nrm, axis, plane};
+        run_axis(aa, s);
+        // candidates: a first guess, then exactly what the kernel counted
+        uint32_t cap = (uint32_t)std::min<int64_t>((int64_t)G.n * 64 + 1024, (int64_t)1 << 30);
+        uint32_t *cnode = nullptr, *ctarget = nullptr;
+        uint32_t n_cand = 0;
+        for (int attempt = 0; attempt < 2; ++attempt) {
+            if ((rc = T.alloc(&cnode, cap)) || (rc = T.alloc(&ctarget, cap))) return fail(rc);
+            if ((rc = fill_u32(counters, 0u, 4, s))) return fail(rc);
+            ConeArgs c{};
+            c.g = I->g;
+            c.gen = G;
+            c.axis = axis;
+            c.plane = plane;
+            c.vox = I->vox;
+            c.near = I->near;
+            c.ie_pos = I->pos;
+            c.ie_sub = I->sub;
+            c.rx = L->rx;
+            c.rx_sub = rx_sub;
+            c.n_rx = n_rx;
+            c.want_ie = k < K ? 1 : 0;
+            c.cos_t = cos_t;
+            c.sin_t = sin_t;
+            c.R = R;
+            c.cap = cap;
+            c.n_cand = counters;
+            c.cand_node = cnode;
+            c.cand_target = ctarget;
+            hipLaunchKernelGGL(k_cones, dim3(blocks(G.n, CONE_BLOCK)), dim3(CONE_BLOCK), 0, s, c);
+            if (hipGetLastError() != hipSuccess || read_u32(counters, &n_cand, s)) {
+                set_error("cone_launch: cone kernel failed: %s", hipGetErrorString(hipGetLastError()));
+                return fail(PCRL_EHIP);
+            }
+            if (n_cand <= cap) break;
+            if (n_cand >= ((uint32_t)1 << 30)) {
+                set_error("cone_launch: %u cone targets in generation %d exceed 2^30", n_cand, k);
+                return fail(PCRL_EINVAL);
+            }
+            cap = n_cand;
+        }
+        L->stats.candidates[k] = n_cand;
+        uint32_t* vis = nullptr;
+        Rec* rec = nullptr;
+        uint32_t* nchild_node = nullptr;
+        uint32_t* nchild_ie = nullptr;
+        if ((rc = T.alloc(&vis, std::max(n_cand, 1u))) || (rc = T.alloc(&rec, std::max(n_cand, 1u))) ||
+            (rc = T.alloc(&nchild_node, std::max(n_cand, 1u))) || (rc = T.alloc(&nchild_ie, std::max(n_cand, 1u))))
+            return fail(rc);
+        va.origin = G.apex;
+        va.cand_node = cnode;
+        va.cand_target = ctarget;
+        va.n = n_cand;
+        va.visible = vis;
+        run_vis(va, s);
+        if ((rc = fill_u32(counters, 0u, 4, s))) return fail(rc);
+        SplitArgs sa{n_cand, cnode, ctarget, vis, counters, nchild_node, nchild_ie, counters + 1, rec,
+                     std::max(n_cand, 1u), (uint32_t)k, G.apex, L->rx};
+        if (n_cand) hipLaunchKernelGGL(k_split, dim3(blocks(n_cand)), dim3(256), 0, s, sa);
+        uint32_t h[2] = {0, 0};
+        if (hipGetLastError() != hipSuccess || read_back(h, counters, 8, s)) {
+            set_error("cone_launch: generation %d kernels failed: %s", k, hipGetErrorString(hipGetLastError()));
+            return fail(PCRL_EHIP);
+        }
+        if ((rc = add_records(h[1], rec))) return fail(rc);
+        L->stats.visible[k] = (int64_t)h[0] + h[1];
+        n_child = k < K ? h[0] : 0u;
+        child_node = nchild_node;
+        child_ie = nchild_ie;
+        p_gid = G.gid;
+        p_prio = G.prio;
+        p_pos = G.apex;
+        p_tx = G.tx;
+    }
+    L->stats.ms_propagation = now_ms() - t1;
+    L->n_rec = (int64_t)recs.size();
+    L->stats.records = L->n_rec;
+    if ((rc = L->bufs.alloc(&L->rec, std::max<size_t>(recs.size(), 1)))) return fail(rc);
+    if (!recs.empty() && hipMemcpy(L->rec, recs.data(), recs.size() * sizeof(Rec), hipMemcpyHostToDevice) != hipSuccess) {
+        set_error("cone_launch: storing the receptions failed");
+        return fail(PCRL_EHIP);
+    }
+    if (hipStreamSynchronize(s) != hipSuccess) {
+        set_error("cone_launch: kernels failed: %s", hipGetErrorString(hipGetLastError()));
+        return fail(PCRL_EHIP);
+    }
+    T.release();
+    *out = L.release();
+    return PCRL_OK;
+}
+
+// ---------------------------------------------------------------------------
+// collect: coarse paths (Section 2.2.3)
+// ---------------------------------------------------------------------------
+
+struct CollectView {
+    Gen gens[PCRL_MAX_REFLECTIONS + 1];
+    const float4* tx;
+    const uint32_t* ie_label;
+    const float4* ie_pos;
+};
+
+// Sort key of a reception: (tx, rx, k, label group of its node).
+__global__ void k_rec_keys(const Rec* rec, uint32_t n, CollectView cv, uint64_t* key, uint64_t* prio,
+                           uint32_t* nodeord) {
+    const uint32_t i = blockIdx.x * blockDim.x + threadIdx.x;
+    if (i >= n) return;
+    const Rec r = rec[i];
+    uint32_t tx = r.node, gid = 0;
+    uint64_t pr = splitmix64(r.node);
+    if (r.k > 0) {
+        const Gen& G = cv.gens[r.k];
+        tx = G.tx[r.node];
+        gid = G.gid[r.node];
+        pr = G.prio[r.node];
+    }
+    key[i] = ((uint64_t)tx << 56) | ((uint64_t)r.rx << 40) | ((uint64_t)r.k << 36) | (uint64_t)gid;
+    prio[i] = pr;
+    nodeord[i] = r.node;
+}
+
+__global__ void k_rec_groups(const uint64_t* key, const uint32_t* perm, uint32_t n, uint32_t* first) {
+    const uint32_t i = blockIdx.x * blockDim.x + threadIdx.x;
+    if (i >= n) return;
+    first[i] = (i == 0 || key[perm[i]] != key[perm[i - 1]]) ? 1u : 0u;
+}
+
+struct RowArgs {
+    const Rec* rec;
+    const uint64_t* key;
+    const uint32_t* perm;
+    const uint32_t* first;   // group start flags (sorted order)
+    uint32_t n;
+    int32_t kappa;
+    int32_t K;
+    CollectView cv;
+    uint32_t* n_rows;        // [2]: rows, keys
+    int64_t cap;
+    PcrlPaths out;
+};
+
+// Rows in sorted order: row slot = exclusive scan of kept counts.
+__global__ void k_rec_keepflags(const uint32_t* first, uint32_t n, int32_t kappa, uint32_t* keep) {
+    const uint32_t i = blockIdx.x * blockDim.x + threadIdx.x;
+    if (i >= n) return;
+    // rank inside the group: distance to the group start
+    uint32_t g = i;
+    while (!first[g]) --g;
+    keep[i] = (kappa <= 0 || i - g < (uint32_t)kappa) ? 1u : 0u;
+}
+
+__global__ void k_rec_write(RowArgs a, const uint32_t* slot) {
+    const uint32_t i = blockIdx.x * blockDim.x + threadIdx.x;
+    if (i >= a.n) return;
+    if (slot[i + 1] == slot[i]) return;
+    const uint32_t row = slot[i];
+    if ((int64_t)row >= a.cap) return;
+    uint32_t g = i;
+    while (!a.first[g]) --g;
+    uint32_t j = i + 1;
+    while (j < a.n && !a.first[j]) ++j;
+    const Rec r = a.rec[a.perm[i]];
+    const int K = a.K;
+    uint32_t tx = r.node;
+    if (r.k > 0) tx = a.cv.gens[r.k].tx[r.node];
+    if (a.out.tx) a.out.tx[row] = (int32_t)tx;
+    if (a.out.rx) a.out.rx[row] = (int32_t)r.rx;
+    if (a.out.n_refl) a.out.n_refl[row] = (int32_t)r.k;
+    if (a.out.count) a.out.count[row] = (int64_t)(j - g);
+    if (a.out.rank) a.out.rank[row] = (int32_t)(i - g);
+    if (a.out.ray) a.out.ray[row] = ((int64_t)r.k << 40) | (int64_t)r.node;
+    if (a.out.len_poly) a.out.len_poly[row] = r.len;
+    if (a.out.len_unf) a.out.len_unf[row] = r.len;
+    for (int q = 0; q < K; ++q) {
+        if (a.out.key) a.out.key[(size_t)row * K + q] = -1;
+        if (a.out.points)
+            for (int c = 0; c < 3; ++c) a.out.points[((size_t)row * K + q) * 3 + c] = NAN;
+    }
+    uint32_t node = r.node;
+    for (int q = (int)r.k; q >= 1; --q) {
+        const Gen& G = a.cv.gens[q];
+        const uint32_t e = G.ie[node];
+        if (a.out.key) a.out.key[(size_t)row * K + (q - 1)] = (int64_t)a.cv.ie_label[e];
+        if (a.out.points) {
+            const float4 P = a.cv.ie_pos[e];
+            a.out.points[((size_t)row * K + (q - 1)) * 3] = P.x;
+            a.out.points[((size_t)row * K + (q - 1)) * 3 + 1] = P.y;
+            a.out.points[((size_t)row * K + (q - 1)) * 3 + 2] = P.z;
+        }
+        node = G.parent[node];
+    }
+}
+
+static int cone_collect_impl(PcrlConeLaunch* L, int32_t kappa, PcrlPaths* out, hipStream_t s) {
+    out->n_rows = 0;
+    out->n_keys = 0;
+    const uint32_t n = (uint32_t)L->n_rec;
+    if (n == 0) return PCRL_OK;
+    DevBufs T;
+    T.stream = s;
+    auto fail = [&](int rc) { T.release(); return rc; };
+    uint64_t *key = nullptr, *prio = nullptr, *tmp64 = nullptr;
+    uint32_t *perm = nullptr, *ord = nullptr, *tmp32 = nullptr, *first = nullptr, *slot = nullptr, *cnt = nullptr;
+    int rc;
+    if ((rc = T.alloc(&key, n)) || (rc = T.alloc(&prio, n)) || (rc = T.alloc(&tmp64, n)) || (rc = T.alloc(&perm, n)) ||
+        (rc = T.alloc(&ord, n)) || (rc = T.alloc(&tmp32, n)) || (rc = T.alloc(&first, n)) ||
+        (rc = T.alloc(&slot, (size_t)n + 1)) || (rc = T.alloc(&cnt, 2)))
+        return fail(rc);
+    CollectView cv{};
+    for (int k = 1; k <= L->K && k <= PCRL_MAX_REFLECTIONS; ++k) cv.gens[k] = L->gens[k];
+    cv.tx = L->tx;
+    cv.ie_label = L->ies->label;
+    cv.ie_pos = L->ies->pos;
+    hipLaunchKernelGGL(k_rec_keys, dim3(blocks(n)), dim3(256), 0, s, L->rec, n, cv, key, prio, ord);
+    if ((rc = iota_u32(perm, n, s))) return fail(rc);
+    // LSD: node index, priority, key -> sorted by (key, priority, node)
+    hipLaunchKernelGGL(k_gather_by<uint32_t>, dim3(blocks(n)), dim3(256), 0, s, ord, perm, n, tmp32);
+    if ((rc = radix_sort_u32(tmp32, perm, n, 32, s))) return fail(rc);
+    hipLaunchKernelGGL(k_gather_by<uint64_t>, dim3(blocks(n)), dim3(256), 0, s, prio, perm, n, tmp64);
+    if ((rc = radix_sort_u64(tmp64, perm, n, 64, s))) return fail(rc);
+    hipLaunchKernelGGL(k_gather_by<uint64_t>, dim3(blocks(n)), dim3(256), 0, s, key, perm, n, tmp64);
+    if ((rc = radix_sort_u64(tmp64, perm, n, 64, s))) return fail(rc);
+    hipLaunchKernelGGL(k_rec_groups, dim3(blocks(n)), dim3(256), 0, s, key, perm, n, first);
+    hipLaunchKernelGGL(k_rec_keepflags, dim3(blocks(n)), dim3(256), 0, s, first, n, kappa, slot);
+    if ((rc = scan_u32(slot, slot, n, slot + n, s))) return fail(rc);
+    if ((rc = scan_u32(first, tmp32, n, cnt + 1, s))) return fail(rc);
+    uint32_t rows = 0, keys = 0;
+    if ((rc = read_u32(slot + n, &rows, s)) || (rc = read_u32(cnt + 1, &keys, s))) return fail(rc);
+    out->n_keys = keys;
+    if ((int64_t)rows > out->capacity) {
+        out->n_rows = rows;
+        set_error("cone_collect: %u rows do not fit in capacity %lld", rows, (long long)out->capacity);
+        return fail(PCRL_EOVERFLOW);
+    }
+    RowArgs ra{L->rec, key, perm, first, n, kappa, L->K, cv, cnt, out->capacity, *out};
+    hipLaunchKernelGGL(k_rec_write, dim3(blocks(n)), dim3(256), 0, s, ra, slot);
+    if (hipGetLastError() != hipSuccess || hipStreamSynchronize(s) != hipSuccess) {
+        set_error("cone_collect: kernels failed: %s", hipGetErrorString(hipGetLastError()));
+        return fail(PCRL_EHIP);
+    }
+    out->n_rows = rows;
+    T.release();
+    return PCRL_OK;
+}
+
+}  // namespace pcrl
+
+using namespace pcrl;
+
+extern "C" int ie_build(PcrlScene* scene, const PcrlIeGrid* grid, pcrl_stream_t stream, PcrlIes** out) {
+    clear_error();
+    if (!scene || !grid || !out) {
+        set_error("ie_build: scene, grid and out must be given");
+        return PCRL_EINVAL;
+    }
+    return ie_build_impl(scene, grid, (hipStream_t)stream, out);
+}
+
+extern "C" int ie_info(const PcrlIes* ies, PcrlIeInfo* out) {
+    clear_error();
+    if (!ies || !out) {
+        set_error("ie_info: NULL argument");
+        return PCRL_EINVAL;
+    }
+    out->n_ies = ies->n_ie;
+    out->n_voxels = ies->n_vox;
+    out->n_occupied = ies->n_occ;
+    out->device_bytes = ies->bytes;
+    return PCRL_OK;
+}
+
+extern "C" int ie_table(const PcrlIes* ies, uint64_t* key, int32_t* sub, uint32_t* label, uint32_t* count, float* pos,
+                        float* nrm, pcrl_stream_t stream) {
+    clear_error();
+    if (!ies) {
+        set_error("ie_table: NULL IE table");
+        return PCRL_EINVAL;
+    }
+    hipStream_t s = (hipStream_t)stream;
+    const size_t n = (size_t)ies->n_ie;
+    if (n == 0) return PCRL_OK;
+    hipError_t e = hipSuccess;
+    if (key && e == hipSuccess) e = hipMemcpyAsync(key, ies->key, n * 8, hipMemcpyDeviceToDevice, s);
+    if (sub && e == hipSuccess) e = hipMemcpyAsync(sub, ies->sub, n * 12, hipMemcpyDeviceToDevice, s);
+    if (label && e == hipSuccess) e = hipMemcpyAsync(label, ies->label, n * 4, hipMemcpyDeviceToDevice, s);
+    if (count && e == hipSuccess) e = hipMemcpyAsync(count, ies->count, n * 4, hipMemcpyDeviceToDevice, s);
+    if (pos && e == hipSuccess) e = hipMemcpy2DAsync(pos, 12, ies->pos, 16, 12, n, hipMemcpyDeviceToDevice, s);
+    if (nrm && e == hipSuccess) e = hipMemcpy2DAsync(nrm, 12, ies->nrm, 16, 12, n, hipMemcpyDeviceToDevice, s);
+    if (e != hipSuccess) {
+        set_error("ie_table: copy failed: %s", hipGetErrorString(e));
+        return PCRL_EHIP;
+    }
+    return PCRL_OK;
+}
+
+extern "C" int release_ies(PcrlIes* ies) {
+    clear_error();
+    if (!ies) return PCRL_OK;
+    ies->bufs.release();
+    delete ies;
+    return PCRL_OK;
+}
+
+extern "C" int cone_launch(const PcrlIes* ies, const float* tx, int32_t n_tx, const float* rx, int32_t n_rx,
+                           const PcrlConeParams* params, pcrl_stream_t stream, PcrlConeLaunch** out) {
+    clear_error();
+    if (!ies || !params || !out || !tx || n_tx < 1 || n_tx > 255 || n_rx < 0 || n_rx > 65535 || (n_rx > 0 && !rx) ||
+        params->max_interactions < 0 || params->max_interactions > PCRL_MAX_REFLECTIONS ||
+        !(params->half_angle <= (float)(M_PI / 4)) || params->flags != 0) {
+        set_error("cone_launch: need IEs, 1 <= n_tx <= 255 TX, 0 <= n_rx <= 65535 RX, 0 <= max_interactions <= %d, "
+                  "half_angle <= pi/4 and flags 0", PCRL_MAX_REFLECTIONS);
+        return PCRL_EINVAL;
+    }
+    if (ies->scene->overlay && ies->scene->overlay->n_entries > 0) {
+        set_error("cone_launch: the scene has dynamic points (update_points)");
+        return PCRL_EINVAL;
+    }
+    return cone_launch_impl(ies, tx, n_tx, rx, n_rx, params, (hipStream_t)stream, out);
+}
+
+extern "C" int cone_stats(const PcrlConeLaunch* launch, PcrlConeStats* out) {
+    clear_error();
+    if (!launch || !out) {
+        set_error("cone_stats: NULL argument");
+        return PCRL_EINVAL;
+    }
+    *out = launch->stats;
+    return PCRL_OK;
+}
+
+extern "C" int cone_nodes(const PcrlConeLaunch* L, int32_t k, int32_t* ie, int32_t* parent, int32_t* tx,
+                          uint64_t* prio, float* length, pcrl_stream_t stream) {
+    clear_error();
+    if (!L || k < 1 || k > L->K) {
+        set_error("cone_nodes: need 1 <= k <= max_interactions");
+        return PCRL_EINVAL;
+    }
+    const Gen& G = L->gens[k];
+    const size_t n = (size_t)G.n;
+    if (n == 0) return PCRL_OK;
+    hipStream_t s = (hipStream_t)stream;
+    hipError_t e = hipSuccess;
+    if (ie && e == hipSuccess) e = hipMemcpyAsync(ie, G.ie, n * 4, hipMemcpyDeviceToDevice, s);
+    if (parent && e == hipSuccess) e = hipMemcpyAsync(parent, G.parent, n * 4, hipMemcpyDeviceToDevice, s);
+    if (tx && e == hipSuccess) e = hipMemcpyAsync(tx, G.tx, n * 4, hipMemcpyDeviceToDevice, s);
+    if (prio && e == hipSuccess) e = hipMemcpyAsync(prio, G.prio, n * 8, hipMemcpyDeviceToDevice, s);
+    if (length && e == hipSuccess)
+        e = hipMemcpy2DAsync(length, 4, (const char*)G.apex + 12, 16, 4, n, hipMemcpyDeviceToDevice, s);
+    if (e != hipSuccess) {
+        set_error("cone_nodes: copy failed: %s", hipGetErrorString(e));
+        return PCRL_EHIP;
+    }
+    return PCRL_OK;
+}
+
+extern "C" int cone_collect(PcrlConeLaunch* launch, int32_t kappa, PcrlPaths* out, pcrl_stream_t stream) {
+    clear_error();
+    if (!launch || !out || kappa < 1 || out->capacity < 0) {
+        set_error("cone_collect: need a launch, kappa >= 1 and capacity >= 0");
+        return PCRL_EINVAL;
+    }
+    return cone_collect_impl(launch, kappa, out, (hipStream_t)stream);
+}
+
+extern "C" int release_cone(PcrlConeLaunch* launch) {
+    clear_error();
+    if (!launch) return PCRL_OK;
+    launch->bufs.release();
+    delete launch;
+    return PCRL_OK;
+}

@@ -330,4 +330,7 @@ struct TraceArgs;
 int launch_prepare(const PcrlScene* scene, const float* tx, int32_t n_tx, const float* rx, int32_t n_rx,
                    const PcrlLaunchParams* p, hipStream_t s, bool timing_events, PcrlLaunch** out, TraceArgs* args);
 void destroy_launch(PcrlLaunch* L);
+// Every static point once, in the leaf that holds its centre (built on first
+// use and kept with the scene; sdf.hip): scene->own_pos / own_nrm.
+int scene_own_index(PcrlScene* S, hipStream_t s);
 }

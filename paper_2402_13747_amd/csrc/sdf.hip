@@ -656,6 +656,8 @@ static int own_index(PcrlScene* S, hipStream_t s) {
     return PCRL_OK;
 }
 
+int scene_own_index(PcrlScene* S, hipStream_t s) { return own_index(S, s); }
+
 // Defaults of the implicit surface for a scene (h, eps, max_steps as
 // sdf_intersect's when its parameters are not given).
 static void sdf_defaults(const PcrlScene* scene, SdfArgs& a) {
