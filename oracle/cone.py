@@ -137,6 +137,112 @@ def subvoxel_box(sub, origin, voxel, dv):
     return lo, lo + sv
 
 
+def edge_ies(seg, normals, labels, origin, voxel, dv, dims):
+    """Diffraction IEs of caller-given convex edges (Section 2.1: a subvoxel may
+    hold diffraction edge segments): every edge a -> b is cut at the subvoxel
+    faces it crosses; each piece is one IE in the subvoxel of its midpoint,
+    reception point = the midpoint, with the edge's label, unit direction and
+    the outward normals of its two faces.  The cut parameters, midpoints and
+    cells are computed in FP32 (t = ((origin + k sv) - a) / (b - a) per face
+    plane k; midpoint a + ((t0 + t1) / 2) (b - a)): integers decided by
+    floating point, in the kernel's precision.  IEs are ordered by (voxel,
+    subvoxel within the voxel, label, edge)."""
+    f = np.float32
+    sv = f(voxel) / f(dv)
+    inv = f(1.0) / sv
+    org = np.asarray(origin, np.float32)
+    dims = np.asarray(dims, np.int64)
+    rows = []
+    for j in range(len(seg)):
+        a = np.asarray(seg[j][0], np.float32)
+        b = np.asarray(seg[j][1], np.float32)
+        d = (b - a).astype(np.float32)
+        ts = {f(0.0), f(1.0)}
+        for ax in range(3):
+            if d[ax] == 0:
+                continue
+            u0 = (a[ax] - org[ax]) * inv
+            u1 = (b[ax] - org[ax]) * inv
+            for k in range(int(math.floor(min(u0, u1))) + 1, int(math.floor(max(u0, u1))) + 1):
+                t = ((org[ax] + f(k) * sv) - a[ax]) / d[ax]
+                if f(0.0) < t < f(1.0):
+                    ts.add(f(t))
+        ts = sorted(ts)
+        wd = d.astype(np.float64) / np.linalg.norm(d.astype(np.float64))
+        for t0, t1 in zip(ts[:-1], ts[1:]):
+            tm = (t0 + t1) * f(0.5)
+            m = (a + tm * d).astype(np.float32)
+            sub = np.floor((m - org) * inv).astype(np.int64)
+            if sub.min() < 0 or np.any(sub >= dims * dv):
+                raise ValueError("edge outside the IE grid")
+            vox = sub // dv
+            loc = sub - vox * dv
+            vlin = int(vox[0] + dims[0] * (vox[1] + dims[1] * vox[2]))
+            llin = int(loc[0] + dv * (loc[1] + dv * loc[2]))
+            key = ((vlin * dv ** 3 + llin) << 32) | int(labels[j])
+            rows.append((key, j, sub, m.astype(np.float64), wd, normals[j]))
+    rows.sort(key=lambda r: (r[0], r[1]))
+    n = len(rows)
+    return {"key": np.array([r[0] for r in rows], np.int64), "edge": np.array([r[1] for r in rows], np.int64),
+            "sub": np.array([r[2] for r in rows], np.int64).reshape(n, 3),
+            "label": np.array([int(labels[r[1]]) for r in rows], np.int64),
+            "pos": np.array([r[3] for r in rows]).reshape(n, 3), "w": np.array([r[4] for r in rows]).reshape(n, 3),
+            "n1": np.array([np.asarray(r[5][0], np.float64) for r in rows]).reshape(n, 3),
+            "n2": np.array([np.asarray(r[5][1], np.float64) for r in rows]).reshape(n, 3)}
+
+
+def combine(point_ies, edges=None):
+    """One IE index space: point IEs first, then edge IEs."""
+    n_p = len(point_ies["label"])
+    n_e = 0 if edges is None else len(edges["label"])
+    out = {"label": np.concatenate([point_ies["label"], edges["label"] if n_e else np.zeros(0, np.int64)]),
+           "sub": np.concatenate([point_ies["sub"], edges["sub"] if n_e else np.zeros((0, 3), np.int64)]),
+           "pos": np.concatenate([point_ies["pos"], edges["pos"] if n_e else np.zeros((0, 3))]),
+           "nrm": np.concatenate([point_ies["nrm"], np.zeros((n_e, 3))]),
+           "type": np.r_[np.zeros(n_p, np.int64), np.ones(n_e, np.int64)],
+           "edge": np.r_[np.full(n_p, -1, np.int64), edges["edge"] if n_e else np.zeros(0, np.int64)]}
+    for f in ("w", "n1", "n2"):
+        out[f] = np.concatenate([np.zeros((n_p, 3)), edges[f] if n_e else np.zeros((0, 3))])
+    return out
+
+
+def keller_sectors(o, prev, w, n1, n2, half_angle):
+    """Diffracted conical rays of an edge point o hit from prev (Section 2.2.4):
+    the Keller cone of the directions d with d . w = d_in . w, cut into N
+    sectors of azimuth dphi = 2 pi / N around the edge, N = max(1, ceil(2 pi
+    sin(beta) / (2 half_angle))) (neighbouring axes 2 half_angle apart);
+    sector i (azimuths [i, i + 1) dphi from the face-1 normal, turning towards
+    w x n1) keeps its axis when that axis leaves the wedge (exterior edges:
+    v . n1 >= 0 or v . n2 >= 0 for its direction v across the edge).  Each
+    sector's two separation planes contain the edge at its bounding azimuths;
+    a target lies in the sector iff (p - o) . n_lo >= 0 and (p - o) . n_hi < 0
+    (no planes when N = 1).  Returns (list of (axis, n_lo, n_hi, exterior
+    margin), N's distance to the nearest integer step)."""
+    din = o - prev
+    din = din / np.linalg.norm(din)
+    cb = float(din @ w)
+    sb = math.sqrt(max(0.0, 1.0 - cb * cb))
+    e1 = n1 - float(n1 @ w) * w
+    e1 = e1 / np.linalg.norm(e1)
+    e2 = np.cross(w, e1)
+    arg = 2.0 * math.pi * sb / (2.0 * half_angle)
+    N = max(1, int(math.ceil(arg)))
+    step_margin = abs(arg - round(arg)) if arg > 0.5 else 1.0
+    dphi = 2.0 * math.pi / N
+    plane = lambda j: math.cos(j * dphi) * e2 - math.sin(j * dphi) * e1  # noqa: E731
+    out = []
+    for i in range(N):
+        phi = (i + 0.5) * dphi
+        v = math.cos(phi) * e1 + math.sin(phi) * e2
+        ext = max(float(v @ n1), float(v @ n2))
+        if ext < 0:
+            continue
+        axis = cb * w + sb * v
+        axis = axis / np.linalg.norm(axis)
+        out.append((axis, plane(i) if N > 1 else None, plane(i + 1) if N > 1 else None, ext))
+    return out, step_margin
+
+
 # --------------------------------------------------------------------------- cone geometry (Section 2.2.4)
 
 def cone_sphere_margin(o, d, cos_t, sin_t, c, R):
@@ -320,7 +426,7 @@ def _merge_similar(kids):
     return out
 
 
-def trace(scene: Scene, ies, tx, rx, origin, voxel, dv, dims, K, kappa, half_angle):
+def trace(scene: Scene, ies, tx, rx, origin, voxel, dv, dims, K, kappa, half_angle, edges=None, max_diff=0):
     """Environment-driven coarse tracing with conical rays (Sections 2.2.2-2.2.4).
 
     A node is a partial path TX -> IE chain.  Per node: ``exact`` (every
@@ -333,6 +439,7 @@ def trace(scene: Scene, ies, tx, rx, origin, voxel, dv, dims, K, kappa, half_ang
     the kappa exact records of smallest (priority, chain))."""
     tx = np.asarray(tx, np.float64).reshape(-1, 3)
     rx = np.asarray(rx, np.float64).reshape(-1, 3)
+    ies = combine(ies, edges)
     sv = float(np.float32(voxel) / np.float32(dv))
     R = sv * math.sqrt(3.0) / 2.0
     cos_t, sin_t = math.cos(half_angle), math.sin(half_angle)
@@ -360,10 +467,10 @@ def trace(scene: Scene, ies, tx, rx, origin, voxel, dv, dims, K, kappa, half_ang
 
     # ---- transmission phase: from every TX a ray towards every IE and RX
     roots = [dict(tx=i, chain=(), labels=(), prio=splitmix64(i), length=0.0, o=tx[i], prev=None, ie=-1,
-                  exact=True, excused=False) for i in range(len(tx))]
+                  ndiff=0, exact=True, excused=False) for i in range(len(tx))]
     q = []   # (parent index, kind, target, exact, excused)
     for i in range(len(tx)):
-        q += [(i, "ie", e, True, False) for e in range(n_ie)]
+        q += [(i, "ie", e, True, False) for e in range(n_ie) if ies["type"][e] == 0 or max_diff > 0]
         q += [(i, "rx", j, True, False) for j in range(len(rx))]
     parents = roots
     nodes_by_depth = []
@@ -386,7 +493,8 @@ def trace(scene: Scene, ies, tx, rx, origin, voxel, dv, dims, K, kappa, half_ang
                 kids.append(dict(tx=P["tx"], chain=P["chain"] + (t,), labels=P["labels"] + (int(ies["label"][t]),),
                                  prio=child_priority(P["prio"], t), parent=pi,
                                  length=P["length"] + float(np.linalg.norm(ies["pos"][t] - P["o"])),
-                                 o=ies["pos"][t], prev=P["o"], ie=t, exact=exact and P["exact"], excused=excused))
+                                 o=ies["pos"][t], prev=P["o"], ie=t, ndiff=P["ndiff"] + int(ies["type"][t]),
+                                 exact=exact and P["exact"], excused=excused))
         if k == K:
             break
         kept = _merge_similar(kids)
@@ -395,44 +503,73 @@ def trace(scene: Scene, ies, tx, rx, origin, voxel, dv, dims, K, kappa, half_ang
         q = []
         if not kept:
             break
-        apex = np.array([c["o"] for c in kept])
-        axes, planes = [], []
-        for c in kept:
-            din = c["o"] - c["prev"]
-            din = din / np.linalg.norm(din)
-            n_e = ies["nrm"][c["ie"]]
-            dout = din - 2.0 * float(din @ n_e) * n_e
-            dout = dout / np.linalg.norm(dout)
-            axes.append(dout)
-            planes.append(n_e if float(n_e @ dout) > 0 else -n_e)
-        axes = np.array(axes)
-        t_hit, t_lo, t_hi = scene.axis_hits(apex.astype(np.float32), axes.astype(np.float32))
+        # cones of every node: the reflected cone of a point IE, the exterior
+        # Keller sectors of an edge IE; (node, axis, plane normals, ambiguous)
+        cones = []
         for ci, c in enumerate(kept):
-            o1, d1, n_o = apex[ci], axes[ci], planes[ci]
+            e = c["ie"]
+            if ies["type"][e] == 0:
+                din = c["o"] - c["prev"]
+                din = din / np.linalg.norm(din)
+                n_e = ies["nrm"][e]
+                dout = din - 2.0 * float(din @ n_e) * n_e
+                dout = dout / np.linalg.norm(dout)
+                cones.append((ci, dout, ("refl", n_e if float(n_e @ dout) > 0 else -n_e), False))
+            else:
+                secs, step_margin = keller_sectors(c["o"], c["prev"], ies["w"][e], ies["n1"][e], ies["n2"][e],
+                                                   half_angle)
+                amb_n = scene.parity and step_margin <= 1e-4
+                for axis, n_lo, n_hi, ext in secs:
+                    cones.append((ci, axis, ("diff", n_lo, n_hi), amb_n or (scene.parity and ext <= band)))
+        if not cones:
+            break
+        apex = np.array([kept[ci]["o"] for ci, _, _, _ in cones])
+        axes = np.array([ax for _, ax, _, _ in cones])
+        t_hit, t_lo, t_hi = scene.axis_hits(apex.astype(np.float32), axes.astype(np.float32))
+        for qi, (ci, d1, sep, cone_amb) in enumerate(cones):
+            c = kept[ci]
+            o1 = apex[qi]
             t_exit = grid_exit(o1, d1, origin, voxel, dims)
-            t_end, t_near, t_far = min(t_hit[ci], t_exit), min(t_lo[ci], t_exit), min(t_hi[ci], t_exit)
+            t_end, t_near, t_far = min(t_hit[qi], t_exit), min(t_lo[qi], t_exit), min(t_hi[qi], t_exit)
             cells = near_cells(o1, d1, t_far, origin, voxel, dims)
             if len(cells) == 0:
                 continue
             m_end = block_margins(o1, d1, t_end, cells, origin, voxel)
             m_near = block_margins(o1, d1, t_near, cells, origin, voxel) if t_near < t_end else m_end
             m_far = block_margins(o1, d1, t_far, cells, origin, voxel) if t_far > t_end else m_end
+            own_edge = ies["edge"][c["ie"]]
             for w, me, mn, mf in zip(cells, m_end, m_near, m_far):
                 if mf < -band:
                     continue                      # no end of the axis reaches this block
                 w_in = me >= 0
                 w_amb = scene.parity and mn <= band   # some acceptable end, or rounding, leaves it out
                 wt = (int(w[0]), int(w[1]), int(w[2]))
-                # the last generation's cones only end paths: no IE targets
-                targets = [("ie", e) for e in by_voxel.get(wt, []) if e != c["ie"]] if k + 1 < K else []
+                # the last generation's cones only end paths: no IE targets; no diffraction beyond
+                # the limit; never a point of the node's own IE or edge
+                targets = []
+                if k + 1 < K:
+                    for e in by_voxel.get(wt, []):
+                        if e == c["ie"] or (ies["type"][e] == 1 and (c["ndiff"] >= max_diff or
+                                                                      (own_edge >= 0 and ies["edge"][e] == own_edge))):
+                            continue
+                        targets.append(("ie", e))
                 targets += [("rx", j) for j in rx_by_voxel.get(wt, [])]
                 for kind, t in targets:
                     pc = ie_lo[t] + 0.5 * sv if kind == "ie" else rx_lo[t] + 0.5 * sv
                     pr = ies["pos"][t] if kind == "ie" else rx[t]
                     m_cone = cone_sphere_margin(o1, d1, cos_t, sin_t, pc, R)
-                    m_plane = float((pr - o1) @ n_o)
-                    exact = w_in and m_cone >= 0 and m_plane > 0
-                    amb = scene.parity and (w_amb or abs(m_cone) <= band or abs(m_plane) <= band)
+                    if sep[0] == "refl":
+                        m_sep = float((pr - o1) @ sep[1])
+                        sep_in = m_sep > 0
+                        sep_amb = abs(m_sep) <= band
+                    elif sep[1] is None:
+                        sep_in, sep_amb = True, False
+                    else:
+                        m_lo, m_hi = float((pr - o1) @ sep[1]), float((pr - o1) @ sep[2])
+                        sep_in = m_lo >= 0 and m_hi < 0
+                        sep_amb = abs(m_lo) <= band or abs(m_hi) <= band
+                    exact = w_in and m_cone >= 0 and sep_in
+                    amb = scene.parity and (cone_amb or w_amb or abs(m_cone) <= band or sep_amb)
                     if exact or amb:
                         q.append((ci, kind, t, exact, amb))
         parents = kept

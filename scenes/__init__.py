@@ -366,6 +366,50 @@ def street_canyon(n_points=20_000_000, seed=0, antenna_seed=1, n_tx=4, n_rx=64, 
 # tiny random scenes for property tests
 # ----------------------------------------------------------------------------
 
+def box_edges(lo, hi, label, top=True, vertical=True):
+    """Convex edges of an axis-aligned box standing on the ground: the four
+    vertical edges and the four roof edges (its bottom edges meet the ground
+    and are not convex).  Returns segments [n, 2, 3], the outward normals of
+    the two faces meeting at each edge [n, 2, 3] and labels [n] (label, label
+    + 1, ...)."""
+    lo = np.asarray(lo, np.float64)
+    hi = np.asarray(hi, np.float64)
+    seg, nrm = [], []
+    if vertical:
+        for x, nx in ((lo[0], -1.0), (hi[0], 1.0)):
+            for y, ny in ((lo[1], -1.0), (hi[1], 1.0)):
+                seg.append(((x, y, lo[2]), (x, y, hi[2])))
+                nrm.append(((nx, 0.0, 0.0), (0.0, ny, 0.0)))
+    if top:
+        z = hi[2]
+        for y, ny in ((lo[1], -1.0), (hi[1], 1.0)):
+            seg.append(((lo[0], y, z), (hi[0], y, z)))
+            nrm.append(((0.0, ny, 0.0), (0.0, 0.0, 1.0)))
+        for x, nx in ((lo[0], -1.0), (hi[0], 1.0)):
+            seg.append(((x, lo[1], z), (x, hi[1], z)))
+            nrm.append(((nx, 0.0, 0.0), (0.0, 0.0, 1.0)))
+    n = len(seg)
+    return (np.asarray(seg, np.float32).reshape(n, 2, 3), np.asarray(nrm, np.float32).reshape(n, 2, 3),
+            (label + np.arange(n)).astype(np.uint32))
+
+
+def corner_building(h=0.1, tx=(-3.0, 5.0, 1.5), rx=(5.0, -3.0, 1.5), n_rays=20_000, K=2, levels=(0.4, 0.2, 0.1)):
+    """A 20 x 20 m ground (label 0) and one building [0,6] x [0,6] x [0,4]
+    (roof 1, faces x=0: 2, x=6: 3, y=0: 4, y=6: 5; outward normals) with its
+    eight convex edges (labels 100..107) in ``extra['edges']``.  The default RX
+    lies in the building's shadow seen from the TX: no line of sight and no
+    reflection reaches it; the vertical edge at (0, 0) diffracts towards it."""
+    faces = [(np.array([-10.0, -10.0, 0.0]), np.array([20.0, 0.0, 0.0]), np.array([0.0, 20.0, 0.0]),
+              np.array([0.0, 0.0, 1.0]), 0)]
+    faces += _box_faces((0.0, 0.0, 0.0), (6.0, 6.0, 4.0), label=(0, 1, 2, 3, 4, 5), inward=False, bottom=False)
+    xyz, nrm, lab = _sample_faces(faces, h)
+    # ground points under the building are not sampled
+    keep = ~((lab == 0) & (xyz[:, 0] > 0) & (xyz[:, 0] < 6) & (xyz[:, 1] > 0) & (xyz[:, 1] < 6))
+    seg, enrm, elab = box_edges((0.0, 0.0, 0.0), (6.0, 6.0, 4.0), 100)
+    return _pack("corner_building", xyz[keep], nrm[keep], lab[keep], tx, rx, h, levels, n_rays, K,
+                 edges=dict(seg=seg, normals=enrm, label=elab))
+
+
 def random_scene(seed, n_planes=4, n_boxes=2, extent=4.0, h=0.25, n_rays=512, n_tx=1, n_rx=3, K=3,
                  pos_sigma=0.0, tilt_sigma=0.0, levels=None):
     """A few random rectangles and boxes inside a cube of side ``extent``.

@@ -140,3 +140,81 @@ def test_two_reflections_find_the_image_sequences():
         assert len(g["rows"]) <= 100 and g["count"] >= len(g["rows"])
         labs = k[3]
         assert all(a != b for a, b in zip(labs, labs[1:]))
+
+
+# --------------------------------------------------------------------------- diffraction (Section 2.2.4)
+
+def test_keller_sectors_law_and_exterior():
+    """Every diffracted axis keeps the incoming angle with the edge (Keller's
+    law), only axes that leave the wedge are kept, and the sectors' planes
+    give every exterior target exactly one sector."""
+    rng = np.random.default_rng(1)
+    w = np.array([0.0, 0.0, 1.0])
+    n1, n2 = np.array([-1.0, 0.0, 0.0]), np.array([0.0, -1.0, 0.0])   # the solid is x > 0, y > 0
+    o = np.array([0.0, 0.0, 1.0])
+    for _ in range(20):
+        prev = np.array([-rng.uniform(1, 5), rng.uniform(-5, 5), rng.uniform(-2, 4)])
+        din = (o - prev) / np.linalg.norm(o - prev)
+        secs, _ = cone.keller_sectors(o, prev, w, n1, n2, math.radians(2.5))
+        assert secs
+        for axis, n_lo, n_hi, ext in secs:
+            assert abs(float(axis @ w) - float(din @ w)) <= 1e-12
+            v = axis - float(axis @ w) * w
+            assert float(v @ n1) >= -1e-12 or float(v @ n2) >= -1e-12
+        for _ in range(50):
+            ang = rng.uniform(0, 2 * math.pi)
+            p = o + np.array([math.cos(ang), math.sin(ang), rng.uniform(-1, 1)]) * rng.uniform(0.5, 5)
+            inside = [float((p - o) @ a) >= 0 and float((p - o) @ b) < 0 for _, a, b, _ in secs]
+            exterior = math.cos(ang) < 0 or math.sin(ang) < 0
+            assert sum(inside) <= 1
+            # directions well inside the exterior quadrants sit in some kept sector
+            if math.cos(ang) < -0.1 or math.sin(ang) < -0.1:
+                assert sum(inside) == 1
+            if not exterior:
+                assert sum(inside) == 0 or min(abs(math.cos(ang)), abs(math.sin(ang))) < 0.05
+
+
+def test_edge_ies_cover_the_edges():
+    """Edge IEs: the pieces of every edge tile it (midpoints on the edge, one piece per subvoxel crossed)."""
+    s = scenes.corner_building()
+    E = s.extra["edges"]
+    origin = np.array([-10.292, -10.292, -0.292], np.float32)
+    eies = cone.edge_ies(E["seg"], E["normals"], E["label"], origin, 0.4, 2, (53, 53, 13))
+    for j in range(len(E["seg"])):
+        m = eies["edge"] == j
+        a, b = E["seg"][j].astype(np.float64)
+        # an axis-aligned edge has one piece per subvoxel layer it spans along its axis
+        ax = int(np.argmax(np.abs(b - a)))
+        u = (np.array([a[ax], b[ax]]) - float(origin[ax])) / 0.2
+        assert int(m.sum()) == int(math.floor(u.max()) - math.floor(u.min()) + 1)
+        d = (b - a) / np.linalg.norm(b - a)
+        r = eies["pos"][m] - a
+        assert np.allclose(r - (r @ d)[:, None] * d, 0.0, atol=1e-5)
+        assert len({tuple(x) for x in eies["sub"][m]}) == int(m.sum())
+    assert np.all(np.diff(eies["key"]) >= 0)
+
+
+@pytest.mark.timeout(600)
+def test_corner_diffraction_closed_form():
+    """The RX behind the building's corner: no line of sight, no reflection;
+    with one diffraction the only coarse path goes through the vertical edge at
+    (0, 0), no shorter than the exact diffraction path 2 sqrt(34) (equal heights:
+    the diffraction point is at z = 1.5) and within a subvoxel of it."""
+    s = scenes.corner_building()
+    E = s.extra["edges"]
+    origin = np.array([-10.292, -10.292, -0.292], np.float32)
+    dims = (53, 53, 13)
+    ies = cone.ie_build(s.xyz, s.normal, s.label, origin, 0.4, 2, dims)
+    eies = cone.edge_ies(E["seg"], E["normals"], E["label"], origin, 0.4, 2, dims)
+    sc = cone.Scene(s.xyz, s.normal, s.label, s.surfel_radius, s.t_eps_value)
+    L_star = 2.0 * math.sqrt(34.0)
+    res = cone.trace(sc, ies, s.tx, s.rx, origin, 0.4, 2, dims, K=1, kappa=100, half_angle=math.radians(2.5),
+                     edges=eies, max_diff=1)
+    assert set(res["paths"]) == {(0, 0, 1, (100,))}
+    for r in res["paths"][(0, 0, 1, (100,))]["rows"]:
+        assert L_star * (1 - 1e-12) <= r["length"] <= L_star + 0.01
+        e = r["chain"][0] - len(ies["label"])
+        assert abs(eies["pos"][e][2] - 1.5) <= 0.2
+    res0 = cone.trace(sc, ies, s.tx, s.rx, origin, 0.4, 2, dims, K=1, kappa=100, half_angle=math.radians(2.5),
+                      edges=eies, max_diff=0)
+    assert not res0["paths"]
