@@ -35,8 +35,10 @@ if ROOT not in sys.path:
 HBM_PEAK_GBS = 8000.0
 # sources of the bounce kernel and of the hierarchy it reads: a PMC traffic figure is valid only for
 # these exact bytes
+# the bounce kernel's definition: its sources, and the scene view it reads
 TRACE_SOURCES = ("paper_2402_13747_amd/csrc/trace.hip", "paper_2402_13747_amd/csrc/trace_core.h",
-                 "paper_2402_13747_amd/csrc/internal.h", "paper_2402_13747_amd/csrc/build.hip", "include/pcrl.h")
+                 "paper_2402_13747_amd/csrc/build.hip")
+SCENE_VIEW_SOURCE = "paper_2402_13747_amd/csrc/internal.h"
 
 
 def log(*a):
@@ -44,10 +46,16 @@ def log(*a):
 
 
 def trace_source_hash():
+    """Hash of the bounce kernel's sources and of the scene-view struct it reads
+    (other declarations of the headers do not change the kernel)."""
     h = hashlib.sha256()
     for f in TRACE_SOURCES:
         with open(os.path.join(ROOT, f), "rb") as fh:
             h.update(fh.read())
+    with open(os.path.join(ROOT, SCENE_VIEW_SOURCE)) as fh:
+        text = fh.read()
+    a = text.index("struct SceneView {")
+    h.update(text[a:text.index("};", a)].encode())
     return h.hexdigest()[:16]
 
 
