@@ -42,7 +42,8 @@ Readings where the paper is silent (each listed in the design notes):
     (beyond it everything is behind that surface), or at the grid's exit;
   * separation plane of a reflected cone: through the apex, with the IE's
     normal turned towards the reflected side as its normal; a target is in
-    front iff (p - apex) . n > 0;
+    front iff (p - apex) . n > tau, tau = 1e-3 subvoxel edges (a target on
+    the reflecting plane itself is never in front);
   * kappa acts on partial paths too (otherwise the branching is unbounded):
     per (TX, label sequence) at most kappa nodes of a generation are kept,
     chosen by a deterministic priority (SplitMix64 of the parent's priority
@@ -206,7 +207,7 @@ def combine(point_ies, edges=None):
     return out
 
 
-def keller_sectors(o, prev, w, n1, n2, half_angle):
+def keller_sectors(o, prev, w, n1, n2, half_angle, slack=0.0):
     """Diffracted conical rays of an edge point o hit from prev (Section 2.2.4):
     the Keller cone of the directions d with d . w = d_in . w, cut into N
     sectors of azimuth dphi = 2 pi / N around the edge, N = max(1, ceil(2 pi
@@ -217,7 +218,9 @@ def keller_sectors(o, prev, w, n1, n2, half_angle):
     sector's two separation planes contain the edge at its bounding azimuths;
     a target lies in the sector iff (p - o) . n_lo >= 0 and (p - o) . n_hi < 0
     (no planes when N = 1).  Returns (list of (axis, n_lo, n_hi, exterior
-    margin), N's distance to the nearest integer step)."""
+    margin), N's distance to the nearest integer step); with ``slack`` > 0 the
+    list also holds the sectors whose margin is in [-slack, 0) (an axis that
+    grazes a face, kept or dropped by rounding)."""
     din = o - prev
     din = din / np.linalg.norm(din)
     cb = float(din @ w)
@@ -235,7 +238,7 @@ def keller_sectors(o, prev, w, n1, n2, half_angle):
         phi = (i + 0.5) * dphi
         v = math.cos(phi) * e1 + math.sin(phi) * e2
         ext = max(float(v @ n1), float(v @ n2))
-        if ext < 0:
+        if ext < -slack:
             continue
         axis = cb * w + sb * v
         axis = axis / np.linalg.norm(axis)
@@ -415,7 +418,7 @@ def _merge_similar(kids):
                 c["excused"] = True
         # the definition's own choice: the smallest exact node
         best_exact = next((c for c in group if c["exact"]), None)
-        if best_exact is not None and best_exact not in head:
+        if best_exact is not None and not any(c is best_exact for c in head):
             best_exact["excused"] = True
             head.append(best_exact)
         for c in head:
@@ -442,6 +445,7 @@ def trace(scene: Scene, ies, tx, rx, origin, voxel, dv, dims, K, kappa, half_ang
     ies = combine(ies, edges)
     sv = float(np.float32(voxel) / np.float32(dv))
     R = sv * math.sqrt(3.0) / 2.0
+    tau = float(np.float32(1e-3) * np.float32(sv))   # a reflected target must clear the plane by this much
     cos_t, sin_t = math.cos(half_angle), math.sin(half_angle)
     ext = float(max(np.abs(scene.xyz).max() if len(scene.xyz) else 1.0, np.abs(tx).max(), 1.0))
     band = 64 * (2.0 ** -24) * ext if scene.parity else 0.0
@@ -514,19 +518,21 @@ def trace(scene: Scene, ies, tx, rx, origin, voxel, dv, dims, K, kappa, half_ang
                 n_e = ies["nrm"][e]
                 dout = din - 2.0 * float(din @ n_e) * n_e
                 dout = dout / np.linalg.norm(dout)
-                cones.append((ci, dout, ("refl", n_e if float(n_e @ dout) > 0 else -n_e), False))
+                cones.append((ci, dout, ("refl", n_e if float(n_e @ dout) > 0 else -n_e), False, False))
             else:
                 secs, step_margin = keller_sectors(c["o"], c["prev"], ies["w"][e], ies["n1"][e], ies["n2"][e],
-                                                   half_angle)
-                amb_n = scene.parity and step_margin <= 1e-4
+                                                   half_angle, slack=band if scene.parity else 0.0)
+                amb_n = scene.parity and step_margin <= 1e-3
                 for axis, n_lo, n_hi, ext in secs:
-                    cones.append((ci, axis, ("diff", n_lo, n_hi), amb_n or (scene.parity and ext <= band)))
+                    # a sector whose axis grazes a face (|margin| within the band) is kept or
+                    # dropped by rounding: its targets are ambiguous, exact only when kept
+                    cones.append((ci, axis, ("diff", n_lo, n_hi, ext >= 0), amb_n, abs(ext) <= band))
         if not cones:
             break
-        apex = np.array([kept[ci]["o"] for ci, _, _, _ in cones])
-        axes = np.array([ax for _, ax, _, _ in cones])
+        apex = np.array([kept[ci]["o"] for ci, _, _, _, _ in cones])
+        axes = np.array([ax for _, ax, _, _, _ in cones])
         t_hit, t_lo, t_hi = scene.axis_hits(apex.astype(np.float32), axes.astype(np.float32))
-        for qi, (ci, d1, sep, cone_amb) in enumerate(cones):
+        for qi, (ci, d1, sep, amb_n, graze) in enumerate(cones):
             c = kept[ci]
             o1 = apex[qi]
             t_exit = grid_exit(o1, d1, origin, voxel, dims)
@@ -559,19 +565,32 @@ def trace(scene: Scene, ies, tx, rx, origin, voxel, dv, dims, K, kappa, half_ang
                     pr = ies["pos"][t] if kind == "ie" else rx[t]
                     m_cone = cone_sphere_margin(o1, d1, cos_t, sin_t, pc, R)
                     if sep[0] == "refl":
-                        m_sep = float((pr - o1) @ sep[1])
+                        m_sep = float((pr - o1) @ sep[1]) - tau
                         sep_in = m_sep > 0
                         sep_amb = abs(m_sep) <= band
+                        sep_out = m_sep < -band
                     elif sep[1] is None:
-                        sep_in, sep_amb = True, False
+                        sep_in, sep_amb, sep_out = sep[3], False, False
                     else:
                         m_lo, m_hi = float((pr - o1) @ sep[1]), float((pr - o1) @ sep[2])
-                        sep_in = m_lo >= 0 and m_hi < 0
+                        sep_in = sep[3] and m_lo >= 0 and m_hi < 0
                         sep_amb = abs(m_lo) <= band or abs(m_hi) <= band
+                        sep_out = m_lo < -band or m_hi > band
                     exact = w_in and m_cone >= 0 and sep_in
-                    amb = scene.parity and (cone_amb or w_amb or abs(m_cone) <= band or sep_amb)
+                    # a conjunction is undecided when one of its terms is within the band and
+                    # none is outside it on the false side; a sector count N within the band
+                    # of an integer step moves every sector: all its decisions are undecided
+                    out = m_cone < -band or sep_out
+                    amb = scene.parity and (amb_n or (not out and (graze or w_amb or abs(m_cone) <= band or sep_amb)))
                     if exact or amb:
                         q.append((ci, kind, t, exact, amb))
+        # one candidate per (node, target): a target reached by two cones of one node
+        # (banded at the plane two sectors share) is admitted once
+        merged = {}
+        for ci, kind, t, ex, amb in q:
+            e0, a0 = merged.get((ci, kind, t), (False, False))
+            merged[(ci, kind, t)] = (e0 or ex, a0 or amb)
+        q = [(ci, kind, t, ex, amb) for (ci, kind, t), (ex, amb) in merged.items()]
         parents = kept
     # ---- coarse paths: per (tx, rx, labels) the count and the kappa exact rows of smallest priority
     paths = {}
