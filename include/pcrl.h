@@ -471,7 +471,8 @@ typedef struct PcrlIes PcrlIes;           /* opaque: a scene's IE table (library
 typedef struct PcrlConeLaunch PcrlConeLaunch;  /* opaque: one cone-traced query (library-owned) */
 
 typedef struct {
-    int64_t n_ies;        /* point IEs: (subvoxel, label) pairs holding points */
+    int64_t n_ies;        /* IEs: point IEs ((subvoxel, label) pairs holding points), then edge pieces */
+    int64_t n_edge_ies;   /* edge pieces (ie_add_edges) */
     int64_t n_voxels;     /* voxels of the grid */
     int64_t n_occupied;   /* voxels holding an IE */
     int64_t device_bytes;
@@ -486,6 +487,19 @@ typedef struct {
  * table.  Synchronous.  PCRL_EINVAL: a point outside the grid, bad grid
  * parameters, a scene with dynamic points (update_points). */
 int ie_build(PcrlScene* scene, const PcrlIeGrid* grid, pcrl_stream_t stream, PcrlIes** out);
+/* Diffraction edges (Section 2: inserted by hand; Section 3: exterior edges
+ * only): nE convex edge segments seg [nE,2,3] (device float32, end points
+ * a, b), the outward normals of the two faces meeting at each edge normals
+ * [nE,2,3] and a label per edge (label [nE], device).  Every edge is cut at
+ * the subvoxel faces it crosses (cut parameters t = ((origin + k sv) - a) /
+ * (b - a) per face plane, in FP32); each piece is an edge IE in the subvoxel
+ * of its midpoint, with the edge's label, its midpoint as reception point,
+ * the edge direction and the two normals.  Edge IEs get the indices after
+ * the point IEs, ordered by (voxel, subvoxel, label, edge).  Once per table;
+ * PCRL_EINVAL for edges outside the grid, zero-length edges, or a second
+ * call.  Synchronous. */
+int ie_add_edges(PcrlIes* ies, const float* seg, const float* normals, const uint32_t* label, int64_t n_edges,
+                 pcrl_stream_t stream);
 int ie_info(const PcrlIes* ies, PcrlIeInfo* out);
 /* Copy the IE table into caller device arrays of at least n_ies entries
  * (any may be NULL): key (voxel * dv^3 + local subvoxel) << 32 | label,
@@ -498,11 +512,14 @@ typedef struct {
     int32_t max_interactions;  /* K in [0, 8] (Table 1: 5) */
     float   half_angle;        /* cone half-angle in radians, (0, pi/4]; <= 0 -> 2.5 degrees */
     int32_t flags;             /* 0 */
-    int32_t reserved;
+    int32_t max_diffractions;  /* edge interactions per path, >= 0 (Section 3, simulation B: 1); edge pieces
+                                  are targets only while a path has fewer */
 } PcrlConeParams;
 
 typedef struct {
     int64_t nodes[PCRL_MAX_REFLECTIONS + 1];       /* [k]: partial paths with k interactions kept */
+    int64_t cones[PCRL_MAX_REFLECTIONS + 1];       /* [k]: conical rays they cast (one per reflection, the
+                                                      exterior Keller-cone sectors per diffraction) */
     int64_t candidates[PCRL_MAX_REFLECTIONS + 1];  /* [k]: targets that passed the cone and plane tests
                                                       ([0]: the transmission phase's rays) */
     int64_t visible[PCRL_MAX_REFLECTIONS + 1];     /* [k]: of those, visible */
@@ -521,7 +538,17 @@ typedef struct {
  *     every IE and RX in the voxels within one voxel of the march is a target
  *     when the cone meets its subvoxel's bounding sphere, its reception
  *     point lies in front of the separation plane at the apex (normal: the
- *     IE's normal on the reflected side) and a visibility ray reaches it;
+ *     IE's normal on the reflected side, cleared by 1e-3 of a subvoxel) and
+ *     a visibility ray reaches it;
+ *   diffraction (max_diffractions > 0, edge IEs of ie_add_edges): an edge
+ *     piece hit from direction d_in casts the Keller cone of the directions d
+ *     with d . w = d_in . w (w the edge direction), cut into N = max(1,
+ *     ceil(pi sin(beta) / half_angle)) sectors of azimuth 2 pi / N measured
+ *     from the first face's normal; a sector is kept when its axis leaves
+ *     the wedge (v . n1 >= 0 or v . n2 >= 0 for its direction v across the
+ *     edge), and its two separation planes contain the edge at its bounding
+ *     azimuths: a target lies in the sector iff (p - o) . n_lo >= 0 and
+ *     (p - o) . n_hi < 0;
  *   partial paths reaching the same IE with the same label sequence are
  *     merged (the one of smallest SplitMix64 priority is kept), up to
  *     max_interactions; an RX target ends a coarse path.

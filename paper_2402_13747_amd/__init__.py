@@ -543,6 +543,23 @@ class IeTable:
                                                                                "nrm")], _stream(dev)))
         return {k: v[:n] for k, v in out.items()}
 
+    def add_edges(self, seg, normals, label):
+        """Diffraction edges: segments [n, 2, 3], the outward normals of their two
+        faces [n, 2, 3] and labels [n] (ie_add_edges)."""
+        dev = self.device
+        segt = _as_tensor(seg, torch.float32, dev).reshape(-1, 6).contiguous()
+        nrmt = _as_tensor(normals, torch.float32, dev).reshape(-1, 6).contiguous()
+        if isinstance(label, np.ndarray):
+            label = torch.from_numpy(np.ascontiguousarray(label.astype(np.uint32)).view(np.int32))
+        labt = _as_tensor(label, torch.int32, dev)
+        n = segt.shape[0]
+        if nrmt.shape[0] != n or labt.shape[0] != n:
+            raise ValueError("seg, normals and label must have the same length")
+        with _on(dev):
+            check("ie_add_edges", lib.ie_add_edges(self._h, _ptr(segt) if n else None, _ptr(nrmt) if n else None,
+                                                   _ptr(labt) if n else None, n, _stream(dev)))
+        self._edges = (segt, nrmt, labt)
+
     def release(self):
         if self._h:
             lib.release_ies(self._h)
@@ -622,12 +639,13 @@ class ConeLaunch:
             pass
 
 
-def cone_launch(ies: IeTable, tx, rx, max_interactions, half_angle=0.0) -> ConeLaunch:
-    """Environment-driven coarse tracing with conical rays (Sections 2.2.2-2.2.4)."""
+def cone_launch(ies: IeTable, tx, rx, max_interactions, half_angle=0.0, max_diffractions=0) -> ConeLaunch:
+    """Environment-driven coarse tracing with conical rays (Sections 2.2.2-2.2.4);
+    with ``max_diffractions`` > 0 the table's edge pieces diffract (Keller-cone sectors)."""
     dev = ies.device
     txt = _as_tensor(tx, torch.float32, dev, 3)
     rxt = _as_tensor(np.zeros((0, 3), np.float32) if rx is None else rx, torch.float32, dev, 3)
-    p = _lib.PcrlConeParams(int(max_interactions), float(half_angle), 0, 0)
+    p = _lib.PcrlConeParams(int(max_interactions), float(half_angle), 0, int(max_diffractions))
     h = C.c_void_p()
     with _on(dev):
         check("cone_launch", lib.cone_launch(ies.handle, _ptr(txt), txt.shape[0],

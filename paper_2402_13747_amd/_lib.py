@@ -144,17 +144,18 @@ class PcrlIeGrid(C.Structure):
 
 
 class PcrlIeInfo(C.Structure):
-    _fields_ = [("n_ies", C.c_int64), ("n_voxels", C.c_int64), ("n_occupied", C.c_int64),
+    _fields_ = [("n_ies", C.c_int64), ("n_edge_ies", C.c_int64), ("n_voxels", C.c_int64), ("n_occupied", C.c_int64),
                 ("device_bytes", C.c_int64)]
 
 
 class PcrlConeParams(C.Structure):
     _fields_ = [("max_interactions", C.c_int32), ("half_angle", C.c_float), ("flags", C.c_int32),
-                ("reserved", C.c_int32)]
+                ("max_diffractions", C.c_int32)]
 
 
 class PcrlConeStats(C.Structure):
-    _fields_ = [("nodes", C.c_int64 * (MAX_REFLECTIONS + 1)), ("candidates", C.c_int64 * (MAX_REFLECTIONS + 1)),
+    _fields_ = [("nodes", C.c_int64 * (MAX_REFLECTIONS + 1)), ("cones", C.c_int64 * (MAX_REFLECTIONS + 1)),
+                ("candidates", C.c_int64 * (MAX_REFLECTIONS + 1)),
                 ("visible", C.c_int64 * (MAX_REFLECTIONS + 1)), ("records", C.c_int64),
                 ("ms_transmission", C.c_double), ("ms_propagation", C.c_double)]
 
@@ -186,6 +187,7 @@ SIGNATURES = {
                                C.POINTER(C.c_void_p)]),
     "batch_autotune": (C.c_int, [C.POINTER(PcrlQuery), C.c_int32, C.c_void_p, C.POINTER(PcrlBatchParams)]),
     "ie_build": (C.c_int, [C.c_void_p, C.POINTER(PcrlIeGrid), C.c_void_p, C.POINTER(C.c_void_p)]),
+    "ie_add_edges": (C.c_int, [C.c_void_p, C.c_void_p, C.c_void_p, C.c_void_p, C.c_int64, C.c_void_p]),
     "ie_info": (C.c_int, [C.c_void_p, C.POINTER(PcrlIeInfo)]),
     "ie_table": (C.c_int, [C.c_void_p, C.c_void_p, C.c_void_p, C.c_void_p, C.c_void_p, C.c_void_p, C.c_void_p,
                            C.c_void_p]),

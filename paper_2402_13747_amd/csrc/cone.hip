@@ -55,8 +55,16 @@ struct PcrlIes {
     uint32_t* count = nullptr;
     float4* pos = nullptr;       // reception point
     float4* nrm = nullptr;       // unit normal
-    uint2* vox = nullptr;        // per voxel: (first IE, count)
-    uint8_t* near = nullptr;     // per voxel: an IE within Chebyshev distance 1
+    uint2* vox = nullptr;        // per voxel: (first point IE, count)
+    uint8_t* near = nullptr;     // per voxel: an IE (point or edge) within Chebyshev distance 1
+    // edge IEs (ie_add_edges): indices [n_pt, n_ie) follow the point IEs
+    int64_t n_pt = 0, n_edges = 0;
+    uint32_t* type = nullptr;    // per IE: 0 points, 1 an edge piece
+    uint32_t* eid = nullptr;     // per IE: its edge (edge pieces), else 0xFFFFFFFF
+    float4* ew = nullptr;        // per edge piece: unit edge direction
+    float4* en1 = nullptr;       // per edge piece: outward normals of the edge's two faces
+    float4* en2 = nullptr;
+    uint2* vox_e = nullptr;      // per voxel: (first edge piece, count), null without edges
 };
 
 namespace pcrl {
@@ -70,6 +78,18 @@ struct Gen {
     uint32_t* tx = nullptr;
     uint32_t* gid = nullptr;     // label-sequence group (dense, in (tx, labels) order)
     uint64_t* prio = nullptr;
+    uint32_t* ndiff = nullptr;   // diffractions on the partial path
+};
+
+// The conical rays of one generation: one reflected cone per node at a point
+// IE, the exterior Keller-cone sectors of a node at an edge piece.
+struct Cones {
+    uint32_t n = 0;
+    uint32_t* node = nullptr;
+    float4* axis = nullptr;
+    float4* s0 = nullptr;        // reflection: separation plane normal; diffraction: lower sector plane
+    float4* s1 = nullptr;        // diffraction: upper sector plane
+    uint32_t* kind = nullptr;    // 0 reflection, 1 diffraction sector, 2 diffraction without planes (one sector)
     float* t_end = nullptr;      // end of the axis march
 };
 
@@ -211,7 +231,7 @@ __global__ void k_ie_voxels(const uint64_t* ie_key, uint32_t n_ie, int dv3, uint
     vox[v] = make_uint2(e, j - e);
 }
 
-__global__ void k_ie_near(const uint2* vox, IeGrid g, uint32_t n_vox, uint8_t* near) {
+__global__ void k_ie_near(const uint2* vox, const uint2* vox_e, IeGrid g, uint32_t n_vox, uint8_t* near) {
     const uint32_t v = blockIdx.x * blockDim.x + threadIdx.x;
     if (v >= n_vox) return;
     const int x = (int)(v % (uint32_t)g.dims[0]);
@@ -223,9 +243,178 @@ __global__ void k_ie_near(const uint2* vox, IeGrid g, uint32_t n_vox, uint8_t* n
             for (int dx = -1; dx <= 1; ++dx) {
                 const int a = x + dx, b = y + dy, c = z + dz;
                 if (a < 0 || b < 0 || c < 0 || a >= g.dims[0] || b >= g.dims[1] || c >= g.dims[2]) continue;
-                if (vox[(size_t)a + (size_t)g.dims[0] * ((size_t)b + (size_t)g.dims[1] * c)].y) any = 1;
+                const size_t w = (size_t)a + (size_t)g.dims[0] * ((size_t)b + (size_t)g.dims[1] * c);
+                if (vox[w].y || (vox_e && vox_e[w].y)) any = 1;
             }
     near[v] = any;
+}
+
+// Cut parameters of edge j at the subvoxel face planes it crosses, in
+// increasing order, each value once (a corner crossing of two axes is one
+// cut): t_k = ((origin + k sv) - a) / (b - a) along every axis, kept when
+// 0 < t < 1.  Returns their number; writes the pieces when `write`.
+struct EdgeArgs {
+    const float* seg;        // [n,2,3]
+    const float* nrm;        // [n,2,3]
+    const uint32_t* label;
+    uint32_t n;
+    IeGrid g;
+    const uint32_t* offset;  // pieces before each edge ([n + 1])
+    uint32_t* count;         // pieces of each edge
+    uint32_t* bad;
+    uint64_t* key;           // out per piece (edge-major, t increasing)
+    uint32_t* edge;
+    int32_t* sub;            // [P,3]
+    float4* pos;
+};
+
+__device__ uint32_t edge_pieces(const EdgeArgs& A, uint32_t j, bool write) {
+#pragma clang fp contract(off)
+    const IeGrid& g = A.g;
+    const float a[3] = {A.seg[6 * j], A.seg[6 * j + 1], A.seg[6 * j + 2]};
+    const float b[3] = {A.seg[6 * j + 3], A.seg[6 * j + 4], A.seg[6 * j + 5]};
+    const float d[3] = {b[0] - a[0], b[1] - a[1], b[2] - a[2]};
+    // per axis: the next plane index k and its last value, in increasing t
+    int kn[3], ke[3], ks[3];
+#pragma unroll
+    for (int ax = 0; ax < 3; ++ax) {
+        ks[ax] = 0;
+        kn[ax] = 0;
+        ke[ax] = -1;
+        if (d[ax] == 0.f) continue;
+        const float u0 = (a[ax] - g.org[ax]) * g.inv_sv, u1 = (b[ax] - g.org[ax]) * g.inv_sv;
+        const int lo = (int)floorf(fminf(u0, u1)) + 1, hi = (int)floorf(fmaxf(u0, u1));
+        if (d[ax] > 0.f) { kn[ax] = lo; ke[ax] = hi; ks[ax] = 1; }
+        else { kn[ax] = hi; ke[ax] = lo; ks[ax] = -1; }
+    }
+    auto t_of = [&](int ax, int k) { return ((g.org[ax] + (float)k * g.sv) - a[ax]) / d[ax]; };
+    auto more = [&](int ax) { return ks[ax] != 0 && (ks[ax] > 0 ? kn[ax] <= ke[ax] : kn[ax] >= ke[ax]); };
+    float prev = 0.f;
+    uint32_t pieces = 0;
+    const uint32_t base = write ? A.offset[j] : 0u;
+    for (;;) {
+        // the smallest next cut in (prev, 1) over the three axes
+        float t = 1.f;
+        int which = -1;
+#pragma unroll
+        for (int ax = 0; ax < 3; ++ax) {
+            while (more(ax) && !(t_of(ax, kn[ax]) > prev)) kn[ax] += ks[ax];   // at or before the last cut
+            if (more(ax)) {
+                const float tc = t_of(ax, kn[ax]);
+                if (tc < t) {
+                    t = tc;
+                    which = ax;
+                }
+            }
+        }
+        if (which < 0 || !(t < 1.f)) t = 1.f;
+        if (write) {
+            const float tm = (prev + t) * 0.5f;
+            const float m[3] = {a[0] + tm * d[0], a[1] + tm * d[1], a[2] + tm * d[2]};
+            int c[3];
+            bool ok = true;
+#pragma unroll
+            for (int ax = 0; ax < 3; ++ax) {
+                const float u = floorf((m[ax] - g.org[ax]) * g.inv_sv);
+                ok = ok && u >= 0.f && u < (float)(g.dims[ax] * g.dv);
+                c[ax] = ok ? (int)u : 0;
+            }
+            if (!ok) atomicAdd(A.bad, 1u);
+            const int dv = g.dv;
+            const uint64_t vox = (uint64_t)(c[0] / dv) +
+                                 (uint64_t)g.dims[0] * ((uint64_t)(c[1] / dv) + (uint64_t)g.dims[1] * (uint64_t)(c[2] / dv));
+            const uint64_t loc = (uint64_t)(c[0] % dv) + (uint64_t)dv * ((uint64_t)(c[1] % dv) + (uint64_t)dv * (c[2] % dv));
+            const uint32_t q = base + pieces;
+            A.key[q] = ((vox * (uint64_t)(dv * dv * dv) + loc) << 32) | (uint64_t)A.label[j];
+            A.edge[q] = j;
+            A.sub[3 * (size_t)q] = c[0];
+            A.sub[3 * (size_t)q + 1] = c[1];
+            A.sub[3 * (size_t)q + 2] = c[2];
+            A.pos[q] = make_float4(m[0], m[1], m[2], 0.f);
+        }
+        ++pieces;
+        if (t >= 1.f) break;
+        prev = t;
+    }
+    return pieces;
+}
+
+__global__ void k_edge_count(EdgeArgs A) {
+    const uint32_t j = blockIdx.x * blockDim.x + threadIdx.x;
+    if (j >= A.n) return;
+    const float dx = A.seg[6 * j + 3] - A.seg[6 * j], dy = A.seg[6 * j + 4] - A.seg[6 * j + 1],
+                dz = A.seg[6 * j + 5] - A.seg[6 * j + 2];
+    if (!(dx * dx + dy * dy + dz * dz > 0.f)) {
+        atomicAdd(A.bad, 1u);
+        A.count[j] = 0;
+        return;
+    }
+    A.count[j] = edge_pieces(A, j, false);
+}
+
+__global__ void k_edge_write(EdgeArgs A) {
+    const uint32_t j = blockIdx.x * blockDim.x + threadIdx.x;
+    if (j >= A.n || A.count[j] == 0) return;
+    edge_pieces(A, j, true);
+}
+
+// Edge pieces in sorted order appended to the IE arrays (from index n_pt).
+struct EdgeAppend {
+    const uint32_t* perm;    // sorted order of the pieces
+    uint32_t P, n_pt;
+    const uint64_t* key;     // sorted keys
+    const uint32_t* edge;
+    const int32_t* sub;
+    const float4* pos;
+    const float* seg;
+    const float* nrm;
+    uint64_t* ie_key;
+    int32_t* ie_sub;
+    uint32_t* ie_label;
+    uint32_t* ie_count;
+    float4* ie_pos;
+    float4* ie_nrm;
+    uint32_t* ie_type;
+    uint32_t* ie_eid;
+    float4* ew;
+    float4* en1;
+    float4* en2;
+};
+
+__global__ void k_edge_append(EdgeAppend A) {
+    const uint32_t q = blockIdx.x * blockDim.x + threadIdx.x;
+    if (q >= A.P) return;
+    const uint32_t p = A.perm[q];
+    const uint32_t j = A.edge[p];
+    const uint32_t e = A.n_pt + q;
+    A.ie_key[e] = A.key[q];
+    A.ie_sub[3 * (size_t)e] = A.sub[3 * (size_t)p];
+    A.ie_sub[3 * (size_t)e + 1] = A.sub[3 * (size_t)p + 1];
+    A.ie_sub[3 * (size_t)e + 2] = A.sub[3 * (size_t)p + 2];
+    A.ie_label[e] = (uint32_t)(A.key[q] & 0xFFFFFFFFull);
+    A.ie_count[e] = 0u;
+    A.ie_pos[e] = A.pos[p];
+    A.ie_nrm[e] = make_float4(0.f, 0.f, 0.f, 0.f);
+    A.ie_type[e] = 1u;
+    A.ie_eid[e] = j;
+    const float dx = A.seg[6 * j + 3] - A.seg[6 * j], dy = A.seg[6 * j + 4] - A.seg[6 * j + 1],
+                dz = A.seg[6 * j + 5] - A.seg[6 * j + 2];
+    const float il = 1.0f / sqrtf(dx * dx + dy * dy + dz * dz);
+    A.ew[q] = make_float4(dx * il, dy * il, dz * il, 0.f);
+    A.en1[q] = make_float4(A.nrm[6 * j], A.nrm[6 * j + 1], A.nrm[6 * j + 2], 0.f);
+    A.en2[q] = make_float4(A.nrm[6 * j + 3], A.nrm[6 * j + 4], A.nrm[6 * j + 5], 0.f);
+}
+
+// Per voxel the range of the edge pieces [n_pt, n_ie) it holds.
+__global__ void k_edge_voxels(const uint64_t* ie_key, uint32_t n_pt, uint32_t n_ie, int dv3, uint2* vox_e) {
+    const uint32_t e = n_pt + blockIdx.x * blockDim.x + threadIdx.x;
+    if (e >= n_ie) return;
+    const uint64_t v = (ie_key[e] >> 32) / (uint64_t)dv3;
+    const bool first = e == n_pt || ((ie_key[e - 1] >> 32) / (uint64_t)dv3) != v;
+    if (!first) return;
+    uint32_t j = e + 1;
+    while (j < n_ie && ((ie_key[j] >> 32) / (uint64_t)dv3) == v) ++j;
+    vox_e[v] = make_uint2(e, j - e);
 }
 
 // ---------------------------------------------------------------------------
@@ -296,17 +485,114 @@ __global__ __launch_bounds__(TRACE_BLOCK) void k_visibility(VisArgs a) {
     }
 }
 
-struct AxisArgs {
-    TraceArgs t;
+// ---------------------------------------------------------------------------
+// cones of a generation (Sections 2.2.3 and 2.2.4)
+// ---------------------------------------------------------------------------
+
+struct ExpandArgs {
     Gen gen;
     const float4* parent_pos;   // previous generation's apex (or the TX)
+    const uint32_t* type;
     const float4* ie_nrm;
-    float4* axis;               // out: reflected direction (w: unused)
-    float4* plane;              // out: separation plane normal
+    const float4* ew;
+    const float4* en1;
+    const float4* en2;
+    uint32_t n_pt;
+    float half;                 // cone half-angle
+    const uint32_t* offset;     // k_cone_fill: exclusive scan of the counts ([n + 1])
+    uint32_t* count;            // k_cone_count: cones per node
+    Cones out;
 };
 
-// The reflected axis of every node and its first surfel hit (t > t_eps): the
-// end of the march.
+// The cones of node i: count them, or write them from `base`.  A point IE
+// reflects: d' = d - 2 (d.n) n, separation plane normal n on the reflected
+// side.  An edge piece diffracts: Keller's cone of the directions d with
+// d.w = d_in.w is cut into N = max(1, ceil(2 pi sin(beta) / (2 half)))
+// sectors of azimuth 2 pi / N measured from the face-1 normal; a sector whose
+// middle direction leaves the wedge (v.n1 >= 0 or v.n2 >= 0) is a cone, with
+// the planes through the edge at its two bounding azimuths.
+__device__ uint32_t node_cones(const ExpandArgs& a, uint32_t i, bool write, uint32_t base) {
+#pragma clang fp contract(off)
+    const float4 A = a.gen.apex[i];
+    const float4 Pp = a.parent_pos[a.gen.parent[i]];
+    const uint32_t e = a.gen.ie[i];
+    float di[3] = {A.x - Pp.x, A.y - Pp.y, A.z - Pp.z};
+    const float li = 1.0f / sqrtf(di[0] * di[0] + di[1] * di[1] + di[2] * di[2]);
+    di[0] *= li; di[1] *= li; di[2] *= li;
+    if (a.type[e] == 0u) {
+        if (write) {
+            const float4 N = a.ie_nrm[e];
+            const float dn = di[0] * N.x + di[1] * N.y + di[2] * N.z;
+            float d[3] = {di[0] - 2.f * dn * N.x, di[1] - 2.f * dn * N.y, di[2] - 2.f * dn * N.z};
+            const float lo = 1.0f / sqrtf(d[0] * d[0] + d[1] * d[1] + d[2] * d[2]);
+            d[0] *= lo; d[1] *= lo; d[2] *= lo;
+            const float side = d[0] * N.x + d[1] * N.y + d[2] * N.z > 0.f ? 1.f : -1.f;
+            a.out.node[base] = i;
+            a.out.axis[base] = make_float4(d[0], d[1], d[2], 0.f);
+            a.out.s0[base] = make_float4(side * N.x, side * N.y, side * N.z, 0.f);
+            a.out.s1[base] = make_float4(0.f, 0.f, 0.f, 0.f);
+            a.out.kind[base] = 0u;
+        }
+        return 1u;
+    }
+    const uint32_t q = e - a.n_pt;
+    const float4 W = a.ew[q], N1 = a.en1[q], N2 = a.en2[q];
+    const float cb = di[0] * W.x + di[1] * W.y + di[2] * W.z;
+    const float sb = sqrtf(fmaxf(0.f, 1.f - cb * cb));
+    const float nw = N1.x * W.x + N1.y * W.y + N1.z * W.z;
+    float e1[3] = {N1.x - nw * W.x, N1.y - nw * W.y, N1.z - nw * W.z};
+    const float l1 = 1.0f / sqrtf(e1[0] * e1[0] + e1[1] * e1[1] + e1[2] * e1[2]);
+    e1[0] *= l1; e1[1] *= l1; e1[2] *= l1;
+    const float e2[3] = {W.y * e1[2] - W.z * e1[1], W.z * e1[0] - W.x * e1[2], W.x * e1[1] - W.y * e1[0]};
+    const float arg = 3.14159265358979f * sb / a.half;
+    const int N = max(1, (int)ceilf(arg));
+    const float dphi = 6.28318530717959f / (float)N;
+    uint32_t c = 0;
+    for (int k = 0; k < N; ++k) {
+        const float phi = ((float)k + 0.5f) * dphi;
+        const float cp = cosf(phi), sp = sinf(phi);
+        const float v[3] = {cp * e1[0] + sp * e2[0], cp * e1[1] + sp * e2[1], cp * e1[2] + sp * e2[2]};
+        const float x1 = v[0] * N1.x + v[1] * N1.y + v[2] * N1.z;
+        const float x2 = v[0] * N2.x + v[1] * N2.y + v[2] * N2.z;
+        if (fmaxf(x1, x2) < 0.f) continue;
+        if (write) {
+            float d[3] = {cb * W.x + sb * v[0], cb * W.y + sb * v[1], cb * W.z + sb * v[2]};
+            const float ld = 1.0f / sqrtf(d[0] * d[0] + d[1] * d[1] + d[2] * d[2]);
+            d[0] *= ld; d[1] *= ld; d[2] *= ld;
+            const float c0 = cosf((float)k * dphi), s0 = sinf((float)k * dphi);
+            const float c1 = cosf((float)(k + 1) * dphi), s1 = sinf((float)(k + 1) * dphi);
+            a.out.node[base + c] = i;
+            a.out.axis[base + c] = make_float4(d[0], d[1], d[2], 0.f);
+            a.out.s0[base + c] = make_float4(c0 * e2[0] - s0 * e1[0], c0 * e2[1] - s0 * e1[1],
+                                             c0 * e2[2] - s0 * e1[2], 0.f);
+            a.out.s1[base + c] = make_float4(c1 * e2[0] - s1 * e1[0], c1 * e2[1] - s1 * e1[1],
+                                             c1 * e2[2] - s1 * e1[2], 0.f);
+            a.out.kind[base + c] = N > 1 ? 1u : 2u;
+        }
+        ++c;
+    }
+    return c;
+}
+
+__global__ void k_cone_count(ExpandArgs a) {
+    const uint32_t i = blockIdx.x * blockDim.x + threadIdx.x;
+    if (i >= (uint32_t)a.gen.n) return;
+    a.count[i] = node_cones(a, i, false, 0u);
+}
+
+__global__ void k_cone_fill(ExpandArgs a) {
+    const uint32_t i = blockIdx.x * blockDim.x + threadIdx.x;
+    if (i >= (uint32_t)a.gen.n) return;
+    node_cones(a, i, true, a.offset[i]);
+}
+
+struct AxisArgs {
+    TraceArgs t;
+    const float4* apex;         // the generation's nodes
+    Cones cones;
+};
+
+// The first surfel hit (t > t_eps) of every cone's axis: the end of its march.
 template <int NL, bool BX>
 __global__ __launch_bounds__(TRACE_BLOCK) void k_axis(AxisArgs a) {
     __shared__ LeafTestLds lds[TRACE_BLOCK / 64];
@@ -314,7 +600,7 @@ __global__ __launch_bounds__(TRACE_BLOCK) void k_axis(AxisArgs a) {
     stat_t cnt[ST_COUNT] = {};
     const uint32_t wave = blockIdx.x * (TRACE_BLOCK / 64) + (threadIdx.x >> 6);
     const uint32_t n_waves = gridDim.x * (TRACE_BLOCK / 64);
-    const uint32_t n = (uint32_t)a.gen.n;
+    const uint32_t n = a.cones.n;
     for (uint32_t base = wave * 64; base < n; base += n_waves * 64) {
         const uint32_t i = base + lane_id();
         const bool act = i < n;
@@ -322,47 +608,38 @@ __global__ __launch_bounds__(TRACE_BLOCK) void k_axis(AxisArgs a) {
         Hit hit;
         hit_reset(hit);
         if (act) {
-            const float4 A = a.gen.apex[i];
-            const float4 Pp = a.parent_pos[a.gen.parent[i]];
-            const float4 N = a.ie_nrm[a.gen.ie[i]];
-            float di[3] = {A.x - Pp.x, A.y - Pp.y, A.z - Pp.z};
-            const float li = 1.0f / sqrtf(di[0] * di[0] + di[1] * di[1] + di[2] * di[2]);
-            di[0] *= li; di[1] *= li; di[2] *= li;
-            const float dn = di[0] * N.x + di[1] * N.y + di[2] * N.z;
-            d[0] = di[0] - 2.f * dn * N.x;
-            d[1] = di[1] - 2.f * dn * N.y;
-            d[2] = di[2] - 2.f * dn * N.z;
-            const float lo = 1.0f / sqrtf(d[0] * d[0] + d[1] * d[1] + d[2] * d[2]);
-            d[0] *= lo; d[1] *= lo; d[2] *= lo;
+            const float4 A = a.apex[a.cones.node[i]];
+            const float4 D = a.cones.axis[i];
             o[0] = A.x; o[1] = A.y; o[2] = A.z;
-            const float side = d[0] * N.x + d[1] * N.y + d[2] * N.z > 0.f ? 1.f : -1.f;
-            a.axis[i] = make_float4(d[0], d[1], d[2], 0.f);
-            a.plane[i] = make_float4(side * N.x, side * N.y, side * N.z, 0.f);
+            d[0] = D.x; d[1] = D.y; d[2] = D.z;
         }
         stage_ray(W, o, d, NO_HIT);
         trace_segment<false, NL, false, BX>(a.t, W, act, o, d, hit, cnt);
-        if (act) a.gen.t_end[i] = hit.id == NO_HIT ? INFINITY : hit.t;
+        if (act) a.cones.t_end[i] = hit.id == NO_HIT ? INFINITY : hit.t;
     }
 }
 
 // ---------------------------------------------------------------------------
-// cones (Section 2.2.4)
+// cone targets (Section 2.2.4)
 // ---------------------------------------------------------------------------
 
 struct ConeArgs {
     IeGrid g;
     Gen gen;
-    const float4* axis;
-    const float4* plane;
+    Cones cones;
     const uint2* vox;
+    const uint2* vox_e;   // null without edges
     const uint8_t* near;
     const float4* ie_pos;
     const int32_t* ie_sub;
+    const uint32_t* eid;
     const float4* rx;
     const int32_t* rx_sub;
     int32_t n_rx;
     int32_t want_ie;      // 0 at the last generation: RX targets only
+    int32_t max_diff;
     float cos_t, sin_t, R;
+    float tau;            // a reflected target lies in front of the separation plane by more than tau
     uint32_t cap;
     uint32_t* n_cand;     // counts every candidate, also beyond cap
     uint32_t* cand_node;
@@ -385,6 +662,19 @@ __device__ __forceinline__ bool cone_meets(const ConeArgs& a, const float o[3], 
     return dist <= a.R;
 }
 
+// The separation test of a target point p for cone q: in front of the
+// reflection's plane, or between the sector's two planes.
+__device__ __forceinline__ bool cone_separates(const ConeArgs& a, uint32_t q, const float o[3], float4 P) {
+    const uint32_t kind = a.cones.kind[q];
+    if (kind == 2u) return true;
+    const float4 S0 = a.cones.s0[q];
+    const float m0 = (P.x - o[0]) * S0.x + (P.y - o[1]) * S0.y + (P.z - o[2]) * S0.z;
+    if (kind == 0u) return m0 - a.tau > 0.f;
+    const float4 S1 = a.cones.s1[q];
+    const float m1 = (P.x - o[0]) * S1.x + (P.y - o[1]) * S1.y + (P.z - o[2]) * S1.z;
+    return m0 >= 0.f && m1 < 0.f;
+}
+
 __device__ __forceinline__ void cone_emit(const ConeArgs& a, uint32_t node, uint32_t target) {
     const uint32_t slot = atomicAdd(a.n_cand, 1u);
     if (slot < a.cap) {
@@ -393,31 +683,35 @@ __device__ __forceinline__ void cone_emit(const ConeArgs& a, uint32_t node, uint
     }
 }
 
-// The targets of voxel w (in the grid) for node i's cone.
-__device__ __forceinline__ void cone_voxel(const ConeArgs& a, uint32_t i, uint32_t own_ie, const float o[3],
-                                           const float d[3], const float n[3], int wx, int wy, int wz) {
+__device__ __forceinline__ void cone_range(const ConeArgs& a, uint32_t q, uint32_t node, uint32_t own_ie,
+                                           uint32_t own_edge, const float o[3], const float d[3], uint2 r) {
     const IeGrid& g = a.g;
-    if (wx < 0 || wy < 0 || wz < 0 || wx >= g.dims[0] || wy >= g.dims[1] || wz >= g.dims[2]) return;
-    const size_t w = (size_t)wx + (size_t)g.dims[0] * ((size_t)wy + (size_t)g.dims[1] * wz);
-    if (a.want_ie) {
-        const uint2 r = a.vox[w];
-        for (uint32_t e = r.x; e < r.x + r.y; ++e) {
-            if (e == own_ie) continue;
-            const int s0 = a.ie_sub[3 * (size_t)e], s1 = a.ie_sub[3 * (size_t)e + 1], s2 = a.ie_sub[3 * (size_t)e + 2];
-            const float cx = g.org[0] + ((float)s0 + 0.5f) * g.sv;
-            const float cy = g.org[1] + ((float)s1 + 0.5f) * g.sv;
-            const float cz = g.org[2] + ((float)s2 + 0.5f) * g.sv;
-            if (!cone_meets(a, o, d, cx, cy, cz)) continue;
-            const float4 P = a.ie_pos[e];
-            if (!((P.x - o[0]) * n[0] + (P.y - o[1]) * n[1] + (P.z - o[2]) * n[2] > 0.f)) continue;
-            cone_emit(a, i, e);
-        }
+    for (uint32_t e = r.x; e < r.x + r.y; ++e) {
+        if (e == own_ie || (own_edge != 0xFFFFFFFFu && a.eid[e] == own_edge)) continue;
+        const int s0 = a.ie_sub[3 * (size_t)e], s1 = a.ie_sub[3 * (size_t)e + 1], s2 = a.ie_sub[3 * (size_t)e + 2];
+        const float cx = g.org[0] + ((float)s0 + 0.5f) * g.sv;
+        const float cy = g.org[1] + ((float)s1 + 0.5f) * g.sv;
+        const float cz = g.org[2] + ((float)s2 + 0.5f) * g.sv;
+        if (!cone_meets(a, o, d, cx, cy, cz)) continue;
+        if (!cone_separates(a, q, o, a.ie_pos[e])) continue;
+        cone_emit(a, node, e);
     }
 }
 
-// The RX of voxel w (in the grid) for node i's cone.
-__device__ __forceinline__ void cone_voxel_rx(const ConeArgs& a, uint32_t i, const float o[3], const float d[3],
-                                              const float n[3], int wx, int wy, int wz) {
+// The IE targets of voxel w (in the grid) for cone q of node `node`.
+__device__ __forceinline__ void cone_voxel(const ConeArgs& a, uint32_t q, uint32_t node, uint32_t own_ie,
+                                           uint32_t own_edge, bool edges_ok, const float o[3], const float d[3],
+                                           int wx, int wy, int wz) {
+    const IeGrid& g = a.g;
+    if (wx < 0 || wy < 0 || wz < 0 || wx >= g.dims[0] || wy >= g.dims[1] || wz >= g.dims[2]) return;
+    const size_t w = (size_t)wx + (size_t)g.dims[0] * ((size_t)wy + (size_t)g.dims[1] * wz);
+    cone_range(a, q, node, own_ie, own_edge, o, d, a.vox[w]);
+    if (edges_ok) cone_range(a, q, node, own_ie, own_edge, o, d, a.vox_e[w]);
+}
+
+// The RX of voxel w (in the grid) for cone q of node `node`.
+__device__ __forceinline__ void cone_voxel_rx(const ConeArgs& a, uint32_t q, uint32_t node, const float o[3],
+                                              const float d[3], int wx, int wy, int wz) {
     const IeGrid& g = a.g;
     for (int j = 0; j < a.n_rx; ++j) {
         const int s0 = a.rx_sub[3 * j], s1 = a.rx_sub[3 * j + 1], s2 = a.rx_sub[3 * j + 2];
@@ -426,56 +720,59 @@ __device__ __forceinline__ void cone_voxel_rx(const ConeArgs& a, uint32_t i, con
         const float cy = g.org[1] + ((float)s1 + 0.5f) * g.sv;
         const float cz = g.org[2] + ((float)s2 + 0.5f) * g.sv;
         if (!cone_meets(a, o, d, cx, cy, cz)) continue;
-        const float4 P = a.rx[j];
-        if (!((P.x - o[0]) * n[0] + (P.y - o[1]) * n[1] + (P.z - o[2]) * n[2] > 0.f)) continue;
-        cone_emit(a, i, RX_BIT | (uint32_t)j);
+        if (!cone_separates(a, q, o, a.rx[j])) continue;
+        cone_emit(a, node, RX_BIT | (uint32_t)j);
     }
 }
 
-// One node per thread: march the axis voxel by voxel (Amanatides and Woo;
+// One cone per thread: march the axis voxel by voxel (Amanatides and Woo;
 // every boundary distance computed from the origin, no accumulation) up to
 // the voxel holding t_end; at every voxel the neighbours it adds to the
 // union of 3x3x3 blocks along the march are evaluated (all 27 at the first
 // voxel, then the 9 of the block's leading face along the step's axis).
-// Voxels with no IE within one voxel add nothing and are only crossed.
+// IE targets only where the block holds some (the march distance); the RX
+// always.  Edge pieces only below the diffraction limit, never of the node's
+// own edge.
 __global__ __launch_bounds__(CONE_BLOCK) void k_cones(ConeArgs a) {
-    const uint32_t i = blockIdx.x * blockDim.x + threadIdx.x;
-    if (i >= (uint32_t)a.gen.n) return;
+    const uint32_t q = blockIdx.x * blockDim.x + threadIdx.x;
+    if (q >= a.cones.n) return;
     const IeGrid& g = a.g;
-    const float4 A = a.gen.apex[i];
-    const float4 D = a.axis[i];
-    const float4 N = a.plane[i];
-    const float o[3] = {A.x, A.y, A.z}, d[3] = {D.x, D.y, D.z}, n[3] = {N.x, N.y, N.z};
-    const uint32_t own = a.gen.ie[i];
-    const float t_end = a.gen.t_end[i];
+    const uint32_t node = a.cones.node[q];
+    const float4 A = a.gen.apex[node];
+    const float4 D = a.cones.axis[q];
+    const float o[3] = {A.x, A.y, A.z}, d[3] = {D.x, D.y, D.z};
+    const uint32_t own = a.gen.ie[node];
+    const uint32_t own_edge = a.eid[own];
+    const bool edges_ok = a.vox_e && (int32_t)a.gen.ndiff[node] < a.max_diff;
+    const float t_end = a.cones.t_end[q];
     int c[3];
 #pragma unroll
     for (int k = 0; k < 3; ++k) c[k] = min(max((int)floorf((o[k] - g.org[k]) / g.V), 0), g.dims[k] - 1);
     int step_axis = -1;
     for (int it = 0; it < g.dims[0] + g.dims[1] + g.dims[2] + 3; ++it) {
         const size_t cv = (size_t)c[0] + (size_t)g.dims[0] * ((size_t)c[1] + (size_t)g.dims[1] * c[2]);
-        // IEs only where the block holds some (the march distance); the RX always
         const bool ies_near = a.want_ie && a.near[cv];
         if (ies_near || a.n_rx > 0) {
             if (step_axis < 0) {
                 for (int dz = -1; dz <= 1; ++dz)
                     for (int dy = -1; dy <= 1; ++dy)
                         for (int dx = -1; dx <= 1; ++dx) {
-                            if (ies_near) cone_voxel(a, i, own, o, d, n, c[0] + dx, c[1] + dy, c[2] + dz);
-                            cone_voxel_rx(a, i, o, d, n, c[0] + dx, c[1] + dy, c[2] + dz);
+                            if (ies_near)
+                                cone_voxel(a, q, node, own, own_edge, edges_ok, o, d, c[0] + dx, c[1] + dy, c[2] + dz);
+                            cone_voxel_rx(a, q, node, o, d, c[0] + dx, c[1] + dy, c[2] + dz);
                         }
             } else {
                 // the block's leading face along the step: the voxels the previous blocks did not hold
                 const int sg = d[step_axis] > 0.f ? 1 : -1;
                 const int a1 = step_axis == 0 ? 1 : 0, a2 = step_axis == 2 ? 1 : 2;
                 for (int p = -1; p <= 1; ++p)
-                    for (int q = -1; q <= 1; ++q) {
+                    for (int r = -1; r <= 1; ++r) {
                         int w[3] = {c[0], c[1], c[2]};
                         w[step_axis] += sg;
                         w[a1] += p;
-                        w[a2] += q;
-                        if (ies_near) cone_voxel(a, i, own, o, d, n, w[0], w[1], w[2]);
-                        cone_voxel_rx(a, i, o, d, n, w[0], w[1], w[2]);
+                        w[a2] += r;
+                        if (ies_near) cone_voxel(a, q, node, own, own_edge, edges_ok, o, d, w[0], w[1], w[2]);
+                        cone_voxel_rx(a, q, node, o, d, w[0], w[1], w[2]);
                     }
             }
         }
@@ -598,7 +895,9 @@ struct NodeArgs {
     const uint64_t* prio;
     const float4* parent_pos;
     const uint32_t* parent_tx;   // null for k = 0 (the parent is the TX)
+    const uint32_t* parent_ndiff;// null for k = 0
     const float4* ie_pos;
+    const uint32_t* ie_type;
     Gen out;
 };
 
@@ -618,6 +917,7 @@ __global__ void k_make_nodes(NodeArgs a) {
     a.out.tx[s] = a.parent_tx ? a.parent_tx[p] : p;
     a.out.gid[s] = a.group[i] + a.newgroup[i] - 1u;
     a.out.prio[s] = a.prio[c];
+    a.out.ndiff[s] = (a.parent_ndiff ? a.parent_ndiff[p] : 0u) + a.ie_type[e];
 }
 
 // ---------------------------------------------------------------------------
@@ -707,10 +1007,14 @@ static int ie_build_impl(PcrlScene* S, const PcrlIeGrid* params, hipStream_t s, 
             return fail(rc);
         hipLaunchKernelGGL(k_ie_reduce, dim3(blocks(n)), dim3(256), 0, s, key, id, flag, n, S->own_pos, S->own_nrm, g,
                            n_ie, I->key, I->sub, I->label, I->count, I->pos, I->nrm);
+        if ((rc = I->bufs.alloc(&I->type, n_ie)) || (rc = I->bufs.alloc(&I->eid, n_ie)) ||
+            (rc = fill_u32(I->type, 0u, n_ie, s)) || (rc = fill_u32(I->eid, 0xFFFFFFFFu, n_ie, s)))
+            return fail(rc);
         hipLaunchKernelGGL(k_ie_voxels, dim3(blocks(n_ie)), dim3(256), 0, s, I->key, n_ie, g.dv * g.dv * g.dv,
                            I->vox);
     }
-    hipLaunchKernelGGL(k_ie_near, dim3(blocks(I->n_vox)), dim3(256), 0, s, I->vox, g, (uint32_t)I->n_vox, I->near);
+    hipLaunchKernelGGL(k_ie_near, dim3(blocks(I->n_vox)), dim3(256), 0, s, I->vox, (const uint2*)nullptr, g,
+                       (uint32_t)I->n_vox, I->near);
     if (hipGetLastError() != hipSuccess || hipStreamSynchronize(s) != hipSuccess) {
         set_error("ie_build: kernels failed: %s", hipGetErrorString(hipGetLastError()));
         return fail(PCRL_EHIP);
@@ -723,8 +1027,115 @@ static int ie_build_impl(PcrlScene* S, const PcrlIeGrid* params, hipStream_t s, 
         return fail(PCRL_EHIP);
     }
     for (const uint2& r : hv) I->n_occ += r.y ? 1 : 0;
-    I->bytes = I->n_ie * (8 + 12 + 4 + 4 + 32) + I->n_vox * 9;
+    I->n_pt = I->n_ie;
+    I->bytes = I->n_ie * (8 + 12 + 4 + 4 + 32 + 8) + I->n_vox * 9;
     *out = I.release();
+    return PCRL_OK;
+}
+
+static int ie_add_edges_impl(PcrlIes* I, const float* seg, const float* nrm, const uint32_t* label, int64_t n_edges,
+                             hipStream_t s) {
+    if (I->n_edges) {
+        set_error("ie_add_edges: the table already has edges");
+        return PCRL_EINVAL;
+    }
+    if (n_edges == 0) return PCRL_OK;
+    const IeGrid g = I->g;
+    DevBufs T;
+    T.stream = s;
+    auto fail = [&](int rc) { T.release(); return rc; };
+    const uint32_t n = (uint32_t)n_edges;
+    uint32_t *cnt = nullptr, *bad = nullptr;
+    int rc;
+    if ((rc = T.alloc(&cnt, (size_t)n + 1)) || (rc = T.alloc(&bad, 1)) || (rc = fill_u32(bad, 0u, 1, s)))
+        return fail(rc);
+    EdgeArgs A{seg, nrm, label, n, g, cnt, cnt, bad, nullptr, nullptr, nullptr, nullptr};
+    hipLaunchKernelGGL(k_edge_count, dim3(blocks(n)), dim3(256), 0, s, A);
+    if ((rc = scan_u32(cnt, cnt, n, cnt + n, s))) return fail(rc);
+    uint32_t P = 0, h_bad = 0;
+    if ((rc = read_u32(cnt + n, &P, s)) || (rc = read_u32(bad, &h_bad, s))) return fail(rc);
+    if (h_bad) {
+        set_error("ie_add_edges: %u edges have zero length", h_bad);
+        return fail(PCRL_EINVAL);
+    }
+    // counts again (the scan replaced them) for the write pass
+    uint32_t* cnt2 = nullptr;
+    uint64_t* key = nullptr;
+    uint32_t *edge = nullptr, *perm = nullptr;
+    int32_t* sub = nullptr;
+    float4* pos = nullptr;
+    if ((rc = T.alloc(&cnt2, n)) || (rc = T.alloc(&key, P)) || (rc = T.alloc(&edge, P)) || (rc = T.alloc(&perm, P)) ||
+        (rc = T.alloc(&sub, (size_t)P * 3)) || (rc = T.alloc(&pos, P)))
+        return fail(rc);
+    EdgeArgs C{seg, nrm, label, n, g, cnt, cnt2, bad, key, edge, sub, pos};
+    hipLaunchKernelGGL(k_edge_count, dim3(blocks(n)), dim3(256), 0, s, C);
+    hipLaunchKernelGGL(k_edge_write, dim3(blocks(n)), dim3(256), 0, s, C);
+    if ((rc = read_u32(bad, &h_bad, s))) return fail(rc);
+    if (h_bad) {
+        set_error("ie_add_edges: %u edge pieces lie outside the IE grid", h_bad);
+        return fail(PCRL_EINVAL);
+    }
+    // stable sort of the (edge, t)-ordered pieces by key: (key, edge) order
+    if ((rc = iota_u32(perm, P, s))) return fail(rc);
+    int bits = 1;
+    const uint64_t max_cell = (uint64_t)I->n_vox * (uint64_t)(g.dv * g.dv * g.dv);
+    while (bits < 32 && (max_cell >> bits)) ++bits;
+    if ((rc = radix_sort_u64(key, perm, P, 32 + bits, s))) return fail(rc);
+    // the combined arrays
+    const uint32_t n_pt = (uint32_t)I->n_pt, N = n_pt + P;
+    uint64_t* nkey = nullptr;
+    int32_t* nsub = nullptr;
+    uint32_t *nlabel = nullptr, *ncount = nullptr, *ntype = nullptr, *neid = nullptr;
+    float4 *npos = nullptr, *nnrm = nullptr, *ew = nullptr, *en1 = nullptr, *en2 = nullptr;
+    uint2* vox_e = nullptr;
+    DevBufs& B = I->bufs;
+    if ((rc = B.alloc(&nkey, N)) || (rc = B.alloc(&nsub, (size_t)N * 3)) || (rc = B.alloc(&nlabel, N)) ||
+        (rc = B.alloc(&ncount, N)) || (rc = B.alloc(&ntype, N)) || (rc = B.alloc(&neid, N)) ||
+        (rc = B.alloc(&npos, N)) || (rc = B.alloc(&nnrm, N)) || (rc = B.alloc(&ew, P)) || (rc = B.alloc(&en1, P)) ||
+        (rc = B.alloc(&en2, P)) || (rc = B.alloc(&vox_e, (size_t)I->n_vox)))
+        return fail(rc);
+    hipError_t e = hipSuccess;
+    if (n_pt) {
+        e = hipMemcpyAsync(nkey, I->key, (size_t)n_pt * 8, hipMemcpyDeviceToDevice, s);
+        if (e == hipSuccess) e = hipMemcpyAsync(nsub, I->sub, (size_t)n_pt * 12, hipMemcpyDeviceToDevice, s);
+        if (e == hipSuccess) e = hipMemcpyAsync(nlabel, I->label, (size_t)n_pt * 4, hipMemcpyDeviceToDevice, s);
+        if (e == hipSuccess) e = hipMemcpyAsync(ncount, I->count, (size_t)n_pt * 4, hipMemcpyDeviceToDevice, s);
+        if (e == hipSuccess) e = hipMemcpyAsync(ntype, I->type, (size_t)n_pt * 4, hipMemcpyDeviceToDevice, s);
+        if (e == hipSuccess) e = hipMemcpyAsync(neid, I->eid, (size_t)n_pt * 4, hipMemcpyDeviceToDevice, s);
+        if (e == hipSuccess) e = hipMemcpyAsync(npos, I->pos, (size_t)n_pt * 16, hipMemcpyDeviceToDevice, s);
+        if (e == hipSuccess) e = hipMemcpyAsync(nnrm, I->nrm, (size_t)n_pt * 16, hipMemcpyDeviceToDevice, s);
+    }
+    if (e != hipSuccess) {
+        set_error("ie_add_edges: copy failed: %s", hipGetErrorString(e));
+        return fail(PCRL_EHIP);
+    }
+    EdgeAppend ap{perm, P, n_pt, key, edge, sub, pos, seg, nrm, nkey, nsub, nlabel, ncount, npos, nnrm, ntype, neid,
+                  ew, en1, en2};
+    hipLaunchKernelGGL(k_edge_append, dim3(blocks(P)), dim3(256), 0, s, ap);
+    if ((rc = fill_u32((uint32_t*)vox_e, 0u, 2 * I->n_vox, s))) return fail(rc);
+    hipLaunchKernelGGL(k_edge_voxels, dim3(blocks(P)), dim3(256), 0, s, nkey, n_pt, N, g.dv * g.dv * g.dv, vox_e);
+    hipLaunchKernelGGL(k_ie_near, dim3(blocks(I->n_vox)), dim3(256), 0, s, I->vox, (const uint2*)vox_e, g,
+                       (uint32_t)I->n_vox, I->near);
+    if (hipGetLastError() != hipSuccess || hipStreamSynchronize(s) != hipSuccess) {
+        set_error("ie_add_edges: kernels failed: %s", hipGetErrorString(hipGetLastError()));
+        return fail(PCRL_EHIP);
+    }
+    I->key = nkey;
+    I->sub = nsub;
+    I->label = nlabel;
+    I->count = ncount;
+    I->type = ntype;
+    I->eid = neid;
+    I->pos = npos;
+    I->nrm = nnrm;
+    I->ew = ew;
+    I->en1 = en1;
+    I->en2 = en2;
+    I->vox_e = vox_e;
+    I->n_ie = N;
+    I->n_edges = P;
+    I->bytes += (int64_t)P * (8 + 12 + 4 + 4 + 32 + 8 + 48) + I->n_vox * 8;
+    T.release();
     return PCRL_OK;
 }
 
@@ -736,7 +1147,7 @@ static void launch_vis(const VisArgs& a, hipStream_t s) {
 
 template <int NL, bool BX>
 static void launch_axis(const AxisArgs& a, hipStream_t s) {
-    const unsigned grid = (unsigned)std::min<int64_t>(blocks(a.gen.n, TRACE_BLOCK), (int64_t)device_cus() * 16);
+    const unsigned grid = (unsigned)std::min<int64_t>(blocks(a.cones.n, TRACE_BLOCK), (int64_t)device_cus() * 16);
     hipLaunchKernelGGL((k_axis<NL, BX>), dim3(grid), dim3(TRACE_BLOCK), 0, s, a);
 }
 
@@ -763,7 +1174,7 @@ static void run_vis(const VisArgs& a, hipStream_t s) {
 }
 
 static void run_axis(const AxisArgs& a, hipStream_t s) {
-    if (a.gen.n == 0) return;
+    if (a.cones.n == 0) return;
     switch (a.t.v.nlev) {
     case 1: dispatch_axis<1>(a, s); break;
     case 2: dispatch_axis<2>(a, s); break;
@@ -808,7 +1219,7 @@ __global__ void k_root_prio(uint32_t n_tx, uint64_t* prio, uint32_t* gid) {
 // Children of the visible IE candidates -> merged, sorted generation.
 static int make_generation(PcrlConeLaunch* L, uint32_t n_child, const uint32_t* child_node, const uint32_t* child_ie,
                            const uint32_t* parent_gid, const uint64_t* parent_prio, const float4* parent_pos,
-                           const uint32_t* parent_tx, Gen& out, hipStream_t s) {
+                           const uint32_t* parent_tx, const uint32_t* parent_ndiff, Gen& out, hipStream_t s) {
     const PcrlIes* I = L->ies;
     DevBufs T;
     T.stream = s;
@@ -843,10 +1254,11 @@ static int make_generation(PcrlConeLaunch* L, uint32_t n_child, const uint32_t* 
     DevBufs& B = L->bufs;
     if ((rc = B.alloc(&out.apex, n_keep)) || (rc = B.alloc(&out.ie, n_keep)) || (rc = B.alloc(&out.parent, n_keep)) ||
         (rc = B.alloc(&out.tx, n_keep)) || (rc = B.alloc(&out.gid, n_keep)) || (rc = B.alloc(&out.prio, n_keep)) ||
-        (rc = B.alloc(&out.t_end, n_keep)))
+        (rc = B.alloc(&out.ndiff, n_keep)))
         return fail(rc);
     out.n = n_keep;
-    NodeArgs na{n, perm, keep, grp, newg, child_node, child_ie, prio, parent_pos, parent_tx, I->pos, out};
+    NodeArgs na{n, perm, keep, grp, newg, child_node, child_ie, prio, parent_pos, parent_tx, parent_ndiff, I->pos,
+                I->type, out};
     hipLaunchKernelGGL(k_make_nodes, dim3(blocks(n)), dim3(256), 0, s, na);
     if (hipGetLastError() != hipSuccess) {
         set_error("cone_launch: merge kernels failed");
@@ -915,7 +1327,10 @@ static int cone_launch_impl(const PcrlIes* I, const float* tx, int32_t n_tx, con
     };
     const double t0 = now_ms();
     // ---- transmission phase: every TX towards every IE and RX
-    const uint64_t n_t = (uint64_t)I->n_ie + (uint64_t)n_rx;
+    // edge pieces are targets only when diffraction is allowed
+    const int32_t max_diff = P->max_diffractions;
+    const uint64_t n_tie = max_diff > 0 ? (uint64_t)I->n_ie : (uint64_t)I->n_pt;
+    const uint64_t n_t = n_tie + (uint64_t)n_rx;
     const uint64_t n_pairs = (uint64_t)n_tx * n_t;
     if (n_pairs >= ((uint64_t)1 << 31)) {
         set_error("cone_launch: %llu transmission rays exceed 2^31", (unsigned long long)n_pairs);
@@ -932,7 +1347,7 @@ static int cone_launch_impl(const PcrlIes* I, const float* tx, int32_t n_tx, con
             (rc = T.alloc(&child_ie, std::max(n, 1u))) || (rc = T.alloc(&rec, std::max<uint32_t>(n_tx * n_rx, 1u))))
             return fail(rc);
         if (n) hipLaunchKernelGGL(k_pairs, dim3(blocks(n)), dim3(256), 0, s, (uint32_t)n_tx, (uint32_t)n_t,
-                                  (uint32_t)I->n_ie, node, target);
+                                  (uint32_t)n_tie, node, target);
         va.origin = L->tx;
         va.cand_node = node;
         va.cand_target = target;
@@ -960,20 +1375,35 @@ static int cone_launch_impl(const PcrlIes* I, const float* tx, int32_t n_tx, con
     const uint64_t* p_prio = root_prio;
     const float4* p_pos = L->tx;
     const uint32_t* p_tx = nullptr;
+    const uint32_t* p_ndiff = nullptr;
     const float cos_t = cosf(half), sin_t = sinf(half);
     const float R = I->g.sv * sqrtf(3.0f) * 0.5f;
     for (int k = 1; k <= K; ++k) {
         Gen& G = L->gens[k];
-        if ((rc = make_generation(L.get(), n_child, child_node, child_ie, p_gid, p_prio, p_pos, p_tx, G, s)))
+        if ((rc = make_generation(L.get(), n_child, child_node, child_ie, p_gid, p_prio, p_pos, p_tx, p_ndiff, G,
+                                  s)))
             return fail(rc);
         L->stats.nodes[k] = G.n;
         if (G.n == 0) break;
-        float4 *axis = nullptr, *plane = nullptr;
-        if ((rc = T.alloc(&axis, G.n)) || (rc = T.alloc(&plane, G.n))) return fail(rc);
-        AxisArgs aa{ta, G, p_pos, I->nrm, axis, plane};
+        // the generation's cones: count per node, scan, fill
+        Cones cs;
+        uint32_t* ccount = nullptr;
+        if ((rc = T.alloc(&ccount, (size_t)G.n + 1))) return fail(rc);
+        ExpandArgs ea{G, p_pos, I->type, I->nrm, I->ew, I->en1, I->en2, (uint32_t)I->n_pt, half, ccount, ccount, cs};
+        hipLaunchKernelGGL(k_cone_count, dim3(blocks(G.n)), dim3(256), 0, s, ea);
+        if ((rc = scan_u32(ccount, ccount, G.n, ccount + G.n, s))) return fail(rc);
+        if ((rc = read_u32(ccount + G.n, &cs.n, s))) return fail(rc);
+        if (cs.n == 0) break;
+        if ((rc = T.alloc(&cs.node, cs.n)) || (rc = T.alloc(&cs.axis, cs.n)) || (rc = T.alloc(&cs.s0, cs.n)) ||
+            (rc = T.alloc(&cs.s1, cs.n)) || (rc = T.alloc(&cs.kind, cs.n)) || (rc = T.alloc(&cs.t_end, cs.n)))
+            return fail(rc);
+        ea.out = cs;
+        hipLaunchKernelGGL(k_cone_fill, dim3(blocks(G.n)), dim3(256), 0, s, ea);
+        L->stats.cones[k] = cs.n;
+        AxisArgs aa{ta, G.apex, cs};
         run_axis(aa, s);
         // candidates: a first guess, then exactly what the kernel counted
-        uint32_t cap = (uint32_t)std::min<int64_t>((int64_t)G.n * 64 + 1024, (int64_t)1 << 30);
+        uint32_t cap = (uint32_t)std::min<int64_t>((int64_t)cs.n * 64 + 1024, (int64_t)1 << 30);
         uint32_t *cnode = nullptr, *ctarget = nullptr;
         uint32_t n_cand = 0;
         for (int attempt = 0; attempt < 2; ++attempt) {
@@ -982,9 +1412,11 @@ static int cone_launch_impl(const PcrlIes* I, const float* tx, int32_t n_tx, con
             ConeArgs c{};
             c.g = I->g;
             c.gen = G;
-            c.axis = axis;
-            c.plane = plane;
+            c.cones = cs;
             c.vox = I->vox;
+            c.vox_e = I->vox_e;
+            c.eid = I->eid;
+            c.max_diff = max_diff;
             c.near = I->near;
             c.ie_pos = I->pos;
             c.ie_sub = I->sub;
@@ -994,12 +1426,13 @@ static int cone_launch_impl(const PcrlIes* I, const float* tx, int32_t n_tx, con
             c.want_ie = k < K ? 1 : 0;
             c.cos_t = cos_t;
             c.sin_t = sin_t;
+            c.tau = 1e-3f * I->g.sv;
             c.R = R;
             c.cap = cap;
             c.n_cand = counters;
             c.cand_node = cnode;
             c.cand_target = ctarget;
-            hipLaunchKernelGGL(k_cones, dim3(blocks(G.n, CONE_BLOCK)), dim3(CONE_BLOCK), 0, s, c);
+            hipLaunchKernelGGL(k_cones, dim3(blocks(cs.n, CONE_BLOCK)), dim3(CONE_BLOCK), 0, s, c);
             if (hipGetLastError() != hipSuccess || read_u32(counters, &n_cand, s)) {
                 set_error("cone_launch: cone kernel failed: %s", hipGetErrorString(hipGetLastError()));
                 return fail(PCRL_EHIP);
@@ -1043,6 +1476,7 @@ static int cone_launch_impl(const PcrlIes* I, const float* tx, int32_t n_tx, con
         p_prio = G.prio;
         p_pos = G.apex;
         p_tx = G.tx;
+        p_ndiff = G.ndiff;
     }
     L->stats.ms_propagation = now_ms() - t1;
     L->n_rec = (int64_t)recs.size();
@@ -1228,6 +1662,16 @@ extern "C" int ie_build(PcrlScene* scene, const PcrlIeGrid* grid, pcrl_stream_t 
     return ie_build_impl(scene, grid, (hipStream_t)stream, out);
 }
 
+extern "C" int ie_add_edges(PcrlIes* ies, const float* seg, const float* normals, const uint32_t* label,
+                            int64_t n_edges, pcrl_stream_t stream) {
+    clear_error();
+    if (!ies || n_edges < 0 || n_edges >= ((int64_t)1 << 31) || (n_edges > 0 && (!seg || !normals || !label))) {
+        set_error("ie_add_edges: need an IE table, 0 <= n_edges < 2^31 and the three arrays");
+        return PCRL_EINVAL;
+    }
+    return ie_add_edges_impl(ies, seg, normals, label, n_edges, (hipStream_t)stream);
+}
+
 extern "C" int ie_info(const PcrlIes* ies, PcrlIeInfo* out) {
     clear_error();
     if (!ies || !out) {
@@ -1235,6 +1679,7 @@ extern "C" int ie_info(const PcrlIes* ies, PcrlIeInfo* out) {
         return PCRL_EINVAL;
     }
     out->n_ies = ies->n_ie;
+    out->n_edge_ies = ies->n_edges;
     out->n_voxels = ies->n_vox;
     out->n_occupied = ies->n_occ;
     out->device_bytes = ies->bytes;
@@ -1278,7 +1723,7 @@ extern "C" int cone_launch(const PcrlIes* ies, const float* tx, int32_t n_tx, co
     clear_error();
     if (!ies || !params || !out || !tx || n_tx < 1 || n_tx > 255 || n_rx < 0 || n_rx > 65535 || (n_rx > 0 && !rx) ||
         params->max_interactions < 0 || params->max_interactions > PCRL_MAX_REFLECTIONS ||
-        !(params->half_angle <= (float)(M_PI / 4)) || params->flags != 0) {
+        !(params->half_angle <= (float)(M_PI / 4)) || params->flags != 0 || params->max_diffractions < 0) {
         set_error("cone_launch: need IEs, 1 <= n_tx <= 255 TX, 0 <= n_rx <= 65535 RX, 0 <= max_interactions <= %d, "
                   "half_angle <= pi/4 and flags 0", PCRL_MAX_REFLECTIONS);
         return PCRL_EINVAL;

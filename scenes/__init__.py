@@ -393,13 +393,14 @@ def box_edges(lo, hi, label, top=True, vertical=True):
             (label + np.arange(n)).astype(np.uint32))
 
 
-def corner_building(h=0.1, tx=(-3.0, 5.0, 1.5), rx=(5.0, -3.0, 1.5), n_rays=20_000, K=2, levels=(0.4, 0.2, 0.1)):
-    """A 20 x 20 m ground (label 0) and one building [0,6] x [0,6] x [0,4]
+def corner_building(h=0.1, tx=(-3.0, 5.0, 1.5), rx=(5.0, -3.0, 1.5), n_rays=20_000, K=2, levels=(0.4, 0.2, 0.1),
+                    ground=10.0):
+    """A ground of 2 ``ground`` x 2 ``ground`` m (label 0) and one building [0,6] x [0,6] x [0,4]
     (roof 1, faces x=0: 2, x=6: 3, y=0: 4, y=6: 5; outward normals) with its
     eight convex edges (labels 100..107) in ``extra['edges']``.  The default RX
     lies in the building's shadow seen from the TX: no line of sight and no
     reflection reaches it; the vertical edge at (0, 0) diffracts towards it."""
-    faces = [(np.array([-10.0, -10.0, 0.0]), np.array([20.0, 0.0, 0.0]), np.array([0.0, 20.0, 0.0]),
+    faces = [(np.array([-ground, -ground, 0.0]), np.array([2 * ground, 0.0, 0.0]), np.array([0.0, 2 * ground, 0.0]),
               np.array([0.0, 0.0, 1.0]), 0)]
     faces += _box_faces((0.0, 0.0, 0.0), (6.0, 6.0, 4.0), label=(0, 1, 2, 3, 4, 5), inward=False, bottom=False)
     xyz, nrm, lab = _sample_faces(faces, h)

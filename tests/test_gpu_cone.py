@@ -58,27 +58,43 @@ def _gpu_chains(L, K):
     return out
 
 
-def _case(env, s, K, voxel=0.5, dv=2, kappa=1 << 30, grid=None):
+def _case(env, s, K, voxel=0.5, dv=2, kappa=1 << 30, grid=None, max_diff=0):
     torch, pcrl, cone = env
     t_eps = float(np.float32(parity.t_eps_of(s)))
     r_s = float(np.float32(s.surfel_radius))
     origin, dims = grid if grid is not None else _grid(np.vstack([s.xyz, s.tx, s.rx]), voxel)
-    print(f"[cone] {s.name}: {s.n_points} points, K={K}, grid {tuple(dims)} x {voxel} m / {dv}", flush=True)
+    E = s.extra.get("edges")
+    print(f"[cone] {s.name}: {s.n_points} points, {0 if E is None else len(E['seg'])} edges, K={K}, "
+          f"diffractions <= {max_diff}, grid {tuple(dims)} x {voxel} m / {dv}", flush=True)
     scene = pcrl.build_voxels(s.xyz, s.normal, s.label, s.levels, r_s, t_eps=t_eps)
     ies = pcrl.ie_build(scene, origin, voxel, dv, dims)
-    L = pcrl.cone_launch(ies, s.tx, s.rx, K, HALF)
+    if E is not None:
+        ies.add_edges(E["seg"], E["normals"], E["label"])
+    L = pcrl.cone_launch(ies, s.tx, s.rx, K, HALF, max_diffractions=max_diff)
     st = L.stats()
-    print(f"[cone] device: {st['nodes']} nodes, {st['candidates']} candidates, {st['records']} records", flush=True)
+    print(f"[cone] device: {st['nodes']} nodes, {st['cones']} cones, {st['candidates']} candidates, "
+          f"{st['records']} records", flush=True)
     oie = cone.ie_build(s.xyz, s.normal, s.label, origin, voxel, dv, dims)
+    oedge = None if E is None else cone.edge_ies(E["seg"], E["normals"], E["label"], origin, voxel, dv, dims)
     bands = parity.fp32_bands(s.xyz, s.tx, s.rx)
     sc = cone.Scene(s.xyz, s.normal, s.label, r_s, t_eps, parity=True, **bands)
-    ref = cone.trace(sc, oie, s.tx, s.rx, origin, voxel, dv, dims, K=K, kappa=kappa, half_angle=HALF)
+    ref = cone.trace(sc, oie, s.tx, s.rx, origin, voxel, dv, dims, K=K, kappa=kappa, half_angle=HALF,
+                     edges=oedge, max_diff=max_diff)
+    ref["edge_ies"] = oedge
     print(f"[cone] oracle: {[len(n) for n in ref['nodes']]} nodes, {len(ref['records'])} records", flush=True)
     return scene, ies, L, oie, ref
 
 
-def _compare_ies(ies, oie):
+def _compare_ies(ies, oie, oedge=None):
     t = {k: v.cpu().numpy() for k, v in ies.table().items()}
+    n_pt = len(oie["key"])
+    if oedge is not None:
+        e = {k: v[n_pt:] for k, v in t.items()}
+        assert np.array_equal(e["key"].view(np.uint64).astype(np.int64), oedge["key"])
+        assert np.array_equal(e["sub"], oedge["sub"])
+        assert np.array_equal(e["pos"].astype(np.float64), oedge["pos"])     # the same FP32 operations
+        assert np.array_equal(e["label"].view(np.uint32).astype(np.int64), oedge["label"])
+    t = {k: v[:n_pt] for k, v in t.items()}
     assert np.array_equal(t["key"].view(np.uint64).astype(np.int64), oie["key"])
     assert np.array_equal(t["count"], oie["count"])
     assert np.array_equal(t["sub"], oie["sub"])
@@ -208,3 +224,30 @@ def test_cone_edge_cases(env):
     assert abs(float(p["len_poly"][0]) - math.sqrt(34.0)) <= 1e-6 * math.sqrt(34.0)
     with pytest.raises(pcrl.PcrlError):
         pcrl.ie_build(scene, origin + 1.0, 0.5, 2, dims)
+
+
+@pytest.mark.parametrize("K", [1, 2])
+def test_cone_corner_diffraction(env, K):
+    """Diffraction at the building's convex edges (one diffraction per path): IE
+    tables with the edge pieces, every generation and every reception against
+    the oracle; the shadowed RX is reached through the vertical corner edge
+    (label 100) with a polyline no shorter than the exact diffraction path."""
+    torch, pcrl, cone = env
+    s = scenes.corner_building()
+    scene, ies, L, oie, ref = _case(env, s, K=K, voxel=0.4, dv=2, max_diff=1)
+    _compare_ies(ies, oie, ref["edge_ies"])
+    gpu = _gpu_chains(L, K)
+    _compare_nodes(gpu, ref)
+    res = _compare_paths(env, L, gpu, ref, K)
+    keys = {(int(res["n_refl"][i]), tuple(int(x) for x in res["key"][i, :int(res["n_refl"][i])]))
+            for i in range(res["n_rows"])}
+    assert (1, (100,)) in keys
+    L_star = 2.0 * math.sqrt(34.0)
+    for i in range(res["n_rows"]):
+        if int(res["n_refl"][i]) == 1 and int(res["key"][i, 0]) == 100:
+            assert L_star * (1 - 1e-6) <= float(res["len_poly"][i]) <= L_star + 0.02
+    if K == 1:
+        assert keys == {(1, (100,))}
+    # without diffraction nothing reaches the shadowed RX
+    L0 = pcrl.cone_launch(ies, s.tx, s.rx, K, HALF, max_diffractions=0)
+    assert pcrl.cone_collect(L0)["n_rows"] == 0
