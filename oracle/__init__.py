@@ -92,6 +92,8 @@ class OracleRefineArgs(C.Structure):
         ("n_threads", C.c_int32),
         ("status", C.c_void_p), ("iters", C.c_void_p), ("grad", C.c_void_p), ("length", C.c_void_p),
         ("out_pts", C.c_void_p), ("out_id", C.c_void_p), ("out_label", C.c_void_p),
+        ("edge_of", C.c_void_p), ("n_edges", C.c_int32), ("edge_seg", C.c_void_p), ("edge_nrm", C.c_void_p),
+        ("edge_label", C.c_void_p),
     ]
 
 
@@ -115,7 +117,7 @@ SDF_EPS_SCALE = 1e-3
 SDF_MAX_STEPS = 64
 
 # refinement outcome of a path
-REF_VALID, REF_NOT_CONVERGED, REF_MISS, REF_WRONG_SIDE, REF_OCCLUDED, REF_DEGENERATE = range(6)
+REF_VALID, REF_NOT_CONVERGED, REF_MISS, REF_WRONG_SIDE, REF_OCCLUDED, REF_DEGENERATE, REF_OFF_EDGE = range(7)
 # Table 1: convergence threshold delta and refinement iterations rho; carrier 60 GHz
 REF_GRAD_TOL = 1e-4
 REF_MAX_ITERS = 2000
@@ -343,17 +345,21 @@ def dedup(res, K, kappa=1, include_ambiguous=False):
 
 
 def refine(xyz, normal, label, r_s, t_eps, tx, rx, n_refl, pts, max_iters=REF_MAX_ITERS, grad_tol=REF_GRAD_TOL,
-           step=REF_STEP, smooth_radius=0.0, n_threads=None):
+           step=REF_STEP, smooth_radius=0.0, n_threads=None, edges=None, edge_of=None):
     """Refine coarse paths into exact paths (Section 2.3, Eq. 2), FP64 brute force.
 
     Per path p: ``tx[p]``, ``rx[p]`` (positions), ``n_refl[p]`` = N and the
     coarse interaction points ``pts[p, :N]`` ([n, K, 3]).  ``smooth_radius`` > 0
     takes the surface normal at each point as the weighted average of the
     normals within that radius (Eq. 1's n(x)) instead of the hit surfel's.
+    ``edges`` = dict(seg [E, 2, 3], normals [E, 2, 3], label [E]) and
+    ``edge_of`` [n, K] (edge of interaction k, -1 for a reflection) make the
+    interactions with an edge diffractions, D_k = c_k + t_k w_k on the edge.
     Returns a dict:
     ``status`` (REF_*), ``iters`` (gradient steps), ``grad`` (final norm of
-    the tangent-plane gradient), ``length`` (f of Eq. 2), ``points``
-    [n, K, 3] (NaN past N), ``ids`` and ``labels`` [n, K] (-1 past N).
+    the gradient), ``length`` (f of Eq. 2), ``points`` [n, K, 3] (NaN past
+    N), ``ids`` (surfel; -2 - edge for a diffraction) and ``labels`` [n, K]
+    (-1 past N).
     """
     lib = _load()
     xyz = np.ascontiguousarray(xyz, np.float32)
@@ -376,6 +382,13 @@ def refine(xyz, normal, label, r_s, t_eps, tx, rx, n_refl, pts, max_iters=REF_MA
     a.n_threads = int(n_threads or default_threads())
     a.status, a.iters, a.grad, a.length = _p(out["status"]), _p(out["iters"]), _p(out["grad"]), _p(out["length"])
     a.out_pts, a.out_id, a.out_label = _p(out["points"]), _p(out["ids"]), _p(out["labels"])
+    if edge_of is not None:
+        edge_of = np.ascontiguousarray(np.asarray(edge_of, np.int32).reshape(n, K))
+        eseg = np.ascontiguousarray(np.asarray(edges["seg"], np.float64).reshape(-1, 6))
+        enrm = np.ascontiguousarray(np.asarray(edges["normals"], np.float64).reshape(-1, 6))
+        elab = np.ascontiguousarray(np.asarray(edges["label"], np.int64).reshape(-1))
+        a.edge_of, a.n_edges = _p(edge_of), eseg.shape[0]
+        a.edge_seg, a.edge_nrm, a.edge_label = _p(eseg), _p(enrm), _p(elab)
     rc = lib.oracle_refine(C.byref(a))
     if rc != 0:
         raise RuntimeError(f"oracle_refine failed with status {rc}")

@@ -777,6 +777,19 @@ int oracle_visibility(const OracleArgs* a, int64_t n, const double* o, const dou
  * if both neighbours of every interaction lie on the same side of its
  * surface (a reflection, not a crossing) and the last segment to the RX is
  * not blocked (the segments before it end at nearest hits by construction).
+ *
+ * Diffraction (edge_of[p*K + k] >= 0): the point is D_k = a + t_k w on its
+ * edge's segment [a, b] (w = (b - a)/|b - a|, Section 2.3), starting at the
+ * projection of the coarse point; the derivative of f_k along the edge is
+ * G_k . w, and t_k steps by a_k (G_k . w) with the same a_k.  No ray is
+ * traced to a diffraction point.  A ray leaving a diffraction point starts
+ * r_s further along its direction (the surfels of the edge's own faces meet
+ * the edge), and a segment arriving at one is blocked only by a hit more
+ * than r_s before it.  A step taking t_k off [0, |b - a|] ends the path
+ * (off the edge).  A converged path also needs both neighbours of every
+ * diffraction point outside the edge's wedge ((I - D) . n1 > 0 or
+ * (I - D) . n2 > 0 with the faces' outward normals) and every segment
+ * arriving at a diffraction point unblocked.
  */
 
 #define ORACLE_REF_VALID 0
@@ -785,6 +798,7 @@ int oracle_visibility(const OracleArgs* a, int64_t n, const double* o, const dou
 #define ORACLE_REF_WRONG_SIDE 3
 #define ORACLE_REF_OCCLUDED 4
 #define ORACLE_REF_DEGENERATE 5
+#define ORACLE_REF_OFF_EDGE 6
 
 typedef struct {
     const float* xyz;          /* [n_pts*3] */
@@ -810,6 +824,12 @@ typedef struct {
     double* out_pts;           /* [n_paths*K*3], NaN past N */
     int64_t* out_id;           /* [n_paths*K] surfel of each interaction, -1 past N */
     int64_t* out_label;        /* [n_paths*K], -1 past N */
+    /* diffraction edges; edge_of NULL: every interaction is a reflection */
+    const int32_t* edge_of;    /* [n_paths*K]: edge of interaction k, -1 for a reflection */
+    int32_t n_edges;
+    const double* edge_seg;    /* [n_edges*6]: end points a, b */
+    const double* edge_nrm;    /* [n_edges*6]: outward normals n1, n2 of the two faces */
+    const int64_t* edge_label; /* [n_edges] */
 } OracleRefineArgs;
 
 typedef struct {
@@ -849,25 +869,27 @@ static void smooth_normal(const Pts64* P, int64_t n_pts, double h, const double*
     if (l > 0.0) { nh[0] = s[0] / l; nh[1] = s[1] / l; nh[2] = s[2] / l; }
 }
 
-/* Nearest hit of the ray from o towards target (excluding surfel `last`).
- * Returns 1 with the hit point, normal and surfel, 0 on a miss, -1 if the
- * target coincides with o. */
+/* Nearest hit of the ray from o towards target (excluding surfel `last`),
+ * the ray starting `skip` along its direction.  Returns 1 with the hit
+ * point, normal and surfel (t_out: its distance from o), 0 on a miss, -1 if
+ * the target coincides with o. */
 static int trace_towards(const OracleArgs* A, const Pts64* P, const double* o, const double* target, int64_t last,
-                         double* c, double* n, int64_t* m, double* t_out)
+                         double skip, double* c, double* n, int64_t* m, double* t_out)
 {
     double d[3] = {target[0] - o[0], target[1] - o[1], target[2] - o[2]};
     double len = sqrt(dot3(d, d));
     if (!(len > 0.0)) return -1;
     d[0] /= len; d[1] /= len; d[2] /= len;
+    const double os[3] = {o[0] + skip * d[0], o[1] + skip * d[1], o[2] + skip * d[2]};
     int64_t best;
     double tb;
     int32_t na;
     int64_t acc[ORACLE_MAXACC];
     double tc, t_lo, t_hi;
-    nearest_hit(A, P, o, d, last, 0, &best, &tb, &na, acc, &tc, &t_lo, &t_hi);
-    if (t_out) *t_out = tb;
+    nearest_hit(A, P, os, d, last, 0, &best, &tb, &na, acc, &tc, &t_lo, &t_hi);
+    if (t_out) *t_out = skip + tb;
     if (best < 0) return 0;
-    c[0] = o[0] + tb * d[0]; c[1] = o[1] + tb * d[1]; c[2] = o[2] + tb * d[2];
+    c[0] = os[0] + tb * d[0]; c[1] = os[1] + tb * d[1]; c[2] = os[2] + tb * d[2];
     n[0] = P->nx[best]; n[1] = P->ny[best]; n[2] = P->nz[best];
     *m = best;
     return 1;
@@ -880,30 +902,55 @@ static void refine_one(const OracleRefineArgs* a, const OracleArgs* A, const Pts
     const double* T = a->tx + 3 * p;
     const double* R = a->rx + 3 * p;
     double c[ORACLE_MAXN][3], n[ORACLE_MAXN][3], g[ORACLE_MAXN][3], tgt[ORACLE_MAXN][3];
+    /* diffraction points: edge, its start a, unit direction w, length, parameter t */
+    int32_t E[ORACLE_MAXN];
+    double ea[ORACLE_MAXN][3], ew[ORACLE_MAXN][3], el[ORACLE_MAXN], tp[ORACLE_MAXN];
     int64_t m[ORACLE_MAXN];
     int32_t status = ORACLE_REF_VALID, it = 0;
     double gnorm = 0.0;
+    const double clear = a->r_s;
     for (int32_t k = 0; k < K; ++k) {
         a->out_id[p * K + k] = -1;
         a->out_label[p * K + k] = -1;
         a->out_pts[(p * K + k) * 3] = a->out_pts[(p * K + k) * 3 + 1] = a->out_pts[(p * K + k) * 3 + 2] = NAN;
     }
-    for (int32_t k = 0; k < N; ++k)
+    for (int32_t k = 0; k < N; ++k) {
         for (int j = 0; j < 3; ++j) tgt[k][j] = a->pts[(p * K + k) * 3 + j];
+        E[k] = a->edge_of ? a->edge_of[p * K + k] : -1;
+        m[k] = -1;
+        if (E[k] >= 0) {
+            const double* sg = a->edge_seg + 6 * (int64_t)E[k];
+            double d[3] = {sg[3] - sg[0], sg[4] - sg[1], sg[5] - sg[2]};
+            el[k] = sqrt(dot3(d, d));
+            for (int j = 0; j < 3; ++j) { ea[k][j] = sg[j]; ew[k][j] = d[j] / el[k]; }
+            double q[3] = {tgt[k][0] - ea[k][0], tgt[k][1] - ea[k][1], tgt[k][2] - ea[k][2]};
+            tp[k] = dot3(q, ew[k]);   /* the coarse point's projection onto the edge */
+        }
+    }
     /* I(k) for k = 0..N+1 */
 #define IPT(k) ((k) == 0 ? T : ((k) == N + 1 ? R : c[(k) - 1]))
+#define DIFF(k) ((k) >= 1 && (k) <= N && E[(k) - 1] >= 0)
     for (;;) {
-        /* trace towards the targets: the coarse points first, then the gradient steps */
+        /* the interaction points: diffraction points on their edges, reflection points traced
+           towards the targets (the coarse points first, then the gradient steps) */
         int64_t last = -1;
+        double skip = 0.0;
         for (int32_t k = 0; k < N && status == ORACLE_REF_VALID; ++k) {
-            int r = trace_towards(A, P, IPT(k), tgt[k], last, c[k], n[k], &m[k], NULL);
+            if (E[k] >= 0) {
+                for (int j = 0; j < 3; ++j) c[k][j] = ea[k][j] + tp[k] * ew[k][j];
+                last = -1;
+                skip = clear;
+                continue;
+            }
+            int r = trace_towards(A, P, IPT(k), tgt[k], last, skip, c[k], n[k], &m[k], NULL);
             if (r > 0 && a->smooth_h > 0.0) smooth_normal(P, a->n_pts, a->smooth_h, c[k], n[k]);
             if (r < 0) status = ORACLE_REF_DEGENERATE;
             else if (r == 0) status = ORACLE_REF_MISS;
             last = m[k];
+            skip = 0.0;
         }
         if (status != ORACLE_REF_VALID) break;
-        /* gradient of the path length in the tangent planes */
+        /* gradient of the path length: tangent planes of reflections, edge directions of diffractions */
         double gg = 0.0;
         for (int32_t k = 1; k <= N; ++k) {
             const double* I = IPT(k);
@@ -913,41 +960,69 @@ static void refine_one(const OracleRefineArgs* a, const OracleArgs* A, const Pts
             if (!(lp > 0.0) || !(ln > 0.0)) { status = ORACLE_REF_DEGENERATE; break; }
             double G[3];
             for (int j = 0; j < 3; ++j) G[j] = (I[j] - Ip[j]) / lp + (I[j] - In[j]) / ln;
-            double gn = dot3(G, n[k - 1]);
-            for (int j = 0; j < 3; ++j) g[k - 1][j] = G[j] - gn * n[k - 1][j];
-            gg += dot3(g[k - 1], g[k - 1]);
+            if (E[k - 1] >= 0) {
+                double gw = dot3(G, ew[k - 1]);
+                for (int j = 0; j < 3; ++j) g[k - 1][j] = gw * ew[k - 1][j];
+                gg += gw * gw;
+            } else {
+                double gn = dot3(G, n[k - 1]);
+                for (int j = 0; j < 3; ++j) g[k - 1][j] = G[j] - gn * n[k - 1][j];
+                gg += dot3(g[k - 1], g[k - 1]);
+            }
         }
         if (status != ORACLE_REF_VALID) break;
         gnorm = sqrt(gg);
         if (gnorm < a->grad_tol) break;
         if (it == a->max_iters) { status = ORACLE_REF_NOT_CONVERGED; break; }
         /* simultaneous gradient step of every point */
+        int off = 0;
         for (int32_t k = 1; k <= N; ++k) {
             const double* I = IPT(k);
             double step = a->step / (1.0 / dist3(I, IPT(k - 1)) + 1.0 / dist3(I, IPT(k + 1)));
-            for (int j = 0; j < 3; ++j) tgt[k - 1][j] = I[j] - step * g[k - 1][j];
+            if (E[k - 1] >= 0) {
+                tp[k - 1] -= step * dot3(g[k - 1], ew[k - 1]);
+                if (!(tp[k - 1] >= 0.0 && tp[k - 1] <= el[k - 1])) off = 1;
+            } else {
+                for (int j = 0; j < 3; ++j) tgt[k - 1][j] = I[j] - step * g[k - 1][j];
+            }
         }
+        if (off) { status = ORACLE_REF_OFF_EDGE; break; }
         ++it;
     }
     if (status == ORACLE_REF_VALID) {
-        /* a reflection keeps both neighbours on one side of the surface */
-        for (int32_t k = 1; k <= N; ++k) {
+        /* a reflection keeps both neighbours on one side of the surface; a diffraction has
+           both outside the edge's wedge */
+        for (int32_t k = 1; k <= N && status == ORACLE_REF_VALID; ++k) {
             const double* I = IPT(k);
+            if (E[k - 1] >= 0) {
+                const double* nn = a->edge_nrm + 6 * (int64_t)E[k - 1];
+                for (int side = 0; side < 2; ++side) {
+                    const double* X = IPT(side ? k + 1 : k - 1);
+                    double v[3] = {X[0] - I[0], X[1] - I[1], X[2] - I[2]};
+                    if (!(dot3(v, nn) > 0.0 || dot3(v, nn + 3) > 0.0)) status = ORACLE_REF_WRONG_SIDE;
+                }
+                continue;
+            }
             double sp = 0.0, sn = 0.0;
             for (int j = 0; j < 3; ++j) {
                 sp += (IPT(k - 1)[j] - I[j]) * n[k - 1][j];
                 sn += (IPT(k + 1)[j] - I[j]) * n[k - 1][j];
             }
-            if (!(sp * sn > 0.0)) { status = ORACLE_REF_WRONG_SIDE; break; }
+            if (!(sp * sn > 0.0)) status = ORACLE_REF_WRONG_SIDE;
         }
     }
-    if (status == ORACLE_REF_VALID) {
-        /* the last segment must reach the RX unblocked */
+    /* segments not ending at a nearest hit: those arriving at a diffraction point (blocked by a
+       hit more than r_s before it) and the last one, to the RX */
+    for (int32_t k = 1; k <= N + 1 && status == ORACLE_REF_VALID; ++k) {
+        if (k <= N && E[k - 1] < 0) continue;
+        const int prev_diff = DIFF(k - 1);
         double cc[3], nn[3], tb;
         int64_t mm;
-        int r = trace_towards(A, P, IPT(N), R, N > 0 ? m[N - 1] : -1, cc, nn, &mm, &tb);
+        const double len = dist3(IPT(k - 1), IPT(k));
+        int r = trace_towards(A, P, IPT(k - 1), IPT(k), (k >= 2 && !prev_diff) ? m[k - 2] : -1,
+                              prev_diff ? clear : 0.0, cc, nn, &mm, &tb);
         if (r < 0) status = ORACLE_REF_DEGENERATE;
-        else if (r > 0 && tb < dist3(IPT(N), R)) status = ORACLE_REF_OCCLUDED;
+        else if (r > 0 && tb < (k <= N ? len - clear : len)) status = ORACLE_REF_OCCLUDED;
     }
     double f = 0.0;
     int finite = (status != ORACLE_REF_MISS && status != ORACLE_REF_DEGENERATE);
@@ -958,10 +1033,11 @@ static void refine_one(const OracleRefineArgs* a, const OracleArgs* A, const Pts
     a->grad[p] = finite ? gnorm : NAN;
     if (finite)
         for (int32_t k = 0; k < N; ++k) {
-            a->out_id[p * K + k] = m[k];
-            a->out_label[p * K + k] = (int64_t)a->label[m[k]];
+            a->out_id[p * K + k] = E[k] >= 0 ? -2 - (int64_t)E[k] : m[k];
+            a->out_label[p * K + k] = E[k] >= 0 ? a->edge_label[E[k]] : (int64_t)a->label[m[k]];
             for (int j = 0; j < 3; ++j) a->out_pts[(p * K + k) * 3 + j] = c[k][j];
         }
+#undef DIFF
 #undef IPT
 }
 
@@ -985,6 +1061,16 @@ int oracle_refine(OracleRefineArgs* a)
         return -1;
     for (int64_t p = 0; p < a->n_paths; ++p)
         if (a->n_refl[p] < 0 || a->n_refl[p] > a->K) return -1;
+    if (a->edge_of) {
+        if (a->n_edges < 0 || (a->n_edges > 0 && (!a->edge_seg || !a->edge_nrm || !a->edge_label))) return -1;
+        for (int64_t q = 0; q < a->n_paths * a->K; ++q)
+            if (a->edge_of[q] < -1 || a->edge_of[q] >= a->n_edges) return -1;
+        for (int32_t e = 0; e < a->n_edges; ++e) {
+            const double* sg = a->edge_seg + 6 * (int64_t)e;
+            double d[3] = {sg[3] - sg[0], sg[4] - sg[1], sg[5] - sg[2]};
+            if (!(dot3(d, d) > 0.0)) return -1;
+        }
+    }
     Pts64 P;
     size_t nb = (size_t)(a->n_pts > 0 ? a->n_pts : 1) * sizeof(double);
     P.px = malloc(nb); P.py = malloc(nb); P.pz = malloc(nb);

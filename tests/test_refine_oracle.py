@@ -13,6 +13,14 @@ own arithmetic:
     point off a finite plate makes the re-traced ray miss.
 The dedup is pinned on hand-made paths with the first Fresnel zone radius
 sqrt(lambda d1 d2 / (d1 + d2)) worked out by hand at 60 GHz.
+
+Diffraction points (D_k = c_k + t_k w_k on an edge) are pinned at the
+corner building's vertical edge at (0, 0): TX and RX lie sqrt(34) from the
+edge on either side, so unfolding the two half-planes about the edge makes
+the diffracted path a straight line of horizontal extent 2 sqrt(34); with a
+ground reflection the RX is mirrored in z = 0 first.  The outcomes a point
+off the finite edge, a neighbour inside the wedge and a segment through the
+ground are decided by the geometry.
 """
 import math
 import os
@@ -275,3 +283,72 @@ def test_invalid_paths_never_kept():
     d = _one_bounce_paths([(0, 0, 0), (2, 0, 0)], [6.0, 6.1], [1, 2])
     d["status"][0] = oracle.REF_NOT_CONVERGED
     assert _dedup(d).tolist() == [False, True]
+
+
+# --------------------------------------------------------------------------- diffraction (Section 2.3)
+
+def _corner(tx, rx, pts, edge_of):
+    s = scenes.corner_building(tx=tx, rx=rx)
+    pts = np.asarray(pts, np.float64).reshape(1, -1, 3)
+    eo = np.asarray(edge_of, np.int32).reshape(1, -1)
+    return oracle.refine(s.xyz, s.normal, s.label, s.surfel_radius, 1e-5, np.asarray(tx, np.float64)[None],
+                         np.asarray(rx, np.float64)[None], np.array([pts.shape[1]], np.int32), pts,
+                         edges=s.extra["edges"], edge_of=eo)
+
+
+def _keller(a, d, b, w):
+    """cosines of the incoming and outgoing directions with the edge"""
+    u, v = (d - a) / np.linalg.norm(d - a), (b - d) / np.linalg.norm(b - d)
+    return float(u @ w), float(v @ w)
+
+
+@pytest.mark.parametrize("z_tx,z_rx", [(1.5, 1.5), (1.0, 2.0), (0.5, 3.5)])
+def test_corner_diffraction_point(z_tx, z_rx):
+    """Unfolded about the edge the path is straight: length sqrt((2 sqrt 34)^2 + dz^2), the point at the
+    height where the straight line crosses the edge, Keller's law at it."""
+    tx, rx = np.array([-3.0, 5.0, z_tx]), np.array([5.0, -3.0, z_rx])
+    r = _corner(tx, rx, [(0.0, 0.0, 2.9)], [0])
+    L = math.sqrt(136.0 + (z_rx - z_tx) ** 2)
+    assert r["status"][0] == oracle.REF_VALID
+    assert L <= r["length"][0] <= L * (1 + 1e-8)
+    d = r["points"][0, 0]
+    assert abs(d[2] - 0.5 * (z_tx + z_rx)) <= 1e-3 and abs(d[0]) + abs(d[1]) == 0.0
+    ci, co = _keller(tx, d, rx, np.array([0.0, 0.0, 1.0]))
+    assert abs(ci - co) <= 1e-4
+    assert r["labels"][0, 0] == 100 and r["ids"][0, 0] == -2
+
+
+def test_corner_diffraction_then_ground_reflection():
+    """TX at 3 m, RX at 1.5 m: mirrored in the ground the RX is at -1.5 m; the straight unfolded line
+    has horizontal extent 2 sqrt(34) and drop 4.5: length 12.5, crossing the edge at 0.75 m and the
+    ground a third of the way from the edge to the RX, at (5/3, -1, 0)."""
+    tx, rx = np.array([-3.0, 5.0, 3.0]), np.array([5.0, -3.0, 1.5])
+    r = _corner(tx, rx, [(0.0, 0.0, 1.0), (1.5, -1.2, 0.0)], [0, -1])
+    assert r["status"][0] == oracle.REF_VALID
+    assert 12.5 <= r["length"][0] <= 12.5 * (1 + 1e-7)
+    assert abs(r["points"][0, 0, 2] - 0.75) <= 2e-3
+    assert np.abs(r["points"][0, 1] - np.array([5.0 / 3.0, -1.0, 0.0])).max() <= 5e-3
+    assert list(r["labels"][0]) == [100, 0]
+    ci, co = _keller(tx, r["points"][0, 0], r["points"][0, 1], np.array([0.0, 0.0, 1.0]))
+    assert abs(ci - co) <= 1e-4
+
+
+def test_diffraction_point_off_the_edge():
+    """TX and RX at 8 m: the stationary point (8 m) lies above the 4 m edge."""
+    r = _corner((-3.0, 5.0, 8.0), (5.0, -3.0, 8.0), [(0.0, 0.0, 3.0)], [0])
+    assert r["status"][0] == oracle.REF_OFF_EDGE
+
+
+def test_diffraction_neighbour_inside_the_wedge():
+    """An RX inside the building: the stationary point exists, but the path enters the wedge."""
+    r = _corner((-3.0, 5.0, 1.5), (3.0, 3.0, 1.5), [(0.0, 0.0, 1.0)], [0])
+    assert r["status"][0] == oracle.REF_WRONG_SIDE
+
+
+@pytest.mark.parametrize("tx_z,rx_z", [(1.5, -1.0), (-1.0, 1.5)])
+def test_diffraction_segment_through_the_ground(tx_z, rx_z):
+    """An antenna 1 m below the ground: the stationary point is at 0.25 m and the segment to the
+    buried antenna crosses the ground's surfels (the last segment, or one arriving at the edge)."""
+    r = _corner((-3.0, 5.0, tx_z), (5.0, -3.0, rx_z), [(0.0, 0.0, 1.0)], [0])
+    assert r["status"][0] == oracle.REF_OCCLUDED
+    assert abs(r["points"][0, 0, 2] - 0.25) <= 1e-3
