@@ -352,6 +352,7 @@ int collect_paths_noalloc(PcrlLaunch* launch, int32_t kappa, int32_t key_mode, P
 #define PCRL_REFINE_WRONG_SIDE     3   /* converged, but a point has its neighbours on both sides of its surfel */
 #define PCRL_REFINE_OCCLUDED       4   /* converged, but a surfel blocks the last segment to the RX */
 #define PCRL_REFINE_DEGENERATE     5   /* a segment of zero length */
+#define PCRL_REFINE_OFF_EDGE       6   /* a diffraction point stepped off its edge's segment */
 
 typedef struct {
     int32_t max_iters;   /* rho: gradient steps before a path is given up; <= 0 -> 2000 (Table 1) */
@@ -363,6 +364,13 @@ typedef struct {
     int32_t flags;       /* 0 or PCRL_REFINE_SMOOTH */
     float   smooth_radius;  /* PCRL_REFINE_SMOOTH: radius h of the normal average, surfel radius < h <= 0.98 x
                                leaf edge (PCRL_EINVAL otherwise); <= 0 -> 0.95 x leaf edge */
+    /* diffraction edges (Section 2.3: D_k = c_k + t_k w_k); edge_of NULL: every interaction is a reflection */
+    const int32_t*  edge_of;       /* device [n_rows * k_stride]: edge of interaction k of row i, -1 for a
+                                      reflection */
+    int32_t         n_edges;
+    const float*    edge_seg;      /* device [n_edges,2,3]: end points a, b (non-zero length) */
+    const float*    edge_normals;  /* device [n_edges,2,3]: outward normals of the edge's two faces */
+    const uint32_t* edge_label;    /* device [n_edges]: the label of a diffraction at the edge */
 } PcrlRefineParams;
 
 /* PcrlRefineParams.flags: the surface normal at an interaction point is the
@@ -379,8 +387,9 @@ typedef struct {
     float*   grad;       /* final gradient norm (NaN after a miss) */
     float*   length;     /* f of Eq. 2 over the final points (NaN after a miss) */
     float*   points;     /* [n*K*3] final interaction points, NaN for k >= n_refl */
-    int32_t* point_id;   /* [n*K] point (surfel) of each interaction, -1 for k >= n_refl */
-    int64_t* key;        /* [n*K] label of each interaction, -1 for k >= n_refl */
+    int32_t* point_id;   /* [n*K] point (surfel) of each interaction, -2 - edge for a diffraction, -1 for
+                            k >= n_refl */
+    int64_t* key;        /* [n*K] label of each interaction (the edge's for a diffraction), -1 for k >= n_refl */
     int32_t* kept;       /* 1 for the unique exact paths: valid, shortest of its label sequence within its
                             (tx, rx, n_refl) group, and not inside the first Fresnel zones of a shorter kept
                             path of that group (every point within sqrt(lambda d1 d2 / (d1 + d2)) of the
@@ -393,7 +402,16 @@ typedef struct {
  * from the previous point towards each updated point to find the new point
  * and surfel, for at most max_iters steps; then the dedup of refined paths
  * (shortest per label sequence, then first-Fresnel-zone uniqueness in order
- * of increasing length).
+ * of increasing length).  With params->edge_of, an interaction with an edge
+ * is a diffraction: its point D_k = a + t_k w stays on the edge's segment
+ * [a, b] (w the unit direction), starting at the coarse point's projection,
+ * and t_k steps along the derivative of the length along the edge; no ray
+ * is traced to it; a ray leaving it starts r_s (the surfel radius) along its
+ * direction, and a segment arriving at it is blocked only by a surfel hit
+ * more than r_s before it; a step off [a, b] ends the path
+ * (PCRL_REFINE_OFF_EDGE); a converged path also needs both neighbours of
+ * every diffraction point outside the edge's wedge ((I - D) . n1 > 0 or
+ * (I - D) . n2 > 0) and every segment arriving at one unblocked.
  *   scene  the scene the paths were traced in (its current overlay epoch is used)
  *   tx, rx device [n_tx,3] / [n_rx,3] float32, the arrays of the launch
  *   paths  a collect_paths result (device arrays; n_rows rows sorted by
@@ -401,8 +419,9 @@ typedef struct {
  *          and points are read
  *   k_stride  K of the launch (points has k_stride entries per row)
  * Synchronous.  PCRL_EINVAL on a row with an index out of range or rows out
- * of order; PCRL_EOVERFLOW if one (tx, rx, n_refl) group keeps more than
- * 2048 paths (the per-path outputs are still written). */
+ * of order, an edge index out of range or an edge of zero length;
+ * PCRL_EOVERFLOW if one (tx, rx, n_refl) group keeps more than 2048 paths
+ * (the per-path outputs are still written). */
 int refine_paths(const PcrlScene* scene, const float* tx, int32_t n_tx, const float* rx, int32_t n_rx,
                  const PcrlPaths* paths, int32_t k_stride, const PcrlRefineParams* params, PcrlRefined* out,
                  pcrl_stream_t stream);
@@ -571,6 +590,13 @@ int cone_nodes(const PcrlConeLaunch* launch, int32_t k, int32_t* ie, int32_t* pa
  * the reception points.  Synchronous; PCRL_EOVERFLOW with n_rows = rows
  * needed when capacity is too small. */
 int cone_collect(PcrlConeLaunch* launch, int32_t kappa, PcrlPaths* out, pcrl_stream_t stream);
+/* Refine the coarse paths of a cone_collect result of this launch (Section
+ * 2.3): refine_paths in the launch's scene with its TX and RX, every
+ * interaction at an edge piece a diffraction on that piece's edge (the
+ * edges of ie_add_edges).  params->edge_* must be unset (the launch supplies
+ * them).  Synchronous; PCRL_EINVAL for rows that are not the launch's. */
+int refine_cone_paths(const PcrlConeLaunch* launch, const PcrlPaths* paths, const PcrlRefineParams* params,
+                      PcrlRefined* out, pcrl_stream_t stream);
 int release_cone(PcrlConeLaunch* launch);
 
 /* ------------------------------------------------------------------------ */

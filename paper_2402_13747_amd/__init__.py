@@ -21,13 +21,13 @@ import torch
 
 from . import _lib
 from ._lib import (KEY_LABELS, KEY_LEAVES, LAUNCH_COHERENT, LAUNCH_SDF, LAUNCH_STATS, LAUNCH_TIMING, PCRL_EOVERFLOW,
-                   REFINE_DEGENERATE, REFINE_MISS, REFINE_NOT_CONVERGED, REFINE_OCCLUDED, REFINE_VALID,
-                   REFINE_WRONG_SIDE, PcrlError, check, lib)
+                   REFINE_DEGENERATE, REFINE_MISS, REFINE_NOT_CONVERGED, REFINE_OCCLUDED, REFINE_OFF_EDGE,
+                   REFINE_VALID, REFINE_WRONG_SIDE, PcrlError, check, lib)
 
 __all__ = ["ie_build", "cone_launch", "cone_collect", "IeTable", "ConeLaunch", "build_voxels", "launch_rays", "launch_batch", "batch_autotune", "launch_directions", "collect_paths",
-           "refine_paths", "sdf_intersect", "use_torch_allocator", "Scene", "Launch", "Server", "PcrlError", "KEY_LABELS",
+           "refine_paths", "refine_cone_paths", "sdf_intersect", "use_torch_allocator", "Scene", "Launch", "Server", "PcrlError", "KEY_LABELS",
            "KEY_LEAVES", "REFINE_VALID", "REFINE_NOT_CONVERGED", "REFINE_MISS", "REFINE_WRONG_SIDE",
-           "REFINE_OCCLUDED", "REFINE_DEGENERATE", "version", "library_path"]
+           "REFINE_OCCLUDED", "REFINE_DEGENERATE", "REFINE_OFF_EDGE", "version", "library_path"]
 
 
 # Every installed allocator's ctypes callbacks, kept for the life of the
@@ -422,24 +422,7 @@ def collect_paths(launch: Launch, kappa=1, key_mode=KEY_LABELS, capacity=None) -
     raise PcrlError("collect_paths", PCRL_EOVERFLOW, "capacity retries exhausted")
 
 
-def refine_paths(scene: Scene, tx, rx, paths: dict, max_iters=2000, grad_tol=1e-4, step=0.75,
-                 carrier_hz=60e9, smooth_radius=0.0) -> dict:
-    """Exact paths from coarse ones (Section 2.3): gradient descent on the path
-    length with re-tracing, then the dedup of refined paths.
-
-    ``paths`` is a ``collect_paths`` result of a launch with these ``tx`` and
-    ``rx`` in ``scene``.  Returns per input row: ``status`` (REFINE_*),
-    ``iters``, ``grad``, ``length``, ``points`` [n, K, 3], ``point_id`` and
-    ``key`` [n, K], ``kept`` (the unique exact paths), plus ``n_kept``.
-    ``carrier_hz < 0`` skips the Fresnel-zone step.  ``smooth_radius > 0``
-    takes the surface normal at each point as the weighted average of the
-    normals within that radius (between the surfel radius and the leaf edge).
-    """
-    device = scene.device
-    txt = _as_tensor(tx, torch.float32, device, 3)
-    rxt = _as_tensor(rx, torch.float32, device, 3)
-    n = int(paths["n_rows"])
-    K = int(paths["points"].shape[1]) if paths["points"].dim() == 3 else 0
+def _refine_outputs(n, K, device):
     res = {
         "status": torch.empty(n, dtype=torch.int32, device=device),
         "iters": torch.empty(n, dtype=torch.int32, device=device),
@@ -450,22 +433,89 @@ def refine_paths(scene: Scene, tx, rx, paths: dict, max_iters=2000, grad_tol=1e-
         "key": torch.empty((n, K), dtype=torch.int64, device=device),
         "kept": torch.empty(n, dtype=torch.int32, device=device),
     }
-    pp = _lib.PcrlPaths()
-    pp.capacity = n
-    pp.n_rows = n
-    for k in ("tx", "rx", "n_refl", "points"):
-        t = paths[k]
-        assert t.is_contiguous() and t.device == device, k
-        setattr(pp, k, t.data_ptr() if t.numel() else None)
     out = _lib.PcrlRefined()
     for k, t in res.items():
         setattr(out, k, t.data_ptr() if t.numel() else None)
+    return res, out
+
+
+def _refine_rows(paths: dict, n, device, fields):
+    pp = _lib.PcrlPaths()
+    pp.capacity = n
+    pp.n_rows = n
+    for k in fields:
+        t = paths[k]
+        assert t.is_contiguous() and t.device == device, k
+        setattr(pp, k, t.data_ptr() if t.numel() else None)
+    return pp
+
+
+def _refine_params(max_iters, grad_tol, step, carrier_hz, smooth_radius):
     smooth = _lib.REFINE_SMOOTH if smooth_radius > 0 else 0
-    prm = _lib.PcrlRefineParams(int(max_iters), float(grad_tol), float(step), float(carrier_hz), smooth,
-                                float(smooth_radius))
+    return _lib.PcrlRefineParams(int(max_iters), float(grad_tol), float(step), float(carrier_hz), smooth,
+                                 float(smooth_radius))
+
+
+def refine_paths(scene: Scene, tx, rx, paths: dict, max_iters=2000, grad_tol=1e-4, step=0.75,
+                 carrier_hz=60e9, smooth_radius=0.0, edges=None, edge_of=None) -> dict:
+    """Exact paths from coarse ones (Section 2.3): gradient descent on the path
+    length with re-tracing, then the dedup of refined paths.
+
+    ``paths`` is a ``collect_paths`` result of a launch with these ``tx`` and
+    ``rx`` in ``scene``.  Returns per input row: ``status`` (REFINE_*),
+    ``iters``, ``grad``, ``length``, ``points`` [n, K, 3], ``point_id`` and
+    ``key`` [n, K], ``kept`` (the unique exact paths), plus ``n_kept``.
+    ``carrier_hz < 0`` skips the Fresnel-zone step.  ``smooth_radius > 0``
+    takes the surface normal at each point as the weighted average of the
+    normals within that radius (between the surfel radius and the leaf edge).
+    ``edges`` = dict(seg [E, 2, 3], normals [E, 2, 3], label [E]) with
+    ``edge_of`` [n, K] (edge of each interaction, -1 for a reflection) makes
+    the interactions at edges diffractions (D_k = c_k + t_k w_k).
+    """
+    device = scene.device
+    txt = _as_tensor(tx, torch.float32, device, 3)
+    rxt = _as_tensor(rx, torch.float32, device, 3)
+    n = int(paths["n_rows"])
+    K = int(paths["points"].shape[1]) if paths["points"].dim() == 3 else 0
+    res, out = _refine_outputs(n, K, device)
+    pp = _refine_rows(paths, n, device, ("tx", "rx", "n_refl", "points"))
+    prm = _refine_params(max_iters, grad_tol, step, carrier_hz, smooth_radius)
+    keep = []
+    if edge_of is not None:
+        eo = _as_tensor(np.asarray(edge_of, np.int32).reshape(n, K) if isinstance(edge_of, np.ndarray) else edge_of,
+                        torch.int32, device).reshape(-1).contiguous()
+        seg = _as_tensor(edges["seg"], torch.float32, device).reshape(-1, 6).contiguous()
+        nrm = _as_tensor(edges["normals"], torch.float32, device).reshape(-1, 6).contiguous()
+        lab = edges["label"]
+        if isinstance(lab, np.ndarray):
+            lab = torch.from_numpy(np.ascontiguousarray(lab.astype(np.uint32)).view(np.int32))
+        lab = _as_tensor(lab, torch.int32, device).contiguous()
+        keep = [eo, seg, nrm, lab]
+        prm.edge_of = eo.data_ptr() if eo.numel() else None
+        prm.n_edges = int(seg.shape[0])
+        prm.edge_seg, prm.edge_normals, prm.edge_label = seg.data_ptr(), nrm.data_ptr(), lab.data_ptr()
     with _on(device):
         check("refine_paths", lib.refine_paths(scene.handle, _ptr(txt), txt.shape[0], _ptr(rxt), rxt.shape[0],
                                                C.byref(pp), K, C.byref(prm), C.byref(out), _stream(device)))
+    del keep
+    res["n_kept"] = int(out.n_kept)
+    return res
+
+
+def refine_cone_paths(launch: "ConeLaunch", paths: dict, max_iters=2000, grad_tol=1e-4, step=0.75,
+                      carrier_hz=60e9, smooth_radius=0.0) -> dict:
+    """Refine the rows of a ``cone_collect`` result of ``launch`` (Section 2.3):
+    interactions at edge pieces are diffractions on their edges.  Returns as
+    ``refine_paths``."""
+    device = launch.device
+    n = int(paths["n_rows"])
+    K = launch.K
+    res, out = _refine_outputs(n, K, device)
+    pp = _refine_rows(paths, n, device, ("tx", "rx", "n_refl", "ray", "points"))
+    prm = _refine_params(max_iters, grad_tol, step, carrier_hz, smooth_radius)
+    with _on(device):
+        check("refine_cone_paths", lib.refine_cone_paths(launch.handle, C.byref(pp), C.byref(prm), C.byref(out),
+                                                         _stream(device)))
     res["n_kept"] = int(out.n_kept)
     return res
 

@@ -39,6 +39,7 @@ REFINE_MISS = 2
 REFINE_WRONG_SIDE = 3
 REFINE_OCCLUDED = 4
 REFINE_DEGENERATE = 5
+REFINE_OFF_EDGE = 6
 REFINE_SMOOTH = 1
 
 STATUS_NAMES = {0: "PCRL_OK", -1: "PCRL_EINVAL", -2: "PCRL_ENOMEM", -3: "PCRL_EOVERFLOW", -4: "PCRL_EHIP",
@@ -97,7 +98,8 @@ class PcrlPaths(C.Structure):
 
 class PcrlRefineParams(C.Structure):
     _fields_ = [("max_iters", C.c_int32), ("grad_tol", C.c_float), ("step", C.c_float), ("carrier_hz", C.c_float),
-                ("flags", C.c_int32), ("smooth_radius", C.c_float)]
+                ("flags", C.c_int32), ("smooth_radius", C.c_float), ("edge_of", C.c_void_p), ("n_edges", C.c_int32),
+                ("edge_seg", C.c_void_p), ("edge_normals", C.c_void_p), ("edge_label", C.c_void_p)]
 
 
 class PcrlRefined(C.Structure):
@@ -198,6 +200,8 @@ SIGNATURES = {
     "cone_nodes": (C.c_int, [C.c_void_p, C.c_int32, C.c_void_p, C.c_void_p, C.c_void_p, C.c_void_p, C.c_void_p,
                              C.c_void_p]),
     "cone_collect": (C.c_int, [C.c_void_p, C.c_int32, C.POINTER(PcrlPaths), C.c_void_p]),
+    "refine_cone_paths": (C.c_int, [C.c_void_p, C.POINTER(PcrlPaths), C.POINTER(PcrlRefineParams),
+                                    C.POINTER(PcrlRefined), C.c_void_p]),
     "release_cone": (C.c_int, [C.c_void_p]),
     "serve_create": (C.c_int, [C.c_void_p, C.POINTER(PcrlServeParams), C.POINTER(C.c_void_p)]),
     "serve_submit": (C.c_int, [C.c_void_p, C.c_void_p, C.c_int32, C.c_void_p, C.c_int32, C.POINTER(PcrlLaunchParams),

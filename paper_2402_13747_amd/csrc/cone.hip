@@ -65,6 +65,11 @@ struct PcrlIes {
     float4* en1 = nullptr;       // per edge piece: outward normals of the edge's two faces
     float4* en2 = nullptr;
     uint2* vox_e = nullptr;      // per voxel: (first edge piece, count), null without edges
+    // the edges as given (refinement of diffraction points)
+    int64_t n_lines = 0;
+    float* line_seg = nullptr;   // [n_lines,2,3]
+    float* line_nrm = nullptr;   // [n_lines,2,3]
+    uint32_t* line_label = nullptr;
 };
 
 namespace pcrl {
@@ -1088,14 +1093,19 @@ static int ie_add_edges_impl(PcrlIes* I, const float* seg, const float* nrm, con
     uint32_t *nlabel = nullptr, *ncount = nullptr, *ntype = nullptr, *neid = nullptr;
     float4 *npos = nullptr, *nnrm = nullptr, *ew = nullptr, *en1 = nullptr, *en2 = nullptr;
     uint2* vox_e = nullptr;
+    float *lseg = nullptr, *lnrm = nullptr;
+    uint32_t* llab = nullptr;
     DevBufs& B = I->bufs;
     if ((rc = B.alloc(&nkey, N)) || (rc = B.alloc(&nsub, (size_t)N * 3)) || (rc = B.alloc(&nlabel, N)) ||
         (rc = B.alloc(&ncount, N)) || (rc = B.alloc(&ntype, N)) || (rc = B.alloc(&neid, N)) ||
         (rc = B.alloc(&npos, N)) || (rc = B.alloc(&nnrm, N)) || (rc = B.alloc(&ew, P)) || (rc = B.alloc(&en1, P)) ||
-        (rc = B.alloc(&en2, P)) || (rc = B.alloc(&vox_e, (size_t)I->n_vox)))
+        (rc = B.alloc(&en2, P)) || (rc = B.alloc(&vox_e, (size_t)I->n_vox)) || (rc = B.alloc(&lseg, (size_t)n * 6)) ||
+        (rc = B.alloc(&lnrm, (size_t)n * 6)) || (rc = B.alloc(&llab, n)))
         return fail(rc);
-    hipError_t e = hipSuccess;
-    if (n_pt) {
+    hipError_t e = hipMemcpyAsync(lseg, seg, (size_t)n * 24, hipMemcpyDeviceToDevice, s);
+    if (e == hipSuccess) e = hipMemcpyAsync(lnrm, nrm, (size_t)n * 24, hipMemcpyDeviceToDevice, s);
+    if (e == hipSuccess) e = hipMemcpyAsync(llab, label, (size_t)n * 4, hipMemcpyDeviceToDevice, s);
+    if (n_pt && e == hipSuccess) {
         e = hipMemcpyAsync(nkey, I->key, (size_t)n_pt * 8, hipMemcpyDeviceToDevice, s);
         if (e == hipSuccess) e = hipMemcpyAsync(nsub, I->sub, (size_t)n_pt * 12, hipMemcpyDeviceToDevice, s);
         if (e == hipSuccess) e = hipMemcpyAsync(nlabel, I->label, (size_t)n_pt * 4, hipMemcpyDeviceToDevice, s);
@@ -1134,7 +1144,11 @@ static int ie_add_edges_impl(PcrlIes* I, const float* seg, const float* nrm, con
     I->vox_e = vox_e;
     I->n_ie = N;
     I->n_edges = P;
-    I->bytes += (int64_t)P * (8 + 12 + 4 + 4 + 32 + 8 + 48) + I->n_vox * 8;
+    I->n_lines = n;
+    I->line_seg = lseg;
+    I->line_nrm = lnrm;
+    I->line_label = llab;
+    I->bytes += (int64_t)P * (8 + 12 + 4 + 4 + 32 + 8 + 48) + I->n_vox * 8 + (int64_t)n * 52;
     T.release();
     return PCRL_OK;
 }
@@ -1777,6 +1791,120 @@ extern "C" int cone_collect(PcrlConeLaunch* launch, int32_t kappa, PcrlPaths* ou
         return PCRL_EINVAL;
     }
     return cone_collect_impl(launch, kappa, out, (hipStream_t)stream);
+}
+
+// Per row of a cone_collect result: the edge of every interaction (-1 for a
+// reflection), walking the row's chain from its last node up the generations.
+struct RowEdgeArgs {
+    const int64_t* ray;
+    uint32_t n;
+    int32_t K;
+    const uint32_t* ie[PCRL_MAX_REFLECTIONS + 1];
+    const uint32_t* parent[PCRL_MAX_REFLECTIONS + 1];
+    const uint32_t* type;
+    const uint32_t* eid;
+    int32_t* edge_of;           // [n][K]
+};
+
+__global__ void k_row_edges(RowEdgeArgs a) {
+    const uint32_t i = blockIdx.x * blockDim.x + threadIdx.x;
+    if (i >= a.n) return;
+    const int64_t r = a.ray[i];
+    const int k = (int)(r >> 40);
+    uint32_t node = (uint32_t)(r & ((1ll << 40) - 1));
+    for (int j = a.K - 1; j >= k; --j) a.edge_of[(size_t)i * a.K + j] = -1;
+    for (int j = k; j >= 1; --j) {
+        const uint32_t e = a.ie[j][node];
+        a.edge_of[(size_t)i * a.K + j - 1] = a.type[e] ? (int32_t)a.eid[e] : -1;
+        node = a.parent[j][node];
+    }
+}
+
+extern "C" int refine_cone_paths(const PcrlConeLaunch* L, const PcrlPaths* paths, const PcrlRefineParams* params,
+                                 PcrlRefined* out, pcrl_stream_t stream) {
+    clear_error();
+    if (!L || !paths || !out || paths->n_rows < 0) {
+        set_error("refine_cone_paths: need a launch, paths and outputs");
+        return PCRL_EINVAL;
+    }
+    if (params && (params->edge_of || params->edge_seg || params->edge_normals || params->edge_label ||
+                   params->n_edges)) {
+        set_error("refine_cone_paths: the launch supplies the edges; leave params->edge_* unset");
+        return PCRL_EINVAL;
+    }
+    const int64_t n = paths->n_rows;
+    out->n_kept = 0;
+    if (n == 0) return PCRL_OK;
+    if (L->n_rx < 1 || !paths->ray || !paths->n_refl) {
+        set_error("refine_cone_paths: rows need their ray and n_refl (a cone_collect result of this launch)");
+        return PCRL_EINVAL;
+    }
+    hipStream_t s = (hipStream_t)stream;
+    const PcrlIes* I = L->ies;
+    const int K = L->K;
+    // the rows must be this launch's: k = n_refl and a node of generation k
+    std::vector<int64_t> h_ray(n);
+    std::vector<int32_t> h_n(n);
+    PCRL_TRY_HIP(hipMemcpyAsync(h_ray.data(), paths->ray, n * 8, hipMemcpyDeviceToHost, s));
+    PCRL_TRY_HIP(hipMemcpyAsync(h_n.data(), paths->n_refl, n * 4, hipMemcpyDeviceToHost, s));
+    PCRL_TRY_HIP(hipStreamSynchronize(s));
+    for (int64_t i = 0; i < n; ++i) {
+        const int k = (int)(h_ray[i] >> 40);
+        const int64_t node = h_ray[i] & ((1ll << 40) - 1);
+        const bool ok = h_ray[i] >= 0 && k == h_n[i] && k <= K &&
+                        (k == 0 ? node < L->n_tx : (k < (int)L->gens.size() && node < L->gens[k].n));
+        if (!ok) {
+            set_error("refine_cone_paths: row %lld (ray %lld, n_refl %d) is not a reception of this launch",
+                      (long long)i, (long long)h_ray[i], h_n[i]);
+            return PCRL_EINVAL;
+        }
+    }
+    DevBufs T;
+    T.stream = s;
+    auto fail = [&](int rc) { T.release(); return rc; };
+    float *tx3 = nullptr, *rx3 = nullptr;
+    int32_t* edge_of = nullptr;
+    int rc;
+    if ((rc = T.alloc(&tx3, (size_t)L->n_tx * 3)) || (rc = T.alloc(&rx3, (size_t)L->n_rx * 3))) return fail(rc);
+    hipError_t e = hipMemcpy2DAsync(tx3, 12, L->tx, 16, 12, L->n_tx, hipMemcpyDeviceToDevice, s);
+    if (e == hipSuccess) e = hipMemcpy2DAsync(rx3, 12, L->rx, 16, 12, L->n_rx, hipMemcpyDeviceToDevice, s);
+    if (e != hipSuccess) {
+        set_error("refine_cone_paths: copy failed: %s", hipGetErrorString(e));
+        return fail(PCRL_EHIP);
+    }
+    PcrlRefineParams P{};
+    if (params) P = *params;
+    if (I->n_lines > 0 && K > 0) {
+        if ((rc = T.alloc(&edge_of, (size_t)n * K))) return fail(rc);
+        RowEdgeArgs a{};
+        a.ray = paths->ray;
+        a.n = (uint32_t)n;
+        a.K = K;
+        for (int j = 1; j < (int)L->gens.size() && j <= PCRL_MAX_REFLECTIONS; ++j) {
+            a.ie[j] = L->gens[j].ie;
+            a.parent[j] = L->gens[j].parent;
+        }
+        a.type = I->type;
+        a.eid = I->eid;
+        a.edge_of = edge_of;
+        hipLaunchKernelGGL(k_row_edges, dim3(blocks(n)), dim3(256), 0, s, a);
+        if (hipGetLastError() != hipSuccess) {
+            set_error("refine_cone_paths: kernel launch failed");
+            return fail(PCRL_EHIP);
+        }
+        P.edge_of = edge_of;
+        P.n_edges = (int32_t)I->n_lines;
+        P.edge_seg = I->line_seg;
+        P.edge_normals = I->line_nrm;
+        P.edge_label = I->line_label;
+    }
+    rc = refine_paths(I->scene, tx3, L->n_tx, rx3, L->n_rx, paths, K, &P, out, stream);
+    if (hipStreamSynchronize(s) != hipSuccess && !rc) {
+        set_error("refine_cone_paths: HIP error: %s", hipGetErrorString(hipGetLastError()));
+        rc = PCRL_EHIP;
+    }
+    T.release();
+    return rc;
 }
 
 extern "C" int release_cone(PcrlConeLaunch* launch) {

@@ -17,6 +17,11 @@
 //     as a launched ray; a ray that hits nothing ends the path (invalid).
 // With PCRL_REFINE_SMOOTH the normal at c_k is instead the weighted average
 // of the normals of the points near c_k (the smooth normal of Eq. 1).
+// A diffraction point D_k = a + t_k w stays on its edge (Section 2.3): t_k
+// steps along G_k . w with the same a_k, no ray is traced to it, a ray
+// leaving it starts r_s along its direction (the surfels of the edge's own
+// faces meet the edge), a segment arriving at it is blocked only by a hit
+// more than r_s before it, and a step off the edge's segment ends the path.
 // The first c_k come from the same tracing towards the coarse points.  A
 // converged path is kept if every interaction has both neighbours on one
 // side of its surfel and the last segment reaches the RX unblocked.
@@ -67,7 +72,18 @@ struct RefineArgs {
     float* out_pts;             // [n][K][3]
     int32_t* out_id;            // [n][K]
     int64_t* out_key;           // [n][K]
+    // diffraction edges (p_edge null: reflections only)
+    const int32_t* p_edge;      // [n][K]: edge of interaction k, -1 a reflection
+    const float4* e_a;          // per edge: end point a, length |b - a| in w
+    const float4* e_w;          // per edge: unit direction, label (bits) in w
+    const float4* e_n1;         // per edge: outward normals of its two faces
+    const float4* e_n2;
+    float clear;                // r_s: the clearance at a diffraction point
 };
+
+__device__ __forceinline__ int edge_at(const RefineArgs& a, uint32_t p, int k) {
+    return a.p_edge ? a.p_edge[(size_t)p * a.K + k] : -1;
+}
 
 __device__ __forceinline__ float dist3(const float a[3], const float b[3]) {
     const float x = a[0] - b[0], y = a[1] - b[1], z = a[2] - b[2];
@@ -79,13 +95,14 @@ __device__ __forceinline__ int wave_max(int x) {
     return __builtin_amdgcn_readlane(wave_scan_max_dpp(x), 63);
 }
 
-// Trace every lane's ray from o towards `target` (lanes with `act` false
-// only help with the leaf tests).  Returns the hit in `hit`; `len` is the
-// distance from o to the target (0: the target is o, no ray).
+// Trace every lane's ray from o towards `target`, starting `skip` along its
+// direction (lanes with `act` false only help with the leaf tests).  Returns
+// the hit in `hit` (t from the start os = o + skip d); `len` is the distance
+// from o to the target (0: the target is o, no ray).
 template <int NL, bool OV>
 __device__ __forceinline__ void trace_towards(const RefineArgs& a, LeafTestLds& W, bool act, const float o[3],
-                                              const float target[3], uint32_t last, Hit& hit, float d[3], float& len,
-                                              stat_t cnt[ST_COUNT]) {
+                                              const float target[3], uint32_t last, float skip, Hit& hit, float d[3],
+                                              float os[3], float& len, stat_t cnt[ST_COUNT]) {
     d[0] = target[0] - o[0];
     d[1] = target[1] - o[1];
     d[2] = target[2] - o[2];
@@ -100,10 +117,13 @@ __device__ __forceinline__ void trace_towards(const RefineArgs& a, LeafTestLds& 
         d[0] = 1.f;
         d[1] = d[2] = 0.f;
     }
+    os[0] = o[0] + skip * d[0];
+    os[1] = o[1] + skip * d[1];
+    os[2] = o[2] + skip * d[2];
     hit_reset(hit);
-    stage_ray(W, o, d, last);
-    trace_segment<false, NL, false>(a.t, W, go, o, d, hit, cnt);
-    if (OV) trace_segment<false, NL, true>(a.t, W, go, o, d, hit, cnt);
+    stage_ray(W, os, d, last);
+    trace_segment<false, NL, false>(a.t, W, go, os, d, hit, cnt);
+    if (OV) trace_segment<false, NL, true>(a.t, W, go, os, d, hit, cnt);
 }
 
 // Add the weighted normals of the points of hierarchy v within sqrt(h2) of c
@@ -176,7 +196,14 @@ __global__ __launch_bounds__(REFINE_BLOCK) void k_refine(RefineArgs a) {
         R[2] = a.rx[3 * ri + 2];
         for (int k = 0; k < N; ++k) {
             const float* q = a.p_pts + ((size_t)p * a.K + k) * 3;
-            a.tgt[k * n + p] = make_float4(q[0], q[1], q[2], 0.f);
+            // a diffraction point starts at the coarse point's projection onto its edge (t in w)
+            float t = 0.f;
+            const int e = edge_at(a, p, k);
+            if (e >= 0) {
+                const float4 A = a.e_a[e], Wd = a.e_w[e];
+                t = (q[0] - A.x) * Wd.x + (q[1] - A.y) * Wd.y + (q[2] - A.z) * Wd.z;
+            }
+            a.tgt[k * n + p] = make_float4(q[0], q[1], q[2], t);
         }
     }
     const int nmax = wave_max(N);
@@ -185,16 +212,29 @@ __global__ __launch_bounds__(REFINE_BLOCK) void k_refine(RefineArgs a) {
     float gnorm = 0.f;
     bool run = in && N > 0;
     while (__ballot(run)) {
-        // the rays towards the targets give the new interaction points
+        // the interaction points: diffraction points on their edges, reflection points where the
+        // rays towards the targets hit
         float o[3] = {T[0], T[1], T[2]};
         uint32_t last = NO_HIT;
+        float skip = 0.f;
         for (int k = 0; k < nmax; ++k) {
             const bool act = run && k < N;
-            float tg[3] = {0.f, 0.f, 0.f}, d[3], len;
+            const int e = act ? edge_at(a, p, k) : -1;
+            float tg[3] = {0.f, 0.f, 0.f}, d[3], os[3], len;
             if (act) load3(&a.tgt[k * n + p], tg);
             Hit hit;
-            trace_towards<NL, OV>(a, W, act, o, tg, last, hit, d, len, cnt);
-            if (act) {
+            trace_towards<NL, OV>(a, W, act && e < 0, o, tg, last, skip, hit, d, os, len, cnt);
+            if (act && e >= 0) {
+                const float4 A = a.e_a[e], Wd = a.e_w[e];
+                const float t = a.tgt[k * n + p].w;
+                o[0] = A.x + t * Wd.x;
+                o[1] = A.y + t * Wd.y;
+                o[2] = A.z + t * Wd.z;
+                last = NO_HIT;
+                skip = a.clear;
+                a.cpos[k * n + p] = make_float4(o[0], o[1], o[2], __uint_as_float(NO_HIT));
+                a.cnrm[k * n + p] = make_float4(0.f, 0.f, 0.f, Wd.w);
+            } else if (act) {
                 if (!(len > 0.f)) {
                     status = PCRL_REFINE_DEGENERATE;
                     run = false;
@@ -202,10 +242,11 @@ __global__ __launch_bounds__(REFINE_BLOCK) void k_refine(RefineArgs a) {
                     status = PCRL_REFINE_MISS;
                     run = false;
                 } else {
-                    o[0] = o[0] + hit.t * d[0];
-                    o[1] = o[1] + hit.t * d[1];
-                    o[2] = o[2] + hit.t * d[2];
+                    o[0] = os[0] + hit.t * d[0];
+                    o[1] = os[1] + hit.t * d[1];
+                    o[2] = os[2] + hit.t * d[2];
                     last = hit.id;
+                    skip = 0.f;
                     float nr[3] = {hit.nx, hit.ny, hit.nz};
                     if (a.smooth_h2 > 0.f) {
                         float acc[3] = {0.f, 0.f, 0.f};
@@ -224,10 +265,12 @@ __global__ __launch_bounds__(REFINE_BLOCK) void k_refine(RefineArgs a) {
             }
         }
         if (!run) continue;
-        // tangent-plane gradient of the path length and the next targets
+        // gradient of the path length (tangent planes of reflections, edge directions of
+        // diffractions) and the next targets
         float prev[3] = {T[0], T[1], T[2]}, cur[3], next[3];
         load3(&a.cpos[p], cur);
         float gg = 0.f;
+        bool off = false;
         for (int k = 0; k < N; ++k) {
             if (k + 1 < N) load3(&a.cpos[(k + 1) * n + p], next);
             else {
@@ -241,20 +284,29 @@ __global__ __launch_bounds__(REFINE_BLOCK) void k_refine(RefineArgs a) {
                 run = false;
                 break;
             }
-            float nrm[3];
-            load3(&a.cnrm[k * n + p], nrm);
-            float g[3];
-            float gn = 0.f;
+            float G[3];
 #pragma unroll
-            for (int j = 0; j < 3; ++j) {
-                g[j] = (cur[j] - prev[j]) / lp + (cur[j] - next[j]) / ln;
-                gn += g[j] * nrm[j];
-            }
-#pragma unroll
-            for (int j = 0; j < 3; ++j) g[j] -= gn * nrm[j];
-            gg += g[0] * g[0] + g[1] * g[1] + g[2] * g[2];
+            for (int j = 0; j < 3; ++j) G[j] = (cur[j] - prev[j]) / lp + (cur[j] - next[j]) / ln;
             const float ak = a.step / (1.0f / lp + 1.0f / ln);
-            a.tgt[k * n + p] = make_float4(cur[0] - ak * g[0], cur[1] - ak * g[1], cur[2] - ak * g[2], 0.f);
+            const int e = edge_at(a, p, k);
+            if (e >= 0) {
+                const float4 A = a.e_a[e], Wd = a.e_w[e];
+                const float gw = G[0] * Wd.x + G[1] * Wd.y + G[2] * Wd.z;
+                gg += gw * gw;
+                const float4 tq = a.tgt[k * n + p];
+                const float t = tq.w - ak * gw;
+                off = off || !(t >= 0.f && t <= A.w);
+                a.tgt[k * n + p] = make_float4(tq.x, tq.y, tq.z, t);
+            } else {
+                float nrm[3];
+                load3(&a.cnrm[k * n + p], nrm);
+                const float gn = G[0] * nrm[0] + G[1] * nrm[1] + G[2] * nrm[2];
+                float g[3];
+#pragma unroll
+                for (int j = 0; j < 3; ++j) g[j] = G[j] - gn * nrm[j];
+                gg += g[0] * g[0] + g[1] * g[1] + g[2] * g[2];
+                a.tgt[k * n + p] = make_float4(cur[0] - ak * g[0], cur[1] - ak * g[1], cur[2] - ak * g[2], 0.f);
+            }
 #pragma unroll
             for (int j = 0; j < 3; ++j) {
                 prev[j] = cur[j];
@@ -268,11 +320,15 @@ __global__ __launch_bounds__(REFINE_BLOCK) void k_refine(RefineArgs a) {
         } else if (it == a.max_iters) {
             status = PCRL_REFINE_NOT_CONVERGED;
             run = false;
+        } else if (off) {
+            status = PCRL_REFINE_OFF_EDGE;
+            run = false;
         } else {
             ++it;
         }
     }
-    // a reflection keeps both neighbours on one side of its surfel
+    // a reflection keeps both neighbours on one side of its surfel; a diffraction has both
+    // outside its edge's wedge
     if (in && status == PCRL_REFINE_VALID && N > 0) {
         float prev[3] = {T[0], T[1], T[2]}, cur[3], next[3], nrm[3];
         load3(&a.cpos[p], cur);
@@ -283,14 +339,26 @@ __global__ __launch_bounds__(REFINE_BLOCK) void k_refine(RefineArgs a) {
                 next[1] = R[1];
                 next[2] = R[2];
             }
-            load3(&a.cnrm[k * n + p], nrm);
-            float sp = 0.f, sn = 0.f;
+            const int e = edge_at(a, p, k);
+            bool ok;
+            if (e >= 0) {
+                const float4 N1 = a.e_n1[e], N2 = a.e_n2[e];
+                const float p1 = (prev[0] - cur[0]) * N1.x + (prev[1] - cur[1]) * N1.y + (prev[2] - cur[2]) * N1.z;
+                const float p2 = (prev[0] - cur[0]) * N2.x + (prev[1] - cur[1]) * N2.y + (prev[2] - cur[2]) * N2.z;
+                const float q1 = (next[0] - cur[0]) * N1.x + (next[1] - cur[1]) * N1.y + (next[2] - cur[2]) * N1.z;
+                const float q2 = (next[0] - cur[0]) * N2.x + (next[1] - cur[1]) * N2.y + (next[2] - cur[2]) * N2.z;
+                ok = (p1 > 0.f || p2 > 0.f) && (q1 > 0.f || q2 > 0.f);
+            } else {
+                load3(&a.cnrm[k * n + p], nrm);
+                float sp = 0.f, sn = 0.f;
 #pragma unroll
-            for (int j = 0; j < 3; ++j) {
-                sp += (prev[j] - cur[j]) * nrm[j];
-                sn += (next[j] - cur[j]) * nrm[j];
+                for (int j = 0; j < 3; ++j) {
+                    sp += (prev[j] - cur[j]) * nrm[j];
+                    sn += (next[j] - cur[j]) * nrm[j];
+                }
+                ok = sp * sn > 0.f;
             }
-            if (!(sp * sn > 0.f)) {
+            if (!ok) {
                 status = PCRL_REFINE_WRONG_SIDE;
                 break;
             }
@@ -301,24 +369,53 @@ __global__ __launch_bounds__(REFINE_BLOCK) void k_refine(RefineArgs a) {
             }
         }
     }
+    // segments arriving at a diffraction point: blocked by a hit more than r_s before it
+    if (a.p_edge) {
+        for (int k = 0; k < nmax; ++k) {
+            const bool act = in && status == PCRL_REFINE_VALID && k < N && edge_at(a, p, k) >= 0;
+            float o[3] = {T[0], T[1], T[2]}, tg[3] = {0.f, 0.f, 0.f};
+            uint32_t last = NO_HIT;
+            float skip = 0.f;
+            if (act) {
+                load3(&a.cpos[k * n + p], tg);
+                if (k > 0) {
+                    const float4 c = a.cpos[(k - 1) * n + p];
+                    o[0] = c.x;
+                    o[1] = c.y;
+                    o[2] = c.z;
+                    if (edge_at(a, p, k - 1) >= 0) skip = a.clear;
+                    else last = __float_as_uint(c.w);
+                }
+            }
+            float d[3], os[3], len;
+            Hit hit;
+            trace_towards<NL, OV>(a, W, act, o, tg, last, skip, hit, d, os, len, cnt);
+            if (act) {
+                if (!(len > 0.f)) status = PCRL_REFINE_DEGENERATE;
+                else if (hit.id != NO_HIT && skip + hit.t < len - a.clear) status = PCRL_REFINE_OCCLUDED;
+            }
+        }
+    }
     // the last segment must reach the RX unblocked
     {
         const bool act = in && status == PCRL_REFINE_VALID;
         float o[3] = {T[0], T[1], T[2]};
         uint32_t last = NO_HIT;
+        float skip = 0.f;
         if (act && N > 0) {
             const float4 c = a.cpos[(N - 1) * n + p];
             o[0] = c.x;
             o[1] = c.y;
             o[2] = c.z;
-            last = __float_as_uint(c.w);
+            if (edge_at(a, p, N - 1) >= 0) skip = a.clear;
+            else last = __float_as_uint(c.w);
         }
-        float d[3], len;
+        float d[3], os[3], len;
         Hit hit;
-        trace_towards<NL, OV>(a, W, act, o, R, last, hit, d, len, cnt);
+        trace_towards<NL, OV>(a, W, act, o, R, last, skip, hit, d, os, len, cnt);
         if (act) {
             if (!(len > 0.f)) status = PCRL_REFINE_DEGENERATE;
-            else if (hit.id != NO_HIT && hit.t < len) status = PCRL_REFINE_OCCLUDED;
+            else if (hit.id != NO_HIT && skip + hit.t < len) status = PCRL_REFINE_OCCLUDED;
         }
     }
     if (!in) return;
@@ -340,7 +437,8 @@ __global__ __launch_bounds__(REFINE_BLOCK) void k_refine(RefineArgs a) {
             q[0] = c.x;
             q[1] = c.y;
             q[2] = c.z;
-            a.out_id[(size_t)p * a.K + k] = (int32_t)__float_as_uint(c.w);
+            const int e = edge_at(a, p, k);
+            a.out_id[(size_t)p * a.K + k] = e >= 0 ? -2 - e : (int32_t)__float_as_uint(c.w);
             a.out_key[(size_t)p * a.K + k] = (int64_t)__float_as_uint(m.w);
         }
         f += dist3(R, prev);
@@ -355,6 +453,25 @@ __global__ __launch_bounds__(REFINE_BLOCK) void k_refine(RefineArgs a) {
     a.iters[p] = it;
     a.grad[p] = finite ? gnorm : NAN;
     a.length[p] = finite ? f : NAN;
+}
+
+// Per edge of refine_paths' edge table: start point and length, unit
+// direction and label, the two face normals.  Zero-length edges are counted
+// in *bad.
+__global__ void k_refine_edges(const float* seg, const float* nrm, const uint32_t* label, uint32_t n, float4* ea,
+                               float4* ew, float4* en1, float4* en2, uint32_t* bad) {
+    const uint32_t i = blockIdx.x * blockDim.x + threadIdx.x;
+    if (i >= n) return;
+    const float* s = seg + 6 * (size_t)i;
+    const float* m = nrm + 6 * (size_t)i;
+    const float d[3] = {s[3] - s[0], s[4] - s[1], s[5] - s[2]};
+    const float L = sqrtf(d[0] * d[0] + d[1] * d[1] + d[2] * d[2]);
+    if (!(L > 0.f)) atomicAdd(bad, 1u);
+    const float inv = L > 0.f ? 1.0f / L : 0.f;
+    ea[i] = make_float4(s[0], s[1], s[2], L);
+    ew[i] = make_float4(d[0] * inv, d[1] * inv, d[2] * inv, __uint_as_float(label[i]));
+    en1[i] = make_float4(m[0], m[1], m[2], 0.f);
+    en2[i] = make_float4(m[3], m[4], m[5], 0.f);
 }
 
 // Sort key of a refined path: its group (the first row of its (TX, RX,
@@ -531,6 +648,23 @@ extern "C" int refine_paths(const PcrlScene* scene, const float* tx, int32_t n_t
             }
         }
     }
+    // diffraction edges: indices checked on the host (the table is small)
+    const bool has_edges = P.edge_of != nullptr && k_stride > 0;
+    if (has_edges) {
+        if (P.n_edges < 1 || !P.edge_seg || !P.edge_normals || !P.edge_label) {
+            set_error("refine_paths: edge_of needs n_edges >= 1 edges with segments, normals and labels");
+            return PCRL_EINVAL;
+        }
+        std::vector<int32_t> h_e((size_t)n * k_stride);
+        PCRL_TRY_HIP(hipMemcpyAsync(h_e.data(), P.edge_of, h_e.size() * 4, hipMemcpyDeviceToHost, s));
+        PCRL_TRY_HIP(hipStreamSynchronize(s));
+        for (size_t i = 0; i < h_e.size(); ++i)
+            if (h_e[i] < -1 || h_e[i] >= P.n_edges) {
+                set_error("refine_paths: row %lld interaction %d has edge %d (n_edges %d)",
+                          (long long)(i / k_stride), (int)(i % k_stride), h_e[i], P.n_edges);
+                return PCRL_EINVAL;
+            }
+    }
     DevBufs T;
     T.stream = s;
     RefineArgs a{};
@@ -568,6 +702,32 @@ extern "C" int refine_paths(const PcrlScene* scene, const float* tx, int32_t n_t
     if (!rc && !(rc = T.alloc(&keys, n)) && !(rc = T.alloc(&idx, n))) rc = T.alloc(&counters, 2);
     if (!rc) rc = fill_u32(counters, 0u, 2, s);
     if (!rc) rc = fill_u32((uint32_t*)out->kept, 0u, n, s);
+    if (!rc && has_edges) {
+        const uint32_t ne = (uint32_t)P.n_edges;
+        float4 *ea = nullptr, *ew = nullptr, *en1 = nullptr, *en2 = nullptr;
+        if (!(rc = T.alloc(&ea, ne)) && !(rc = T.alloc(&ew, ne)) && !(rc = T.alloc(&en1, ne)) &&
+            !(rc = T.alloc(&en2, ne))) {
+            hipLaunchKernelGGL(k_refine_edges, dim3((ne + 255) / 256), dim3(256), 0, s, P.edge_seg, P.edge_normals,
+                               P.edge_label, ne, ea, ew, en1, en2, counters);
+            uint32_t bad = 0;
+            if (hipMemcpyAsync(&bad, counters, 4, hipMemcpyDeviceToHost, s) != hipSuccess ||
+                hipStreamSynchronize(s) != hipSuccess) {
+                set_error("refine_paths: edge table failed: %s", hipGetErrorString(hipGetLastError()));
+                rc = PCRL_EHIP;
+            } else if (bad) {
+                set_error("refine_paths: %u edges have zero length", bad);
+                rc = PCRL_EINVAL;
+            } else {
+                rc = fill_u32(counters, 0u, 2, s);
+            }
+        }
+        a.p_edge = P.edge_of;
+        a.e_a = ea;
+        a.e_w = ew;
+        a.e_n1 = en1;
+        a.e_n2 = en2;
+    }
+    a.clear = scene->view.r_s;
     if (rc) {
         T.release();
         return rc;

@@ -70,7 +70,7 @@ def test_struct_sizes(pcrl):
     assert C.sizeof(_lib.PcrlLaunchParams) == 64
     assert C.sizeof(_lib.PcrlSceneInfo) == 168
     assert C.sizeof(_lib.PcrlPaths) == 13 * 8
-    assert C.sizeof(_lib.PcrlRefineParams) == 24
+    assert C.sizeof(_lib.PcrlRefineParams) == 64
     assert C.sizeof(_lib.PcrlRefined) == 9 * 8
     assert C.sizeof(_lib.PcrlSdfParams) == 24
 
@@ -134,3 +134,36 @@ def test_no_cpu_fallback(tmp_path, monkeypatch):
         _lib._load()
     assert "paper_2402_13747_amd" in sys.modules
     importlib.invalidate_caches()
+
+
+STRUCTS = ["PcrlAllocator", "PcrlVoxelParams", "PcrlSceneInfo", "PcrlLaunchParams", "PcrlLaunchStats", "PcrlQuery",
+           "PcrlBatchParams", "PcrlPaths", "PcrlRefineParams", "PcrlRefined", "PcrlSdfParams", "PcrlIeGrid",
+           "PcrlIeInfo", "PcrlConeParams", "PcrlConeStats", "PcrlServeParams", "PcrlServeResult", "PcrlServeStats"]
+
+
+def test_binding_structs_match_the_header(pcrl, tmp_path):
+    """Every struct of include/pcrl.h, compiled by the host C compiler, has the
+    size and field offsets of its ctypes twin."""
+    import shutil
+    import subprocess
+    from paper_2402_13747_amd import _lib
+    cc = shutil.which("gcc") or shutil.which("cc")
+    if cc is None:
+        pytest.skip("no host C compiler")
+    inc = os.path.join(os.path.dirname(os.path.dirname(os.path.abspath(__file__))), "include")
+    lines = ["#include <stdio.h>", "#include <stddef.h>", '#include "pcrl.h"', "int main(void) {"]
+    for name in STRUCTS:
+        lines.append(f'    printf("{name} size %zu\\n", sizeof({name}));')
+        for f in getattr(_lib, name)._fields_:
+            lines.append(f'    printf("{name} {f[0]} %zu\\n", offsetof({name}, {f[0]}));')
+    lines += ["    return 0;", "}"]
+    src = tmp_path / "abi.c"
+    src.write_text("\n".join(lines) + "\n")
+    exe = tmp_path / "abi"
+    subprocess.run([cc, "-std=c11", "-I", inc, str(src), "-o", str(exe)], check=True, capture_output=True)
+    out = subprocess.run([str(exe)], check=True, capture_output=True, text=True).stdout.split("\n")
+    for line in filter(None, out):
+        name, field, value = line.split()
+        cls = getattr(_lib, name)
+        want = C.sizeof(cls) if field == "size" else getattr(cls, field).offset
+        assert int(value) == want, (name, field, int(value), want)

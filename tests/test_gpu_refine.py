@@ -327,3 +327,131 @@ def test_refine_over_overlay_equals_rebuilt_scene(env):
     for k in ("length", "grad", "points"):
         assert np.array_equal(r0[k], r1[k], equal_nan=True), k
     assert ((r0["key"] == 9).any(axis=1) & (r0["status"] == pcrl.REFINE_VALID)).any()   # off the dynamic box
+
+
+# --------------------------------------------------------------------------- diffraction (Section 2.3)
+
+CORNER_TX = np.array([(-3.0, 5.0, 3.0), (-3.0, 5.0, 8.0), (-3.0, 5.0, 1.5)], np.float32)
+CORNER_RX = np.array([(5.0, -3.0, 1.5), (3.0, 3.0, 1.5), (5.0, -3.0, -1.0)], np.float32)
+
+
+def _corner_rows(cone):
+    """Coarse rows at the corner building, from the oracle only: edge pieces of the vertical edge at
+    (0, 0) (oracle/cone.py's edge IEs), ground points placed by hand, and the receptions of the
+    oracle's own cone trace (TX 2, one diffraction).  Returns (rows sorted by (tx, rx, n), the
+    expected status of the hand-made ones or None)."""
+    s = scenes.corner_building()
+    E = s.extra["edges"]
+    origin, dims = np.array([-10.292, -10.292, -0.292], np.float32), (53, 53, 13)
+    eies = cone.edge_ies(E["seg"], E["normals"], E["label"], origin, 0.4, 2, dims)
+    on0 = np.nonzero(eies["edge"] == 0)[0]
+
+    def piece(z):
+        return eies["pos"][on0[np.argmin(np.abs(eies["pos"][on0, 2] - z))]]
+    ground_a = np.array([1.5, -1.2, 0.0])
+    V, OFF, WS, OCC = 0, 6, 3, 4
+    rows = [  # (tx, rx, points, edges, expected status)
+        (0, 0, [piece(1.0)], [0], V), (0, 0, [piece(2.5)], [0], V), (0, 0, [piece(3.7)], [0], V),
+        (0, 0, [piece(1.0), ground_a], [0, -1], V),
+        (0, 1, [piece(1.0)], [0], WS),                       # RX inside the building
+        (0, 2, [piece(1.0)], [0], OCC),                      # RX under the ground
+        (1, 0, [piece(3.7)], [0], OFF),                      # the stationary point is at 4.75 m
+    ]
+    # the oracle's cone trace from TX 2 (the default corner scene): its receptions through the edge
+    ies = cone.ie_build(s.xyz, s.normal, s.label, origin, 0.4, 2, dims)
+    sc = cone.Scene(s.xyz, s.normal, s.label, s.surfel_radius, s.t_eps_value)
+    res = cone.trace(sc, ies, CORNER_TX[2:3], CORNER_RX[0:1], origin, 0.4, 2, dims, K=1, kappa=100,
+                     half_angle=math.radians(2.5), edges=eies, max_diff=1)
+    C = cone.combine(ies, eies)
+    for r in res["records"]:
+        if r["exact"]:
+            rows.append((2, 0, [C["pos"][e] for e in r["chain"]], [int(C["edge"][e]) for e in r["chain"]], V))
+    rows.sort(key=lambda r: (r[0], r[1], len(r[2])))
+    return s, rows
+
+
+def _rows_arrays(rows, K):
+    n = len(rows)
+    pts = np.full((n, K, 3), np.nan, np.float32)
+    eo = np.full((n, K), -1, np.int32)
+    for i, (_, _, ps, es, _) in enumerate(rows):
+        pts[i, :len(ps)] = np.asarray(ps, np.float32)
+        eo[i, :len(es)] = es
+    return dict(tx=np.array([r[0] for r in rows], np.int32), rx=np.array([r[1] for r in rows], np.int32),
+                n_refl=np.array([len(r[2]) for r in rows], np.int32), points=pts, n_rows=n), eo
+
+
+def test_refine_diffraction_corner(env):
+    """Diffraction points on the corner building's vertical edge against the oracle, row by row:
+    outcomes, steps, labels, lengths and points; the closed forms sqrt(136 + 1.5^2) (one
+    diffraction, TX at 3 m) and 12.5 (diffraction then ground reflection); Keller's law at
+    every valid diffraction point; the dedup against the oracle's."""
+    torch, pcrl, oracle = env
+    from oracle import cone
+    s, rows = _corner_rows(cone)
+    K = 2
+    p, eo = _rows_arrays(rows, K)
+    E = s.extra["edges"]
+    r_s, t_eps = float(np.float32(s.surfel_radius)), float(np.float32(parity.t_eps_of(s)))
+    print(f"[refine] corner building: {len(rows)} rows with diffraction points", flush=True)
+    scene = pcrl.build_voxels(s.xyz, s.normal, s.label, s.levels, r_s, t_eps=t_eps)
+    P = {k: torch.from_numpy(v).cuda() if isinstance(v, np.ndarray) else v for k, v in p.items()}
+    r = parity.to_numpy(pcrl.refine_paths(scene, CORNER_TX, CORNER_RX, P, edges=E, edge_of=eo))
+    o = oracle.refine(s.xyz, s.normal, s.label, r_s, t_eps, CORNER_TX[p["tx"]].astype(np.float64),
+                      CORNER_RX[p["rx"]].astype(np.float64), p["n_refl"], p["points"].astype(np.float64),
+                      edges=E, edge_of=eo)
+    want = np.array([w for *_, w in rows])
+    assert np.array_equal(o["status"], want), (o["status"], want)
+    rows_all = np.arange(len(rows))
+    assert _compare_rows(s, p, r, o, rows_all) == int((want == 0).sum())
+    w = np.array([0.0, 0.0, 1.0])
+    for i in np.nonzero(r["status"] == 0)[0]:
+        N = p["n_refl"][i]
+        I = [CORNER_TX[p["tx"][i]].astype(np.float64)] + list(r["points"][i, :N].astype(np.float64)) + \
+            [CORNER_RX[p["rx"][i]].astype(np.float64)]
+        for k in range(N):
+            if eo[i, k] >= 0:
+                assert r["point_id"][i, k] == -2 - eo[i, k] and r["key"][i, k] == 100 + eo[i, k]
+                u, v = I[k + 1] - I[k], I[k + 2] - I[k + 1]
+                assert abs(u @ w / np.linalg.norm(u) - v @ w / np.linalg.norm(v)) <= 1e-3
+        if p["tx"][i] == 0 and N == 1:
+            L = math.sqrt(136.0 + 1.5 ** 2)
+            assert abs(r["length"][i] - L) <= 1e-5 * L
+        if p["tx"][i] == 0 and N == 2:
+            assert abs(r["length"][i] - 12.5) <= 1e-5 * 12.5
+        if p["tx"][i] == 2:
+            L = 2.0 * math.sqrt(34.0)
+            assert abs(r["length"][i] - L) <= 1e-5 * L
+    grp = p["tx"].astype(np.int64) * 65536 + p["rx"]
+    kept = oracle.refine_dedup(grp, p["n_refl"], r["key"], r["points"], r["length"], r["status"],
+                               CORNER_TX[p["tx"]].astype(np.float64))
+    assert np.array_equal(kept, r["kept"].astype(bool))
+
+
+def test_refine_cone_paths_corner(env):
+    """refine_cone_paths on the cone tracer's own coarse paths (two interactions, one diffraction):
+    equal to refine_paths given the edges explicitly (each edge's label is 100 + its index); the
+    corner diffraction (label 100) is kept with length 2 sqrt(34)."""
+    torch, pcrl, oracle = env
+    s = scenes.corner_building()
+    E = s.extra["edges"]
+    r_s, t_eps = float(np.float32(s.surfel_radius)), float(np.float32(parity.t_eps_of(s)))
+    scene = pcrl.build_voxels(s.xyz, s.normal, s.label, s.levels, r_s, t_eps=t_eps)
+    origin, dims = np.array([-10.292, -10.292, -0.292], np.float32), np.array([53, 53, 13])
+    ies = pcrl.ie_build(scene, origin, 0.4, 2, dims)
+    ies.add_edges(E["seg"], E["normals"], E["label"])
+    L = pcrl.cone_launch(ies, s.tx, s.rx, 2, math.radians(2.5), max_diffractions=1)
+    P = pcrl.cone_collect(L, kappa=1 << 20)
+    print(f"[refine] corner building cone paths: {P['n_rows']} rows", flush=True)
+    r1 = parity.to_numpy(pcrl.refine_cone_paths(L, P))
+    key = P["key"].cpu().numpy()
+    eo = np.where(key >= 100, key - 100, -1).astype(np.int32)
+    r2 = parity.to_numpy(pcrl.refine_paths(scene, s.tx, s.rx, P, edges=E, edge_of=eo))
+    for k in ("status", "iters", "point_id", "key", "kept"):
+        assert np.array_equal(r1[k], r2[k]), k
+    for k in ("grad", "length", "points"):
+        assert np.array_equal(r1[k], r2[k], equal_nan=True), k
+    kept = [(tuple(int(x) for x in r1["key"][i, :int(P["n_refl"][i])]), float(r1["length"][i]))
+            for i in np.nonzero(r1["kept"])[0]]
+    Ls = [ln for seq, ln in kept if seq == (100,)]
+    assert len(Ls) == 1 and abs(Ls[0] - 2.0 * math.sqrt(34.0)) <= 1e-5 * 2.0 * math.sqrt(34.0)
