@@ -819,5 +819,31 @@ def main():
     print(json.dumps(out), flush=True)
 
 
+def reap_children():
+    """End any child process still alive (a worker pool or a compiler started
+    on the way) and name it on stderr, so that bench.py leaves nothing behind."""
+    try:
+        import psutil
+    except ImportError:
+        return
+    kids = psutil.Process().children(recursive=True)
+    for k in kids:
+        try:
+            log(f"[bench] child process left at exit: pid {k.pid} {' '.join(k.cmdline())[:200]}")
+            k.terminate()
+        except psutil.Error:
+            pass
+    if kids:
+        _, alive = psutil.wait_procs(kids, timeout=5)
+        for k in alive:
+            try:
+                k.kill()
+            except psutil.Error:
+                pass
+
+
 if __name__ == "__main__":
-    main()
+    try:
+        main()
+    finally:
+        reap_children()
