@@ -19,8 +19,8 @@
 //
 // Pipeline: ingest (normalise normals, validate, AABB, max label) -> sync ->
 // label ranks -> per-point leaf counts -> scan -> sync -> emit (key, id) ->
-// radix sort -> per-level boundary flags + scans -> sync -> level-0 map,
-// bricks, leaf ranges -> surfel gather.
+// radix sort -> per-tile node-start counts + their scan -> sync -> level-0
+// map, bricks, leaf ranges (one pass over the sorted keys) -> surfel gather.
 #include "internal.h"
 
 #include <algorithm>
@@ -152,7 +152,31 @@ struct KeyParams {
     float r_s;
     float pad;
     int32_t id_bits;   // packed 64-bit items: bits of the point index below the key
+    uint8_t* occ0;     // k_key_count: level-0 cells that a point's leaf box reaches (set to 1)
+    const uint32_t* c0;  // k_key_emit: rank of each such level-0 cell (the key's level-0 part)
 };
+
+// Hierarchical key of leaf (x, y, z) with level 0 numbered by `c0` (rank of
+// the level-0 cell among the occupied ones) or by its linear index (c0
+// null); the quotients use the traversal's magic divisions.  Equal to
+// leaf_key_of when c0 is null.
+__host__ __device__ __forceinline__ uint64_t leaf_key_fast(const SceneView& v, const uint32_t* c0, int x, int y, int z) {
+    int p[3] = {span_div(x, v.mspan[0]), span_div(y, v.mspan[0]), span_div(z, v.mspan[0])};
+    const uint32_t cell0 = (uint32_t)p[0] + (uint32_t)v.dim0[0] * ((uint32_t)p[1] + (uint32_t)v.dim0[1] * (uint32_t)p[2]);
+    uint64_t k = c0 ? (uint64_t)c0[cell0] : (uint64_t)cell0;
+#pragma unroll
+    for (int i = 1; i < PCRL_MAX_LEVELS; ++i) {
+        if (i >= v.nlev) break;
+        const int q[3] = {span_div(x, v.mspan[i]), span_div(y, v.mspan[i]), span_div(z, v.mspan[i])};
+        const int r = v.ratio[i - 1];
+        const int loc = (q[0] - r * p[0]) + r * ((q[1] - r * p[1]) + r * (q[2] - r * p[2]));
+        k = (k << v.lbits[i]) | (uint64_t)loc;
+        p[0] = q[0];
+        p[1] = q[1];
+        p[2] = q[2];
+    }
+    return k;
+}
 
 __device__ __forceinline__ void disk_leaf_box(const KeyParams& kp, const float* xyz, const float4* un, int64_t i,
                                               int lo[3], int hi[3]) {
@@ -191,9 +215,14 @@ __device__ __forceinline__ bool disk_meets_leaf(const KeyParams& kp, const float
     return d2 <= r * r && fabsf(dn) <= pr + kp.pad;
 }
 
+// Keys of one wave staged in LDS before a coalesced copy out (entries past
+// the stage are written directly).
+constexpr int EMIT_STAGE = 2048;
+
 template <bool EMIT, typename K>
 __device__ __forceinline__ uint32_t disk_leaves(const KeyParams& kp, const float* xyz, const float4* un, int64_t i,
-                                                K* keys, uint32_t* ids, uint32_t o) {
+                                                K* keys, uint32_t* ids, uint32_t o, K* stage = nullptr,
+                                                uint32_t base = 0) {
     int lo[3], hi[3];
     disk_leaf_box(kp, xyz, un, i, lo, hi);
     const float p[3] = {xyz[3 * i], xyz[3 * i + 1], xyz[3 * i + 2]};
@@ -207,12 +236,16 @@ __device__ __forceinline__ uint32_t disk_leaves(const KeyParams& kp, const float
                 const bool one = lo[0] == hi[0] && lo[1] == hi[1] && lo[2] == hi[2];
                 if (!one && !disk_meets_leaf(kp, p, nv, x, y, z)) continue;
                 if (EMIT) {
+                    const uint64_t key = leaf_key_fast(kp.v, kp.c0, x, y, z);
                     if (ids) {
-                        keys[o + k] = (K)leaf_key_of(kp.v, x, y, z);
+                        keys[o + k] = (K)key;
                         ids[o + k] = (uint32_t)i;
                     } else {
                         // packed: the key above the point index (one 8-byte item to sort)
-                        keys[o + k] = (K)((leaf_key_of(kp.v, x, y, z) << kp.id_bits) | (uint64_t)i);
+                        const K item = (K)((key << kp.id_bits) | (uint64_t)i);
+                        const uint32_t at = o + k;
+                        if (stage && at - base < (uint32_t)EMIT_STAGE) stage[at - base] = item;
+                        else keys[at] = item;
                     }
                 }
                 ++k;
@@ -220,12 +253,34 @@ __device__ __forceinline__ uint32_t disk_leaves(const KeyParams& kp, const float
     return k;
 }
 
-// Per point, the number of leaves its disk meets.
+// Per point, the number of leaves its disk meets; the level-0 cells its leaf
+// box reaches are marked in occ0 (a superset of those of its leaves).
 __global__ __launch_bounds__(BUILD_BLOCK) void k_key_count(KeyParams kp, const float* xyz, const float4* un, int64_t n,
                                                            uint32_t* cnt) {
     int64_t i = (int64_t)blockIdx.x * BUILD_BLOCK + threadIdx.x;
     if (i >= n) return;
     cnt[i] = disk_leaves<false, uint64_t>(kp, xyz, un, i, nullptr, nullptr, 0);
+    if (kp.occ0) {
+        int lo[3], hi[3];
+        disk_leaf_box(kp, xyz, un, i, lo, hi);
+        const SceneView& v = kp.v;
+        for (int cz = span_div(lo[2], v.mspan[0]); cz <= span_div(hi[2], v.mspan[0]); ++cz)
+            for (int cy = span_div(lo[1], v.mspan[0]); cy <= span_div(hi[1], v.mspan[0]); ++cy)
+                for (int cx = span_div(lo[0], v.mspan[0]); cx <= span_div(hi[0], v.mspan[0]); ++cx)
+                    kp.occ0[(size_t)cx + (size_t)v.dim0[0] * ((size_t)cy + (size_t)v.dim0[1] * cz)] = 1;
+    }
+}
+
+// Ranks of the marked level-0 cells (exclusive scan of occ0, widened to 32
+// bits first) and the inverse map rank -> cell.
+__global__ void k_occ0_widen(const uint8_t* occ0, int64_t n, uint32_t* out) {
+    const int64_t c = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (c < n) out[c] = occ0[c];
+}
+
+__global__ void k_occ0_unmap(const uint8_t* occ0, const uint32_t* rank, int64_t n, uint32_t* unmap) {
+    const int64_t c = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (c < n && occ0[c]) unmap[rank[c]] = (uint32_t)c;
 }
 
 // The counts' sum in 64 bits, for inputs whose 32-bit scan might wrap: a
@@ -238,13 +293,28 @@ __global__ __launch_bounds__(BUILD_BLOCK) void k_count_total(const uint32_t* cnt
     if (lane_id() == 0 && acc) atomicAdd(total, acc);
 }
 
-// Keys are 32-bit when the hierarchical key fits (less sort traffic), else 64-bit.
+// The (key, point) items of every point's leaves at its offset.  Packed items
+// (ids null) of a one-wave block are contiguous from its first point's
+// offset: they are staged in LDS and copied out with coalesced stores.
 template <typename K>
-__global__ __launch_bounds__(BUILD_BLOCK) void k_key_emit(KeyParams kp, const float* xyz, const float4* un, int64_t n,
-                                                          const uint32_t* off, K* keys, uint32_t* ids) {
-    int64_t i = (int64_t)blockIdx.x * BUILD_BLOCK + threadIdx.x;
-    if (i >= n) return;
-    (void)disk_leaves<true, K>(kp, xyz, un, i, keys, ids, off[i]);
+__global__ __launch_bounds__(64) void k_key_emit(KeyParams kp, const float* xyz, const float4* un, int64_t n,
+                                                 const uint32_t* off, K* keys, uint32_t* ids) {
+    const int64_t i = (int64_t)blockIdx.x * 64 + threadIdx.x;
+    const bool in = i < n;
+    if (ids) {
+        if (in) (void)disk_leaves<true, K>(kp, xyz, un, i, keys, ids, off[i]);
+        return;
+    }
+    __shared__ K stage[EMIT_STAGE];
+    const uint32_t o = in ? off[i] : 0u;
+    const uint32_t base = __builtin_amdgcn_readfirstlane(o);  // lane 0 holds the block's first point
+    const uint32_t cnt = in ? disk_leaves<true, K>(kp, xyz, un, i, keys, nullptr, o, stage, base) : 0u;
+    uint32_t end = in ? o + cnt : base;
+#pragma unroll
+    for (int sh = 32; sh >= 1; sh >>= 1) end = max(end, (uint32_t)__shfl_xor((int)end, sh, 64));
+    const uint32_t total = min(end - base, (uint32_t)EMIT_STAGE);
+    __syncthreads();
+    for (uint32_t j = threadIdx.x; j < total; j += 64) keys[(size_t)base + j] = stage[j];
 }
 
 // ---------------------------------------------------------------------------
@@ -256,19 +326,9 @@ struct LevelShifts {
     int32_t sh[PCRL_MAX_LEVELS];  // node key of level i = key >> sh[i]
 };
 
-// flag[l][e] = entry e starts a new node of level l
-// Levels of `flags` are `stride` apart (m rounded up to 4: 16-byte aligned rows).
-template <typename K>
-__global__ void k_level_flags(const K* keys, int64_t m, int64_t stride, LevelShifts ls, uint32_t* flags) {
-    int64_t e = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
-    if (e >= m) return;
-    const uint64_t k = keys[e];
-    const uint64_t kp = e > 0 ? keys[e - 1] : 0;
-    for (int l = 0; l < ls.nlev; ++l)
-        flags[(size_t)l * stride + e] = (e == 0 || (k >> ls.sh[l]) != (kp >> ls.sh[l])) ? 1u : 0u;
-}
-
 struct HierOut {
+    const uint32_t* unmap0;   // rank of an occupied level-0 cell -> the cell (null: keys hold the cell)
+    int32_t g_sh0;            // bits below the level-0 part of a key (without the packed point index)
     int32_t* map0;
     uint64_t* mask[PCRL_MAX_LEVELS - 1];
     uint32_t* first_child[PCRL_MAX_LEVELS - 1];
@@ -276,35 +336,96 @@ struct HierOut {
     uint64_t* leaf_key;
 };
 
-// For every entry that opens a node: register the node with its parent.
-// scans[l][e] is the exclusive scan of the level-l flags, so the node index
-// of entry e at level l is scans[l][e] + flag - 1.
-template <typename K>
-__global__ void k_hier_link(const K* keys, int64_t m, int64_t stride, LevelShifts ls, SceneView v,
-                            const uint32_t* scans, HierOut h, int id_bits) {
-    int64_t e = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
-    if (e >= m) return;
+// Node starts of every level from the sorted keys: an entry opens a node of
+// level l when its key differs from the previous entry's above bit sh[l].
+// A wave owns a tile of LINK_TILE consecutive entries, read in LINK_ROUNDS
+// coalesced rounds of 64 (lane j of round r: entry tile + 64 r + j).
+constexpr int LINK_ROUNDS = 16;
+constexpr int LINK_TILE = 64 * LINK_ROUNDS;
+
+__device__ __forceinline__ uint32_t link_flags(const uint64_t* keys, int64_t e, const LevelShifts& ls) {
     const uint64_t k = keys[e];
-    const uint64_t kp = e > 0 ? keys[e - 1] : 0;
+    const uint64_t prev = e > 0 ? keys[e - 1] : 0ull;
+    uint32_t f = 0;
+#pragma unroll
+    for (int l = 0; l < PCRL_MAX_LEVELS; ++l)
+        if (l < ls.nlev && (e == 0 || ((k ^ prev) >> ls.sh[l]) != 0)) f |= 1u << l;
+    return f;
+}
+
+// Per wave tile and level: the nodes that start in the tile ([level][tile]).
+__global__ __launch_bounds__(BUILD_BLOCK) void k_link_count(const uint64_t* keys, int64_t m, LevelShifts ls,
+                                                            uint32_t* tile_cnt, uint32_t n_tiles) {
+    const uint32_t tile = blockIdx.x * (BUILD_BLOCK / 64) + (threadIdx.x >> 6);
+    if (tile >= n_tiles) return;
+    uint32_t c[PCRL_MAX_LEVELS] = {0u, 0u, 0u, 0u};
+    for (int r = 0; r < LINK_ROUNDS; ++r) {
+        const int64_t e = (int64_t)tile * LINK_TILE + 64 * r + lane_id();
+        const uint32_t f = e < m ? link_flags(keys, e, ls) : 0u;
+#pragma unroll
+        for (int l = 0; l < PCRL_MAX_LEVELS; ++l) c[l] += (f >> l) & 1u;
+    }
+#pragma unroll
+    for (int l = 0; l < PCRL_MAX_LEVELS; ++l) {
+        const uint32_t t = (uint32_t)wave_sum_u64(c[l]);
+        if (l < ls.nlev && lane_id() == 0) tile_cnt[(size_t)l * n_tiles + tile] = t;
+    }
+}
+
+// For every entry that opens a node: register the node with its parent (its
+// bit in the parent brick's mask, the parent's first child), the level-0 map
+// and the leaf's first entry and key.  tile_off[l][t] is the exclusive scan
+// of the tiles' node counts, so the node of level l holding entry e is the
+// number of level-l nodes opened up to and including e, minus one.
+__global__ __launch_bounds__(BUILD_BLOCK) void k_link(const uint64_t* keys, int64_t m, LevelShifts ls, SceneView v,
+                                                      const uint32_t* tile_off, uint32_t n_tiles, HierOut h,
+                                                      int id_bits) {
+    const uint32_t tile = blockIdx.x * (BUILD_BLOCK / 64) + (threadIdx.x >> 6);
+    if (tile >= n_tiles) return;
     const int L = ls.nlev;
-    for (int l = 0; l < L; ++l) {
-        const bool f = (e == 0 || (k >> ls.sh[l]) != (kp >> ls.sh[l]));
-        if (!f) continue;
-        const uint32_t node = scans[(size_t)l * stride + e];  // exclusive scan at a flagged entry = node index
-        if (l == 0) h.map0[k >> ls.sh[0]] = (int32_t)node;
-        if (l == L - 1) {
-            h.leaf[node].x = (uint32_t)e;
-            h.leaf_key[node] = k >> id_bits;
+    uint32_t carry[PCRL_MAX_LEVELS] = {0u, 0u, 0u, 0u};
+    for (int l = 0; l < L; ++l) carry[l] = tile_off[(size_t)l * n_tiles + tile];
+    for (int r = 0; r < LINK_ROUNDS; ++r) {
+        const int64_t e = (int64_t)tile * LINK_TILE + 64 * r + lane_id();
+        const bool in = e < m;
+        const uint32_t f = in ? link_flags(keys, e, ls) : 0u;
+        const uint64_t k = in ? keys[e] : 0ull;
+        // the levels' flags in 8-bit fields of one word (at most 64 per field): one wave scan
+        uint32_t fp = 0;
+#pragma unroll
+        for (int l = 0; l < PCRL_MAX_LEVELS; ++l) fp |= ((f >> l) & 1u) << (8 * l);
+        const uint32_t incl = wave_incl_scan(fp);
+        const uint32_t sum = __shfl(incl, 63, 64);
+        uint32_t node[PCRL_MAX_LEVELS];
+#pragma unroll
+        for (int l = 0; l < PCRL_MAX_LEVELS; ++l) {
+            node[l] = carry[l] + ((incl >> (8 * l)) & 0xFFu) - 1u;
+            carry[l] += (sum >> (8 * l)) & 0xFFu;
         }
-        if (l > 0) {
-            const uint32_t parent = scans[(size_t)(l - 1) * stride + e] +
-                                    (((k >> ls.sh[l - 1]) != (kp >> ls.sh[l - 1]) || e == 0) ? 1u : 0u) - 1u;
-            const uint32_t local = (uint32_t)((k >> ls.sh[l]) & ((uint64_t(1) << v.lbits[l]) - 1));
-            atomicOr((unsigned long long*)&h.mask[l - 1][(size_t)parent * v.nw[l - 1] + (local >> 6)],
-                     (unsigned long long)(uint64_t(1) << (local & 63)));
-            // the first child of a parent is the entry that opens the parent too
-            const bool opens_parent = (e == 0 || (k >> ls.sh[l - 1]) != (kp >> ls.sh[l - 1]));
-            if (opens_parent) h.first_child[l - 1][parent] = node;
+        if (!in) continue;
+#pragma unroll
+        for (int l = 0; l < PCRL_MAX_LEVELS; ++l) {
+            if (!((f >> l) & 1u)) continue;
+            if (l == 0) {
+                const uint64_t top = k >> ls.sh[0];
+                h.map0[h.unmap0 ? (uint64_t)h.unmap0[top] : top] = (int32_t)node[0];
+            }
+            if (l == L - 1) {
+                const uint64_t top = k >> ls.sh[0];
+                const uint64_t cell0 = h.unmap0 ? (uint64_t)h.unmap0[top] : top;
+                const uint64_t kk = k >> id_bits;
+                h.leaf[node[l]].x = (uint32_t)e;
+                // the leaf's key with level 0 as the linear cell index
+                h.leaf_key[node[l]] = (cell0 << h.g_sh0) | (kk & ((uint64_t(1) << h.g_sh0) - 1));
+            }
+            if (l > 0) {
+                const uint32_t parent = node[l - 1];
+                const uint32_t local = (uint32_t)((k >> ls.sh[l]) & ((uint64_t(1) << v.lbits[l]) - 1));
+                atomicOr((unsigned long long*)&h.mask[l - 1][(size_t)parent * v.nw[l - 1] + (local >> 6)],
+                         (unsigned long long)(uint64_t(1) << (local & 63)));
+                // the first child of a parent is the entry that opens the parent too
+                if ((f >> (l - 1)) & 1u) h.first_child[l - 1][parent] = node[l];
+            }
         }
     }
 }
@@ -698,9 +819,18 @@ static int build_hierarchy(const float* xyz, const float4* unit_nrm, const uint3
     kp.v = v;
     kp.r_s = v.r_s;
     kp.pad = v.pad;
-    uint32_t *cnt = nullptr, *tot = nullptr;
-    if ((rc = T.alloc(&cnt, (size_t)n)) || (rc = T.alloc(&tot, 1))) return rc;
+    uint32_t *cnt = nullptr, *tot = nullptr, *rank0 = nullptr;
+    uint8_t* occ0 = nullptr;
+    if ((rc = T.alloc(&cnt, (size_t)n)) || (rc = T.alloc(&tot, 2)) || (rc = T.alloc(&rank0, (size_t)cells0)) ||
+        (rc = T.alloc(&occ0, (size_t)((cells0 + 3) & ~3ull))) ||
+        (rc = fill_u32((uint32_t*)occ0, 0u, (int64_t)((cells0 + 3) / 4), s)))
+        return rc;
+    kp.occ0 = occ0;
     hipLaunchKernelGGL(k_key_count, dim3(blocks_for(n)), dim3(BUILD_BLOCK), 0, s, kp, xyz, unit_nrm, n, cnt);
+    // the key's level-0 part: the rank of the cell among the marked ones
+    hipLaunchKernelGGL(k_occ0_widen, dim3(blocks_for((int64_t)cells0)), dim3(BUILD_BLOCK), 0, s, occ0,
+                       (int64_t)cells0, rank0);
+    if ((rc = scan_u32(rank0, rank0, (int64_t)cells0, tot + 1, s))) return rc;
     // a disk meets at most (ceil(2 (r_s + pad) / leaf) + 1)^3 leaves: when n times
     // that could reach 2^32, the counts are also summed in 64 bits
     const double span = std::ceil(2.0 * ((double)v.r_s + (double)v.pad) / (double)v.h) + 1.0;
@@ -713,9 +843,10 @@ static int build_hierarchy(const float* xyz, const float4* unit_nrm, const uint3
     }
     if ((rc = scan_u32(cnt, cnt, n, tot, s))) return rc;
     unsigned long long host_tot = 0;
-    uint32_t host_tot32 = 0;
-    const bool copied = may_wrap ? read_back(&host_tot, tot64, 8, s) == PCRL_OK
-                                 : read_back(&host_tot32, tot, 4, s) == PCRL_OK;
+    uint32_t host_tot2[2] = {0u, 0u};
+    const bool copied = read_back(host_tot2, tot, 8, s) == PCRL_OK &&
+                        (!may_wrap || read_back(&host_tot, tot64, 8, s) == PCRL_OK);
+    const uint32_t host_tot32 = host_tot2[0], n_marked0 = host_tot2[1];
     if (!copied) {
         set_error("build_voxels: key count failed: %s", hipGetErrorString(hipGetLastError()));
         return PCRL_EHIP;
@@ -730,49 +861,54 @@ static int build_hierarchy(const float* xyz, const float4* unit_nrm, const uint3
     const int64_t m = (int64_t)host_tot;
     hb.n_entries = m;
 
-    // emit and sort (key, local point index); 32-bit keys when they fit; wider
-    // keys with the point index packed below them in one 64-bit item when both
-    // fit (the stable sort on the key bits then moves 8 bytes per entry, not 12)
-    const bool narrow = v.key_bits <= 32;
+    // the key's level 0 numbered by rank among the marked cells when that
+    // takes fewer bits than the linear cell index (fewer radix passes)
+    const int lbits0 = bits_for(n_marked0 > 1 ? n_marked0 - 1 : 1);
+    const bool ranked0 = lbits0 < v.lbits[0];
+    const int kbits = ranked0 ? v.key_bits - v.lbits[0] + lbits0 : v.key_bits;
+    uint32_t* unmap0 = nullptr;
+    if (ranked0) {
+        if ((rc = T.alloc(&unmap0, n_marked0))) return rc;
+        hipLaunchKernelGGL(k_occ0_unmap, dim3(blocks_for((int64_t)cells0)), dim3(BUILD_BLOCK), 0, s, occ0, rank0,
+                           (int64_t)cells0, unmap0);
+        kp.c0 = rank0;
+    }
+    kp.occ0 = nullptr;
+
+    // emit and sort (key, local point index): the point index packed below the
+    // key in one 64-bit item when both fit (the stable sort on the key bits
+    // then moves one 8-byte item per entry), else 64-bit keys and 32-bit ids
     int id_bits = 1;
     while (id_bits < 32 && ((uint64_t)(n > 0 ? n - 1 : 0) >> id_bits)) ++id_bits;
-    const bool packed = !narrow && v.key_bits + id_bits <= 64;
+    const bool packed = kbits + id_bits <= 64;
     kp.id_bits = packed ? id_bits : 0;
+    const int g_sh0 = ls.sh[0];
     uint64_t* keys = nullptr;
-    uint32_t* keys32 = nullptr;
     uint32_t* ids = nullptr;
     if ((rc = B.alloc(&ids, (size_t)m))) return rc;
-    if (narrow) {
-        if ((rc = T.alloc(&keys32, (size_t)m))) return rc;
-        hipLaunchKernelGGL(k_key_emit<uint32_t>, dim3(blocks_for(n)), dim3(BUILD_BLOCK), 0, s, kp, xyz, unit_nrm, n,
-                           cnt, keys32, ids);
-        if ((rc = radix_sort_u32(keys32, ids, m, v.key_bits, s))) return rc;
-    } else if (packed) {
+    if (packed) {
         if ((rc = T.alloc(&keys, (size_t)m))) return rc;
-        hipLaunchKernelGGL(k_key_emit<uint64_t>, dim3(blocks_for(n)), dim3(BUILD_BLOCK), 0, s, kp, xyz, unit_nrm, n,
-                           cnt, keys, (uint32_t*)nullptr);
-        if ((rc = radix_sort_u64_bits(keys, nullptr, m, id_bits, v.key_bits, s))) return rc;
+        hipLaunchKernelGGL(k_key_emit<uint64_t>, dim3(blocks_for(n, 64)), dim3(64), 0, s, kp, xyz, unit_nrm, n, cnt,
+                           keys, (uint32_t*)nullptr);
+        if ((rc = radix_sort_u64_bits(keys, nullptr, m, id_bits, kbits, s))) return rc;
         for (int l = 0; l < L; ++l) ls.sh[l] += id_bits;
     } else {
         if ((rc = T.alloc(&keys, (size_t)m))) return rc;
-        hipLaunchKernelGGL(k_key_emit<uint64_t>, dim3(blocks_for(n)), dim3(BUILD_BLOCK), 0, s, kp, xyz, unit_nrm, n,
-                           cnt, keys, ids);
-        if ((rc = radix_sort_u64(keys, ids, m, v.key_bits, s))) return rc;
+        hipLaunchKernelGGL(k_key_emit<uint64_t>, dim3(blocks_for(n, 64)), dim3(64), 0, s, kp, xyz, unit_nrm, n, cnt,
+                           keys, ids);
+        if ((rc = radix_sort_u64(keys, ids, m, kbits, s))) return rc;
     }
     hb.entry_point = ids;
 
-    // per-level node boundaries
-    uint32_t *scans = nullptr, *ltot = nullptr;
-    const int64_t stride = (m + 3) & ~(int64_t)3;  // 16-byte aligned levels: vector loads in the scans
-    if ((rc = T.alloc(&scans, (size_t)L * stride)) || (rc = T.alloc(&ltot, PCRL_MAX_LEVELS))) return rc;
-    if (narrow)
-        hipLaunchKernelGGL(k_level_flags<uint32_t>, dim3(blocks_for(m)), dim3(BUILD_BLOCK), 0, s, keys32, m, stride, ls,
-                           scans);
-    else
-        hipLaunchKernelGGL(k_level_flags<uint64_t>, dim3(blocks_for(m)), dim3(BUILD_BLOCK), 0, s, keys, m, stride, ls,
-                           scans);
+    // per-level node boundaries: node starts counted per tile, the tiles' counts scanned
+    const int64_t n_tiles64 = (m + LINK_TILE - 1) / LINK_TILE;
+    const uint32_t n_tiles = (uint32_t)n_tiles64;
+    uint32_t *tiles = nullptr, *ltot = nullptr;
+    if ((rc = T.alloc(&tiles, (size_t)L * n_tiles)) || (rc = T.alloc(&ltot, PCRL_MAX_LEVELS))) return rc;
+    const unsigned link_blocks = (unsigned)((n_tiles64 + BUILD_BLOCK / 64 - 1) / (BUILD_BLOCK / 64));
+    hipLaunchKernelGGL(k_link_count, dim3(link_blocks), dim3(BUILD_BLOCK), 0, s, keys, m, ls, tiles, n_tiles);
     for (int l = 0; l < L; ++l)
-        if ((rc = scan_u32(scans + (size_t)l * stride, scans + (size_t)l * stride, m, ltot + l, s))) return rc;
+        if ((rc = scan_u32(tiles + (size_t)l * n_tiles, tiles + (size_t)l * n_tiles, n_tiles, ltot + l, s))) return rc;
     uint32_t host_nodes[PCRL_MAX_LEVELS] = {0, 0, 0, 0};
     if (read_back(host_nodes, ltot, 4 * L, s) != PCRL_OK) {
         set_error("build_voxels: level scan failed: %s", hipGetErrorString(hipGetLastError()));
@@ -786,6 +922,8 @@ static int build_hierarchy(const float* xyz, const float4* unit_nrm, const uint3
     hb.n_leaves = n_leaves;
 
     HierOut ho{};
+    ho.unmap0 = unmap0;
+    ho.g_sh0 = g_sh0;
     ho.map0 = map0;
     for (int l = 0; l + 1 < L; ++l) {
         const size_t words = (size_t)host_nodes[l] * v.nw[l];
@@ -804,12 +942,8 @@ static int build_hierarchy(const float* xyz, const float4* unit_nrm, const uint3
     if ((rc = B.alloc(&leaf, (size_t)n_leaves)) || (rc = B.alloc(&lkey, (size_t)n_leaves))) return rc;
     ho.leaf = leaf;
     ho.leaf_key = lkey;
-    if (narrow)
-        hipLaunchKernelGGL(k_hier_link<uint32_t>, dim3(blocks_for(m)), dim3(BUILD_BLOCK), 0, s, keys32, m, stride, ls, v,
-                           scans, ho, 0);
-    else
-        hipLaunchKernelGGL(k_hier_link<uint64_t>, dim3(blocks_for(m)), dim3(BUILD_BLOCK), 0, s, keys, m, stride, ls, v,
-                           scans, ho, packed ? id_bits : 0);
+    hipLaunchKernelGGL(k_link, dim3(link_blocks), dim3(BUILD_BLOCK), 0, s, keys, m, ls, v, tiles, n_tiles, ho,
+                       packed ? id_bits : 0);
     for (int l = 0; l + 1 < L; ++l)
         hipLaunchKernelGGL(k_brick_base, dim3(blocks_for(host_nodes[l])), dim3(BUILD_BLOCK), 0, s, ho.mask[l],
                            ho.first_child[l], (int64_t)host_nodes[l], v.nw[l], (uint32_t*)v.base[l]);
