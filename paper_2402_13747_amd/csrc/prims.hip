@@ -469,32 +469,87 @@ __global__ __launch_bounds__(SORT_WAVE) void k_radix_hist(const K* keys, int64_t
     constexpr int R = 1 << DB;
     __shared__ uint32_t h[R];
     for (int d = threadIdx.x; d < R; d += SORT_WAVE) h[d] = 0;
-    __syncthreads();
     const int64_t tile = (int64_t)blockIdx.x * SORT_TILE;
+    // all of the lane's loads first (one memory round trip per tile)
+    K kr[SORT_ITEMS];
+#pragma unroll
     for (int k = 0; k < SORT_ITEMS; ++k) {
-        int64_t i = tile + (int64_t)k * SORT_WAVE + threadIdx.x;
-        if (i < n) atomicAdd(&h[(uint32_t)(keys[i] >> shift) & (R - 1)], 1u);
+        const int64_t i = tile + (int64_t)k * SORT_WAVE + threadIdx.x;
+        kr[k] = i < n ? keys[i] : K(0);
+    }
+    __syncthreads();
+#pragma unroll
+    for (int k = 0; k < SORT_ITEMS; ++k) {
+        const int64_t i = tile + (int64_t)k * SORT_WAVE + threadIdx.x;
+        if (i < n) atomicAdd(&h[(uint32_t)(kr[k] >> shift) & (R - 1)], 1u);
     }
     __syncthreads();
     for (int d = threadIdx.x; d < R; d += SORT_WAVE) hist[(size_t)d * n_tiles + blockIdx.x] = h[d];
 }
 
-template <typename K, int DB>
+// One tile of one pass: the keys are ranked stably by digit into LDS (digit
+// by digit, input order within a digit), then copied out in that order, so
+// that consecutive lanes write consecutive addresses of one digit's run.
+// offs is the exclusive scan of the histogram in [digit][tile] order: cell
+// (d, t) starts at offs[d n_tiles + t] and ends where the next cell starts
+// (the last cell at n).  V: values move with the keys.
+template <typename K, int DB, bool V>
 __global__ __launch_bounds__(SORT_WAVE) void k_radix_scatter(const K* keys_in, const uint32_t* vals_in, K* keys_out,
                                                              uint32_t* vals_out, int64_t n, int shift,
                                                              const uint32_t* offs, uint32_t n_tiles) {
     constexpr int R = 1 << DB;
-    __shared__ uint32_t run[R];
-    for (int d = threadIdx.x; d < R; d += SORT_WAVE) run[d] = offs[(size_t)d * n_tiles + blockIdx.x];
-    __syncthreads();
+    constexpr int PER = (R + SORT_WAVE - 1) / SORT_WAVE;
+    __shared__ uint32_t gstart[R], lstart[R], lrun[R];
+    __shared__ K skey[SORT_TILE];
+    __shared__ uint32_t sval[V ? SORT_TILE : 1];
+    const uint32_t lane = lane_id();
     const int64_t tile = (int64_t)blockIdx.x * SORT_TILE;
-    const uint64_t lt = lanemask_lt();
+    const uint32_t tn = (uint32_t)min((int64_t)SORT_TILE, n - tile);
+    // all of the lane's loads first (one memory round trip per tile)
+    K kr[SORT_ITEMS];
+    uint32_t vr[V ? SORT_ITEMS : 1];
+#pragma unroll
     for (int k = 0; k < SORT_ITEMS; ++k) {
-        const int64_t i = tile + (int64_t)k * SORT_WAVE + threadIdx.x;
-        const bool valid = i < n;
-        K key = valid ? keys_in[i] : K(0);
-        uint32_t val = (valid && vals_in) ? vals_in[i] : 0u;
-        const uint32_t digit = (uint32_t)(key >> shift) & (R - 1);
+        const int64_t i = tile + (int64_t)k * SORT_WAVE + lane;
+        kr[k] = i < n ? keys_in[i] : K(0);
+        if (V) vr[k] = i < n ? vals_in[i] : 0u;
+    }
+    const size_t cells = (size_t)R * n_tiles;
+    for (int d = lane; d < R; d += SORT_WAVE) {
+        const size_t c = (size_t)d * n_tiles + blockIdx.x;
+        const uint32_t a = offs[c];
+        gstart[d] = a;
+        lrun[d] = (c + 1 < cells ? offs[c + 1] : (uint32_t)n) - a;  // the tile's count of digit d
+    }
+    __syncthreads();
+    {
+        // tile-local start of every digit: exclusive scan of the counts (PER consecutive digits per lane)
+        uint32_t cnt[PER], sum = 0;
+#pragma unroll
+        for (int j = 0; j < PER; ++j) {
+            const int d = (int)lane * PER + j;
+            cnt[j] = d < R ? lrun[d] : 0u;
+            sum += cnt[j];
+        }
+        uint32_t run = wave_incl_scan(sum) - sum;
+        __syncthreads();
+#pragma unroll
+        for (int j = 0; j < PER; ++j) {
+            const int d = (int)lane * PER + j;
+            if (d < R) {
+                lstart[d] = run;
+                lrun[d] = 0u;
+            }
+            run += cnt[j];
+        }
+    }
+    __syncthreads();
+    const uint64_t lt = lanemask_lt();
+#pragma unroll
+    for (int k = 0; k < SORT_ITEMS; ++k) {
+        const uint32_t i = (uint32_t)k * SORT_WAVE + lane;
+        const bool valid = i < tn;
+        const uint32_t digit = (uint32_t)(kr[k] >> shift) & (R - 1);
         uint64_t peers = __ballot(valid);
 #pragma unroll
         for (int b = 0; b < DB; ++b) {
@@ -504,15 +559,22 @@ __global__ __launch_bounds__(SORT_WAVE) void k_radix_scatter(const K* keys_in, c
         }
         const uint32_t rank = __popcll(peers & lt);
         uint32_t pos = 0;
-        if (valid) pos = run[digit] + rank;
+        if (valid) pos = lstart[digit] + lrun[digit] + rank;
         __syncthreads();
-        // the highest lane of each digit group advances the running offset
-        if (valid && (peers >> lane_id()) == 1ull) run[digit] += rank + 1;
-        __syncthreads();
+        // the highest lane of each digit group advances the digit's running count
+        if (valid && (peers >> lane) == 1ull) lrun[digit] += rank + 1;
         if (valid) {
-            keys_out[pos] = key;
-            if (vals_out) vals_out[pos] = val;
+            skey[pos] = kr[k];
+            if (V) sval[pos] = vr[k];
         }
+        __syncthreads();
+    }
+    for (uint32_t j = lane; j < tn; j += SORT_WAVE) {
+        const K key = skey[j];
+        const uint32_t d = (uint32_t)(key >> shift) & (R - 1);
+        const uint32_t g = gstart[d] + (j - lstart[d]);
+        keys_out[g] = key;
+        if (V) vals_out[g] = sval[j];
     }
 }
 
@@ -522,8 +584,12 @@ static int radix_pass(const K* ka, const uint32_t* va, K* kb, uint32_t* vb, int6
     hipLaunchKernelGGL((k_radix_hist<K, DB>), dim3(n_tiles), dim3(SORT_WAVE), 0, s, ka, n, shift, hist, n_tiles);
     if (hipGetLastError() != hipSuccess) return PCRL_EHIP;
     PCRL_TRY(scan_u32(hist, hist, ((int64_t)1 << DB) * n_tiles, nullptr, s));
-    hipLaunchKernelGGL((k_radix_scatter<K, DB>), dim3(n_tiles), dim3(SORT_WAVE), 0, s, ka, va, kb, vb, n, shift, hist,
-                       n_tiles);
+    if (va)
+        hipLaunchKernelGGL((k_radix_scatter<K, DB, true>), dim3(n_tiles), dim3(SORT_WAVE), 0, s, ka, va, kb, vb, n, shift,
+                           hist, n_tiles);
+    else
+        hipLaunchKernelGGL((k_radix_scatter<K, DB, false>), dim3(n_tiles), dim3(SORT_WAVE), 0, s, ka, va, kb, vb, n,
+                           shift, hist, n_tiles);
     return hipGetLastError() == hipSuccess ? PCRL_OK : PCRL_EHIP;
 }
 
