@@ -469,44 +469,86 @@ __global__ void k_brick_aabb(const uint64_t* mask, int64_t n_nodes, int nw, int 
 // such that the cube of cells within Chebyshev distance k - 1 is empty and
 // inside the brick.  This is the per-voxel march distance of Section 2.2.4
 // (the longest per-axis distance to the closest voxel with content), limited
-// to the brick.  The L-infinity distance transform is separable: 1D distances
-// along x, then min over y' of max(|y - y'|, .), then the same along z.
+// to the brick.  The cells within Chebyshev distance k of an occupied cell
+// are the occupancy dilated k times by the 3 x 3 x 3 cube, and the dilation
+// is separable: with the brick held as r^2 rows of r bits (row y + r z, bit
+// x), one step ORs each row with its shifts along x, then with its y and z
+// neighbour rows.  A cell first reached at step k is at distance k; the
+// border limits every radius to at most (r - 1) / 2 + 1, so that many steps
+// suffice.  One wave per brick (rows and distances in the wave's LDS).
 // RC > 0: the ratio is the compile-time constant RC (index arithmetic by
 // constants); RC = 0: the runtime r.
+constexpr int BDIST_RMAX = 16;
+
+__device__ __forceinline__ void build_wave_sync() {
+    __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
+    __builtin_amdgcn_wave_barrier();
+    __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
+}
+
 template <int RC>
-__global__ __launch_bounds__(BUILD_BLOCK) void k_brick_dist(const uint64_t* mask, int nw, int r_rt, uint8_t* dist) {
-    extern __shared__ uint8_t sm[];
-    __shared__ uint64_t wm[64];  // the brick's occupancy words (nw <= 64 for r <= 16)
+__global__ __launch_bounds__(BUILD_BLOCK) void k_brick_dist(const uint64_t* mask, int nw, int r_rt, int64_t n_bricks,
+                                                            uint8_t* dist) {
+    __shared__ uint32_t rows_s[BUILD_BLOCK / 64][2][BDIST_RMAX * BDIST_RMAX];
+    __shared__ uint8_t d_s[BUILD_BLOCK / 64][BDIST_RMAX * BDIST_RMAX * BDIST_RMAX];
     const int r = RC > 0 ? RC : r_rt;
-    const int n3 = r * r * r;
-    uint8_t* A = sm;
-    uint8_t* B = sm + n3;
-    const size_t P = blockIdx.x;
-    for (int k = threadIdx.x; k < nw; k += BUILD_BLOCK) wm[k] = mask[P * nw + k];
-    __syncthreads();
-    for (int c = threadIdx.x; c < n3; c += BUILD_BLOCK) A[c] = ((wm[c >> 6] >> (c & 63)) & 1ull) ? 0 : 255;
-    __syncthreads();
-    for (int c = threadIdx.x; c < n3; c += BUILD_BLOCK) {
-        const int x = c % r, row = c - x;
-        int m = 255;
-        for (int xp = 0; xp < r; ++xp)
-            if (A[row + xp] == 0) m = min(m, abs(x - xp));
-        B[c] = (uint8_t)m;
+    const int n2 = r * r, n3 = n2 * r;
+    const int w = threadIdx.x >> 6;
+    const int lane = (int)lane_id();
+    const int64_t P = (int64_t)blockIdx.x * (BUILD_BLOCK / 64) + w;
+    if (P >= n_bricks) return;  // the whole wave: no block-wide barrier follows
+    uint32_t* cur = rows_s[w][0];
+    uint32_t* tmp = rows_s[w][1];
+    uint8_t* D = d_s[w];
+    const uint32_t full = (1u << r) - 1u;
+    // row j holds bits [r j, r j + r) of the brick's mask
+    for (int j = lane; j < n2; j += 64) {
+        const int b0 = r * j;
+        const uint64_t* m = mask + (size_t)P * nw + (b0 >> 6);
+        uint64_t bits = m[0] >> (b0 & 63);
+        if ((b0 & 63) + r > 64) bits |= m[1] << (64 - (b0 & 63));
+        cur[j] = (uint32_t)bits & full;
     }
-    __syncthreads();
-    for (int c = threadIdx.x; c < n3; c += BUILD_BLOCK) {
-        const int x = c % r, y = (c / r) % r, z = c / (r * r);
-        int m = 255;
-        for (int yp = 0; yp < r; ++yp) m = min(m, max(abs(y - yp), (int)B[x + r * (yp + r * z)]));
-        A[c] = (uint8_t)m;
+    build_wave_sync();
+    for (int c = lane; c < n3; c += 64) D[c] = ((cur[c / r] >> (c % r)) & 1u) ? 0 : 255;
+    const int K = (r - 1) / 2 + 1;
+    for (int k = 1; k <= K; ++k) {
+        // along x, then y
+        for (int j = lane; j < n2; j += 64) {
+            const int y = j % r;
+            const uint32_t a = cur[j];
+            uint32_t t = a | (a << 1) | (a >> 1);
+            if (y > 0) {
+                const uint32_t b = cur[j - 1];
+                t |= b | (b << 1) | (b >> 1);
+            }
+            if (y < r - 1) {
+                const uint32_t b = cur[j + 1];
+                t |= b | (b << 1) | (b >> 1);
+            }
+            tmp[j] = t & full;
+        }
+        build_wave_sync();
+        // along z; the cells reached now are at distance k
+        for (int j = lane; j < n2; j += 64) {
+            const int z = j / r;
+            uint32_t t = tmp[j];
+            if (z > 0) t |= tmp[j - r];
+            if (z < r - 1) t |= tmp[j + r];
+            uint32_t nb = t & ~cur[j];
+            while (nb) {
+                const int x = __ffs(nb) - 1;
+                nb &= nb - 1u;
+                D[x + r * j] = (uint8_t)k;
+            }
+            cur[j] = t;
+        }
+        build_wave_sync();
     }
-    __syncthreads();
-    for (int c = threadIdx.x; c < n3; c += BUILD_BLOCK) {
-        const int x = c % r, y = (c / r) % r, z = c / (r * r);
-        int m = 255;
-        for (int zp = 0; zp < r; ++zp) m = min(m, max(abs(z - zp), (int)A[x + r * (y + r * zp)]));
+    for (int c = lane; c < n3; c += 64) {
+        const int x = c % r, y = (c / r) % r, z = c / n2;
         const int db = min(min(min(x, r - 1 - x), min(y, r - 1 - y)), min(z, r - 1 - z));
-        dist[P * n3 + c] = (uint8_t)min(m, db + 1);
+        dist[P * n3 + c] = (uint8_t)min((int)D[c], db + 1);
     }
 }
 
@@ -663,7 +705,7 @@ __global__ void k_split_leaf(const uint2* r, int64_t n, uint32_t* b, uint32_t* c
 }
 
 // With packed items (`packed` non-null) the point index is taken from their
-// low id_bits and also written to ids (the scene's entry -> point table).
+// low id_bits, else from ids (the sort's values).
 __global__ void k_gather_surfels(uint32_t* ids, const uint64_t* packed, int id_bits, int64_t m, const float* xyz,
                                  const float4* un, const uint32_t* label, const uint32_t* gid, float4* spos,
                                  float4* snrm) {
@@ -672,7 +714,6 @@ __global__ void k_gather_surfels(uint32_t* ids, const uint64_t* packed, int id_b
     uint32_t i;
     if (packed) {
         i = (uint32_t)(packed[e] & ((uint64_t(1) << id_bits) - 1));
-        ids[e] = i;
     } else {
         i = ids[e];
     }
@@ -680,6 +721,12 @@ __global__ void k_gather_surfels(uint32_t* ids, const uint64_t* packed, int id_b
     spos[e] = make_float4(xyz[3 * (size_t)i], xyz[3 * (size_t)i + 1], xyz[3 * (size_t)i + 2], __uint_as_float(g));
     const float4 nn = un[i];
     snrm[e] = make_float4(nn.x, nn.y, nn.z, __uint_as_float(label[i]));
+}
+
+// Entry -> point table of a scene from its surfel stream.
+__global__ void k_entry_points(const float4* spos, int64_t m, uint32_t* out) {
+    const int64_t e = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (e < m) out[e] = __float_as_uint(spos[e].w);
 }
 
 // ---------------------------------------------------------------------------
@@ -884,8 +931,8 @@ static int build_hierarchy(const float* xyz, const float4* unit_nrm, const uint3
     kp.id_bits = packed ? id_bits : 0;
     const int g_sh0 = ls.sh[0];
     uint64_t* keys = nullptr;
-    uint32_t* ids = nullptr;
-    if ((rc = B.alloc(&ids, (size_t)m))) return rc;
+    uint32_t* ids = nullptr;  // entry -> point: packed items carry it; else the sort's values
+    if (!packed && (rc = B.alloc(&ids, (size_t)m))) return rc;
     if (packed) {
         if ((rc = T.alloc(&keys, (size_t)m))) return rc;
         hipLaunchKernelGGL(k_key_emit<uint64_t>, dim3(blocks_for(n, 64)), dim3(64), 0, s, kp, xyz, unit_nrm, n, cnt,
@@ -983,13 +1030,14 @@ static int build_hierarchy(const float* xyz, const float4* unit_nrm, const uint3
         } else if (r >= 3 && r <= 16) {
             uint8_t* ld = nullptr;
             if ((rc = B.alloc(&ld, (size_t)n_cells))) return rc;
-            const dim3 g((unsigned)host_nodes[L - 2]);
+            const int64_t nb = host_nodes[L - 2];
+            const dim3 g(blocks_for(nb, BUILD_BLOCK / 64));
             if (r == 10)
-                hipLaunchKernelGGL(k_brick_dist<10>, g, dim3(BUILD_BLOCK), 2 * r3, s, ho.mask[L - 2], v.nw[L - 2], r, ld);
+                hipLaunchKernelGGL(k_brick_dist<10>, g, dim3(BUILD_BLOCK), 0, s, ho.mask[L - 2], v.nw[L - 2], r, nb, ld);
             else if (r == 8)
-                hipLaunchKernelGGL(k_brick_dist<8>, g, dim3(BUILD_BLOCK), 2 * r3, s, ho.mask[L - 2], v.nw[L - 2], r, ld);
+                hipLaunchKernelGGL(k_brick_dist<8>, g, dim3(BUILD_BLOCK), 0, s, ho.mask[L - 2], v.nw[L - 2], r, nb, ld);
             else
-                hipLaunchKernelGGL(k_brick_dist<0>, g, dim3(BUILD_BLOCK), 2 * r3, s, ho.mask[L - 2], v.nw[L - 2], r, ld);
+                hipLaunchKernelGGL(k_brick_dist<0>, g, dim3(BUILD_BLOCK), 0, s, ho.mask[L - 2], v.nw[L - 2], r, nb, ld);
             v.ldist = ld;
             hb.bytes += n_cells;
         }
@@ -1022,7 +1070,7 @@ static int build_hierarchy(const float* xyz, const float4* unit_nrm, const uint3
         set_error("build_voxels: kernel launch failed");
         return PCRL_EHIP;
     }
-    hb.bytes += m * (4 + 32) + n_leaves * 16;
+    hb.bytes += m * ((ids ? 4 : 0) + 32) + n_leaves * 16;
     for (int l = 0; l + 1 < L; ++l) hb.bytes += (int64_t)host_nodes[l] * v.nw[l] * 12;
     return PCRL_OK;
 }
@@ -1221,8 +1269,16 @@ extern "C" int scene_leaf_table(const PcrlScene* scene, uint64_t* leaf_key, uint
                            leaf_begin, leaf_count);
         PCRL_TRY_HIP(hipGetLastError());
     }
-    if (entry_point && m)
-        PCRL_TRY_HIP(hipMemcpyAsync(entry_point, scene->entry_point, (size_t)m * 4, hipMemcpyDeviceToDevice, s));
+    if (entry_point && m) {
+        if (scene->entry_point) {
+            PCRL_TRY_HIP(hipMemcpyAsync(entry_point, scene->entry_point, (size_t)m * 4, hipMemcpyDeviceToDevice, s));
+        } else {
+            // the point id rides in the surfel stream (x, y, z, id)
+            hipLaunchKernelGGL(k_entry_points, dim3(blocks_for(m)), dim3(BUILD_BLOCK), 0, s, scene->view.spos, m,
+                               entry_point);
+            PCRL_TRY_HIP(hipGetLastError());
+        }
+    }
     PCRL_TRY_HIP(hipStreamSynchronize(s));
     return PCRL_OK;
 }

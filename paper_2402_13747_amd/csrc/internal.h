@@ -286,7 +286,7 @@ struct PcrlScene {
     pcrl::DevBufs bufs;
     PcrlSceneInfo info{};
     uint64_t* leaf_key = nullptr;     // per leaf hierarchical key
-    uint32_t* entry_point = nullptr;  // per entry: point id (leaf order)
+    uint32_t* entry_point = nullptr;  // per entry: point id (leaf order); null: read from spos.w
     uint2* leaf_range = nullptr;
     uint32_t max_label = 0;
     bool compact = false;             // PCRL_VOXEL_COMPACT: no dense cell tables (base and overlays)
