@@ -26,10 +26,12 @@
 // converged path is kept if every interaction has both neighbours on one
 // side of its surfel and the last segment reaches the RX unblocked.
 //
-// Lane = path; the wave iterates in lockstep until all its paths are done
-// (traversal and leaf tests are the launcher's own, trace_core.h).  The
-// per-path interaction state lives in global arrays [k][path] (a dynamically
-// indexed private array would be placed in scratch memory).
+// Lane = path, with few paths per wave (one, unless the paths outnumber the
+// GPU's SIMDs): a wave iterates in lockstep until all its paths are done, and
+// all 64 lanes share the leaf tests of its rays (traversal and leaf tests are
+// the launcher's own, trace_core.h).  The per-path interaction state lives
+// in global arrays [k][path] (a dynamically indexed private array would be
+// placed in scratch memory).
 //
 // Dedup of the valid paths of one (TX, RX, number of reflections) group, in
 // order of increasing length: a path whose label sequence already occurred
@@ -57,6 +59,7 @@ struct RefineArgs {
     const int32_t* p_n;         // per path: reflections N
     const float* p_pts;         // [n][K][3] coarse interaction points
     uint32_t n;
+    uint32_t ppw;               // paths per wave (lanes 0..ppw-1 hold one each; the others help the leaf tests)
     int32_t K;
     int32_t max_iters;
     float grad_tol;
@@ -180,8 +183,8 @@ template <int NL, bool OV>
 __global__ __launch_bounds__(REFINE_BLOCK) void k_refine(RefineArgs a) {
     __shared__ LeafTestLds W;
     stat_t cnt[ST_COUNT] = {};
-    const uint32_t p = blockIdx.x * REFINE_BLOCK + threadIdx.x;
-    const bool in = p < a.n;
+    const uint32_t p = blockIdx.x * a.ppw + threadIdx.x;
+    const bool in = threadIdx.x < a.ppw && p < a.n;
     const size_t n = a.n;
     int N = 0;
     float T[3] = {0.f, 0.f, 0.f}, R[3] = {0.f, 0.f, 0.f};
@@ -574,7 +577,7 @@ __global__ __launch_bounds__(64) void k_refine_sweep(const uint64_t* skey, const
 
 template <int NL>
 static void launch_refine_nl(const RefineArgs& a, hipStream_t s) {
-    const unsigned grid = (a.n + REFINE_BLOCK - 1) / REFINE_BLOCK;
+    const unsigned grid = (a.n + a.ppw - 1) / a.ppw;
     if (a.t.has_ov) hipLaunchKernelGGL((k_refine<NL, true>), dim3(grid), dim3(REFINE_BLOCK), 0, s, a);
     else hipLaunchKernelGGL((k_refine<NL, false>), dim3(grid), dim3(REFINE_BLOCK), 0, s, a);
 }
@@ -680,6 +683,12 @@ extern "C" int refine_paths(const PcrlScene* scene, const float* tx, int32_t n_t
     a.p_n = paths->n_refl;
     a.p_pts = paths->points;
     a.n = (uint32_t)n;
+    // paths per wave: a path's iterations run in lockstep with the wave's other paths, so
+    // few paths per wave (down to one) as long as the waves still fill the GPU (one per SIMD)
+    {
+        const int64_t waves = (int64_t)device_cus() * 4;
+        a.ppw = (uint32_t)std::min<int64_t>(REFINE_BLOCK, std::max<int64_t>(1, (n + waves - 1) / waves));
+    }
     a.K = k_stride;
     a.max_iters = max_iters;
     a.grad_tol = grad_tol;
