@@ -483,6 +483,7 @@ def bench_cone(args, torch, pcrl):
         "ms_transmission": round(st["ms_transmission"], 3), "ms_propagation": round(st["ms_propagation"], 3),
         "visibility_rays_per_s": round(vis / (ms * 1e-3), 1),
     }
+    out["diffraction"] = bench_cone_diffraction(args, torch, pcrl)
     if not args.no_cpu_baseline:
         # the oracle's visibility rays (FP64, every surfel) on a sample of the transmission phase
         import oracle
@@ -507,6 +508,61 @@ def bench_cone(args, torch, pcrl):
                                          f"{s.n_points} points"}
     log(f"[cone] {out}")
     print(json.dumps(out), flush=True)
+
+
+def bench_cone_diffraction(args, torch, pcrl):
+    """Diffraction leg of the cone workload (Sections 2.2.4 and 3, simulation B: at most one
+    diffraction): the corner building (20 x 20 m ground, a 6 x 6 x 4 m building, its eight
+    convex edges given as diffraction edges), the TX and RX on either side of it, up to
+    --cone-k interactions; then the refinement of the coarse paths with their diffraction
+    points on the edges."""
+    import scenes
+    dev = torch.device("cuda", 0)
+    s = scenes.corner_building()
+    E = s.extra["edges"]
+    voxel, dv = 0.4, 2
+    pts = np.vstack([s.xyz, s.tx, s.rx])
+    origin = (np.floor(pts.min(axis=0) / voxel) * voxel - 0.73 * voxel).astype(np.float32)
+    dims = np.ceil((pts.max(axis=0) - origin) / voxel).astype(int) + 2
+    scene = pcrl.build_voxels(s.xyz, s.normal, s.label, s.levels, float(np.float32(s.surfel_radius)),
+                              t_eps=float(np.float32(s.t_eps_value)), device=dev)
+    ies = pcrl.ie_build(scene, origin, voxel, dv, dims)
+    ies.add_edges(E["seg"], E["normals"], E["label"])
+    K = args.cone_k
+    runs = []
+    for rep in range(args.warmup + args.steps):
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        L = pcrl.cone_launch(ies, s.tx, s.rx, K, max_diffractions=1)
+        paths = pcrl.cone_collect(L, kappa=100)
+        torch.cuda.synchronize()
+        dt = time.perf_counter() - t0
+        if rep >= args.warmup:
+            runs.append(dt)
+        st = L.stats()
+        if rep + 1 < args.warmup + args.steps:
+            L.release()
+    ms = 1e3 * float(np.median(runs))
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    ref = pcrl.refine_cone_paths(L, paths)
+    torch.cuda.synchronize()
+    r_ms = 1e3 * (time.perf_counter() - t0)
+    status = ref["status"].cpu().numpy()
+    kept = np.nonzero(ref["kept"].cpu().numpy())[0]
+    keys = ref["key"].cpu().numpy()
+    n_refl = paths["n_refl"].cpu().numpy()
+    length = ref["length"].cpu().numpy()
+    kept_paths = sorted((tuple(int(x) for x in keys[i, :n_refl[i]]), round(float(length[i]), 4)) for i in kept)
+    L.release()
+    out = {"scene": "corner_building", "points": s.n_points, "edges": int(len(E["seg"])),
+           "edge_ies": ies.info()["n_edge_ies"], "max_interactions": K, "max_diffractions": 1,
+           "ms_per_step": round(ms, 3), "nodes": st["nodes"], "cones": st["cones"], "visible": st["visible"],
+           "paths": {"rows": int(paths["n_rows"]), "keys": int(paths["n_keys"])},
+           "refine": {"ms": round(r_ms, 3), "valid": int((status == 0).sum()), "rows": int(len(status)),
+                      "kept": kept_paths[:16]}}
+    log(f"[cone] diffraction: {out}")
+    return out
 
 
 def copy_rate_gbs(torch, mib=1024, reps=5):
