@@ -86,3 +86,32 @@ def test_batch_scene_sizes():
     s = scenes.batch_scenes(seeds=[0, 1], point_scale=0.05, ray_scale=0.05)
     assert s[0].name.startswith("batch_0_furnished_room") and s[1].name.startswith("batch_1_street_canyon")
     assert all(x.n_rays % 256 == 0 and 1 <= len(x.rx) <= 32 for x in s)
+
+
+def test_box_edges_are_convex_edges_of_the_box():
+    """Every edge lies on the box's surface along one axis, its two face normals are
+    unit, perpendicular to it and to each other and point away from the box; the
+    RX of the corner building lies in the building's shadow seen from its TX."""
+    lo, hi = np.array([0.0, 0.0, 0.0]), np.array([6.0, 6.0, 4.0])
+    seg, nrm, lab = scenes.box_edges(lo, hi, 100)
+    assert seg.shape == (8, 2, 3) and nrm.shape == (8, 2, 3)
+    assert list(lab) == list(range(100, 108))
+    centre = 0.5 * (lo + hi)
+    for (a, b), (n1, n2) in zip(seg.astype(np.float64), nrm.astype(np.float64)):
+        w = b - a
+        assert np.count_nonzero(w) == 1 and np.linalg.norm(w) > 0
+        mid = 0.5 * (a + b)
+        # on two faces of the box: two coordinates at a bound
+        at_bound = np.isclose(mid, lo) | np.isclose(mid, hi)
+        assert at_bound.sum() == 2
+        for n in (n1, n2):
+            assert abs(np.linalg.norm(n) - 1.0) < 1e-6 and abs(n @ w) < 1e-9
+            assert n @ (mid - centre) > 0
+        assert abs(n1 @ n2) < 1e-9
+    s = scenes.corner_building()
+    t, r = s.tx[0].astype(np.float64), s.rx[0].astype(np.float64)
+    # the straight segment TX -> RX passes through the building's footprint below its roof
+    u = np.linspace(0.0, 1.0, 1001)[:, None]
+    p = t + u * (r - t)
+    inside = np.all((p > lo) & (p < hi), axis=1)
+    assert inside.any()
