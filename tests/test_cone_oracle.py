@@ -218,3 +218,24 @@ def test_corner_diffraction_closed_form():
     res0 = cone.trace(sc, ies, s.tx, s.rx, origin, 0.4, 2, dims, K=1, kappa=100, half_angle=math.radians(2.5),
                       edges=eies, max_diff=0)
     assert not res0["paths"]
+
+
+def test_edges_are_inert_without_diffraction():
+    """With a diffraction limit of 0 the edge pieces are never targets: the
+    partial paths, their priorities and the receptions equal those of the
+    table without edges (point IEs keep their indices ahead of the pieces)."""
+    s = scenes.corner_building(tx=(-3.0, 5.0, 1.5), rx=(-2.0, -3.0, 1.5))
+    E = s.extra["edges"]
+    origin = np.array([-10.292, -10.292, -0.292], np.float32)
+    dims = (53, 53, 13)
+    ies = cone.ie_build(s.xyz, s.normal, s.label, origin, 0.4, 2, dims)
+    eies = cone.edge_ies(E["seg"], E["normals"], E["label"], origin, 0.4, 2, dims)
+    sc = cone.Scene(s.xyz, s.normal, s.label, s.surfel_radius, s.t_eps_value)
+    kw = dict(K=1, kappa=100, half_angle=math.radians(2.5))
+    a = cone.trace(sc, ies, s.tx, s.rx, origin, 0.4, 2, dims, **kw)
+    b = cone.trace(sc, ies, s.tx, s.rx, origin, 0.4, 2, dims, edges=eies, max_diff=0, **kw)
+    key = lambda c: (c["tx"], c["chain"], c["prio"], round(c["length"], 12))  # noqa: E731
+    assert [key(c) for c in a["nodes"][0]] == [key(c) for c in b["nodes"][0]]
+    rec = lambda r: (r["tx"], r["rx"], r["chain"], r["labels"], round(r["length"], 12))  # noqa: E731
+    assert sorted(map(rec, a["records"])) == sorted(map(rec, b["records"]))
+    assert a["records"], "the RX in front of the building is reached"
