@@ -245,8 +245,8 @@ def test_keller_sector_count_closed_form():
     """Incidence perpendicular to the edge (beta = 90 degrees) with a 2.5 degree
     half-angle: N = ceil(pi sin(beta) / theta) = 72 sectors of 5 degrees; a 90 degree
     convex wedge leaves 270 degrees of exterior, which hold the centres of 54 of
-    them.  At beta = 40 degrees N = ceil(46.28) = 47, of which the centres in the
-    exterior are counted directly; along the edge N = 1."""
+    them.  At beta = 41 degrees N = ceil(47.24) = 48 (no sector centre on a face),
+    of which the centres in the exterior are counted directly; along the edge N = 1."""
     w = np.array([0.0, 0.0, 1.0])
     n1, n2 = np.array([-1.0, 0.0, 0.0]), np.array([0.0, -1.0, 0.0])
     o = np.zeros(3)
@@ -255,13 +255,13 @@ def test_keller_sector_count_closed_form():
     assert len(secs) == 54
     for axis, _, _, _ in secs:
         assert abs(axis[2]) < 1e-12                      # Keller: the cone degenerates to the plane
-    # beta = 40 degrees: the incoming direction makes 40 degrees with the edge; the sector
+    # beta = 41 degrees: the incoming direction makes 41 degrees with the edge; the sector
     # centres (k + 1/2) 360 / N degrees from the first face's normal lie outside the wedge
     # when in [0, 180] or [270, 360] (cos >= 0 against face 1, sin >= 0 against face 2)
-    b = math.radians(40.0)
+    b = math.radians(41.0)
     prev = -np.array([math.sin(b), 0.0, math.cos(b)])
     N = math.ceil(math.pi * math.sin(b) / th)
-    assert N == 47
+    assert N == 48
     ext = sum(1 for k in range(N) if (k + 0.5) * 360.0 / N <= 180.0 or (k + 0.5) * 360.0 / N >= 270.0)
     secs, _ = cone.keller_sectors(o, prev, w, n1, n2, th)
     assert len(secs) == ext
