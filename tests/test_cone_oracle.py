@@ -269,3 +269,37 @@ def test_keller_sector_count_closed_form():
         assert axis[2] == pytest.approx(math.cos(b), abs=1e-12)
     secs, _ = cone.keller_sectors(o, np.array([0.0, 0.0, -3.0]), w, n1, n2, th)
     assert len(secs) == 1 and secs[0][1] is None
+
+
+def test_transmission_behind_a_partition():
+    """Transmission phase in a non-convex room: the box room with a partition
+    wall in the plane x = 5 (y in [0, 6], full height; a 2 m gap at y > 6).  From
+    the TX at (2, 3, 1.5), an IE whose segment from the TX crosses the wall's
+    rectangle at least 0.3 m inside its border is hidden; every IE with x < 4.7
+    (the convex half of the room the TX stands in) is visible."""
+    s = scenes.box_room()
+    wall = [(np.array([5.0, 0.0, 0.0]), np.array([0.0, 6.0, 0.0]), np.array([0.0, 0.0, 3.0]),
+             np.array([-1.0, 0.0, 0.0]), 6)]
+    wx, wn, wl = scenes._sample_faces(wall, 0.2)
+    xyz = np.vstack([s.xyz, wx.astype(np.float32)]).astype(np.float32)
+    nrm = np.vstack([s.normal, wn.astype(np.float32)]).astype(np.float32)
+    lab = np.concatenate([s.label, wl.astype(np.uint32)]).astype(np.uint32)
+    tx = np.array([[2.0, 3.0, 1.5]], np.float32)
+    ies = cone.ie_build(xyz, nrm, lab, ORIGIN, VOXEL, DV, DIMS)
+    sc = cone.Scene(xyz, nrm, lab, s.surfel_radius, 1e-4)
+    res = cone.trace(sc, ies, tx, np.zeros((0, 3), np.float32), ORIGIN, VOXEL, DV, DIMS, K=1, kappa=0,
+                     half_angle=math.radians(2.5))
+    seen = {c["chain"][0] for c in res["nodes"][0]}
+    t = tx[0].astype(np.float64)
+    hidden, front = [], []
+    for e, p in enumerate(ies["pos"]):
+        if p[0] < 4.7:
+            front.append(e)
+        if p[0] > 5.3:
+            u = (5.0 - t[0]) / (p[0] - t[0])
+            q = t + u * (p - t)
+            if 0.3 <= q[1] <= 5.7 and 0.3 <= q[2] <= 2.7:
+                hidden.append(e)
+    assert len(hidden) > 100 and len(front) > 1000
+    assert not (set(hidden) & seen)
+    assert set(front) <= seen
