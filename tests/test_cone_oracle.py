@@ -13,7 +13,13 @@
   every single reflection of the image method is found with a polyline no
   shorter than the image path, no partial path interacts twice with one
   planar wall in a row (the separation plane), and with two reflections the
-  25 image-method label sequences are all found.
+  25 image-method label sequences are all found;
+* transmission behind a partition wall: IEs whose sight line crosses the
+  wall's rectangle are hidden, the TX's convex half is all visible;
+* diffraction: Keller's law and the sector partition, the sector count
+  N = ceil(pi sin(beta) / theta) and the exterior sectors of a 90 degree
+  wedge counted by hand, edge pieces tiling their edges, edges inert at a
+  diffraction limit of 0, and the corner diffraction's closed form 2 sqrt(34).
 """
 import math
 
