@@ -44,18 +44,37 @@ Readings where the paper is silent (each listed in the design notes):
     normal turned towards the reflected side as its normal; a target is in
     front iff (p - apex) . n > tau, tau = 1e-3 subvoxel edges (a target on
     the reflecting plane itself is never in front);
-  * kappa acts on partial paths too (otherwise the branching is unbounded):
-    per (TX, label sequence) at most kappa nodes of a generation are kept,
-    chosen by a deterministic priority (SplitMix64 of the parent's priority
-    plus the IE index + 1; the TX's priority is SplitMix64(tx)), ties by
-    parent then IE index; the same holds for the paths reaching one RX;
+  * similar partial paths (Section 2.2.3: the same labels in the same
+    order, here also reaching the same IE) are merged: one node is kept,
+    the one of smallest priority (SplitMix64 of the parent's priority plus
+    the IE index + 1; the TX's priority is SplitMix64(tx)), ties by parent;
+    kappa then bounds the rows of each coarse path (TX, RX, labels), chosen
+    by the same priority, with the count of all;
   * coarse path length = polyline TX -> reception points -> RX.
 
+Diffraction (Sections 2, 2.2.4 and 3): caller-given convex edges with the
+outward normals of their two faces are cut at the subvoxel faces they cross;
+each piece is an IE in the subvoxel of its midpoint (reception point the
+midpoint, the edge's label).  A node at an edge piece casts the Keller cone
+of the directions keeping the incoming angle with the edge, cut into
+N = max(1, ceil(pi sin(beta) / half_angle)) sectors measured from the first
+face's normal across the edge; a sector is cast when its axis leaves the
+wedge (v . n1 >= 0 or v . n2 >= 0), and its two separation planes contain
+the edge at its bounding azimuths (a target lies in the sector iff
+(p - o) . n_lo >= 0 and (p - o) . n_hi < 0).  A node's own edge is never its
+target, and edge pieces are targets only while the path has fewer than
+max_diff diffractions.
+
 Parity: every decision that compares floating-point values (cone-sphere,
-separation plane, visibility, the candidate block of a voxel, the axis's
-first hit) is reported with its margin; a decision whose margin lies inside
-the FP32 error band is ambiguous, and a node reached through an ambiguous
-decision is excused together with its subtree.
+separation planes, visibility, the candidate block of a voxel, the axis's
+first hit, a sector's exterior test, the sector count) is reported with its
+margin.  An admission (a conjunction of such tests) is undecided when one
+term lies inside the FP32 error band and none is outside it on the false
+side; a sector whose exterior margin is inside the band is kept or dropped
+by rounding, so its targets are undecided; a sector count within 1e-3 of an
+integer step makes every sector's decisions undecided.  A node reached
+through an undecided decision is excused together with its subtree, and a
+target reached by two cones of one node is one candidate.
 """
 from __future__ import annotations
 
