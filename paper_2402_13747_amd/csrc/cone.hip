@@ -4,15 +4,21 @@
 //
 // Intersectable entities (IEs): the points of one label inside one subvoxel
 // of a low-resolution voxel grid (voxel edge V, subvoxel V / D_v), each with
-// a reception point (mean position) and a normal (normalised mean normal).
+// a reception point (mean position) and a normal (normalised mean normal);
+// and the pieces of caller-given diffraction edges, one per subvoxel an edge
+// crosses (reception point its midpoint, the edge's direction and the
+// outward normals of its two faces).
 // One query is traced generation by generation:
 //   transmission   a visibility ray from every TX towards every IE and RX;
 //   generation k   the kept partial paths with k interactions; each casts a
-//                  reflected cone whose axis is marched through the voxel
+//                  reflected cone (a node at a point IE) or the exterior
+//                  sectors of its Keller cone (a node at an edge piece,
+//                  Section 2.2.4), whose axes are marched through the voxel
 //                  grid: the IEs and RX of the voxels within one voxel of the
 //                  march (the paper's neighbour evaluation) that meet the cone
 //                  (subvoxel bounding sphere), lie in front of the separation
-//                  plane and are visible become generation k + 1 or receptions;
+//                  plane (between the sector's two planes) and are visible
+//                  become generation k + 1 or receptions;
 //   merge          partial paths reaching the same IE with the same labels in
 //                  the same order are one (the smallest SplitMix64 priority
 //                  wins), sorted by (TX, labels, IE, priority);
