@@ -644,11 +644,32 @@ typedef struct {
  * thread and streams.  Queries are admitted while the stream budget, the
  * in-flight limit and the memory budget allow; each admission round packs
  * every admissible pending query into one launch_batch on a free stream, so
- * rounds overlap on the device (continuous batching).  The memory estimate
- * of a query with R = n_tx * n_rays rays is R*72 (ray state, if K > 0) +
- * R*16*K (history) + 16*C (records; C = record_capacity, or its default
- * R*(K+1)*min(n_rx,8)/16 + 65536) + 8*n_rays (ray order) + 4096. */
+ * rounds overlap on the device (continuous batching).  Each query is
+ * charged serve_query_bytes against hbm_budget_bytes while it is in flight. */
 int serve_create(PcrlScene* scene, const PcrlServeParams* params, PcrlServer** out);
+
+/* Device bytes a query of n_tx TX, n_rx RX and these launch params holds
+ * while it is in flight: what the server charges it against the memory
+ * budget.  With R = n_tx * n_rays, the sum of its launch's blocks, each
+ * rounded up to the allocator's size class (at least 512 B; a request above
+ * 2^e and at most 2^(e+1) bytes takes 1.5 * 2^e or 2^(e+1)):
+ *   records 16*C (C = record_capacity, or its default
+ *     R*(K+1)*min(n_rx,8)/16 + 65536; 1 without RX); counters 4*(K+3);
+ *   history 16*R*K (K > 0); statistics 128*(K+1) (PCRL_LAUNCH_STATS);
+ *   ray state: 16*R, 16*R and 4*R per set, two sets for K >= 2, one for
+ *     K = 1;
+ *   directions 12*n_rays;
+ *   PCRL_LAUNCH_COHERENT: bucket keys 2*n_rays, the bounce-0 order and its
+ *     positions 4*n_rays each, bucket counts and starts 256 KiB each; and
+ *     for R >= 65536 with K > 0 the later bounces' order 4*R, keys 2*R,
+ *     positions 4*R and counts K*256 KiB;
+ * plus 12*(n_tx + max(n_rx, 1)) + 64 bytes (unrounded) for the round's
+ * antenna arrays and batch words.  The collection of a finished query is
+ * not charged: rounds collect one query at a time, and it takes about 64 B
+ * per reception record plus the result rows for that moment.  Host
+ * arithmetic only (no device call).  PCRL_EINVAL for arguments that
+ * serve_submit refuses. */
+int serve_query_bytes(int32_t n_tx, int32_t n_rx, const PcrlLaunchParams* params, int64_t* bytes);
 
 /* Queue one query (host arrays tx [n_tx,3], rx [n_rx,3]; params as in
  * launch_rays, Fibonacci directions, no hit log).  Returns at once with a

@@ -25,7 +25,8 @@ from ._lib import (KEY_LABELS, KEY_LEAVES, LAUNCH_COHERENT, LAUNCH_SDF, LAUNCH_S
                    REFINE_VALID, REFINE_WRONG_SIDE, PcrlError, check, lib)
 
 __all__ = ["ie_build", "cone_launch", "cone_collect", "IeTable", "ConeLaunch", "build_voxels", "launch_rays", "launch_batch", "batch_autotune", "launch_directions", "collect_paths",
-           "refine_paths", "refine_cone_paths", "sdf_intersect", "use_torch_allocator", "Scene", "Launch", "Server", "PcrlError", "KEY_LABELS",
+           "refine_paths", "refine_cone_paths", "sdf_intersect", "use_torch_allocator", "Scene", "Launch", "Server",
+           "serve_query_bytes", "PcrlError", "KEY_LABELS",
            "KEY_LEAVES", "REFINE_VALID", "REFINE_NOT_CONVERGED", "REFINE_MISS", "REFINE_WRONG_SIDE",
            "REFINE_OCCLUDED", "REFINE_DEGENERATE", "REFINE_OFF_EDGE", "version", "library_path"]
 
@@ -752,6 +753,25 @@ def _relaunch(launch: Launch, record_capacity: int):
     launch._args = new._args
 
 
+def _served_params(n_rays, max_reflections, record_capacity=0, coherent=True):
+    p = _lib.PcrlLaunchParams()
+    p.n_rays = int(n_rays)
+    p.max_reflections = int(max_reflections)
+    p.record_capacity = int(record_capacity)
+    p.flags = LAUNCH_COHERENT if coherent else 0
+    return p
+
+
+def serve_query_bytes(n_tx, n_rx, n_rays, max_reflections, record_capacity=0, coherent=True) -> int:
+    """Device bytes a Server charges a query of these arguments (as Server.submit
+    takes them) against its memory budget (serve_query_bytes of the C ABI; no
+    device call)."""
+    p = _served_params(n_rays, max_reflections, record_capacity, coherent)
+    b = C.c_int64()
+    check("serve_query_bytes", lib.serve_query_bytes(int(n_tx), int(n_rx), C.byref(p), C.byref(b)))
+    return b.value
+
+
 class Server:
     """Request loop over one device-resident, incrementally re-voxelised scene (serve_* of the C ABI).
 
@@ -784,11 +804,7 @@ class Server:
         tx = np.ascontiguousarray(np.asarray(tx, np.float32).reshape(-1, 3))
         rx = np.ascontiguousarray(np.asarray(rx, np.float32).reshape(-1, 3)) if rx is not None else \
             np.zeros((0, 3), np.float32)
-        p = _lib.PcrlLaunchParams()
-        p.n_rays = int(n_rays)
-        p.max_reflections = int(max_reflections)
-        p.record_capacity = int(record_capacity)
-        p.flags = LAUNCH_COHERENT if coherent else 0
+        p = _served_params(n_rays, max_reflections, record_capacity, coherent)
         t = C.c_int64()
         check("serve_submit", lib.serve_submit(self._h, tx.ctypes.data, tx.shape[0],
                                                rx.ctypes.data if rx.shape[0] else None, rx.shape[0], C.byref(p),

@@ -206,6 +206,7 @@ SIGNATURES = {
     "serve_create": (C.c_int, [C.c_void_p, C.POINTER(PcrlServeParams), C.POINTER(C.c_void_p)]),
     "serve_submit": (C.c_int, [C.c_void_p, C.c_void_p, C.c_int32, C.c_void_p, C.c_int32, C.POINTER(PcrlLaunchParams),
                                C.POINTER(C.c_int64)]),
+    "serve_query_bytes": (C.c_int, [C.c_int32, C.c_int32, C.POINTER(PcrlLaunchParams), C.POINTER(C.c_int64)]),
     "serve_update": (C.c_int, [C.c_void_p, C.c_void_p, C.c_void_p, C.c_void_p, C.c_void_p, C.c_int64]),
     "serve_poll": (C.c_int, [C.c_void_p, C.c_int64, C.c_double, C.POINTER(PcrlServeResult)]),
     "serve_result": (C.c_int, [C.c_void_p, C.c_int64, C.POINTER(PcrlPaths)]),

@@ -129,6 +129,11 @@ int fill_u32(uint32_t* p, uint32_t v, int64_t n, hipStream_t s);
 int fill_u64(uint64_t* p, uint64_t v, int64_t n, hipStream_t s);
 int iota_u32(uint32_t* p, int64_t n, hipStream_t s);
 
+// Bytes the device allocator reserves for a request of `bytes`: 512 B, then
+// two size classes per power of two (1.5 * 2^e and 2^(e+1) for requests
+// above 2^e; under 50 % slack).
+size_t size_class(size_t bytes);
+
 // Number of CUs of the current device (cached).
 int device_cus();
 

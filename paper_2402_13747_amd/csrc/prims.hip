@@ -52,9 +52,16 @@ const char* get_error() { return g_err.c_str(); }
 //     order keeps the old and the new user apart);
 //   * to an allocation on another stream once an event recorded at the free
 //     has completed.
-// Size classes are 512 B, then four classes per power of two (at most 25 %
-// slack).  Cached blocks are returned to the runtime when an allocation
+// Size classes are 512 B, then two per power of two: a request above 2^e
+// and at most 2^(e+1) bytes gets 1.5 * 2^e or 2^(e+1) (under 50 % slack).  Cached blocks are returned to the runtime when an allocation
 // fails, then the allocation is retried once.
+
+size_t size_class(size_t bytes) {
+    if (bytes <= 512) return 512;
+    int e = 63 - __builtin_clzll((unsigned long long)(bytes - 1));  // 2^e < bytes <= 2^(e+1)
+    const size_t q = (size_t)1 << (e - 1);                           // quarter of 2^(e+1)
+    return (bytes + q - 1) / q * q;
+}
 
 namespace {
 
@@ -74,13 +81,6 @@ struct Pool {
 Pool& pool() {
     static Pool* p = new Pool();  // never destroyed: blocks live until the process ends
     return *p;
-}
-
-size_t size_class(size_t bytes) {
-    if (bytes <= 512) return 512;
-    int e = 63 - __builtin_clzll((unsigned long long)(bytes - 1));  // 2^e < bytes <= 2^(e+1)
-    const size_t q = (size_t)1 << (e - 1);                           // quarter of 2^(e+1)
-    return (bytes + q - 1) / q * q;
 }
 
 // Return every cached block whose last use has completed to the runtime.

@@ -96,12 +96,38 @@ struct PcrlServer {
 
 namespace pcrl {
 
-static int64_t estimate_bytes(const ServeReq& r) {
-    const int64_t rays = (int64_t)r.n_tx * r.p.n_rays;
-    const int64_t K = r.p.max_reflections;
-    const int64_t rec = r.p.record_capacity > 0 ? r.p.record_capacity
-                                                : rays * (K + 1) * std::min<int64_t>(r.n_rx, 8) / 16 + 65536;
-    return rays * (K > 0 ? 72 : 0) + rays * 16 * K + rec * 16 + r.p.n_rays * 8 + 4096;
+// Device bytes a served query holds while it is in flight, as the library
+// allocates them (every block rounded up to its size class): its launch's
+// buffers (history, records, counters, statistics, the ray state of even and
+// of odd bounces, the Fibonacci directions; with PCRL_LAUNCH_COHERENT the
+// bounce-0 order and its sort's counts, positions and starts, and, for a
+// launch of 65536 rays or more run on its own, the order of the later
+// bounces), plus its share of the round's antenna arrays and of the batch
+// kernel's per-query words.  The collection of a finished query is left out:
+// rounds collect one query at a time, for a moment, with O(records) bytes.
+static int64_t query_device_bytes(int32_t n_tx, int32_t n_rx, const PcrlLaunchParams& p) {
+    auto cls = [](int64_t b) { return (int64_t)size_class((size_t)std::max<int64_t>(b, 1)); };
+    const int64_t nr = p.n_rays, rays = (int64_t)n_tx * nr, K = p.max_reflections;
+    int64_t rec = p.record_capacity > 0 ? p.record_capacity
+                                        : (n_rx == 0 ? 1 : rays * (K + 1) * std::min<int64_t>(n_rx, 8) / 16 + 65536);
+    rec = std::min<int64_t>(rec, 0xFFFFFFF0ll);
+    int64_t b = cls(rec * 16) + cls((K + 3) * 4);  // records, counters
+    if (K > 0) b += cls(K * rays * 16);             // history
+    if (p.flags & PCRL_LAUNCH_STATS) b += cls((int64_t)PCRL_NSTATS * (K + 1) * 8);
+    if (K > 0) b += 2 * cls(rays * 16) + cls(rays * 4);
+    if (K > 1) b += 2 * cls(rays * 16) + cls(rays * 4);
+    b += cls(nr * 12);
+    if (p.flags & PCRL_LAUNCH_COHERENT) {
+        b += cls(nr * 2) + cls(nr * 4) + 2 * cls(65536 * 4) + cls(nr * 4);
+        if (K > 0 && rays >= 65536) b += cls(rays * 4) + cls(rays * 2) + cls(rays * 4) + cls(K * 65536 * 4);
+    }
+    return b + (int64_t)n_tx * 12 + (int64_t)std::max<int32_t>(n_rx, 1) * 12 + 64;
+}
+
+// The arguments a served query may have (serve_submit's checks).
+static bool served_params_ok(int32_t n_tx, int32_t n_rx, const PcrlLaunchParams* p) {
+    return n_tx >= 1 && n_rx >= 0 && p && !p->directions && !p->hit_log_id && !p->hit_log_t && p->n_rays >= 1 &&
+           p->max_reflections >= 0 && p->max_reflections <= PCRL_MAX_REFLECTIONS && !(p->flags & PCRL_LAUNCH_SDF);
 }
 
 static int collect_one(PcrlServer* S, PcrlLaunch* L, ServeReq* r, hipStream_t s) {
@@ -384,6 +410,16 @@ extern "C" int serve_create(PcrlScene* scene, const PcrlServeParams* params, Pcr
     return PCRL_OK;
 }
 
+extern "C" int serve_query_bytes(int32_t n_tx, int32_t n_rx, const PcrlLaunchParams* p, int64_t* bytes) {
+    clear_error();
+    if (!bytes || !served_params_ok(n_tx, n_rx, p)) {
+        set_error("serve_query_bytes: invalid arguments (n_tx >= 1, n_rx >= 0, the params of a served query)");
+        return PCRL_EINVAL;
+    }
+    *bytes = query_device_bytes(n_tx, n_rx, *p);
+    return PCRL_OK;
+}
+
 extern "C" int serve_submit(PcrlServer* S, const float* tx, int32_t n_tx, const float* rx, int32_t n_rx,
                             const PcrlLaunchParams* p, int64_t* ticket) {
     clear_error();
@@ -391,8 +427,7 @@ extern "C" int serve_submit(PcrlServer* S, const float* tx, int32_t n_tx, const 
         set_error("serve_submit: invalid arguments");
         return PCRL_EINVAL;
     }
-    if (p->directions || p->hit_log_id || p->hit_log_t || p->n_rays < 1 || p->max_reflections < 0 ||
-        p->max_reflections > PCRL_MAX_REFLECTIONS || (p->flags & PCRL_LAUNCH_SDF)) {
+    if (!served_params_ok(n_tx, n_rx, p)) {
         set_error("serve_submit: served queries use Fibonacci directions, surfels (no PCRL_LAUNCH_SDF), no hit logs, 0 <= K <= 8");
         return PCRL_EINVAL;
     }
@@ -408,7 +443,7 @@ extern "C" int serve_submit(PcrlServer* S, const float* tx, int32_t n_tx, const 
     r->p = *p;
     r->p.flags &= ~PCRL_LAUNCH_TIMING;
     r->K = p->max_reflections;
-    r->bytes = estimate_bytes(*r);
+    r->bytes = query_device_bytes(n_tx, n_rx, r->p);
     r->t_submit = clk::now();
     std::lock_guard<std::mutex> lock(S->mu);
     if (r->bytes > S->prm.hbm_budget_bytes) {

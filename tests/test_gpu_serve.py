@@ -168,11 +168,12 @@ def test_serve_epochs(env, world):
 def test_serve_budget(env, world):
     torch, pcrl = env
     sc, mover, base, n_static, r_s, t_eps = world
-    # the engine's memory estimate of one query (ray state, history, records, ray order)
+    # what the server charges one query against its budget (its launch's buffers)
     rays, K, n_rx = 20_000, 3, 2
-    one = rays * 72 + rays * 16 * K + (rays * (K + 1) * n_rx // 16 + 65536) * 16 + rays * 8 + 4096
+    one = pcrl.serve_query_bytes(len(sc.tx), n_rx, rays, K)
+    assert one >= len(sc.tx) * rays * (72 + 16 * K)     # ray state and history at least
     srv = pcrl.Server(base, n_streams=4, max_batch=8, hbm_budget_bytes=int(1.5 * one))
-    qs = [dict(tx=sc.tx, rx=sc.rx[:2], n_rays=20_000, max_reflections=3) for _ in range(5)]
+    qs = [dict(tx=sc.tx, rx=sc.rx[:n_rx], n_rays=rays, max_reflections=K) for _ in range(5)]
     tickets = [srv.submit(**q) for q in qs]
     for t in tickets:
         assert srv.poll(t, timeout=60.0)["status"] == 2
@@ -188,7 +189,7 @@ def test_serve_cancel(env, world):
     torch, pcrl = env
     sc, mover, base, n_static, r_s, t_eps = world
     rays, K, n_rx = 20_000, 3, 2
-    one = rays * 72 + rays * 16 * K + (rays * (K + 1) * n_rx // 16 + 65536) * 16 + rays * 8 + 4096
+    one = pcrl.serve_query_bytes(len(sc.tx), n_rx, rays, K)
     # room for one query at a time: the last two are still queued when cancelled
     srv = pcrl.Server(base, n_streams=4, max_batch=8, hbm_budget_bytes=int(1.5 * one))
     tickets = [srv.submit(sc.tx, sc.rx[:2], n_rays=rays, max_reflections=K) for _ in range(6)]
