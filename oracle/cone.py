@@ -75,6 +75,11 @@ by rounding, so its targets are undecided; a sector count within 1e-3 of an
 integer step makes every sector's decisions undecided.  A node reached
 through an undecided decision is excused together with its subtree, and a
 target reached by two cones of one node is one candidate.
+
+Parity unpinned: the cone half-angle, the separation-plane clearance tau,
+the merge priorities (SplitMix64 of the parent's priority and the IE) and
+the FP32 error band are conventions the paper does not fix; they are pinned
+only by the shared definition.  The pins fix the method around them.
 """
 from __future__ import annotations
 
