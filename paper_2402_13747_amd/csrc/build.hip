@@ -18,12 +18,9 @@
 // traversal that tests the leaves it passes finds every disk it crosses.
 //
 // Pipeline: ingest (normalise normals, validate, AABB, max label) -> sync ->
-// label ranks -> per-point leaf counts, marking the level-0 cells the points
-// reach -> scans -> sync -> ranks of the marked level-0 cells (the keys'
-// level-0 part when that takes fewer bits) -> emit keys (the point index
-// packed below the key when both fit in 64 bits) -> radix sort -> per-tile
-// node-start counts + their scan -> sync -> level-0 map, bricks, leaf ranges
-// (one pass over the sorted keys) -> skip radii -> surfel gather.
+// label ranks -> per-point leaf counts -> scan -> sync -> emit (key, id) ->
+// radix sort -> per-tile node-start counts + their scan -> sync -> level-0
+// map, bricks, leaf ranges (one pass over the sorted keys) -> surfel gather.
 #include "internal.h"
 
 #include <algorithm>
