@@ -17,9 +17,18 @@
 * transmission behind a partition wall: IEs whose sight line crosses the
   wall's rectangle are hidden, the TX's convex half is all visible;
 * diffraction: Keller's law and the sector partition, the sector count
-  N = ceil(pi sin(beta) / theta) and the exterior sectors of a 90 degree
-  wedge counted by hand, edge pieces tiling their edges, edges inert at a
-  diffraction limit of 0, and the corner diffraction's closed form 2 sqrt(34).
+  N = ceil(pi sin(beta) / theta) (each sector 360 / N degrees wide between its
+  planes) and the exterior sectors of a 90 degree wedge counted by hand, every
+  diffraction child of the corner building inside one of its node's kept
+  sectors, edge pieces tiling their edges, edges inert at a diffraction limit
+  of 0, and the corner diffraction's closed form 2 sqrt(34).
+
+Each of these mistakes planted in the oracle fails one of the pins: the
+sector count rounded down, a sector plane's sign, the exterior test's "or"
+made "and", the cone-sphere distance with sine and cosine swapped, the
+reflected separation plane's sign, a SplitMix64 constant, the Keller cone
+reversed along the edge, and a sector's upper plane left out of the target
+test.
 """
 import math
 
@@ -259,8 +268,10 @@ def test_keller_sector_count_closed_form():
     th = math.radians(2.5)
     secs, _ = cone.keller_sectors(o, np.array([-4.0, 1.0, 0.0]), w, n1, n2, th)
     assert len(secs) == 54
-    for axis, _, _, _ in secs:
+    for axis, n_lo, n_hi, _ in secs:
         assert abs(axis[2]) < 1e-12                      # Keller: the cone degenerates to the plane
+        # a sector spans 360 / N degrees between its planes (pins N itself)
+        assert math.degrees(math.acos(float(np.clip(n_lo @ n_hi, -1, 1)))) == pytest.approx(5.0, abs=1e-9)
     # beta = 41 degrees: the incoming direction makes 41 degrees with the edge; the sector
     # centres (k + 1/2) 360 / N degrees from the first face's normal lie outside the wedge
     # when in [0, 180] or [270, 360] (cos >= 0 against face 1, sin >= 0 against face 2)
@@ -271,10 +282,49 @@ def test_keller_sector_count_closed_form():
     ext = sum(1 for k in range(N) if (k + 0.5) * 360.0 / N <= 180.0 or (k + 0.5) * 360.0 / N >= 270.0)
     secs, _ = cone.keller_sectors(o, prev, w, n1, n2, th)
     assert len(secs) == ext
-    for axis, _, _, _ in secs:
+    for axis, n_lo, n_hi, _ in secs:
         assert axis[2] == pytest.approx(math.cos(b), abs=1e-12)
+        assert math.degrees(math.acos(float(np.clip(n_lo @ n_hi, -1, 1)))) == pytest.approx(7.5, abs=1e-9)
     secs, _ = cone.keller_sectors(o, np.array([0.0, 0.0, -3.0]), w, n1, n2, th)
     assert len(secs) == 1 and secs[0][1] is None
+
+
+def test_diffraction_children_lie_in_kept_sectors():
+    """Corner building, two interactions, one diffraction: every certain child
+    of a node at an edge piece lies between the two separation planes of one
+    of the exterior sectors that node casts (Keller sectors of the incoming
+    direction from the TX).  A sector is cast whole, so a child may lie up to
+    half a sector inside the wedge; none lies beyond the kept sectors."""
+    s = scenes.corner_building()
+    E = s.extra["edges"]
+    origin = np.array([-10.292, -10.292, -0.292], np.float32)
+    dims = (53, 53, 13)
+    ies = cone.ie_build(s.xyz, s.normal, s.label, origin, 0.4, 2, dims)
+    eies = cone.edge_ies(E["seg"], E["normals"], E["label"], origin, 0.4, 2, dims)
+    sc = cone.Scene(s.xyz, s.normal, s.label, s.surfel_radius, s.t_eps_value)
+    th = math.radians(2.5)
+    res = cone.trace(sc, ies, s.tx, s.rx, origin, 0.4, 2, dims, K=2, kappa=100, half_angle=th, edges=eies,
+                     max_diff=1)
+    npt = len(ies["label"])
+
+    def pos(i):
+        return np.asarray(ies["pos"][i] if i < npt else eies["pos"][i - npt], np.float64)
+
+    tx = np.asarray(s.tx[0], np.float64)
+    n_children = 0
+    for c in res["nodes"][1]:
+        a, b = c["chain"]
+        if a < npt or not c["exact"] or c["excused"]:
+            continue
+        e = int(eies["edge"][a - npt])
+        seg = np.asarray(E["seg"][e], np.float64)
+        w = (seg[1] - seg[0]) / np.linalg.norm(seg[1] - seg[0])
+        secs, _ = cone.keller_sectors(pos(a), tx, w, np.asarray(E["normals"][e][0], np.float64),
+                                      np.asarray(E["normals"][e][1], np.float64), th)
+        v = pos(b) - pos(a)
+        assert any(lo is None or (v @ lo >= 0 and v @ hi < 0) for _, lo, hi, _ in secs), (a, b)
+        n_children += 1
+    assert n_children > 10_000
 
 
 def test_transmission_behind_a_partition():

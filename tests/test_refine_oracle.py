@@ -20,7 +20,15 @@ edge on either side, so unfolding the two half-planes about the edge makes
 the diffracted path a straight line of horizontal extent 2 sqrt(34); with a
 ground reflection the RX is mirrored in z = 0 first.  The outcomes a point
 off the finite edge, a neighbour inside the wedge and a segment through the
-ground are decided by the geometry.
+ground are decided by the geometry.  A face surfel tilted across the
+segments leaving the diffraction point, within r_s of it, changes nothing
+(rays leave a diffraction point r_s along).
+
+Each of these mistakes planted in the oracle's diffraction code fails one of
+the pins: the step along the edge with the wrong sign, no clearance for
+segments arriving at a diffraction point, the wedge test's "or" made "and",
+and no clearance for rays leaving it (in the iteration or in the final
+check).
 """
 import math
 import os
@@ -316,6 +324,39 @@ def test_corner_diffraction_point(z_tx, z_rx):
     ci, co = _keller(tx, d, rx, np.array([0.0, 0.0, 1.0]))
     assert abs(ci - co) <= 1e-4
     assert r["labels"][0, 0] == 100 and r["ids"][0, 0] == -2
+
+
+@pytest.mark.parametrize("case", ["to the RX", "to a ground reflection"])
+def test_rays_leave_a_diffraction_point_clear_of_its_faces(case):
+    """A face surfel at the corner edge tilted by 30 degrees (normal (0.5, -0.866, 0), centre 5 cm
+    along the face y = 0, at the diffraction point's height) meets the segment leaving the
+    diffraction point about 3 cm from it, inside the disk.  A ray leaving a diffraction point starts
+    r_s = 7.5 cm along, so the path keeps its status and points: the last segment to the RX, or the
+    re-trace towards the ground reflection that follows the diffraction (the closed forms of the
+    tests around this one)."""
+    if case == "to the RX":
+        tx, rx = np.array([-3.0, 5.0, 1.5]), np.array([5.0, -3.0, 1.5])
+        D, nxt = np.array([0.0, 0.0, 1.5]), rx
+        pts, eo, L = np.array([[[0.0, 0.0, 2.9]]]), np.array([[0]], np.int32), 2.0 * math.sqrt(34.0)
+    else:
+        tx, rx = np.array([-3.0, 5.0, 3.0]), np.array([5.0, -3.0, 1.5])
+        D, nxt = np.array([0.0, 0.0, 0.75]), np.array([5.0 / 3.0, -1.0, 0.0])
+        pts, eo, L = np.array([[[0.0, 0.0, 1.0], [1.5, -1.2, 0.0]]]), np.array([[0, -1]], np.int32), 12.5
+    s = scenes.corner_building(tx=tx, rx=rx)
+    u = np.array([0.5, -math.sqrt(0.75), 0.0])
+    c = np.array([0.05, 0.0, D[2]])
+    d = (nxt - D) / np.linalg.norm(nxt - D)
+    t = float(u @ (c - D)) / float(u @ d)         # where the leaving ray meets the tilted disk
+    assert 1e-3 < t < 0.75 * s.surfel_radius and np.linalg.norm(D + t * d - c) < 0.5 * s.surfel_radius
+    xyz = np.vstack([s.xyz, c[None]]).astype(np.float32)
+    nrm = np.vstack([s.normal, u[None]]).astype(np.float32)
+    lab = np.concatenate([s.label, np.array([4], s.label.dtype)])
+    args = (s.surfel_radius, 1e-5, tx[None], rx[None], np.array([pts.shape[1]], np.int32), pts)
+    plain = oracle.refine(s.xyz, s.normal, s.label, *args, edges=s.extra["edges"], edge_of=eo)
+    tilted = oracle.refine(xyz, nrm, lab, *args, edges=s.extra["edges"], edge_of=eo)
+    assert plain["status"][0] == tilted["status"][0] == oracle.REF_VALID
+    assert L <= tilted["length"][0] <= L * (1 + 1e-7)
+    assert np.array_equal(plain["points"], tilted["points"])
 
 
 def test_corner_diffraction_then_ground_reflection():
