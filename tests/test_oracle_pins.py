@@ -142,6 +142,24 @@ def test_skip_surfel_just_left(oracle_lib):
     assert np.allclose(r["hit_t"][0], [0.5, 1.0, 1.0, 1.0])
 
 
+def test_skip_surfel_just_left_tilted_mirrors(oracle_lib):
+    # two parallel mirrors tilted off the axes, 1 m apart, t_eps = 0: a reflection point computed
+    # in floating point sits a rounding error off its mirror's plane, in front of or behind it;
+    # from behind, the plane lies at a tiny positive distance ahead.  Skipping the surfel just
+    # left, every ray still alternates between the two mirrors for all six segments.
+    n = np.array([0.3, 0.2, 1.0]) / np.linalg.norm([0.3, 0.2, 1.0])
+    pts = np.array([[0.0, 0.0, 0.0], n]).astype(np.float32)
+    nrm = np.array([n, -n]).astype(np.float32)
+    rng = np.random.default_rng(7)
+    dirs = -n[None] + 0.05 * rng.normal(size=(400, 3))
+    dirs /= np.linalg.norm(dirs, axis=1, keepdims=True)
+    o = (0.5 * n).astype(np.float32)[None]
+    r = oracle_lib.launch(pts, nrm, np.arange(2, dtype=np.uint32), o, np.zeros((0, 3), np.float32),
+                          dirs.astype(np.float32), K=5, r_s=10.0, t_eps=0.0, n_threads=1)
+    assert np.array_equal(r["hit_id"], np.tile([0, 1, 0, 1, 0, 1], (400, 1)))
+    assert np.all(r["hit_t"] > 0.4)
+
+
 def test_reception_sphere(oracle_lib):
     # no points; one RX straight ahead at distance 10 and one off-axis
     alpha = 0.01
