@@ -12,8 +12,9 @@
 * propagation in the box room: the line-of-sight path has length |TX - RX|,
   every single reflection of the image method is found with a polyline no
   shorter than the image path, no partial path interacts twice with one
-  planar wall in a row (the separation plane), and with two reflections the
-  25 image-method label sequences are all found;
+  planar wall in a row (the separation plane), with two reflections the
+  25 image-method label sequences are all found, and similar partial paths
+  are merged (one certain node per TX, labels and IE in every generation);
 * transmission behind a partition wall: IEs whose sight line crosses the
   wall's rectangle are hidden, the TX's convex half is all visible;
 * diffraction: Keller's law and the sector partition, the sector count
@@ -27,8 +28,10 @@ Each of these mistakes planted in the oracle fails one of the pins: the
 sector count rounded down, a sector plane's sign, the exterior test's "or"
 made "and", the cone-sphere distance with sine and cosine swapped, the
 reflected separation plane's sign, a SplitMix64 constant, the Keller cone
-reversed along the edge, and a sector's upper plane left out of the target
-test.
+reversed along the edge, a sector's upper plane left out of the target
+test, the visibility ray's box exit taken for its entry, hits counted up to
+the target point, the slab test without its swap, an IE's reception point
+taken as its first point, subvoxels by rounding, and no merge.
 """
 import math
 
@@ -155,6 +158,16 @@ def test_two_reflections_find_the_image_sequences():
         assert len(g["rows"]) <= 100 and g["count"] >= len(g["rows"])
         labs = k[3]
         assert all(a != b for a, b in zip(labs, labs[1:]))
+    # similar partial paths (same TX, labels in the same order, same IE) are merged into one:
+    # every generation holds at most one certain node per (TX, labels, IE), and the second
+    # generation reaches IEs through several first-generation nodes of one wall
+    for gen in res["nodes"]:
+        sure = [(c["tx"], c["labels"], c["chain"][-1]) for c in gen if c["exact"] and not c["excused"]]
+        assert len(sure) == len(set(sure))
+    reached = {}
+    for c in res["nodes"][1]:
+        reached.setdefault((c["labels"], c["chain"][-1]), set()).add(c["chain"][0])
+    assert max(len(v) for v in reached.values()) == 1      # the kept node of each group only
 
 
 # --------------------------------------------------------------------------- diffraction (Section 2.2.4)
