@@ -4,7 +4,7 @@ Run by hand (not collected by pytest; several minutes):
 
     python tests/plant_mistakes.py [group ...]
 
-Groups: launch, refl, diff, cone, vis.  Each mistake is applied alone to a
+Groups: launch, refl, diff, sdf, cone, vis.  Each mistake is applied alone to a
 fresh copy of oracle/, scenes/ and tests/ in a temporary directory (the C
 oracle is rebuilt there), then the group's pin file runs with -x.  A mistake
 is caught when that run fails.  Two mistakes only reverse the order of the
@@ -86,6 +86,16 @@ GROUPS = {
         ("kappa keeps the largest priorities (convention)", CONE,
          'key=lambda r: (r["tx"], r["rx"], len(r["labels"]), r["labels"], r["prio"], r["chain"])',
          'key=lambda r: (r["tx"], r["rx"], len(r["labels"]), r["labels"], -r["prio"], r["chain"])'),
+    ]),
+    "sdf": ("tests/test_sdf_oracle.py", [
+        ("weight squared once", "oracle/sdf.c", "                    w = w * w;\n                    w = w * w;\n",
+         "                    w = w * w;\n"),
+        ("step over an undefined sample h", "oracle/sdf.c", "            t += 0.5 * a->h;\n", "            t += a->h;\n"),
+        ("interpolation from the new sample", "oracle/sdf.c", "*th = tp + (t - tp) * fp / (fp - f);",
+         "*th = t + (t - tp) * fp / (fp - f);"),
+        ("segment half as long", "oracle/sdf.c", "double ta = tc - 0.5 * D, tb = tc + 0.5 * D;",
+         "double ta = tc - 0.25 * D, tb = tc + 0.25 * D;"),
+        ("march by twice |f|", "oracle/sdf.c", "        t += fabs(f);\n", "        t += 2.0 * fabs(f);\n"),
     ]),
     "vis": ("tests/test_cone_oracle.py", [
         ("box exit for entry", C, "    return t0 <= t1 ? t0 : INFINITY;\n}", "    return t0 <= t1 ? t1 : INFINITY;\n}"),
