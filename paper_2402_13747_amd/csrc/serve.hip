@@ -571,7 +571,10 @@ extern "C" int serve_cancel(PcrlServer* S, int64_t ticket) {
 
 extern "C" int serve_release(PcrlServer* S, int64_t ticket) {
     clear_error();
-    if (!S) return PCRL_EINVAL;
+    if (!S) {
+        set_error("serve_release: NULL server");
+        return PCRL_EINVAL;
+    }
     std::lock_guard<std::mutex> lock(S->mu);
     auto it = S->reqs.find(ticket);
     if (it == S->reqs.end()) return PCRL_OK;

@@ -124,6 +124,46 @@ def test_version_and_validation_without_gpu(pcrl):
     assert b"alloc and free" in lib.last_error()
 
 
+def test_every_entry_point_refuses_null_handles_without_a_device(pcrl):
+    """NULL handles and arrays are refused with PCRL_EINVAL and a message naming
+    the entry point, before any device call; releasing NULL is a no-op."""
+    from paper_2402_13747_amd import _lib
+    L, N = _lib.lib, None
+    calls = {
+        "update_points": lambda: L.update_points(N, N, N, N, N, 1, N),
+        "scene_info": lambda: L.scene_info(N, N),
+        "scene_leaf_table": lambda: L.scene_leaf_table(N, N, N, N, N, N),
+        "launch_stats": lambda: L.launch_stats(N, N),
+        "launch_records": lambda: L.launch_records(N, 0, N, N, N, N, N, N),
+        "launch_batch": lambda: L.launch_batch(N, 0, N, N, N),
+        "batch_autotune": lambda: L.batch_autotune(N, 0, N, N),
+        "launch_directions": lambda: L.launch_directions(0, N, N),
+        "collect_paths_noalloc": lambda: L.collect_paths_noalloc(N, 1, 0, N, N),
+        "ie_build": lambda: L.ie_build(N, N, N, N),
+        "ie_add_edges": lambda: L.ie_add_edges(N, N, N, N, 1, N),
+        "ie_info": lambda: L.ie_info(N, N),
+        "ie_table": lambda: L.ie_table(N, N, N, N, N, N, N, N),
+        "cone_launch": lambda: L.cone_launch(N, N, 1, N, 0, N, N, N),
+        "cone_stats": lambda: L.cone_stats(N, N),
+        "cone_nodes": lambda: L.cone_nodes(N, 0, N, N, N, N, N, N),
+        "cone_collect": lambda: L.cone_collect(N, 1, N, N),
+        "refine_cone_paths": lambda: L.refine_cone_paths(N, N, N, N, N),
+        "serve_create": lambda: L.serve_create(N, N, N),
+        "serve_submit": lambda: L.serve_submit(N, N, 1, N, 0, N, N),
+        "serve_update": lambda: L.serve_update(N, N, N, N, N, 1),
+        "serve_poll": lambda: L.serve_poll(N, 1, 0.0, N),
+        "serve_result": lambda: L.serve_result(N, 1, N),
+        "serve_cancel": lambda: L.serve_cancel(N, 1),
+        "serve_release": lambda: L.serve_release(N, 1),
+        "serve_stats": lambda: L.serve_stats(N, N),
+    }
+    for name, call in calls.items():
+        assert call() == _lib.PCRL_EINVAL, name
+        assert L.last_error().decode().startswith(name + ":"), (name, L.last_error())
+    for name in ("release_scene", "release_launch", "release_ies", "release_cone", "serve_destroy"):
+        assert getattr(L, name)(N) == _lib.PCRL_OK, name
+
+
 def test_no_cpu_fallback(tmp_path, monkeypatch):
     """Without the built library the binding refuses to import."""
     import importlib
