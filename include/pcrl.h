@@ -645,7 +645,9 @@ typedef struct {
  * in-flight limit and the memory budget allow; each admission round packs
  * every admissible pending query into one launch_batch on a free stream, so
  * rounds overlap on the device (continuous batching).  Each query is
- * charged serve_query_bytes against hbm_budget_bytes while it is in flight. */
+ * charged serve_query_bytes against hbm_budget_bytes while it is in flight.
+ * PCRL_EINVAL for a NULL argument, PCRL_ENOMEM when the server cannot be
+ * allocated, PCRL_EHIP when its streams cannot be created. */
 int serve_create(PcrlScene* scene, const PcrlServeParams* params, PcrlServer** out);
 
 /* Device bytes a query of n_tx TX, n_rx RX and these launch params holds
@@ -680,16 +682,20 @@ int serve_submit(PcrlServer* server, const float* tx, int32_t n_tx, const float*
 
 /* Frame update: replace the dynamic points (update_points on the server's
  * update stream).  Rounds admitted afterwards trace the new epoch; rounds in
- * flight finish on theirs.  Synchronous.  Thread-safe. */
+ * flight finish on theirs.  Synchronous.  Thread-safe.  PCRL_EINVAL for a
+ * NULL server; otherwise update_points' status. */
 int serve_update(PcrlServer* server, const uint32_t* ids, const float* xyz, const float* normal, const uint32_t* label,
                  int64_t n);
 
 /* State of a ticket; waits up to timeout_s seconds (0: no wait) for it to
- * finish.  Returns the query's failure status if it failed. */
+ * finish.  Returns the query's failure status if it failed; PCRL_EINVAL for a
+ * NULL argument or an unknown ticket. */
 int serve_poll(PcrlServer* server, int64_t ticket, double timeout_s, PcrlServeResult* out);
 
 /* Copy a finished query's coarse paths (rows as in collect_paths) into HOST
- * arrays of out->capacity rows.  PCRL_EOVERFLOW if they do not fit. */
+ * arrays of out->capacity rows.  PCRL_EOVERFLOW if they do not fit;
+ * PCRL_EINVAL for a NULL argument or a ticket without a result (unknown or
+ * not finished). */
 int serve_result(PcrlServer* server, int64_t ticket, PcrlPaths* out);
 
 /* Cancel a query.  A pending one leaves the queue at once; a running one
@@ -699,13 +705,17 @@ int serve_result(PcrlServer* server, int64_t ticket, PcrlPaths* out);
  * PCRL_EINVAL for an unknown ticket. */
 int serve_cancel(PcrlServer* server, int64_t ticket);
 
-/* Forget a finished ticket (frees its host result). */
+/* Forget a finished ticket (frees its host result).  An unknown ticket is
+ * ignored; PCRL_EBUSY while the ticket is pending or running; PCRL_EINVAL
+ * for a NULL server. */
 int serve_release(PcrlServer* server, int64_t ticket);
 
-/* Throughput and latency (p50 / p99 over completed queries). */
+/* Throughput and latency (p50 / p99 over completed queries).  PCRL_EINVAL
+ * for a NULL argument. */
 int serve_stats(PcrlServer* server, PcrlServeStats* out);
 
-/* Finish every pending and running query, then stop the worker. */
+/* Finish every pending and running query, then stop the worker and free the
+ * server.  NULL is ignored. */
 int serve_destroy(PcrlServer* server);
 
 /* Message of the last failed call on this thread ("" if none). */
