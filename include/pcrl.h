@@ -153,13 +153,14 @@ int build_voxels(const float* xyz, const float* normal, const uint32_t* label, i
 int update_points(PcrlScene* scene, const uint32_t* ids, const float* xyz, const float* normal, const uint32_t* label,
                   int64_t n, pcrl_stream_t stream);
 
-/* Sizes of a built scene (host struct). */
+/* Sizes of a built scene (host struct).  PCRL_EINVAL for a NULL argument. */
 int scene_info(const PcrlScene* scene, PcrlSceneInfo* out);
 
 /* Copy the leaf table to caller device buffers of capacity >= n_leaves:
  * leaf_key (hierarchical key), leaf_begin and leaf_count (ranges into the
  * leaf-ordered entries) and entry_point (the point id of every entry,
- * capacity >= n_entries).  Any pointer may be NULL.  Synchronous. */
+ * capacity >= n_entries).  Any pointer may be NULL.  Synchronous;
+ * PCRL_EINVAL for a NULL scene, PCRL_EHIP if a copy fails. */
 int scene_leaf_table(const PcrlScene* scene, uint64_t* leaf_key, uint32_t* leaf_begin, uint32_t* leaf_count,
                      uint32_t* entry_point, pcrl_stream_t stream);
 
@@ -227,17 +228,22 @@ typedef struct {
 
 /* Launch n_rays rays from each of n_tx TX and trace them.
  *   tx device [n_tx,3] float32, rx device [n_rx,3] float32 (n_rx may be 0).
- * The scene must stay alive until the launch is released.  Asynchronous. */
+ * The scene must stay alive until the launch is released.  Asynchronous.
+ * PCRL_EINVAL for NULL arrays, n_rays < 1, K outside [0, 8], more than 65535
+ * RX, n_tx * n_rays >= 2^31 or a hit log given half; then
+ * PCRL_ENOMEM or PCRL_EHIP from the allocations and launches. */
 int launch_rays(const PcrlScene* scene, const float* tx, int32_t n_tx, const float* rx, int32_t n_rx,
                 const PcrlLaunchParams* params, pcrl_stream_t stream, PcrlLaunch** out);
 
 /* The launch directions used when PcrlLaunchParams.directions is NULL: the
  * Fibonacci lattice z_j = 1 - (2j+1)/N, phi_j = 2 pi frac(j (3 - sqrt 5)/2),
  * evaluated in FP64 and rounded to FP32 (uniformly spaced rays, Section 1's
- * ray launching).  out: device [n_rays,3] float32.  Asynchronous. */
+ * ray launching).  out: device [n_rays,3] float32.  Asynchronous;
+ * PCRL_EINVAL unless 1 <= n_rays < 2^31 and out is given. */
 int launch_directions(int64_t n_rays, float* out, pcrl_stream_t stream);
 
-/* Counters and timings of a launch (synchronises the launch's stream). */
+/* Counters and timings of a launch (synchronises the launch's stream).
+ * PCRL_EINVAL for a NULL argument, PCRL_EHIP if the copy fails. */
 int launch_stats(PcrlLaunch* launch, PcrlLaunchStats* out);
 
 /* Raw reception records (synchronous).  Device arrays of capacity `cap`:
@@ -293,7 +299,8 @@ int launch_batch(const PcrlQuery* queries, int32_t n_queries, const PcrlBatchPar
  * several times and the results discarded).  The winner is stored in the
  * process-wide table used by launch_batch(autotune = 1) for this scene class
  * (GPU architecture, number of levels, log2 mean entries, log2 mean rays)
- * and returned in *out.  Synchronous. */
+ * and returned in *out.  Synchronous; PCRL_EINVAL without queries or out,
+ * otherwise launch_batch's statuses. */
 int batch_autotune(const PcrlQuery* queries, int32_t n_queries, pcrl_stream_t stream, PcrlBatchParams* out);
 
 /* ------------------------------------------------------------------------ */
@@ -519,10 +526,12 @@ int ie_build(PcrlScene* scene, const PcrlIeGrid* grid, pcrl_stream_t stream, Pcr
  * call.  Synchronous. */
 int ie_add_edges(PcrlIes* ies, const float* seg, const float* normals, const uint32_t* label, int64_t n_edges,
                  pcrl_stream_t stream);
+/* Sizes of an IE table (host struct).  PCRL_EINVAL for a NULL argument. */
 int ie_info(const PcrlIes* ies, PcrlIeInfo* out);
 /* Copy the IE table into caller device arrays of at least n_ies entries
  * (any may be NULL): key (voxel * dv^3 + local subvoxel) << 32 | label,
- * sub [n,3] subvoxel cell, label, count, pos [n,3], nrm [n,3]. */
+ * sub [n,3] subvoxel cell, label, count, pos [n,3], nrm [n,3].
+ * PCRL_EINVAL for a NULL table, PCRL_EHIP if a copy fails. */
 int ie_table(const PcrlIes* ies, uint64_t* key, int32_t* sub, uint32_t* label, uint32_t* count, float* pos,
              float* nrm, pcrl_stream_t stream);
 int release_ies(PcrlIes* ies);
@@ -575,11 +584,14 @@ typedef struct {
  * Synchronous; PCRL_EINVAL for bad arguments or IEs of another scene. */
 int cone_launch(const PcrlIes* ies, const float* tx, int32_t n_tx, const float* rx, int32_t n_rx,
                 const PcrlConeParams* params, pcrl_stream_t stream, PcrlConeLaunch** out);
+/* Counts and timings of a cone launch (host struct).  PCRL_EINVAL for a NULL
+ * argument. */
 int cone_stats(const PcrlConeLaunch* launch, PcrlConeStats* out);
 /* Partial paths with k (1..K) interactions, in their kept order (by TX,
  * label sequence, IE, priority): device arrays of at least nodes[k] entries
  * (any may be NULL): IE, parent (index in generation k-1, or the TX for
- * k = 1), TX, priority, polyline length TX -> reception points. */
+ * k = 1), TX, priority, polyline length TX -> reception points.
+ * PCRL_EINVAL for a NULL launch or k outside 1..K. */
 int cone_nodes(const PcrlConeLaunch* launch, int32_t k, int32_t* ie, int32_t* parent, int32_t* tx,
                uint64_t* prio, float* length, pcrl_stream_t stream);
 /* Coarse paths: receptions grouped by (tx, rx, number of interactions,
